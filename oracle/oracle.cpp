@@ -1,0 +1,1518 @@
+/*
+ * ToF ReSTIR CPU oracle (FP64) -- TEST INFRASTRUCTURE ONLY; no product code
+ * links or calls it.  See oracle.h.
+ *
+ * What it computes, following the paper (Kim, Jarosz, Pediredla, "ToF ReSTIR",
+ * ACM TOG 45(4) 2026):
+ *   - the time-of-flight path integral I(tau) = int W_tau(l(x)) f(x) dmu(x)
+ *     (Sec. 3.1, eq. tof_path_integral), estimated with path trees and NEE to a
+ *     delta light (Sec. 5, "Light Source");
+ *   - RIS / weighted reservoir sampling (Sec. 3.2.1 and 3.2.4), one reservoir
+ *     per pixel and time bin (Sec. 4.5) seeded by per-bin path deposit
+ *     (Sec. 4.5, comparison with Jarabo's path reuse);
+ *   - GRIS with the generalized balance heuristic (Sec. 3.2.3,
+ *     eq. GRIS_resampling_weight and eq. GRIS_MIS_weight);
+ *   - the hybrid replay/reconnection shift followed by the path-length-aware
+ *     perturbation of the reconnection vertex (Sec. 4.1, eq.
+ *     path_length_constraint) with the average-gradient gauge, Newton with
+ *     backtracking, and the implicit-function Jacobian (Sec. 4.3);
+ *   - gradient and Hessian of the length function (Sec. 4.3, "Gradient and
+ *     Hessian Evaluation"), including the curvature term Q on sphere charts;
+ *   - the four-stage frame: initial, temporal, spatial, final shading
+ *     (Sec. 3.2.4).
+ * Readings of passages that are ambiguous or garbled are listed in the design doc
+ * (section "Readings"); the code states the reading it takes where it matters.
+ *
+ * Pins (tests/test_oracle_*.py): Philox against numpy's Philox4x64-10; BVH
+ * closest hit against brute force; the closed-form transient of a Lambertian
+ * plane; the confocal radial closed form of the Newton shift; finite-difference
+ * Jacobians; the gate constraint; the identity shift; bijectivity; WRS
+ * selection frequencies; unbiasedness of the full ReSTIR estimator against
+ * plain path tracing.  Parity of the complete multi-pass image beyond these
+ * properties is "parity unpinned" (no per-pixel values exist in the paper).
+ */
+#include "oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small vector algebra
+// ---------------------------------------------------------------------------
+struct V3 {
+    double x = 0, y = 0, z = 0;
+    V3() = default;
+    V3(double a, double b, double c) : x(a), y(b), z(c) {}
+    double operator[](int i) const { return i == 0 ? x : (i == 1 ? y : z); }
+};
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline V3 operator-(V3 a) { return {-a.x, -a.y, -a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double length(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 normalize(V3 a) { return (1.0 / length(a)) * a; }
+
+const double PI = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// multiply-xor bijection with the key bumped by the Weyl constants.
+// ---------------------------------------------------------------------------
+void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += W0; k1 += W1; }
+        unsigned __int128 p0 = (unsigned __int128)M0 * x0;
+        unsigned __int128 p1 = (unsigned __int128)M1 * x2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4 };
+
+struct Draw {
+    uint64_t x[4];
+    // uniform in [0,1) from the top 24 bits: exact in FP32 and FP64
+    double u(int i) const { return (double)(x[i] >> 40) * (1.0 / 16777216.0); }
+};
+
+Draw draw(uint64_t seed, uint64_t pixel, uint64_t frame, uint64_t pass, uint64_t a, uint64_t b) {
+    uint64_t ctr[4] = {pixel, frame, (pass << 56) | (a << 32) | b, 0};
+    uint64_t key[2] = {seed, 0};
+    Draw d;
+    philox4x64_10(ctr, key, d.x);
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// scene description
+// ---------------------------------------------------------------------------
+struct Material { int type; double albedo, alpha, f0; };
+struct Object {
+    int type, material;
+    int nu, nv, wrap_u, wrap_v, voff;
+    V3 centre; double radius;
+    int tri_base;
+};
+struct TriRef { int obj, i, j, h; };
+
+struct Vertex {           // a surface point in one frame
+    int obj = -1;
+    double xi[2] = {0, 0};
+    V3 p, n;
+};
+
+struct ChartEval {
+    bool on = false, ok = false;
+    V3 p, ju, jv, puu, puv, pvv, n;
+};
+
+struct BNode { double lo[3], hi[3]; int left, right, first, count; };
+
+struct FrameGeom {
+    bool valid = false;
+    int index = 0;
+    std::vector<double> xf;      // per object: 3x4 row-major
+    std::vector<V3> wv;          // world vertices
+    std::vector<BNode> nodes;
+    std::vector<int> order;      // triangle ids in BVH leaf order
+    V3 cam_pos, cam_fwd, cam_right, cam_up;
+    double tan_half = 0, aspect = 1, ortho_hx = 0, ortho_hy = 0;
+    V3 light_pos;
+};
+
+struct GBuf { bool hit = false; Vertex v; };
+
+struct VRef { int obj = -1; double xi[2] = {0, 0}; };
+
+struct PathRec {
+    uint32_t opix = 0, ofr = 0;
+    int tree = 0, n = 0, k = 0, nsfx = 0;
+    VRef xkm1, p, p2, sfx[2];
+    double len = 0, pre_pdf = 1, phat = 0;
+};
+
+struct Res { PathRec y; double W = 0; };
+
+struct Stats {
+    uint64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    void add(const Stats& o) { for (int i = 0; i < 8; ++i) c[i] += o.c[i]; }
+};
+enum { ST_SHIFTS = 0, ST_SHIFTS_OK, ST_NEWTON_ATT, ST_NEWTON_CONV, ST_NEWTON_ITERS, ST_NEWTON_OK, ST_RAYS };
+
+typedef std::map<int, Res> PixelRes;   // non-empty planes only
+
+struct Oracle {
+    // scene
+    std::vector<Object> objs;
+    std::vector<Material> mats;
+    std::vector<V3> lverts;
+    std::vector<TriRef> tris;
+    double sc = 1, eps = 1e-4, dmin = 0.01;
+    // sensor
+    orc_sensor s;
+    int P = 0, B = 0;            // pixels in the crop, planes
+    int nthreads = 1;
+    // state: slot 0 = current frame, slot 1 = previous frame
+    FrameGeom fg[2];
+    std::vector<GBuf> gb[2];
+    std::vector<PixelRes> fin_prev;
+    std::vector<double> M_prev;
+    bool prev_valid = false;
+    Stats stats;
+
+    // -------------------------------------------------------------------
+    const Material& mat_of(int obj) const { return mats[objs[obj].material]; }
+    bool rough(int obj) const {
+        const Material& m = mat_of(obj);
+        return m.type == 0 || m.alpha >= 0.2;
+    }
+
+    // -------------------------------------------------------------------
+    // frame geometry
+    // -------------------------------------------------------------------
+    V3 xf_point(const FrameGeom& F, int o, V3 q) const {
+        const double* m = &F.xf[12 * o];
+        return {m[0] * q.x + m[1] * q.y + m[2] * q.z + m[3],
+                m[4] * q.x + m[5] * q.y + m[6] * q.z + m[7],
+                m[8] * q.x + m[9] * q.y + m[10] * q.z + m[11]};
+    }
+    V3 xf_dir(const FrameGeom& F, int o, V3 q) const {
+        const double* m = &F.xf[12 * o];
+        return {m[0] * q.x + m[1] * q.y + m[2] * q.z, m[4] * q.x + m[5] * q.y + m[6] * q.z,
+                m[8] * q.x + m[9] * q.y + m[10] * q.z};
+    }
+    V3 xf_inv_point(const FrameGeom& F, int o, V3 p) const {
+        const double* m = &F.xf[12 * o];
+        V3 d = {p.x - m[3], p.y - m[7], p.z - m[11]};
+        return {m[0] * d.x + m[4] * d.y + m[8] * d.z, m[1] * d.x + m[5] * d.y + m[9] * d.z,
+                m[2] * d.x + m[6] * d.y + m[10] * d.z};
+    }
+    V3 gvert(const FrameGeom& F, int o, int i, int j) const {
+        const Object& ob = objs[o];
+        return F.wv[ob.voff + j * (ob.nu + 1) + i];
+    }
+    void tri_verts(const FrameGeom& F, int t, V3& a, V3& b, V3& c) const {
+        const TriRef& r = tris[t];
+        if (r.h == 0) {
+            a = gvert(F, r.obj, r.i, r.j); b = gvert(F, r.obj, r.i + 1, r.j); c = gvert(F, r.obj, r.i, r.j + 1);
+        } else {
+            a = gvert(F, r.obj, r.i + 1, r.j + 1); b = gvert(F, r.obj, r.i, r.j + 1); c = gvert(F, r.obj, r.i + 1, r.j);
+        }
+    }
+
+    void build_bvh(FrameGeom& F) {
+        int T = (int)tris.size();
+        F.order.resize(T);
+        std::vector<V3> cen(T);
+        for (int t = 0; t < T; ++t) {
+            F.order[t] = t;
+            V3 a, b, c;
+            tri_verts(F, t, a, b, c);
+            cen[t] = (1.0 / 3.0) * (a + b + c);
+        }
+        F.nodes.clear();
+        if (T == 0) return;
+        build_node(F, cen, 0, T);
+    }
+    int build_node(FrameGeom& F, const std::vector<V3>& cen, int first, int count) {
+        int id = (int)F.nodes.size();
+        F.nodes.push_back(BNode());
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        double clo[3] = {1e300, 1e300, 1e300}, chi[3] = {-1e300, -1e300, -1e300};
+        for (int q = first; q < first + count; ++q) {
+            V3 a, b, c;
+            tri_verts(F, F.order[q], a, b, c);
+            for (int ax = 0; ax < 3; ++ax) {
+                lo[ax] = std::min(lo[ax], std::min(a[ax], std::min(b[ax], c[ax])));
+                hi[ax] = std::max(hi[ax], std::max(a[ax], std::max(b[ax], c[ax])));
+                clo[ax] = std::min(clo[ax], cen[F.order[q]][ax]);
+                chi[ax] = std::max(chi[ax], cen[F.order[q]][ax]);
+            }
+        }
+        BNode nd;
+        for (int ax = 0; ax < 3; ++ax) {   // pad so the slab test is conservative
+            double pad = 1e-9 * (std::fabs(lo[ax]) + std::fabs(hi[ax]) + 1.0);
+            nd.lo[ax] = lo[ax] - pad;
+            nd.hi[ax] = hi[ax] + pad;
+        }
+        if (count <= 4) {
+            nd.left = nd.right = -1; nd.first = first; nd.count = count;
+            F.nodes[id] = nd;
+            return id;
+        }
+        int axis = 0;
+        for (int ax = 1; ax < 3; ++ax)
+            if (chi[ax] - clo[ax] > chi[axis] - clo[axis]) axis = ax;
+        int mid = first + count / 2;
+        std::nth_element(F.order.begin() + first, F.order.begin() + mid, F.order.begin() + first + count,
+                         [&](int x, int y) {
+                             double cx = cen[x][axis], cy = cen[y][axis];
+                             return cx < cy || (cx == cy && x < y);
+                         });
+        nd.first = 0; nd.count = 0;
+        nd.left = build_node(F, cen, first, mid - first);
+        nd.right = build_node(F, cen, mid, first + count - mid);
+        F.nodes[id] = nd;
+        return id;
+    }
+
+    void load_frame(FrameGeom& F, const orc_frame* fr) {
+        F.valid = true;
+        F.index = fr->index;
+        int O = (int)objs.size();
+        F.xf.assign(12 * O, 0.0);
+        for (int k = 0; k < 12 * O; ++k) F.xf[k] = (double)fr->xforms[k];
+        F.wv.resize(lverts.size());
+        for (int o = 0; o < O; ++o) {
+            const Object& ob = objs[o];
+            if (ob.type != 0) continue;
+            int nvtx = (ob.nu + 1) * (ob.nv + 1);
+            for (int q = 0; q < nvtx; ++q) F.wv[ob.voff + q] = xf_point(F, o, lverts[ob.voff + q]);
+        }
+        build_bvh(F);
+        F.cam_pos = {fr->cam_pos[0], fr->cam_pos[1], fr->cam_pos[2]};
+        V3 fwd = normalize(V3(fr->cam_fwd[0], fr->cam_fwd[1], fr->cam_fwd[2]));
+        V3 up = {fr->cam_up[0], fr->cam_up[1], fr->cam_up[2]};
+        F.cam_fwd = fwd;
+        F.cam_right = normalize(cross(fwd, up));
+        F.cam_up = cross(F.cam_right, fwd);
+        F.tan_half = std::tan(0.5 * (double)fr->fov_y_deg * PI / 180.0);
+        F.aspect = (double)s.full_width / (double)s.full_height;
+        F.ortho_hx = fr->ortho_half[0];
+        F.ortho_hy = fr->ortho_half[1];
+        F.light_pos = {fr->light_pos[0], fr->light_pos[1], fr->light_pos[2]};
+    }
+
+    // -------------------------------------------------------------------
+    // surface charts (Sec. 4.2): xi -> p on a grid object (piecewise-affine
+    // in cell units) or on a sphere ((theta, phi) about the local z axis).
+    // -------------------------------------------------------------------
+    ChartEval chart(const FrameGeom& F, int obj, double u, double v) const {
+        ChartEval c;
+        const Object& ob = objs[obj];
+        if (ob.type == 0) {
+            c.on = true;
+            double uu = u, vv = v;
+            if (ob.wrap_u) uu = u - ob.nu * std::floor(u / ob.nu);
+            else if (u < 0.0 || u > (double)ob.nu) c.on = false;
+            if (ob.wrap_v) vv = v - ob.nv * std::floor(v / ob.nv);
+            else if (v < 0.0 || v > (double)ob.nv) c.on = false;
+            int i = (int)std::floor(uu), j = (int)std::floor(vv);
+            i = std::min(std::max(i, 0), ob.nu - 1);
+            j = std::min(std::max(j, 0), ob.nv - 1);
+            double a = uu - i, b = vv - j;
+            V3 v00 = gvert(F, obj, i, j), v10 = gvert(F, obj, i + 1, j);
+            V3 v01 = gvert(F, obj, i, j + 1), v11 = gvert(F, obj, i + 1, j + 1);
+            if (a + b <= 1.0) {
+                c.p = v00 + a * (v10 - v00) + b * (v01 - v00);
+                c.ju = v10 - v00;
+                c.jv = v01 - v00;
+            } else {
+                c.p = v11 + (1.0 - a) * (v01 - v11) + (1.0 - b) * (v10 - v11);
+                c.ju = v11 - v01;
+                c.jv = v11 - v10;
+            }
+            V3 cr = cross(c.ju, c.jv);
+            double l = length(cr);
+            c.ok = l > 0.0;
+            if (c.ok) c.n = (1.0 / l) * cr;
+        } else {
+            double th = u, ph = v, r = ob.radius;
+            double st = std::sin(th), ct = std::cos(th), sp = std::sin(ph), cp = std::cos(ph);
+            V3 radial = {st * cp, st * sp, ct};
+            c.p = xf_point(F, obj, ob.centre + r * radial);
+            c.ju = xf_dir(F, obj, V3(r * ct * cp, r * ct * sp, -r * st));
+            c.jv = xf_dir(F, obj, V3(-r * st * sp, r * st * cp, 0.0));
+            c.puu = xf_dir(F, obj, -r * radial);
+            c.puv = xf_dir(F, obj, V3(-r * ct * sp, r * ct * cp, 0.0));
+            c.pvv = xf_dir(F, obj, V3(-r * st * cp, -r * st * sp, 0.0));
+            c.n = xf_dir(F, obj, radial);
+            c.on = th >= 1e-3 && th <= PI - 1e-3;
+            c.ok = true;
+        }
+        return c;
+    }
+    double wrap_coord(int obj, int dim, double x) const {
+        const Object& ob = objs[obj];
+        if (ob.type == 0) {
+            if (dim == 0 && ob.wrap_u) return x - ob.nu * std::floor(x / ob.nu);
+            if (dim == 1 && ob.wrap_v) return x - ob.nv * std::floor(x / ob.nv);
+            return x;
+        }
+        if (dim == 1) return x - 2.0 * PI * std::floor(x / (2.0 * PI));
+        return x;
+    }
+    Vertex vertex_at(const FrameGeom& F, int obj, const double xi[2]) const {
+        Vertex vx;
+        vx.obj = obj;
+        vx.xi[0] = xi[0];
+        vx.xi[1] = xi[1];
+        ChartEval c = chart(F, obj, xi[0], xi[1]);
+        vx.p = c.p;
+        vx.n = c.n;
+        return vx;
+    }
+    Vertex vertex_at(const FrameGeom& F, const VRef& r) const { return vertex_at(F, r.obj, r.xi); }
+
+    // -------------------------------------------------------------------
+    // ray casting: watertight ray/triangle test (Woop, Benthin, Wald,
+    // JCGT 2013), analytic spheres, a median-split BVH.
+    // -------------------------------------------------------------------
+    static bool isect_tri(V3 o, V3 d, V3 v0, V3 v1, V3 v2, double tmax, double& t, double& b1, double& b2) {
+        int kz = 0;
+        if (std::fabs(d.y) > std::fabs(d[kz])) kz = 1;
+        if (std::fabs(d.z) > std::fabs(d[kz])) kz = 2;
+        int kx = (kz + 1) % 3, ky = (kx + 1) % 3;
+        if (d[kz] < 0.0) std::swap(kx, ky);
+        double sx = d[kx] / d[kz], sy = d[ky] / d[kz], sz = 1.0 / d[kz];
+        V3 A = v0 - o, B = v1 - o, C = v2 - o;
+        double ax = A[kx] - sx * A[kz], ay = A[ky] - sy * A[kz];
+        double bx = B[kx] - sx * B[kz], by = B[ky] - sy * B[kz];
+        double cx = C[kx] - sx * C[kz], cy = C[ky] - sy * C[kz];
+        double U = cx * by - cy * bx, Vv = ax * cy - ay * cx, W = bx * ay - by * ax;
+        if ((U < 0 || Vv < 0 || W < 0) && (U > 0 || Vv > 0 || W > 0)) return false;
+        double det = U + Vv + W;
+        if (det == 0.0) return false;
+        double T = U * (sz * A[kz]) + Vv * (sz * B[kz]) + W * (sz * C[kz]);
+        double tt = T / det;
+        if (!(tt > 0.0 && tt < tmax)) return false;
+        t = tt;
+        b1 = Vv / det;
+        b2 = W / det;
+        return true;
+    }
+    static bool isect_sphere(V3 o, V3 d, V3 c, double r, double tmax, double& t) {
+        V3 oc = o - c;
+        double b = dot(oc, d), cc = dot(oc, oc) - r * r;
+        double disc = b * b - cc;
+        if (disc < 0.0) return false;
+        double sq = std::sqrt(disc);
+        double t0 = -b - sq, t1 = -b + sq;
+        if (t0 > 0.0 && t0 < tmax) { t = t0; return true; }
+        if (t1 > 0.0 && t1 < tmax) { t = t1; return true; }
+        return false;
+    }
+    static bool slab(const BNode& nd, V3 o, V3 d, double tmax) {
+        double tn = 0.0, tf = tmax;
+        for (int ax = 0; ax < 3; ++ax) {
+            if (d[ax] == 0.0) {
+                if (o[ax] < nd.lo[ax] || o[ax] > nd.hi[ax]) return false;
+                continue;
+            }
+            double t1 = (nd.lo[ax] - o[ax]) / d[ax], t2 = (nd.hi[ax] - o[ax]) / d[ax];
+            if (t1 > t2) std::swap(t1, t2);
+            tn = std::max(tn, t1);
+            tf = std::min(tf, t2);
+            if (tn > tf) return false;
+        }
+        return true;
+    }
+
+    struct Hit { bool hit = false; int prim = -1; int obj = -1; double t = 0, b1 = 0, b2 = 0; };
+
+    // closest hit; ties in t go to the smaller primitive id
+    Hit closest(const FrameGeom& F, V3 o, V3 d, bool brute = false) const {
+        Hit best;
+        double tb = 1e300;
+        auto consider_tri = [&](int t) {
+            V3 a, b, c;
+            tri_verts(F, t, a, b, c);
+            double tt, b1, b2;
+            if (isect_tri(o, d, a, b, c, tb * (1.0 + 1e-12) + 1e-300, tt, b1, b2)) {
+                if (tt < tb || (tt == tb && t < best.prim)) {
+                    tb = tt; best.hit = true; best.prim = t; best.obj = tris[t].obj; best.t = tt; best.b1 = b1; best.b2 = b2;
+                }
+            }
+        };
+        if (brute) {
+            for (int t = 0; t < (int)tris.size(); ++t) consider_tri(t);
+        } else if (!F.nodes.empty()) {
+            std::vector<int> stack;
+            stack.push_back(0);
+            while (!stack.empty()) {
+                int ni = stack.back();
+                stack.pop_back();
+                const BNode& nd = F.nodes[ni];
+                if (!slab(nd, o, d, tb)) continue;
+                if (nd.left < 0) {
+                    for (int q = nd.first; q < nd.first + nd.count; ++q) consider_tri(F.order[q]);
+                } else {
+                    stack.push_back(nd.left);
+                    stack.push_back(nd.right);
+                }
+            }
+        }
+        int T = (int)tris.size();
+        for (int ob = 0; ob < (int)objs.size(); ++ob) {
+            if (objs[ob].type != 1) continue;
+            double tt;
+            V3 cw = xf_point(F, ob, objs[ob].centre);
+            int prim = T + ob;
+            if (isect_sphere(o, d, cw, objs[ob].radius, tb * (1.0 + 1e-12) + 1e-300, tt)) {
+                if (tt < tb || (tt == tb && prim < best.prim)) {
+                    tb = tt; best.hit = true; best.prim = prim; best.obj = ob; best.t = tt;
+                }
+            }
+        }
+        return best;
+    }
+
+    bool occluded(const FrameGeom& F, V3 o, V3 d, double tmax) const {
+        if (!F.nodes.empty()) {
+            std::vector<int> stack;
+            stack.push_back(0);
+            while (!stack.empty()) {
+                int ni = stack.back();
+                stack.pop_back();
+                const BNode& nd = F.nodes[ni];
+                if (!slab(nd, o, d, tmax)) continue;
+                if (nd.left < 0) {
+                    for (int q = nd.first; q < nd.first + nd.count; ++q) {
+                        V3 a, b, c;
+                        tri_verts(F, F.order[q], a, b, c);
+                        double tt, b1, b2;
+                        if (isect_tri(o, d, a, b, c, tmax, tt, b1, b2)) return true;
+                    }
+                } else {
+                    stack.push_back(nd.left);
+                    stack.push_back(nd.right);
+                }
+            }
+        }
+        for (int ob = 0; ob < (int)objs.size(); ++ob) {
+            if (objs[ob].type != 1) continue;
+            double tt;
+            if (isect_sphere(o, d, xf_point(F, ob, objs[ob].centre), objs[ob].radius, tmax, tt)) return true;
+        }
+        return false;
+    }
+
+    // chart coordinates of a hit, then the vertex re-evaluated from its chart
+    Vertex hit_vertex(const FrameGeom& F, const Hit& h, V3 o, V3 d) const {
+        double xi[2];
+        if (h.prim < (int)tris.size()) {
+            const TriRef& r = tris[h.prim];
+            if (r.h == 0) { xi[0] = r.i + h.b1; xi[1] = r.j + h.b2; }
+            else { xi[0] = r.i + 1 - h.b1; xi[1] = r.j + 1 - h.b2; }
+        } else {
+            const Object& ob = objs[h.obj];
+            V3 q = xf_inv_point(F, h.obj, o + h.t * d) - ob.centre;
+            double ct = std::min(1.0, std::max(-1.0, q.z / ob.radius));
+            xi[0] = std::acos(ct);
+            double ph = std::atan2(q.y, q.x);
+            if (ph < 0.0) ph += 2.0 * PI;
+            xi[1] = ph;
+        }
+        return vertex_at(F, h.obj, xi);
+    }
+
+    V3 offset(V3 p, V3 n, V3 dir) const { return dot(n, dir) > 0.0 ? p + eps * n : p - eps * n; }
+
+    bool trace(const FrameGeom& F, const Vertex& from, V3 dir, Vertex& out) const {
+        V3 o = offset(from.p, from.n, dir);
+        Hit h = closest(F, o, dir);
+        if (!h.hit) return false;
+        out = hit_vertex(F, h, o, dir);
+        return true;
+    }
+    bool visible_pts(const FrameGeom& F, const Vertex& a, const Vertex& b) const {
+        V3 o = offset(a.p, a.n, b.p - a.p);
+        V3 t = offset(b.p, b.n, a.p - b.p);
+        V3 dv = t - o;
+        double dist = length(dv);
+        return !occluded(F, o, (1.0 / dist) * dv, dist);
+    }
+
+    // -------------------------------------------------------------------
+    // domains: pixel of the current (slot 0) or previous (slot 1) frame
+    // -------------------------------------------------------------------
+    uint64_t full_pixel(int pix) const {
+        int x = pix % s.width, y = pix / s.width;
+        return (uint64_t)(s.crop_y0 + y) * (uint64_t)s.full_width + (uint64_t)(s.crop_x0 + x);
+    }
+    V3 toward_camera(int slot, const Vertex& y1) const {
+        const FrameGeom& F = fg[slot];
+        if (s.camera_model == 0) return normalize(F.cam_pos - y1.p);
+        return -F.cam_fwd;
+    }
+    double camera_leg(int slot, const Vertex& y1) const {
+        if (!s.count_camera_leg) return 0.0;
+        const FrameGeom& F = fg[slot];
+        if (s.camera_model == 0) return length(y1.p - F.cam_pos);
+        return dot(y1.p - F.cam_pos, F.cam_fwd);
+    }
+    // Delta lights (Sec. 5, "Light Source"): an isotropic point light, or the
+    // confocal laser spot at the domain's primary hit re-emitting with the
+    // wall's Lambertian BRDF.
+    V3 light_pos(int slot, int pix) const {
+        if (s.light_model == 0) return fg[slot].light_pos;
+        return gb[slot][pix].v.p;
+    }
+    double light_emit(int slot, int pix, V3 x) const {
+        if (s.light_model == 0) return s.light_intensity;
+        const Vertex& g = gb[slot][pix].v;
+        V3 w = normalize(x - g.p);
+        double cw = dot(g.n, w), cs = dot(g.n, -fg[slot].cam_fwd);
+        if (cw * cs <= 0.0) return 0.0;
+        const Material& m = mat_of(g.obj);
+        return s.light_intensity * m.albedo / PI * std::fabs(cw);
+    }
+    bool light_visible(int slot, int pix, const Vertex& x) const {
+        const FrameGeom& F = fg[slot];
+        if (s.light_model == 0) {
+            V3 o = offset(x.p, x.n, F.light_pos - x.p);
+            V3 dv = F.light_pos - o;
+            double dist = length(dv);
+            return !occluded(F, o, (1.0 / dist) * dv, dist);
+        }
+        return visible_pts(F, x, gb[slot][pix].v);
+    }
+
+    // -------------------------------------------------------------------
+    // BSDFs: Lambert and GGX (Walter et al. 2007, separable Smith G,
+    // Schlick Fresnel), sampled cosine-weighted / proportional to D cos.
+    // -------------------------------------------------------------------
+    static void onb(V3 n, V3& t, V3& b) {   // Duff et al., JCGT 2017
+        double sg = std::copysign(1.0, n.z);
+        double a = -1.0 / (sg + n.z);
+        double bb = n.x * n.y * a;
+        t = {1.0 + sg * n.x * n.x * a, sg * bb, -sg * n.x};
+        b = {bb, sg + n.y * n.y * a, -n.y};
+    }
+    static double ggx_d(double alpha, double ch) {
+        double a2 = alpha * alpha;
+        double den = ch * ch * (a2 - 1.0) + 1.0;
+        return a2 / (PI * den * den);
+    }
+    static double ggx_g1(double alpha, double c) {
+        double a2 = alpha * alpha;
+        return 2.0 * c / (c + std::sqrt(a2 + (1.0 - a2) * c * c));
+    }
+    double bsdf(int obj, V3 n, V3 wi, V3 wo) const {
+        double ci = dot(n, wi), co = dot(n, wo);
+        if (ci * co <= 0.0) return 0.0;
+        const Material& m = mat_of(obj);
+        if (m.type == 0) return m.albedo / PI;
+        ci = std::fabs(ci); co = std::fabs(co);
+        V3 ns = dot(n, wi) > 0.0 ? n : -n;
+        V3 h = normalize(wi + wo);
+        double ch = dot(ns, h);
+        double D = ggx_d(m.alpha, ch);
+        double G = ggx_g1(m.alpha, ci) * ggx_g1(m.alpha, co);
+        double F = m.f0 + (1.0 - m.f0) * std::pow(1.0 - dot(wi, h), 5.0);
+        return D * G * F / (4.0 * ci * co);
+    }
+    bool bsdf_sample(int obj, V3 n, V3 wi, double u1, double u2, V3& wo, double& pdf) const {
+        double ci = dot(n, wi);
+        if (ci == 0.0) return false;
+        V3 ns = ci > 0.0 ? n : -n;
+        V3 t, b;
+        onb(ns, t, b);
+        const Material& m = mat_of(obj);
+        if (m.type == 0) {
+            double r = std::sqrt(u1), ph = 2.0 * PI * u2;
+            double z = std::sqrt(std::max(0.0, 1.0 - u1));
+            wo = normalize(r * std::cos(ph) * t + r * std::sin(ph) * b + z * ns);
+            pdf = dot(ns, wo) / PI;
+            return pdf > 0.0;
+        }
+        double a2 = m.alpha * m.alpha;
+        double t2 = a2 * u1 / (1.0 - u1);
+        double ch = 1.0 / std::sqrt(1.0 + t2);
+        double sh = std::sqrt(std::max(0.0, 1.0 - ch * ch));
+        double ph = 2.0 * PI * u2;
+        V3 h = sh * std::cos(ph) * t + sh * std::sin(ph) * b + ch * ns;
+        double wh = dot(wi, h);
+        wo = normalize(2.0 * wh * h - wi);
+        if (dot(ns, wo) <= 0.0) return false;
+        pdf = ggx_d(m.alpha, ch) * ch / (4.0 * std::fabs(wh));
+        return pdf > 0.0;
+    }
+
+    // -------------------------------------------------------------------
+    // time gate / bins (Sec. 3.1 W_tau; half-open boxes)
+    // -------------------------------------------------------------------
+    double plane_lo(int pl) const {
+        return pl < s.n_bins ? s.bin_t0 + pl * s.bin_width : s.gate_center - 0.5 * s.gate_width;
+    }
+    double plane_hi(int pl) const {
+        return pl < s.n_bins ? s.bin_t0 + (pl + 1) * s.bin_width : s.gate_center + 0.5 * s.gate_width;
+    }
+    double plane_width(int pl) const { return pl < s.n_bins ? s.bin_width : s.gate_width; }
+    bool in_plane(int pl, double len) const { return len >= plane_lo(pl) && len < plane_hi(pl); }
+    int bin_of(double len) const {
+        if (s.n_bins <= 0) return -1;
+        double f = std::floor((len - s.bin_t0) / s.bin_width);
+        if (!(f > -2.0 && f < (double)s.n_bins + 1.0)) return -1;
+        int b = (int)f;
+        if (b >= 0 && b < s.n_bins && len < plane_lo(b)) b -= 1;
+        if (b >= -1 && b + 1 < s.n_bins && b + 1 >= 0 && len >= plane_lo(b + 1)) b += 1;
+        if (b < 0 || b >= s.n_bins || !in_plane(b, len)) return -1;
+        return b;
+    }
+
+    // reconnection criterion (Sec. 4.1, first consecutive rough vertices)
+    bool recon_ok(const Vertex& a, const Vertex& b) const {
+        return rough(a.obj) && rough(b.obj) && length(b.p - a.p) >= dmin;
+    }
+
+    // -------------------------------------------------------------------
+    // path contribution f(y) in the product solid-angle measure of the
+    // sampled directions, with NEE to the delta light (no visibility).
+    // -------------------------------------------------------------------
+    double path_eval(int slot, int pix, const std::vector<Vertex>& ys, double& len) const {
+        V3 wi = toward_camera(slot, ys[0]);
+        double f = 1.0;
+        len = camera_leg(slot, ys[0]);
+        for (size_t j = 0; j + 1 < ys.size(); ++j) {
+            V3 dv = ys[j + 1].p - ys[j].p;
+            double dl = length(dv);
+            V3 wo = (1.0 / dl) * dv;
+            f *= bsdf(ys[j].obj, ys[j].n, wi, wo) * std::fabs(dot(ys[j].n, wo));
+            len += dl;
+            wi = -wo;
+        }
+        const Vertex& y = ys.back();
+        V3 L = light_pos(slot, pix);
+        V3 dv = L - y.p;
+        double dl = length(dv);
+        V3 wo = (1.0 / dl) * dv;
+        f *= bsdf(y.obj, y.n, wi, wo) * std::fabs(dot(y.n, wo)) * light_emit(slot, pix, y.p) / (dl * dl);
+        len += dl;
+        return f;
+    }
+
+    // -------------------------------------------------------------------
+    // Newton solve of the path-length constraint with the average-gradient
+    // gauge (Sec. 4.3).  Reading: the length functions use the source
+    // endpoints at xi and the destination endpoints at xi', and dF2/dxi' is
+    // derived by differentiating F2 (the printed sign of its Hessian term is
+    // not used).
+    // -------------------------------------------------------------------
+    struct LenEval { bool ok = false; double L = 0, g[2] = {0, 0}, H[2][2] = {{0, 0}, {0, 0}}; double area = 0; };
+    LenEval len_eval(const FrameGeom& F, int obj, double u, double v, V3 a, V3 b, double c) const {
+        LenEval e;
+        ChartEval ch = chart(F, obj, u, v);
+        if (!ch.ok) return e;
+        V3 r1 = a - ch.p, r2 = b - ch.p;
+        double l1 = length(r1), l2 = length(r2);
+        if (!(l1 > 0.0 && l2 > 0.0)) return e;
+        V3 d1 = (1.0 / l1) * r1, d2 = (1.0 / l2) * r2;
+        V3 sv = d1 + d2;
+        e.L = c + l1 + l2;
+        // grad_p l = -s; grad_xi l = J^T (-s)
+        e.g[0] = -dot(sv, ch.ju);
+        e.g[1] = -dot(sv, ch.jv);
+        // Hessian: J^T A J + Q with A = sum (I - d d^T)/|p_i - p|, Q_ij = (-s).p_ij
+        auto A = [&](V3 x) { return (1.0 / l1) * (x - dot(d1, x) * d1) + (1.0 / l2) * (x - dot(d2, x) * d2); };
+        V3 Aju = A(ch.ju), Ajv = A(ch.jv);
+        e.H[0][0] = dot(ch.ju, Aju) - dot(sv, ch.puu);
+        e.H[0][1] = dot(ch.ju, Ajv) - dot(sv, ch.puv);
+        e.H[1][0] = e.H[0][1];
+        e.H[1][1] = dot(ch.jv, Ajv) - dot(sv, ch.pvv);
+        e.area = length(cross(ch.ju, ch.jv));
+        e.ok = true;
+        return e;
+    }
+
+    struct NewtonOut { bool conv = false; double xi[2] = {0, 0}; int iters = 0; double det_dxi = 0, det_area = 0, F[2] = {0, 0}; int status = 0; };
+
+    NewtonOut newton(const FrameGeom& FS, const FrameGeom& FD, int obj, const double xi[2], V3 as, V3 bs,
+                     double cs, V3 ad, V3 bd, double cd, double dl0, double tol, int maxit) const {
+        NewtonOut out;
+        LenEval S = len_eval(FS, obj, xi[0], xi[1], as, bs, cs);
+        if (!S.ok) { out.status = 1; return out; }
+        auto Fval = [&](const double xp[2], LenEval& D, double Fv[2]) {
+            D = len_eval(FD, obj, xp[0], xp[1], ad, bd, cd);
+            if (!D.ok) return false;
+            double m0 = 0.5 * (S.g[0] + D.g[0]), m1 = 0.5 * (S.g[1] + D.g[1]);
+            double d0 = xp[0] - xi[0], d1 = xp[1] - xi[1];
+            Fv[0] = D.L - S.L - dl0;
+            Fv[1] = -m1 * d0 + m0 * d1;         // (R m)^T (xi' - xi), R = 90 deg rotation
+            return true;
+        };
+        // dF/dxi' = [grad L_dst ; (R m - 0.5 H_dst R d)^T]
+        auto jac_dst = [&](const double xp[2], const LenEval& D, double J[2][2]) {
+            double m0 = 0.5 * (S.g[0] + D.g[0]), m1 = 0.5 * (S.g[1] + D.g[1]);
+            double d0 = xp[0] - xi[0], d1 = xp[1] - xi[1];
+            double rd0 = -d1, rd1 = d0;
+            J[0][0] = D.g[0];
+            J[0][1] = D.g[1];
+            J[1][0] = -m1 - 0.5 * (D.H[0][0] * rd0 + D.H[0][1] * rd1);
+            J[1][1] = m0 - 0.5 * (D.H[1][0] * rd0 + D.H[1][1] * rd1);
+        };
+        double xp[2] = {xi[0], xi[1]};
+        LenEval D;
+        double Fv[2];
+        if (!Fval(xp, D, Fv)) { out.status = 1; return out; }
+        int it = 0;
+        while (true) {
+            if (std::fabs(Fv[0]) <= tol && std::fabs(Fv[1]) <= tol) break;
+            if (it >= maxit) { out.status = 2; out.F[0] = Fv[0]; out.F[1] = Fv[1]; return out; }
+            double J[2][2];
+            jac_dst(xp, D, J);
+            double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            if (std::fabs(det) < 1e-12) { out.status = 3; return out; }
+            double step0 = -(J[1][1] * Fv[0] - J[0][1] * Fv[1]) / det;
+            double step1 = -(-J[1][0] * Fv[0] + J[0][0] * Fv[1]) / det;
+            double norm0 = std::hypot(Fv[0], Fv[1]);
+            bool accepted = false;
+            double alpha = 1.0;
+            for (int ls = 0; ls < 4; ++ls, alpha *= 0.5) {   // backtracking line search
+                double xt[2] = {xp[0] + alpha * step0, xp[1] + alpha * step1};
+                LenEval Dt;
+                double Ft[2];
+                if (Fval(xt, Dt, Ft) && std::hypot(Ft[0], Ft[1]) < norm0) {
+                    xp[0] = xt[0]; xp[1] = xt[1]; D = Dt; Fv[0] = Ft[0]; Fv[1] = Ft[1];
+                    accepted = true;
+                    break;
+                }
+            }
+            if (!accepted) { out.status = 4; return out; }
+            ++it;
+        }
+        // implicit-function Jacobian: |det dxi'/dxi| = |det dF/dxi| / |det dF/dxi'|
+        double Jd[2][2];
+        jac_dst(xp, D, Jd);
+        double m0 = 0.5 * (S.g[0] + D.g[0]), m1 = 0.5 * (S.g[1] + D.g[1]);
+        double d0 = xp[0] - xi[0], d1 = xp[1] - xi[1];
+        double rd0 = -d1, rd1 = d0;
+        double Js[2][2];   // dF/dxi = [-grad L_src ; -(R m + 0.5 H_src R d)^T]
+        Js[0][0] = -S.g[0];
+        Js[0][1] = -S.g[1];
+        Js[1][0] = -(-m1 + 0.5 * (S.H[0][0] * rd0 + S.H[0][1] * rd1));
+        Js[1][1] = -(m0 + 0.5 * (S.H[1][0] * rd0 + S.H[1][1] * rd1));
+        double detd = Jd[0][0] * Jd[1][1] - Jd[0][1] * Jd[1][0];
+        double dets = Js[0][0] * Js[1][1] - Js[0][1] * Js[1][0];
+        if (std::fabs(detd) < 1e-12) { out.status = 3; return out; }
+        out.conv = true;
+        out.xi[0] = xp[0];
+        out.xi[1] = xp[1];
+        out.iters = it;
+        out.det_dxi = std::fabs(dets) / std::fabs(detd);
+        // chart -> surface area factor sqrt(det J'^T J') / sqrt(det J^T J)
+        out.det_area = D.area / S.area * out.det_dxi;
+        out.F[0] = Fv[0];
+        out.F[1] = Fv[1];
+        return out;
+    }
+
+    // -------------------------------------------------------------------
+    // shift T_{src -> dst} of a stored path (Sec. 4.1): random replay up to
+    // the vertex before the reconnection vertex, reconnection, then the
+    // path-length-aware perturbation of the reconnection vertex.
+    // -------------------------------------------------------------------
+    struct ShiftOut { bool ok = false; PathRec y; double J = 0, phat = 0; };
+
+    ShiftOut shift(const PathRec& x, int src_slot, int src_pix, int dst_slot, int dst_pix, int plane, double dl0,
+                   Stats& st) const {
+        ShiftOut R;
+        st.c[ST_SHIFTS]++;
+        const GBuf& g = gb[dst_slot][dst_pix];
+        if (!g.hit) return R;
+        const FrameGeom& FS = fg[src_slot];
+        const FrameGeom& FD = fg[dst_slot];
+        std::vector<Vertex> ys;
+        ys.push_back(g.v);
+        double pdf_y = 1.0;
+        V3 wi = toward_camera(dst_slot, ys[0]);
+        int nrep = (x.k == 0) ? x.n - 1 : x.k - 2;
+        for (int i = 1; i <= nrep; ++i) {
+            const Vertex cur = ys.back();
+            Draw u = draw(s.seed, x.opix, x.ofr, PASS_BSDF, (uint64_t)x.tree, (uint64_t)i);
+            V3 wo;
+            double pdf;
+            if (!bsdf_sample(cur.obj, cur.n, wi, u.u(0), u.u(1), wo, pdf)) return R;
+            Vertex nx;
+            st.c[ST_RAYS]++;
+            if (!trace(FD, cur, wo, nx)) return R;
+            pdf_y *= pdf;
+            ys.push_back(nx);
+            wi = -wo;
+        }
+        // the offset path must not reconnect earlier than the base path
+        for (size_t kk = 2; kk <= ys.size(); ++kk)
+            if (recon_ok(ys[kk - 2], ys[kk - 1])) return R;
+
+        if (x.k == 0) {   // pure random replay
+            double len;
+            double C = path_eval(dst_slot, dst_pix, ys, len);
+            st.c[ST_RAYS]++;
+            if (C <= 0.0 || !light_visible(dst_slot, dst_pix, ys.back())) return R;
+            double J = x.pre_pdf / pdf_y;
+            if (!(J >= 1.0 / s.j_max && J <= s.j_max)) return R;
+            double ph = in_plane(plane, len) ? C : 0.0;
+            if (!(ph > 0.0)) return R;
+            R.y = x;
+            R.y.len = len;
+            R.y.pre_pdf = pdf_y;
+            R.y.phat = ph;
+            R.J = J;
+            R.phat = ph;
+            R.ok = true;
+            st.c[ST_SHIFTS_OK]++;
+            return R;
+        }
+
+        const Vertex ykm1 = ys.back();
+        if (!rough(ykm1.obj)) return R;
+        const int obj = x.p.obj;
+        Vertex xkm1_s = vertex_at(FS, x.xkm1);
+        Vertex p_s = vertex_at(FS, x.p);
+        const bool p2light = x.p2.obj < 0;
+        Vertex p2_s, p2_d;
+        V3 p2s_pos, p2d_pos;
+        if (p2light) {
+            p2s_pos = light_pos(src_slot, src_pix);
+            p2d_pos = light_pos(dst_slot, dst_pix);
+        } else {
+            p2_s = vertex_at(FS, x.p2);
+            p2_d = vertex_at(FD, x.p2);
+            p2s_pos = p2_s.p;
+            p2d_pos = p2_d.p;
+        }
+        std::vector<Vertex> sfx_d;
+        for (int q = 0; q < x.nsfx; ++q) sfx_d.push_back(vertex_at(FD, x.sfx[q]));
+        double c_src = x.len - length(xkm1_s.p - p_s.p) - length(p2s_pos - p_s.p);
+        double c_dst = camera_leg(dst_slot, ys[0]);
+        for (size_t j = 0; j + 1 < ys.size(); ++j) c_dst += length(ys[j + 1].p - ys[j].p);
+        if (!p2light) {
+            V3 prev = p2d_pos;
+            for (const Vertex& v : sfx_d) { c_dst += length(v.p - prev); prev = v.p; }
+            c_dst += length(light_pos(dst_slot, dst_pix) - prev);
+        }
+        double xi2[2] = {x.p.xi[0], x.p.xi[1]};
+        double det_area;
+        if (s.shift_mode == 1) {
+            st.c[ST_NEWTON_ATT]++;
+            double tol = s.newton_tol_rel * plane_width(plane);
+            NewtonOut no = newton(FS, FD, obj, x.p.xi, xkm1_s.p, p2s_pos, c_src, ykm1.p, p2d_pos, c_dst, dl0, tol,
+                                  s.newton_max_iter);
+            if (!no.conv) return R;
+            st.c[ST_NEWTON_CONV]++;
+            st.c[ST_NEWTON_ITERS] += (uint64_t)no.iters;
+            xi2[0] = no.xi[0];
+            xi2[1] = no.xi[1];
+            det_area = no.det_area;
+        } else {
+            ChartEval cs = chart(FS, obj, xi2[0], xi2[1]), cd = chart(FD, obj, xi2[0], xi2[1]);
+            if (!cs.ok || !cd.ok) return R;
+            det_area = length(cross(cd.ju, cd.jv)) / length(cross(cs.ju, cs.jv));
+        }
+        ChartEval cp = chart(FD, obj, xi2[0], xi2[1]);
+        if (!cp.on || !cp.ok) return R;
+        Vertex pd;
+        pd.obj = obj;
+        pd.xi[0] = wrap_coord(obj, 0, xi2[0]);
+        pd.xi[1] = wrap_coord(obj, 1, xi2[1]);
+        pd.p = cp.p;
+        pd.n = cp.n;
+        if (length(pd.p - ykm1.p) < dmin) return R;
+        // visibility of the moved edges; the suffix is re-tested when the two
+        // domains belong to different frames (the scene may have moved)
+        st.c[ST_RAYS]++;
+        if (!visible_pts(FD, ykm1, pd)) return R;
+        if (p2light) {
+            st.c[ST_RAYS]++;
+            if (!light_visible(dst_slot, dst_pix, pd)) return R;
+        } else {
+            st.c[ST_RAYS]++;
+            if (!visible_pts(FD, pd, p2_d)) return R;
+            if (src_slot != dst_slot) {
+                Vertex prev = p2_d;
+                for (const Vertex& v : sfx_d) {
+                    st.c[ST_RAYS]++;
+                    if (!visible_pts(FD, prev, v)) return R;
+                    prev = v;
+                }
+                st.c[ST_RAYS]++;
+                if (!light_visible(dst_slot, dst_pix, prev)) return R;
+            }
+        }
+        std::vector<Vertex> yfull = ys;
+        yfull.push_back(pd);
+        if (!p2light) {
+            yfull.push_back(p2_d);
+            for (const Vertex& v : sfx_d) yfull.push_back(v);
+        }
+        double len;
+        double C = path_eval(dst_slot, dst_pix, yfull, len);
+        // Jacobian of the whole shift in the product solid-angle measure
+        double J = x.pre_pdf / pdf_y;
+        V3 ey = ykm1.p - pd.p, ex = xkm1_s.p - p_s.p;
+        double ly = length(ey), lx = length(ex);
+        double gy = std::fabs(dot(pd.n, (1.0 / ly) * ey)) / (ly * ly);
+        double gx = std::fabs(dot(p_s.n, (1.0 / lx) * ex)) / (lx * lx);
+        J *= gy / gx * det_area;
+        if (!p2light) {
+            V3 e2d = pd.p - p2_d.p, e2s = p_s.p - p2_s.p;
+            double l2d = length(e2d), l2s = length(e2s);
+            double g2d = std::fabs(dot(p2_d.n, (1.0 / l2d) * e2d)) / (l2d * l2d);
+            double g2s = std::fabs(dot(p2_s.n, (1.0 / l2s) * e2s)) / (l2s * l2s);
+            J *= g2d / g2s;
+        }
+        if (!(J >= 1.0 / s.j_max && J <= s.j_max)) return R;
+        double ph = in_plane(plane, len) ? C : 0.0;
+        if (!(ph > 0.0)) return R;
+        R.y = x;
+        R.y.xkm1.obj = ykm1.obj;
+        R.y.xkm1.xi[0] = ykm1.xi[0];
+        R.y.xkm1.xi[1] = ykm1.xi[1];
+        R.y.p.obj = obj;
+        R.y.p.xi[0] = pd.xi[0];
+        R.y.p.xi[1] = pd.xi[1];
+        R.y.len = len;
+        R.y.pre_pdf = pdf_y;
+        R.y.phat = ph;
+        R.J = J;
+        R.phat = ph;
+        R.ok = true;
+        st.c[ST_SHIFTS_OK]++;
+        if (s.shift_mode == 1) st.c[ST_NEWTON_OK]++;
+        return R;
+    }
+
+    // -------------------------------------------------------------------
+    // passes
+    // -------------------------------------------------------------------
+    void gbuffer_pass(int slot, uint64_t frame) {
+        const FrameGeom& F = fg[slot];
+        gb[slot].assign(P, GBuf());
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+        for (int pix = 0; pix < P; ++pix) {
+            int x = pix % s.width, y = pix / s.width;
+            double fx = s.crop_x0 + x, fy = s.crop_y0 + y;
+            double u0 = 0.5, u1 = 0.5;
+            if (s.jitter) {
+                Draw d = draw(s.seed, full_pixel(pix), frame, PASS_JITTER, 0, 0);
+                u0 = d.u(0);
+                u1 = d.u(1);
+            }
+            double sx = 2.0 * (fx + u0) / s.full_width - 1.0;
+            double sy = 1.0 - 2.0 * (fy + u1) / s.full_height;
+            V3 o, dir;
+            if (s.camera_model == 0) {
+                o = F.cam_pos;
+                dir = normalize(F.cam_fwd + (sx * F.tan_half * F.aspect) * F.cam_right + (sy * F.tan_half) * F.cam_up);
+            } else {
+                o = F.cam_pos + (sx * F.ortho_hx) * F.cam_right + (sy * F.ortho_hy) * F.cam_up;
+                dir = F.cam_fwd;
+            }
+            Hit h = closest(F, o, dir);
+            if (h.hit) {
+                gb[slot][pix].hit = true;
+                gb[slot][pix].v = hit_vertex(F, h, o, dir);
+            }
+        }
+    }
+
+    // initial candidates: path trees with NEE at every vertex, each sub-path
+    // deposited into the reservoir of its bin (and the gate) (Sec. 4.5).
+    void initial_pass(uint64_t frame, std::vector<PixelRes>& can, std::vector<double>& Mc,
+                      std::vector<double>& pt, std::vector<double>& direct_c, std::vector<double>& direct_l) {
+        can.assign(P, PixelRes());
+        Mc.assign(P, 0.0);
+        pt.assign((size_t)B * P, 0.0);
+        direct_c.assign(P, 0.0);
+        direct_l.assign(P, 0.0);
+        std::vector<Stats> ts(nthreads);
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
+        for (int pix = 0; pix < P; ++pix) {
+#ifdef _OPENMP
+            Stats& st = ts[omp_get_thread_num()];
+#else
+            Stats& st = ts[0];
+#endif
+            const GBuf& g = gb[0][pix];
+            if (!g.hit) continue;
+            Mc[pix] = (double)s.m_init;
+            const FrameGeom& F = fg[0];
+            uint64_t fp = full_pixel(pix);
+            std::map<int, double> wsum;
+            for (int tree = 0; tree < s.m_init; ++tree) {
+                std::vector<Vertex> vs;
+                std::vector<double> pdfs;   // pdfs[j-1] = p(omega_j)
+                vs.push_back(g.v);
+                double beta = 1.0, pdf = 1.0, len = camera_leg(0, g.v);
+                V3 wi = toward_camera(0, g.v);
+                int kfound = 0;
+                for (int i = 1; i <= s.n_max; ++i) {
+                    const Vertex xi = vs.back();
+                    if (i >= 2 && kfound == 0 && recon_ok(vs[i - 2], vs[i - 1])) kfound = i;
+                    bool want = (i >= 2 && i >= s.n_min) || (i == 1 && s.include_direct && s.n_min <= 1);
+                    if (want) {
+                        V3 L = light_pos(0, pix);
+                        V3 dv = L - xi.p;
+                        double dl = length(dv);
+                        V3 wl = (1.0 / dl) * dv;
+                        double fs = bsdf(xi.obj, xi.n, wi, wl);
+                        double C = beta * fs * std::fabs(dot(xi.n, wl)) * light_emit(0, pix, xi.p) / (dl * dl);
+                        if (C > 0.0) {
+                            st.c[ST_RAYS]++;
+                            if (!light_visible(0, pix, xi)) C = 0.0;
+                        }
+                        double l_i = len + dl;
+                        if (C > 0.0 && i == 1) {
+                            if (tree == 0) { direct_c[pix] = C; direct_l[pix] = l_i; }
+                        } else if (C > 0.0) {
+                            PathRec rec;
+                            rec.opix = (uint32_t)fp;
+                            rec.ofr = (uint32_t)frame;
+                            rec.tree = tree;
+                            rec.n = i;
+                            rec.k = kfound;
+                            rec.len = l_i;
+                            rec.phat = C;
+                            if (kfound >= 2) {
+                                int k = kfound;
+                                rec.pre_pdf = 1.0;
+                                for (int j = 1; j <= k - 2; ++j) rec.pre_pdf *= pdfs[j - 1];
+                                auto ref = [&](const Vertex& v) { VRef r; r.obj = v.obj; r.xi[0] = v.xi[0]; r.xi[1] = v.xi[1]; return r; };
+                                rec.xkm1 = ref(vs[k - 2]);
+                                rec.p = ref(vs[k - 1]);
+                                if (k < i) rec.p2 = ref(vs[k]);
+                                rec.nsfx = 0;
+                                for (int q = k + 1; q < i; ++q) rec.sfx[rec.nsfx++] = ref(vs[q]);
+                            } else {
+                                rec.pre_pdf = pdf;
+                            }
+                            Draw u = draw(s.seed, fp, frame, PASS_RIS, (uint64_t)tree, (uint64_t)i);
+                            double w = C / ((double)s.m_init * pdf);
+                            int planes[2] = {bin_of(l_i), (s.gate_enabled && in_plane(s.n_bins, l_i)) ? s.n_bins : -1};
+                            for (int q = 0; q < 2; ++q) {
+                                int pl = planes[q];
+                                if (pl < 0) continue;
+                                pt[(size_t)pl * P + pix] += C / pdf / (double)s.m_init;
+                                double& ws = wsum[pl];
+                                ws += w;
+                                if (u.u(q) * ws < w) can[pix][pl].y = rec;
+                            }
+                        }
+                    }
+                    if (i == s.n_max) break;
+                    Draw u = draw(s.seed, fp, frame, PASS_BSDF, (uint64_t)tree, (uint64_t)i);
+                    V3 wo;
+                    double pw;
+                    if (!bsdf_sample(xi.obj, xi.n, wi, u.u(0), u.u(1), wo, pw)) break;
+                    double fcos = bsdf(xi.obj, xi.n, wi, wo) * std::fabs(dot(xi.n, wo));
+                    Vertex nx;
+                    st.c[ST_RAYS]++;
+                    if (!trace(F, xi, wo, nx)) break;
+                    beta *= fcos;
+                    pdf *= pw;
+                    pdfs.push_back(pw);
+                    len += length(nx.p - xi.p);
+                    vs.push_back(nx);
+                    wi = -wo;
+                }
+            }
+            for (auto& kv : can[pix]) kv.second.W = wsum[kv.first] / kv.second.y.phat;
+        }
+        for (auto& t : ts) stats.add(t);
+    }
+
+    int reproject(int pix) const {
+        const GBuf& g = gb[0][pix];
+        const FrameGeom& F = fg[1];
+        V3 p = chart(F, g.v.obj, g.v.xi[0], g.v.xi[1]).p;
+        V3 v = p - F.cam_pos;
+        double px, py;
+        if (s.camera_model == 0) {
+            double z = dot(v, F.cam_fwd);
+            if (!(z > 0.0)) return -1;
+            double sx = dot(v, F.cam_right) / z / (F.tan_half * F.aspect);
+            double sy = dot(v, F.cam_up) / z / F.tan_half;
+            px = 0.5 * (sx + 1.0) * s.full_width;
+            py = 0.5 * (1.0 - sy) * s.full_height;
+        } else {
+            px = 0.5 * (dot(v, F.cam_right) / F.ortho_hx + 1.0) * s.full_width;
+            py = 0.5 * (1.0 - dot(v, F.cam_up) / F.ortho_hy) * s.full_height;
+        }
+        double fx = std::floor(px) - s.crop_x0, fy = std::floor(py) - s.crop_y0;
+        if (!(fx >= 0.0 && fx < s.width && fy >= 0.0 && fy < s.height)) return -1;
+        int q = (int)fy * s.width + (int)fx;
+        if (!gb[1][q].hit || gb[1][q].v.obj != g.v.obj) return -1;
+        return q;
+    }
+
+    // temporal reuse: GRIS of the canonical and the previous frame's final
+    // reservoir with the generalized balance heuristic (Sec. 3.2.3, 3.2.4)
+    void temporal_pass(uint64_t frame, const std::vector<PixelRes>& can, const std::vector<double>& Mc,
+                       std::vector<PixelRes>& out, std::vector<double>& Mo) {
+        out.assign(P, PixelRes());
+        Mo.assign(P, 0.0);
+        std::vector<Stats> ts(nthreads);
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
+        for (int pix = 0; pix < P; ++pix) {
+#ifdef _OPENMP
+            Stats& st = ts[omp_get_thread_num()];
+#else
+            Stats& st = ts[0];
+#endif
+            if (!gb[0][pix].hit) continue;
+            int qp = reproject(pix);
+            double mc = Mc[pix];
+            double mp = qp >= 0 ? std::min(M_prev[qp], s.m_cap) : 0.0;
+            Mo[pix] = mc + mp;
+            std::vector<int> planes;
+            for (auto& kv : can[pix]) planes.push_back(kv.first);
+            if (qp >= 0)
+                for (auto& kv : fin_prev[qp]) planes.push_back(kv.first);
+            std::sort(planes.begin(), planes.end());
+            planes.erase(std::unique(planes.begin(), planes.end()), planes.end());
+            uint64_t fp = full_pixel(pix);
+            for (int pl : planes) {
+                Draw u = draw(s.seed, fp, frame, PASS_TEMPORAL, 0, (uint64_t)pl);
+                double ws = 0.0;
+                bool have = false;
+                PathRec sel;
+                auto itc = can[pix].find(pl);
+                if (itc != can[pix].end()) {
+                    const Res& xr = itc->second;
+                    double ph = xr.y.phat;
+                    double den = mc * ph;
+                    if (qp >= 0) {
+                        ShiftOut sh = shift(xr.y, 0, pix, 1, qp, pl, 0.0, st);
+                        if (sh.ok) den += mp * sh.phat * sh.J;
+                    }
+                    double w = (mc * ph / den) * ph * xr.W;
+                    ws += w;
+                    if (u.u(0) * ws < w) { sel = xr.y; have = true; }
+                }
+                if (qp >= 0) {
+                    auto itp = fin_prev[qp].find(pl);
+                    if (itp != fin_prev[qp].end()) {
+                        const Res& xr = itp->second;
+                        ShiftOut sh = shift(xr.y, 1, qp, 0, pix, pl, 0.0, st);
+                        if (sh.ok) {
+                            double a = mp * xr.y.phat / sh.J;
+                            double m = a / (a + mc * sh.phat);
+                            double w = m * sh.phat * xr.W * sh.J;
+                            ws += w;
+                            if (u.u(1) * ws < w) { sel = sh.y; have = true; }
+                        }
+                    }
+                }
+                if (have && ws > 0.0) {
+                    Res r;
+                    r.y = sel;
+                    r.W = ws / sel.phat;
+                    out[pix][pl] = r;
+                }
+            }
+        }
+        for (auto& t : ts) stats.add(t);
+    }
+
+    // neighbour choice: integer rejection sampling in the disk of radius r
+    void neighbours(int pix, uint64_t frame, int round, std::vector<int>& nb) const {
+        nb.assign(s.spatial_k, -1);
+        int x = pix % s.width, y = pix / s.width;
+        uint64_t fp = full_pixel(pix);
+        int64_t R = s.spatial_radius;
+        uint64_t span = (uint64_t)(2 * R + 1);
+        for (int sl = 0; sl < s.spatial_k; ++sl) {
+            for (int t = 0; t < 8; ++t) {
+                Draw d = draw(s.seed, fp, frame, PASS_SPATIAL + (uint64_t)round, 1, (uint64_t)(sl * 16 + t / 2));
+                uint64_t a = d.x[(t & 1) ? 2 : 0] >> 32, b = d.x[(t & 1) ? 3 : 1] >> 32;
+                int64_t dx = (int64_t)((a * span) >> 32) - R;
+                int64_t dy = (int64_t)((b * span) >> 32) - R;
+                if (dx * dx + dy * dy > R * R || (dx == 0 && dy == 0)) continue;
+                int64_t nx = x + dx, ny = y + dy;
+                if (nx >= 0 && nx < s.width && ny >= 0 && ny < s.height) {
+                    int q = (int)(ny * s.width + nx);
+                    if (gb[0][q].hit) nb[sl] = q;
+                }
+                break;
+            }
+        }
+    }
+
+    // spatial reuse round: canonical + k neighbours, GBH MIS (Sec. 3.2.3)
+    void spatial_pass(uint64_t frame, int round, const std::vector<PixelRes>& in, const std::vector<double>& Mi,
+                      std::vector<PixelRes>& out, std::vector<double>& Mo) {
+        out.assign(P, PixelRes());
+        Mo.assign(P, 0.0);
+        std::vector<Stats> ts(nthreads);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+        for (int pix = 0; pix < P; ++pix) {
+#ifdef _OPENMP
+            Stats& st = ts[omp_get_thread_num()];
+#else
+            Stats& st = ts[0];
+#endif
+            if (!gb[0][pix].hit) continue;
+            std::vector<int> nb;
+            neighbours(pix, frame, round, nb);
+            const int K = s.spatial_k;
+            double mq = Mi[pix];
+            std::vector<double> ms(K, 0.0);
+            double mtot = mq;
+            std::vector<int> planes;
+            for (auto& kv : in[pix]) planes.push_back(kv.first);
+            for (int sl = 0; sl < K; ++sl) {
+                if (nb[sl] < 0) continue;
+                ms[sl] = Mi[nb[sl]];
+                mtot += ms[sl];
+                for (auto& kv : in[nb[sl]]) planes.push_back(kv.first);
+            }
+            Mo[pix] = mtot;
+            std::sort(planes.begin(), planes.end());
+            planes.erase(std::unique(planes.begin(), planes.end()), planes.end());
+            uint64_t fp = full_pixel(pix);
+            for (int pl : planes) {
+                double ws = 0.0;
+                bool have = false;
+                PathRec sel;
+                auto uni = [&](int cand) {
+                    Draw d = draw(s.seed, fp, frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + cand / 4));
+                    return d.u(cand % 4);
+                };
+                auto itq = in[pix].find(pl);
+                if (itq != in[pix].end()) {
+                    const Res& xr = itq->second;
+                    double ph = xr.y.phat;
+                    double den = mq * ph;
+                    for (int l = 0; l < K; ++l) {
+                        if (nb[l] < 0) continue;
+                        ShiftOut sh = shift(xr.y, 0, pix, 0, nb[l], pl, 0.0, st);
+                        if (sh.ok) den += ms[l] * sh.phat * sh.J;
+                    }
+                    double w = (mq * ph / den) * ph * xr.W;
+                    ws += w;
+                    if (uni(0) * ws < w) { sel = xr.y; have = true; }
+                }
+                for (int j = 0; j < K; ++j) {
+                    if (nb[j] < 0) continue;
+                    auto itj = in[nb[j]].find(pl);
+                    if (itj == in[nb[j]].end()) continue;
+                    const Res& xr = itj->second;
+                    ShiftOut sh = shift(xr.y, 0, nb[j], 0, pix, pl, 0.0, st);
+                    if (!sh.ok) continue;
+                    double a = ms[j] * xr.y.phat / sh.J;
+                    double den = a + mq * sh.phat;
+                    for (int l = 0; l < K; ++l) {
+                        if (l == j || nb[l] < 0) continue;
+                        ShiftOut t2 = shift(sh.y, 0, pix, 0, nb[l], pl, 0.0, st);
+                        if (t2.ok) den += ms[l] * t2.phat * t2.J;
+                    }
+                    double w = (a / den) * sh.phat * xr.W * sh.J;
+                    ws += w;
+                    if (uni(j + 1) * ws < w) { sel = sh.y; have = true; }
+                }
+                if (have && ws > 0.0) {
+                    Res r;
+                    r.y = sel;
+                    r.W = ws / sel.phat;
+                    out[pix][pl] = r;
+                }
+            }
+        }
+        for (auto& t : ts) stats.add(t);
+    }
+
+    int render(const orc_frame* fr, double* img, double* hist, double* pt_img, double* pt_hist) {
+        // rotate: the previous call's frame becomes slot 1
+        if (fg[0].valid) {
+            fg[1] = fg[0];
+            gb[1] = gb[0];
+        }
+        load_frame(fg[0], fr);
+        uint64_t frame = (uint64_t)(uint32_t)fr->index;
+        gbuffer_pass(0, frame);
+        std::vector<PixelRes> can, tmp, fin;
+        std::vector<double> Mc, Mt, Mf, pt, dc, dl;
+        initial_pass(frame, can, Mc, pt, dc, dl);
+        const std::vector<PixelRes>* cur = &can;
+        const std::vector<double>* curM = &Mc;
+        if (s.temporal && prev_valid) {
+            temporal_pass(frame, can, Mc, tmp, Mt);
+            cur = &tmp;
+            curM = &Mt;
+        }
+        const std::vector<PixelRes>* stage_t = cur;
+        std::vector<PixelRes> rin;
+        std::vector<double> rM;
+        for (int r = 0; r < s.spatial_rounds; ++r) {
+            std::vector<PixelRes> o;
+            std::vector<double> oM;
+            spatial_pass(frame, r, *cur, *curM, o, oM);
+            rin.swap(o);
+            rM.swap(oM);
+            cur = &rin;
+            curM = &rM;
+        }
+        fin = *cur;
+        Mf = *curM;
+        const std::vector<PixelRes>* shown = s.debug_stage == 0 ? &can : (s.debug_stage == 1 ? stage_t : &fin);
+        auto splat = [&](int pl, int pix, bool restir) {
+            double v = 0.0;
+            if (restir) {
+                auto it = (*shown)[pix].find(pl);
+                if (it != (*shown)[pix].end()) v = it->second.W * it->second.y.phat;
+            } else {
+                v = pt[(size_t)pl * P + pix];
+            }
+            if (s.include_direct && dc[pix] > 0.0 && in_plane(pl, dl[pix])) v += dc[pix];
+            return v / plane_width(pl);
+        };
+        for (int pix = 0; pix < P; ++pix) {
+            if (s.gate_enabled) {
+                if (img) img[pix] = splat(s.n_bins, pix, true);
+                if (pt_img) pt_img[pix] = splat(s.n_bins, pix, false);
+            }
+            for (int b = 0; b < s.n_bins; ++b) {
+                if (hist) hist[(size_t)b * P + pix] = splat(b, pix, true);
+                if (pt_hist) pt_hist[(size_t)b * P + pix] = splat(b, pix, false);
+            }
+        }
+        fin_prev.swap(fin);
+        M_prev.swap(Mf);
+        prev_valid = true;
+        return 0;
+    }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void* orc_create(const orc_scene* sc, const orc_sensor* sn, int num_threads) {
+    Oracle* o = new Oracle();
+    o->s = *sn;
+    o->nthreads = num_threads > 0 ? num_threads : 1;
+    for (int m = 0; m < sc->num_materials; ++m)
+        o->mats.push_back({sc->mat_type[m], (double)sc->mat_params[3 * m], (double)sc->mat_params[3 * m + 1],
+                           (double)sc->mat_params[3 * m + 2]});
+    for (int v = 0; v < sc->num_vertices; ++v)
+        o->lverts.push_back(V3(sc->vertices[3 * v], sc->vertices[3 * v + 1], sc->vertices[3 * v + 2]));
+    for (int ob = 0; ob < sc->num_objects; ++ob) {
+        Object obj;
+        obj.type = sc->obj_type[ob];
+        obj.material = sc->obj_material[ob];
+        const int32_t* g = sc->obj_grid + 5 * ob;
+        obj.nu = g[0]; obj.nv = g[1]; obj.wrap_u = g[2]; obj.wrap_v = g[3]; obj.voff = g[4];
+        const float* sp = sc->obj_sphere + 4 * ob;
+        obj.centre = V3(sp[0], sp[1], sp[2]);
+        obj.radius = sp[3];
+        obj.tri_base = (int)o->tris.size();
+        if (obj.type == 0)
+            for (int j = 0; j < obj.nv; ++j)
+                for (int i = 0; i < obj.nu; ++i)
+                    for (int h = 0; h < 2; ++h) o->tris.push_back({ob, i, j, h});
+        o->objs.push_back(obj);
+    }
+    o->sc = sc->scene_scale;
+    o->eps = 1e-4 * o->sc;
+    o->dmin = 0.01 * o->sc;
+    o->P = sn->width * sn->height;
+    o->B = sn->n_bins + (sn->gate_enabled ? 1 : 0);
+    return o;
+}
+
+void orc_destroy(void* ctx) { delete (Oracle*)ctx; }
+
+void orc_reset(void* ctx) {
+    Oracle* o = (Oracle*)ctx;
+    o->prev_valid = false;
+    o->fin_prev.clear();
+    o->M_prev.clear();
+}
+
+int orc_render_frame(void* ctx, const orc_frame* frame, double* out_image, double* out_hist, double* out_pt_image,
+                     double* out_pt_hist) {
+    return ((Oracle*)ctx)->render(frame, out_image, out_hist, out_pt_image, out_pt_hist);
+}
+
+void orc_get_stats(void* ctx, uint64_t out[8]) {
+    Oracle* o = (Oracle*)ctx;
+    for (int i = 0; i < 8; ++i) out[i] = o->stats.c[i];
+}
+
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) { philox4x64_10(ctr, key, out); }
+
+int orc_load_frame(void* ctx, const orc_frame* frame) {
+    Oracle* o = (Oracle*)ctx;
+    o->load_frame(o->fg[0], frame);
+    return 0;
+}
+
+int orc_trace(void* ctx, const double o3[3], const double d3[3], int brute_force, double out[4]) {
+    Oracle* o = (Oracle*)ctx;
+    V3 org(o3[0], o3[1], o3[2]), dir = normalize(V3(d3[0], d3[1], d3[2]));
+    Oracle::Hit h = o->closest(o->fg[0], org, dir, brute_force != 0);
+    if (!h.hit) return -1;
+    Vertex v = o->hit_vertex(o->fg[0], h, org, dir);
+    out[0] = h.t;
+    out[1] = h.obj;
+    out[2] = v.xi[0];
+    out[3] = v.xi[1];
+    return h.prim;
+}
+
+int orc_chart(void* ctx, int obj, const double xi[2], double out[12]) {
+    Oracle* o = (Oracle*)ctx;
+    ChartEval c = o->chart(o->fg[0], obj, xi[0], xi[1]);
+    V3 vs[4] = {c.p, c.ju, c.jv, c.n};
+    for (int k = 0; k < 4; ++k) {
+        out[3 * k] = vs[k].x;
+        out[3 * k + 1] = vs[k].y;
+        out[3 * k + 2] = vs[k].z;
+    }
+    return (c.on && c.ok) ? 1 : 0;
+}
+
+int orc_newton(void* ctx, int obj, const double xi[2], const double as[3], const double bs[3], double cs,
+               const double ad[3], const double bd[3], double cd, double dl0, double tol, int max_iter,
+               double out[8]) {
+    Oracle* o = (Oracle*)ctx;
+    Oracle::NewtonOut no = o->newton(o->fg[0], o->fg[0], obj, xi, V3(as[0], as[1], as[2]), V3(bs[0], bs[1], bs[2]),
+                                     cs, V3(ad[0], ad[1], ad[2]), V3(bd[0], bd[1], bd[2]), cd, dl0, tol, max_iter);
+    out[0] = no.xi[0];
+    out[1] = no.xi[1];
+    out[2] = no.iters;
+    out[3] = no.det_dxi;
+    out[4] = no.det_area;
+    out[5] = no.F[0];
+    out[6] = no.F[1];
+    out[7] = no.status;
+    return no.conv ? 1 : 0;
+}
+
+int orc_wrs(const double* w, const double* u, int n, double* w_sum) {
+    double ws = 0.0;
+    int sel = -1;
+    for (int i = 0; i < n; ++i) {
+        ws += w[i];
+        if (u[i] * ws < w[i]) sel = i;
+    }
+    *w_sum = ws;
+    return sel;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+/*
+ * ToF ReSTIR CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 reference implementation of the ToF ReSTIR frame
+ * (path trees with NEE, per-bin RIS reservoirs, temporal and spatial GRIS
+ * reuse with the path-length-aware Newton shift, splat).  It exists so that
+ * tests, the smoke check and the benchmark's CPU baseline can compare the
+ * HIP path against it; no product code may link or call it.
+ *
+ * It shares no code with the HIP library: every routine here (Philox, BVH,
+ * intersection, BSDFs, shift, reuse) is written separately.
+ *
+ * Parity status of each part is listed at the top of oracle.cpp.
+ */
+#ifndef TOF_ORACLE_H
+#define TOF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t num_objects;
+    const int32_t* obj_type;      /* 0 = grid, 1 = sphere */
+    const int32_t* obj_material;
+    const int32_t* obj_grid;      /* [num_objects*5]: nu, nv, wrap_u, wrap_v, vertex_offset */
+    const float* obj_sphere;      /* [num_objects*4]: local centre xyz, radius */
+    int32_t num_materials;
+    const int32_t* mat_type;      /* 0 = Lambert, 1 = GGX */
+    const float* mat_params;      /* [num_materials*3]: albedo, alpha, f0 */
+    int32_t num_vertices;
+    const float* vertices;        /* [num_vertices*3] object-local */
+    float scene_scale;
+} orc_scene;
+
+typedef struct {
+    int32_t width, height, full_width, full_height, crop_x0, crop_y0;
+    int32_t camera_model, light_model, count_camera_leg, jitter;
+    double light_intensity;
+    int32_t gate_enabled;
+    double gate_center, gate_width;
+    int32_t n_bins;
+    double bin_t0, bin_width;
+    int32_t n_min, n_max, m_init, temporal, spatial_rounds, spatial_k, spatial_radius;
+    double m_cap, newton_tol_rel;
+    int32_t newton_max_iter;
+    double j_max;
+    int32_t shift_mode, include_direct, debug_stage;
+    uint64_t seed;
+} orc_sensor;
+
+typedef struct {
+    int32_t index;
+    float cam_pos[3], cam_fwd[3], cam_up[3];
+    float fov_y_deg;
+    float ortho_half[2];
+    float light_pos[3];
+    const float* xforms;          /* [num_objects*12], rigid 3x4 row-major */
+} orc_frame;
+
+/* lifecycle */
+void* orc_create(const orc_scene* scene, const orc_sensor* sensor, int num_threads);
+void orc_destroy(void* ctx);
+void orc_reset(void* ctx);
+
+/* One full frame.  Outputs are FP64, plane-major [B][H][W]; any may be NULL.
+ * gate image = gate plane / gate width; histogram bins / bin width.
+ * pt_* are the plain (no reuse) ToF path-tracing estimates of the same frame.
+ * Returns 0 on success. */
+int orc_render_frame(void* ctx, const orc_frame* frame, double* out_image, double* out_hist,
+                     double* out_pt_image, double* out_pt_hist);
+
+/* Counters: shifts, shifts_ok, newton_attempts, newton_converged,
+ * newton_iters_sum, newton_paths_ok, rays, reserved. */
+void orc_get_stats(void* ctx, uint64_t out[8]);
+
+/* ---- unit-level entry points used by the pin tests ---- */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* Make `frame` the current frame geometry (slot 0) without rendering. */
+int orc_load_frame(void* ctx, const orc_frame* frame);
+
+/* Closest hit in the current frame.  Returns the primitive id (triangles
+ * first, then spheres) or -1; out = {t, object, xi0, xi1}. */
+int orc_trace(void* ctx, const double o[3], const double d[3], int brute_force, double out[4]);
+
+/* Position, chart Jacobian and normal of chart point (obj, xi) in the current
+ * frame.  out = {p(3), J_u(3), J_v(3), n(3)}.  Returns 1 if xi is on the chart. */
+int orc_chart(void* ctx, int obj, const double xi[2], double out[12]);
+
+/* Path-length Newton solve on object `obj` in the current frame.
+ * Source length L_src(xi) = c_src + |a_src - p(xi)| + |b_src - p(xi)|, same for
+ * the destination.  out = {xi'0, xi'1, iterations, |det dxi'/dxi|,
+ * |det dp'/dp|, F1, F2, status}.  Returns 1 on convergence. */
+int orc_newton(void* ctx, int obj, const double xi[2], const double a_src[3], const double b_src[3],
+               double c_src, const double a_dst[3], const double b_dst[3], double c_dst,
+               double dl0, double tol, int max_iter, double out[8]);
+
+/* Weighted reservoir streaming of n candidate weights with uniforms u. */
+int orc_wrs(const double* w, const double* u, int n, double* w_sum);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,153 @@
+"""Statistical pins of the oracle's estimators.
+
+* Closed-form transient of a Lambertian plane under a co-located point light
+  (direct light; derived from the ToF path integral, Sec. 3.1): summed over
+  the image plane, sum_q I_q a_p = (4 rho I / d)(1/l_lo - 1/l_hi) for a bin
+  [l_lo, l_hi) whose ring lies inside the field of view.
+* Closed-form 2- and 3-bounce transients inside a Lambertian sphere with the
+  camera and light at its centre: between two points of a sphere
+  cos*cos/r^2 = 1/(4R^2), so the chord length c has density c/(2R^2) on
+  [0, 2R] and h_2(l) = rho^2 I/(pi R^2) * (l-2R)/(2R^2); h_3 is the
+  convolution of two chord densities times rho^3 I/(pi R^2).
+* Unbiasedness of ToF ReSTIR (GRIS is unbiased, Sec. 3.2.3): its per-pixel
+  mean over independent seeds equals plain path tracing's, including with
+  Newton forced to fail and with the naive (non path-length-aware) shift.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_11536_amd import scenes
+
+
+def _chord_pdf(c, R):
+    return np.where((c >= 0) & (c <= 2 * R), c / (2 * R * R), 0.0)
+
+
+def test_plane_transient_closed_form(oracle_lib):
+    d, rho, I = 1.0, 0.5, 1.0
+    nb, t0, bw = 12, 2.0, 0.025
+    w = scenes.lambert_plane(depth=d, albedo=rho, intensity=I, width=256, height=256, fov=60.0,
+                             n_bins=nb, bin_t0=t0, bin_width=bw, gate_enabled=1,
+                             gate_center=2.1, gate_width=0.05)
+    o = oracle_lib.Oracle(w.scene, w.sensor)
+    tan_half = math.tan(math.radians(30.0))
+    a_p = (2 * tan_half / 256) ** 2
+    sums = []
+    gates = []
+    for f in range(20):
+        fr = w.frames[0]
+        fr.index = f
+        out = o.render(fr)
+        sums.append(out["pt_hist"].sum(axis=(1, 2)) * a_p * bw)
+        gates.append(out["pt_image"].sum() * a_p * 0.05)
+    sums = np.array(sums)
+    lo = t0 + bw * np.arange(nb)
+    hi = lo + bw
+    exp = 4 * rho * I / d * (1 / lo - 1 / hi)
+    mean = sums.mean(0)
+    se = sums.std(0, ddof=1) / math.sqrt(len(sums)) + 1e-12
+    assert np.all(np.abs(mean - exp) < 4.5 * se), (mean / exp)
+    assert np.mean(gates) == pytest.approx(4 * rho * I / d * (1 / 2.075 - 1 / 2.125), rel=5e-3)
+    # ReSTIR with only the deterministic direct term equals plain PT exactly
+    assert np.allclose(out["hist"], out["pt_hist"])
+
+
+def _sphere_expect(rho, I, R, lo, hi, bounces):
+    """Bin-averaged closed-form transient inside the sphere."""
+    out = []
+    for a, b in zip(lo, hi):
+        ls = np.linspace(a, b, 401)
+        if bounces == 2:
+            h = rho ** 2 * I / (math.pi * R * R) * _chord_pdf(ls - 2 * R, R)
+        else:
+            cs = np.linspace(0, 2 * R, 4001)
+            h = []
+            for l in ls:
+                s = l - 2 * R
+                h.append(np.trapezoid(_chord_pdf(cs, R) * _chord_pdf(s - cs, R), cs))
+            h = rho ** 3 * I / (math.pi * R * R) * np.array(h)
+        out.append(np.trapezoid(h, ls) / (b - a))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("bounces", [2, 3])
+def test_sphere_interior_closed_form_plain_pt(oracle_lib, bounces):
+    R, rho, I = 1.0, 0.5, 1.0
+    nb = 20 if bounces == 2 else 40
+    w = scenes.lambert_sphere_interior(radius=R, albedo=rho, intensity=I, width=32, height=32,
+                                       n_min=bounces, n_max=bounces, n_bins=nb, bin_width=0.1,
+                                       temporal=0, spatial_rounds=0)
+    o = oracle_lib.Oracle(w.scene, w.sensor)
+    per = []
+    for f in range(24):
+        fr = w.frames[0]
+        fr.index = f
+        per.append(o.render(fr)["pt_hist"].mean(axis=(1, 2)))
+    per = np.array(per)
+    lo = 2 * R + 0.1 * np.arange(nb)
+    exp = _sphere_expect(rho, I, R, lo, lo + 0.1, bounces)
+    mean, se = per.mean(0), per.std(0, ddof=1) / math.sqrt(len(per))
+    assert np.all(np.abs(mean - exp) < 4.5 * se + 1e-3 * exp.max()), (mean - exp) / (se + 1e-15)
+    assert abs(mean.sum() - exp.sum()) < 4 * math.sqrt((se ** 2).sum())
+
+
+def test_sphere_interior_closed_form_restir(oracle_lib):
+    """ReSTIR (temporal + spatial, path-length-aware shift on the curved
+    sphere chart) matches the closed form in expectation over seeds."""
+    R, rho, I = 1.0, 0.5, 1.0
+    nb = 20
+    lo = 2 * R + 0.1 * np.arange(nb)
+    exp = _sphere_expect(rho, I, R, lo, lo + 0.1, 2)
+    per = []
+    for seed in range(16):
+        w = scenes.lambert_sphere_interior(radius=R, albedo=rho, intensity=I, width=24, height=24,
+                                           n_bins=nb, frames=3, seed=seed)
+        o = oracle_lib.Oracle(w.scene, w.sensor)
+        for fr in w.frames:
+            out = o.render(fr)
+        per.append(out["hist"].mean(axis=(1, 2)))
+        o.close()
+    per = np.array(per)
+    mean, se = per.mean(0), per.std(0, ddof=1) / math.sqrt(len(per))
+    assert np.all(np.abs(mean - exp) < 4.5 * se + 1e-3 * exp.max()), (mean - exp) / (se + 1e-15)
+    assert abs(mean.sum() - exp.sum()) < 4 * math.sqrt((se ** 2).sum())
+
+
+def _unbiased_case(oracle_lib, seeds, **kw):
+    r_img, p_img = [], []
+    for seed in range(seeds):
+        w = scenes.cornell_box(width=32, height=32, frames=3, seed=seed, gate_width=0.2,
+                               spatial_radius=4, **kw)
+        o = oracle_lib.Oracle(w.scene, w.sensor)
+        pts = []
+        for fr in w.frames:
+            out = o.render(fr)
+            pts.append(out["pt_image"])
+        r_img.append(out["image"])
+        p_img.append(np.mean(pts, 0))
+        o.close()
+    return np.array(r_img), np.array(p_img)
+
+
+@pytest.mark.parametrize("variant", ["pathlen", "newton_fails", "naive"])
+def test_restir_unbiased_against_plain_pt(oracle_lib, variant):
+    kw = {}
+    if variant == "newton_fails":
+        kw = dict(newton_max_iter=0)
+    elif variant == "naive":
+        kw = dict(shift_mode=scenes.SHIFT_NAIVE)
+    n = 96
+    R, Pt = _unbiased_case(oracle_lib, n, **kw)
+    # sensor sum per seed: independent across seeds
+    rs, ps = R.sum(axis=(1, 2)), Pt.sum(axis=(1, 2))
+    z_sum = (rs.mean() - ps.mean()) / math.sqrt(rs.var(ddof=1) / n + ps.var(ddof=1) / n)
+    assert abs(z_sum) < 3.5, z_sum
+    # per pixel (pixels with signal in both)
+    mr, mp = R.mean(0), Pt.mean(0)
+    vr, vp = R.var(0, ddof=1) / n, Pt.var(0, ddof=1) / n
+    mask = (vr > 0) & (vp > 0)
+    z = (mr - mp)[mask] / np.sqrt(vr + vp)[mask]
+    assert mask.sum() > 50
+    assert np.mean(np.abs(z) > 3.5) <= 0.01, np.mean(np.abs(z) > 3.5)
