@@ -1,0 +1,204 @@
+/*
+ * tof.h -- C ABI of the ToF ReSTIR hot path on AMD Instinct MI355X (gfx950).
+ *
+ * The library renders time-of-flight measurements -- a time-gated image and/or
+ * a transient histogram per frame -- with spatio-temporal reservoir
+ * resampling and the path-length-aware shift of Kim, Jarosz and Pediredla,
+ * "ToF ReSTIR" (ACM TOG 45(4), 2026):
+ *   - the measurement is the ToF path integral (Sec. 3.1,
+ *     eq. tof_path_integral) with box time gates;
+ *   - per pixel and per time bin a reservoir is filled by RIS over path-tree
+ *     sub-paths (Sec. 3.2.1, 3.2.4; Sec. 4.5 per-bin deposit);
+ *   - temporal and spatial reuse use generalized RIS with the generalized
+ *     balance heuristic (Sec. 3.2.3, eq. GRIS_resampling_weight and
+ *     eq. GRIS_MIS_weight);
+ *   - reused paths are shifted by random replay + reconnection and then the
+ *     reconnection vertex is moved by a Newton solve so that the shifted path
+ *     keeps its optical length (Sec. 4.1 eq. path_length_constraint, Sec. 4.2,
+ *     Sec. 4.3 average-gradient gauge and implicit-function Jacobian).
+ *
+ * Conventions shared by every entry point:
+ *   - Status codes only; no exception crosses the ABI.  On any error nothing
+ *     observable changes (no partial state).
+ *   - Host pointers passed in descriptors are read during the call only; the
+ *     caller keeps ownership.  Device pointers (outputs) are owned by the
+ *     caller and must stay valid until the work enqueued on `stream` finishes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - One context per host thread, or external locking.
+ *   - Units: c = 1, so time and optical path length are the same quantity.
+ */
+#ifndef TOF_H
+#define TOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tof_ctx tof_ctx;
+
+typedef enum {
+    TOF_OK = 0,
+    TOF_ERR_INVALID_ARG = -1,      /* a NULL/out-of-range argument or inconsistent descriptor */
+    TOF_ERR_OUT_OF_MEMORY = -2,    /* footprint above the context's HBM budget, or hipMalloc failed */
+    TOF_ERR_INVALID_SCENE = -3,    /* NaN/Inf vertices, bad object ranges, degenerate objects */
+    TOF_ERR_NOT_READY = -4,        /* render before a scene upload and a sensor set */
+    TOF_ERR_DEVICE = -5,           /* a HIP runtime error (launch, copy, fault) */
+    TOF_ERR_UNIMPLEMENTED = -6
+} tof_status;
+
+enum { TOF_OBJ_GRID = 0, TOF_OBJ_SPHERE = 1 };
+enum { TOF_MAT_LAMBERT = 0, TOF_MAT_GGX = 1 };
+enum { TOF_CAMERA_PINHOLE = 0, TOF_CAMERA_ORTHO = 1 };
+enum { TOF_LIGHT_POINT = 0, TOF_LIGHT_CONFOCAL = 1 };
+enum { TOF_SHIFT_NAIVE = 0, TOF_SHIFT_PATHLEN = 1 };
+enum { TOF_STAGE_CANONICAL = 0, TOF_STAGE_TEMPORAL = 1, TOF_STAGE_FINAL = 2 };
+
+/* Scene: rigid objects made of a regular vertex lattice ("grid": cell (i,j)
+ * split into triangles (V[i,j],V[i+1,j],V[i,j+1]) and (V[i+1,j+1],V[i,j+1],
+ * V[i+1,j]); the surface chart is xi = (u,v) in cell units) or analytic
+ * spheres (chart xi = (theta, phi) about the object's local z axis).  These
+ * charts carry the 2-D parameterisation of the reconnection vertex
+ * (Sec. 4.2).  All arrays are host memory, copied during the call. */
+typedef struct {
+    int32_t num_objects;
+    const int32_t* object_type;      /* [num_objects] TOF_OBJ_* */
+    const int32_t* object_material;  /* [num_objects] index into the material arrays */
+    const int32_t* object_grid;      /* [num_objects*5] nu, nv, wrap_u, wrap_v, vertex_offset
+                                        (grid: (nu+1)*(nv+1) object-local vertices, row-major in v) */
+    const float* object_sphere;      /* [num_objects*4] local centre xyz, radius (spheres) */
+    int32_t num_materials;
+    const int32_t* material_type;    /* [num_materials] TOF_MAT_* */
+    const float* material_params;    /* [num_materials*3] albedo (Lambert), alpha, F0 (GGX) */
+    int32_t num_vertices;
+    const float* vertices;           /* [num_vertices*3] object-local positions */
+    float scene_scale;               /* s_c: ray offsets are 1e-4*s_c, reconnection distance 0.01*s_c */
+} tof_scene_desc;
+
+/* Sensor, time domain and reuse settings.  The time domain is a gate
+ * [gate_center - gate_width/2, gate_center + gate_width/2) and/or n_bins
+ * histogram bins [bin_t0 + b*bin_width, bin_t0 + (b+1)*bin_width); each has its
+ * own reservoir plane per pixel (Sec. 4.5).  Rendering may be restricted to a
+ * crop [crop_x0, crop_x0+width) x [crop_y0, crop_y0+height) of a full_width x
+ * full_height image (random streams are keyed by full-image pixel index). */
+typedef struct {
+    int32_t width, height, full_width, full_height, crop_x0, crop_y0;
+    int32_t camera_model;            /* TOF_CAMERA_*; ORTHO scans a plane (NLOS relay wall) */
+    int32_t light_model;             /* TOF_LIGHT_*; CONFOCAL = laser spot at each pixel's primary hit */
+    int32_t count_camera_leg;        /* include |camera - first hit| in the path length */
+    int32_t jitter;                  /* box-filter pixel jitter */
+    float light_intensity;           /* point intensity, or laser power for CONFOCAL */
+    int32_t gate_enabled;
+    float gate_center, gate_width;
+    int32_t n_bins;
+    float bin_t0, bin_width;
+    int32_t n_min, n_max;            /* scattering vertices per path, 1 <= n_min <= n_max <= 4 */
+    int32_t m_init;                  /* path trees per pixel, 1..32 */
+    int32_t temporal;                /* temporal reuse on/off */
+    int32_t spatial_rounds, spatial_k, spatial_radius;   /* rounds 0..4, k 0..8, radius px */
+    float m_cap;                     /* confidence cap of the temporal candidate */
+    float newton_tol_rel;            /* Newton tolerance as a fraction of the gate/bin width */
+    int32_t newton_max_iter;
+    float j_max;                     /* shifts with |J| outside [1/j_max, j_max] are rejected */
+    int32_t shift_mode;              /* TOF_SHIFT_NAIVE (replay+reconnect) or TOF_SHIFT_PATHLEN */
+    int32_t include_direct;          /* add the deterministic 1-vertex term */
+    int32_t debug_stage;             /* TOF_STAGE_*: which reservoirs the splat shows */
+} tof_sensor_desc;
+
+/* Per-frame poses.  object_xforms: host [num_objects*12], rigid 3x4 row-major
+ * [R | t] mapping object-local to world coordinates for this frame. */
+typedef struct {
+    int32_t frame_index;             /* keys the random streams of this frame */
+    float cam_pos[3], cam_fwd[3], cam_up[3];
+    float fov_y_deg;                 /* pinhole vertical field of view */
+    float ortho_half[2];             /* orthographic half extents */
+    float light_pos[3];              /* point light position */
+    const float* object_xforms;
+} tof_frame_desc;
+
+typedef struct {
+    uint64_t shifts;                 /* shift attempts (temporal + spatial, incl. MIS shifts) */
+    uint64_t shifts_ok;              /* shifts with a non-zero target in the destination */
+    uint64_t newton_attempts;        /* path-length shifts that reached the Newton solve */
+    uint64_t newton_converged;       /* "Newton SR" numerator (Sec. 6, Table 1) */
+    uint64_t newton_iters;           /* iterations summed over converged solves */
+    uint64_t newton_paths_ok;        /* "actual SR" numerator: converged and fully valid */
+    uint64_t rays;                   /* closest-hit + shadow rays traced */
+    uint64_t frames;                 /* frames rendered */
+    uint64_t bvh_overflow;           /* traversal stack overflows (must be 0) */
+} tof_stats;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps what the
+ * context may allocate (0 = no cap).  seed keys every random stream
+ * (Philox4x64-10 with key (seed, 0)).  *out receives the context. */
+tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64_t seed);
+
+/* Release every device allocation of the context (synchronizes the device). */
+void tof_destroy(tof_ctx* ctx);
+
+/* Copy the scene to the device and validate it.  Drops reservoir history. */
+tof_status tof_scene_upload(tof_ctx* ctx, const tof_scene_desc* scene);
+
+/* Set sensor and time-domain settings and (re)allocate per-pixel state after
+ * checking the footprint against the budget.  Any change drops the temporal
+ * history (reservoirs are reset). */
+tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
+
+/* Render one frame asynchronously on `stream`: BVH build for the frame's
+ * transforms, G-buffer, path trees + initial RIS, temporal reuse (when a
+ * previous frame exists), spatial rounds, splat.  Outputs are device float32
+ * arrays owned by the caller, plane-major, each value divided by its gate or
+ * bin width; any may be NULL:
+ *   out_image    [height*width]           ReSTIR gate image
+ *   out_hist     [n_bins*height*width]    ReSTIR transient histogram
+ *   out_pt_image / out_pt_hist            plain ToF path tracing of the same frame
+ * Errors: TOF_ERR_NOT_READY without scene+sensor; TOF_ERR_INVALID_ARG for a
+ * NULL frame/xforms or an image requested without a gate; TOF_ERR_DEVICE on a
+ * HIP error. */
+tof_status tof_render_frame(tof_ctx* ctx, const tof_frame_desc* frame, float* out_image, float* out_hist,
+                            float* out_pt_image, float* out_pt_hist, void* stream);
+
+/* Drop the temporal history: the next frame renders without temporal reuse. */
+tof_status tof_reservoirs_reset(tof_ctx* ctx);
+
+/* Accumulated counters (synchronizes the device). */
+tof_status tof_get_stats(tof_ctx* ctx, tof_stats* out);
+
+/* Reservoir planes of one reservoir set in host memory.  P = width*height,
+ * B = n_bins + gate_enabled; element [plane*P + pixel].  meta packs
+ * tree | n<<8 | k<<12 | nsfx<<16 (n = path vertices, k = reconnection index,
+ * 0 = pure replay); vertex_obj is [4][P*B] (x_{k-1}, p, next vertex or -1 for
+ * the light, suffix vertex); vertex_xi is [4][2][P*B] chart coordinates;
+ * M is the per-pixel confidence; mask bit (plane) of word [plane/32][pixel]
+ * marks non-empty reservoirs. */
+typedef struct {
+    const float* W;
+    const float* phat;
+    const float* len;
+    const float* pre_pdf;
+    const uint32_t* origin_pixel;
+    const uint32_t* origin_frame;
+    const uint32_t* meta;
+    const int32_t* vertex_obj;
+    const float* vertex_xi;
+    const float* M;
+    const uint32_t* mask;
+} tof_history_desc;
+
+/* Test support (per-frame parity from an identical history): replace the
+ * temporal history -- the final reservoirs of the previously rendered frame --
+ * with host-provided reservoirs.  Needs one rendered frame (its G-buffer and
+ * geometry stay those of that frame).  Synchronous.  TOF_ERR_NOT_READY before
+ * the first frame; TOF_ERR_INVALID_ARG on NULL pointers or out-of-range
+ * object ids. */
+tof_status tof_debug_set_history(tof_ctx* ctx, const tof_history_desc* history);
+
+/* Static string for a status code. */
+const char* tof_status_string(tof_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOF_H */

@@ -859,8 +859,9 @@ struct Oracle {
         if (x.k == 0) {   // pure random replay
             double len;
             double C = path_eval(dst_slot, dst_pix, ys, len);
+            if (!(C > 0.0)) return R;
             st.c[ST_RAYS]++;
-            if (C <= 0.0 || !light_visible(dst_slot, dst_pix, ys.back())) return R;
+            if (!light_visible(dst_slot, dst_pix, ys.back())) return R;
             double J = x.pre_pdf / pdf_y;
             if (!(J >= 1.0 / s.j_max && J <= s.j_max)) return R;
             double ph = in_plane(plane, len) ? C : 0.0;
@@ -1452,6 +1453,37 @@ int orc_render_frame(void* ctx, const orc_frame* frame, double* out_image, doubl
 void orc_get_stats(void* ctx, uint64_t out[8]) {
     Oracle* o = (Oracle*)ctx;
     for (int i = 0; i < 8; ++i) out[i] = o->stats.c[i];
+}
+
+int orc_export_history(void* ctx, float* W, float* phat, float* len, float* pre_pdf, uint32_t* opix, uint32_t* ofr,
+                       uint32_t* meta, int32_t* vobj, float* vxi, float* M, uint32_t* mask) {
+    Oracle* o = (Oracle*)ctx;
+    if (!o->prev_valid) return 1;
+    const size_t P = (size_t)o->P, B = (size_t)o->B, PB = P * B;
+    const size_t words = (B + 31) / 32;
+    for (size_t i = 0; i < words * P; ++i) mask[i] = 0u;
+    for (size_t pix = 0; pix < P; ++pix) {
+        M[pix] = (float)o->M_prev[pix];
+        for (const auto& kv : o->fin_prev[pix]) {
+            const size_t pl = (size_t)kv.first, idx = pl * P + pix;
+            const PathRec& y = kv.second.y;
+            W[idx] = (float)kv.second.W;
+            phat[idx] = (float)y.phat;
+            len[idx] = (float)y.len;
+            pre_pdf[idx] = (float)y.pre_pdf;
+            opix[idx] = y.opix;
+            ofr[idx] = y.ofr;
+            meta[idx] = (uint32_t)y.tree | ((uint32_t)y.n << 8) | ((uint32_t)y.k << 12) | ((uint32_t)y.nsfx << 16);
+            const VRef* vr[4] = {&y.xkm1, &y.p, &y.p2, &y.sfx[0]};
+            for (int q = 0; q < 4; ++q) {
+                vobj[q * PB + idx] = vr[q]->obj;
+                vxi[(2 * q) * PB + idx] = (float)vr[q]->xi[0];
+                vxi[(2 * q + 1) * PB + idx] = (float)vr[q]->xi[1];
+            }
+            mask[(pl >> 5) * P + pix] |= 1u << (pl & 31);
+        }
+    }
+    return 0;
 }
 
 void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) { philox4x64_10(ctr, key, out); }

@@ -76,6 +76,16 @@ int orc_render_frame(void* ctx, const orc_frame* frame, double* out_image, doubl
  * newton_iters_sum, newton_paths_ok, rays, reserved. */
 void orc_get_stats(void* ctx, uint64_t out[8]);
 
+/* Export the final reservoirs of the last rendered frame (the temporal
+ * history of the next frame) in a flat plane-major layout, element
+ * [plane*P + pixel]: W, phat, len, pre_pdf, origin pixel, origin frame,
+ * meta = tree | n<<8 | k<<12 | nsfx<<16, vertex objects [4][P*B] (-1 = none
+ * or light), vertex chart coordinates [4][2][P*B], M [P], non-empty mask
+ * [ceil(B/32)][P].  Values are rounded to float32.  Returns 0 if a history
+ * exists. */
+int orc_export_history(void* ctx, float* W, float* phat, float* len, float* pre_pdf, uint32_t* opix, uint32_t* ofr,
+                       uint32_t* meta, int32_t* vobj, float* vxi, float* M, uint32_t* mask);
+
 /* ---- unit-level entry points used by the pin tests ---- */
 void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 

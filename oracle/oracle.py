@@ -69,6 +69,9 @@ def lib():
         _lib.orc_chart.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p]
         _lib.orc_newton.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p, _f64p, C.c_double, _f64p, _f64p,
                                     C.c_double, C.c_double, C.c_double, C.c_int, _f64p]
+        _u32p = C.POINTER(C.c_uint32)
+        _lib.orc_export_history.argtypes = [C.c_void_p, _f32p, _f32p, _f32p, _f32p, _u32p, _u32p, _u32p, _i32p,
+                                            _f32p, _f32p, _u32p]
         _lib.orc_wrs.restype = C.c_int
         _lib.orc_wrs.argtypes = [_f64p, _f64p, C.c_int, _f64p]
     return _lib
@@ -142,8 +145,11 @@ class Oracle:
         sc.vertices = _p(arrs["vertices"], _f32p)
         sc.scene_scale = scene.scene_scale
         sn = OrcSensor()
-        for name, _t in OrcSensor._fields_:
-            setattr(sn, name, getattr(sensor, name))
+        for name, t in OrcSensor._fields_:
+            v = getattr(sensor, name)
+            if t is C.c_double:   # the same float32 value the HIP library receives
+                v = float(np.float32(v))
+            setattr(sn, name, v)
         self.sensor = sensor
         nt = num_threads or os.cpu_count() or 1
         self.num_threads = nt
@@ -189,6 +195,23 @@ class Oracle:
         keys = ["shifts", "shifts_ok", "newton_attempts", "newton_converged", "newton_iters",
                 "newton_paths_ok", "rays", "reserved"]
         return {k: int(v) for k, v in zip(keys, o)}
+
+    def export_history(self):
+        """Final reservoirs of the last frame (float32 SoA, plane-major)."""
+        s = self.sensor
+        P, B = s.width * s.height, s.n_bins + (1 if s.gate_enabled else 0)
+        PB = P * B
+        h = dict(W=np.zeros(PB, np.float32), phat=np.zeros(PB, np.float32), len=np.zeros(PB, np.float32),
+                 pre_pdf=np.zeros(PB, np.float32), opix=np.zeros(PB, np.uint32), ofr=np.zeros(PB, np.uint32),
+                 meta=np.zeros(PB, np.uint32), vobj=np.full(4 * PB, -1, np.int32), vxi=np.zeros(8 * PB, np.float32),
+                 M=np.zeros(P, np.float32), mask=np.zeros(((B + 31) // 32) * P, np.uint32))
+        u32 = C.POINTER(C.c_uint32)
+        rc = lib().orc_export_history(self.h, _p(h["W"], _f32p), _p(h["phat"], _f32p), _p(h["len"], _f32p),
+                                      _p(h["pre_pdf"], _f32p), _p(h["opix"], u32), _p(h["ofr"], u32),
+                                      _p(h["meta"], u32), _p(h["vobj"], _i32p), _p(h["vxi"], _f32p),
+                                      _p(h["M"], _f32p), _p(h["mask"], u32))
+        assert rc == 0, "no history"
+        return h
 
     # unit-level helpers
     def load_frame(self, frame):

@@ -1,0 +1,645 @@
+// C ABI of the ToF ReSTIR library: context, scene upload, sensor set,
+// frame driver and statistics.  See include/tof.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "tof.h"
+#include "tof_internal.h"
+
+using namespace tofd;
+
+namespace {
+
+struct Alloc {
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+};
+
+struct GeomBuf {
+    float* xf = nullptr;
+    float4* wv = nullptr;
+    Node* nodes = nullptr;
+    float4* leaves = nullptr;
+    int* parent = nullptr;
+    std::vector<float> xf_host;
+    bool built = false;
+};
+
+struct SlotHost {
+    bool valid = false;
+    int geom = 0;
+    V3 cam_pos, cam_fwd, cam_right, cam_up;
+    float tan_half = 0, aspect = 1, ohx = 0, ohy = 0;
+    V3 light_pos;
+    int* gb_obj = nullptr;
+    float* gb_xi0 = nullptr;
+    float* gb_xi1 = nullptr;
+    float4* gb_p = nullptr;
+    float4* gb_n = nullptr;
+};
+
+}  // namespace
+
+struct tof_ctx {
+    int device = 0;
+    size_t budget = 0;
+    uint64_t seed = 0;
+    Alloc scene_mem, sensor_mem;
+    // scene
+    bool has_scene = false;
+    int n_obj = 0, n_mat = 0, n_vert = 0, n_tri = 0, n_sph = 0;
+    float scale = 1.f;
+    std::vector<Obj> h_objs;
+    Obj* d_objs = nullptr;
+    Mat* d_mats = nullptr;
+    TriInfo* d_tri = nullptr;
+    int* d_sph = nullptr;
+    float4* d_lv = nullptr;
+    int* d_vobj = nullptr;
+    int4* d_tv = nullptr;
+    void* bvh_scratch = nullptr;
+    GeomBuf geom[2];
+    // sensor
+    bool has_sensor = false;
+    tof_sensor_desc sd{};
+    Sens s{};
+    SlotHost slot[2];
+    ResSet sets[4];          // 0 canonical, 1 scratch/temporal, 2-3 final ping-pong
+    int fin_prev = 2;
+    bool prev_valid = false;
+    float* pt = nullptr;
+    float2* direct = nullptr;
+    int* prev_pix = nullptr;
+    int* nb = nullptr;
+    uint2* items = nullptr;
+    uint32_t* count = nullptr;
+    size_t max_items = 0;
+    // misc
+    unsigned long long* counters = nullptr;
+    float* xf_pinned[2] = {nullptr, nullptr};
+    hipEvent_t xf_ev[2] = {nullptr, nullptr};
+    int xf_ring = 0;
+    uint64_t frames = 0;
+};
+
+namespace {
+
+tof_status dev_alloc(tof_ctx* c, Alloc& a, void** out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (c->budget && c->scene_mem.bytes + c->sensor_mem.bytes + bytes > c->budget) return TOF_ERR_OUT_OF_MEMORY;
+    if (hipMalloc(out, bytes) != hipSuccess) {
+        *out = nullptr;
+        (void)hipGetLastError();
+        return TOF_ERR_OUT_OF_MEMORY;
+    }
+    a.ptrs.push_back(*out);
+    a.bytes += bytes;
+    return TOF_OK;
+}
+
+void free_all(Alloc& a) {
+    for (void* p : a.ptrs) (void)hipFree(p);
+    a.ptrs.clear();
+    a.bytes = 0;
+}
+
+template <typename T>
+tof_status alloc_t(tof_ctx* c, Alloc& a, T** out, size_t count) {
+    void* p = nullptr;
+    tof_status st = dev_alloc(c, a, &p, sizeof(T) * count);
+    *out = (T*)p;
+    return st;
+}
+
+#define TOF_TRY(expr)                    \
+    do {                                 \
+        tof_status _st = (expr);         \
+        if (_st != TOF_OK) return _st;   \
+    } while (0)
+#define HIP_TRY(expr)                                    \
+    do {                                                 \
+        if ((expr) != hipSuccess) {                      \
+            (void)hipGetLastError();                     \
+            return TOF_ERR_DEVICE;                       \
+        }                                                \
+    } while (0)
+
+bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+V3 hv(float a, float b, float c) { return V3{a, b, c}; }
+V3 hnorm(V3 a) {
+    float l = std::sqrt(a.x * a.x + a.y * a.y + a.z * a.z);
+    return V3{a.x / l, a.y / l, a.z / l};
+}
+V3 hcross(V3 a, V3 b) { return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+
+constexpr size_t kRecBytes = 4 * 7 + 4 * 3 * 4;   // 4 floats + 3 u32 + 4 vertex refs
+
+size_t sensor_footprint(const tof_sensor_desc& d) {
+    size_t P = (size_t)d.width * d.height;
+    size_t B = (size_t)d.n_bins + (d.gate_enabled ? 1 : 0);
+    size_t words = (B + 31) / 32;
+    size_t per_set = P * B * kRecBytes + P * 4 + P * words * 4;
+    size_t gbuf = 2 * P * (4 + 4 + 4 + 16 + 16);
+    return 4 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
+           P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ + 64 * 1024;
+}
+
+tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
+    Alloc& a = c->sensor_mem;
+    size_t n = P * B;
+    TOF_TRY(alloc_t(c, a, &r.W, n));
+    TOF_TRY(alloc_t(c, a, &r.phat, n));
+    TOF_TRY(alloc_t(c, a, &r.len, n));
+    TOF_TRY(alloc_t(c, a, &r.pre_pdf, n));
+    TOF_TRY(alloc_t(c, a, &r.opix, n));
+    TOF_TRY(alloc_t(c, a, &r.ofr, n));
+    TOF_TRY(alloc_t(c, a, &r.meta, n));
+    for (int q = 0; q < 4; ++q) {
+        TOF_TRY(alloc_t(c, a, &r.vobj[q], n));
+        TOF_TRY(alloc_t(c, a, &r.vxi0[q], n));
+        TOF_TRY(alloc_t(c, a, &r.vxi1[q], n));
+    }
+    TOF_TRY(alloc_t(c, a, &r.M, P));
+    TOF_TRY(alloc_t(c, a, &r.mask, P * words));
+    return TOF_OK;
+}
+
+SlotDev slot_dev(const tof_ctx* c, int i) {
+    const SlotHost& h = c->slot[i];
+    const GeomBuf& g = c->geom[h.geom];
+    SlotDev d;
+    d.wv = g.wv;
+    d.xf = g.xf;
+    d.nodes = g.nodes;
+    d.leaves = g.leaves;
+    d.n_tri = c->n_tri;
+    d.cam_pos = h.cam_pos;
+    d.cam_fwd = h.cam_fwd;
+    d.cam_right = h.cam_right;
+    d.cam_up = h.cam_up;
+    d.tan_half = h.tan_half;
+    d.aspect = h.aspect;
+    d.ohx = h.ohx;
+    d.ohy = h.ohy;
+    d.light_pos = h.light_pos;
+    d.gb_obj = h.gb_obj;
+    d.gb_xi0 = h.gb_xi0;
+    d.gb_xi1 = h.gb_xi1;
+    d.gb_p = h.gb_p;
+    d.gb_n = h.gb_n;
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tof_status_string(tof_status s) {
+    switch (s) {
+        case TOF_OK: return "ok";
+        case TOF_ERR_INVALID_ARG: return "invalid argument";
+        case TOF_ERR_OUT_OF_MEMORY: return "out of memory (HBM budget or hipMalloc)";
+        case TOF_ERR_INVALID_SCENE: return "invalid scene";
+        case TOF_ERR_NOT_READY: return "scene or sensor not set";
+        case TOF_ERR_DEVICE: return "HIP device error";
+        case TOF_ERR_UNIMPLEMENTED: return "unimplemented";
+    }
+    return "unknown status";
+}
+
+tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64_t seed) {
+    if (!out) return TOF_ERR_INVALID_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) {
+        (void)hipGetLastError();
+        return TOF_ERR_DEVICE;
+    }
+    if (device < 0 || device >= ndev) return TOF_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(device));
+    tof_ctx* c = new (std::nothrow) tof_ctx();
+    if (!c) return TOF_ERR_OUT_OF_MEMORY;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    c->seed = seed;
+    if (hipMalloc(&c->counters, 16 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->counters, 0, 16 * sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return TOF_ERR_DEVICE;
+    }
+    *out = c;
+    return TOF_OK;
+}
+
+void tof_destroy(tof_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    free_all(c->scene_mem);
+    free_all(c->sensor_mem);
+    if (c->counters) (void)hipFree(c->counters);
+    for (int i = 0; i < 2; ++i) {
+        if (c->xf_pinned[i]) (void)hipHostFree(c->xf_pinned[i]);
+        if (c->xf_ev[i]) (void)hipEventDestroy(c->xf_ev[i]);
+    }
+    delete c;
+}
+
+tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
+    if (!c || !d) return TOF_ERR_INVALID_ARG;
+    if (d->num_objects < 1 || d->num_objects > (1 << 20) || d->num_materials < 1 || d->num_vertices < 0 ||
+        !d->object_type || !d->object_material || !d->object_grid || !d->object_sphere || !d->material_type ||
+        !d->material_params || (d->num_vertices > 0 && !d->vertices))
+        return TOF_ERR_INVALID_ARG;
+    if (!(std::isfinite(d->scene_scale) && d->scene_scale > 0.f)) return TOF_ERR_INVALID_SCENE;
+    for (int v = 0; v < d->num_vertices; ++v)
+        if (!finite3(d->vertices + 3 * v)) return TOF_ERR_INVALID_SCENE;
+    std::vector<Mat> mats(d->num_materials);
+    for (int m = 0; m < d->num_materials; ++m) {
+        const float* p = d->material_params + 3 * m;
+        mats[m] = Mat{d->material_type[m], p[0], p[1], p[2]};
+        bool ok = finite3(p) && (mats[m].type == TOF_MAT_LAMBERT || mats[m].type == TOF_MAT_GGX) &&
+                  p[0] >= 0.f && p[0] <= 1.f && (mats[m].type == TOF_MAT_LAMBERT || (p[1] > 0.f && p[2] >= 0.f && p[2] <= 1.f));
+        if (!ok) return TOF_ERR_INVALID_SCENE;
+    }
+    std::vector<Obj> objs(d->num_objects);
+    std::vector<TriInfo> tris;
+    std::vector<int> sph;
+    std::vector<int> vobj(d->num_vertices, -1);
+    std::vector<int4> tv;
+    for (int o = 0; o < d->num_objects; ++o) {
+        Obj ob{};
+        ob.type = d->object_type[o];
+        ob.material = d->object_material[o];
+        if (ob.material < 0 || ob.material >= d->num_materials) return TOF_ERR_INVALID_SCENE;
+        const int32_t* g = d->object_grid + 5 * o;
+        const float* sp = d->object_sphere + 4 * o;
+        ob.tri_base = (int)tris.size();
+        if (ob.type == TOF_OBJ_GRID) {
+            ob.nu = g[0];
+            ob.nv = g[1];
+            ob.wrap_u = g[2] ? 1 : 0;
+            ob.wrap_v = g[3] ? 1 : 0;
+            ob.voff = g[4];
+            if (ob.nu < 1 || ob.nv < 1 || ob.nu > 65535 || ob.nv > 65535 || ob.voff < 0) return TOF_ERR_INVALID_SCENE;
+            long long nvtx = (long long)(ob.nu + 1) * (ob.nv + 1);
+            if (ob.voff + nvtx > d->num_vertices) return TOF_ERR_INVALID_SCENE;
+            if ((long long)tris.size() + 2LL * ob.nu * ob.nv > (1LL << 30)) return TOF_ERR_INVALID_SCENE;
+            for (long long q = 0; q < nvtx; ++q) vobj[ob.voff + q] = o;
+            int row = ob.nu + 1;
+            for (int j = 0; j < ob.nv; ++j)
+                for (int i = 0; i < ob.nu; ++i) {
+                    int b = ob.voff + j * row + i;
+                    tris.push_back(TriInfo{o, i, j, 0});
+                    tv.push_back(make_int4(b, b + 1, b + row, 0));
+                    tris.push_back(TriInfo{o, i, j, 1});
+                    tv.push_back(make_int4(b + row + 1, b + row, b + 1, 0));
+                }
+        } else if (ob.type == TOF_OBJ_SPHERE) {
+            if (!finite3(sp) || !(std::isfinite(sp[3]) && sp[3] > 0.f)) return TOF_ERR_INVALID_SCENE;
+            ob.cx = sp[0];
+            ob.cy = sp[1];
+            ob.cz = sp[2];
+            ob.r = sp[3];
+            sph.push_back(o);
+        } else {
+            return TOF_ERR_INVALID_SCENE;
+        }
+        objs[o] = ob;
+    }
+    // a vertex referenced by two grids would get two transforms
+    for (int o = 0; o < d->num_objects; ++o) {
+        const Obj& ob = objs[o];
+        if (ob.type != TOF_OBJ_GRID) continue;
+        long long nvtx = (long long)(ob.nu + 1) * (ob.nv + 1);
+        for (long long q = 0; q < nvtx; ++q)
+            if (vobj[ob.voff + q] != o) return TOF_ERR_INVALID_SCENE;
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    free_all(c->scene_mem);
+    c->has_scene = false;
+    c->prev_valid = false;
+    c->slot[0].valid = c->slot[1].valid = false;
+    for (auto& g : c->geom) g = GeomBuf();
+    const int T = (int)tris.size();
+    Alloc& a = c->scene_mem;
+    TOF_TRY(alloc_t(c, a, &c->d_objs, objs.size()));
+    TOF_TRY(alloc_t(c, a, &c->d_mats, mats.size()));
+    TOF_TRY(alloc_t(c, a, &c->d_tri, std::max(T, 1)));
+    TOF_TRY(alloc_t(c, a, &c->d_tv, std::max(T, 1)));
+    TOF_TRY(alloc_t(c, a, &c->d_sph, std::max<size_t>(sph.size(), 1)));
+    TOF_TRY(alloc_t(c, a, &c->d_lv, std::max(d->num_vertices, 1)));
+    TOF_TRY(alloc_t(c, a, &c->d_vobj, std::max(d->num_vertices, 1)));
+    std::vector<float4> lv(d->num_vertices);
+    for (int v = 0; v < d->num_vertices; ++v)
+        lv[v] = make_float4(d->vertices[3 * v], d->vertices[3 * v + 1], d->vertices[3 * v + 2], 0.f);
+    HIP_TRY(hipMemcpy(c->d_objs, objs.data(), sizeof(Obj) * objs.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_mats, mats.data(), sizeof(Mat) * mats.size(), hipMemcpyHostToDevice));
+    if (T) {
+        HIP_TRY(hipMemcpy(c->d_tri, tris.data(), sizeof(TriInfo) * T, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->d_tv, tv.data(), sizeof(int4) * T, hipMemcpyHostToDevice));
+    }
+    if (!sph.empty()) HIP_TRY(hipMemcpy(c->d_sph, sph.data(), sizeof(int) * sph.size(), hipMemcpyHostToDevice));
+    if (d->num_vertices) {
+        HIP_TRY(hipMemcpy(c->d_lv, lv.data(), sizeof(float4) * lv.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c->d_vobj, vobj.data(), sizeof(int) * vobj.size(), hipMemcpyHostToDevice));
+    }
+    for (auto& g : c->geom) {
+        TOF_TRY(alloc_t(c, a, &g.xf, 12 * (size_t)objs.size()));
+        TOF_TRY(alloc_t(c, a, &g.wv, std::max(d->num_vertices, 1)));
+        TOF_TRY(alloc_t(c, a, &g.nodes, std::max(T - 1, 1)));
+        TOF_TRY(alloc_t(c, a, &g.leaves, 3 * (size_t)std::max(T, 1)));
+        TOF_TRY(alloc_t(c, a, &g.parent, 2 * (size_t)std::max(T, 1)));
+    }
+    TOF_TRY(dev_alloc(c, a, &c->bvh_scratch, tofh::bvh_scratch_bytes(std::max(T, 1))));
+    c->h_objs = objs;
+    c->n_obj = d->num_objects;
+    c->n_mat = d->num_materials;
+    c->n_vert = d->num_vertices;
+    c->n_tri = T;
+    c->n_sph = (int)sph.size();
+    c->scale = d->scene_scale;
+    for (int i = 0; i < 2; ++i) {
+        if (c->xf_pinned[i]) (void)hipHostFree(c->xf_pinned[i]);
+        c->xf_pinned[i] = nullptr;
+        HIP_TRY(hipHostMalloc((void**)&c->xf_pinned[i], sizeof(float) * 12 * objs.size()));
+        if (!c->xf_ev[i]) HIP_TRY(hipEventCreateWithFlags(&c->xf_ev[i], hipEventDisableTiming));
+    }
+    c->has_scene = true;
+    return TOF_OK;
+}
+
+tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
+    if (!c || !d) return TOF_ERR_INVALID_ARG;
+    const int B = d->n_bins + (d->gate_enabled ? 1 : 0);
+    bool ok = d->width >= 1 && d->height >= 1 && d->full_width >= d->width && d->full_height >= d->height &&
+              d->crop_x0 >= 0 && d->crop_y0 >= 0 && d->crop_x0 + d->width <= d->full_width &&
+              d->crop_y0 + d->height <= d->full_height && (long long)d->full_width * d->full_height < (1LL << 31) &&
+              (d->camera_model == TOF_CAMERA_PINHOLE || d->camera_model == TOF_CAMERA_ORTHO) &&
+              (d->light_model == TOF_LIGHT_POINT || d->light_model == TOF_LIGHT_CONFOCAL) && B >= 1 &&
+              d->n_bins >= 0 && d->n_bins <= 8192 && (d->n_bins == 0 || d->bin_width > 0.f) &&
+              (!d->gate_enabled || d->gate_width > 0.f) && d->n_min >= 1 && d->n_min <= d->n_max && d->n_max <= kMaxVerts &&
+              d->m_init >= 1 && d->m_init <= 255 && d->spatial_rounds >= 0 && d->spatial_rounds <= 8 &&
+              d->spatial_k >= 0 && d->spatial_k <= kMaxK && (d->spatial_rounds == 0 || d->spatial_k == 0 || d->spatial_radius >= 1) &&
+              d->spatial_radius <= 1024 && d->m_cap > 0.f && d->newton_tol_rel > 0.f && d->newton_max_iter >= 0 &&
+              d->newton_max_iter <= 64 && d->j_max >= 1.f &&
+              (d->shift_mode == TOF_SHIFT_NAIVE || d->shift_mode == TOF_SHIFT_PATHLEN) &&
+              d->debug_stage >= TOF_STAGE_CANONICAL && d->debug_stage <= TOF_STAGE_FINAL &&
+              std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
+    if (!ok) return TOF_ERR_INVALID_ARG;
+    if (c->budget && c->scene_mem.bytes + sensor_footprint(*d) > c->budget) return TOF_ERR_OUT_OF_MEMORY;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    free_all(c->sensor_mem);
+    c->has_sensor = false;
+    c->prev_valid = false;
+    c->slot[0].valid = c->slot[1].valid = false;
+    const size_t P = (size_t)d->width * d->height;
+    const size_t words = ((size_t)B + 31) / 32;
+    for (int i = 0; i < 4; ++i) TOF_TRY(alloc_set(c, c->sets[i], P, B, words));
+    Alloc& a = c->sensor_mem;
+    for (int i = 0; i < 2; ++i) {
+        SlotHost& h = c->slot[i];
+        TOF_TRY(alloc_t(c, a, &h.gb_obj, P));
+        TOF_TRY(alloc_t(c, a, &h.gb_xi0, P));
+        TOF_TRY(alloc_t(c, a, &h.gb_xi1, P));
+        TOF_TRY(alloc_t(c, a, &h.gb_p, P));
+        TOF_TRY(alloc_t(c, a, &h.gb_n, P));
+    }
+    TOF_TRY(alloc_t(c, a, &c->pt, P * B));
+    TOF_TRY(alloc_t(c, a, &c->direct, P));
+    TOF_TRY(alloc_t(c, a, &c->prev_pix, P));
+    TOF_TRY(alloc_t(c, a, &c->nb, P * (size_t)std::max(d->spatial_k, 1)));
+    TOF_TRY(alloc_t(c, a, &c->items, P * B));
+    TOF_TRY(alloc_t(c, a, &c->count, 64));
+    c->max_items = P * B;
+    c->sd = *d;
+    Sens& s = c->s;
+    s.W = d->width;
+    s.H = d->height;
+    s.FW = d->full_width;
+    s.FH = d->full_height;
+    s.cx0 = d->crop_x0;
+    s.cy0 = d->crop_y0;
+    s.cam_model = d->camera_model;
+    s.light_model = d->light_model;
+    s.count_leg = d->count_camera_leg;
+    s.jitter = d->jitter;
+    s.light_I = d->light_intensity;
+    s.gate_en = d->gate_enabled ? 1 : 0;
+    s.gate_c = d->gate_center;
+    s.gate_w = d->gate_width;
+    s.n_bins = d->n_bins;
+    s.t0 = d->bin_t0;
+    s.bw = d->bin_width;
+    s.n_min = d->n_min;
+    s.n_max = d->n_max;
+    s.m_init = d->m_init;
+    s.temporal = d->temporal;
+    s.rounds = d->spatial_rounds;
+    s.k = d->spatial_k;
+    s.radius = d->spatial_radius;
+    s.m_cap = d->m_cap;
+    s.tol_rel = d->newton_tol_rel;
+    s.max_it = d->newton_max_iter;
+    s.j_max = d->j_max;
+    s.shift_mode = d->shift_mode;
+    s.include_direct = d->include_direct;
+    s.debug_stage = d->debug_stage;
+    s.P = (int)P;
+    s.B = B;
+    s.mask_words = (int)words;
+    s.seed = c->seed;
+    c->fin_prev = 2;
+    c->has_sensor = true;
+    return TOF_OK;
+}
+
+tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
+    if (!c || !h) return TOF_ERR_INVALID_ARG;
+    if (!c->has_scene || !c->has_sensor || !c->slot[0].valid) return TOF_ERR_NOT_READY;
+    if (!h->W || !h->phat || !h->len || !h->pre_pdf || !h->origin_pixel || !h->origin_frame || !h->meta ||
+        !h->vertex_obj || !h->vertex_xi || !h->M || !h->mask)
+        return TOF_ERR_INVALID_ARG;
+    const size_t P = (size_t)c->s.P, B = (size_t)c->s.B, PB = P * B, words = (size_t)c->s.mask_words;
+    for (size_t i = 0; i < 4 * PB; ++i)
+        if (h->vertex_obj[i] < -1 || h->vertex_obj[i] >= c->n_obj) return TOF_ERR_INVALID_ARG;
+    for (size_t i = 0; i < PB; ++i) {
+        uint32_t m = h->meta[i];
+        if (((m >> 8) & 15u) > (uint32_t)kMaxVerts || ((m >> 12) & 15u) > (uint32_t)kMaxVerts) return TOF_ERR_INVALID_ARG;
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    ResSet& r = c->sets[c->fin_prev];
+    HIP_TRY(hipMemcpy(r.W, h->W, 4 * PB, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(r.phat, h->phat, 4 * PB, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(r.len, h->len, 4 * PB, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(r.pre_pdf, h->pre_pdf, 4 * PB, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(r.opix, h->origin_pixel, 4 * PB, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(r.ofr, h->origin_frame, 4 * PB, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(r.meta, h->meta, 4 * PB, hipMemcpyHostToDevice));
+    for (int q = 0; q < 4; ++q) {
+        HIP_TRY(hipMemcpy(r.vobj[q], h->vertex_obj + q * PB, 4 * PB, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(r.vxi0[q], h->vertex_xi + (2 * q) * PB, 4 * PB, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(r.vxi1[q], h->vertex_xi + (2 * q + 1) * PB, 4 * PB, hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMemcpy(r.M, h->M, 4 * P, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(r.mask, h->mask, 4 * P * words, hipMemcpyHostToDevice));
+    c->prev_valid = true;
+    return TOF_OK;
+}
+
+tof_status tof_reservoirs_reset(tof_ctx* c) {
+    if (!c) return TOF_ERR_INVALID_ARG;
+    c->prev_valid = false;
+    return TOF_OK;
+}
+
+tof_status tof_get_stats(tof_ctx* c, tof_stats* out) {
+    if (!c || !out) return TOF_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    unsigned long long h[16];
+    HIP_TRY(hipMemcpy(h, c->counters, sizeof(h), hipMemcpyDeviceToHost));
+    out->shifts = h[ST_SHIFTS];
+    out->shifts_ok = h[ST_SHIFTS_OK];
+    out->newton_attempts = h[ST_NEWTON_ATT];
+    out->newton_converged = h[ST_NEWTON_CONV];
+    out->newton_iters = h[ST_NEWTON_ITERS];
+    out->newton_paths_ok = h[ST_NEWTON_OK];
+    out->rays = h[ST_RAYS];
+    out->frames = c->frames;
+    out->bvh_overflow = h[ST_OVERFLOW];
+    return TOF_OK;
+}
+
+tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_image, float* out_hist,
+                            float* out_pt_image, float* out_pt_hist, void* stream) {
+    if (!c || !fr) return TOF_ERR_INVALID_ARG;
+    if (!c->has_scene || !c->has_sensor) return TOF_ERR_NOT_READY;
+    if (!fr->object_xforms) return TOF_ERR_INVALID_ARG;
+    if ((out_image || out_pt_image) && !c->sd.gate_enabled) return TOF_ERR_INVALID_ARG;
+    if ((out_hist || out_pt_hist) && c->sd.n_bins == 0) return TOF_ERR_INVALID_ARG;
+    for (int k = 0; k < 12 * c->n_obj; ++k)
+        if (!std::isfinite(fr->object_xforms[k])) return TOF_ERR_INVALID_ARG;
+    if (!finite3(fr->cam_pos) || !finite3(fr->cam_fwd) || !finite3(fr->cam_up) || !finite3(fr->light_pos))
+        return TOF_ERR_INVALID_ARG;
+    V3 fwd = hv(fr->cam_fwd[0], fr->cam_fwd[1], fr->cam_fwd[2]);
+    V3 up = hv(fr->cam_up[0], fr->cam_up[1], fr->cam_up[2]);
+    V3 rc = hcross(fwd, up);
+    if (!(rc.x * rc.x + rc.y * rc.y + rc.z * rc.z > 0.f)) return TOF_ERR_INVALID_ARG;
+    if (c->sd.camera_model == TOF_CAMERA_PINHOLE && !(fr->fov_y_deg > 0.f && fr->fov_y_deg < 180.f))
+        return TOF_ERR_INVALID_ARG;
+    if (c->sd.camera_model == TOF_CAMERA_ORTHO && !(fr->ortho_half[0] > 0.f && fr->ortho_half[1] > 0.f))
+        return TOF_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t O = (size_t)c->n_obj;
+    // rotate: the previous call's frame becomes slot 1
+    if (c->slot[0].valid) std::swap(c->slot[0], c->slot[1]);
+    SlotHost& cur = c->slot[0];
+    const SlotHost& prev = c->slot[1];
+    bool same = prev.valid && c->geom[prev.geom].built &&
+                std::memcmp(c->geom[prev.geom].xf_host.data(), fr->object_xforms, sizeof(float) * 12 * O) == 0;
+    if (same) {
+        cur.geom = prev.geom;
+    } else {
+        cur.geom = prev.valid ? 1 - prev.geom : 0;
+        GeomBuf& g = c->geom[cur.geom];
+        g.xf_host.assign(fr->object_xforms, fr->object_xforms + 12 * O);
+        int ring = c->xf_ring;
+        c->xf_ring ^= 1;
+        HIP_TRY(hipEventSynchronize(c->xf_ev[ring]));
+        std::memcpy(c->xf_pinned[ring], fr->object_xforms, sizeof(float) * 12 * O);
+        HIP_TRY(hipMemcpyAsync(g.xf, c->xf_pinned[ring], sizeof(float) * 12 * O, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipEventRecord(c->xf_ev[ring], st));
+        tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, c->n_vert, st);
+        if (c->n_tri > 0) tofh::launch_bvh_build(c->d_tv, g.wv, c->n_tri, g.nodes, g.leaves, g.parent, c->bvh_scratch, st);
+        g.built = true;
+    }
+    cur.valid = true;
+    cur.cam_pos = hv(fr->cam_pos[0], fr->cam_pos[1], fr->cam_pos[2]);
+    cur.cam_fwd = hnorm(fwd);
+    cur.cam_right = hnorm(hcross(cur.cam_fwd, up));
+    cur.cam_up = hcross(cur.cam_right, cur.cam_fwd);
+    cur.tan_half = std::tan(0.5 * (double)fr->fov_y_deg * 3.14159265358979323846 / 180.0);
+    cur.aspect = (float)((double)c->sd.full_width / (double)c->sd.full_height);
+    cur.ohx = fr->ortho_half[0];
+    cur.ohy = fr->ortho_half[1];
+    cur.light_pos = hv(fr->light_pos[0], fr->light_pos[1], fr->light_pos[2]);
+
+    tofh::FrameArgs a;
+    a.s = c->s;
+    a.S.objs = c->d_objs;
+    a.S.mats = c->d_mats;
+    a.S.tri_info = c->d_tri;
+    a.S.sphere_ids = c->d_sph;
+    a.S.n_obj = c->n_obj;
+    a.S.n_sph = c->n_sph;
+    a.S.n_tri = c->n_tri;
+    a.S.eps = 1e-4f * c->scale;
+    a.S.dmin = 0.01f * c->scale;
+    a.F.g[0] = slot_dev(c, 0);
+    a.F.g[1] = prev.valid ? slot_dev(c, 1) : slot_dev(c, 0);
+    a.frame = (uint32_t)fr->frame_index;
+    a.counters = c->counters;
+    const size_t P = (size_t)c->s.P, B = (size_t)c->s.B;
+
+    tofh::GBufOut gout{cur.gb_obj, cur.gb_xi0, cur.gb_xi1, cur.gb_p, cur.gb_n};
+    tofh::launch_gbuffer(a, gout, st);
+    tofh::launch_fill_u32((uint32_t*)c->pt, 0u, P * B, st);
+    ResSet& can = c->sets[0];
+    ResSet& tmp = c->sets[1];
+    const int fin_new = c->fin_prev == 2 ? 3 : 2;
+    tofh::launch_initial(a, can, c->pt, c->direct, st);
+    const ResSet* shown = nullptr;
+    if (c->s.debug_stage == TOF_STAGE_CANONICAL) shown = &can;
+    const ResSet* cur_set = &can;
+    bool temporal_done = false;
+    if (c->s.temporal && c->prev_valid && prev.valid) {
+        const ResSet& pf = c->sets[c->fin_prev];
+        tofh::launch_reproject(a, can, pf, c->prev_pix, tmp.M, st);
+        tofh::launch_fill_u32(c->count, 0u, 1, st);
+        tofh::launch_items(a, 0, can, pf, c->prev_pix, 0, c->items, c->count, tmp.mask, st);
+        tofh::launch_temporal(a, can, pf, c->prev_pix, c->items, c->count, c->max_items, tmp, st);
+        cur_set = &tmp;
+        temporal_done = true;
+    }
+    if (c->s.debug_stage == TOF_STAGE_TEMPORAL) {
+        tofh::launch_splat(a, *cur_set, c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
+    } else if (shown) {
+        tofh::launch_splat(a, *shown, c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
+    }
+    // spatial rounds alternate between the new final set and the scratch set
+    int cur_idx = temporal_done ? 1 : 0;
+    for (int r = 0; r < c->s.rounds && c->s.k > 0; ++r) {
+        int out_idx = (cur_idx == fin_new) ? 1 : fin_new;
+        if (out_idx == cur_idx) out_idx = 0;
+        ResSet& in = c->sets[cur_idx];
+        ResSet& out = c->sets[out_idx];
+        tofh::launch_neighbours(a, r, in, c->nb, out.M, st);
+        tofh::launch_fill_u32(c->count, 0u, 1, st);
+        tofh::launch_items(a, 1, in, in, c->nb, c->s.k, c->items, c->count, out.mask, st);
+        tofh::launch_spatial(a, r, in, c->nb, c->items, c->count, c->max_items, out, st);
+        cur_idx = out_idx;
+    }
+    if (cur_idx != fin_new) std::swap(c->sets[cur_idx], c->sets[fin_new]);
+    if (c->s.debug_stage == TOF_STAGE_FINAL)
+        tofh::launch_splat(a, c->sets[fin_new], c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
+    if (hipGetLastError() != hipSuccess) return TOF_ERR_DEVICE;
+    c->fin_prev = fin_new;
+    c->prev_valid = true;
+    c->frames++;
+    return TOF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Host-side launchers of the library's kernels (internal; not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "tof_device.h"
+
+namespace tofh {
+
+struct FrameArgs {
+    tofd::Sens s;
+    tofd::SceneDev S;
+    tofd::Frames F;
+    uint32_t frame;
+    unsigned long long* counters;   // 9 x u64
+};
+
+// bvh.hip
+void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
+void launch_world_verts(const float4* lv, const int* vobj, const float* xf, float4* wv, int nv, hipStream_t st);
+size_t bvh_scratch_bytes(int T);
+void launch_bvh_build(const int4* tv, const float4* wv, int T, tofd::Node* nodes, float4* leaves, int* parent,
+                      void* scratch, hipStream_t st);
+
+// render.hip
+struct GBufOut {
+    int* obj;
+    float* xi0;
+    float* xi1;
+    float4* p;
+    float4* n;
+};
+void launch_gbuffer(const FrameArgs& a, GBufOut out, hipStream_t st);
+void launch_initial(const FrameArgs& a, tofd::ResSet can, float* pt, float2* direct, hipStream_t st);
+void launch_reproject(const FrameArgs& a, const tofd::ResSet& can, const tofd::ResSet& prev, int* prev_pix,
+                      float* M_out, hipStream_t st);
+void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, int* nb, float* M_out,
+                       hipStream_t st);
+// Work items (pixel, plane) for every plane non-empty in any candidate.
+void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const tofd::ResSet& second,
+                  const int* links, int nlinks, uint2* items, uint32_t* count, uint32_t* out_mask,
+                  hipStream_t st);
+void launch_temporal(const FrameArgs& a, const tofd::ResSet& can, const tofd::ResSet& prev, const int* prev_pix,
+                     const uint2* items, const uint32_t* count, size_t max_items, tofd::ResSet out,
+                     hipStream_t st);
+void launch_spatial(const FrameArgs& a, int round, const tofd::ResSet& in, const int* nb, const uint2* items,
+                    const uint32_t* count, size_t max_items, tofd::ResSet out, hipStream_t st);
+void launch_splat(const FrameArgs& a, const tofd::ResSet& shown, const float* pt, const float2* direct,
+                  float* out_image, float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st);
+
+}  // namespace tofh

@@ -1,0 +1,277 @@
+"""Python binding of the ToF ReSTIR C ABI (include/tof.h).
+
+Argument marshalling only: every step of the frame runs in the HIP library
+``libtof.so`` built in this package.  PyTorch provides device memory and the
+stream.  There is no fallback: a missing library or device raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtof.so")
+
+TOF_OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "invalid scene", -4: "not ready",
+          -5: "device error", -6: "unimplemented"}
+
+_i32p = C.POINTER(C.c_int32)
+_f32p = C.POINTER(C.c_float)
+
+
+class TofError(RuntimeError):
+    def __init__(self, func: str, status: int):
+        super().__init__(f"{func} failed: {STATUS.get(status, status)} ({status})")
+        self.status = status
+
+
+class tof_scene_desc(C.Structure):
+    _fields_ = [("num_objects", C.c_int32), ("object_type", _i32p), ("object_material", _i32p),
+                ("object_grid", _i32p), ("object_sphere", _f32p), ("num_materials", C.c_int32),
+                ("material_type", _i32p), ("material_params", _f32p), ("num_vertices", C.c_int32),
+                ("vertices", _f32p), ("scene_scale", C.c_float)]
+
+
+class tof_sensor_desc(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("full_width", C.c_int32),
+                ("full_height", C.c_int32), ("crop_x0", C.c_int32), ("crop_y0", C.c_int32),
+                ("camera_model", C.c_int32), ("light_model", C.c_int32), ("count_camera_leg", C.c_int32),
+                ("jitter", C.c_int32), ("light_intensity", C.c_float), ("gate_enabled", C.c_int32),
+                ("gate_center", C.c_float), ("gate_width", C.c_float), ("n_bins", C.c_int32),
+                ("bin_t0", C.c_float), ("bin_width", C.c_float), ("n_min", C.c_int32), ("n_max", C.c_int32),
+                ("m_init", C.c_int32), ("temporal", C.c_int32), ("spatial_rounds", C.c_int32),
+                ("spatial_k", C.c_int32), ("spatial_radius", C.c_int32), ("m_cap", C.c_float),
+                ("newton_tol_rel", C.c_float), ("newton_max_iter", C.c_int32), ("j_max", C.c_float),
+                ("shift_mode", C.c_int32), ("include_direct", C.c_int32), ("debug_stage", C.c_int32)]
+
+
+class tof_frame_desc(C.Structure):
+    _fields_ = [("frame_index", C.c_int32), ("cam_pos", C.c_float * 3), ("cam_fwd", C.c_float * 3),
+                ("cam_up", C.c_float * 3), ("fov_y_deg", C.c_float), ("ortho_half", C.c_float * 2),
+                ("light_pos", C.c_float * 3), ("object_xforms", _f32p)]
+
+
+class tof_history_desc(C.Structure):
+    _fields_ = [("W", _f32p), ("phat", _f32p), ("len", _f32p), ("pre_pdf", _f32p),
+                ("origin_pixel", C.POINTER(C.c_uint32)), ("origin_frame", C.POINTER(C.c_uint32)),
+                ("meta", C.POINTER(C.c_uint32)), ("vertex_obj", _i32p), ("vertex_xi", _f32p), ("M", _f32p),
+                ("mask", C.POINTER(C.c_uint32))]
+
+
+class tof_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("shifts", "shifts_ok", "newton_attempts", "newton_converged",
+                                          "newton_iters", "newton_paths_ok", "rays", "frames", "bvh_overflow")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtof.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        L.tof_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_size_t, C.c_uint64]
+        L.tof_destroy.argtypes = [C.c_void_p]
+        L.tof_destroy.restype = None
+        L.tof_scene_upload.argtypes = [C.c_void_p, C.POINTER(tof_scene_desc)]
+        L.tof_sensor_set.argtypes = [C.c_void_p, C.POINTER(tof_sensor_desc)]
+        L.tof_render_frame.argtypes = [C.c_void_p, C.POINTER(tof_frame_desc), C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]
+        L.tof_reservoirs_reset.argtypes = [C.c_void_p]
+        L.tof_get_stats.argtypes = [C.c_void_p, C.POINTER(tof_stats)]
+        L.tof_debug_set_history.argtypes = [C.c_void_p, C.POINTER(tof_history_desc)]
+        L.tof_debug_set_history.restype = C.c_int
+        L.tof_status_string.argtypes = [C.c_int]
+        L.tof_status_string.restype = C.c_char_p
+        for f in ("tof_create", "tof_scene_upload", "tof_sensor_set", "tof_render_frame",
+                  "tof_reservoirs_reset", "tof_get_stats"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(func: str, st: int):
+    if st != TOF_OK:
+        raise TofError(func, st)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+# ---------------------------------------------------------------------------
+# the C entry points, one Python function each
+# ---------------------------------------------------------------------------
+
+def tof_create(device: int = 0, hbm_budget_bytes: int = 0, seed: int = 0) -> C.c_void_p:
+    h = C.c_void_p()
+    _check("tof_create", lib().tof_create(C.byref(h), int(device), int(hbm_budget_bytes), int(seed)))
+    return h
+
+
+def tof_destroy(h) -> None:
+    if h:
+        lib().tof_destroy(h)
+
+
+def tof_scene_upload(h, scene) -> None:
+    arrs = dict(
+        t=np.ascontiguousarray(scene.obj_type, dtype=np.int32),
+        m=np.ascontiguousarray(scene.obj_material, dtype=np.int32),
+        g=np.ascontiguousarray(scene.obj_grid, dtype=np.int32),
+        s=np.ascontiguousarray(scene.obj_sphere, dtype=np.float32),
+        mt=np.ascontiguousarray(scene.mat_type, dtype=np.int32),
+        mp=np.ascontiguousarray(scene.mat_params, dtype=np.float32),
+        v=np.ascontiguousarray(scene.vertices, dtype=np.float32),
+    )
+    d = tof_scene_desc(int(arrs["t"].shape[0]), _ptr(arrs["t"], _i32p), _ptr(arrs["m"], _i32p),
+                       _ptr(arrs["g"], _i32p), _ptr(arrs["s"], _f32p), int(arrs["mt"].shape[0]),
+                       _ptr(arrs["mt"], _i32p), _ptr(arrs["mp"], _f32p), int(arrs["v"].shape[0]),
+                       _ptr(arrs["v"], _f32p), float(scene.scene_scale))
+    _check("tof_scene_upload", lib().tof_scene_upload(h, C.byref(d)))
+
+
+def sensor_desc(sensor) -> tof_sensor_desc:
+    d = tof_sensor_desc()
+    for name, _ in tof_sensor_desc._fields_:
+        setattr(d, name, getattr(sensor, name))
+    return d
+
+
+def tof_sensor_set(h, sensor) -> None:
+    d = sensor_desc(sensor)
+    _check("tof_sensor_set", lib().tof_sensor_set(h, C.byref(d)))
+
+
+def frame_desc(frame):
+    d = tof_frame_desc()
+    d.frame_index = int(frame.index)
+    for i in range(3):
+        d.cam_pos[i] = float(frame.cam_pos[i])
+        d.cam_fwd[i] = float(frame.cam_fwd[i])
+        d.cam_up[i] = float(frame.cam_up[i])
+        d.light_pos[i] = float(frame.light_pos[i])
+    d.fov_y_deg = float(frame.fov_y_deg)
+    d.ortho_half[0] = float(frame.ortho_half[0])
+    d.ortho_half[1] = float(frame.ortho_half[1])
+    xf = np.ascontiguousarray(frame.xforms, dtype=np.float32)
+    d.object_xforms = _ptr(xf, _f32p)
+    return d, xf
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def tof_render_frame(h, frame, out_image=None, out_hist=None, out_pt_image=None, out_pt_hist=None,
+                     stream=None) -> None:
+    """Outputs are float32 CUDA/HIP torch tensors (or None); stream is a
+    torch.cuda.Stream (None = torch's current stream)."""
+    import torch
+    for t in (out_image, out_hist, out_pt_image, out_pt_hist):
+        if t is not None:
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    d, xf = frame_desc(frame)
+    _check("tof_render_frame", lib().tof_render_frame(h, C.byref(d), _dptr(out_image), _dptr(out_hist),
+                                                      _dptr(out_pt_image), _dptr(out_pt_hist),
+                                                      C.c_void_p(stream.cuda_stream)))
+
+
+def tof_reservoirs_reset(h) -> None:
+    _check("tof_reservoirs_reset", lib().tof_reservoirs_reset(h))
+
+
+def tof_get_stats(h) -> dict:
+    s = tof_stats()
+    _check("tof_get_stats", lib().tof_get_stats(h, C.byref(s)))
+    return {name: int(getattr(s, name)) for name, _ in tof_stats._fields_}
+
+
+def tof_debug_set_history(h, hist: dict) -> None:
+    """hist: numpy arrays W, phat, len, pre_pdf (f32), opix, ofr, meta (u32),
+    vobj (i32, 4*P*B), vxi (f32, 8*P*B), M (f32, P), mask (u32)."""
+    u32 = C.POINTER(C.c_uint32)
+    types = dict(W=np.float32, phat=np.float32, len=np.float32, pre_pdf=np.float32, opix=np.uint32,
+                 ofr=np.uint32, meta=np.uint32, vobj=np.int32, vxi=np.float32, M=np.float32, mask=np.uint32)
+    # converted arrays stay referenced by `a` until the call returns
+    a = {k: np.ascontiguousarray(hist[k], dtype=t) for k, t in types.items()}
+    d = tof_history_desc(_ptr(a["W"], _f32p), _ptr(a["phat"], _f32p), _ptr(a["len"], _f32p),
+                         _ptr(a["pre_pdf"], _f32p), _ptr(a["opix"], u32), _ptr(a["ofr"], u32),
+                         _ptr(a["meta"], u32), _ptr(a["vobj"], _i32p), _ptr(a["vxi"], _f32p),
+                         _ptr(a["M"], _f32p), _ptr(a["mask"], u32))
+    _check("tof_debug_set_history", lib().tof_debug_set_history(h, C.byref(d)))
+
+
+def tof_status_string(status: int) -> str:
+    return lib().tof_status_string(int(status)).decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+class Renderer:
+    """One render stream: a context with a scene and a sensor."""
+
+    def __init__(self, scene, sensor, device: int = 0, hbm_budget_bytes: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the ToF ReSTIR library runs on HIP devices only")
+        self.device = torch.device("cuda", device)
+        self.sensor = sensor
+        self.h = tof_create(device, hbm_budget_bytes, sensor.seed)
+        tof_scene_upload(self.h, scene)
+        tof_sensor_set(self.h, sensor)
+        P = sensor.width * sensor.height
+        self.out_image = torch.zeros(P, dtype=torch.float32, device=self.device) if sensor.gate_enabled else None
+        self.out_pt_image = torch.zeros(P, dtype=torch.float32, device=self.device) if sensor.gate_enabled else None
+        nb = sensor.n_bins
+        self.out_hist = torch.zeros(nb * P, dtype=torch.float32, device=self.device) if nb else None
+        self.out_pt_hist = torch.zeros(nb * P, dtype=torch.float32, device=self.device) if nb else None
+
+    def render(self, frame, stream=None):
+        tof_render_frame(self.h, frame, self.out_image, self.out_hist, self.out_pt_image, self.out_pt_hist,
+                         stream)
+
+    def fetch(self) -> dict:
+        import torch
+        torch.cuda.synchronize(self.device)
+        s = self.sensor
+        shp = (s.height, s.width)
+        out = {}
+        if self.out_image is not None:
+            out["image"] = self.out_image.cpu().numpy().reshape(shp)
+            out["pt_image"] = self.out_pt_image.cpu().numpy().reshape(shp)
+        if self.out_hist is not None:
+            out["hist"] = self.out_hist.cpu().numpy().reshape((s.n_bins,) + shp)
+            out["pt_hist"] = self.out_pt_hist.cpu().numpy().reshape((s.n_bins,) + shp)
+        return out
+
+    def stats(self) -> dict:
+        return tof_get_stats(self.h)
+
+    def reset(self):
+        tof_reservoirs_reset(self.h)
+
+    def set_history(self, hist: dict):
+        tof_debug_set_history(self.h, hist)
+
+    def close(self):
+        if self.h:
+            tof_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
