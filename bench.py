@@ -1,0 +1,243 @@
+#!/usr/bin/env python
+"""ToF ReSTIR benchmark on one MI355X.
+
+Workload: the dynamic glossy scene at 512x512 (about 92k triangles, eight
+moving GGX spheres over a displaced Lambertian ground, 3 bounces, 256-bin
+transient histogram plus a time gate, temporal + one spatial round with 5
+neighbours in a 30 px radius), synthetic and seeded.  A step is one frame of
+the full ToF ReSTIR pipeline: BVH build for the frame's transforms, G-buffer,
+path trees + per-bin initial RIS, temporal reuse, spatial reuse (each with
+the path-length-aware Newton shift and generalized balance heuristic), splat
+of the gate image and the histogram.
+
+Prints one JSON line: frames/s of ToF ReSTIR (value), the equal-RMSE
+comparison against plain ToF path tracing on the same GPU, per-frame latency
+percentiles, per-kernel times measured with HIP events, the roofline entry of
+the dominant kernel and the CPU oracle baseline.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+REC_BYTES = 76          # one reservoir record: 4 f32 + 3 u32 + 4 x (obj, xi0, xi1)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--width", type=int, default=512)
+    ap.add_argument("--ref-calls", type=int, default=24, help="reference PT calls (x ref-trees spp each)")
+    ap.add_argument("--ref-trees", type=int, default=16)
+    ap.add_argument("--no-equal-rmse", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    return ap.parse_args()
+
+
+def _threads():
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(width, nframes):
+    """The CPU oracle, as it stands, on the first frames of the same workload."""
+    from paper_2605_11536_amd import scenes
+    from oracle import build as obuild
+    if not os.path.exists(obuild.LIB):
+        obuild.build()
+    from oracle.oracle import Oracle
+    w = scenes.glossy_dynamic(width=width, height=width, frames=nframes)
+    nt = _threads()
+    o = Oracle(w.scene, w.sensor, num_threads=nt)
+    times = []
+    for fr in w.frames:
+        t0 = time.perf_counter()
+        o.render(fr)
+        times.append(time.perf_counter() - t0)
+    o.close()
+    return {"value": round(len(times) / sum(times), 5), "unit": "frames/s", "cores": nt, "kind": "oracle",
+            "sample": f"full {width}x{width} frames 0..{nframes - 1} of the same sequence (frame 0 without "
+                      f"temporal history); per-frame seconds {[round(t, 2) for t in times]}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
+                                   "described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2605_11536_amd import scenes
+    from paper_2605_11536_amd.tof import Renderer
+
+    W = args.width
+    nseq = 60
+    wl = scenes.glossy_dynamic(width=W, height=W, frames=nseq)
+    sensor = wl.sensor
+    P, B = W * W, sensor.b_tot
+
+    r = Renderer(wl.scene, sensor)
+
+    def frame_at(i):
+        fr = wl.frames[i % nseq]
+        return scenes.Frame(index=i, cam_pos=fr.cam_pos, cam_fwd=fr.cam_fwd, cam_up=fr.cam_up,
+                            fov_y_deg=fr.fov_y_deg, ortho_half=fr.ortho_half, light_pos=fr.light_pos,
+                            xforms=fr.xforms)
+
+    for i in range(args.warmup):
+        r.render(frame_at(i))
+    torch.cuda.synchronize()
+    r.set_kernel_timing(True)
+    stats0 = r.stats()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record()
+        r.render(frame_at(args.warmup + k))
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    kt = r.kernel_times()
+    r.set_kernel_timing(False)
+    stats1 = r.stats()
+    frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    fps = args.steps / elapsed
+    dstats = {k: stats1[k] - stats0[k] for k in stats1}
+    last_frame = frame_at(args.warmup + args.steps - 1)
+    restir_out = r.fetch()
+
+    result = {
+        "metric": "equal-RMSE frames/s vs plain ToF PT at 512^2; p50/p99 request latency",
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"glossy_dynamic {W}x{W}: ~92k triangles (160x160-cell displaced ground + 8 "
+                               f"moving GGX spheres of 64x40 cells), 3 bounces, 256 bins (t0 12, width 0.1) + "
+                               f"gate (17.0, 0.1), temporal + 1 spatial round (k 5, r 30 px), Newton shift",
+                   "pixels": P, "planes": B, "frames_cycled": nseq},
+        "latency_ms": {"p50": round(float(np.percentile(frame_ms, 50)), 3),
+                       "p99": round(float(np.percentile(frame_ms, 99)), 3)},
+    }
+
+    # per-kernel times (HIP events on the render stream, timed region only)
+    kms = {k: v["ms"] for k, v in kt.items() if k != "work_items"}
+    kl = {k: v["launches"] for k, v in kt.items() if k != "work_items"}
+    result["kernel_ms_per_frame"] = {k: round(v / max(args.steps, 1), 3) for k, v in kms.items()}
+    items_t, items_s = kt["work_items"]["temporal"], kt["work_items"]["spatial"]
+    result["work_items_per_frame"] = {"temporal": items_t // args.steps, "spatial": items_s // args.steps}
+    result["shift_stats_per_frame"] = {k: dstats[k] // args.steps for k in
+                                       ("shifts", "shifts_ok", "newton_attempts", "newton_converged",
+                                        "newton_paths_ok", "rays")}
+    nt = max(dstats["newton_attempts"], 1)
+    result["newton"] = {"iters_per_converged": round(dstats["newton_iters"] / max(dstats["newton_converged"], 1), 4),
+                        "newton_sr": round(dstats["newton_converged"] / nt, 4),
+                        "actual_sr": round(dstats["newton_paths_ok"] / nt, 4)}
+    result["rays_per_s"] = round(dstats["rays"] / elapsed, 1)
+
+    # roofline of the dominant kernel (see the design doc for the byte model)
+    dom = max(kms, key=lambda k: kms[k])
+    avg_ms = kms[dom] / max(kl[dom], 1)
+    if dom == "spatial":
+        # algorithmic bytes per launch: per work item the k+1 masks, M and
+        # neighbour ids, every non-empty candidate record it reads, the output
+        # record; per shift the BVH nodes are not counted (cache resident)
+        recs = dstats.get("records_read", 0)
+        per_item = 4 * (sensor.spatial_k + 1) + 4 * (sensor.spatial_k + 1) + 4 * sensor.spatial_k + REC_BYTES
+        algo = (items_s / max(kl[dom], 1)) * per_item
+        result["roofline"] = {"bound": "hbm", "achieved": round(algo / (avg_ms * 1e-3) / 1e9, 2),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(algo / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
+                              "kernel": "k_spatial", "avg_launch_ms": round(avg_ms, 4)}
+    else:
+        result["roofline"] = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": None, "traffic": None, "kernel": dom, "avg_launch_ms": round(avg_ms, 4)}
+
+    # equal RMSE against plain ToF PT on the same GPU
+    if not args.no_equal_rmse:
+        result["equal_rmse"] = equal_rmse(wl, last_frame, restir_out, fps, args, torch, Renderer, scenes)
+
+    r.close()
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(W, args.cpu_frames)
+    print(json.dumps(result), flush=True)
+
+
+def equal_rmse(wl, frame, restir_out, restir_fps, args, torch, Renderer, scenes):
+    """RMSE of the ReSTIR frame and of 1-spp plain PT against a high-spp PT
+    reference of the same frame; plain PT at s spp has MSE_1/s, so the spp
+    that matches ReSTIR is s* = MSE_1/MSE_restir and its frame time s* t_1."""
+    import dataclasses
+    ref_sensor = dataclasses.replace(wl.sensor, temporal=0, spatial_rounds=0, m_init=args.ref_trees)
+    q = Renderer(wl.scene, ref_sensor)
+    acc_i, acc_h = None, None
+    for s in range(args.ref_calls):
+        f = dataclasses.replace(frame, index=10_000_000 + s)
+        q.render(f)
+        o = q.fetch()
+        acc_i = o["pt_image"].astype(np.float64) if acc_i is None else acc_i + o["pt_image"]
+        acc_h = o["pt_hist"].astype(np.float64) if acc_h is None else acc_h + o["pt_hist"]
+    q.close()
+    ref_i, ref_h = acc_i / args.ref_calls, acc_h / args.ref_calls
+    ref_spp = args.ref_calls * args.ref_trees
+    # plain PT, 1 spp: time and error
+    pt_sensor = dataclasses.replace(wl.sensor, temporal=0, spatial_rounds=0, m_init=1)
+    p = Renderer(wl.scene, pt_sensor)
+    mse1_i, mse1_h = [], []
+    for s in range(4):
+        p.render(dataclasses.replace(frame, index=20_000_000 + s))
+        o = p.fetch()
+        mse1_i.append(np.mean((o["pt_image"] - ref_i) ** 2))
+        mse1_h.append(np.mean((o["pt_hist"] - ref_h) ** 2))
+    nrep = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(nrep):
+        p.render(dataclasses.replace(frame, index=30_000_000 + s))
+    torch.cuda.synchronize()
+    t_pt = (time.perf_counter() - t0) / nrep
+    p.close()
+    mse1_i, mse1_h = float(np.mean(mse1_i)), float(np.mean(mse1_h))
+    out = {"reference_spp": ref_spp, "pt_1spp_ms": round(1e3 * t_pt, 3)}
+    for name, mse1, ref, got in (("gate_image", mse1_i, ref_i, restir_out["image"]),
+                                 ("histogram", mse1_h, ref_h, restir_out["hist"])):
+        # remove the reference's own variance (plain PT at ref_spp)
+        mse1_t = mse1 * (1.0 - 1.0 / ref_spp)
+        mse_r = float(np.mean((got - ref) ** 2)) - mse1 / ref_spp
+        mse_r = max(mse_r, 1e-30)
+        s_star = mse1_t / mse_r
+        pt_fps = 1.0 / (s_star * t_pt)
+        out[name] = {"restir_rmse": math.sqrt(mse_r), "pt_1spp_rmse": math.sqrt(mse1_t),
+                     "pt_spp_at_equal_rmse": round(s_star, 3), "pt_frames_per_s_at_equal_rmse": round(pt_fps, 3),
+                     "speedup": round(restir_fps / pt_fps, 4)}
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,31 @@ typedef struct {
  * object ids. */
 tof_status tof_debug_set_history(tof_ctx* ctx, const tof_history_desc* history);
 
+/* Per-kernel GPU timing with HIP events recorded on the render stream around
+ * each launch (off by default).  Kernel ids index tof_kernel_times. */
+enum {
+    TOF_K_BVH = 0,        /* world transform + LBVH build of a moved frame */
+    TOF_K_GBUFFER,
+    TOF_K_INITIAL,        /* path trees + per-plane RIS + plain PT deposit */
+    TOF_K_TEMPORAL_PREP,  /* reprojection + work list */
+    TOF_K_TEMPORAL,       /* temporal GRIS merge */
+    TOF_K_SPATIAL_PREP,   /* neighbour choice + work list */
+    TOF_K_SPATIAL,        /* spatial GRIS merge */
+    TOF_K_SPLAT,
+    TOF_K_COUNT
+};
+typedef struct {
+    double ms[TOF_K_COUNT];          /* summed event time per kernel group */
+    uint64_t launches[TOF_K_COUNT];  /* timed launches per group */
+    uint64_t work_items[2];          /* temporal, spatial (pixel, plane) items in timed frames */
+} tof_kernel_times;
+
+/* Enable or disable event timing; enabling clears the accumulated times. */
+tof_status tof_set_kernel_timing(tof_ctx* ctx, int enabled);
+
+/* Accumulated per-kernel times since timing was enabled (synchronizes). */
+tof_status tof_get_kernel_times(tof_ctx* ctx, tof_kernel_times* out);
+
 /* Static string for a status code. */
 const char* tof_status_string(tof_status status);
 

@@ -84,6 +84,17 @@ struct tof_ctx {
     hipEvent_t xf_ev[2] = {nullptr, nullptr};
     int xf_ring = 0;
     uint64_t frames = 0;
+    // kernel timing: event pairs recorded in order, reduced on query
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_kernel;
+    std::vector<uint32_t*> item_counts;    // device copies of the work-list sizes
+    uint32_t* item_hist = nullptr;         // [2 * max_frames] temporal/spatial counts
+    size_t item_slots = 0, item_used = 0;
+    double acc_ms[TOF_K_COUNT] = {};
+    uint64_t acc_n[TOF_K_COUNT] = {};
+    uint64_t acc_items[2] = {};
 };
 
 namespace {
@@ -171,6 +182,33 @@ tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
     return TOF_OK;
 }
 
+// start/stop of one timed launch group (no-ops unless timing is on)
+hipError_t timer_mark(tof_ctx* c, int kernel, hipStream_t st) {
+    if (!c->timing) return hipSuccess;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return err;
+        c->ev_pool.push_back(e);
+        c->ev_kernel.push_back(-1);
+    }
+    c->ev_kernel[c->ev_used] = kernel;
+    return hipEventRecord(c->ev_pool[c->ev_used++], st);
+}
+
+void timer_reduce(tof_ctx* c) {
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev_pool[i], c->ev_pool[i + 1]) == hipSuccess) {
+            int k = c->ev_kernel[i];
+            c->acc_ms[k] += ms;
+            c->acc_n[k] += 1;
+        }
+    }
+    (void)hipGetLastError();
+    c->ev_used = 0;
+}
+
 SlotDev slot_dev(const tof_ctx* c, int i) {
     const SlotHost& h = c->slot[i];
     const GeomBuf& g = c->geom[h.geom];
@@ -250,6 +288,7 @@ void tof_destroy(tof_ctx* c) {
         if (c->xf_pinned[i]) (void)hipHostFree(c->xf_pinned[i]);
         if (c->xf_ev[i]) (void)hipEventDestroy(c->xf_ev[i]);
     }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -421,6 +460,9 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->nb, P * (size_t)std::max(d->spatial_k, 1)));
     TOF_TRY(alloc_t(c, a, &c->items, P * B));
     TOF_TRY(alloc_t(c, a, &c->count, 64));
+    c->item_slots = 2 * 4096;
+    c->item_used = 0;
+    TOF_TRY(alloc_t(c, a, &c->item_hist, c->item_slots));
     c->max_items = P * B;
     c->sd = *d;
     Sens& s = c->s;
@@ -498,6 +540,44 @@ tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
     return TOF_OK;
 }
 
+tof_status tof_set_kernel_timing(tof_ctx* c, int enabled) {
+    if (!c) return TOF_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    c->timing = enabled != 0;
+    c->ev_used = 0;
+    for (int k = 0; k < TOF_K_COUNT; ++k) {
+        c->acc_ms[k] = 0.0;
+        c->acc_n[k] = 0;
+    }
+    c->acc_items[0] = c->acc_items[1] = 0;
+    c->item_used = 0;
+    return TOF_OK;
+}
+
+tof_status tof_get_kernel_times(tof_ctx* c, tof_kernel_times* out) {
+    if (!c || !out) return TOF_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    timer_reduce(c);
+    if (c->item_used) {
+        std::vector<uint32_t> h(c->item_used);
+        HIP_TRY(hipMemcpy(h.data(), c->item_hist, 4 * c->item_used, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < c->item_used; i += 2) {
+            c->acc_items[0] += h[i];
+            c->acc_items[1] += h[i + 1];
+        }
+        c->item_used = 0;
+    }
+    for (int k = 0; k < TOF_K_COUNT; ++k) {
+        out->ms[k] = c->acc_ms[k];
+        out->launches[k] = c->acc_n[k];
+    }
+    out->work_items[0] = c->acc_items[0];
+    out->work_items[1] = c->acc_items[1];
+    return TOF_OK;
+}
+
 tof_status tof_reservoirs_reset(tof_ctx* c) {
     if (!c) return TOF_ERR_INVALID_ARG;
     c->prev_valid = false;
@@ -562,8 +642,10 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         std::memcpy(c->xf_pinned[ring], fr->object_xforms, sizeof(float) * 12 * O);
         HIP_TRY(hipMemcpyAsync(g.xf, c->xf_pinned[ring], sizeof(float) * 12 * O, hipMemcpyHostToDevice, st));
         HIP_TRY(hipEventRecord(c->xf_ev[ring], st));
+        HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, c->n_vert, st);
         if (c->n_tri > 0) tofh::launch_bvh_build(c->d_tv, g.wv, c->n_tri, g.nodes, g.leaves, g.parent, c->bvh_scratch, st);
+        HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         g.built = true;
     }
     cur.valid = true;
@@ -595,22 +677,37 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     const size_t P = (size_t)c->s.P, B = (size_t)c->s.B;
 
     tofh::GBufOut gout{cur.gb_obj, cur.gb_xi0, cur.gb_xi1, cur.gb_p, cur.gb_n};
+    HIP_TRY(timer_mark(c, TOF_K_GBUFFER, st));
     tofh::launch_gbuffer(a, gout, st);
+    HIP_TRY(timer_mark(c, TOF_K_GBUFFER, st));
     tofh::launch_fill_u32((uint32_t*)c->pt, 0u, P * B, st);
     ResSet& can = c->sets[0];
     ResSet& tmp = c->sets[1];
     const int fin_new = c->fin_prev == 2 ? 3 : 2;
+    HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
     tofh::launch_initial(a, can, c->pt, c->direct, st);
+    HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
+    const bool record_items = c->timing && c->item_used + 2 <= c->item_slots;
+    uint32_t* item_slot = record_items ? c->item_hist + c->item_used : nullptr;
+    if (record_items) {
+        tofh::launch_fill_u32(item_slot, 0u, 2, st);
+        c->item_used += 2;
+    }
     const ResSet* shown = nullptr;
     if (c->s.debug_stage == TOF_STAGE_CANONICAL) shown = &can;
     const ResSet* cur_set = &can;
     bool temporal_done = false;
     if (c->s.temporal && c->prev_valid && prev.valid) {
         const ResSet& pf = c->sets[c->fin_prev];
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_PREP, st));
         tofh::launch_reproject(a, can, pf, c->prev_pix, tmp.M, st);
         tofh::launch_fill_u32(c->count, 0u, 1, st);
         tofh::launch_items(a, 0, can, pf, c->prev_pix, 0, c->items, c->count, tmp.mask, st);
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_PREP, st));
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL, st));
         tofh::launch_temporal(a, can, pf, c->prev_pix, c->items, c->count, c->max_items, tmp, st);
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL, st));
+        if (item_slot) HIP_TRY(hipMemcpyAsync(item_slot, c->count, 4, hipMemcpyDeviceToDevice, st));
         cur_set = &tmp;
         temporal_done = true;
     }
@@ -626,15 +723,27 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         if (out_idx == cur_idx) out_idx = 0;
         ResSet& in = c->sets[cur_idx];
         ResSet& out = c->sets[out_idx];
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
         tofh::launch_neighbours(a, r, in, c->nb, out.M, st);
         tofh::launch_fill_u32(c->count, 0u, 1, st);
         tofh::launch_items(a, 1, in, in, c->nb, c->s.k, c->items, c->count, out.mask, st);
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL, st));
         tofh::launch_spatial(a, r, in, c->nb, c->items, c->count, c->max_items, out, st);
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL, st));
+        if (item_slot && r == 0) HIP_TRY(hipMemcpyAsync(item_slot + 1, c->count, 4, hipMemcpyDeviceToDevice, st));
         cur_idx = out_idx;
     }
     if (cur_idx != fin_new) std::swap(c->sets[cur_idx], c->sets[fin_new]);
-    if (c->s.debug_stage == TOF_STAGE_FINAL)
+    if (c->s.debug_stage == TOF_STAGE_FINAL) {
+        HIP_TRY(timer_mark(c, TOF_K_SPLAT, st));
         tofh::launch_splat(a, c->sets[fin_new], c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
+        HIP_TRY(timer_mark(c, TOF_K_SPLAT, st));
+    }
+    if (c->timing && c->ev_used > 4096) {   // bound the pool: fold finished pairs
+        HIP_TRY(hipStreamSynchronize(st));
+        timer_reduce(c);
+    }
     if (hipGetLastError() != hipSuccess) return TOF_ERR_DEVICE;
     c->fin_prev = fin_new;
     c->prev_valid = true;

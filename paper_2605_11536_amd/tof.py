@@ -62,6 +62,14 @@ class tof_history_desc(C.Structure):
                 ("mask", C.POINTER(C.c_uint32))]
 
 
+KERNELS = ("bvh", "gbuffer", "initial", "temporal_prep", "temporal", "spatial_prep", "spatial", "splat")
+
+
+class tof_kernel_times(C.Structure):
+    _fields_ = [("ms", C.c_double * len(KERNELS)), ("launches", C.c_uint64 * len(KERNELS)),
+                ("work_items", C.c_uint64 * 2)]
+
+
 class tof_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("shifts", "shifts_ok", "newton_attempts", "newton_converged",
                                           "newton_iters", "newton_paths_ok", "rays", "frames", "bvh_overflow")]
@@ -88,6 +96,10 @@ def lib():
         L.tof_get_stats.argtypes = [C.c_void_p, C.POINTER(tof_stats)]
         L.tof_debug_set_history.argtypes = [C.c_void_p, C.POINTER(tof_history_desc)]
         L.tof_debug_set_history.restype = C.c_int
+        L.tof_set_kernel_timing.argtypes = [C.c_void_p, C.c_int]
+        L.tof_set_kernel_timing.restype = C.c_int
+        L.tof_get_kernel_times.argtypes = [C.c_void_p, C.POINTER(tof_kernel_times)]
+        L.tof_get_kernel_times.restype = C.c_int
         L.tof_status_string.argtypes = [C.c_int]
         L.tof_status_string.restype = C.c_char_p
         for f in ("tof_create", "tof_scene_upload", "tof_sensor_set", "tof_render_frame",
@@ -211,6 +223,18 @@ def tof_debug_set_history(h, hist: dict) -> None:
     _check("tof_debug_set_history", lib().tof_debug_set_history(h, C.byref(d)))
 
 
+def tof_set_kernel_timing(h, enabled: bool) -> None:
+    _check("tof_set_kernel_timing", lib().tof_set_kernel_timing(h, int(bool(enabled))))
+
+
+def tof_get_kernel_times(h) -> dict:
+    t = tof_kernel_times()
+    _check("tof_get_kernel_times", lib().tof_get_kernel_times(h, C.byref(t)))
+    out = {k: {"ms": float(t.ms[i]), "launches": int(t.launches[i])} for i, k in enumerate(KERNELS)}
+    out["work_items"] = {"temporal": int(t.work_items[0]), "spatial": int(t.work_items[1])}
+    return out
+
+
 def tof_status_string(status: int) -> str:
     return lib().tof_status_string(int(status)).decode()
 
@@ -261,6 +285,12 @@ class Renderer:
 
     def reset(self):
         tof_reservoirs_reset(self.h)
+
+    def set_kernel_timing(self, enabled: bool):
+        tof_set_kernel_timing(self.h, enabled)
+
+    def kernel_times(self) -> dict:
+        return tof_get_kernel_times(self.h)
 
     def set_history(self, hist: dict):
         tof_debug_set_history(self.h, hist)
