@@ -30,7 +30,21 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-REC_BYTES = 76          # one reservoir record: 4 f32 + 3 u32 + 4 x (obj, xi0, xi1)
+# Algorithmic work model (counted events x fixed per-event costs)
+NODE_BYTES = 64         # one BVH internal node: two child boxes + two child links
+TRI_BYTES = 48          # one leaf: three float4 vertices
+F_NODE = 55             # FP32 ops of one node visit (two slab tests, near/far order)
+F_TRI = 47              # FP32 ops of one watertight ray/triangle test
+F_NEWTON_ITER = 220     # one Newton iteration: length function + derivatives, step, line-search trial
+F_NEWTON_SETUP = 600    # per solve: chart points, source/destination evaluation, final determinants
+F_SHIFT = 300           # per shift: replayed BSDF sampling/evaluation, Jacobian and target
+SPLAT_BYTES = 4 + 4 + 4 + 0.125   # per (pixel, plane): PT deposit read, two histogram writes, mask bits
+REC_HEAD_BYTES = 8      # per non-empty (pixel, plane): W and phat
+
+
+def valu_flops(w):
+    return (F_NODE * w["node_visits"] + F_TRI * w["tri_tests"] + F_NEWTON_ITER * w["newton_iters"]
+            + F_NEWTON_SETUP * w["newton_attempts"] + F_SHIFT * w["shifts"])
 
 
 def parse():
@@ -147,37 +161,55 @@ def main():
     }
 
     # per-kernel times (HIP events on the render stream, timed region only)
-    kms = {k: v["ms"] for k, v in kt.items() if k != "work_items"}
-    kl = {k: v["launches"] for k, v in kt.items() if k != "work_items"}
+    groups = [k for k in kt if k != "work_items"]
+    kms = {k: kt[k]["ms"] for k in groups}
+    kl = {k: kt[k]["launches"] for k in groups}
     result["kernel_ms_per_frame"] = {k: round(v / max(args.steps, 1), 3) for k, v in kms.items()}
-    items_t, items_s = kt["work_items"]["temporal"], kt["work_items"]["spatial"]
-    result["work_items_per_frame"] = {"temporal": items_t // args.steps, "spatial": items_s // args.steps}
+    wi = kt["work_items"]
+    result["work_items_per_frame"] = {k: v // args.steps for k, v in wi.items()}
     result["shift_stats_per_frame"] = {k: dstats[k] // args.steps for k in
                                        ("shifts", "shifts_ok", "newton_attempts", "newton_converged",
-                                        "newton_paths_ok", "rays")}
+                                        "newton_paths_ok", "rays", "node_visits", "tri_tests")}
     nt = max(dstats["newton_attempts"], 1)
     result["newton"] = {"iters_per_converged": round(dstats["newton_iters"] / max(dstats["newton_converged"], 1), 4),
                         "newton_sr": round(dstats["newton_converged"] / nt, 4),
                         "actual_sr": round(dstats["newton_paths_ok"] / nt, 4)}
     result["rays_per_s"] = round(dstats["rays"] / elapsed, 1)
+    result["integrity"] = {"bvh_overflow": dstats["bvh_overflow"], "bad_records": dstats["bad_records"]}
+    result["traversal"] = {"nodes_per_ray": round(dstats["node_visits"] / max(dstats["rays"], 1), 2),
+                           "tri_tests_per_ray": round(dstats["tri_tests"] / max(dstats["rays"], 1), 2),
+                           "bytes_per_ray": round((NODE_BYTES * dstats["node_visits"] + TRI_BYTES * dstats["tri_tests"])
+                                                  / max(dstats["rays"], 1), 1)}
 
-    # roofline of the dominant kernel (see the design doc for the byte model)
+    # roofline of the dominant kernel group (byte and flop models in the design doc)
     dom = max(kms, key=lambda k: kms[k])
-    avg_ms = kms[dom] / max(kl[dom], 1)
-    if dom == "spatial":
-        # algorithmic bytes per launch: per work item the k+1 masks, M and
-        # neighbour ids, every non-empty candidate record it reads, the output
-        # record; per shift the BVH nodes are not counted (cache resident)
-        recs = dstats.get("records_read", 0)
-        per_item = 4 * (sensor.spatial_k + 1) + 4 * (sensor.spatial_k + 1) + 4 * sensor.spatial_k + REC_BYTES
-        algo = (items_s / max(kl[dom], 1)) * per_item
-        result["roofline"] = {"bound": "hbm", "achieved": round(algo / (avg_ms * 1e-3) / 1e9, 2),
-                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(algo / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5), "traffic": None,
-                              "kernel": "k_spatial", "avg_launch_ms": round(avg_ms, 4)}
+    avg_s = kms[dom] / max(kl[dom], 1) * 1e-3
+    if dom in ("splat",):
+        occ = float(np.count_nonzero(restir_out["hist"])) / restir_out["hist"].size
+        per_launch = P * B * (SPLAT_BYTES + REC_HEAD_BYTES * occ)
+        ach = per_launch / avg_s / 1e9
+        result["roofline"] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_splat",
+                              "avg_launch_ms": round(avg_s * 1e3, 4)}
     else:
-        result["roofline"] = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": None, "traffic": None, "kernel": dom, "avg_launch_ms": round(avg_ms, 4)}
+        w = kt[dom]["work"]
+        per_launch = valu_flops(w) / max(kl[dom], 1)
+        ach = per_launch / avg_s / 1e12
+        kname = {"spatial": "k_cand", "temporal": "k_cand", "spatial_merge": "k_merge", "temporal_merge": "k_merge",
+                 "initial": "k_initial", "gbuffer": "k_gbuffer"}.get(dom, dom)
+        result["roofline"] = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(ach / FP32_PEAK_TFLOPS, 5), "traffic": None,
+                              "kernel": f"{kname} ({dom})", "avg_launch_ms": round(avg_s * 1e3, 4),
+                              "flops_per_launch": per_launch}
+    # the streaming passes against HBM: the splat over every (pixel, plane)
+    if kl.get("splat"):
+        occ = float(np.count_nonzero(restir_out["hist"])) / restir_out["hist"].size
+        sp_s = kms["splat"] / kl["splat"] * 1e-3
+        sp_bytes = P * B * (SPLAT_BYTES + REC_HEAD_BYTES * occ)
+        result["splat_hbm"] = {"achieved_GBs": round(sp_bytes / sp_s / 1e9, 1),
+                               "frac": round(sp_bytes / sp_s / 1e9 / HBM_PEAK_GBS, 4),
+                               "bytes_per_launch": int(sp_bytes), "occupancy": round(occ, 5),
+                               "avg_launch_ms": round(sp_s * 1e3, 4)}
 
     # equal RMSE against plain ToF PT on the same GPU
     if not args.no_equal_rmse:

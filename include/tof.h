@@ -128,6 +128,9 @@ typedef struct {
     uint64_t rays;                   /* closest-hit + shadow rays traced */
     uint64_t frames;                 /* frames rendered */
     uint64_t bvh_overflow;           /* traversal stack overflows (must be 0) */
+    uint64_t node_visits;            /* BVH internal nodes visited (two box tests each) */
+    uint64_t tri_tests;              /* ray/triangle tests */
+    uint64_t bad_records;            /* reservoir records rejected as malformed (must be 0) */
 } tof_stats;
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps what the
@@ -202,22 +205,36 @@ enum {
     TOF_K_GBUFFER,
     TOF_K_INITIAL,        /* path trees + per-plane RIS + plain PT deposit */
     TOF_K_TEMPORAL_PREP,  /* reprojection + work list */
-    TOF_K_TEMPORAL,       /* temporal GRIS merge */
+    TOF_K_TEMPORAL,       /* temporal candidate weights (shifts) */
+    TOF_K_TEMPORAL_MERGE, /* temporal reservoir merge */
     TOF_K_SPATIAL_PREP,   /* neighbour choice + work list */
-    TOF_K_SPATIAL,        /* spatial GRIS merge */
+    TOF_K_SPATIAL,        /* spatial candidate weights (shifts) */
+    TOF_K_SPATIAL_MERGE,  /* spatial reservoir merge */
     TOF_K_SPLAT,
     TOF_K_COUNT
 };
 typedef struct {
+    uint64_t rays;                   /* closest-hit + shadow rays */
+    uint64_t node_visits;            /* BVH internal nodes visited */
+    uint64_t tri_tests;              /* ray/triangle tests */
+    uint64_t shifts;                 /* shift attempts counted by the group */
+    uint64_t newton_attempts;        /* Newton solves started */
+    uint64_t newton_iters;           /* Newton iterations of converged solves */
+} tof_kernel_work;
+typedef struct {
     double ms[TOF_K_COUNT];          /* summed event time per kernel group */
     uint64_t launches[TOF_K_COUNT];  /* timed launches per group */
-    uint64_t work_items[2];          /* temporal, spatial (pixel, plane) items in timed frames */
+    uint64_t work_items[4];          /* in timed frames: temporal items, temporal candidate tasks,
+                                        spatial items, spatial candidate tasks (first round) */
+    tof_kernel_work work[TOF_K_COUNT]; /* events per group since timing was enabled; the merge
+                                          groups re-derive selected shifts without counting them */
 } tof_kernel_times;
 
 /* Enable or disable event timing; enabling clears the accumulated times. */
 tof_status tof_set_kernel_timing(tof_ctx* ctx, int enabled);
 
-/* Accumulated per-kernel times since timing was enabled (synchronizes). */
+/* Accumulated per-kernel times and work since timing was enabled
+ * (synchronizes). */
 tof_status tof_get_kernel_times(tof_ctx* ctx, tof_kernel_times* out);
 
 /* Static string for a status code. */

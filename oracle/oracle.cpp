@@ -848,24 +848,26 @@ struct Oracle {
             Vertex nx;
             st.c[ST_RAYS]++;
             if (!trace(FD, cur, wo, nx)) return R;
+            // the offset path must not reconnect earlier than the base path
+            if (recon_ok(cur, nx)) return R;
             pdf_y *= pdf;
             ys.push_back(nx);
             wi = -wo;
         }
-        // the offset path must not reconnect earlier than the base path
-        for (size_t kk = 2; kk <= ys.size(); ++kk)
-            if (recon_ok(ys[kk - 2], ys[kk - 1])) return R;
-
+        // Every rejection below is a plain conjunction, so the order of the
+        // tests does not change the result; rays are traced last so that only
+        // shifts that would contribute pay for them (the ray count depends on
+        // this order).
         if (x.k == 0) {   // pure random replay
             double len;
             double C = path_eval(dst_slot, dst_pix, ys, len);
             if (!(C > 0.0)) return R;
-            st.c[ST_RAYS]++;
-            if (!light_visible(dst_slot, dst_pix, ys.back())) return R;
             double J = x.pre_pdf / pdf_y;
             if (!(J >= 1.0 / s.j_max && J <= s.j_max)) return R;
             double ph = in_plane(plane, len) ? C : 0.0;
             if (!(ph > 0.0)) return R;
+            st.c[ST_RAYS]++;
+            if (!light_visible(dst_slot, dst_pix, ys.back())) return R;
             R.y = x;
             R.y.len = len;
             R.y.pre_pdf = pdf_y;
@@ -931,27 +933,6 @@ struct Oracle {
         pd.p = cp.p;
         pd.n = cp.n;
         if (length(pd.p - ykm1.p) < dmin) return R;
-        // visibility of the moved edges; the suffix is re-tested when the two
-        // domains belong to different frames (the scene may have moved)
-        st.c[ST_RAYS]++;
-        if (!visible_pts(FD, ykm1, pd)) return R;
-        if (p2light) {
-            st.c[ST_RAYS]++;
-            if (!light_visible(dst_slot, dst_pix, pd)) return R;
-        } else {
-            st.c[ST_RAYS]++;
-            if (!visible_pts(FD, pd, p2_d)) return R;
-            if (src_slot != dst_slot) {
-                Vertex prev = p2_d;
-                for (const Vertex& v : sfx_d) {
-                    st.c[ST_RAYS]++;
-                    if (!visible_pts(FD, prev, v)) return R;
-                    prev = v;
-                }
-                st.c[ST_RAYS]++;
-                if (!light_visible(dst_slot, dst_pix, prev)) return R;
-            }
-        }
         std::vector<Vertex> yfull = ys;
         yfull.push_back(pd);
         if (!p2light) {
@@ -977,6 +958,27 @@ struct Oracle {
         if (!(J >= 1.0 / s.j_max && J <= s.j_max)) return R;
         double ph = in_plane(plane, len) ? C : 0.0;
         if (!(ph > 0.0)) return R;
+        // visibility of the moved edges; the suffix is re-tested when the two
+        // domains belong to different frames (the scene may have moved)
+        st.c[ST_RAYS]++;
+        if (!visible_pts(FD, ykm1, pd)) return R;
+        if (p2light) {
+            st.c[ST_RAYS]++;
+            if (!light_visible(dst_slot, dst_pix, pd)) return R;
+        } else {
+            st.c[ST_RAYS]++;
+            if (!visible_pts(FD, pd, p2_d)) return R;
+            if (src_slot != dst_slot) {
+                Vertex prev = p2_d;
+                for (const Vertex& v : sfx_d) {
+                    st.c[ST_RAYS]++;
+                    if (!visible_pts(FD, prev, v)) return R;
+                    prev = v;
+                }
+                st.c[ST_RAYS]++;
+                if (!light_visible(dst_slot, dst_pix, prev)) return R;
+            }
+        }
         R.y = x;
         R.y.xkm1.obj = ykm1.obj;
         R.y.xkm1.xi[0] = ykm1.xi[0];

@@ -13,6 +13,12 @@ using tofh::GBufOut;
 
 namespace {
 
+// Waves per SIMD the tracing kernels are compiled for: caps their VGPRs at
+// 512 / TOF_TRACE_WAVES (the LDS stacks allow 2.5 waves per SIMD).
+#ifndef TOF_TRACE_WAVES
+#define TOF_TRACE_WAVES 2
+#endif
+#define TOF_TRACE_KERNEL __global__ void __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(TOF_TRACE_WAVES)))
 constexpr int kTB = 128;   // lanes per block of the tracing kernels (LDS stack: 64 x 128 x 4 B = 32 KB)
 
 __device__ __forceinline__ bool mask_bit(const uint32_t* mask, int P, int pl, int pix) {
@@ -71,7 +77,7 @@ __global__ void __launch_bounds__(kTB) k_gbuffer(FrameArgs a, GBufOut out) {
 // of the reservoir of its time bin and of the gate (Sec. 4.5 per-bin deposit),
 // and is splatted into the plain path-tracing buffer.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kTB) k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
+TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                                                  float2* __restrict__ direct) {
     __shared__ uint32_t stk[kStackDepth * kTB];
     Counters st = {};
@@ -110,7 +116,7 @@ __global__ void __launch_bounds__(kTB) k_initial(FrameArgs a, ResSet can, float*
                         float C = beta * fs * fabsf(dot(xi.n, wl)) * light_emit(s, S, G, pix, xi.p) / (dl * dl);
                         if (C > 0.f) {
                             Seg sg = seg_light(s, S, G, pix, xi);
-                            if (!tr.all_visible(G, &sg, 1)) C = 0.f;
+                            if (!tr.visible(G, sg)) C = 0.f;
                         }
                         float li = plen + dl;
                         if (C > 0.f && i == 1) {
@@ -156,9 +162,9 @@ __global__ void __launch_bounds__(kTB) k_initial(FrameArgs a, ResSet can, float*
                                     *mw = m | bit;
                                     store_rec(can, idx, rec, w);
                                 } else {
-                                    float ws = can.W[idx] + w;
+                                    float ws = rec_W(can, idx) + w;
                                     if (u.u(q) * ws < w) store_rec(can, idx, rec, ws);
-                                    else can.W[idx] = ws;
+                                    else rec_W(can, idx) = ws;
                                 }
                             }
                         }
@@ -186,7 +192,7 @@ __global__ void __launch_bounds__(kTB) k_initial(FrameArgs a, ResSet can, float*
                     int b = __ffs(m) - 1;
                     m &= m - 1;
                     size_t idx = (size_t)(32 * w + b) * P + pix;
-                    can.W[idx] = can.W[idx] / can.phat[idx];
+                    rec_W(can, idx) = rec_W(can, idx) / rec_phat(can, idx);
                 }
             }
         }
@@ -276,197 +282,235 @@ __global__ void k_neighbours(FrameArgs a, int round, const float* __restrict__ M
 }
 
 // ---------------------------------------------------------------------------
-// work lists: mode 0 (temporal) ORs the canonical mask and the previous
-// frame's mask at the reprojected pixel; mode 1 (spatial) ORs the input mask
-// of the pixel and of its neighbours.  Also clears the output mask.
+// work lists.  Mode 0 (temporal): candidates are the canonical reservoir and
+// the previous frame's final reservoir at the reprojected pixel.  Mode 1
+// (spatial): the pixel's input reservoir and those of its k neighbours.  For
+// every plane non-empty in any candidate one item (pixel, plane | cmask << 16)
+// is emitted, cmask bit c marking the non-empty candidates, and one task
+// (item, c) per non-empty candidate.  Also clears the output mask.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t union_word(const FrameArgs& a, int mode, const uint32_t* m1, const uint32_t* m2,
-                                               const int* links, int nlinks, int w, int pix) {
+__device__ __forceinline__ uint32_t cand_word(const FrameArgs& a, int mode, const uint32_t* m1, const uint32_t* m2,
+                                              const int* links, int c, int w, int pix) {
     const int P = a.s.P;
-    uint32_t m = m1[(size_t)w * P + pix];
-    if (mode == 0) {
-        int q = links[pix];
-        if (q >= 0) m |= m2[(size_t)w * P + q];
-    } else {
-        for (int l = 0; l < nlinks; ++l) {
-            int q = links[(size_t)l * P + pix];
-            if (q >= 0) m |= m1[(size_t)w * P + q];
-        }
+    if (c == 0) return m1[(size_t)w * P + pix];
+    int q = mode == 0 ? links[pix] : links[(size_t)(c - 1) * P + pix];
+    if (q < 0) return 0u;
+    return (mode == 0 ? m2 : m1)[(size_t)w * P + q];
+}
+
+__device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t& ea, uint32_t& eb, uint32_t* base,
+                                            uint32_t* count) {
+    __shared__ uint32_t s_a[256], s_b[256];
+    __shared__ uint32_t s_base[2];
+    s_a[threadIdx.x] = a;
+    s_b[threadIdx.x] = b;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t va = (int)threadIdx.x >= off ? s_a[threadIdx.x - off] : 0u;
+        uint32_t vb = (int)threadIdx.x >= off ? s_b[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s_a[threadIdx.x] += va;
+        s_b[threadIdx.x] += vb;
+        __syncthreads();
     }
-    return m;
+    if (threadIdx.x == 255) {
+        s_base[0] = atomicAdd(count, s_a[255]);
+        s_base[1] = atomicAdd(count + 1, s_b[255]);
+    }
+    __syncthreads();
+    ea = s_base[0] + s_a[threadIdx.x] - a;
+    eb = s_base[1] + s_b[threadIdx.x] - b;
+    (void)base;
 }
 
 __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint32_t* __restrict__ m1,
                                                const uint32_t* __restrict__ m2, const int* __restrict__ links,
-                                               int nlinks, uint2* __restrict__ items, uint32_t* __restrict__ count,
-                                               uint32_t* __restrict__ out_mask) {
-    __shared__ uint32_t s_scan[256];
-    __shared__ uint32_t s_base;
+                                               int ncand, uint2* __restrict__ items, uint2* __restrict__ tasks,
+                                               uint32_t* __restrict__ count, uint32_t* __restrict__ out_mask) {
     const int P = a.s.P;
     int pix = blockIdx.x * 256 + threadIdx.x;
     bool valid = pix < P && a.F.g[0].gb_obj[pix] >= 0;
-    uint32_t c = 0;
+    uint32_t ni = 0, nt = 0;
     if (pix < P)
         for (int w = 0; w < a.s.mask_words; ++w) out_mask[(size_t)w * P + pix] = 0u;
-    if (valid)
-        for (int w = 0; w < a.s.mask_words; ++w) c += __popc(union_word(a, mode, m1, m2, links, nlinks, w, pix));
-    s_scan[threadIdx.x] = c;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        uint32_t v = (int)threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0u;
-        __syncthreads();
-        s_scan[threadIdx.x] += v;
-        __syncthreads();
-    }
-    if (threadIdx.x == 255) s_base = atomicAdd(count, s_scan[255]);
-    __syncthreads();
-    uint32_t pos = s_base + s_scan[threadIdx.x] - c;
-    if (valid && c) {
+    if (valid) {
         for (int w = 0; w < a.s.mask_words; ++w) {
-            uint32_t m = union_word(a, mode, m1, m2, links, nlinks, w, pix);
-            while (m) {
-                int b = __ffs(m) - 1;
-                m &= m - 1;
-                items[pos++] = make_uint2((uint32_t)pix, (uint32_t)(32 * w + b));
+            uint32_t u = 0;
+            for (int c = 0; c < ncand; ++c) {
+                uint32_t m = cand_word(a, mode, m1, m2, links, c, w, pix);
+                u |= m;
+                nt += __popc(m);
             }
+            ni += __popc(u);
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// temporal GRIS (Sec. 3.2.3-3.2.4): canonical + previous final reservoir,
-// generalized balance heuristic with confidence M, M_prev capped.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kTB) k_temporal(FrameArgs a, ResSet can, ResSet prev, const int* __restrict__ prev_pix,
-                                                  const uint2* __restrict__ items, const uint32_t* __restrict__ count,
-                                                  ResSet out) {
-    __shared__ uint32_t stk[kStackDepth * kTB];
-    Counters st = {};
-    Tracer tr{a.S, stk + threadIdx.x, kTB, st};
-    const Sens& s = a.s;
-    const int P = s.P;
-    const uint32_t n = *count;
-    for (uint32_t it = blockIdx.x * kTB + threadIdx.x; it < n; it += gridDim.x * kTB) {
-        const uint2 item = items[it];
-        const int pix = (int)item.x, pl = (int)item.y;
-        const int qp = prev_pix[pix];
-        const float mc = can.M[pix];
-        const float mp = qp >= 0 ? fminf(prev.M[qp], s.m_cap) : 0.f;
-        const Draw u = philox(s.seed, full_pixel(s, pix), a.frame, PASS_TEMPORAL, 0, (uint64_t)pl);
-        const size_t idx = (size_t)pl * P + pix;
-        const bool hasc = mask_bit(can.mask, P, pl, pix);
-        const bool hasp = qp >= 0 && mask_bit(prev.mask, P, pl, qp);
-        float ws = 0.f;
-        bool have = false;
-        Rec sel;
-        for (int cand = 0; cand < 2; ++cand) {
-            if (cand == 0 ? !hasc : !hasp) continue;
-            float Wx;
-            Rec x = cand == 0 ? load_rec(can, idx, Wx) : load_rec(prev, (size_t)pl * P + qp, Wx);
-            ShiftOut sh;
-            sh.ok = false;
-            if (cand == 1 || qp >= 0)
-                sh = shift_path(s, a.S, a.F, tr, x, cand == 0 ? 0 : 1, cand == 0 ? pix : qp, cand == 0 ? 1 : 0,
-                                cand == 0 ? qp : pix, pl, 0.f);
-            float w;
-            if (cand == 0) {
-                float ph = x.phat;
-                float den = mc * ph;
-                if (sh.ok) den += mp * sh.phat * sh.J;
-                w = (mc * ph / den) * ph * Wx;
-            } else {
-                if (!sh.ok) continue;
-                float A = mp * x.phat / sh.J;
-                float m = A / (A + mc * sh.phat);
-                w = m * sh.phat * Wx * sh.J;
-                x = sh.y;
+    uint32_t pi, pt_;
+    block_scan2(ni, nt, pi, pt_, nullptr, count);
+    if (valid && ni) {
+        for (int w = 0; w < a.s.mask_words; ++w) {
+            uint32_t wm[kMaxK + 1];
+            uint32_t u = 0;
+            for (int c = 0; c < ncand; ++c) {
+                wm[c] = cand_word(a, mode, m1, m2, links, c, w, pix);
+                u |= wm[c];
             }
-            ws += w;
-            if (u.u(cand) * ws < w) {
-                sel = x;
-                have = true;
-            }
-        }
-        if (have && ws > 0.f) {
-            store_rec(out, idx, sel, ws / sel.phat);
-            atomicOr(out.mask + (size_t)(pl >> 5) * P + pix, 1u << (pl & 31));
-        }
-    }
-    flush_counters(st, a.counters);
-}
-
-// ---------------------------------------------------------------------------
-// spatial GRIS round: canonical + k neighbours, generalized balance heuristic;
-// empty neighbour domains still enter every denominator through their M.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kTB) k_spatial(FrameArgs a, int round, ResSet in, const int* __restrict__ nb,
-                                                 const uint2* __restrict__ items, const uint32_t* __restrict__ count,
-                                                 ResSet out) {
-    __shared__ uint32_t stk[kStackDepth * kTB];
-    Counters st = {};
-    Tracer tr{a.S, stk + threadIdx.x, kTB, st};
-    const Sens& s = a.s;
-    const int P = s.P;
-    const int K = s.k;
-    const uint32_t n = *count;
-    for (uint32_t it = blockIdx.x * kTB + threadIdx.x; it < n; it += gridDim.x * kTB) {
-        const uint2 item = items[it];
-        const int pix = (int)item.x, pl = (int)item.y;
-        int nbs[kMaxK];
-        float ms[kMaxK];
-        for (int l = 0; l < K; ++l) {
-            nbs[l] = nb[(size_t)l * P + pix];
-            ms[l] = nbs[l] >= 0 ? in.M[nbs[l]] : 0.f;
-        }
-        const float mq = in.M[pix];
-        const uint64_t fp = full_pixel(s, pix);
-        float ws = 0.f;
-        bool have = false;
-        Rec sel;
-        for (int cand = 0; cand <= K; ++cand) {
-            const int src = cand == 0 ? pix : nbs[cand - 1];
-            if (src < 0 || !mask_bit(in.mask, P, pl, src)) continue;
-            float Wx;
-            const Rec x = load_rec(in, (size_t)pl * P + src, Wx);
-            Rec y = x;
-            float phq = x.phat, Jj = 1.0f;
-            float den = mq * x.phat;
-            bool fail = false;
-            // step -1 brings a neighbour's sample into q; steps 0..K-1 shift the
-            // sample from q into every other domain for the MIS denominator
-            for (int step = (cand == 0 ? 0 : -1); step < K; ++step) {
-                if (step >= 0 && (step == cand - 1 || nbs[step] < 0)) continue;
-                ShiftOut sh = shift_path(s, a.S, a.F, tr, step < 0 ? x : y, 0, step < 0 ? src : pix, 0,
-                                         step < 0 ? pix : nbs[step], pl, 0.f);
-                if (step < 0) {
-                    if (!sh.ok) {
-                        fail = true;
-                        break;
+            while (u) {
+                int b = __ffs(u) - 1;
+                u &= u - 1;
+                uint32_t cm = 0;
+                for (int c = 0; c < ncand; ++c)
+                    if ((wm[c] >> b) & 1u) {
+                        cm |= 1u << c;
+                        tasks[pt_++] = make_uint2(pi, (uint32_t)c);
                     }
-                    y = sh.y;
-                    phq = sh.phat;
-                    Jj = sh.J;
-                    den = ms[cand - 1] * x.phat / Jj + mq * phq;
-                } else if (sh.ok) {
-                    den += ms[step] * sh.phat * sh.J;
-                }
-            }
-            if (fail) continue;
-            float w = cand == 0 ? (mq * phq / den) * phq * Wx : ((ms[cand - 1] * x.phat / Jj) / den) * phq * Wx * Jj;
-            float uu = philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + cand / 4))
-                           .u(cand % 4);
-            ws += w;
-            if (uu * ws < w) {
-                sel = y;
-                have = true;
+                items[pi++] = make_uint2((uint32_t)pix, (uint32_t)(32 * w + b) | (cm << 16));
             }
         }
-        if (have && ws > 0.f) {
-            store_rec(out, (size_t)pl * P + pix, sel, ws / sel.phat);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// candidate weights (Sec. 3.2.3, eq. GRIS_resampling_weight with the
+// generalized balance heuristic eq. GRIS_MIS_weight).  One lane per (item,
+// candidate): a neighbour's sample is first shifted into q; then the sample
+// in q is shifted into every other candidate domain for the MIS denominator.
+// Writes (w_c, phat_q(y_c)) to cw[item * ncand + c] and, for c > 0, the
+// fields the forward shift rewrote to sh[2 * (item * ncand + c) + {0, 1}], so
+// that the merge stores exactly the sample that was weighed.
+// ---------------------------------------------------------------------------
+TOF_TRACE_KERNEL k_cand(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
+                                              const uint2* __restrict__ items, const uint2* __restrict__ tasks,
+                                              const uint32_t* __restrict__ count, float2* __restrict__ cw,
+                                              float4* __restrict__ shv) {
+    __shared__ uint32_t stk[kStackDepth * kTB];
+    Counters st = {};
+    Tracer tr{a.S, stk + threadIdx.x, kTB, st};
+    const Sens& s = a.s;
+    const int P = s.P;
+    const int K = mode == 0 ? 1 : s.k;
+    const int ncand = K + 1;
+    const uint32_t n = count[1];
+    for (uint32_t it = blockIdx.x * kTB + threadIdx.x; it < n; it += gridDim.x * kTB) {
+        const uint2 task = tasks[it];
+        const uint2 item = items[task.x];
+        const int c = (int)task.y;
+        const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
+        // candidate source domain: (slot, pixel)
+        int src_slot = 0, src = pix;
+        if (c > 0) {
+            src = mode == 0 ? links[pix] : links[(size_t)(c - 1) * P + pix];
+            src_slot = mode == 0 ? 1 : 0;
+        }
+        const ResSet& R = (mode == 0 && c == 1) ? Bp : A;
+        float Wx;
+        // y starts as the candidate and becomes its shift into q; a shift only
+        // rewrites fields, so one record stays live
+        Rec y = load_rec(R, (size_t)pl * P + src, Wx);
+        const float xphat = y.phat;
+        const float mq = A.M[pix];
+        const float mc = (c == 0) ? mq : (mode == 0 ? fminf(Bp.M[src], s.m_cap) : A.M[src]);
+        float phq = xphat, Jj = 1.0f;
+        float den = mq * xphat;
+        bool fail = false;
+        for (int step = (c == 0 ? 0 : -1); step < K; ++step) {
+            int dpix, dslot;
+            if (step < 0) {
+                dpix = pix;
+                dslot = 0;
+            } else {
+                if (step == c - 1) continue;
+                dpix = mode == 0 ? links[pix] : links[(size_t)step * P + pix];
+                dslot = mode == 0 ? 1 : 0;
+                if (dpix < 0) continue;
+            }
+            const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, step < 0 ? src_slot : 0, step < 0 ? src : pix, dslot,
+                                           dpix, pl, 0.f);
+            if (step < 0) {
+                if (!sh.ok) {
+                    fail = true;
+                    break;
+                }
+                apply_shift(y, sh);
+                phq = sh.phat;
+                Jj = sh.J;
+                den = mc * xphat / Jj + mq * phq;
+            } else if (sh.ok) {
+                const float ml = mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
+                den += ml * sh.phat * sh.J;
+            }
+        }
+        float w = 0.f;
+        const size_t slot = (size_t)task.x * ncand + c;
+        if (!fail) {
+            w = c == 0 ? (mq * phq / den) * phq * Wx : ((mc * xphat / Jj) / den) * phq * Wx * Jj;
+            if (c > 0) {
+                shv[2 * slot] = make_float4(__int_as_float(y.v[0].obj), y.v[0].xi0, y.v[0].xi1,
+                                            __int_as_float(y.v[1].obj));
+                shv[2 * slot + 1] = make_float4(y.v[1].xi0, y.v[1].xi1, y.len, y.pre_pdf);
+            }
+        }
+        cw[slot] = make_float2(w, phq);
+    }
+    flush_counters(st, a.counters);
+}
+
+// ---------------------------------------------------------------------------
+// merge: weighted reservoir sampling over the candidates in order, W = sum/phat.
+// A selected neighbour sample is its source record with the fields its shift
+// into q rewrote (stored by the candidate pass).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, ResSet Bp,
+                                               const int* __restrict__ links, const uint2* __restrict__ items,
+                                               const uint32_t* __restrict__ count, const float2* __restrict__ cw,
+                                               const float4* __restrict__ shv, int round, ResSet out) {
+    const Sens& s = a.s;
+    const int P = s.P;
+    const int K = mode == 0 ? 1 : s.k;
+    const int ncand = K + 1;
+    const uint32_t n = count[0];
+    for (uint32_t it = blockIdx.x * 256 + threadIdx.x; it < n; it += gridDim.x * 256) {
+        const uint2 item = items[it];
+        const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
+        const uint32_t cm = item.y >> 16;
+        const uint64_t fp = full_pixel(s, pix);
+        Draw ut;
+        if (mode == 0) ut = philox(s.seed, fp, a.frame, PASS_TEMPORAL, 0, (uint64_t)pl);
+        float ws = 0.f, sel_phat = 0.f;
+        int sel = -1;
+        for (int c = 0; c < ncand; ++c) {
+            if (!((cm >> c) & 1u)) continue;
+            const float2 r = cw[(size_t)it * ncand + c];
+            if (c > 0 && !(r.x > 0.f)) continue;   // the shift into q failed
+            float u;
+            if (mode == 0) u = ut.u(c);
+            else u = philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + c / 4)).u(c % 4);
+            ws += r.x;
+            if (u * ws < r.x) {
+                sel = c;
+                sel_phat = r.y;
+            }
+        }
+        if (sel >= 0 && ws > 0.f) {
+            const size_t oidx = (size_t)pl * P + pix;
+            float Wx;
+            if (sel == 0) {
+                const Rec x = load_rec(A, oidx, Wx);
+                store_rec(out, oidx, x, ws / sel_phat);
+            } else {
+                const int src = mode == 0 ? links[pix] : links[(size_t)(sel - 1) * P + pix];
+                Rec x = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
+                const size_t slot = (size_t)it * ncand + sel;
+                const float4 s0 = shv[2 * slot], s1 = shv[2 * slot + 1];
+                x.v[0] = VRef{__float_as_int(s0.x), s0.y, s0.z};
+                x.v[1] = VRef{__float_as_int(s0.w), s1.x, s1.y};
+                x.len = s1.z;
+                x.pre_pdf = s1.w;
+                x.phat = sel_phat;
+                store_rec(out, oidx, x, ws / sel_phat);
+            }
             atomicOr(out.mask + (size_t)(pl >> 5) * P + pix, 1u << (pl & 31));
         }
     }
-    flush_counters(st, a.counters);
 }
 
 // ---------------------------------------------------------------------------
@@ -482,7 +526,10 @@ __global__ void k_splat(FrameArgs a, ResSet shown, const float* __restrict__ pt,
         const int pl = (int)(i / (size_t)s.P);
         const int pix = (int)(i - (size_t)pl * s.P);
         float v = 0.f;
-        if (mask_bit(shown.mask, s.P, pl, pix)) v = shown.W[i] * shown.phat[i];
+        if (mask_bit(shown.mask, s.P, pl, pix)) {
+            float2 wp = *(const float2*)(shown.rec + i * 5);
+            v = wp.x * wp.y;
+        }
         float vp = pt[i];
         if (s.include_direct) {
             float2 d = direct[pix];
@@ -527,19 +574,21 @@ void launch_neighbours(const FrameArgs& a, int round, const ResSet& in, int* nb,
                        M_out);
 }
 void launch_items(const FrameArgs& a, int mode, const ResSet& first, const ResSet& second, const int* links,
-                  int nlinks, uint2* items, uint32_t* count, uint32_t* out_mask, hipStream_t st) {
+                  int ncand, uint2* items, uint2* tasks, uint32_t* count, uint32_t* out_mask, hipStream_t st) {
     hipLaunchKernelGGL(k_items, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, mode, first.mask,
-                       second.mask, links, nlinks, items, count, out_mask);
+                       second.mask, links, ncand, items, tasks, count, out_mask);
 }
-void launch_temporal(const FrameArgs& a, const ResSet& can, const ResSet& prev, const int* prev_pix,
-                     const uint2* items, const uint32_t* count, size_t max_items, ResSet out, hipStream_t st) {
-    hipLaunchKernelGGL(k_temporal, dim3(grid_for(max_items, kTB, 16384)), dim3(kTB), 0, st, a, can, prev, prev_pix,
-                       items, count, out);
+void launch_cand(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
+                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, float2* cw,
+                 float4* shv, hipStream_t st) {
+    hipLaunchKernelGGL(k_cand, dim3(grid_for(max_tasks, kTB, 32768)), dim3(kTB), 0, st, a, mode, A, Bp, links, items,
+                       tasks, count, cw, shv);
 }
-void launch_spatial(const FrameArgs& a, int round, const ResSet& in, const int* nb, const uint2* items,
-                    const uint32_t* count, size_t max_items, ResSet out, hipStream_t st) {
-    hipLaunchKernelGGL(k_spatial, dim3(grid_for(max_items, kTB, 16384)), dim3(kTB), 0, st, a, round, in, nb, items,
-                       count, out);
+void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
+                  const uint2* items, const uint32_t* count, size_t max_items, const float2* cw, const float4* shv,
+                  int round, ResSet out, hipStream_t st) {
+    hipLaunchKernelGGL(k_merge, dim3(grid_for(max_items, 256, 32768)), dim3(256), 0, st, a, mode, A, Bp, links, items,
+                       count, cw, shv, round, out);
 }
 void launch_splat(const FrameArgs& a, const ResSet& shown, const float* pt, const float2* direct, float* out_image,
                   float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st) {

@@ -14,6 +14,11 @@ using namespace tofd;
 
 namespace {
 
+// event counters: one bank of kBank u64 per kernel group, summed by tof_get_stats
+constexpr int kBank = 16;
+static_assert(kNumCounters <= kBank, "counter bank too small");
+constexpr size_t kCounterBytes = (size_t)TOF_K_COUNT * kBank * sizeof(unsigned long long);
+
 struct Alloc {
     std::vector<void*> ptrs;
     size_t bytes = 0;
@@ -76,8 +81,11 @@ struct tof_ctx {
     int* prev_pix = nullptr;
     int* nb = nullptr;
     uint2* items = nullptr;
+    uint2* tasks = nullptr;
+    float2* cw = nullptr;
+    float4* shv = nullptr;     // [2 * max_tasks]: fields rewritten by each forward shift
     uint32_t* count = nullptr;
-    size_t max_items = 0;
+    size_t max_items = 0, max_tasks = 0;
     // misc
     unsigned long long* counters = nullptr;
     float* xf_pinned[2] = {nullptr, nullptr};
@@ -94,7 +102,8 @@ struct tof_ctx {
     size_t item_slots = 0, item_used = 0;
     double acc_ms[TOF_K_COUNT] = {};
     uint64_t acc_n[TOF_K_COUNT] = {};
-    uint64_t acc_items[2] = {};
+    uint64_t acc_items[4] = {};
+    unsigned long long work0[TOF_K_COUNT * kBank] = {};   // counters when timing was enabled
 };
 
 namespace {
@@ -150,7 +159,7 @@ V3 hnorm(V3 a) {
 }
 V3 hcross(V3 a, V3 b) { return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 
-constexpr size_t kRecBytes = 4 * 7 + 4 * 3 * 4;   // 4 floats + 3 u32 + 4 vertex refs
+constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 
 size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t P = (size_t)d.width * d.height;
@@ -159,24 +168,14 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t per_set = P * B * kRecBytes + P * 4 + P * words * 4;
     size_t gbuf = 2 * P * (4 + 4 + 4 + 16 + 16);
     return 4 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
-           P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ + 64 * 1024;
+           P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ +
+           P * B * ((size_t)std::max(d.spatial_k, 1) + 1) * (8 + 8 + 32) /*tasks, weights, shifted fields*/ +
+           64 * 1024;
 }
 
 tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
     Alloc& a = c->sensor_mem;
-    size_t n = P * B;
-    TOF_TRY(alloc_t(c, a, &r.W, n));
-    TOF_TRY(alloc_t(c, a, &r.phat, n));
-    TOF_TRY(alloc_t(c, a, &r.len, n));
-    TOF_TRY(alloc_t(c, a, &r.pre_pdf, n));
-    TOF_TRY(alloc_t(c, a, &r.opix, n));
-    TOF_TRY(alloc_t(c, a, &r.ofr, n));
-    TOF_TRY(alloc_t(c, a, &r.meta, n));
-    for (int q = 0; q < 4; ++q) {
-        TOF_TRY(alloc_t(c, a, &r.vobj[q], n));
-        TOF_TRY(alloc_t(c, a, &r.vxi0[q], n));
-        TOF_TRY(alloc_t(c, a, &r.vxi1[q], n));
-    }
+    TOF_TRY(alloc_t(c, a, &r.rec, P * B * 5));
     TOF_TRY(alloc_t(c, a, &r.M, P));
     TOF_TRY(alloc_t(c, a, &r.mask, P * words));
     return TOF_OK;
@@ -267,8 +266,7 @@ tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64
     c->device = device;
     c->budget = hbm_budget_bytes;
     c->seed = seed;
-    if (hipMalloc(&c->counters, 16 * sizeof(unsigned long long)) != hipSuccess ||
-        hipMemset(c->counters, 0, 16 * sizeof(unsigned long long)) != hipSuccess) {
+    if (hipMalloc(&c->counters, kCounterBytes) != hipSuccess || hipMemset(c->counters, 0, kCounterBytes) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
         return TOF_ERR_DEVICE;
@@ -458,9 +456,14 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->direct, P));
     TOF_TRY(alloc_t(c, a, &c->prev_pix, P));
     TOF_TRY(alloc_t(c, a, &c->nb, P * (size_t)std::max(d->spatial_k, 1)));
+    const size_t ncand = (size_t)std::max(d->spatial_k, 1) + 1;
     TOF_TRY(alloc_t(c, a, &c->items, P * B));
+    TOF_TRY(alloc_t(c, a, &c->tasks, P * B * ncand));
+    TOF_TRY(alloc_t(c, a, &c->cw, P * B * ncand));
+    TOF_TRY(alloc_t(c, a, &c->shv, 2 * P * B * ncand));
     TOF_TRY(alloc_t(c, a, &c->count, 64));
-    c->item_slots = 2 * 4096;
+    c->max_tasks = P * B * ncand;
+    c->item_slots = 4 * 4096;
     c->item_used = 0;
     TOF_TRY(alloc_t(c, a, &c->item_hist, c->item_slots));
     c->max_items = P * B;
@@ -522,18 +525,24 @@ tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
     ResSet& r = c->sets[c->fin_prev];
-    HIP_TRY(hipMemcpy(r.W, h->W, 4 * PB, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(r.phat, h->phat, 4 * PB, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(r.len, h->len, 4 * PB, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(r.pre_pdf, h->pre_pdf, 4 * PB, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(r.opix, h->origin_pixel, 4 * PB, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(r.ofr, h->origin_frame, 4 * PB, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(r.meta, h->meta, 4 * PB, hipMemcpyHostToDevice));
-    for (int q = 0; q < 4; ++q) {
-        HIP_TRY(hipMemcpy(r.vobj[q], h->vertex_obj + q * PB, 4 * PB, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(r.vxi0[q], h->vertex_xi + (2 * q) * PB, 4 * PB, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(r.vxi1[q], h->vertex_xi + (2 * q + 1) * PB, 4 * PB, hipMemcpyHostToDevice));
+    std::vector<float> packed(PB * kRecWords, 0.f);
+    auto u2f = [](uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; };
+    for (size_t i = 0; i < PB; ++i) {
+        float* q = packed.data() + i * kRecWords;
+        q[0] = h->W[i];
+        q[1] = h->phat[i];
+        q[2] = h->len[i];
+        q[3] = h->pre_pdf[i];
+        q[4] = u2f(h->origin_pixel[i]);
+        q[5] = u2f(h->origin_frame[i]);
+        q[6] = u2f(h->meta[i]);
+        for (int v = 0; v < 4; ++v) {
+            q[8 + 3 * v] = u2f((uint32_t)h->vertex_obj[v * PB + i]);
+            q[9 + 3 * v] = h->vertex_xi[(2 * v) * PB + i];
+            q[10 + 3 * v] = h->vertex_xi[(2 * v + 1) * PB + i];
+        }
     }
+    HIP_TRY(hipMemcpy(r.rec, packed.data(), sizeof(float) * packed.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(r.M, h->M, 4 * P, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(r.mask, h->mask, 4 * P * words, hipMemcpyHostToDevice));
     c->prev_valid = true;
@@ -550,8 +559,9 @@ tof_status tof_set_kernel_timing(tof_ctx* c, int enabled) {
         c->acc_ms[k] = 0.0;
         c->acc_n[k] = 0;
     }
-    c->acc_items[0] = c->acc_items[1] = 0;
+    for (int q = 0; q < 4; ++q) c->acc_items[q] = 0;
     c->item_used = 0;
+    HIP_TRY(hipMemcpy(c->work0, c->counters, kCounterBytes, hipMemcpyDeviceToHost));
     return TOF_OK;
 }
 
@@ -563,18 +573,26 @@ tof_status tof_get_kernel_times(tof_ctx* c, tof_kernel_times* out) {
     if (c->item_used) {
         std::vector<uint32_t> h(c->item_used);
         HIP_TRY(hipMemcpy(h.data(), c->item_hist, 4 * c->item_used, hipMemcpyDeviceToHost));
-        for (size_t i = 0; i < c->item_used; i += 2) {
-            c->acc_items[0] += h[i];
-            c->acc_items[1] += h[i + 1];
-        }
+        for (size_t i = 0; i + 3 < c->item_used; i += 4)
+            for (int q = 0; q < 4; ++q) c->acc_items[q] += h[i + q];
         c->item_used = 0;
     }
     for (int k = 0; k < TOF_K_COUNT; ++k) {
         out->ms[k] = c->acc_ms[k];
         out->launches[k] = c->acc_n[k];
     }
-    out->work_items[0] = c->acc_items[0];
-    out->work_items[1] = c->acc_items[1];
+    for (int q = 0; q < 4; ++q) out->work_items[q] = c->acc_items[q];
+    unsigned long long h[TOF_K_COUNT * kBank];
+    HIP_TRY(hipMemcpy(h, c->counters, kCounterBytes, hipMemcpyDeviceToHost));
+    for (int k = 0; k < TOF_K_COUNT; ++k) {
+        auto d = [&](int i) { return (uint64_t)(h[k * kBank + i] - c->work0[k * kBank + i]); };
+        out->work[k].rays = d(ST_RAYS);
+        out->work[k].node_visits = d(ST_NODES);
+        out->work[k].tri_tests = d(ST_TRIS);
+        out->work[k].shifts = d(ST_SHIFTS);
+        out->work[k].newton_attempts = d(ST_NEWTON_ATT);
+        out->work[k].newton_iters = d(ST_NEWTON_ITERS);
+    }
     return TOF_OK;
 }
 
@@ -588,8 +606,11 @@ tof_status tof_get_stats(tof_ctx* c, tof_stats* out) {
     if (!c || !out) return TOF_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
-    unsigned long long h[16];
-    HIP_TRY(hipMemcpy(h, c->counters, sizeof(h), hipMemcpyDeviceToHost));
+    unsigned long long hb[TOF_K_COUNT * kBank];
+    HIP_TRY(hipMemcpy(hb, c->counters, kCounterBytes, hipMemcpyDeviceToHost));
+    unsigned long long h[kBank] = {};
+    for (int k = 0; k < TOF_K_COUNT; ++k)
+        for (int i = 0; i < kBank; ++i) h[i] += hb[k * kBank + i];
     out->shifts = h[ST_SHIFTS];
     out->shifts_ok = h[ST_SHIFTS_OK];
     out->newton_attempts = h[ST_NEWTON_ATT];
@@ -599,6 +620,9 @@ tof_status tof_get_stats(tof_ctx* c, tof_stats* out) {
     out->rays = h[ST_RAYS];
     out->frames = c->frames;
     out->bvh_overflow = h[ST_OVERFLOW];
+    out->node_visits = h[ST_NODES];
+    out->tri_tests = h[ST_TRIS];
+    out->bad_records = h[ST_BADREC];
     return TOF_OK;
 }
 
@@ -673,11 +697,11 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     a.F.g[0] = slot_dev(c, 0);
     a.F.g[1] = prev.valid ? slot_dev(c, 1) : slot_dev(c, 0);
     a.frame = (uint32_t)fr->frame_index;
-    a.counters = c->counters;
     const size_t P = (size_t)c->s.P, B = (size_t)c->s.B;
 
     tofh::GBufOut gout{cur.gb_obj, cur.gb_xi0, cur.gb_xi1, cur.gb_p, cur.gb_n};
     HIP_TRY(timer_mark(c, TOF_K_GBUFFER, st));
+    a.counters = c->counters + (size_t)TOF_K_GBUFFER * kBank;
     tofh::launch_gbuffer(a, gout, st);
     HIP_TRY(timer_mark(c, TOF_K_GBUFFER, st));
     tofh::launch_fill_u32((uint32_t*)c->pt, 0u, P * B, st);
@@ -685,13 +709,14 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     ResSet& tmp = c->sets[1];
     const int fin_new = c->fin_prev == 2 ? 3 : 2;
     HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
+    a.counters = c->counters + (size_t)TOF_K_INITIAL * kBank;
     tofh::launch_initial(a, can, c->pt, c->direct, st);
     HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
-    const bool record_items = c->timing && c->item_used + 2 <= c->item_slots;
+    const bool record_items = c->timing && c->item_used + 4 <= c->item_slots;
     uint32_t* item_slot = record_items ? c->item_hist + c->item_used : nullptr;
     if (record_items) {
-        tofh::launch_fill_u32(item_slot, 0u, 2, st);
-        c->item_used += 2;
+        tofh::launch_fill_u32(item_slot, 0u, 4, st);
+        c->item_used += 4;
     }
     const ResSet* shown = nullptr;
     if (c->s.debug_stage == TOF_STAGE_CANONICAL) shown = &can;
@@ -700,17 +725,24 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     if (c->s.temporal && c->prev_valid && prev.valid) {
         const ResSet& pf = c->sets[c->fin_prev];
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_PREP, st));
+        a.counters = c->counters + (size_t)TOF_K_TEMPORAL_PREP * kBank;
         tofh::launch_reproject(a, can, pf, c->prev_pix, tmp.M, st);
-        tofh::launch_fill_u32(c->count, 0u, 1, st);
-        tofh::launch_items(a, 0, can, pf, c->prev_pix, 0, c->items, c->count, tmp.mask, st);
+        tofh::launch_fill_u32(c->count, 0u, 2, st);
+        tofh::launch_items(a, 0, can, pf, c->prev_pix, 2, c->items, c->tasks, c->count, tmp.mask, st);
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_PREP, st));
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL, st));
-        tofh::launch_temporal(a, can, pf, c->prev_pix, c->items, c->count, c->max_items, tmp, st);
+        a.counters = c->counters + (size_t)TOF_K_TEMPORAL * kBank;
+        tofh::launch_cand(a, 0, can, pf, c->prev_pix, c->items, c->tasks, c->count, c->max_tasks, c->cw, c->shv, st);
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL, st));
-        if (item_slot) HIP_TRY(hipMemcpyAsync(item_slot, c->count, 4, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MERGE, st));
+        a.counters = c->counters + (size_t)TOF_K_TEMPORAL_MERGE * kBank;
+        tofh::launch_merge(a, 0, can, pf, c->prev_pix, c->items, c->count, c->max_items, c->cw, c->shv, 0, tmp, st);
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MERGE, st));
+        if (item_slot) HIP_TRY(hipMemcpyAsync(item_slot, c->count, 8, hipMemcpyDeviceToDevice, st));
         cur_set = &tmp;
         temporal_done = true;
     }
+    a.counters = c->counters + (size_t)TOF_K_SPLAT * kBank;
     if (c->s.debug_stage == TOF_STAGE_TEMPORAL) {
         tofh::launch_splat(a, *cur_set, c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
     } else if (shown) {
@@ -724,17 +756,24 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         ResSet& in = c->sets[cur_idx];
         ResSet& out = c->sets[out_idx];
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
+        a.counters = c->counters + (size_t)TOF_K_SPATIAL_PREP * kBank;
         tofh::launch_neighbours(a, r, in, c->nb, out.M, st);
-        tofh::launch_fill_u32(c->count, 0u, 1, st);
-        tofh::launch_items(a, 1, in, in, c->nb, c->s.k, c->items, c->count, out.mask, st);
+        tofh::launch_fill_u32(c->count, 0u, 2, st);
+        tofh::launch_items(a, 1, in, in, c->nb, c->s.k + 1, c->items, c->tasks, c->count, out.mask, st);
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL, st));
-        tofh::launch_spatial(a, r, in, c->nb, c->items, c->count, c->max_items, out, st);
+        a.counters = c->counters + (size_t)TOF_K_SPATIAL * kBank;
+        tofh::launch_cand(a, 1, in, in, c->nb, c->items, c->tasks, c->count, c->max_tasks, c->cw, c->shv, st);
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL, st));
-        if (item_slot && r == 0) HIP_TRY(hipMemcpyAsync(item_slot + 1, c->count, 4, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MERGE, st));
+        a.counters = c->counters + (size_t)TOF_K_SPATIAL_MERGE * kBank;
+        tofh::launch_merge(a, 1, in, in, c->nb, c->items, c->count, c->max_items, c->cw, c->shv, r, out, st);
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MERGE, st));
+        if (item_slot && r == 0) HIP_TRY(hipMemcpyAsync(item_slot + 2, c->count, 8, hipMemcpyDeviceToDevice, st));
         cur_idx = out_idx;
     }
     if (cur_idx != fin_new) std::swap(c->sets[cur_idx], c->sets[fin_new]);
+    a.counters = c->counters + (size_t)TOF_K_SPLAT * kBank;
     if (c->s.debug_stage == TOF_STAGE_FINAL) {
         HIP_TRY(timer_mark(c, TOF_K_SPLAT, st));
         tofh::launch_splat(a, c->sets[fin_new], c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);

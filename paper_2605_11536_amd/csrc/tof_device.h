@@ -111,56 +111,52 @@ struct Rec {
     float len, pre_pdf, phat;
 };
 
-// SoA reservoir planes, element [plane * P + pixel]; M and masks per pixel.
+// Reservoirs: one 80-byte record (5 x float4) per (plane, pixel), index
+// [plane * P + pixel].  Reuse work lists visit a pixel's planes together, so
+// neighbouring lanes touch different planes; a contiguous record keeps each
+// lane's access inside one or two cache lines.  Words: 0 W, 1 phat, 2 len,
+// 3 pre_pdf, 4 origin pixel, 5 origin frame, 6 meta (tree | n << 8 | k << 12
+// | nsfx << 16), 7 unused, 8..19 four vertex refs (obj, xi0, xi1).
+// M (confidence) and the non-empty bitmask are per pixel.
+constexpr int kRecWords = 20;
+
 struct ResSet {
-    float* W;
-    float* phat;
-    float* len;
-    float* pre_pdf;
-    uint32_t* opix;
-    uint32_t* ofr;
-    uint32_t* meta;          // tree | n << 8 | k << 12 | nsfx << 16
-    int* vobj[4];
-    float* vxi0[4];
-    float* vxi1[4];
+    float4* rec;             // [P * B * 5]
     float* M;                // [P]
     uint32_t* mask;          // [mask_words * P]: bit set <=> reservoir non-empty
 };
 
+__device__ __forceinline__ float& rec_W(const ResSet& R, size_t idx) { return ((float*)R.rec)[idx * kRecWords]; }
+__device__ __forceinline__ float rec_phat(const ResSet& R, size_t idx) { return ((const float*)R.rec)[idx * kRecWords + 1]; }
+
 __device__ __forceinline__ void store_rec(const ResSet& R, size_t idx, const Rec& r, float W) {
-    R.W[idx] = W;
-    R.phat[idx] = r.phat;
-    R.len[idx] = r.len;
-    R.pre_pdf[idx] = r.pre_pdf;
-    R.opix[idx] = r.opix;
-    R.ofr[idx] = r.ofr;
-    R.meta[idx] = (uint32_t)r.tree | ((uint32_t)r.n << 8) | ((uint32_t)r.k << 12) | ((uint32_t)r.nsfx << 16);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        R.vobj[q][idx] = r.v[q].obj;
-        R.vxi0[q][idx] = r.v[q].xi0;
-        R.vxi1[q][idx] = r.v[q].xi1;
-    }
+    float4* q = R.rec + idx * 5;
+    uint32_t meta = (uint32_t)r.tree | ((uint32_t)r.n << 8) | ((uint32_t)r.k << 12) | ((uint32_t)r.nsfx << 16);
+    q[0] = make_float4(W, r.phat, r.len, r.pre_pdf);
+    q[1] = make_float4(__uint_as_float(r.opix), __uint_as_float(r.ofr), __uint_as_float(meta), 0.f);
+    q[2] = make_float4(__int_as_float(r.v[0].obj), r.v[0].xi0, r.v[0].xi1, __int_as_float(r.v[1].obj));
+    q[3] = make_float4(r.v[1].xi0, r.v[1].xi1, __int_as_float(r.v[2].obj), r.v[2].xi0);
+    q[4] = make_float4(r.v[2].xi1, __int_as_float(r.v[3].obj), r.v[3].xi0, r.v[3].xi1);
 }
 __device__ __forceinline__ Rec load_rec(const ResSet& R, size_t idx, float& W) {
+    const float4* q = R.rec + idx * 5;
+    float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
     Rec r;
-    W = R.W[idx];
-    r.phat = R.phat[idx];
-    r.len = R.len[idx];
-    r.pre_pdf = R.pre_pdf[idx];
-    r.opix = R.opix[idx];
-    r.ofr = R.ofr[idx];
-    uint32_t m = R.meta[idx];
+    W = a.x;
+    r.phat = a.y;
+    r.len = a.z;
+    r.pre_pdf = a.w;
+    r.opix = __float_as_uint(b.x);
+    r.ofr = __float_as_uint(b.y);
+    uint32_t m = __float_as_uint(b.z);
     r.tree = (int)(m & 255u);
     r.n = (int)((m >> 8) & 15u);
     r.k = (int)((m >> 12) & 15u);
     r.nsfx = (int)((m >> 16) & 15u);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        r.v[q].obj = R.vobj[q][idx];
-        r.v[q].xi0 = R.vxi0[q][idx];
-        r.v[q].xi1 = R.vxi1[q][idx];
-    }
+    r.v[0] = VRef{__float_as_int(c.x), c.y, c.z};
+    r.v[1] = VRef{__float_as_int(c.w), d.x, d.y};
+    r.v[2] = VRef{__float_as_int(d.z), d.w, e.x};
+    r.v[3] = VRef{__float_as_int(e.y), e.z, e.w};
     return r;
 }
 
@@ -420,11 +416,13 @@ struct Hit {
     float t, b1, b2;
 };
 
+// per-lane event counters; one lane's share of a launch fits 32 bits
+constexpr int kNumCounters = 12;
 struct Counters {
-    uint64_t c[9];
+    uint32_t c[kNumCounters];
 };
 enum { ST_SHIFTS = 0, ST_SHIFTS_OK, ST_NEWTON_ATT, ST_NEWTON_CONV, ST_NEWTON_ITERS, ST_NEWTON_OK, ST_RAYS, ST_FRAMES,
-       ST_OVERFLOW };
+       ST_OVERFLOW, ST_NODES, ST_TRIS, ST_BADREC };
 
 // Closest hit (any_hit = false; ties in t go to the smaller primitive id) or
 // any hit in (0, tmax) (any_hit = true).  `stack` points at this lane's LDS
@@ -437,6 +435,7 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
     h.obj = -1;
     const int T = G.n_tri;
     auto test_leaf = [&](int k) -> bool {
+        st.c[ST_TRIS]++;
         float4 a = G.leaves[3 * k], b = G.leaves[3 * k + 1], c = G.leaves[3 * k + 2];
         float t, b1, b2;
         float lim = any_hit ? tmax : __fmul_rn(tb, 1.0000001f) + 1e-30f;
@@ -464,6 +463,7 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
         int budget = 2 * T + 64;
         while (--budget > 0) {
             const Node& nd = G.nodes[node];
+            st.c[ST_NODES]++;
             float t0, t1;
             bool h0 = slab(nd.lo0, nd.hi0, r, tb, t0);
             bool h1 = slab(nd.lo1, nd.hi1, r, tb, t1);
@@ -584,14 +584,10 @@ struct Tracer {
         out = hit_vertex(S, G, h, o, dir);
         return true;
     }
-    // true if every segment is unoccluded (stops at the first blocked one)
-    __device__ bool all_visible(const SlotDev& G, const Seg* segs, int n) {
-        for (int i = 0; i < n; ++i) {
-            Hit h;
-            st.c[ST_RAYS]++;
-            if (traverse(S, G, segs[i].o, segs[i].d, segs[i].t, true, h, stack, stride, st)) return false;
-        }
-        return true;
+    __device__ bool visible(const SlotDev& G, const Seg& sg) {
+        Hit h;
+        st.c[ST_RAYS]++;
+        return !traverse(S, G, sg.o, sg.d, sg.t, true, h, stack, stride, st);
     }
 };
 
@@ -741,203 +737,185 @@ __device__ __forceinline__ bool recon_ok(const SceneDev& S, const Vtx& a, const 
     return is_rough(S, a.obj) && is_rough(S, b.obj) && len(b.p - a.p) >= S.dmin;
 }
 
-// path contribution in the product solid-angle measure (no visibility)
-__device__ inline float path_eval(const Sens& s, const SceneDev& S, const SlotDev& G, int pix, const Vtx* ys, int n,
-                                  float& plen) {
-    V3 wi = toward_camera(s, G, ys[0]);
-    float f = 1.0f;
-    plen = camera_leg(s, G, ys[0]);
-    for (int j = 0; j + 1 < n; ++j) {
-        V3 dv = ys[j + 1].p - ys[j].p;
-        float dl = len(dv);
-        V3 wo = (1.0f / dl) * dv;
-        f *= bsdf_eval(S, ys[j].obj, ys[j].n, wi, wo) * fabsf(dot(ys[j].n, wo));
-        plen += dl;
-        wi = -wo;
-    }
-    const Vtx& y = ys[n - 1];
-    V3 L = light_pos(s, G, pix);
-    V3 dv = L - y.p;
-    float dl = len(dv);
-    V3 wo = (1.0f / dl) * dv;
-    f *= bsdf_eval(S, y.obj, y.n, wi, wo) * fabsf(dot(y.n, wo)) * light_emit(s, S, G, pix, y.p) / (dl * dl);
-    plen += dl;
-    return f;
-}
-
 // ---------------------------------------------------------------------------
 // Newton solve of the path-length constraint (Sec. 4.3), average-gradient
 // gauge.  Length functions use the source endpoints at xi and the
 // destination endpoints at xi'; dF2/dxi' is the derivative of F2 itself.
-//
-// The solve runs in FP64: near stationary points of the length function the
-// system is ill-conditioned and FP32 evaluation of F moves xi' and the
-// determinant by up to ~1e-3 relative.  gfx950 issues FP64 vector math at
-// half the FP32 rate and the solve is a few hundred flops per shift, small
-// next to the traversal of the same shift.
+// The length function and its derivatives are evaluated in NReal (FP32 by
+// default); the 2x2 Newton step and both determinants are solved in FP64.
 // ---------------------------------------------------------------------------
-struct D3 {
-    double x, y, z;
+#ifndef TOF_NEWTON_FP64
+#define TOF_NEWTON_FP64 0
+#endif
+#if TOF_NEWTON_FP64
+typedef double NReal;
+#else
+typedef float NReal;
+#endif
+
+template <typename T>
+struct T3 {
+    T x, y, z;
 };
-__device__ __forceinline__ D3 dk(double a, double b, double c) { return D3{a, b, c}; }
-__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return D3{a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return D3{a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ __forceinline__ D3 operator*(double s, D3 a) { return D3{s * a.x, s * a.y, s * a.z}; }
-__device__ __forceinline__ double ddot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ __forceinline__ D3 dcross(D3 a, D3 b) {
-    return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+template <typename T>
+__device__ __forceinline__ T3<T> operator+(T3<T> a, T3<T> b) { return T3<T>{a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <typename T>
+__device__ __forceinline__ T3<T> operator-(T3<T> a, T3<T> b) { return T3<T>{a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T>
+__device__ __forceinline__ T3<T> operator*(T s, T3<T> a) { return T3<T>{s * a.x, s * a.y, s * a.z}; }
+template <typename T>
+__device__ __forceinline__ T tdot(T3<T> a, T3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T>
+__device__ __forceinline__ T3<T> tcross(T3<T> a, T3<T> b) {
+    return T3<T>{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-__device__ __forceinline__ double dlen(D3 a) { return sqrt(ddot(a, a)); }
-__device__ __forceinline__ D3 up3(V3 a) { return D3{a.x, a.y, a.z}; }
-__device__ __forceinline__ D3 ldd3(const float4* a, int i) {
+template <typename T>
+__device__ __forceinline__ T tlen(T3<T> a) { return sqrt(tdot(a, a)); }
+template <typename T>
+__device__ __forceinline__ T3<T> tof3(V3 a) { return T3<T>{(T)a.x, (T)a.y, (T)a.z}; }
+template <typename T>
+__device__ __forceinline__ T3<T> tld(const float4* a, int i) {
     float4 v = a[i];
-    return D3{v.x, v.y, v.z};
+    return T3<T>{(T)v.x, (T)v.y, (T)v.z};
 }
-__device__ __forceinline__ D3 dxf_point(const float* m, D3 q) {
-    return dk((double)m[0] * q.x + (double)m[1] * q.y + (double)m[2] * q.z + (double)m[3],
-              (double)m[4] * q.x + (double)m[5] * q.y + (double)m[6] * q.z + (double)m[7],
-              (double)m[8] * q.x + (double)m[9] * q.y + (double)m[10] * q.z + (double)m[11]);
-}
-__device__ __forceinline__ D3 dxf_dir(const float* m, D3 q) {
-    return dk((double)m[0] * q.x + (double)m[1] * q.y + (double)m[2] * q.z,
-              (double)m[4] * q.x + (double)m[5] * q.y + (double)m[6] * q.z,
-              (double)m[8] * q.x + (double)m[9] * q.y + (double)m[10] * q.z);
+template <typename T>
+__device__ __forceinline__ T3<T> txf(const float* m, T3<T> q, T w) {
+    return T3<T>{(T)m[0] * q.x + (T)m[1] * q.y + (T)m[2] * q.z + w * (T)m[3],
+                 (T)m[4] * q.x + (T)m[5] * q.y + (T)m[6] * q.z + w * (T)m[7],
+                 (T)m[8] * q.x + (T)m[9] * q.y + (T)m[10] * q.z + w * (T)m[11]};
 }
 
-struct ChartD {
+template <typename T>
+struct ChartT {
     bool ok;
-    D3 p, ju, jv, puu, puv, pvv;
+    T3<T> p, ju, jv, puu, puv, pvv;
 };
 
-// FP64 twin of chart_eval (positions from the frame's FP32 world vertices)
-__device__ inline ChartD chart_eval_d(const SceneDev& S, const SlotDev& G, int obj, double u, double v) {
-    ChartD c;
+template <typename T>
+__device__ inline ChartT<T> chart_eval_t(const SceneDev& S, const SlotDev& G, int obj, T u, T v) {
+    ChartT<T> c;
     const Obj ob = S.objs[obj];
-    D3 z = dk(0.0, 0.0, 0.0);
+    T3<T> z = T3<T>{0, 0, 0};
     c.puu = z;
     c.puv = z;
     c.pvv = z;
     if (ob.type == 0) {
-        double uu = u, vv = v;
-        if (ob.wrap_u) uu = u - (double)ob.nu * floor(u / (double)ob.nu);
-        if (ob.wrap_v) vv = v - (double)ob.nv * floor(v / (double)ob.nv);
-        double fi = floor(uu), fj = floor(vv);
-        int i = (int)fmin(fmax(fi, 0.0), (double)(ob.nu - 1));
-        int j = (int)fmin(fmax(fj, 0.0), (double)(ob.nv - 1));
-        double a = uu - (double)i, b = vv - (double)j;
+        T uu = u, vv = v;
+        if (ob.wrap_u) uu = u - (T)ob.nu * floor(u / (T)ob.nu);
+        if (ob.wrap_v) vv = v - (T)ob.nv * floor(v / (T)ob.nv);
+        T fi = floor(uu), fj = floor(vv);
+        int i = (int)fmin(fmax(fi, (T)0), (T)(ob.nu - 1));
+        int j = (int)fmin(fmax(fj, (T)0), (T)(ob.nv - 1));
+        T a = uu - (T)i, b = vv - (T)j;
         int row = ob.nu + 1;
         int base = ob.voff + j * row + i;
-        D3 v00 = ldd3(G.wv, base), v10 = ldd3(G.wv, base + 1);
-        D3 v01 = ldd3(G.wv, base + row), v11 = ldd3(G.wv, base + row + 1);
-        if (a + b <= 1.0) {
+        T3<T> v00 = tld<T>(G.wv, base), v10 = tld<T>(G.wv, base + 1);
+        T3<T> v01 = tld<T>(G.wv, base + row), v11 = tld<T>(G.wv, base + row + 1);
+        if (a + b <= (T)1) {
             c.p = v00 + a * (v10 - v00) + b * (v01 - v00);
             c.ju = v10 - v00;
             c.jv = v01 - v00;
         } else {
-            c.p = v11 + (1.0 - a) * (v01 - v11) + (1.0 - b) * (v10 - v11);
+            c.p = v11 + ((T)1 - a) * (v01 - v11) + ((T)1 - b) * (v10 - v11);
             c.ju = v11 - v01;
             c.jv = v11 - v10;
         }
-        c.ok = dlen(dcross(c.ju, c.jv)) > 0.0;
+        c.ok = tlen(tcross(c.ju, c.jv)) > (T)0;
     } else {
         const float* m = G.xf + 12 * obj;
-        double th = u, ph = v, r = ob.r;
-        double st = sin(th), ct = cos(th), sp = sin(ph), cp = cos(ph);
-        D3 radial = dk(st * cp, st * sp, ct);
-        c.p = dxf_point(m, dk(ob.cx, ob.cy, ob.cz) + r * radial);
-        c.ju = dxf_dir(m, dk(r * ct * cp, r * ct * sp, -r * st));
-        c.jv = dxf_dir(m, dk(-r * st * sp, r * st * cp, 0.0));
-        c.puu = dxf_dir(m, (-r) * radial);
-        c.puv = dxf_dir(m, dk(-r * ct * sp, r * ct * cp, 0.0));
-        c.pvv = dxf_dir(m, dk(-r * st * cp, -r * st * sp, 0.0));
+        T th = u, ph = v, r = (T)ob.r;
+        T st = sin(th), ct = cos(th), sp = sin(ph), cp = cos(ph);
+        T3<T> radial = T3<T>{st * cp, st * sp, ct};
+        c.p = txf(m, T3<T>{(T)ob.cx, (T)ob.cy, (T)ob.cz} + r * radial, (T)1);
+        c.ju = txf(m, T3<T>{r * ct * cp, r * ct * sp, -r * st}, (T)0);
+        c.jv = txf(m, T3<T>{-r * st * sp, r * st * cp, (T)0}, (T)0);
+        c.puu = txf(m, (-r) * radial, (T)0);
+        c.puv = txf(m, T3<T>{-r * ct * sp, r * ct * cp, (T)0}, (T)0);
+        c.pvv = txf(m, T3<T>{-r * st * cp, -r * st * sp, (T)0}, (T)0);
         c.ok = true;
     }
     return c;
 }
 
-struct LenEval {
+template <typename T>
+struct LenEvalT {
     bool ok;
-    double L, g0, g1, h00, h01, h11, area;
+    T L, g0, g1, h00, h01, h11;
 };
 
-__device__ inline LenEval len_eval(const SceneDev& S, const SlotDev& G, int obj, double u, double v, D3 a, D3 b,
-                                   double c) {
-    LenEval e;
+// l(xi) = c + |a - p(xi)| + |b - p(xi)|, its chart gradient J^T(-s) and
+// Hessian J^T A J + Q with A = sum (I - d d^T)/|p_i - p|, Q_ij = (-s).p_ij
+template <typename T>
+__device__ __forceinline__ LenEvalT<T> len_eval_t(const SceneDev& S, const SlotDev& G, int obj, T u, T v, T3<T> a, T3<T> b,
+                                         T c) {
+    LenEvalT<T> e;
     e.ok = false;
-    ChartD ch = chart_eval_d(S, G, obj, u, v);
+    ChartT<T> ch = chart_eval_t<T>(S, G, obj, u, v);
     if (!ch.ok) return e;
-    D3 r1 = a - ch.p, r2 = b - ch.p;
-    double l1 = dlen(r1), l2 = dlen(r2);
-    if (!(l1 > 0.0 && l2 > 0.0)) return e;
-    D3 d1 = (1.0 / l1) * r1, d2 = (1.0 / l2) * r2;
-    D3 sv = d1 + d2;
+    T3<T> r1 = a - ch.p, r2 = b - ch.p;
+    T l1 = tlen(r1), l2 = tlen(r2);
+    if (!(l1 > (T)0 && l2 > (T)0)) return e;
+    T i1 = (T)1 / l1, i2 = (T)1 / l2;
+    T3<T> d1 = i1 * r1, d2 = i2 * r2;
+    T3<T> sv = d1 + d2;
     e.L = c + l1 + l2;
-    e.g0 = -ddot(sv, ch.ju);
-    e.g1 = -ddot(sv, ch.jv);
-    double i1 = 1.0 / l1, i2 = 1.0 / l2;
-    auto A = [&](D3 x) { return i1 * (x - ddot(d1, x) * d1) + i2 * (x - ddot(d2, x) * d2); };
-    D3 Aju = A(ch.ju), Ajv = A(ch.jv);
-    e.h00 = ddot(ch.ju, Aju) - ddot(sv, ch.puu);
-    e.h01 = ddot(ch.ju, Ajv) - ddot(sv, ch.puv);
-    e.h11 = ddot(ch.jv, Ajv) - ddot(sv, ch.pvv);
-    e.area = dlen(dcross(ch.ju, ch.jv));
+    e.g0 = -tdot(sv, ch.ju);
+    e.g1 = -tdot(sv, ch.jv);
+    T3<T> Aju = i1 * (ch.ju - tdot(d1, ch.ju) * d1) + i2 * (ch.ju - tdot(d2, ch.ju) * d2);
+    T3<T> Ajv = i1 * (ch.jv - tdot(d1, ch.jv) * d1) + i2 * (ch.jv - tdot(d2, ch.jv) * d2);
+    e.h00 = tdot(ch.ju, Aju) - tdot(sv, ch.puu);
+    e.h01 = tdot(ch.ju, Ajv) - tdot(sv, ch.puv);
+    e.h11 = tdot(ch.jv, Ajv) - tdot(sv, ch.pvv);
     e.ok = true;
     return e;
 }
 
 struct NewtonOut {
     bool conv;
-    double xi0, xi1;
+    float xi0, xi1;
     int iters;
     double det_area;
 };
 
-__device__ inline NewtonOut newton_solve(const SceneDev& S, const SlotDev& GS, const SlotDev& GD, int obj,
-                                         double xs0, double xs1, D3 as, D3 bs, double cs, D3 ad, D3 bd, double cd,
-                                         double dl0, double tol, int maxit) {
+template <typename T>
+__device__ inline NewtonOut newton_solve(const SceneDev& S, const SlotDev& GS, const SlotDev& GD, int obj, T xs0,
+                                         T xs1, T3<T> as, T3<T> bs, T cs, T3<T> ad, T3<T> bd, T cd, T dl0, T tol,
+                                         int maxit) {
     NewtonOut out;
     out.conv = false;
     out.iters = 0;
-    LenEval Sv = len_eval(S, GS, obj, xs0, xs1, as, bs, cs);
+    const LenEvalT<T> Sv = len_eval_t<T>(S, GS, obj, xs0, xs1, as, bs, cs);
     if (!Sv.ok) return out;
-    double xp0 = xs0, xp1 = xs1;
-    LenEval D = len_eval(S, GD, obj, xp0, xp1, ad, bd, cd);
+    T xp0 = xs0, xp1 = xs1;
+    LenEvalT<T> D = len_eval_t<T>(S, GD, obj, xp0, xp1, ad, bd, cd);
     if (!D.ok) return out;
-    auto Fv = [&](const LenEval& E, double x0, double x1, double& F0, double& F1) {
-        double m0 = 0.5 * (Sv.g0 + E.g0), m1 = 0.5 * (Sv.g1 + E.g1);
-        double d0 = x0 - xs0, d1 = x1 - xs1;
-        F0 = E.L - Sv.L - dl0;
-        F1 = -m1 * d0 + m0 * d1;
-    };
-    auto jac_dst = [&](const LenEval& E, double x0, double x1, double J[4]) {
-        double m0 = 0.5 * (Sv.g0 + E.g0), m1 = 0.5 * (Sv.g1 + E.g1);
-        double rd0 = -(x1 - xs1), rd1 = x0 - xs0;
-        J[0] = E.g0;
-        J[1] = E.g1;
-        J[2] = -m1 - 0.5 * (E.h00 * rd0 + E.h01 * rd1);
-        J[3] = m0 - 0.5 * (E.h01 * rd0 + E.h11 * rd1);
-    };
-    double F0, F1;
-    Fv(D, xp0, xp1, F0, F1);
+    // F = [L_dst(xi') - L_src(xi) - dl ; (R m)^T (xi' - xi)], R = 90 degree rotation
+    T F0 = D.L - Sv.L - dl0;
+    T F1 = (T)0;
     int it = 0;
     while (true) {
         if (fabs(F0) <= tol && fabs(F1) <= tol) break;
         if (it >= maxit) return out;
-        double J[4];
-        jac_dst(D, xp0, xp1, J);
-        double det = J[0] * J[3] - J[1] * J[2];
+        const T m0 = (T)0.5 * (Sv.g0 + D.g0), m1 = (T)0.5 * (Sv.g1 + D.g1);
+        const T rd0 = -(xp1 - xs1), rd1 = xp0 - xs0;
+        // dF/dxi' = [grad L_dst ; (R m - 0.5 H_dst R d)^T], solved in FP64
+        const double J00 = D.g0, J01 = D.g1;
+        const double J10 = (double)(-m1 - (T)0.5 * (D.h00 * rd0 + D.h01 * rd1));
+        const double J11 = (double)(m0 - (T)0.5 * (D.h01 * rd0 + D.h11 * rd1));
+        const double det = J00 * J11 - J01 * J10;
         if (fabs(det) < 1e-12) return out;
-        double s0 = -(J[3] * F0 - J[1] * F1) / det;
-        double s1 = -(-J[2] * F0 + J[0] * F1) / det;
-        double norm0 = sqrt(F0 * F0 + F1 * F1);
+        const double s0 = -(J11 * (double)F0 - J01 * (double)F1) / det;
+        const double s1 = -(-J10 * (double)F0 + J00 * (double)F1) / det;
+        const T norm0 = sqrt(F0 * F0 + F1 * F1);
         bool accepted = false;
-        double alpha = 1.0;
-        for (int ls = 0; ls < 4; ++ls, alpha *= 0.5) {   // backtracking line search
-            double x0 = xp0 + alpha * s0, x1 = xp1 + alpha * s1;
-            LenEval Dt = len_eval(S, GD, obj, x0, x1, ad, bd, cd);
+        T alpha = (T)1;
+        for (int ls = 0; ls < 4; ++ls, alpha *= (T)0.5) {   // backtracking line search
+            const T x0 = xp0 + alpha * (T)s0, x1 = xp1 + alpha * (T)s1;
+            const LenEvalT<T> Dt = len_eval_t<T>(S, GD, obj, x0, x1, ad, bd, cd);
             if (!Dt.ok) continue;
-            double G0, G1;
-            Fv(Dt, x0, x1, G0, G1);
+            const T n0 = (T)0.5 * (Sv.g0 + Dt.g0), n1 = (T)0.5 * (Sv.g1 + Dt.g1);
+            const T G0 = Dt.L - Sv.L - dl0;
+            const T G1 = -n1 * (x0 - xs0) + n0 * (x1 - xs1);
             if (sqrt(G0 * G0 + G1 * G1) < norm0) {
                 xp0 = x0;
                 xp1 = x1;
@@ -952,207 +930,255 @@ __device__ inline NewtonOut newton_solve(const SceneDev& S, const SlotDev& GS, c
         ++it;
     }
     // implicit-function Jacobian |det dxi'/dxi| = |det dF/dxi| / |det dF/dxi'|
-    double Jd[4];
-    jac_dst(D, xp0, xp1, Jd);
-    double m0 = 0.5 * (Sv.g0 + D.g0), m1 = 0.5 * (Sv.g1 + D.g1);
-    double rd0 = -(xp1 - xs1), rd1 = xp0 - xs0;
-    double Js00 = -Sv.g0, Js01 = -Sv.g1;
-    double Js10 = -(-m1 + 0.5 * (Sv.h00 * rd0 + Sv.h01 * rd1));
-    double Js11 = -(m0 + 0.5 * (Sv.h01 * rd0 + Sv.h11 * rd1));
-    double detd = Jd[0] * Jd[3] - Jd[1] * Jd[2];
-    double dets = Js00 * Js11 - Js01 * Js10;
+    const T m0 = (T)0.5 * (Sv.g0 + D.g0), m1 = (T)0.5 * (Sv.g1 + D.g1);
+    const T rd0 = -(xp1 - xs1), rd1 = xp0 - xs0;
+    const double Jd00 = D.g0, Jd01 = D.g1;
+    const double Jd10 = (double)(-m1 - (T)0.5 * (D.h00 * rd0 + D.h01 * rd1));
+    const double Jd11 = (double)(m0 - (T)0.5 * (D.h01 * rd0 + D.h11 * rd1));
+    const double Js00 = -(double)Sv.g0, Js01 = -(double)Sv.g1;
+    const double Js10 = -(double)(-m1 + (T)0.5 * (Sv.h00 * rd0 + Sv.h01 * rd1));
+    const double Js11 = -(double)(m0 + (T)0.5 * (Sv.h01 * rd0 + Sv.h11 * rd1));
+    const double detd = Jd00 * Jd11 - Jd01 * Jd10;
+    const double dets = Js00 * Js11 - Js01 * Js10;
     if (fabs(detd) < 1e-12) return out;
-    out.conv = true;
-    out.xi0 = xp0;
-    out.xi1 = xp1;
-    out.iters = it;
     // chart -> surface: sqrt(det J'^T J') / sqrt(det J^T J)
-    out.det_area = D.area / Sv.area * (fabs(dets) / fabs(detd));
+    const ChartT<T> cd_ = chart_eval_t<T>(S, GD, obj, xp0, xp1);
+    const ChartT<T> cs_ = chart_eval_t<T>(S, GS, obj, xs0, xs1);
+    const double area = (double)tlen(tcross(cd_.ju, cd_.jv)) / (double)tlen(tcross(cs_.ju, cs_.jv));
+    out.conv = true;
+    out.xi0 = (float)xp0;
+    out.xi1 = (float)xp1;
+    out.iters = it;
+    out.det_area = area * (fabs(dets) / fabs(detd));
     return out;
 }
 
 // ---------------------------------------------------------------------------
 // shift T_{src -> dst} (Sec. 4.1): random replay up to x_{k-1}, reconnection
-// at p, Newton perturbation of p, visibility, full Jacobian in the product
-// solid-angle measure, target in the destination plane.
+// at p, Newton perturbation of p, full Jacobian in the product solid-angle
+// measure, target in the destination plane, then visibility of the moved
+// edges (the suffix too when the domains belong to different frames).
+// Returns only what changes in the record.
 // ---------------------------------------------------------------------------
 struct ShiftOut {
     bool ok;
-    Rec y;
-    float J, phat;
+    float J, phat, len, pre_pdf;
+    VRef v0, v1;
 };
 
-__device__ inline ShiftOut shift_path(const Sens& s, const SceneDev& S, const Frames& F, Tracer& tr, const Rec& x,
+__device__ __forceinline__ void apply_shift(Rec& y, const ShiftOut& r) {
+    y.v[0] = r.v0;
+    y.v[1] = r.v1;
+    y.len = r.len;
+    y.pre_pdf = r.pre_pdf;
+    y.phat = r.phat;
+}
+
+// a stored record may only be shifted if every object it names exists and its
+// vertex counts are in range (the shift dereferences them)
+__device__ __forceinline__ bool rec_valid(const SceneDev& S, const Rec& x) {
+    const unsigned no = (unsigned)S.n_obj;
+    if (x.n < 1 || x.n > kMaxVerts) return false;
+    if (x.k == 0) return true;
+    if (x.k < 2 || x.k > x.n) return false;
+    if ((unsigned)x.v[0].obj >= no || (unsigned)x.v[1].obj >= no) return false;
+    if (x.v[2].obj != -1 && (unsigned)x.v[2].obj >= no) return false;
+    if (x.nsfx != 0 && (x.nsfx != 1 || (unsigned)x.v[3].obj >= no)) return false;
+    return true;
+}
+
+__device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S, const Frames& F, Tracer& tr, const Rec& x,
                                       int src_slot, int src_pix, int dst_slot, int dst_pix, int plane, float dl0) {
     ShiftOut R;
     R.ok = false;
     Counters& st = tr.st;
     st.c[ST_SHIFTS]++;
+    if (!rec_valid(S, x)) {
+        st.c[ST_BADREC]++;
+        return R;
+    }
     const SlotDev& GS = F.g[src_slot];
     const SlotDev& GD = F.g[dst_slot];
     if (GD.gb_obj[dst_pix] < 0) return R;
-    Vtx ys[kMaxVerts + 1];
-    int ny = 1;
-    ys[0] = gbuf_vertex(GD, dst_pix);
-    float pdf_y = 1.0f;
-    V3 wi = toward_camera(s, GD, ys[0]);
+    // replay in primary sample space, evaluating the prefix as we go
+    Vtx cur = gbuf_vertex(GD, dst_pix);
+    V3 wi_s = toward_camera(s, GD, cur);   // incoming direction for sampling
+    V3 wi_e = wi_s;                        // incoming direction for evaluation (from positions)
+    float plen = camera_leg(s, GD, cur);
+    NReal cpre = (NReal)plen;   // prefix length in the Newton precision
+    float beta = 1.0f, pdf_y = 1.0f;
     const int nrep = (x.k == 0) ? x.n - 1 : x.k - 2;
     for (int i = 1; i <= nrep; ++i) {
-        const Vtx cur = ys[ny - 1];
         Draw u = philox(s.seed, x.opix, x.ofr, PASS_BSDF, (uint64_t)x.tree, (uint64_t)i);
         V3 wo;
         float pdf;
-        if (!bsdf_sample(S, cur.obj, cur.n, wi, u.u(0), u.u(1), wo, pdf)) return R;
+        if (!bsdf_sample(S, cur.obj, cur.n, wi_s, u.u(0), u.u(1), wo, pdf)) return R;
         Vtx nx;
         if (!tr.trace(GD, cur, wo, nx)) return R;
+        // the offset path must not reconnect earlier than the base path
+        if (recon_ok(S, cur, nx)) return R;
+        V3 dv = nx.p - cur.p;
+        float dl = len(dv);
+        V3 we = (1.0f / dl) * dv;
+        beta *= bsdf_eval(S, cur.obj, cur.n, wi_e, we) * fabsf(dot(cur.n, we));
+        plen += dl;
+        cpre += tlen(tof3<NReal>(nx.p) - tof3<NReal>(cur.p));
         pdf_y *= pdf;
-        ys[ny++] = nx;
-        wi = -wo;
+        wi_s = -wo;
+        wi_e = -we;
+        cur = nx;
     }
-    for (int kk = 2; kk <= ny; ++kk)
-        if (recon_ok(S, ys[kk - 2], ys[kk - 1])) return R;
-
-    if (x.k == 0) {   // pure random replay
-        float plen;
-        float C = path_eval(s, S, GD, dst_pix, ys, ny, plen);
-        if (!(C > 0.f)) return R;
-        Seg sg = seg_light(s, S, GD, dst_pix, ys[ny - 1]);
-        if (!tr.all_visible(GD, &sg, 1)) return R;
-        float J = x.pre_pdf / pdf_y;
-        if (!(J >= 1.0f / s.j_max && J <= s.j_max)) return R;
-        float ph = in_plane(s, plane, plen) ? C : 0.f;
-        if (!(ph > 0.f)) return R;
-        R.y = x;
-        R.y.len = plen;
-        R.y.pre_pdf = pdf_y;
-        R.y.phat = ph;
-        R.J = J;
-        R.phat = ph;
-        R.ok = true;
-        st.c[ST_SHIFTS_OK]++;
-        return R;
-    }
-
-    const Vtx ykm1 = ys[ny - 1];
-    if (!is_rough(S, ykm1.obj)) return R;
-    const int obj = x.v[1].obj;
-    const Vtx xkm1_s = vertex_at(S, GS, x.v[0].obj, x.v[0].xi0, x.v[0].xi1);
-    const Vtx p_s = vertex_at(S, GS, obj, x.v[1].xi0, x.v[1].xi1);
+    const bool replay_only = x.k == 0;
     const bool p2light = x.v[2].obj < 0;
-    Vtx p2_s, p2_d;
-    V3 p2s_pos, p2d_pos;
-    if (p2light) {
-        p2s_pos = light_pos(s, GS, src_pix);
-        p2d_pos = light_pos(s, GD, dst_pix);
-    } else {
-        p2_s = vertex_at(S, GS, x.v[2].obj, x.v[2].xi0, x.v[2].xi1);
-        p2_d = vertex_at(S, GD, x.v[2].obj, x.v[2].xi0, x.v[2].xi1);
-        p2s_pos = p2_s.p;
-        p2d_pos = p2_d.p;
-    }
-    Vtx sfx_d;
-    if (x.nsfx > 0) sfx_d = vertex_at(S, GD, x.v[3].obj, x.v[3].xi0, x.v[3].xi1);
-    // fixed parts of the two length functions (prefix before x_{k-1}, suffix
-    // after p2), formed in FP64 so that L_src(xi) reproduces the stored length
-    double c_dst = (double)camera_leg(s, GD, ys[0]);
-    for (int j = 0; j + 1 < ny; ++j) c_dst += dlen(up3(ys[j + 1].p) - up3(ys[j].p));
-    if (!p2light) {
-        D3 prev = up3(p2d_pos);
-        if (x.nsfx > 0) {
-            c_dst += dlen(up3(sfx_d.p) - prev);
-            prev = up3(sfx_d.p);
-        }
-        c_dst += dlen(up3(light_pos(s, GD, dst_pix)) - prev);
-    }
-    float xi0 = x.v[1].xi0, xi1 = x.v[1].xi1;
-    double det_area;
-    if (s.shift_mode == 1) {
-        st.c[ST_NEWTON_ATT]++;
-        double tol = (double)s.tol_rel * (double)plane_width(s, plane);
-        // endpoints in FP64 from the FP32 chart points of the two frames
-        D3 xkm1_d = chart_eval_d(S, GS, x.v[0].obj, x.v[0].xi0, x.v[0].xi1).p;
-        D3 ykm1_d = chart_eval_d(S, GD, ykm1.obj, ykm1.xi0, ykm1.xi1).p;
-        D3 p2s_d = p2light ? up3(p2s_pos) : chart_eval_d(S, GS, x.v[2].obj, x.v[2].xi0, x.v[2].xi1).p;
-        D3 p2d_d = p2light ? up3(p2d_pos) : chart_eval_d(S, GD, x.v[2].obj, x.v[2].xi0, x.v[2].xi1).p;
-        D3 p_d = chart_eval_d(S, GS, obj, xi0, xi1).p;
-        double c_src = (double)x.len - dlen(xkm1_d - p_d) - dlen(p2s_d - p_d);
-        NewtonOut no = newton_solve(S, GS, GD, obj, xi0, xi1, xkm1_d, p2s_d, c_src, ykm1_d, p2d_d, c_dst,
-                                    (double)dl0, tol, s.max_it);
-        if (!no.conv) return R;
-        st.c[ST_NEWTON_CONV]++;
-        st.c[ST_NEWTON_ITERS] += (uint64_t)no.iters;
-        xi0 = (float)no.xi0;
-        xi1 = (float)no.xi1;
-        det_area = no.det_area;
-    } else {
-        Chart cs = chart_eval(S, GS, obj, xi0, xi1), cd = chart_eval(S, GD, obj, xi0, xi1);
-        if (!cs.ok || !cd.ok) return R;
-        det_area = (double)len(cross(cd.ju, cd.jv)) / (double)len(cross(cs.ju, cs.jv));
-    }
-    Chart cp = chart_eval(S, GD, obj, xi0, xi1);
-    if (!cp.on || !cp.ok) return R;
-    Vtx pd;
-    pd.obj = obj;
-    pd.xi0 = wrap_coord(S, obj, 0, xi0);
-    pd.xi1 = wrap_coord(S, obj, 1, xi1);
-    pd.p = cp.p;
-    pd.n = cp.n;
-    if (len(pd.p - ykm1.p) < S.dmin) return R;
-    {
-        Seg segs[4];
-        int ns = 0;
-        segs[ns++] = seg_pts(S, ykm1, pd);
-        if (p2light) {
-            segs[ns++] = seg_light(s, S, GD, dst_pix, pd);
-        } else {
-            segs[ns++] = seg_pts(S, pd, p2_d);
-            if (src_slot != dst_slot) {   // the scene may have moved: re-test the suffix
-                Vtx prev = p2_d;
-                if (x.nsfx > 0) {
-                    segs[ns++] = seg_pts(S, prev, sfx_d);
-                    prev = sfx_d;
-                }
-                segs[ns++] = seg_light(s, S, GD, dst_pix, prev);
-            }
-        }
-        if (!tr.all_visible(GD, segs, ns)) return R;
-    }
-    ys[ny++] = pd;
-    if (!p2light) {
-        ys[ny++] = p2_d;
-        if (x.nsfx > 0) ys[ny++] = sfx_d;
-    }
-    float plen;
-    float C = path_eval(s, S, GD, dst_pix, ys, ny, plen);
+    const int obj = x.v[1].obj;
+    float C;
     double J = (double)x.pre_pdf / (double)pdf_y;
-    V3 ey = ykm1.p - pd.p, ex = xkm1_s.p - p_s.p;
-    float ly = len(ey), lx = len(ex);
-    float gy = fabsf(dot(pd.n, (1.0f / ly) * ey)) / (ly * ly);
-    float gx = fabsf(dot(p_s.n, (1.0f / lx) * ex)) / (lx * lx);
-    J *= (double)gy / (double)gx * det_area;
-    if (!p2light) {
-        V3 e2d = pd.p - p2_d.p, e2s = p_s.p - p2_s.p;
-        float l2d = len(e2d), l2s = len(e2s);
-        float g2d = fabsf(dot(p2_d.n, (1.0f / l2d) * e2d)) / (l2d * l2d);
-        float g2s = fabsf(dot(p2_s.n, (1.0f / l2s) * e2s)) / (l2s * l2s);
-        J *= (double)g2d / (double)g2s;
+    Vtx pd, p2_d, sfx_d;
+    if (replay_only) {   // pure random replay: NEE at y_n
+        V3 L = light_pos(s, GD, dst_pix);
+        V3 dv = L - cur.p;
+        float dl = len(dv);
+        V3 wo = (1.0f / dl) * dv;
+        C = beta * (bsdf_eval(S, cur.obj, cur.n, wi_e, wo) * fabsf(dot(cur.n, wo)) *
+                    light_emit(s, S, GD, dst_pix, cur.p) / (dl * dl));
+        plen += dl;
+        R.v0 = x.v[0];
+        R.v1 = x.v[1];
+    } else {
+        if (!is_rough(S, cur.obj)) return R;
+        const Vtx xkm1_s = vertex_at(S, GS, x.v[0].obj, x.v[0].xi0, x.v[0].xi1);
+        const Vtx p_s = vertex_at(S, GS, obj, x.v[1].xi0, x.v[1].xi1);
+        Vtx p2_s;
+        V3 p2s_pos, p2d_pos;
+        if (p2light) {
+            p2s_pos = light_pos(s, GS, src_pix);
+            p2d_pos = light_pos(s, GD, dst_pix);
+        } else {
+            p2_s = vertex_at(S, GS, x.v[2].obj, x.v[2].xi0, x.v[2].xi1);
+            p2_d = vertex_at(S, GD, x.v[2].obj, x.v[2].xi0, x.v[2].xi1);
+            p2s_pos = p2_s.p;
+            p2d_pos = p2_d.p;
+        }
+        if (x.nsfx > 0) sfx_d = vertex_at(S, GD, x.v[3].obj, x.v[3].xi0, x.v[3].xi1);
+        float xi0 = x.v[1].xi0, xi1 = x.v[1].xi1;
+        double det_area;
+        if (s.shift_mode == 1) {
+            st.c[ST_NEWTON_ATT]++;
+            // fixed parts of the two length functions: prefix up to x_{k-1},
+            // suffix after p2 (so that L_src(xi) reproduces the stored length)
+            NReal c_dst = cpre;
+            if (!p2light) {
+                V3 prev = p2d_pos;
+                if (x.nsfx > 0) {
+                    c_dst += (NReal)len(sfx_d.p - prev);
+                    prev = sfx_d.p;
+                }
+                c_dst += (NReal)len(light_pos(s, GD, dst_pix) - prev);
+            }
+            const T3<NReal> xk = chart_eval_t<NReal>(S, GS, x.v[0].obj, x.v[0].xi0, x.v[0].xi1).p;
+            const T3<NReal> pp = chart_eval_t<NReal>(S, GS, obj, xi0, xi1).p;
+            const T3<NReal> p2s = p2light ? tof3<NReal>(p2s_pos)
+                                          : chart_eval_t<NReal>(S, GS, x.v[2].obj, x.v[2].xi0, x.v[2].xi1).p;
+            const T3<NReal> p2d = p2light ? tof3<NReal>(p2d_pos)
+                                          : chart_eval_t<NReal>(S, GD, x.v[2].obj, x.v[2].xi0, x.v[2].xi1).p;
+            const NReal c_src = (NReal)x.len - tlen(xk - pp) - tlen(p2s - pp);
+            const T3<NReal> yk = chart_eval_t<NReal>(S, GD, cur.obj, cur.xi0, cur.xi1).p;
+            const NReal tol = (NReal)s.tol_rel * (NReal)plane_width(s, plane);
+            NewtonOut no = newton_solve<NReal>(S, GS, GD, obj, (NReal)xi0, (NReal)xi1, xk, p2s, c_src, yk, p2d, c_dst,
+                                              (NReal)dl0, tol, s.max_it);
+            if (!no.conv) return R;
+            st.c[ST_NEWTON_CONV]++;
+            st.c[ST_NEWTON_ITERS] += (uint32_t)no.iters;
+            xi0 = no.xi0;
+            xi1 = no.xi1;
+            det_area = no.det_area;
+        } else {
+            Chart cs = chart_eval(S, GS, obj, xi0, xi1), cd = chart_eval(S, GD, obj, xi0, xi1);
+            if (!cs.ok || !cd.ok) return R;
+            det_area = (double)len(cross(cd.ju, cd.jv)) / (double)len(cross(cs.ju, cs.jv));
+        }
+        const Chart cp = chart_eval(S, GD, obj, xi0, xi1);
+        if (!cp.on || !cp.ok) return R;
+        pd.obj = obj;
+        pd.xi0 = wrap_coord(S, obj, 0, xi0);
+        pd.xi1 = wrap_coord(S, obj, 1, xi1);
+        pd.p = cp.p;
+        pd.n = cp.n;
+        V3 e1 = pd.p - cur.p;
+        float l1 = len(e1);
+        if (l1 < S.dmin) return R;
+        // contribution of the offset path beyond y_{k-1}
+        V3 w1 = (1.0f / l1) * e1;
+        C = beta * (bsdf_eval(S, cur.obj, cur.n, wi_e, w1) * fabsf(dot(cur.n, w1)));
+        plen += l1;
+        V3 wi2 = -w1;
+        if (p2light) {
+            V3 e2 = light_pos(s, GD, dst_pix) - pd.p;
+            float l2 = len(e2);
+            V3 w2 = (1.0f / l2) * e2;
+            C *= bsdf_eval(S, obj, pd.n, wi2, w2) * fabsf(dot(pd.n, w2)) * light_emit(s, S, GD, dst_pix, pd.p) /
+                 (l2 * l2);
+            plen += l2;
+        } else {
+            V3 e2 = p2_d.p - pd.p;
+            float l2 = len(e2);
+            V3 w2 = (1.0f / l2) * e2;
+            C *= bsdf_eval(S, obj, pd.n, wi2, w2) * fabsf(dot(pd.n, w2));
+            plen += l2;
+            Vtx last = p2_d;
+            V3 wil = -w2;
+            if (x.nsfx > 0) {
+                V3 e3 = sfx_d.p - p2_d.p;
+                float l3 = len(e3);
+                V3 w3 = (1.0f / l3) * e3;
+                C *= bsdf_eval(S, p2_d.obj, p2_d.n, wil, w3) * fabsf(dot(p2_d.n, w3));
+                plen += l3;
+                last = sfx_d;
+                wil = -w3;
+            }
+            V3 e4 = light_pos(s, GD, dst_pix) - last.p;
+            float l4 = len(e4);
+            V3 w4 = (1.0f / l4) * e4;
+            C *= bsdf_eval(S, last.obj, last.n, wil, w4) * fabsf(dot(last.n, w4)) *
+                 light_emit(s, S, GD, dst_pix, last.p) / (l4 * l4);
+            plen += l4;
+        }
+        // Jacobian: replayed directions, reconnection edge, chart area, next edge
+        V3 ex = xkm1_s.p - p_s.p;
+        float lx = len(ex);
+        float gy = fabsf(dot(pd.n, w1)) / (l1 * l1);
+        float gx = fabsf(dot(p_s.n, (1.0f / lx) * ex)) / (lx * lx);
+        J *= (double)gy / (double)gx * det_area;
+        if (!p2light) {
+            V3 e2d = pd.p - p2_d.p, e2s = p_s.p - p2_s.p;
+            float l2d = len(e2d), l2s = len(e2s);
+            float g2d = fabsf(dot(p2_d.n, (1.0f / l2d) * e2d)) / (l2d * l2d);
+            float g2s = fabsf(dot(p2_s.n, (1.0f / l2s) * e2s)) / (l2s * l2s);
+            J *= (double)g2d / (double)g2s;
+        }
+        R.v0 = VRef{cur.obj, cur.xi0, cur.xi1};
+        R.v1 = VRef{obj, pd.xi0, pd.xi1};
     }
-    float Jf = (float)J;
+    if (!(C > 0.f)) return R;
+    const float Jf = (float)J;
     if (!(Jf >= 1.0f / s.j_max && Jf <= s.j_max)) return R;
-    float ph = in_plane(s, plane, plen) ? C : 0.f;
+    const float ph = in_plane(s, plane, plen) ? C : 0.f;
     if (!(ph > 0.f)) return R;
-    R.y = x;
-    R.y.v[0].obj = ykm1.obj;
-    R.y.v[0].xi0 = ykm1.xi0;
-    R.y.v[0].xi1 = ykm1.xi1;
-    R.y.v[1].obj = obj;
-    R.y.v[1].xi0 = pd.xi0;
-    R.y.v[1].xi1 = pd.xi1;
-    R.y.len = plen;
-    R.y.pre_pdf = pdf_y;
-    R.y.phat = ph;
-    R.J = Jf;
+    // visibility last: only shifts that would contribute pay for rays
+    const int nseg = replay_only ? 1 : 2 + ((!p2light && src_slot != dst_slot) ? (x.nsfx > 0 ? 2 : 1) : 0);
+    for (int e = 0; e < nseg; ++e) {
+        Seg sg;
+        if (replay_only) sg = seg_light(s, S, GD, dst_pix, cur);
+        else if (e == 0) sg = seg_pts(S, cur, pd);
+        else if (e == 1) sg = p2light ? seg_light(s, S, GD, dst_pix, pd) : seg_pts(S, pd, p2_d);
+        else if (e == 2 && x.nsfx > 0) sg = seg_pts(S, p2_d, sfx_d);
+        else sg = seg_light(s, S, GD, dst_pix, x.nsfx > 0 ? sfx_d : p2_d);
+        if (!tr.visible(GD, sg)) return R;
+    }
+    R.len = plen;
+    R.pre_pdf = pdf_y;
     R.phat = ph;
+    R.J = Jf;
     R.ok = true;
     st.c[ST_SHIFTS_OK]++;
     if (s.shift_mode == 1) st.c[ST_NEWTON_OK]++;
@@ -1162,8 +1188,8 @@ __device__ inline ShiftOut shift_path(const Sens& s, const SceneDev& S, const Fr
 // wave-reduced accumulation of the per-lane counters (one atomic per wave)
 __device__ inline void flush_counters(Counters& st, unsigned long long* global) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        unsigned long long v = st.c[i];
+    for (int i = 0; i < kNumCounters; ++i) {
+        unsigned long long v = st.c[i];   // widened before the wave sum
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
         if ((threadIdx.x & 63) == 0 && v) atomicAdd(global + i, v);
     }

@@ -15,7 +15,7 @@ struct FrameArgs {
     tofd::SceneDev S;
     tofd::Frames F;
     uint32_t frame;
-    unsigned long long* counters;   // 9 x u64
+    unsigned long long* counters;   // kNumCounters x u64
 };
 
 // bvh.hip
@@ -39,15 +39,21 @@ void launch_reproject(const FrameArgs& a, const tofd::ResSet& can, const tofd::R
                       float* M_out, hipStream_t st);
 void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, int* nb, float* M_out,
                        hipStream_t st);
-// Work items (pixel, plane) for every plane non-empty in any candidate.
+// Work items (pixel, plane | cmask << 16) for every plane non-empty in any of
+// the ncand candidates, and one (item, candidate) task per non-empty one;
+// count[0] = items, count[1] = tasks.
 void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const tofd::ResSet& second,
-                  const int* links, int nlinks, uint2* items, uint32_t* count, uint32_t* out_mask,
+                  const int* links, int ncand, uint2* items, uint2* tasks, uint32_t* count, uint32_t* out_mask,
                   hipStream_t st);
-void launch_temporal(const FrameArgs& a, const tofd::ResSet& can, const tofd::ResSet& prev, const int* prev_pix,
-                     const uint2* items, const uint32_t* count, size_t max_items, tofd::ResSet out,
-                     hipStream_t st);
-void launch_spatial(const FrameArgs& a, int round, const tofd::ResSet& in, const int* nb, const uint2* items,
-                    const uint32_t* count, size_t max_items, tofd::ResSet out, hipStream_t st);
+// Candidate weights: cw[item * ncand + c] = (w_c, phat_q(y_c)); for c > 0 the
+// fields rewritten by the shift into q go to shv[2 * (item * ncand + c) + {0,1}].
+void launch_cand(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
+                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, float2* cw,
+                 float4* shv, hipStream_t st);
+// Weighted reservoir merge of each item's candidates into `out`.
+void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
+                  const uint2* items, const uint32_t* count, size_t max_items, const float2* cw, const float4* shv,
+                  int round, tofd::ResSet out, hipStream_t st);
 void launch_splat(const FrameArgs& a, const tofd::ResSet& shown, const float* pt, const float2* direct,
                   float* out_image, float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st);
 

@@ -62,17 +62,26 @@ class tof_history_desc(C.Structure):
                 ("mask", C.POINTER(C.c_uint32))]
 
 
-KERNELS = ("bvh", "gbuffer", "initial", "temporal_prep", "temporal", "spatial_prep", "spatial", "splat")
+KERNELS = ("bvh", "gbuffer", "initial", "temporal_prep", "temporal", "temporal_merge", "spatial_prep", "spatial",
+           "spatial_merge", "splat")
+
+
+WORK_FIELDS = ("rays", "node_visits", "tri_tests", "shifts", "newton_attempts", "newton_iters")
+
+
+class tof_kernel_work(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in WORK_FIELDS]
 
 
 class tof_kernel_times(C.Structure):
     _fields_ = [("ms", C.c_double * len(KERNELS)), ("launches", C.c_uint64 * len(KERNELS)),
-                ("work_items", C.c_uint64 * 2)]
+                ("work_items", C.c_uint64 * 4), ("work", tof_kernel_work * len(KERNELS))]
 
 
 class tof_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("shifts", "shifts_ok", "newton_attempts", "newton_converged",
-                                          "newton_iters", "newton_paths_ok", "rays", "frames", "bvh_overflow")]
+                                          "newton_iters", "newton_paths_ok", "rays", "frames", "bvh_overflow",
+                                          "node_visits", "tri_tests", "bad_records")]
 
 
 _lib = None
@@ -230,8 +239,10 @@ def tof_set_kernel_timing(h, enabled: bool) -> None:
 def tof_get_kernel_times(h) -> dict:
     t = tof_kernel_times()
     _check("tof_get_kernel_times", lib().tof_get_kernel_times(h, C.byref(t)))
-    out = {k: {"ms": float(t.ms[i]), "launches": int(t.launches[i])} for i, k in enumerate(KERNELS)}
-    out["work_items"] = {"temporal": int(t.work_items[0]), "spatial": int(t.work_items[1])}
+    out = {k: {"ms": float(t.ms[i]), "launches": int(t.launches[i]),
+               "work": {n: int(getattr(t.work[i], n)) for n in WORK_FIELDS}} for i, k in enumerate(KERNELS)}
+    out["work_items"] = {"temporal_items": int(t.work_items[0]), "temporal_tasks": int(t.work_items[1]),
+                         "spatial_items": int(t.work_items[2]), "spatial_tasks": int(t.work_items[3])}
     return out
 
 

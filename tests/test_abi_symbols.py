@@ -62,3 +62,34 @@ def test_binding_struct_layouts_match_header():
                 if n:
                     fields.append(n)
         assert fields == [f[0] for f in pycls._fields_], cname
+
+
+def test_binding_struct_sizes_and_offsets_match_c(tmp_path):
+    """gcc compiles the header; every ctypes mirror has the C size and field
+    offsets."""
+    import subprocess
+    from paper_2605_11536_amd import tof
+    structs = {"tof_scene_desc": tof.tof_scene_desc, "tof_sensor_desc": tof.tof_sensor_desc,
+               "tof_frame_desc": tof.tof_frame_desc, "tof_stats": tof.tof_stats,
+               "tof_history_desc": tof.tof_history_desc, "tof_kernel_work": tof.tof_kernel_work,
+               "tof_kernel_times": tof.tof_kernel_times}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tof.h"', "int main(void) {"]
+    for cname, pycls in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in pycls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            c, f, v = ln.split()
+            got[(c, f)] = int(v)
+    for cname, pycls in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(pycls), cname
+        for fname, _ in pycls._fields_:
+            assert got[(cname, fname)] == getattr(pycls, fname).offset, (cname, fname)

@@ -67,6 +67,7 @@ def _run_pair(w, nframes=None, check=("image", "pt_image", "hist", "pt_hist"), i
     gs, os_ = gpu.stats(), orc.stats()
     gpu.close()
     orc.close()
+    assert gs["bad_records"] == 0
     return gs, os_
 
 
