@@ -57,7 +57,10 @@ def parse():
     ap.add_argument("--ref-trees", type=int, default=16)
     ap.add_argument("--no-equal-rmse", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-frames", type=int, default=3, help="oracle frames timed for the CPU baseline")
+    ap.add_argument("--cpu-crop", type=int, default=64, help="side of the oracle's crop for the CPU baseline")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="bytes of a plain device copy run after the timed region (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -69,25 +72,38 @@ def _threads():
     return max(1, n)
 
 
-def cpu_baseline(width, nframes):
-    """The CPU oracle, as it stands, on the first frames of the same workload."""
+def cpu_baseline(width, first, count, crop):
+    """The CPU oracle, as it stands, on a crop of the same workload: frames
+    0..first+count-1 of the same sequence are rendered on a crop x crop window
+    at the image centre, the last `count` (the frames the GPU's timed window
+    starts with) are timed, and the rate is scaled by the pixel ratio."""
     from paper_2605_11536_amd import scenes
     from oracle import build as obuild
     if not os.path.exists(obuild.LIB):
         obuild.build()
     from oracle.oracle import Oracle
-    w = scenes.glossy_dynamic(width=width, height=width, frames=nframes)
+    x0 = (width - crop) // 2
+    w = scenes.glossy_dynamic(width=crop, height=crop, full_width=width, full_height=width, crop_x0=x0,
+                              crop_y0=x0, frames=first + count)
     nt = _threads()
     o = Oracle(w.scene, w.sensor, num_threads=nt)
-    times = []
+    times, shifts = [], 0
     for fr in w.frames:
+        s0 = o.stats()["shifts"]
         t0 = time.perf_counter()
         o.render(fr)
-        times.append(time.perf_counter() - t0)
+        dt = time.perf_counter() - t0
+        if fr.index >= first:
+            times.append(dt)
+            shifts += o.stats()["shifts"] - s0
     o.close()
-    return {"value": round(len(times) / sum(times), 5), "unit": "frames/s", "cores": nt, "kind": "oracle",
-            "sample": f"full {width}x{width} frames 0..{nframes - 1} of the same sequence (frame 0 without "
-                      f"temporal history); per-frame seconds {[round(t, 2) for t in times]}"}
+    scale = (width * width) / float(crop * crop)
+    return {"value": round(len(times) / (sum(times) * scale), 6), "unit": "frames/s", "cores": nt, "kind": "oracle",
+            "sample": f"{crop}x{crop} crop at ({x0},{x0}) of the {width}x{width} sequence, frames 0..{first + count - 1} "
+                      f"rendered, frames {first}..{first + count - 1} timed ({[round(t, 3) for t in times]} s), "
+                      f"rate divided by the pixel ratio {scale:g}; the crop clips the 30 px spatial disk at its "
+                      f"border, so it does somewhat less work per pixel than the full frame",
+            "shifts_per_s": round(shifts / sum(times), 1)}
 
 
 def main():
@@ -175,6 +191,7 @@ def main():
                         "newton_sr": round(dstats["newton_converged"] / nt, 4),
                         "actual_sr": round(dstats["newton_paths_ok"] / nt, 4)}
     result["rays_per_s"] = round(dstats["rays"] / elapsed, 1)
+    result["shifts_per_s"] = round(dstats["shifts"] / elapsed, 1)
     result["integrity"] = {"bvh_overflow": dstats["bvh_overflow"], "bad_records": dstats["bad_records"]}
     result["traversal"] = {"nodes_per_ray": round(dstats["node_visits"] / max(dstats["rays"], 1), 2),
                            "tri_tests_per_ray": round(dstats["tri_tests"] / max(dstats["rays"], 1), 2),
@@ -214,14 +231,48 @@ def main():
     # equal RMSE against plain ToF PT on the same GPU
     if not args.no_equal_rmse:
         result["equal_rmse"] = equal_rmse(wl, last_frame, restir_out, fps, args, torch, Renderer, scenes)
+        result["equal_rmse_gate_only"] = gate_only(wl, frame_at, args, torch, Renderer, scenes)
 
     r.close()
+    if args.copy_probe:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+        # the scale from counter units to bytes for the traffic figure
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = 4 * n
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(W, args.cpu_frames)
+        result["cpu_baseline"] = cpu_baseline(W, args.warmup, args.cpu_frames, args.cpu_crop)
     print(json.dumps(result), flush=True)
 
 
-def equal_rmse(wl, frame, restir_out, restir_fps, args, torch, Renderer, scenes):
+def gate_only(wl, frame_at, args, torch, Renderer, scenes):
+    """The same scene and sequence with the gate alone (no histogram bins):
+    the regime the paper targets (a narrow gate), same ReSTIR settings."""
+    import dataclasses
+    sensor = dataclasses.replace(wl.sensor, n_bins=0)
+    g = Renderer(wl.scene, sensor)
+    for i in range(args.warmup):
+        g.render(frame_at(i))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        g.render(frame_at(args.warmup + k))
+    torch.cuda.synchronize()
+    fps = args.steps / (time.perf_counter() - t0)
+    out = g.fetch()
+    g.close()
+    gw = dataclasses.replace(wl, sensor=sensor)
+    res = equal_rmse(gw, frame_at(args.warmup + args.steps - 1), out, fps, args, torch, Renderer, scenes,
+                     planes=("gate_image",))
+    res["restir_frames_per_s"] = round(fps, 3)
+    return res
+
+
+def equal_rmse(wl, frame, restir_out, restir_fps, args, torch, Renderer, scenes, planes=("gate_image", "histogram")):
     """RMSE of the ReSTIR frame and of 1-spp plain PT against a high-spp PT
     reference of the same frame; plain PT at s spp has MSE_1/s, so the spp
     that matches ReSTIR is s* = MSE_1/MSE_restir and its frame time s* t_1."""
@@ -234,9 +285,11 @@ def equal_rmse(wl, frame, restir_out, restir_fps, args, torch, Renderer, scenes)
         q.render(f)
         o = q.fetch()
         acc_i = o["pt_image"].astype(np.float64) if acc_i is None else acc_i + o["pt_image"]
-        acc_h = o["pt_hist"].astype(np.float64) if acc_h is None else acc_h + o["pt_hist"]
+        if "pt_hist" in o:
+            acc_h = o["pt_hist"].astype(np.float64) if acc_h is None else acc_h + o["pt_hist"]
     q.close()
-    ref_i, ref_h = acc_i / args.ref_calls, acc_h / args.ref_calls
+    ref_i = acc_i / args.ref_calls
+    ref_h = acc_h / args.ref_calls if acc_h is not None else None
     ref_spp = args.ref_calls * args.ref_trees
     # plain PT, 1 spp: time and error
     pt_sensor = dataclasses.replace(wl.sensor, temporal=0, spatial_rounds=0, m_init=1)
@@ -246,7 +299,8 @@ def equal_rmse(wl, frame, restir_out, restir_fps, args, torch, Renderer, scenes)
         p.render(dataclasses.replace(frame, index=20_000_000 + s))
         o = p.fetch()
         mse1_i.append(np.mean((o["pt_image"] - ref_i) ** 2))
-        mse1_h.append(np.mean((o["pt_hist"] - ref_h) ** 2))
+        if ref_h is not None:
+            mse1_h.append(np.mean((o["pt_hist"] - ref_h) ** 2))
     nrep = 20
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -255,10 +309,13 @@ def equal_rmse(wl, frame, restir_out, restir_fps, args, torch, Renderer, scenes)
     torch.cuda.synchronize()
     t_pt = (time.perf_counter() - t0) / nrep
     p.close()
-    mse1_i, mse1_h = float(np.mean(mse1_i)), float(np.mean(mse1_h))
+    mse1_i = float(np.mean(mse1_i))
+    mse1_h = float(np.mean(mse1_h)) if mse1_h else None
     out = {"reference_spp": ref_spp, "pt_1spp_ms": round(1e3 * t_pt, 3)}
-    for name, mse1, ref, got in (("gate_image", mse1_i, ref_i, restir_out["image"]),
-                                 ("histogram", mse1_h, ref_h, restir_out["hist"])):
+    for name, mse1, ref, got in (("gate_image", mse1_i, ref_i, restir_out.get("image")),
+                                 ("histogram", mse1_h, ref_h, restir_out.get("hist"))):
+        if name not in planes or ref is None:
+            continue
         # remove the reference's own variance (plain PT at ref_spp)
         mse1_t = mse1 * (1.0 - 1.0 / ref_spp)
         mse_r = float(np.mean((got - ref) ** 2)) - mse1 / ref_spp
