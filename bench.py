@@ -31,9 +31,9 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 # Algorithmic work model (counted events x fixed per-event costs)
-NODE_BYTES = 64         # one BVH internal node: two child boxes + two child links
+NODE_BYTES = 128        # one 4-wide BVH node: four child boxes, links and count
 TRI_BYTES = 48          # one leaf: three float4 vertices
-F_NODE = 55             # FP32 ops of one node visit (two slab tests, near/far order)
+F_NODE = 125            # FP32 ops of one node visit (four slab tests, sorting network of the hits)
 F_TRI = 47              # FP32 ops of one watertight ray/triangle test
 F_NEWTON_ITER = 220     # one Newton iteration: length function + derivatives, step, line-search trial
 F_NEWTON_SETUP = 600    # per solve: chart points, source/destination evaluation, final determinants
@@ -212,8 +212,9 @@ def main():
         w = kt[dom]["work"]
         per_launch = valu_flops(w) / max(kl[dom], 1)
         ach = per_launch / avg_s / 1e12
-        kname = {"spatial": "k_cand", "temporal": "k_cand", "spatial_merge": "k_merge", "temporal_merge": "k_merge",
-                 "initial": "k_initial", "gbuffer": "k_gbuffer"}.get(dom, dom)
+        kname = {"spatial_mis": "k_mis", "temporal_mis": "k_mis", "spatial_fwd": "k_fwd", "temporal_fwd": "k_fwd",
+                 "spatial_merge": "k_merge", "temporal_merge": "k_merge", "initial": "k_initial",
+                 "gbuffer": "k_gbuffer"}.get(dom, dom)
         result["roofline"] = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": round(ach / FP32_PEAK_TFLOPS, 5), "traffic": None,
                               "kernel": f"{kname} ({dom})", "avg_launch_ms": round(avg_s * 1e3, 4),

@@ -2,7 +2,9 @@
 // centroid bounds -> 30-bit Morton codes -> 4-pass LSD radix sort (8-bit
 // digits, ballot-ranked stable scatter) -> binary hierarchy from the sorted
 // codes (Karras, HPG 2012) -> bottom-up refit with per-node arrival counters.
-// Nodes store both child boxes so traversal fetches one 64-byte node per step.
+// The binary tree is then collapsed into a 4-wide tree (every node at even
+// depth keeps its grandchildren) whose 128-byte nodes carry the four child
+// boxes, halving the chain of dependent node fetches of a traversal.
 #include "tof_device.h"
 #include "tof_internal.h"
 
@@ -283,6 +285,75 @@ __global__ void k_leaves_refit(const uint32_t* __restrict__ vals, const int4* __
     }
 }
 
+__device__ __forceinline__ int depth_of(const int* __restrict__ parent, int i) {
+    int d = 0;   // bounded walk: a tree over 30-bit codes and 32-bit indices is < 64 deep
+    for (int p = parent[i]; p >= 0 && d < 4096; p = parent[p]) ++d;
+    return d;
+}
+
+// even[i] = 1 for binary internal nodes at even depth (they become 4-wide nodes)
+__global__ void k_even_depth(const int* __restrict__ parent, int ni, uint32_t* __restrict__ even,
+                             uint32_t* __restrict__ map) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    uint32_t e = (depth_of(parent, i) & 1) == 0 ? 1u : 0u;
+    even[i] = e;
+    map[i] = e;   // scanned in place into the 4-wide node index
+}
+
+// one 4-wide node per even-depth binary node: its children, with every
+// internal child replaced by that child's two children
+__global__ void k_collapse(const Node* __restrict__ nodes, int ni, const uint32_t* __restrict__ even,
+                           const uint32_t* __restrict__ map, Node4* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni || !even[i]) return;
+    float lo[4][3], hi[4][3];
+    int ch[4];
+    int n = 0;
+    const Node& b = nodes[i];
+    for (int side = 0; side < 2; ++side) {
+        const int c = side ? b.c1 : b.c0;
+        const float* clo = side ? b.lo1 : b.lo0;
+        const float* chi = side ? b.hi1 : b.hi0;
+        if (c < 0) {
+            for (int q = 0; q < 3; ++q) {
+                lo[n][q] = clo[q];
+                hi[n][q] = chi[q];
+            }
+            ch[n++] = c;
+        } else {
+            const Node& g = nodes[c];
+            for (int gs = 0; gs < 2; ++gs) {
+                const int gc = gs ? g.c1 : g.c0;
+                const float* glo = gs ? g.lo1 : g.lo0;
+                const float* ghi = gs ? g.hi1 : g.hi0;
+                for (int q = 0; q < 3; ++q) {
+                    lo[n][q] = glo[q];
+                    hi[n][q] = ghi[q];
+                }
+                ch[n++] = gc < 0 ? gc : (int)map[gc];
+            }
+        }
+    }
+    for (int j = n; j < 4; ++j) {
+        for (int q = 0; q < 3; ++q) {
+            lo[j][q] = 0.f;
+            hi[j][q] = 0.f;
+        }
+        ch[j] = -1;
+    }
+    Node4 o;
+    o.lox = make_float4(lo[0][0], lo[1][0], lo[2][0], lo[3][0]);
+    o.loy = make_float4(lo[0][1], lo[1][1], lo[2][1], lo[3][1]);
+    o.loz = make_float4(lo[0][2], lo[1][2], lo[2][2], lo[3][2]);
+    o.hix = make_float4(hi[0][0], hi[1][0], hi[2][0], hi[3][0]);
+    o.hiy = make_float4(hi[0][1], hi[1][1], hi[2][1], hi[3][1]);
+    o.hiz = make_float4(hi[0][2], hi[1][2], hi[2][2], hi[3][2]);
+    o.child = make_int4(ch[0], ch[1], ch[2], ch[3]);
+    o.meta = make_int4(n, 0, 0, 0);
+    out[map[i]] = o;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -313,9 +384,10 @@ size_t bvh_scratch_bytes(int T) {
            sizeof(float) * (6 * (size_t)std::max(cb, 1) + 6) + 256;
 }
 
-// Build the BVH of T >= 2 triangles into nodes[T-1], leaves[3T], parent[2T-1].
-void launch_bvh_build(const int4* tv, const float4* wv, int T, Node* nodes, float4* leaves, int* parent,
-                      void* scratch, hipStream_t st) {
+// Build the BVH of T >= 1 triangles: binary nodes[T-1] and parent[2T-1]
+// (build state), leaves[3T] and the 4-wide traversal nodes nodes4[T-1].
+void launch_bvh_build(const int4* tv, const float4* wv, int T, Node* nodes, Node4* nodes4, float4* leaves,
+                      int* parent, void* scratch, hipStream_t st) {
     if (T < 1) return;
     int nb = (T + kSortTile - 1) / kSortTile;
     int cb = (T + 255) / 256;
@@ -347,6 +419,15 @@ void launch_bvh_build(const int4* tv, const float4* wv, int T, Node* nodes, floa
     }
     hipLaunchKernelGGL(k_leaves_refit, dim3(blocks_for(T, 256)), dim3(256), 0, st, vals, tv, wv, T, nodes, parent,
                        flags, leaves);
+    if (T >= 2) {
+        // the sort buffers are free again: even-depth flags and their scan
+        uint32_t* even = keys2;
+        uint32_t* map = vals2;
+        const int ni = T - 1;
+        hipLaunchKernelGGL(k_even_depth, dim3(blocks_for(ni, 256)), dim3(256), 0, st, parent, ni, even, map);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, map, ni);
+        hipLaunchKernelGGL(k_collapse, dim3(blocks_for(ni, 256)), dim3(256), 0, st, nodes, ni, even, map, nodes4);
+    }
 }
 
 }  // namespace tofh

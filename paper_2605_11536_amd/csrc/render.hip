@@ -14,12 +14,15 @@ using tofh::GBufOut;
 namespace {
 
 // Waves per SIMD the tracing kernels are compiled for: caps their VGPRs at
-// 512 / TOF_TRACE_WAVES (the LDS stacks allow 2.5 waves per SIMD).
+// 512 / TOF_TRACE_WAVES.  The LDS stacks (TOF_STACK_DEPTH x 4 B per lane)
+// must allow as many: 48 entries x 128 lanes = 24 KB per block, 6 blocks per
+// CU, 3 waves per SIMD.  Measured on the glossy 512^2 sequence, 3 waves beat
+// 2 by 21%; 4 and 5 spill registers and lose 3% and 8%.
 #ifndef TOF_TRACE_WAVES
-#define TOF_TRACE_WAVES 2
+#define TOF_TRACE_WAVES 3
 #endif
 #define TOF_TRACE_KERNEL __global__ void __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(TOF_TRACE_WAVES)))
-constexpr int kTB = 128;   // lanes per block of the tracing kernels (LDS stack: 64 x 128 x 4 B = 32 KB)
+constexpr int kTB = 128;   // lanes per block of the tracing kernels
 
 __device__ __forceinline__ bool mask_bit(const uint32_t* mask, int P, int pl, int pix) {
     return (mask[(size_t)(pl >> 5) * P + pix] >> (pl & 31)) & 1u;
@@ -325,8 +328,9 @@ __device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t& ea
 
 __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint32_t* __restrict__ m1,
                                                const uint32_t* __restrict__ m2, const int* __restrict__ links,
-                                               int ncand, uint2* __restrict__ items, uint2* __restrict__ tasks,
-                                               uint32_t* __restrict__ count, uint32_t* __restrict__ out_mask) {
+                                               int ncand, uint2* __restrict__ items, uint32_t* __restrict__ task0,
+                                               uint2* __restrict__ tasks, uint32_t* __restrict__ count,
+                                               uint32_t* __restrict__ out_mask) {
     const int P = a.s.P;
     int pix = blockIdx.x * 256 + threadIdx.x;
     bool valid = pix < P && a.F.g[0].gb_obj[pix] >= 0;
@@ -358,6 +362,7 @@ __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint
                 int b = __ffs(u) - 1;
                 u &= u - 1;
                 uint32_t cm = 0;
+                task0[pi] = pt_;
                 for (int c = 0; c < ncand; ++c)
                     if ((wm[c] >> b) & 1u) {
                         cm |= 1u << c;
@@ -371,97 +376,120 @@ __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint
 
 // ---------------------------------------------------------------------------
 // candidate weights (Sec. 3.2.3, eq. GRIS_resampling_weight with the
-// generalized balance heuristic eq. GRIS_MIS_weight).  One lane per (item,
-// candidate): a neighbour's sample is first shifted into q; then the sample
-// in q is shifted into every other candidate domain for the MIS denominator.
-// Writes (w_c, phat_q(y_c)) to cw[item * ncand + c] and, for c > 0, the
-// fields the forward shift rewrote to sh[2 * (item * ncand + c) + {0, 1}], so
-// that the merge stores exactly the sample that was weighed.
+// generalized balance heuristic eq. GRIS_MIS_weight), one shift per lane.
+//
+// k_fwd, one lane per (item, candidate) task: a neighbour's sample x_c is
+// shifted into q (y_c = T_{c->q}(x_c)); fwd[t] = (phat_q(y_c), |J|,
+// M_c phat_c(x_c) / |J|, W_c), phat_q = 0 marking a failed shift, and the
+// fields the shift rewrote go to shv[2t], shv[2t+1].  The canonical
+// candidate (c = 0) records (phat_q(x_q), 1, 0, W_q).
+//
+// k_mis, one lane per (task, neighbour l): y_c is shifted into l's domain and
+// term[t * K + l] = M_l phat_l(T_{q->l}(y_c)) |J| (0 if the shift fails, if
+// l has no pixel, or for the candidate's own domain l = c - 1).
+//
+// The merge forms m_c = (own or M_q phat_q) / (own + M_q phat_q + sum terms).
 // ---------------------------------------------------------------------------
-TOF_TRACE_KERNEL k_cand(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
-                                              const uint2* __restrict__ items, const uint2* __restrict__ tasks,
-                                              const uint32_t* __restrict__ count, float2* __restrict__ cw,
-                                              float4* __restrict__ shv) {
+__device__ __forceinline__ int cand_src(int mode, const int* links, int P, int pix, int c) {
+    return mode == 0 ? links[pix] : links[(size_t)(c - 1) * P + pix];
+}
+
+TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
+                       const uint2* __restrict__ items, const uint2* __restrict__ tasks,
+                       const uint32_t* __restrict__ count, float4* __restrict__ fwd, float4* __restrict__ shv) {
     __shared__ uint32_t stk[kStackDepth * kTB];
     Counters st = {};
     Tracer tr{a.S, stk + threadIdx.x, kTB, st};
     const Sens& s = a.s;
     const int P = s.P;
-    const int K = mode == 0 ? 1 : s.k;
-    const int ncand = K + 1;
     const uint32_t n = count[1];
-    for (uint32_t it = blockIdx.x * kTB + threadIdx.x; it < n; it += gridDim.x * kTB) {
-        const uint2 task = tasks[it];
+    for (uint32_t t = blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
+        const uint2 task = tasks[t];
         const uint2 item = items[task.x];
         const int c = (int)task.y;
         const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
-        // candidate source domain: (slot, pixel)
-        int src_slot = 0, src = pix;
-        if (c > 0) {
-            src = mode == 0 ? links[pix] : links[(size_t)(c - 1) * P + pix];
-            src_slot = mode == 0 ? 1 : 0;
+        if (c == 0) {
+            const size_t idx = (size_t)pl * P + pix;
+            fwd[t] = make_float4(rec_phat(A, idx), 1.0f, 0.f, rec_W(A, idx));
+            continue;
         }
-        const ResSet& R = (mode == 0 && c == 1) ? Bp : A;
+        const int src = cand_src(mode, links, P, pix, c);
         float Wx;
-        // y starts as the candidate and becomes its shift into q; a shift only
-        // rewrites fields, so one record stays live
-        Rec y = load_rec(R, (size_t)pl * P + src, Wx);
+        Rec y = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
         const float xphat = y.phat;
-        const float mq = A.M[pix];
-        const float mc = (c == 0) ? mq : (mode == 0 ? fminf(Bp.M[src], s.m_cap) : A.M[src]);
-        float phq = xphat, Jj = 1.0f;
-        float den = mq * xphat;
-        bool fail = false;
-        for (int step = (c == 0 ? 0 : -1); step < K; ++step) {
-            int dpix, dslot;
-            if (step < 0) {
-                dpix = pix;
-                dslot = 0;
-            } else {
-                if (step == c - 1) continue;
-                dpix = mode == 0 ? links[pix] : links[(size_t)step * P + pix];
-                dslot = mode == 0 ? 1 : 0;
-                if (dpix < 0) continue;
-            }
-            const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, step < 0 ? src_slot : 0, step < 0 ? src : pix, dslot,
-                                           dpix, pl, 0.f);
-            if (step < 0) {
-                if (!sh.ok) {
-                    fail = true;
-                    break;
+        const float mc = mode == 0 ? fminf(Bp.M[src], s.m_cap) : A.M[src];
+        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, mode == 0 ? 1 : 0, src, 0, pix, pl, 0.f);
+        if (!sh.ok) {
+            fwd[t] = make_float4(0.f, 1.0f, 0.f, Wx);
+            continue;
+        }
+        apply_shift(y, sh);
+        fwd[t] = make_float4(sh.phat, sh.J, mc * xphat / sh.J, Wx);
+        shv[2 * (size_t)t] = make_float4(__int_as_float(y.v[0].obj), y.v[0].xi0, y.v[0].xi1, __int_as_float(y.v[1].obj));
+        shv[2 * (size_t)t + 1] = make_float4(y.v[1].xi0, y.v[1].xi1, y.len, y.pre_pdf);
+    }
+    flush_counters(st, a.counters);
+}
+
+TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
+                       const uint2* __restrict__ items, const uint2* __restrict__ tasks,
+                       const uint32_t* __restrict__ count, const float4* __restrict__ fwd,
+                       const float4* __restrict__ shv, float* __restrict__ term) {
+    __shared__ uint32_t stk[kStackDepth * kTB];
+    Counters st = {};
+    Tracer tr{a.S, stk + threadIdx.x, kTB, st};
+    const Sens& s = a.s;
+    const int P = s.P;
+    const uint32_t K = mode == 0 ? 1u : (uint32_t)s.k;
+    const uint64_t n = (uint64_t)count[1] * K;
+    for (uint64_t g = (uint64_t)blockIdx.x * kTB + threadIdx.x; g < n; g += (uint64_t)gridDim.x * kTB) {
+        const uint32_t t = (uint32_t)(g / K);
+        const int l = (int)(g - (uint64_t)t * K);
+        const uint2 task = tasks[t];
+        const int c = (int)task.y;
+        const float4 fw = fwd[t];
+        float out = 0.f;
+        if (c == 0 || (fw.x > 0.f && l != c - 1)) {
+            const uint2 item = items[task.x];
+            const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
+            const int dpix = mode == 0 ? links[pix] : links[(size_t)l * P + pix];
+            if (dpix >= 0) {
+                float Wx;
+                Rec y;
+                if (c == 0) {
+                    y = load_rec(A, (size_t)pl * P + pix, Wx);
+                } else {
+                    const int src = cand_src(mode, links, P, pix, c);
+                    y = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
+                    const float4 s0 = shv[2 * (size_t)t], s1 = shv[2 * (size_t)t + 1];
+                    y.v[0] = VRef{__float_as_int(s0.x), s0.y, s0.z};
+                    y.v[1] = VRef{__float_as_int(s0.w), s1.x, s1.y};
+                    y.len = s1.z;
+                    y.pre_pdf = s1.w;
+                    y.phat = fw.x;
                 }
-                apply_shift(y, sh);
-                phq = sh.phat;
-                Jj = sh.J;
-                den = mc * xphat / Jj + mq * phq;
-            } else if (sh.ok) {
-                const float ml = mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
-                den += ml * sh.phat * sh.J;
+                const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, pl, 0.f);
+                if (sh.ok) {
+                    const float ml = mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
+                    out = ml * sh.phat * sh.J;
+                }
             }
         }
-        float w = 0.f;
-        const size_t slot = (size_t)task.x * ncand + c;
-        if (!fail) {
-            w = c == 0 ? (mq * phq / den) * phq * Wx : ((mc * xphat / Jj) / den) * phq * Wx * Jj;
-            if (c > 0) {
-                shv[2 * slot] = make_float4(__int_as_float(y.v[0].obj), y.v[0].xi0, y.v[0].xi1,
-                                            __int_as_float(y.v[1].obj));
-                shv[2 * slot + 1] = make_float4(y.v[1].xi0, y.v[1].xi1, y.len, y.pre_pdf);
-            }
-        }
-        cw[slot] = make_float2(w, phq);
+        term[g] = out;
     }
     flush_counters(st, a.counters);
 }
 
 // ---------------------------------------------------------------------------
 // merge: weighted reservoir sampling over the candidates in order, W = sum/phat.
-// A selected neighbour sample is its source record with the fields its shift
-// into q rewrote (stored by the candidate pass).
+// Weights follow eq. GRIS_resampling_weight with the generalized balance
+// heuristic from the terms of k_fwd and k_mis.  A selected neighbour sample is
+// its source record with the fields its shift into q rewrote.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, ResSet Bp,
                                                const int* __restrict__ links, const uint2* __restrict__ items,
-                                               const uint32_t* __restrict__ count, const float2* __restrict__ cw,
+                                               const uint32_t* __restrict__ task0, const uint32_t* __restrict__ count,
+                                               const float4* __restrict__ fwd, const float* __restrict__ term,
                                                const float4* __restrict__ shv, int round, ResSet out) {
     const Sens& s = a.s;
     const int P = s.P;
@@ -472,22 +500,32 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
         const uint2 item = items[it];
         const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
         const uint32_t cm = item.y >> 16;
+        const uint32_t t0 = task0[it];
         const uint64_t fp = full_pixel(s, pix);
+        const float mq = A.M[pix];
         Draw ut;
         if (mode == 0) ut = philox(s.seed, fp, a.frame, PASS_TEMPORAL, 0, (uint64_t)pl);
         float ws = 0.f, sel_phat = 0.f;
         int sel = -1;
+        uint32_t sel_t = 0;
         for (int c = 0; c < ncand; ++c) {
             if (!((cm >> c) & 1u)) continue;
-            const float2 r = cw[(size_t)it * ncand + c];
-            if (c > 0 && !(r.x > 0.f)) continue;   // the shift into q failed
+            const uint32_t t = t0 + (uint32_t)__popc(cm & ((1u << c) - 1u));
+            const float4 fw = fwd[t];
+            const float phq = fw.x;
+            if (c > 0 && !(phq > 0.f)) continue;   // the shift into q failed
+            float den = fw.z + mq * phq;
+            for (int l = 0; l < K; ++l) den += term[(size_t)t * K + l];
+            const float w = ((c == 0 ? mq * phq : fw.z) / den) * phq * fw.w * fw.y;
+            if (c > 0 && !(w > 0.f)) continue;
             float u;
             if (mode == 0) u = ut.u(c);
             else u = philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + c / 4)).u(c % 4);
-            ws += r.x;
-            if (u * ws < r.x) {
+            ws += w;
+            if (u * ws < w) {
                 sel = c;
-                sel_phat = r.y;
+                sel_phat = phq;
+                sel_t = t;
             }
         }
         if (sel >= 0 && ws > 0.f) {
@@ -497,10 +535,9 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
                 const Rec x = load_rec(A, oidx, Wx);
                 store_rec(out, oidx, x, ws / sel_phat);
             } else {
-                const int src = mode == 0 ? links[pix] : links[(size_t)(sel - 1) * P + pix];
+                const int src = cand_src(mode, links, P, pix, sel);
                 Rec x = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
-                const size_t slot = (size_t)it * ncand + sel;
-                const float4 s0 = shv[2 * slot], s1 = shv[2 * slot + 1];
+                const float4 s0 = shv[2 * (size_t)sel_t], s1 = shv[2 * (size_t)sel_t + 1];
                 x.v[0] = VRef{__float_as_int(s0.x), s0.y, s0.z};
                 x.v[1] = VRef{__float_as_int(s0.w), s1.x, s1.y};
                 x.len = s1.z;
@@ -574,21 +611,29 @@ void launch_neighbours(const FrameArgs& a, int round, const ResSet& in, int* nb,
                        M_out);
 }
 void launch_items(const FrameArgs& a, int mode, const ResSet& first, const ResSet& second, const int* links,
-                  int ncand, uint2* items, uint2* tasks, uint32_t* count, uint32_t* out_mask, hipStream_t st) {
+                  int ncand, uint2* items, uint32_t* task0, uint2* tasks, uint32_t* count, uint32_t* out_mask,
+                  hipStream_t st) {
     hipLaunchKernelGGL(k_items, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, mode, first.mask,
-                       second.mask, links, ncand, items, tasks, count, out_mask);
+                       second.mask, links, ncand, items, task0, tasks, count, out_mask);
 }
-void launch_cand(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, float2* cw,
-                 float4* shv, hipStream_t st) {
-    hipLaunchKernelGGL(k_cand, dim3(grid_for(max_tasks, kTB, 32768)), dim3(kTB), 0, st, a, mode, A, Bp, links, items,
-                       tasks, count, cw, shv);
+void launch_fwd(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, float4* fwd,
+                float4* shv, hipStream_t st) {
+    hipLaunchKernelGGL(k_fwd, dim3(grid_for(max_tasks, kTB, 32768)), dim3(kTB), 0, st, a, mode, A, Bp, links, items,
+                       tasks, count, fwd, shv);
+}
+void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, const float4* fwd,
+                const float4* shv, float* term, hipStream_t st) {
+    const size_t K = mode == 0 ? 1 : (size_t)a.s.k;
+    hipLaunchKernelGGL(k_mis, dim3(grid_for(max_tasks * K, kTB, 65536)), dim3(kTB), 0, st, a, mode, A, Bp, links,
+                       items, tasks, count, fwd, shv, term);
 }
 void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                  const uint2* items, const uint32_t* count, size_t max_items, const float2* cw, const float4* shv,
-                  int round, ResSet out, hipStream_t st) {
+                  const uint2* items, const uint32_t* task0, const uint32_t* count, size_t max_items,
+                  const float4* fwd, const float* term, const float4* shv, int round, ResSet out, hipStream_t st) {
     hipLaunchKernelGGL(k_merge, dim3(grid_for(max_items, 256, 32768)), dim3(256), 0, st, a, mode, A, Bp, links, items,
-                       count, cw, shv, round, out);
+                       task0, count, fwd, term, shv, round, out);
 }
 void launch_splat(const FrameArgs& a, const ResSet& shown, const float* pt, const float2* direct, float* out_image,
                   float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st) {

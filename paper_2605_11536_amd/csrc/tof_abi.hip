@@ -27,7 +27,8 @@ struct Alloc {
 struct GeomBuf {
     float* xf = nullptr;
     float4* wv = nullptr;
-    Node* nodes = nullptr;
+    Node* nodes = nullptr;       // binary build nodes
+    Node4* nodes4 = nullptr;     // 4-wide traversal nodes
     float4* leaves = nullptr;
     int* parent = nullptr;
     std::vector<float> xf_host;
@@ -82,8 +83,10 @@ struct tof_ctx {
     int* nb = nullptr;
     uint2* items = nullptr;
     uint2* tasks = nullptr;
-    float2* cw = nullptr;
+    uint32_t* task0 = nullptr; // [max_items]: first task of each item
+    float4* fwd = nullptr;     // [max_tasks]: forward-shift terms per task
     float4* shv = nullptr;     // [2 * max_tasks]: fields rewritten by each forward shift
+    float* term = nullptr;     // [max_tasks * max(k, 1)]: MIS terms per (task, neighbour)
     uint32_t* count = nullptr;
     size_t max_items = 0, max_tasks = 0;
     // misc
@@ -169,8 +172,9 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t gbuf = 2 * P * (4 + 4 + 4 + 16 + 16);
     return 4 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
            P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ +
-           P * B * ((size_t)std::max(d.spatial_k, 1) + 1) * (8 + 8 + 32) /*tasks, weights, shifted fields*/ +
-           64 * 1024;
+           P * B * 4 /*first task per item*/ +
+           P * B * ((size_t)std::max(d.spatial_k, 1) + 1) * (8 + 16 + 32 + 4 * (size_t)std::max(d.spatial_k, 1))
+           /*tasks, forward terms, shifted fields, MIS terms*/ + 64 * 1024;
 }
 
 tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
@@ -214,7 +218,7 @@ SlotDev slot_dev(const tof_ctx* c, int i) {
     SlotDev d;
     d.wv = g.wv;
     d.xf = g.xf;
-    d.nodes = g.nodes;
+    d.nodes = g.nodes4;
     d.leaves = g.leaves;
     d.n_tri = c->n_tri;
     d.cam_pos = h.cam_pos;
@@ -394,6 +398,7 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
         TOF_TRY(alloc_t(c, a, &g.xf, 12 * (size_t)objs.size()));
         TOF_TRY(alloc_t(c, a, &g.wv, std::max(d->num_vertices, 1)));
         TOF_TRY(alloc_t(c, a, &g.nodes, std::max(T - 1, 1)));
+        TOF_TRY(alloc_t(c, a, &g.nodes4, std::max(T - 1, 1)));
         TOF_TRY(alloc_t(c, a, &g.leaves, 3 * (size_t)std::max(T, 1)));
         TOF_TRY(alloc_t(c, a, &g.parent, 2 * (size_t)std::max(T, 1)));
     }
@@ -459,8 +464,10 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     const size_t ncand = (size_t)std::max(d->spatial_k, 1) + 1;
     TOF_TRY(alloc_t(c, a, &c->items, P * B));
     TOF_TRY(alloc_t(c, a, &c->tasks, P * B * ncand));
-    TOF_TRY(alloc_t(c, a, &c->cw, P * B * ncand));
+    TOF_TRY(alloc_t(c, a, &c->task0, P * B));
+    TOF_TRY(alloc_t(c, a, &c->fwd, P * B * ncand));
     TOF_TRY(alloc_t(c, a, &c->shv, 2 * P * B * ncand));
+    TOF_TRY(alloc_t(c, a, &c->term, P * B * ncand * (ncand - 1)));
     TOF_TRY(alloc_t(c, a, &c->count, 64));
     c->max_tasks = P * B * ncand;
     c->item_slots = 4 * 4096;
@@ -668,7 +675,8 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         HIP_TRY(hipEventRecord(c->xf_ev[ring], st));
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, c->n_vert, st);
-        if (c->n_tri > 0) tofh::launch_bvh_build(c->d_tv, g.wv, c->n_tri, g.nodes, g.leaves, g.parent, c->bvh_scratch, st);
+        if (c->n_tri > 0) tofh::launch_bvh_build(c->d_tv, g.wv, c->n_tri, g.nodes, g.nodes4, g.leaves, g.parent,
+                                                c->bvh_scratch, st);
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         g.built = true;
     }
@@ -728,15 +736,21 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         a.counters = c->counters + (size_t)TOF_K_TEMPORAL_PREP * kBank;
         tofh::launch_reproject(a, can, pf, c->prev_pix, tmp.M, st);
         tofh::launch_fill_u32(c->count, 0u, 2, st);
-        tofh::launch_items(a, 0, can, pf, c->prev_pix, 2, c->items, c->tasks, c->count, tmp.mask, st);
+        tofh::launch_items(a, 0, can, pf, c->prev_pix, 2, c->items, c->task0, c->tasks, c->count, tmp.mask, st);
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_PREP, st));
-        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL, st));
-        a.counters = c->counters + (size_t)TOF_K_TEMPORAL * kBank;
-        tofh::launch_cand(a, 0, can, pf, c->prev_pix, c->items, c->tasks, c->count, c->max_tasks, c->cw, c->shv, st);
-        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL, st));
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_FWD, st));
+        a.counters = c->counters + (size_t)TOF_K_TEMPORAL_FWD * kBank;
+        tofh::launch_fwd(a, 0, can, pf, c->prev_pix, c->items, c->tasks, c->count, c->max_tasks, c->fwd, c->shv, st);
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_FWD, st));
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MIS, st));
+        a.counters = c->counters + (size_t)TOF_K_TEMPORAL_MIS * kBank;
+        tofh::launch_mis(a, 0, can, pf, c->prev_pix, c->items, c->tasks, c->count, c->max_tasks, c->fwd, c->shv,
+                         c->term, st);
+        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MIS, st));
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MERGE, st));
         a.counters = c->counters + (size_t)TOF_K_TEMPORAL_MERGE * kBank;
-        tofh::launch_merge(a, 0, can, pf, c->prev_pix, c->items, c->count, c->max_items, c->cw, c->shv, 0, tmp, st);
+        tofh::launch_merge(a, 0, can, pf, c->prev_pix, c->items, c->task0, c->count, c->max_items, c->fwd, c->term,
+                           c->shv, 0, tmp, st);
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MERGE, st));
         if (item_slot) HIP_TRY(hipMemcpyAsync(item_slot, c->count, 8, hipMemcpyDeviceToDevice, st));
         cur_set = &tmp;
@@ -759,15 +773,21 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         a.counters = c->counters + (size_t)TOF_K_SPATIAL_PREP * kBank;
         tofh::launch_neighbours(a, r, in, c->nb, out.M, st);
         tofh::launch_fill_u32(c->count, 0u, 2, st);
-        tofh::launch_items(a, 1, in, in, c->nb, c->s.k + 1, c->items, c->tasks, c->count, out.mask, st);
+        tofh::launch_items(a, 1, in, in, c->nb, c->s.k + 1, c->items, c->task0, c->tasks, c->count, out.mask, st);
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
-        HIP_TRY(timer_mark(c, TOF_K_SPATIAL, st));
-        a.counters = c->counters + (size_t)TOF_K_SPATIAL * kBank;
-        tofh::launch_cand(a, 1, in, in, c->nb, c->items, c->tasks, c->count, c->max_tasks, c->cw, c->shv, st);
-        HIP_TRY(timer_mark(c, TOF_K_SPATIAL, st));
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_FWD, st));
+        a.counters = c->counters + (size_t)TOF_K_SPATIAL_FWD * kBank;
+        tofh::launch_fwd(a, 1, in, in, c->nb, c->items, c->tasks, c->count, c->max_tasks, c->fwd, c->shv, st);
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_FWD, st));
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MIS, st));
+        a.counters = c->counters + (size_t)TOF_K_SPATIAL_MIS * kBank;
+        tofh::launch_mis(a, 1, in, in, c->nb, c->items, c->tasks, c->count, c->max_tasks, c->fwd, c->shv, c->term,
+                         st);
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MIS, st));
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MERGE, st));
         a.counters = c->counters + (size_t)TOF_K_SPATIAL_MERGE * kBank;
-        tofh::launch_merge(a, 1, in, in, c->nb, c->items, c->count, c->max_items, c->cw, c->shv, r, out, st);
+        tofh::launch_merge(a, 1, in, in, c->nb, c->items, c->task0, c->count, c->max_items, c->fwd, c->term, c->shv, r,
+                           out, st);
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MERGE, st));
         if (item_slot && r == 0) HIP_TRY(hipMemcpyAsync(item_slot + 2, c->count, 8, hipMemcpyDeviceToDevice, st));
         cur_idx = out_idx;

@@ -13,7 +13,10 @@
 namespace tofd {
 
 constexpr float kPi = 3.14159265358979323846f;
-constexpr int kStackDepth = 64;      // per-lane traversal stack entries (LDS)
+#ifndef TOF_STACK_DEPTH
+#define TOF_STACK_DEPTH 48
+#endif
+constexpr int kStackDepth = TOF_STACK_DEPTH;   // per-lane traversal stack entries (LDS)
 constexpr int kMaxVerts = 4;         // scattering vertices per path
 constexpr int kMaxK = 8;             // spatial neighbours
 
@@ -50,11 +53,19 @@ struct Mat {
 struct TriInfo {
     int obj, i, j, h;
 };
-// Binary BVH node holding both child boxes; child index has bit 31 set for a
-// leaf (sorted primitive position).
+// Binary BVH node of the builder, holding both child boxes; child index has
+// bit 31 set for a leaf (sorted primitive position).
 struct Node {
     float lo0[3], hi0[3], lo1[3], hi1[3];
     int c0, c1, parent, pad;
+};
+// Traversal node: four child boxes, one 128-byte line.  Component j of each
+// float4 belongs to child j; child[j] >= 0 is a Node4 index, bit 31 set marks
+// a leaf (sorted triangle slot); meta.x = number of children (2..4).
+struct Node4 {
+    float4 lox, loy, loz, hix, hiy, hiz;
+    int4 child;
+    int4 meta;
 };
 
 struct SceneDev {
@@ -70,7 +81,7 @@ struct SceneDev {
 struct SlotDev {
     const float4* wv;       // world vertices
     const float* xf;        // object transforms, 12 floats each
-    const Node* nodes;
+    const Node4* nodes;     // 4-wide traversal nodes, root at 0
     const float4* leaves;   // 3 float4 per sorted triangle: v0 (w = tri id bits), v1, v2
     int n_tri;
     V3 cam_pos, cam_fwd, cam_right, cam_up;
@@ -435,6 +446,10 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
     h.obj = -1;
     const int T = G.n_tri;
     auto test_leaf = [&](int k) -> bool {
+        if ((unsigned)k >= (unsigned)T) {   // never for a well-formed tree
+            st.c[ST_OVERFLOW]++;
+            return false;
+        }
         st.c[ST_TRIS]++;
         float4 a = G.leaves[3 * k], b = G.leaves[3 * k + 1], c = G.leaves[3 * k + 2];
         float t, b1, b2;
@@ -458,47 +473,85 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
     } else if (T > 1) {
         int sp = 0;
         uint32_t node = 0;
-        // a binary tree over T leaves has T-1 internal nodes: any valid walk
+        constexpr float kInfT = 3.0e38f;
+        auto push = [&](int n) {
+            if (sp < kStackDepth) {
+                stack[sp * stride] = (uint32_t)n;
+                ++sp;
+            } else {
+                st.c[ST_OVERFLOW]++;
+            }
+        };
+        // a 4-wide tree over T leaves has fewer than T nodes: any valid walk
         // visits each at most once, so this bound only stops a malformed tree
         int budget = 2 * T + 64;
         while (--budget > 0) {
-            const Node& nd = G.nodes[node];
+            if (node >= (uint32_t)(T - 1)) {   // never for a well-formed tree
+                st.c[ST_OVERFLOW]++;
+                break;
+            }
+            const Node4& nd = G.nodes[node];
             st.c[ST_NODES]++;
-            float t0, t1;
-            bool h0 = slab(nd.lo0, nd.hi0, r, tb, t0);
-            bool h1 = slab(nd.lo1, nd.hi1, r, tb, t1);
-            uint32_t c0 = (uint32_t)nd.c0, c1 = (uint32_t)nd.c1;
-            // leaves are tested right away; internal children are visited near-first
-            if (h0 && (c0 & 0x80000000u)) {
-                if (test_leaf((int)(c0 & 0x7fffffffu))) return true;
-                h0 = false;
-            }
-            if (h1 && (c1 & 0x80000000u)) {
-                if (test_leaf((int)(c1 & 0x7fffffffu))) return true;
-                h1 = false;
-            }
-            if (h0 && h1) {
-                uint32_t nearc = t0 <= t1 ? c0 : c1, farc = t0 <= t1 ? c1 : c0;
-                if (sp < kStackDepth) {
-                    stack[sp * stride] = farc;
-                    ++sp;
-                } else {
-                    st.c[ST_OVERFLOW]++;
+            const float4 lx = nd.lox, ly = nd.loy, lz = nd.loz, hx = nd.hix, hy = nd.hiy, hz = nd.hiz;
+            const int4 cc = nd.child;
+            const int nc = nd.meta.x;
+            const float bx[4][6] = {{lx.x, ly.x, lz.x, hx.x, hy.x, hz.x}, {lx.y, ly.y, lz.y, hx.y, hy.y, hz.y},
+                                    {lx.z, ly.z, lz.z, hx.z, hy.z, hz.z}, {lx.w, ly.w, lz.w, hx.w, hy.w, hz.w}};
+            const int ch[4] = {cc.x, cc.y, cc.z, cc.w};
+            // key = entry distance of an internal child that is hit, +inf otherwise
+            float k0 = kInfT, k1 = kInfT, k2 = kInfT, k3 = kInfT;
+            int n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+            uint32_t leaf_hits = 0;   // bit j: leaf child j is hit
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float t;
+                if (j < nc && slab(bx[j], bx[j] + 3, r, tb, t)) {
+                    const uint32_t c = (uint32_t)ch[j];
+                    if (c & 0x80000000u) {
+                        leaf_hits |= 1u << j;
+                    } else {
+                        if (j == 0) { k0 = t; n0 = (int)c; }
+                        if (j == 1) { k1 = t; n1 = (int)c; }
+                        if (j == 2) { k2 = t; n2 = (int)c; }
+                        if (j == 3) { k3 = t; n3 = (int)c; }
+                    }
                 }
-                node = nearc;
+            }
+            // leaves are tested right away (one call site keeps the code small);
+            // internal children are visited near-first
+            while (leaf_hits) {
+                const int j = __ffs(leaf_hits) - 1;
+                leaf_hits &= leaf_hits - 1;
+                const int c = j == 0 ? cc.x : (j == 1 ? cc.y : (j == 2 ? cc.z : cc.w));
+                if (test_leaf(c & 0x7fffffff)) return true;
+            }
+            // sorting network on (key, node): nearest first
+            auto cswap = [](float& ka, int& na, float& kb, int& nb) {
+                if (kb < ka) {
+                    const float kt = ka;
+                    ka = kb;
+                    kb = kt;
+                    const int nt = na;
+                    na = nb;
+                    nb = nt;
+                }
+            };
+            cswap(k0, n0, k1, n1);
+            cswap(k2, n2, k3, n3);
+            cswap(k0, n0, k2, n2);
+            cswap(k1, n1, k3, n3);
+            cswap(k1, n1, k2, n2);
+            if (!(k0 < kInfT)) {
+                if (sp == 0) break;
+                --sp;
+                node = stack[sp * stride];
                 continue;
             }
-            if (h0) {
-                node = c0;
-                continue;
-            }
-            if (h1) {
-                node = c1;
-                continue;
-            }
-            if (sp == 0) break;
-            --sp;
-            node = stack[sp * stride];
+            // the others onto the stack, farthest deepest
+            if (k3 < kInfT) push(n3);
+            if (k2 < kInfT) push(n2);
+            if (k1 < kInfT) push(n1);
+            node = (uint32_t)n0;
         }
         if (budget <= 0) st.c[ST_OVERFLOW]++;
     }

@@ -22,8 +22,8 @@ struct FrameArgs {
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 void launch_world_verts(const float4* lv, const int* vobj, const float* xf, float4* wv, int nv, hipStream_t st);
 size_t bvh_scratch_bytes(int T);
-void launch_bvh_build(const int4* tv, const float4* wv, int T, tofd::Node* nodes, float4* leaves, int* parent,
-                      void* scratch, hipStream_t st);
+void launch_bvh_build(const int4* tv, const float4* wv, int T, tofd::Node* nodes, tofd::Node4* nodes4,
+                      float4* leaves, int* parent, void* scratch, hipStream_t st);
 
 // render.hip
 struct GBufOut {
@@ -40,20 +40,25 @@ void launch_reproject(const FrameArgs& a, const tofd::ResSet& can, const tofd::R
 void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, int* nb, float* M_out,
                        hipStream_t st);
 // Work items (pixel, plane | cmask << 16) for every plane non-empty in any of
-// the ncand candidates, and one (item, candidate) task per non-empty one;
-// count[0] = items, count[1] = tasks.
+// the ncand candidates, the index of each item's first task, and one
+// (item, candidate) task per non-empty candidate; count[0] = items,
+// count[1] = tasks.
 void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const tofd::ResSet& second,
-                  const int* links, int ncand, uint2* items, uint2* tasks, uint32_t* count, uint32_t* out_mask,
-                  hipStream_t st);
-// Candidate weights: cw[item * ncand + c] = (w_c, phat_q(y_c)); for c > 0 the
-// fields rewritten by the shift into q go to shv[2 * (item * ncand + c) + {0,1}].
-void launch_cand(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
-                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, float2* cw,
-                 float4* shv, hipStream_t st);
+                  const int* links, int ncand, uint2* items, uint32_t* task0, uint2* tasks, uint32_t* count,
+                  uint32_t* out_mask, hipStream_t st);
+// Shifts of a reuse pass: the forward shifts into q (fwd[t], shv[2t..2t+1]),
+// then the MIS shifts into every neighbour domain (term[t * K + l]).
+void launch_fwd(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, float4* fwd,
+                float4* shv, hipStream_t st);
+void launch_mis(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, const float4* fwd,
+                const float4* shv, float* term, hipStream_t st);
 // Weighted reservoir merge of each item's candidates into `out`.
 void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
-                  const uint2* items, const uint32_t* count, size_t max_items, const float2* cw, const float4* shv,
-                  int round, tofd::ResSet out, hipStream_t st);
+                  const uint2* items, const uint32_t* task0, const uint32_t* count, size_t max_items,
+                  const float4* fwd, const float* term, const float4* shv, int round, tofd::ResSet out,
+                  hipStream_t st);
 void launch_splat(const FrameArgs& a, const tofd::ResSet& shown, const float* pt, const float2* direct,
                   float* out_image, float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st);
 
