@@ -405,19 +405,14 @@ __device__ __forceinline__ RayPre ray_pre(V3 o, V3 d) {
     return r;
 }
 
-__device__ __forceinline__ bool slab(const float* lo, const float* hi, const RayPre& r, float tmax, float& tn) {
-    float t1 = (lo[0] - r.o.x) * r.inv.x, t2 = (hi[0] - r.o.x) * r.inv.x;
-    float a = fminf(t1, t2), b = fmaxf(t1, t2);
-    t1 = (lo[1] - r.o.y) * r.inv.y;
-    t2 = (hi[1] - r.o.y) * r.inv.y;
-    a = fmaxf(a, fminf(t1, t2));
-    b = fminf(b, fmaxf(t1, t2));
-    t1 = (lo[2] - r.o.z) * r.inv.z;
-    t2 = (hi[2] - r.o.z) * r.inv.z;
-    a = fmaxf(a, fminf(t1, t2));
-    b = fminf(b, fmaxf(t1, t2));
-    a = fmaxf(a, 0.f);
-    b = fminf(b, tmax);
+// ray/box slab test; tn = entry distance (clamped at 0)
+__device__ __forceinline__ bool slab(float lox, float loy, float loz, float hix, float hiy, float hiz, const RayPre& r,
+                                     float tmax, float& tn) {
+    const float x1 = (lox - r.o.x) * r.inv.x, x2 = (hix - r.o.x) * r.inv.x;
+    const float y1 = (loy - r.o.y) * r.inv.y, y2 = (hiy - r.o.y) * r.inv.y;
+    const float z1 = (loz - r.o.z) * r.inv.z, z2 = (hiz - r.o.z) * r.inv.z;
+    const float a = fmaxf(fmaxf(fminf(x1, x2), fminf(y1, y2)), fmaxf(fminf(z1, z2), 0.f));
+    const float b = fminf(fminf(fmaxf(x1, x2), fmaxf(y1, y2)), fminf(fmaxf(z1, z2), tmax));
     tn = a;
     return a <= b;
 }
@@ -490,33 +485,25 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
                 st.c[ST_OVERFLOW]++;
                 break;
             }
-            const Node4& nd = G.nodes[node];
+            // the whole 128-byte node, loaded unconditionally
+            const float4* nq = reinterpret_cast<const float4*>(G.nodes + node);
+            const float4 lx = nq[0], ly = nq[1], lz = nq[2], hx = nq[3], hy = nq[4], hz = nq[5];
+            const int4 cc = reinterpret_cast<const int4*>(nq)[6];
+            const int nc = reinterpret_cast<const int4*>(nq)[7].x;
             st.c[ST_NODES]++;
-            const float4 lx = nd.lox, ly = nd.loy, lz = nd.loz, hx = nd.hix, hy = nd.hiy, hz = nd.hiz;
-            const int4 cc = nd.child;
-            const int nc = nd.meta.x;
-            const float bx[4][6] = {{lx.x, ly.x, lz.x, hx.x, hy.x, hz.x}, {lx.y, ly.y, lz.y, hx.y, hy.y, hz.y},
-                                    {lx.z, ly.z, lz.z, hx.z, hy.z, hz.z}, {lx.w, ly.w, lz.w, hx.w, hy.w, hz.w}};
-            const int ch[4] = {cc.x, cc.y, cc.z, cc.w};
+            // all four boxes, without branches; children j >= nc are padding
+            float t0, t1, t2, t3;
+            const bool h0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, tb, t0);
+            const bool h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, tb, t1);
+            const bool h2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, tb, t2) && nc > 2;
+            const bool h3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, tb, t3) && nc > 3;
+            const bool f0 = cc.x < 0, f1 = cc.y < 0, f2 = cc.z < 0, f3 = cc.w < 0;   // leaves
             // key = entry distance of an internal child that is hit, +inf otherwise
-            float k0 = kInfT, k1 = kInfT, k2 = kInfT, k3 = kInfT;
-            int n0 = 0, n1 = 0, n2 = 0, n3 = 0;
-            uint32_t leaf_hits = 0;   // bit j: leaf child j is hit
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                float t;
-                if (j < nc && slab(bx[j], bx[j] + 3, r, tb, t)) {
-                    const uint32_t c = (uint32_t)ch[j];
-                    if (c & 0x80000000u) {
-                        leaf_hits |= 1u << j;
-                    } else {
-                        if (j == 0) { k0 = t; n0 = (int)c; }
-                        if (j == 1) { k1 = t; n1 = (int)c; }
-                        if (j == 2) { k2 = t; n2 = (int)c; }
-                        if (j == 3) { k3 = t; n3 = (int)c; }
-                    }
-                }
-            }
+            float k0 = (h0 && !f0) ? t0 : kInfT, k1 = (h1 && !f1) ? t1 : kInfT;
+            float k2 = (h2 && !f2) ? t2 : kInfT, k3 = (h3 && !f3) ? t3 : kInfT;
+            int n0 = cc.x, n1 = cc.y, n2 = cc.z, n3 = cc.w;
+            uint32_t leaf_hits = (h0 && f0 ? 1u : 0u) | (h1 && f1 ? 2u : 0u) | (h2 && f2 ? 4u : 0u) |
+                                 (h3 && f3 ? 8u : 0u);
             // leaves are tested right away (one call site keeps the code small);
             // internal children are visited near-first
             while (leaf_hits) {
