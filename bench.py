@@ -259,17 +259,21 @@ def gate_only(wl, frame_at, args, torch, Renderer, scenes):
     for i in range(args.warmup):
         g.render(frame_at(i))
     torch.cuda.synchronize()
+    g.set_kernel_timing(True)
     t0 = time.perf_counter()
     for k in range(args.steps):
         g.render(frame_at(args.warmup + k))
     torch.cuda.synchronize()
     fps = args.steps / (time.perf_counter() - t0)
+    kt = g.kernel_times()
+    g.set_kernel_timing(False)
     out = g.fetch()
     g.close()
     gw = dataclasses.replace(wl, sensor=sensor)
     res = equal_rmse(gw, frame_at(args.warmup + args.steps - 1), out, fps, args, torch, Renderer, scenes,
                      planes=("gate_image",))
     res["restir_frames_per_s"] = round(fps, 3)
+    res["kernel_ms_per_frame"] = {k: round(v["ms"] / args.steps, 3) for k, v in kt.items() if k != "work_items"}
     return res
 
 
@@ -302,11 +306,15 @@ def equal_rmse(wl, frame, restir_out, restir_fps, args, torch, Renderer, scenes,
         mse1_i.append(np.mean((o["pt_image"] - ref_i) ** 2))
         if ref_h is not None:
             mse1_h.append(np.mean((o["pt_hist"] - ref_h) ** 2))
+    # timed over consecutive frames of the sequence, so that plain PT pays the
+    # same per-frame geometry update as ReSTIR
     nrep = 20
+    seq = [dataclasses.replace(f, index=30_000_000 + i) for i, f in enumerate(wl.frames[:nrep])]
+    p.render(seq[-1])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(nrep):
-        p.render(dataclasses.replace(frame, index=30_000_000 + s))
+    for f in seq:
+        p.render(f)
     torch.cuda.synchronize()
     t_pt = (time.perf_counter() - t0) / nrep
     p.close()

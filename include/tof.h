@@ -207,10 +207,12 @@ enum {
     TOF_K_TEMPORAL_PREP,  /* reprojection + work list */
     TOF_K_TEMPORAL_FWD,   /* temporal forward shifts into the pixel */
     TOF_K_TEMPORAL_MIS,   /* temporal MIS shifts into the other domain */
+    TOF_K_TEMPORAL_VIS,   /* visibility rays queued by the temporal shifts */
     TOF_K_TEMPORAL_MERGE, /* temporal weights + reservoir merge */
     TOF_K_SPATIAL_PREP,   /* neighbour choice + work list */
     TOF_K_SPATIAL_FWD,    /* spatial forward shifts into the pixel */
     TOF_K_SPATIAL_MIS,    /* spatial MIS shifts into the neighbours */
+    TOF_K_SPATIAL_VIS,    /* visibility rays queued by the spatial shifts */
     TOF_K_SPATIAL_MERGE,  /* spatial weights + reservoir merge */
     TOF_K_SPLAT,
     TOF_K_COUNT

@@ -867,7 +867,7 @@ struct Oracle {
             double ph = in_plane(plane, len) ? C : 0.0;
             if (!(ph > 0.0)) return R;
             st.c[ST_RAYS]++;
-            if (!light_visible(dst_slot, dst_pix, ys.back())) return R;
+            if (!light_visible(dst_slot, dst_pix, ys.back())) return R;   // the only visibility ray
             R.y = x;
             R.y.len = len;
             R.y.pre_pdf = pdf_y;
@@ -959,26 +959,30 @@ struct Oracle {
         double ph = in_plane(plane, len) ? C : 0.0;
         if (!(ph > 0.0)) return R;
         // visibility of the moved edges; the suffix is re-tested when the two
-        // domains belong to different frames (the scene may have moved)
+        // domains belong to different frames (the scene may have moved).  All
+        // of the shift's visibility rays are traced (and counted), then the
+        // shift fails if any is blocked.
+        bool vis = true;
         st.c[ST_RAYS]++;
-        if (!visible_pts(FD, ykm1, pd)) return R;
+        vis = visible_pts(FD, ykm1, pd) && vis;
         if (p2light) {
             st.c[ST_RAYS]++;
-            if (!light_visible(dst_slot, dst_pix, pd)) return R;
+            vis = light_visible(dst_slot, dst_pix, pd) && vis;
         } else {
             st.c[ST_RAYS]++;
-            if (!visible_pts(FD, pd, p2_d)) return R;
+            vis = visible_pts(FD, pd, p2_d) && vis;
             if (src_slot != dst_slot) {
                 Vertex prev = p2_d;
                 for (const Vertex& v : sfx_d) {
                     st.c[ST_RAYS]++;
-                    if (!visible_pts(FD, prev, v)) return R;
+                    vis = visible_pts(FD, prev, v) && vis;
                     prev = v;
                 }
                 st.c[ST_RAYS]++;
-                if (!light_visible(dst_slot, dst_pix, prev)) return R;
+                vis = light_visible(dst_slot, dst_pix, prev) && vis;
             }
         }
+        if (!vis) return R;
         R.y = x;
         R.y.xkm1.obj = ykm1.obj;
         R.y.xkm1.xi[0] = ykm1.xi[0];

@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kTB) k_gbuffer(FrameArgs a, GBufOut out) {
             dir = G.cam_fwd;
         }
         Hit h;
-        if (traverse(a.S, G, o, dir, 3.0e38f, false, h, stk + threadIdx.x, kTB, st)) {
+        if (traverse(a.S, G, o, dir, 3.0e38f, false, kStackDepth, h, stk + threadIdx.x, kTB, st)) {
             Vtx v = hit_vertex(a.S, G, h, o, dir);
             out.obj[pix] = v.obj;
             out.xi0[pix] = v.xi0;
@@ -84,7 +84,7 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                                                  float2* __restrict__ direct) {
     __shared__ uint32_t stk[kStackDepth * kTB];
     Counters st = {};
-    Tracer tr{a.S, stk + threadIdx.x, kTB, st};
+    Tracer tr{a.S, stk + threadIdx.x, kTB, kStackDepth, st};
     const Sens& s = a.s;
     const SceneDev& S = a.S;
     int pix = blockIdx.x * kTB + threadIdx.x;
@@ -396,14 +396,15 @@ __device__ __forceinline__ int cand_src(int mode, const int* links, int P, int p
 
 TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
                        const uint2* __restrict__ items, const uint2* __restrict__ tasks,
-                       const uint32_t* __restrict__ count, float4* __restrict__ fwd, float4* __restrict__ shv) {
+                       const uint32_t* __restrict__ count, uint32_t t_begin, uint32_t t_end,
+                       float4* __restrict__ fwd, float4* __restrict__ shv, RayQueue q) {
     __shared__ uint32_t stk[kStackDepth * kTB];
     Counters st = {};
-    Tracer tr{a.S, stk + threadIdx.x, kTB, st};
+    Tracer tr{a.S, stk + threadIdx.x, kTB, kStackDepth, st};
     const Sens& s = a.s;
     const int P = s.P;
-    const uint32_t n = count[1];
-    for (uint32_t t = blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
+    const uint32_t n = min(count[1], t_end);
+    for (uint32_t t = t_begin + blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
         const uint2 task = tasks[t];
         const uint2 item = items[task.x];
         const int c = (int)task.y;
@@ -418,7 +419,8 @@ TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
         Rec y = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
         const float xphat = y.phat;
         const float mc = mode == 0 ? fminf(Bp.M[src], s.m_cap) : A.M[src];
-        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, mode == 0 ? 1 : 0, src, 0, pix, pl, 0.f);
+        // a blocked visibility ray zeroes phat_q (component x of fwd[t])
+        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, mode == 0 ? 1 : 0, src, 0, pix, pl, 0.f, q, 4u * t);
         if (!sh.ok) {
             fwd[t] = make_float4(0.f, 1.0f, 0.f, Wx);
             continue;
@@ -433,16 +435,17 @@ TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
 
 TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
                        const uint2* __restrict__ items, const uint2* __restrict__ tasks,
-                       const uint32_t* __restrict__ count, const float4* __restrict__ fwd,
-                       const float4* __restrict__ shv, float* __restrict__ term) {
+                       const uint32_t* __restrict__ count, uint64_t g_begin, uint64_t g_end,
+                       const float4* __restrict__ fwd, const float4* __restrict__ shv, float* __restrict__ term,
+                       RayQueue q) {
     __shared__ uint32_t stk[kStackDepth * kTB];
     Counters st = {};
-    Tracer tr{a.S, stk + threadIdx.x, kTB, st};
+    Tracer tr{a.S, stk + threadIdx.x, kTB, kStackDepth, st};
     const Sens& s = a.s;
     const int P = s.P;
     const uint32_t K = mode == 0 ? 1u : (uint32_t)s.k;
-    const uint64_t n = (uint64_t)count[1] * K;
-    for (uint64_t g = (uint64_t)blockIdx.x * kTB + threadIdx.x; g < n; g += (uint64_t)gridDim.x * kTB) {
+    const uint64_t n = min((uint64_t)count[1] * K, g_end);
+    for (uint64_t g = g_begin + (uint64_t)blockIdx.x * kTB + threadIdx.x; g < n; g += (uint64_t)gridDim.x * kTB) {
         const uint32_t t = (uint32_t)(g / K);
         const int l = (int)(g - (uint64_t)t * K);
         const uint2 task = tasks[t];
@@ -468,7 +471,8 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
                     y.pre_pdf = s1.w;
                     y.phat = fw.x;
                 }
-                const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, pl, 0.f);
+                const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, pl, 0.f, q,
+                                               (uint32_t)g);
                 if (sh.ok) {
                     const float ml = mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
                     out = ml * sh.phat * sh.J;
@@ -476,6 +480,28 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
             }
         }
         term[g] = out;
+    }
+    flush_counters(st, a.counters);
+}
+
+// ---------------------------------------------------------------------------
+// visibility of queued shift segments in the frame of `slot`, one ray per
+// lane; a blocked ray zeroes kill[owner] (the first one counts the shift as
+// failed).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kTB) k_vis(FrameArgs a, int slot, RayQueue q, float* __restrict__ kill) {
+    __shared__ uint32_t stk[kVisStackDepth * kTB];
+    Counters st = {};
+    Tracer tr{a.S, stk + threadIdx.x, kTB, kVisStackDepth, st};
+    const SlotDev& G = slot ? a.F.g[1] : a.F.g[0];
+    const uint32_t n = min(*q.count, q.cap);
+    for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
+        const float4 r0 = q.buf[2 * (size_t)i], r1 = q.buf[2 * (size_t)i + 1];
+        const Seg sg{mk(r0.x, r0.y, r0.z), mk(r1.x, r1.y, r1.z), r0.w};
+        if (!tr.visible(G, sg)) {
+            const float old = atomicExch(kill + __float_as_uint(r1.w), 0.f);
+            if (old != 0.f) st.c[ST_VISFAIL]++;
+        }
     }
     flush_counters(st, a.counters);
 }
@@ -617,17 +643,19 @@ void launch_items(const FrameArgs& a, int mode, const ResSet& first, const ResSe
                        second.mask, links, ncand, items, task0, tasks, count, out_mask);
 }
 void launch_fwd(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, float4* fwd,
-                float4* shv, hipStream_t st) {
-    hipLaunchKernelGGL(k_fwd, dim3(grid_for(max_tasks, kTB, 32768)), dim3(kTB), 0, st, a, mode, A, Bp, links, items,
-                       tasks, count, fwd, shv);
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
+                float4* fwd, float4* shv, const RayQueue& q, hipStream_t st) {
+    hipLaunchKernelGGL(k_fwd, dim3(grid_for(t_end - t_begin, kTB, 8192)), dim3(kTB), 0, st, a, mode, A, Bp, links,
+                       items, tasks, count, (uint32_t)t_begin, (uint32_t)t_end, fwd, shv, q);
 }
 void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, const float4* fwd,
-                const float4* shv, float* term, hipStream_t st) {
-    const size_t K = mode == 0 ? 1 : (size_t)a.s.k;
-    hipLaunchKernelGGL(k_mis, dim3(grid_for(max_tasks * K, kTB, 65536)), dim3(kTB), 0, st, a, mode, A, Bp, links,
-                       items, tasks, count, fwd, shv, term);
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t g_begin, size_t g_end,
+                const float4* fwd, const float4* shv, float* term, const RayQueue& q, hipStream_t st) {
+    hipLaunchKernelGGL(k_mis, dim3(grid_for(g_end - g_begin, kTB, 8192)), dim3(kTB), 0, st, a, mode, A, Bp, links,
+                       items, tasks, count, (uint64_t)g_begin, (uint64_t)g_end, fwd, shv, term, q);
+}
+void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, hipStream_t st) {
+    hipLaunchKernelGGL(k_vis, dim3(grid_for(q.cap, kTB, 4096)), dim3(kTB), 0, st, a, slot, q, kill);
 }
 void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                   const uint2* items, const uint32_t* task0, const uint32_t* count, size_t max_items,

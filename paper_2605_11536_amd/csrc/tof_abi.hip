@@ -87,6 +87,9 @@ struct tof_ctx {
     float4* fwd = nullptr;     // [max_tasks]: forward-shift terms per task
     float4* shv = nullptr;     // [2 * max_tasks]: fields rewritten by each forward shift
     float* term = nullptr;     // [max_tasks * max(k, 1)]: MIS terms per (task, neighbour)
+    float4* rays = nullptr;    // [2 * ray_cap]: queued visibility segments
+    uint32_t* ray_count = nullptr;
+    size_t ray_cap = 0;
     uint32_t* count = nullptr;
     size_t max_items = 0, max_tasks = 0;
     // misc
@@ -164,6 +167,13 @@ V3 hcross(V3 a, V3 b) { return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, 
 
 constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 
+// Queued visibility rays per chunk of shifts: enough for every shift of a pass
+// at once when that is at most 2^28 rays (8.6 GB), else the passes run in chunks.
+size_t ray_queue_cap(size_t max_tasks, size_t k) {
+    const size_t need = std::max(4 * max_tasks, 2 * max_tasks * std::max<size_t>(k, 1));
+    return std::min<size_t>(need, (size_t)1 << 28);
+}
+
 size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t P = (size_t)d.width * d.height;
     size_t B = (size_t)d.n_bins + (d.gate_enabled ? 1 : 0);
@@ -174,7 +184,9 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
            P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ +
            P * B * 4 /*first task per item*/ +
            P * B * ((size_t)std::max(d.spatial_k, 1) + 1) * (8 + 16 + 32 + 4 * (size_t)std::max(d.spatial_k, 1))
-           /*tasks, forward terms, shifted fields, MIS terms*/ + 64 * 1024;
+           /*tasks, forward terms, shifted fields, MIS terms*/ +
+           32 * ray_queue_cap(P * B * ((size_t)std::max(d.spatial_k, 1) + 1), (size_t)std::max(d.spatial_k, 1)) +
+           64 * 1024;
 }
 
 tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
@@ -468,6 +480,9 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->fwd, P * B * ncand));
     TOF_TRY(alloc_t(c, a, &c->shv, 2 * P * B * ncand));
     TOF_TRY(alloc_t(c, a, &c->term, P * B * ncand * (ncand - 1)));
+    c->ray_cap = ray_queue_cap(P * B * ncand, ncand - 1);
+    TOF_TRY(alloc_t(c, a, &c->rays, 2 * c->ray_cap));
+    TOF_TRY(alloc_t(c, a, &c->ray_count, 64));
     TOF_TRY(alloc_t(c, a, &c->count, 64));
     c->max_tasks = P * B * ncand;
     c->item_slots = 4 * 4096;
@@ -619,17 +634,59 @@ tof_status tof_get_stats(tof_ctx* c, tof_stats* out) {
     for (int k = 0; k < TOF_K_COUNT; ++k)
         for (int i = 0; i < kBank; ++i) h[i] += hb[k * kBank + i];
     out->shifts = h[ST_SHIFTS];
-    out->shifts_ok = h[ST_SHIFTS_OK];
+    out->shifts_ok = h[ST_SHIFTS_OK] - h[ST_VISFAIL];   // provisional successes minus blocked ones
     out->newton_attempts = h[ST_NEWTON_ATT];
     out->newton_converged = h[ST_NEWTON_CONV];
     out->newton_iters = h[ST_NEWTON_ITERS];
-    out->newton_paths_ok = h[ST_NEWTON_OK];
+    out->newton_paths_ok = h[ST_NEWTON_OK] - (c->s.shift_mode == 1 ? h[ST_VISFAIL] : 0);
     out->rays = h[ST_RAYS];
     out->frames = c->frames;
     out->bvh_overflow = h[ST_OVERFLOW];
     out->node_visits = h[ST_NODES];
     out->tri_tests = h[ST_TRIS];
     out->bad_records = h[ST_BADREC];
+    return TOF_OK;
+}
+
+// Forward shifts, then MIS shifts of a reuse pass (mode 0 temporal, 1
+// spatial), in chunks whose queued visibility rays fit the ray queue; each
+// chunk's rays are traced before the next chunk is queued.
+tof_status run_shifts(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
+                      hipStream_t st) {
+    const int kf = mode == 0 ? TOF_K_TEMPORAL_FWD : TOF_K_SPATIAL_FWD;
+    const int km = mode == 0 ? TOF_K_TEMPORAL_MIS : TOF_K_SPATIAL_MIS;
+    const int kv = mode == 0 ? TOF_K_TEMPORAL_VIS : TOF_K_SPATIAL_VIS;
+    const size_t K = mode == 0 ? 1 : (size_t)c->s.k;
+    const tofd::RayQueue q{c->rays, c->ray_count, (uint32_t)c->ray_cap};
+    // at most 4 segments per shift across frames (temporal), 2 within one frame
+    const size_t per_shift = mode == 0 ? 4 : 2;
+    const size_t chunk = std::max<size_t>(c->ray_cap / per_shift, 1);
+    auto vis = [&](int slot, float* kill) -> hipError_t {
+        hipError_t e = timer_mark(c, kv, st);
+        if (e != hipSuccess) return e;
+        a.counters = c->counters + (size_t)kv * kBank;
+        tofh::launch_vis(a, slot, q, kill, st);
+        return timer_mark(c, kv, st);
+    };
+    for (size_t b = 0; b < c->max_tasks; b += chunk) {
+        tofh::launch_fill_u32(c->ray_count, 0u, 1, st);
+        HIP_TRY(timer_mark(c, kf, st));
+        a.counters = c->counters + (size_t)kf * kBank;
+        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, std::min(b + chunk, c->max_tasks),
+                         c->fwd, c->shv, q, st);
+        HIP_TRY(timer_mark(c, kf, st));
+        HIP_TRY(vis(0, (float*)c->fwd));
+    }
+    const size_t lanes = c->max_tasks * K;
+    for (size_t b = 0; b < lanes; b += chunk) {
+        tofh::launch_fill_u32(c->ray_count, 0u, 1, st);
+        HIP_TRY(timer_mark(c, km, st));
+        a.counters = c->counters + (size_t)km * kBank;
+        tofh::launch_mis(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, std::min(b + chunk, lanes), c->fwd,
+                         c->shv, c->term, q, st);
+        HIP_TRY(timer_mark(c, km, st));
+        HIP_TRY(vis(mode == 0 ? 1 : 0, c->term));
+    }
     return TOF_OK;
 }
 
@@ -738,15 +795,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         tofh::launch_fill_u32(c->count, 0u, 2, st);
         tofh::launch_items(a, 0, can, pf, c->prev_pix, 2, c->items, c->task0, c->tasks, c->count, tmp.mask, st);
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_PREP, st));
-        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_FWD, st));
-        a.counters = c->counters + (size_t)TOF_K_TEMPORAL_FWD * kBank;
-        tofh::launch_fwd(a, 0, can, pf, c->prev_pix, c->items, c->tasks, c->count, c->max_tasks, c->fwd, c->shv, st);
-        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_FWD, st));
-        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MIS, st));
-        a.counters = c->counters + (size_t)TOF_K_TEMPORAL_MIS * kBank;
-        tofh::launch_mis(a, 0, can, pf, c->prev_pix, c->items, c->tasks, c->count, c->max_tasks, c->fwd, c->shv,
-                         c->term, st);
-        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MIS, st));
+        TOF_TRY(run_shifts(c, a, 0, can, pf, c->prev_pix, st));
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MERGE, st));
         a.counters = c->counters + (size_t)TOF_K_TEMPORAL_MERGE * kBank;
         tofh::launch_merge(a, 0, can, pf, c->prev_pix, c->items, c->task0, c->count, c->max_items, c->fwd, c->term,
@@ -775,15 +824,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         tofh::launch_fill_u32(c->count, 0u, 2, st);
         tofh::launch_items(a, 1, in, in, c->nb, c->s.k + 1, c->items, c->task0, c->tasks, c->count, out.mask, st);
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
-        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_FWD, st));
-        a.counters = c->counters + (size_t)TOF_K_SPATIAL_FWD * kBank;
-        tofh::launch_fwd(a, 1, in, in, c->nb, c->items, c->tasks, c->count, c->max_tasks, c->fwd, c->shv, st);
-        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_FWD, st));
-        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MIS, st));
-        a.counters = c->counters + (size_t)TOF_K_SPATIAL_MIS * kBank;
-        tofh::launch_mis(a, 1, in, in, c->nb, c->items, c->tasks, c->count, c->max_tasks, c->fwd, c->shv, c->term,
-                         st);
-        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MIS, st));
+        TOF_TRY(run_shifts(c, a, 1, in, in, c->nb, st));
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MERGE, st));
         a.counters = c->counters + (size_t)TOF_K_SPATIAL_MERGE * kBank;
         tofh::launch_merge(a, 1, in, in, c->nb, c->items, c->task0, c->count, c->max_items, c->fwd, c->term, c->shv, r,

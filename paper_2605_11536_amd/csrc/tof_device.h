@@ -16,7 +16,11 @@ constexpr float kPi = 3.14159265358979323846f;
 #ifndef TOF_STACK_DEPTH
 #define TOF_STACK_DEPTH 48
 #endif
-constexpr int kStackDepth = TOF_STACK_DEPTH;   // per-lane traversal stack entries (LDS)
+#ifndef TOF_VIS_STACK_DEPTH
+#define TOF_VIS_STACK_DEPTH 32
+#endif
+constexpr int kStackDepth = TOF_STACK_DEPTH;           // per-lane traversal stack entries (LDS)
+constexpr int kVisStackDepth = TOF_VIS_STACK_DEPTH;    // the same for the visibility pass
 constexpr int kMaxVerts = 4;         // scattering vertices per path
 constexpr int kMaxK = 8;             // spatial neighbours
 
@@ -423,17 +427,17 @@ struct Hit {
 };
 
 // per-lane event counters; one lane's share of a launch fits 32 bits
-constexpr int kNumCounters = 12;
+constexpr int kNumCounters = 13;
 struct Counters {
     uint32_t c[kNumCounters];
 };
 enum { ST_SHIFTS = 0, ST_SHIFTS_OK, ST_NEWTON_ATT, ST_NEWTON_CONV, ST_NEWTON_ITERS, ST_NEWTON_OK, ST_RAYS, ST_FRAMES,
-       ST_OVERFLOW, ST_NODES, ST_TRIS, ST_BADREC };
+       ST_OVERFLOW, ST_NODES, ST_TRIS, ST_BADREC, ST_VISFAIL };
 
 // Closest hit (any_hit = false; ties in t go to the smaller primitive id) or
 // any hit in (0, tmax) (any_hit = true).  `stack` points at this lane's LDS
 // column; consecutive entries are `stride` apart.
-__device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d, float tmax, bool any_hit, Hit& h,
+__device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d, float tmax, bool any_hit, int depth, Hit& h,
                                 uint32_t* stack, int stride, Counters& st) {
     RayPre r = ray_pre(o, d);
     float tb = tmax;
@@ -470,7 +474,7 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
         uint32_t node = 0;
         constexpr float kInfT = 3.0e38f;
         auto push = [&](int n) {
-            if (sp < kStackDepth) {
+            if (sp < depth) {
                 stack[sp * stride] = (uint32_t)n;
                 ++sp;
             } else {
@@ -614,20 +618,56 @@ struct Tracer {
     const SceneDev& S;
     uint32_t* stack;
     int stride;
+    int depth;          // stack entries per lane
     Counters& st;
 
     __device__ bool trace(const SlotDev& G, const Vtx& from, V3 dir, Vtx& out) {
         V3 o = offset_pt(S, from.p, from.n, dir);
         Hit h;
         st.c[ST_RAYS]++;
-        if (!traverse(S, G, o, dir, 3.0e38f, false, h, stack, stride, st)) return false;
+        if (!traverse(S, G, o, dir, 3.0e38f, false, depth, h, stack, stride, st)) return false;
         out = hit_vertex(S, G, h, o, dir);
         return true;
     }
     __device__ bool visible(const SlotDev& G, const Seg& sg) {
         Hit h;
         st.c[ST_RAYS]++;
-        return !traverse(S, G, sg.o, sg.d, sg.t, true, h, stack, stride, st);
+        return !traverse(S, G, sg.o, sg.d, sg.t, true, depth, h, stack, stride, st);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Deferred visibility.  A shift appends its visibility segments to a queue
+// (two float4 per ray: origin and length, direction and owner); a separate
+// pass traces them one ray per lane and zeroes kill[owner] when one is
+// blocked.  Appends are aggregated per wave: one atomic per wave and call.
+// ---------------------------------------------------------------------------
+struct RayQueue {
+    float4* buf;
+    uint32_t* count;
+    uint32_t cap;
+
+    // first of n consecutive slots for this lane
+    __device__ uint32_t alloc(uint32_t n) const {
+        const int lane = (int)__lane_id();
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {   // n < 8
+            const uint64_t m = __ballot((n >> b) & 1u);
+            pre += (uint32_t)__popcll(m & lt) << b;
+            tot += (uint32_t)__popcll(m) << b;
+        }
+        const uint64_t act = __ballot(1);
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(count, tot);
+        base = __shfl(base, leader, 64);
+        return base + pre;
+    }
+    __device__ void put(uint32_t i, const Seg& sg, uint32_t owner) const {
+        buf[2 * (size_t)i] = make_float4(sg.o.x, sg.o.y, sg.o.z, sg.t);
+        buf[2 * (size_t)i + 1] = make_float4(sg.d.x, sg.d.y, sg.d.z, __uint_as_float(owner));
     }
 };
 
@@ -1027,8 +1067,11 @@ __device__ __forceinline__ bool rec_valid(const SceneDev& S, const Rec& x) {
     return true;
 }
 
+// The returned ok is provisional: the shift's visibility segments are queued
+// under `owner` and a blocked one zeroes the owner's weight later.
 __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S, const Frames& F, Tracer& tr, const Rec& x,
-                                      int src_slot, int src_pix, int dst_slot, int dst_pix, int plane, float dl0) {
+                                      int src_slot, int src_pix, int dst_slot, int dst_pix, int plane, float dl0,
+                                      const RayQueue& q, uint32_t owner) {
     ShiftOut R;
     R.ok = false;
     Counters& st = tr.st;
@@ -1206,6 +1249,11 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
     if (!(ph > 0.f)) return R;
     // visibility last: only shifts that would contribute pay for rays
     const int nseg = replay_only ? 1 : 2 + ((!p2light && src_slot != dst_slot) ? (x.nsfx > 0 ? 2 : 1) : 0);
+    const uint32_t base = q.alloc((uint32_t)nseg);
+    if (base + (uint32_t)nseg > q.cap) {   // the launch sizes its chunk so that this never happens
+        st.c[ST_OVERFLOW]++;
+        return R;
+    }
     for (int e = 0; e < nseg; ++e) {
         Seg sg;
         if (replay_only) sg = seg_light(s, S, GD, dst_pix, cur);
@@ -1213,7 +1261,7 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
         else if (e == 1) sg = p2light ? seg_light(s, S, GD, dst_pix, pd) : seg_pts(S, pd, p2_d);
         else if (e == 2 && x.nsfx > 0) sg = seg_pts(S, p2_d, sfx_d);
         else sg = seg_light(s, S, GD, dst_pix, x.nsfx > 0 ? sfx_d : p2_d);
-        if (!tr.visible(GD, sg)) return R;
+        q.put(base + (uint32_t)e, sg, owner);
     }
     R.len = plen;
     R.pre_pdf = pdf_y;

@@ -46,14 +46,19 @@ void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, in
 void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const tofd::ResSet& second,
                   const int* links, int ncand, uint2* items, uint32_t* task0, uint2* tasks, uint32_t* count,
                   uint32_t* out_mask, hipStream_t st);
-// Shifts of a reuse pass: the forward shifts into q (fwd[t], shv[2t..2t+1]),
-// then the MIS shifts into every neighbour domain (term[t * K + l]).
+// Shifts of a reuse pass, over a chunk of their index range: the forward
+// shifts into q of tasks [t_begin, t_end) (fwd[t], shv[2t..2t+1]), then the MIS
+// shifts (task, neighbour) g in [g_begin, g_end) into every neighbour domain
+// (term[g]).  Each shift queues its visibility segments in q; launch_vis traces
+// them in the frame of `slot` and zeroes kill[owner] for blocked ones.  A
+// chunk must not queue more rays than q.cap (at most 4 per shift).
 void launch_fwd(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, float4* fwd,
-                float4* shv, hipStream_t st);
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
+                float4* fwd, float4* shv, const tofd::RayQueue& q, hipStream_t st);
 void launch_mis(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t max_tasks, const float4* fwd,
-                const float4* shv, float* term, hipStream_t st);
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t g_begin, size_t g_end,
+                const float4* fwd, const float4* shv, float* term, const tofd::RayQueue& q, hipStream_t st);
+void launch_vis(const FrameArgs& a, int slot, const tofd::RayQueue& q, float* kill, hipStream_t st);
 // Weighted reservoir merge of each item's candidates into `out`.
 void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
                   const uint2* items, const uint32_t* task0, const uint32_t* count, size_t max_items,

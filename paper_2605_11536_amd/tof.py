@@ -62,8 +62,8 @@ class tof_history_desc(C.Structure):
                 ("mask", C.POINTER(C.c_uint32))]
 
 
-KERNELS = ("bvh", "gbuffer", "initial", "temporal_prep", "temporal_fwd", "temporal_mis", "temporal_merge",
-           "spatial_prep", "spatial_fwd", "spatial_mis", "spatial_merge", "splat")
+KERNELS = ("bvh", "gbuffer", "initial", "temporal_prep", "temporal_fwd", "temporal_mis", "temporal_vis",
+           "temporal_merge", "spatial_prep", "spatial_fwd", "spatial_mis", "spatial_vis", "spatial_merge", "splat")
 
 
 WORK_FIELDS = ("rays", "node_visits", "tri_tests", "shifts", "newton_attempts", "newton_iters")
