@@ -494,9 +494,13 @@ __global__ void __launch_bounds__(kTB) k_vis(FrameArgs a, int slot, RayQueue q, 
     Counters st = {};
     Tracer tr{a.S, stk + threadIdx.x, kTB, kVisStackDepth, st};
     const SlotDev& G = slot ? a.F.g[1] : a.F.g[0];
-    const uint32_t n = min(*q.count, q.cap);
-    for (uint32_t i = blockIdx.x * kTB + threadIdx.x; i < n; i += gridDim.x * kTB) {
-        const float4 r0 = q.buf[2 * (size_t)i], r1 = q.buf[2 * (size_t)i + 1];
+    // blocks are dealt to the sub-queues round robin
+    const uint32_t sub = blockIdx.x % kRaySubQueues;
+    const uint32_t nb = gridDim.x / kRaySubQueues;
+    const uint32_t n = min(q.count[sub * kCounterStride], q.sub_cap);
+    const float4* buf = q.buf + 2 * (size_t)sub * q.sub_cap;
+    for (uint32_t i = (blockIdx.x / kRaySubQueues) * kTB + threadIdx.x; i < n; i += nb * kTB) {
+        const float4 r0 = buf[2 * (size_t)i], r1 = buf[2 * (size_t)i + 1];
         const Seg sg{mk(r0.x, r0.y, r0.z), mk(r1.x, r1.y, r1.z), r0.w};
         if (!tr.visible(G, sg)) {
             const float old = atomicExch(kill + __float_as_uint(r1.w), 0.f);
@@ -645,17 +649,17 @@ void launch_items(const FrameArgs& a, int mode, const ResSet& first, const ResSe
 void launch_fwd(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
                 float4* fwd, float4* shv, const RayQueue& q, hipStream_t st) {
-    hipLaunchKernelGGL(k_fwd, dim3(grid_for(t_end - t_begin, kTB, 8192)), dim3(kTB), 0, st, a, mode, A, Bp, links,
+    hipLaunchKernelGGL(k_fwd, dim3(kShiftGrid), dim3(kTB), 0, st, a, mode, A, Bp, links,
                        items, tasks, count, (uint32_t)t_begin, (uint32_t)t_end, fwd, shv, q);
 }
 void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t g_begin, size_t g_end,
                 const float4* fwd, const float4* shv, float* term, const RayQueue& q, hipStream_t st) {
-    hipLaunchKernelGGL(k_mis, dim3(grid_for(g_end - g_begin, kTB, 8192)), dim3(kTB), 0, st, a, mode, A, Bp, links,
+    hipLaunchKernelGGL(k_mis, dim3(kShiftGrid), dim3(kTB), 0, st, a, mode, A, Bp, links,
                        items, tasks, count, (uint64_t)g_begin, (uint64_t)g_end, fwd, shv, term, q);
 }
 void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, hipStream_t st) {
-    hipLaunchKernelGGL(k_vis, dim3(grid_for(q.cap, kTB, 4096)), dim3(kTB), 0, st, a, slot, q, kill);
+    hipLaunchKernelGGL(k_vis, dim3(kVisGrid), dim3(kTB), 0, st, a, slot, q, kill);
 }
 void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                   const uint2* items, const uint32_t* task0, const uint32_t* count, size_t max_items,

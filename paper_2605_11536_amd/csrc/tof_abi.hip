@@ -167,10 +167,15 @@ V3 hcross(V3 a, V3 b) { return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, 
 
 constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 
-// Queued visibility rays per chunk of shifts: enough for every shift of a pass
-// at once when that is at most 2^28 rays (8.6 GB), else the passes run in chunks.
+// Queued visibility rays: enough for every shift of a pass at once when that
+// is at most 2^28 rays (8.6 GB), else the passes run in chunks.  Chunks are
+// multiples of tofh::kChunkQuantum lanes; a shift queues at most 4 rays
+// across frames (temporal) and 2 within one frame (spatial).
+size_t round_up(size_t x, size_t q) { return (x + q - 1) / q * q; }
 size_t ray_queue_cap(size_t max_tasks, size_t k) {
-    const size_t need = std::max(4 * max_tasks, 2 * max_tasks * std::max<size_t>(k, 1));
+    const size_t Q = tofh::kChunkQuantum;
+    const size_t need = std::max(4 * round_up(std::max<size_t>(max_tasks, 1), Q),
+                                 2 * round_up(std::max<size_t>(max_tasks * std::max<size_t>(k, 1), 1), Q));
     return std::min<size_t>(need, (size_t)1 << 28);
 }
 
@@ -482,7 +487,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->term, P * B * ncand * (ncand - 1)));
     c->ray_cap = ray_queue_cap(P * B * ncand, ncand - 1);
     TOF_TRY(alloc_t(c, a, &c->rays, 2 * c->ray_cap));
-    TOF_TRY(alloc_t(c, a, &c->ray_count, 64));
+    TOF_TRY(alloc_t(c, a, &c->ray_count, (size_t)tofd::kRaySubQueues * tofd::kCounterStride));
     TOF_TRY(alloc_t(c, a, &c->count, 64));
     c->max_tasks = P * B * ncand;
     c->item_slots = 4 * 4096;
@@ -657,35 +662,42 @@ tof_status run_shifts(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A,
     const int km = mode == 0 ? TOF_K_TEMPORAL_MIS : TOF_K_SPATIAL_MIS;
     const int kv = mode == 0 ? TOF_K_TEMPORAL_VIS : TOF_K_SPATIAL_VIS;
     const size_t K = mode == 0 ? 1 : (size_t)c->s.k;
-    const tofd::RayQueue q{c->rays, c->ray_count, (uint32_t)c->ray_cap};
     // at most 4 segments per shift across frames (temporal), 2 within one frame
     const size_t per_shift = mode == 0 ? 4 : 2;
-    const size_t chunk = std::max<size_t>(c->ray_cap / per_shift, 1);
-    auto vis = [&](int slot, float* kill) -> hipError_t {
+    const size_t Q = tofh::kChunkQuantum;
+    const size_t chunk_max = c->ray_cap / per_shift / Q * Q;   // >= Q by the allocation
+    const size_t ncounters = (size_t)tofd::kRaySubQueues * tofd::kCounterStride;
+    auto queue_for = [&](size_t chunk) {
+        return tofd::RayQueue{c->rays, c->ray_count, (uint32_t)(per_shift * chunk / tofd::kRaySubQueues)};
+    };
+    auto vis = [&](int slot, const tofd::RayQueue& q, float* kill) -> hipError_t {
         hipError_t e = timer_mark(c, kv, st);
         if (e != hipSuccess) return e;
         a.counters = c->counters + (size_t)kv * kBank;
         tofh::launch_vis(a, slot, q, kill, st);
         return timer_mark(c, kv, st);
     };
-    for (size_t b = 0; b < c->max_tasks; b += chunk) {
-        tofh::launch_fill_u32(c->ray_count, 0u, 1, st);
+    const size_t chunk_f = std::min(round_up(std::max<size_t>(c->max_tasks, 1), Q), chunk_max);
+    const tofd::RayQueue qf = queue_for(chunk_f);
+    for (size_t b = 0; b < c->max_tasks; b += chunk_f) {
+        tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
         HIP_TRY(timer_mark(c, kf, st));
         a.counters = c->counters + (size_t)kf * kBank;
-        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, std::min(b + chunk, c->max_tasks),
-                         c->fwd, c->shv, q, st);
+        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + chunk_f, c->fwd, c->shv, qf, st);
         HIP_TRY(timer_mark(c, kf, st));
-        HIP_TRY(vis(0, (float*)c->fwd));
+        HIP_TRY(vis(0, qf, (float*)c->fwd));
     }
     const size_t lanes = c->max_tasks * K;
-    for (size_t b = 0; b < lanes; b += chunk) {
-        tofh::launch_fill_u32(c->ray_count, 0u, 1, st);
+    const size_t chunk_m = std::min(round_up(std::max<size_t>(lanes, 1), Q), chunk_max);
+    const tofd::RayQueue qm = queue_for(chunk_m);
+    for (size_t b = 0; b < lanes; b += chunk_m) {
+        tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
         HIP_TRY(timer_mark(c, km, st));
         a.counters = c->counters + (size_t)km * kBank;
-        tofh::launch_mis(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, std::min(b + chunk, lanes), c->fwd,
-                         c->shv, c->term, q, st);
+        tofh::launch_mis(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + chunk_m, c->fwd, c->shv, c->term,
+                         qm, st);
         HIP_TRY(timer_mark(c, km, st));
-        HIP_TRY(vis(mode == 0 ? 1 : 0, c->term));
+        HIP_TRY(vis(mode == 0 ? 1 : 0, qm, c->term));
     }
     return TOF_OK;
 }

@@ -640,30 +640,42 @@ struct Tracer {
 // Deferred visibility.  A shift appends its visibility segments to a queue
 // (two float4 per ray: origin and length, direction and owner); a separate
 // pass traces them one ray per lane and zeroes kill[owner] when one is
-// blocked.  Appends are aggregated per wave: one atomic per wave and call.
+// blocked.  The queue is split into kRaySubQueues parts, each with its own
+// counter on its own cache line, chosen by block index: appends take one
+// atomic per wave on one of 64 addresses (atomics on a single address
+// serialize in L2).  Within a wave's allocation, segment e of every lane is
+// stored contiguously, so a wave of the visibility pass traces rays of one
+// kind from neighbouring shifts.
 // ---------------------------------------------------------------------------
-struct RayQueue {
-    float4* buf;
-    uint32_t* count;
-    uint32_t cap;
+constexpr int kRaySubQueues = 64;
+constexpr int kCounterStride = 32;   // u32 words between counters (128 B)
 
-    // first of n consecutive slots for this lane
-    __device__ uint32_t alloc(uint32_t n) const {
+struct RayQueue {
+    float4* buf;        // [kRaySubQueues][sub_cap] rays, 2 float4 each
+    uint32_t* count;    // count[s * kCounterStride]: rays in sub-queue s
+    uint32_t sub_cap;
+
+    // slots for this lane's n segments: slot of segment e = out + e-major offset
+    __device__ bool alloc(uint32_t n, uint32_t slot[4]) const {
         const int lane = (int)__lane_id();
         const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-        uint32_t pre = 0, tot = 0;
+        uint32_t off = 0, rank[4];
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {   // n < 8
-            const uint64_t m = __ballot((n >> b) & 1u);
-            pre += (uint32_t)__popcll(m & lt) << b;
-            tot += (uint32_t)__popcll(m) << b;
+        for (int e = 0; e < 4; ++e) {
+            const uint64_t m = __ballot(n > (uint32_t)e);
+            rank[e] = off + (uint32_t)__popcll(m & lt);
+            off += (uint32_t)__popcll(m);
         }
         const uint64_t act = __ballot(1);
         const int leader = __ffsll((unsigned long long)act) - 1;
+        const uint32_t sub = blockIdx.x % kRaySubQueues;
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(count, tot);
+        if (lane == leader) base = atomicAdd(count + sub * kCounterStride, off);
         base = __shfl(base, leader, 64);
-        return base + pre;
+        bool fits = base + off <= sub_cap;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) slot[e] = sub * sub_cap + base + rank[e];
+        return fits;
     }
     __device__ void put(uint32_t i, const Seg& sg, uint32_t owner) const {
         buf[2 * (size_t)i] = make_float4(sg.o.x, sg.o.y, sg.o.z, sg.t);
@@ -1249,8 +1261,8 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
     if (!(ph > 0.f)) return R;
     // visibility last: only shifts that would contribute pay for rays
     const int nseg = replay_only ? 1 : 2 + ((!p2light && src_slot != dst_slot) ? (x.nsfx > 0 ? 2 : 1) : 0);
-    const uint32_t base = q.alloc((uint32_t)nseg);
-    if (base + (uint32_t)nseg > q.cap) {   // the launch sizes its chunk so that this never happens
+    uint32_t slot_e[4];
+    if (!q.alloc((uint32_t)nseg, slot_e)) {   // the launch sizes its chunk so that this never happens
         st.c[ST_OVERFLOW]++;
         return R;
     }
@@ -1261,7 +1273,7 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
         else if (e == 1) sg = p2light ? seg_light(s, S, GD, dst_pix, pd) : seg_pts(S, pd, p2_d);
         else if (e == 2 && x.nsfx > 0) sg = seg_pts(S, p2_d, sfx_d);
         else sg = seg_light(s, S, GD, dst_pix, x.nsfx > 0 ? sfx_d : p2_d);
-        q.put(base + (uint32_t)e, sg, owner);
+        q.put(e == 0 ? slot_e[0] : (e == 1 ? slot_e[1] : (e == 2 ? slot_e[2] : slot_e[3])), sg, owner);
     }
     R.len = plen;
     R.pre_pdf = pdf_y;

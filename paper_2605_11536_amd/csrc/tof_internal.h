@@ -46,6 +46,14 @@ void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, in
 void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const tofd::ResSet& second,
                   const int* links, int ncand, uint2* items, uint32_t* task0, uint2* tasks, uint32_t* count,
                   uint32_t* out_mask, hipStream_t st);
+// Grids of the shift and visibility launches.  The shift kernels always run
+// kShiftGrid blocks of 128 lanes in a grid-stride loop; with chunks that are
+// multiples of kShiftGrid * 128 lanes every ray sub-queue receives the rays of
+// exactly chunk / kRaySubQueues lanes.
+constexpr unsigned kShiftGrid = 8192;
+constexpr unsigned kVisGrid = 8192;
+constexpr size_t kChunkQuantum = (size_t)kShiftGrid * 128;
+
 // Shifts of a reuse pass, over a chunk of their index range: the forward
 // shifts into q of tasks [t_begin, t_end) (fwd[t], shv[2t..2t+1]), then the MIS
 // shifts (task, neighbour) g in [g_begin, g_end) into every neighbour domain
