@@ -527,11 +527,19 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
                     nb = nt;
                 }
             };
-            cswap(k0, n0, k1, n1);
-            cswap(k2, n2, k3, n3);
-            cswap(k0, n0, k2, n2);
-            cswap(k1, n1, k3, n3);
-            cswap(k1, n1, k2, n2);
+            if (any_hit) {
+                // any hit: order does not matter for a ray that is not blocked;
+                // only bring the nearest to the front
+                cswap(k0, n0, k1, n1);
+                cswap(k2, n2, k3, n3);
+                cswap(k0, n0, k2, n2);
+            } else {
+                cswap(k0, n0, k1, n1);
+                cswap(k2, n2, k3, n3);
+                cswap(k0, n0, k2, n2);
+                cswap(k1, n1, k3, n3);
+                cswap(k1, n1, k2, n2);
+            }
             if (!(k0 < kInfT)) {
                 if (sp == 0) break;
                 --sp;
