@@ -42,6 +42,35 @@ SPLAT_BYTES = 4 + 4 + 4 + 0.125   # per (pixel, plane): PT deposit read, two his
 REC_HEAD_BYTES = 8      # per non-empty (pixel, plane): W and phat
 
 
+def sources_digest():
+    """sha256 over the HIP sources and the C header: identifies the kernels
+    that a stored counter measurement belongs to."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2605_11536_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "tof.h"), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(group, steps, warmup):
+    """HBM bytes per launch of a kernel group from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy's reading),
+    or None when the kernels changed since it was taken or it covers another
+    group or frame window."""
+    path = os.path.join(ROOT, "profiles", "traffic_glossy_dynamic_512.json")
+    if not os.path.exists(path):
+        return None
+    t = json.load(open(path))
+    if (t.get("sources_sha256") != sources_digest() or t.get("group") != group
+            or t.get("steps") != steps or t.get("warmup") != warmup):
+        return None
+    return t["hbm_bytes_per_launch"]
+
+
 def valu_flops(w):
     return (F_NODE * w["node_visits"] + F_TRI * w["tri_tests"] + F_NEWTON_ITER * w["newton_iters"]
             + F_NEWTON_SETUP * w["newton_attempts"] + F_SHIFT * w["shifts"])
@@ -213,10 +242,12 @@ def main():
         per_launch = valu_flops(w) / max(kl[dom], 1)
         ach = per_launch / avg_s / 1e12
         kname = {"spatial_mis": "k_mis", "temporal_mis": "k_mis", "spatial_fwd": "k_fwd", "temporal_fwd": "k_fwd",
+                 "spatial_vis": "k_vis", "temporal_vis": "k_vis",
                  "spatial_merge": "k_merge", "temporal_merge": "k_merge", "initial": "k_initial",
                  "gbuffer": "k_gbuffer"}.get(dom, dom)
         result["roofline"] = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                              "frac": round(ach / FP32_PEAK_TFLOPS, 5), "traffic": None,
+                              "frac": round(ach / FP32_PEAK_TFLOPS, 5),
+                              "traffic": measured_traffic(dom, args.steps, args.warmup),
                               "kernel": f"{kname} ({dom})", "avg_launch_ms": round(avg_s * 1e3, 4),
                               "flops_per_launch": per_launch}
     # the streaming passes against HBM: the splat over every (pixel, plane)

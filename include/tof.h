@@ -146,7 +146,10 @@ tof_status tof_scene_upload(tof_ctx* ctx, const tof_scene_desc* scene);
 
 /* Set sensor and time-domain settings and (re)allocate per-pixel state after
  * checking the footprint against the budget.  Any change drops the temporal
- * history (reservoirs are reset). */
+ * history (reservoirs are reset), except a move of gate_center alone: that
+ * keeps the history, and the next frame's temporal reuse shifts the previous
+ * frame's paths by the move, Delta l = new centre - old centre (Sec. 4.1,
+ * time-gate shifting).  Bins never move. */
 tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
 
 /* Render one frame asynchronously on `stream`: BVH build for the frame's

@@ -133,6 +133,7 @@ struct BNode { double lo[3], hi[3]; int left, right, first, count; };
 struct FrameGeom {
     bool valid = false;
     int index = 0;
+    double gate_center = 0.0;    // the time gate's centre when the frame was rendered
     std::vector<double> xf;      // per object: 3x4 row-major
     std::vector<V3> wv;          // world vertices
     std::vector<BNode> nodes;
@@ -281,6 +282,7 @@ struct Oracle {
     void load_frame(FrameGeom& F, const orc_frame* fr) {
         F.valid = true;
         F.index = fr->index;
+        F.gate_center = s.gate_center;
         int O = (int)objs.size();
         F.xf.assign(12 * O, 0.0);
         for (int k = 0; k < 12 * O; ++k) F.xf[k] = (double)fr->xforms[k];
@@ -654,14 +656,20 @@ struct Oracle {
     // -------------------------------------------------------------------
     // time gate / bins (Sec. 3.1 W_tau; half-open boxes)
     // -------------------------------------------------------------------
-    double plane_lo(int pl) const {
-        return pl < s.n_bins ? s.bin_t0 + pl * s.bin_width : s.gate_center - 0.5 * s.gate_width;
+    // the gate plane of a frame slot uses the gate centre of that frame
+    double plane_lo(int pl, int slot = 0) const {
+        return pl < s.n_bins ? s.bin_t0 + pl * s.bin_width : fg[slot].gate_center - 0.5 * s.gate_width;
     }
-    double plane_hi(int pl) const {
-        return pl < s.n_bins ? s.bin_t0 + (pl + 1) * s.bin_width : s.gate_center + 0.5 * s.gate_width;
+    double plane_hi(int pl, int slot = 0) const {
+        return pl < s.n_bins ? s.bin_t0 + (pl + 1) * s.bin_width : fg[slot].gate_center + 0.5 * s.gate_width;
     }
     double plane_width(int pl) const { return pl < s.n_bins ? s.bin_width : s.gate_width; }
-    bool in_plane(int pl, double len) const { return len >= plane_lo(pl) && len < plane_hi(pl); }
+    bool in_plane(int pl, double len, int slot = 0) const {
+        return len >= plane_lo(pl, slot) && len < plane_hi(pl, slot);
+    }
+    // Delta l of a temporal shift from the previous frame into the current one
+    // (Sec. 4.1, time-gate shifting): the gate's move; bins do not move
+    double gate_shift(int pl) const { return pl < s.n_bins ? 0.0 : fg[0].gate_center - fg[1].gate_center; }
     int bin_of(double len) const {
         if (s.n_bins <= 0) return -1;
         double f = std::floor((len - s.bin_t0) / s.bin_width);
@@ -864,7 +872,7 @@ struct Oracle {
             if (!(C > 0.0)) return R;
             double J = x.pre_pdf / pdf_y;
             if (!(J >= 1.0 / s.j_max && J <= s.j_max)) return R;
-            double ph = in_plane(plane, len) ? C : 0.0;
+            double ph = in_plane(plane, len, dst_slot) ? C : 0.0;
             if (!(ph > 0.0)) return R;
             st.c[ST_RAYS]++;
             if (!light_visible(dst_slot, dst_pix, ys.back())) return R;   // the only visibility ray
@@ -956,7 +964,7 @@ struct Oracle {
             J *= g2d / g2s;
         }
         if (!(J >= 1.0 / s.j_max && J <= s.j_max)) return R;
-        double ph = in_plane(plane, len) ? C : 0.0;
+        double ph = in_plane(plane, len, dst_slot) ? C : 0.0;
         if (!(ph > 0.0)) return R;
         // visibility of the moved edges; the suffix is re-tested when the two
         // domains belong to different frames (the scene may have moved).  All
@@ -1201,7 +1209,7 @@ struct Oracle {
                     double ph = xr.y.phat;
                     double den = mc * ph;
                     if (qp >= 0) {
-                        ShiftOut sh = shift(xr.y, 0, pix, 1, qp, pl, 0.0, st);
+                        ShiftOut sh = shift(xr.y, 0, pix, 1, qp, pl, -gate_shift(pl), st);
                         if (sh.ok) den += mp * sh.phat * sh.J;
                     }
                     double w = (mc * ph / den) * ph * xr.W;
@@ -1212,7 +1220,7 @@ struct Oracle {
                     auto itp = fin_prev[qp].find(pl);
                     if (itp != fin_prev[qp].end()) {
                         const Res& xr = itp->second;
-                        ShiftOut sh = shift(xr.y, 1, qp, 0, pix, pl, 0.0, st);
+                        ShiftOut sh = shift(xr.y, 1, qp, 0, pix, pl, gate_shift(pl), st);
                         if (sh.ok) {
                             double a = mp * xr.y.phat / sh.J;
                             double m = a / (a + mc * sh.phat);
@@ -1449,6 +1457,11 @@ void orc_reset(void* ctx) {
     o->prev_valid = false;
     o->fin_prev.clear();
     o->M_prev.clear();
+}
+
+void orc_set_gate_center(void* ctx, double center) {
+    // the history is kept: the next temporal pass shifts it by the gate's move
+    ((Oracle*)ctx)->s.gate_center = center;
 }
 
 int orc_render_frame(void* ctx, const orc_frame* frame, double* out_image, double* out_hist, double* out_pt_image,

@@ -64,6 +64,9 @@ typedef struct {
 void* orc_create(const orc_scene* scene, const orc_sensor* sensor, int num_threads);
 void orc_destroy(void* ctx);
 void orc_reset(void* ctx);
+/* Move the time gate's centre, keeping the reservoir history: the next
+ * temporal reuse shifts previous-frame paths by the move (Sec. 4.1). */
+void orc_set_gate_center(void* ctx, double center);
 
 /* One full frame.  Outputs are FP64, plane-major [B][H][W]; any may be NULL.
  * gate image = gate plane / gate width; histogram bins / bin width.

@@ -61,6 +61,7 @@ def lib():
         _lib.orc_create.argtypes = [C.POINTER(OrcScene), C.POINTER(OrcSensor), C.c_int]
         _lib.orc_destroy.argtypes = [C.c_void_p]
         _lib.orc_reset.argtypes = [C.c_void_p]
+        _lib.orc_set_gate_center.argtypes = [C.c_void_p, C.c_double]
         _lib.orc_render_frame.argtypes = [C.c_void_p, C.POINTER(OrcFrame), _f64p, _f64p, _f64p, _f64p]
         _lib.orc_get_stats.argtypes = [C.c_void_p, _u64p]
         _lib.orc_philox4x64.argtypes = [_u64p, _u64p, _u64p]
@@ -168,6 +169,13 @@ class Oracle:
 
     def reset(self):
         lib().orc_reset(self.h)
+
+    def set_gate_center(self, center: float):
+        """Move the gate, keeping the history (Sec. 4.1 time-gate shifting)."""
+        import dataclasses
+        c = float(np.float32(center))
+        self.sensor = dataclasses.replace(self.sensor, gate_center=c)
+        lib().orc_set_gate_center(self.h, c)
 
     def render(self, frame):
         s = self.sensor

@@ -420,7 +420,8 @@ TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
         const float xphat = y.phat;
         const float mc = mode == 0 ? fminf(Bp.M[src], s.m_cap) : A.M[src];
         // a blocked visibility ray zeroes phat_q (component x of fwd[t])
-        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, mode == 0 ? 1 : 0, src, 0, pix, pl, 0.f, q, 4u * t);
+        const float dl = mode == 0 ? gate_shift(s, a.F.g[0], a.F.g[1], pl) : 0.f;
+        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, mode == 0 ? 1 : 0, src, 0, pix, pl, dl, q, 4u * t);
         if (!sh.ok) {
             fwd[t] = make_float4(0.f, 1.0f, 0.f, Wx);
             continue;
@@ -471,7 +472,8 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
                     y.pre_pdf = s1.w;
                     y.phat = fw.x;
                 }
-                const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, pl, 0.f, q,
+                const float dl = mode == 0 ? -gate_shift(s, a.F.g[0], a.F.g[1], pl) : 0.f;
+                const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, pl, dl, q,
                                                (uint32_t)g);
                 if (sh.ok) {
                     const float ml = mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];

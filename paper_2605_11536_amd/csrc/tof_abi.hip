@@ -38,6 +38,7 @@ struct GeomBuf {
 struct SlotHost {
     bool valid = false;
     int geom = 0;
+    float gate_c = 0.f;   // gate centre the frame was rendered with
     V3 cam_pos, cam_fwd, cam_right, cam_up;
     float tan_half = 0, aspect = 1, ohx = 0, ohy = 0;
     V3 light_pos;
@@ -247,6 +248,7 @@ SlotDev slot_dev(const tof_ctx* c, int i) {
     d.ohx = h.ohx;
     d.ohy = h.ohy;
     d.light_pos = h.light_pos;
+    d.gate_c = h.gate_c;
     d.gb_obj = h.gb_obj;
     d.gb_xi0 = h.gb_xi0;
     d.gb_xi1 = h.gb_xi1;
@@ -455,6 +457,17 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
               d->debug_stage >= TOF_STAGE_CANONICAL && d->debug_stage <= TOF_STAGE_FINAL &&
               std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
     if (!ok) return TOF_ERR_INVALID_ARG;
+    if (c->has_sensor) {
+        // a move of the gate alone keeps the history: the next temporal reuse
+        // shifts previous-frame paths by the move (Sec. 4.1)
+        tof_sensor_desc moved = c->sd;
+        moved.gate_center = d->gate_center;
+        if (std::memcmp(&moved, d, sizeof(moved)) == 0) {
+            c->sd.gate_center = d->gate_center;
+            c->s.gate_c = d->gate_center;
+            return TOF_OK;
+        }
+    }
     if (c->budget && c->scene_mem.bytes + sensor_footprint(*d) > c->budget) return TOF_ERR_OUT_OF_MEMORY;
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
@@ -758,6 +771,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     cur.aspect = (float)((double)c->sd.full_width / (double)c->sd.full_height);
     cur.ohx = fr->ortho_half[0];
     cur.ohy = fr->ortho_half[1];
+    cur.gate_c = c->s.gate_c;
     cur.light_pos = hv(fr->light_pos[0], fr->light_pos[1], fr->light_pos[2]);
 
     tofh::FrameArgs a;

@@ -91,6 +91,7 @@ struct SlotDev {
     V3 cam_pos, cam_fwd, cam_right, cam_up;
     float tan_half, aspect, ohx, ohy;
     V3 light_pos;
+    float gate_c;           // the time gate's centre when the frame was rendered
     // G-buffer (obj = -1: no primary hit)
     const int* gb_obj;
     const float* gb_xi0;
@@ -781,6 +782,16 @@ __device__ __forceinline__ float plane_width(const Sens& s, int pl) { return pl 
 __device__ __forceinline__ bool in_plane(const Sens& s, int pl, float l) {
     return l >= plane_lo(s, pl) && l < plane_hi(s, pl);
 }
+// the same, with the gate plane of the frame held in slot G
+__device__ __forceinline__ bool in_plane_at(const Sens& s, const SlotDev& G, int pl, float l) {
+    if (pl < s.n_bins) return in_plane(s, pl, l);
+    return l >= G.gate_c - 0.5f * s.gate_w && l < G.gate_c + 0.5f * s.gate_w;
+}
+// Delta l of a temporal shift from the previous frame into the current one
+// (Sec. 4.1, time-gate shifting): the gate's move; bins do not move
+__device__ __forceinline__ float gate_shift(const Sens& s, const SlotDev& cur, const SlotDev& prev, int pl) {
+    return pl < s.n_bins ? 0.f : cur.gate_c - prev.gate_c;
+}
 __device__ __forceinline__ int bin_of(const Sens& s, float l) {
     if (s.n_bins <= 0) return -1;
     float f = floorf((l - s.t0) / s.bw);
@@ -1265,7 +1276,7 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
     if (!(C > 0.f)) return R;
     const float Jf = (float)J;
     if (!(Jf >= 1.0f / s.j_max && Jf <= s.j_max)) return R;
-    const float ph = in_plane(s, plane, plen) ? C : 0.f;
+    const float ph = in_plane_at(s, GD, plane, plen) ? C : 0.f;
     if (!(ph > 0.f)) return R;
     // visibility last: only shifts that would contribute pay for rays
     const int nseg = replay_only ? 1 : 2 + ((!p2light && src_slot != dst_slot) ? (x.nsfx > 0 ? 2 : 1) : 0);

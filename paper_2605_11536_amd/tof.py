@@ -297,6 +297,13 @@ class Renderer:
     def reset(self):
         tof_reservoirs_reset(self.h)
 
+    def set_gate_center(self, center: float):
+        """Move the gate, keeping the history (tof_sensor_set with only the
+        centre changed)."""
+        import dataclasses
+        self.sensor = dataclasses.replace(self.sensor, gate_center=float(center))
+        tof_sensor_set(self.h, self.sensor)
+
     def set_kernel_timing(self, enabled: bool):
         tof_set_kernel_timing(self.h, enabled)
 

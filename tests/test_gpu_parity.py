@@ -48,7 +48,7 @@ def _assert_parity(g, o, what):
     assert abs(z) <= 3.0, f"{what}: discrepant entries biased (z = {z})"
 
 
-def _run_pair(w, nframes=None, check=("image", "pt_image", "hist", "pt_hist"), inject=True):
+def _run_pair(w, nframes=None, check=("image", "pt_image", "hist", "pt_hist"), inject=True, gate_step=0.0):
     from oracle.oracle import Oracle
     from paper_2605_11536_amd.tof import Renderer
     gpu = Renderer(w.scene, w.sensor)
@@ -56,6 +56,10 @@ def _run_pair(w, nframes=None, check=("image", "pt_image", "hist", "pt_hist"), i
     frames = w.frames[:nframes] if nframes else w.frames
     for f, fr in enumerate(frames):
         print(f"case {w.name} frame {fr.index} stage {w.sensor.debug_stage}", flush=True)
+        if gate_step and f > 0:   # move the gate, keeping the history on both sides
+            c = float(np.float32(w.sensor.gate_center + gate_step * f))
+            gpu.set_gate_center(c)
+            orc.set_gate_center(c)
         if inject and f > 0:
             gpu.set_history(orc.export_history())
         gpu.render(fr)
@@ -101,6 +105,15 @@ def test_free_running_drift_is_small():
         assert gs[k] == os_[k], (k, gs[k], os_[k])
     gpu.close()
     orc.close()
+
+
+def test_gate_sweep_parity():
+    """The gate moves by +0.02 per frame; temporal reuse shifts the previous
+    frame's paths by the move (Sec. 4.1 time-gate shifting)."""
+    w = scenes.cornell_box(frames=4)
+    gs, os_ = _run_pair(w, gate_step=0.02)
+    for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+        assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
 
 
 def test_cornell_box_naive_shift_parity():
