@@ -27,10 +27,9 @@ struct Alloc {
 struct GeomBuf {
     float* xf = nullptr;
     float4* wv = nullptr;
-    Node* nodes = nullptr;       // binary build nodes
-    Node4* nodes4 = nullptr;     // 4-wide traversal nodes
+    Node4* nodes = nullptr;      // [n_nodes]: the tree over the objects, then the objects' trees
+    uint32_t* order = nullptr;   // refit order: object-tree nodes by height, then the top tree's
     float4* leaves = nullptr;
-    int* parent = nullptr;
     std::vector<float> xf_host;
     bool built = false;
 };
@@ -68,7 +67,15 @@ struct tof_ctx {
     float4* d_lv = nullptr;
     int* d_vobj = nullptr;
     int4* d_tv = nullptr;
-    void* bvh_scratch = nullptr;
+    // acceleration structure: the objects' 4-wide trees (topology built once,
+    // boxes refit per frame) under a per-frame tree over the objects
+    int* d_leaf_tri = nullptr;         // [T] triangle of each leaf slot
+    std::vector<int> mesh_objs;        // objects with triangles
+    std::vector<int32_t> blas_root;    // per mesh object: root reference of its tree
+    std::vector<float> obj_lbox;       // per mesh object: object-space box lo xyz, hi xyz
+    std::vector<int> level_off;        // refit levels of the objects' trees (offsets into order)
+    int n_tlas_cap = 0, n_blas = 0, n_nodes = 0;
+    size_t pinned_bytes = 0;
     GeomBuf geom[2];
     // sensor
     bool has_sensor = false;
@@ -236,7 +243,8 @@ SlotDev slot_dev(const tof_ctx* c, int i) {
     SlotDev d;
     d.wv = g.wv;
     d.xf = g.xf;
-    d.nodes = g.nodes4;
+    d.nodes = g.nodes;
+    d.n_nodes = c->n_nodes;
     d.leaves = g.leaves;
     d.n_tri = c->n_tri;
     d.cam_pos = h.cam_pos;
@@ -413,15 +421,72 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
         HIP_TRY(hipMemcpy(c->d_lv, lv.data(), sizeof(float4) * lv.size(), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(c->d_vobj, vobj.data(), sizeof(int) * vobj.size(), hipMemcpyHostToDevice));
     }
+    // objects' trees: binned SAH over each mesh object's triangles in object
+    // space, leaves of at most 4 triangles, leaf slots object after object
+    c->mesh_objs.clear();
+    c->blas_root.clear();
+    c->obj_lbox.clear();
+    std::vector<Node4> blas;
+    std::vector<int> heights, leaf_tri(T), order;
+    int n_mesh = 0;
+    for (int o = 0; o < d->num_objects; ++o) n_mesh += objs[o].type == TOF_OBJ_GRID ? 1 : 0;
+    c->n_tlas_cap = std::max(n_mesh, 1);
+    int slot = 0;
+    for (int o = 0; o < d->num_objects; ++o) {
+        const Obj& ob = objs[o];
+        if (ob.type != TOF_OBJ_GRID) continue;
+        const int nt = 2 * ob.nu * ob.nv;
+        std::vector<tofh::BvhPrim> prims(nt);
+        float lb[6] = {3e38f, 3e38f, 3e38f, -3e38f, -3e38f, -3e38f};
+        for (int i = 0; i < nt; ++i) {
+            const int4 v = tv[ob.tri_base + i];
+            const int vi[3] = {v.x, v.y, v.z};
+            tofh::BvhPrim& p = prims[i];
+            for (int k = 0; k < 3; ++k) {
+                p.lo[k] = 3e38f;
+                p.hi[k] = -3e38f;
+            }
+            for (int q = 0; q < 3; ++q)
+                for (int k = 0; k < 3; ++k) {
+                    const float x = d->vertices[3 * vi[q] + k];
+                    p.lo[k] = std::min(p.lo[k], x);
+                    p.hi[k] = std::max(p.hi[k], x);
+                    lb[k] = std::min(lb[k], x);
+                    lb[3 + k] = std::max(lb[3 + k], x);
+                }
+        }
+        const int32_t root = tofh::build_bvh4(prims, 4, c->n_tlas_cap + (int)blas.size(), slot, blas, heights, order);
+        for (int i = 0; i < nt; ++i) leaf_tri[slot + i] = ob.tri_base + order[i];
+        slot += nt;
+        c->mesh_objs.push_back(o);
+        c->blas_root.push_back(root);
+        c->obj_lbox.insert(c->obj_lbox.end(), lb, lb + 6);
+    }
+    c->n_blas = (int)blas.size();
+    c->n_nodes = c->n_tlas_cap + c->n_blas;
+    // refit order of the objects' trees: by height, children first
+    std::vector<uint32_t> border;
+    c->level_off.assign(1, 0);
+    const int hmax = heights.empty() ? -1 : *std::max_element(heights.begin(), heights.end());
+    for (int h = 0; h <= hmax; ++h) {
+        for (int i = 0; i < c->n_blas; ++i)
+            if (heights[i] == h) border.push_back((uint32_t)(c->n_tlas_cap + i));
+        c->level_off.push_back((int)border.size());
+    }
+    TOF_TRY(alloc_t(c, a, &c->d_leaf_tri, (size_t)std::max(T, 1)));
+    if (T) HIP_TRY(hipMemcpy(c->d_leaf_tri, leaf_tri.data(), sizeof(int) * T, hipMemcpyHostToDevice));
     for (auto& g : c->geom) {
         TOF_TRY(alloc_t(c, a, &g.xf, 12 * (size_t)objs.size()));
         TOF_TRY(alloc_t(c, a, &g.wv, std::max(d->num_vertices, 1)));
-        TOF_TRY(alloc_t(c, a, &g.nodes, std::max(T - 1, 1)));
-        TOF_TRY(alloc_t(c, a, &g.nodes4, std::max(T - 1, 1)));
+        TOF_TRY(alloc_t(c, a, &g.nodes, (size_t)c->n_nodes));
+        TOF_TRY(alloc_t(c, a, &g.order, (size_t)c->n_nodes));
         TOF_TRY(alloc_t(c, a, &g.leaves, 3 * (size_t)std::max(T, 1)));
-        TOF_TRY(alloc_t(c, a, &g.parent, 2 * (size_t)std::max(T, 1)));
+        HIP_TRY(hipMemset(g.nodes, 0, sizeof(Node4) * (size_t)c->n_nodes));
+        if (c->n_blas) {
+            HIP_TRY(hipMemcpy(g.nodes + c->n_tlas_cap, blas.data(), sizeof(Node4) * blas.size(), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(g.order, border.data(), sizeof(uint32_t) * border.size(), hipMemcpyHostToDevice));
+        }
     }
-    TOF_TRY(dev_alloc(c, a, &c->bvh_scratch, tofh::bvh_scratch_bytes(std::max(T, 1))));
     c->h_objs = objs;
     c->n_obj = d->num_objects;
     c->n_mat = d->num_materials;
@@ -432,7 +497,9 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
     for (int i = 0; i < 2; ++i) {
         if (c->xf_pinned[i]) (void)hipHostFree(c->xf_pinned[i]);
         c->xf_pinned[i] = nullptr;
-        HIP_TRY(hipHostMalloc((void**)&c->xf_pinned[i], sizeof(float) * 12 * objs.size()));
+        // per frame: transforms, the tree over the objects and its refit order
+        c->pinned_bytes = sizeof(float) * 12 * objs.size() + (sizeof(Node4) + sizeof(uint32_t)) * c->n_tlas_cap;
+        HIP_TRY(hipHostMalloc((void**)&c->xf_pinned[i], c->pinned_bytes));
         if (!c->xf_ev[i]) HIP_TRY(hipEventCreateWithFlags(&c->xf_ev[i], hipEventDisableTiming));
     }
     c->has_scene = true;
@@ -752,13 +819,68 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         int ring = c->xf_ring;
         c->xf_ring ^= 1;
         HIP_TRY(hipEventSynchronize(c->xf_ev[ring]));
-        std::memcpy(c->xf_pinned[ring], fr->object_xforms, sizeof(float) * 12 * O);
-        HIP_TRY(hipMemcpyAsync(g.xf, c->xf_pinned[ring], sizeof(float) * 12 * O, hipMemcpyHostToDevice, st));
+        char* pin = (char*)c->xf_pinned[ring];
+        std::memcpy(pin, fr->object_xforms, sizeof(float) * 12 * O);
+        HIP_TRY(hipMemcpyAsync(g.xf, pin, sizeof(float) * 12 * O, hipMemcpyHostToDevice, st));
+        std::vector<int> levels = c->level_off;
+        if (!c->mesh_objs.empty()) {
+            // the tree over the objects' world boxes (corners of the object-space
+            // boxes moved by this frame's transforms; grouping only, the device
+            // refit computes the exact boxes)
+            const size_t M = c->mesh_objs.size();
+            std::vector<tofh::BvhPrim> prims(M);
+            for (size_t m = 0; m < M; ++m) {
+                const float* x = fr->object_xforms + 12 * c->mesh_objs[m];
+                const float* lb = &c->obj_lbox[6 * m];
+                tofh::BvhPrim& p = prims[m];
+                for (int k = 0; k < 3; ++k) {
+                    p.lo[k] = 3e38f;
+                    p.hi[k] = -3e38f;
+                }
+                for (int corner = 0; corner < 8; ++corner) {
+                    const float q[3] = {lb[(corner & 1) ? 3 : 0], lb[(corner & 2) ? 4 : 1], lb[(corner & 4) ? 5 : 2]};
+                    for (int k = 0; k < 3; ++k) {
+                        const float w = x[4 * k] * q[0] + x[4 * k + 1] * q[1] + x[4 * k + 2] * q[2] + x[4 * k + 3];
+                        p.lo[k] = std::min(p.lo[k], w);
+                        p.hi[k] = std::max(p.hi[k], w);
+                    }
+                }
+            }
+            std::vector<Node4> tl;
+            std::vector<int> th, torder;
+            const int32_t root = tofh::build_bvh4(prims, 1, 0, 0, tl, th, torder);
+            if (root < 0) {   // a single object: a root with one child
+                tl.assign(1, Node4{});
+                th.assign(1, 0);
+                tl[0].child = make_int4(c->blas_root[0], -1, -1, -1);
+                tl[0].meta = make_int4(1, 0, 0, 0);
+            } else {
+                for (Node4& n : tl) {
+                    int* ch = &n.child.x;
+                    for (int j = 0; j < n.meta.x; ++j)
+                        if (ch[j] < 0) ch[j] = c->blas_root[torder[ch[j] & 0x0FFFFFFF]];
+                }
+            }
+            const int nt = (int)tl.size();   // <= n_tlas_cap: fewer 4-wide nodes than objects
+            std::vector<uint32_t> tord;
+            const int thmax = *std::max_element(th.begin(), th.end());
+            for (int h = 0; h <= thmax; ++h) {
+                for (int i = 0; i < nt; ++i)
+                    if (th[i] == h) tord.push_back((uint32_t)i);
+                levels.push_back(c->n_blas + (int)tord.size());
+            }
+            char* pn = pin + sizeof(float) * 12 * O;
+            char* po = pn + sizeof(Node4) * c->n_tlas_cap;
+            std::memcpy(pn, tl.data(), sizeof(Node4) * nt);
+            std::memcpy(po, tord.data(), sizeof(uint32_t) * nt);
+            HIP_TRY(hipMemcpyAsync(g.nodes, pn, sizeof(Node4) * nt, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(g.order + c->n_blas, po, sizeof(uint32_t) * nt, hipMemcpyHostToDevice, st));
+        }
         HIP_TRY(hipEventRecord(c->xf_ev[ring], st));
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, c->n_vert, st);
-        if (c->n_tri > 0) tofh::launch_bvh_build(c->d_tv, g.wv, c->n_tri, g.nodes, g.nodes4, g.leaves, g.parent,
-                                                c->bvh_scratch, st);
+        tofh::launch_leaf_gather(c->d_leaf_tri, c->d_tv, g.wv, c->n_tri, g.leaves, st);
+        tofh::launch_refit(g.nodes, g.order, levels, g.leaves, c->n_tri, st);
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         g.built = true;
     }

@@ -65,7 +65,9 @@ struct Node {
 };
 // Traversal node: four child boxes, one 128-byte line.  Component j of each
 // float4 belongs to child j; child[j] >= 0 is a Node4 index, bit 31 set marks
-// a leaf (sorted triangle slot); meta.x = number of children (2..4).
+// a leaf: (count - 1) << 28 | first triangle slot, count <= 8; meta.x =
+// number of children (1..4).  Node 0 is the root of the tree over the
+// objects, whose leaves are the roots of the objects' trees.
 struct Node4 {
     float4 lox, loy, loz, hix, hiy, hiz;
     int4 child;
@@ -86,6 +88,7 @@ struct SlotDev {
     const float4* wv;       // world vertices
     const float* xf;        // object transforms, 12 floats each
     const Node4* nodes;     // 4-wide traversal nodes, root at 0
+    int n_nodes;
     const float4* leaves;   // 3 float4 per sorted triangle: v0 (w = tri id bits), v1, v2
     int n_tri;
     V3 cam_pos, cam_fwd, cam_right, cam_up;
@@ -468,9 +471,7 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
         }
         return false;
     };
-    if (T == 1) {
-        if (test_leaf(0)) return true;
-    } else if (T > 1) {
+    if (T > 0) {
         int sp = 0;
         uint32_t node = 0;
         constexpr float kInfT = 3.0e38f;
@@ -482,11 +483,11 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
                 st.c[ST_OVERFLOW]++;
             }
         };
-        // a 4-wide tree over T leaves has fewer than T nodes: any valid walk
-        // visits each at most once, so this bound only stops a malformed tree
-        int budget = 2 * T + 64;
+        // any valid walk visits each node at most once, so this bound only
+        // stops a malformed tree
+        int budget = 2 * G.n_nodes + 64;
         while (--budget > 0) {
-            if (node >= (uint32_t)(T - 1)) {   // never for a well-formed tree
+            if (node >= (uint32_t)G.n_nodes) {   // never for a well-formed tree
                 st.c[ST_OVERFLOW]++;
                 break;
             }
@@ -499,7 +500,7 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
             // all four boxes, without branches; children j >= nc are padding
             float t0, t1, t2, t3;
             const bool h0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, tb, t0);
-            const bool h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, tb, t1);
+            const bool h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, tb, t1) && nc > 1;
             const bool h2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, tb, t2) && nc > 2;
             const bool h3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, tb, t3) && nc > 3;
             const bool f0 = cc.x < 0, f1 = cc.y < 0, f2 = cc.z < 0, f3 = cc.w < 0;   // leaves
@@ -514,8 +515,10 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
             while (leaf_hits) {
                 const int j = __ffs(leaf_hits) - 1;
                 leaf_hits &= leaf_hits - 1;
-                const int c = j == 0 ? cc.x : (j == 1 ? cc.y : (j == 2 ? cc.z : cc.w));
-                if (test_leaf(c & 0x7fffffff)) return true;
+                const uint32_t c = (uint32_t)(j == 0 ? cc.x : (j == 1 ? cc.y : (j == 2 ? cc.z : cc.w)));
+                const int first = (int)(c & 0x0FFFFFFFu), cnt = (int)((c >> 28) & 7u) + 1;
+                for (int k = first; k < first + cnt; ++k)
+                    if (test_leaf(k)) return true;
             }
             // sorting network on (key, node): nearest first
             auto cswap = [](float& ka, int& na, float& kb, int& nb) {

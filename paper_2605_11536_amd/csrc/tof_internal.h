@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "tof_device.h"
 
@@ -18,12 +19,25 @@ struct FrameArgs {
     unsigned long long* counters;   // kNumCounters x u64
 };
 
+// bvh_host.hip (host code): 4-wide tree topology over axis-aligned boxes (binned SAH,
+// then a collapse of the binary tree).  Leaf references are
+// 0x80000000 | (count - 1) << 28 | first slot, count <= 8.
+struct BvhPrim {
+    float lo[3], hi[3];
+};
+int32_t leaf_ref(int first, int count);
+int32_t build_bvh4(const std::vector<BvhPrim>& prims, int leaf_max, int node_base, int slot_base,
+                   std::vector<tofd::Node4>& nodes, std::vector<int>& heights, std::vector<int>& order);
+
 // bvh.hip
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 void launch_world_verts(const float4* lv, const int* vobj, const float* xf, float4* wv, int nv, hipStream_t st);
-size_t bvh_scratch_bytes(int T);
-void launch_bvh_build(const int4* tv, const float4* wv, int T, tofd::Node* nodes, tofd::Node4* nodes4,
-                      float4* leaves, int* parent, void* scratch, hipStream_t st);
+void launch_leaf_gather(const int* leaf_tri, const int4* tv, const float4* wv, int T, float4* leaves,
+                        hipStream_t st);
+// boxes of the nodes order[level_off[l] .. level_off[l+1]) for l = 0, 1, ...
+// (children before parents)
+void launch_refit(tofd::Node4* nodes, const uint32_t* order, const std::vector<int>& level_off,
+                  const float4* leaves, int T, hipStream_t st);
 
 // render.hip
 struct GBufOut {
