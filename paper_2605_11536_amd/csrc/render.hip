@@ -434,9 +434,41 @@ TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
     flush_counters(st, a.counters);
 }
 
+// MIS work list: for tasks [t_begin, t_end), every (task, neighbour l) pair
+// that needs a shift -- all neighbours of a canonical task, the neighbours
+// other than the source of a forward-shifted one, none after a failed forward
+// shift, never an off-screen neighbour -- as g = t * K + l; term[g] = 0 for all.
+__global__ void __launch_bounds__(kTB) k_mis_list(FrameArgs a, int mode, const int* __restrict__ links,
+                                                  const uint2* __restrict__ items, const uint2* __restrict__ tasks,
+                                                  const uint32_t* __restrict__ count, uint32_t t_begin,
+                                                  uint32_t t_end, const float4* __restrict__ fwd,
+                                                  float* __restrict__ term, IdxQueue lq) {
+    const int P = a.s.P;
+    const uint32_t K = mode == 0 ? 1u : (uint32_t)a.s.k;
+    const uint32_t n = min(count[1], t_end);
+    for (uint32_t t = t_begin + blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
+        uint32_t valid = 0;
+        const uint2 task = tasks[t];
+        const int c = (int)task.y;
+        const int pix = (int)items[task.x].x;
+        const bool open = c == 0 || fwd[t].x > 0.f;
+        for (uint32_t l = 0; l < K; ++l) {
+            term[(size_t)t * K + l] = 0.f;
+            const int dpix = mode == 0 ? links[pix] : links[(size_t)l * P + pix];
+            if (open && (int)l != c - 1 && dpix >= 0) valid |= 1u << l;
+        }
+        uint32_t first;
+        const bool fits = lq.alloc((uint32_t)__popc(valid), first);   // bounded by the chunk size
+        if (fits)
+            for (uint32_t l = 0; valid; ++l, valid >>= 1)
+                if (valid & 1u) lq.buf[first++] = t * K + l;
+    }
+}
+
+// MIS shifts of the listed pairs; blocks are dealt to the sub-lists round
+// robin (and so append their rays to the ray sub-queue of the same index)
 TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
-                       const uint2* __restrict__ items, const uint2* __restrict__ tasks,
-                       const uint32_t* __restrict__ count, uint64_t g_begin, uint64_t g_end,
+                       const uint2* __restrict__ items, const uint2* __restrict__ tasks, IdxQueue lq,
                        const float4* __restrict__ fwd, const float4* __restrict__ shv, float* __restrict__ term,
                        RayQueue q) {
     __shared__ uint32_t stk[kStackDepth * kTB];
@@ -445,43 +477,39 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
     const Sens& s = a.s;
     const int P = s.P;
     const uint32_t K = mode == 0 ? 1u : (uint32_t)s.k;
-    const uint64_t n = min((uint64_t)count[1] * K, g_end);
-    for (uint64_t g = g_begin + (uint64_t)blockIdx.x * kTB + threadIdx.x; g < n; g += (uint64_t)gridDim.x * kTB) {
-        const uint32_t t = (uint32_t)(g / K);
-        const int l = (int)(g - (uint64_t)t * K);
+    const uint32_t sub = blockIdx.x % kRaySubQueues;
+    const uint32_t n = min(lq.count[sub * kCounterStride], lq.sub_cap);
+    const uint32_t* list = lq.buf + (size_t)sub * lq.sub_cap;
+    const uint32_t step = (gridDim.x / kRaySubQueues) * kTB;
+    for (uint32_t i = (blockIdx.x / kRaySubQueues) * kTB + threadIdx.x; i < n; i += step) {
+        const uint32_t g = list[i];
+        const uint32_t t = g / K;
+        const int l = (int)(g - t * K);
         const uint2 task = tasks[t];
         const int c = (int)task.y;
-        const float4 fw = fwd[t];
-        float out = 0.f;
-        if (c == 0 || (fw.x > 0.f && l != c - 1)) {
-            const uint2 item = items[task.x];
-            const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
-            const int dpix = mode == 0 ? links[pix] : links[(size_t)l * P + pix];
-            if (dpix >= 0) {
-                float Wx;
-                Rec y;
-                if (c == 0) {
-                    y = load_rec(A, (size_t)pl * P + pix, Wx);
-                } else {
-                    const int src = cand_src(mode, links, P, pix, c);
-                    y = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
-                    const float4 s0 = shv[2 * (size_t)t], s1 = shv[2 * (size_t)t + 1];
-                    y.v[0] = VRef{__float_as_int(s0.x), s0.y, s0.z};
-                    y.v[1] = VRef{__float_as_int(s0.w), s1.x, s1.y};
-                    y.len = s1.z;
-                    y.pre_pdf = s1.w;
-                    y.phat = fw.x;
-                }
-                const float dl = mode == 0 ? -gate_shift(s, a.F.g[0], a.F.g[1], pl) : 0.f;
-                const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, pl, dl, q,
-                                               (uint32_t)g);
-                if (sh.ok) {
-                    const float ml = mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
-                    out = ml * sh.phat * sh.J;
-                }
-            }
+        const uint2 item = items[task.x];
+        const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
+        const int dpix = mode == 0 ? links[pix] : links[(size_t)l * P + pix];
+        float Wx;
+        Rec y;
+        if (c == 0) {
+            y = load_rec(A, (size_t)pl * P + pix, Wx);
+        } else {
+            const int src = cand_src(mode, links, P, pix, c);
+            y = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
+            const float4 s0 = shv[2 * (size_t)t], s1 = shv[2 * (size_t)t + 1];
+            y.v[0] = VRef{__float_as_int(s0.x), s0.y, s0.z};
+            y.v[1] = VRef{__float_as_int(s0.w), s1.x, s1.y};
+            y.len = s1.z;
+            y.pre_pdf = s1.w;
+            y.phat = fwd[t].x;
         }
-        term[g] = out;
+        const float dl = mode == 0 ? -gate_shift(s, a.F.g[0], a.F.g[1], pl) : 0.f;
+        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, pl, dl, q, g);
+        if (sh.ok) {
+            const float ml = mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
+            term[g] = ml * sh.phat * sh.J;
+        }
     }
     flush_counters(st, a.counters);
 }
@@ -655,10 +683,13 @@ void launch_fwd(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp,
                        items, tasks, count, (uint32_t)t_begin, (uint32_t)t_end, fwd, shv, q);
 }
 void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t g_begin, size_t g_end,
-                const float4* fwd, const float4* shv, float* term, const RayQueue& q, hipStream_t st) {
-    hipLaunchKernelGGL(k_mis, dim3(kShiftGrid), dim3(kTB), 0, st, a, mode, A, Bp, links,
-                       items, tasks, count, (uint64_t)g_begin, (uint64_t)g_end, fwd, shv, term, q);
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
+                const float4* fwd, const float4* shv, float* term, const IdxQueue& lq, const RayQueue& q,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_mis_list, dim3(kShiftGrid), dim3(kTB), 0, st, a, mode, links, items, tasks, count,
+                       (uint32_t)t_begin, (uint32_t)t_end, fwd, term, lq);
+    hipLaunchKernelGGL(k_mis, dim3(kShiftGrid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, lq, fwd, shv,
+                       term, q);
 }
 void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, hipStream_t st) {
     hipLaunchKernelGGL(k_vis, dim3(kVisGrid), dim3(kTB), 0, st, a, slot, q, kill);

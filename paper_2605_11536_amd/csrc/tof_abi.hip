@@ -98,6 +98,8 @@ struct tof_ctx {
     float4* rays = nullptr;    // [2 * ray_cap]: queued visibility segments
     uint32_t* ray_count = nullptr;
     size_t ray_cap = 0;
+    uint32_t* mis_list = nullptr;   // [max(k, 1) * task chunk]: (task, neighbour) pairs of one chunk
+    uint32_t* mis_count = nullptr;
     uint32_t* count = nullptr;
     size_t max_items = 0, max_tasks = 0;
     // misc
@@ -180,11 +182,15 @@ constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 // multiples of tofh::kChunkQuantum lanes; a shift queues at most 4 rays
 // across frames (temporal) and 2 within one frame (spatial).
 size_t round_up(size_t x, size_t q) { return (x + q - 1) / q * q; }
-size_t ray_queue_cap(size_t max_tasks, size_t k) {
+// Tasks per chunk of a pass whose shifts queue at most `rays` rays per task.
+size_t task_chunk(size_t max_tasks, size_t rays) {
     const size_t Q = tofh::kChunkQuantum;
-    const size_t need = std::max(4 * round_up(std::max<size_t>(max_tasks, 1), Q),
-                                 2 * round_up(std::max<size_t>(max_tasks * std::max<size_t>(k, 1), 1), Q));
-    return std::min<size_t>(need, (size_t)1 << 28);
+    return std::min(round_up(std::max<size_t>(max_tasks, 1), Q), std::max(((size_t)1 << 28) / rays / Q, (size_t)1) * Q);
+}
+// temporal: 4 rays per shift, one MIS shift per task; spatial: 2 rays, k
+size_t ray_queue_cap(size_t max_tasks, size_t k) {
+    k = std::max<size_t>(k, 1);
+    return std::max(4 * task_chunk(max_tasks, 4), 2 * k * task_chunk(max_tasks, 2 * k));
 }
 
 size_t sensor_footprint(const tof_sensor_desc& d) {
@@ -568,6 +574,8 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     c->ray_cap = ray_queue_cap(P * B * ncand, ncand - 1);
     TOF_TRY(alloc_t(c, a, &c->rays, 2 * c->ray_cap));
     TOF_TRY(alloc_t(c, a, &c->ray_count, (size_t)tofd::kRaySubQueues * tofd::kCounterStride));
+    TOF_TRY(alloc_t(c, a, &c->mis_list, (ncand - 1) * task_chunk(P * B * ncand, 2 * (ncand - 1))));
+    TOF_TRY(alloc_t(c, a, &c->mis_count, (size_t)tofd::kRaySubQueues * tofd::kCounterStride));
     TOF_TRY(alloc_t(c, a, &c->count, 64));
     c->max_tasks = P * B * ncand;
     c->item_slots = 4 * 4096;
@@ -744,12 +752,8 @@ tof_status run_shifts(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A,
     const size_t K = mode == 0 ? 1 : (size_t)c->s.k;
     // at most 4 segments per shift across frames (temporal), 2 within one frame
     const size_t per_shift = mode == 0 ? 4 : 2;
-    const size_t Q = tofh::kChunkQuantum;
-    const size_t chunk_max = c->ray_cap / per_shift / Q * Q;   // >= Q by the allocation
     const size_t ncounters = (size_t)tofd::kRaySubQueues * tofd::kCounterStride;
-    auto queue_for = [&](size_t chunk) {
-        return tofd::RayQueue{c->rays, c->ray_count, (uint32_t)(per_shift * chunk / tofd::kRaySubQueues)};
-    };
+    const size_t NQ = tofd::kRaySubQueues;
     auto vis = [&](int slot, const tofd::RayQueue& q, float* kill) -> hipError_t {
         hipError_t e = timer_mark(c, kv, st);
         if (e != hipSuccess) return e;
@@ -757,24 +761,28 @@ tof_status run_shifts(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A,
         tofh::launch_vis(a, slot, q, kill, st);
         return timer_mark(c, kv, st);
     };
-    const size_t chunk_f = std::min(round_up(std::max<size_t>(c->max_tasks, 1), Q), chunk_max);
-    const tofd::RayQueue qf = queue_for(chunk_f);
-    for (size_t b = 0; b < c->max_tasks; b += chunk_f) {
+    // forward shifts: one per task; a chunk of tc tasks queues at most
+    // per_shift * tc rays, per_shift * tc / NQ in each sub-queue
+    const size_t tf = task_chunk(c->max_tasks, per_shift);
+    const tofd::RayQueue qf{c->rays, c->ray_count, (uint32_t)(per_shift * tf / NQ)};
+    for (size_t b = 0; b < c->max_tasks; b += tf) {
         tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
         HIP_TRY(timer_mark(c, kf, st));
         a.counters = c->counters + (size_t)kf * kBank;
-        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + chunk_f, c->fwd, c->shv, qf, st);
+        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + tf, c->fwd, c->shv, qf, st);
         HIP_TRY(timer_mark(c, kf, st));
         HIP_TRY(vis(0, qf, (float*)c->fwd));
     }
-    const size_t lanes = c->max_tasks * K;
-    const size_t chunk_m = std::min(round_up(std::max<size_t>(lanes, 1), Q), chunk_max);
-    const tofd::RayQueue qm = queue_for(chunk_m);
-    for (size_t b = 0; b < lanes; b += chunk_m) {
+    // MIS shifts: at most K per task
+    const size_t tm = task_chunk(c->max_tasks, per_shift * K);
+    const tofd::RayQueue qm{c->rays, c->ray_count, (uint32_t)(per_shift * K * tm / NQ)};
+    const tofd::IdxQueue lq{c->mis_list, c->mis_count, (uint32_t)(K * tm / NQ)};
+    for (size_t b = 0; b < c->max_tasks; b += tm) {
         tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
+        tofh::launch_fill_u32(c->mis_count, 0u, ncounters, st);
         HIP_TRY(timer_mark(c, km, st));
         a.counters = c->counters + (size_t)km * kBank;
-        tofh::launch_mis(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + chunk_m, c->fwd, c->shv, c->term,
+        tofh::launch_mis(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + tm, c->fwd, c->shv, c->term, lq,
                          qm, st);
         HIP_TRY(timer_mark(c, km, st));
         HIP_TRY(vis(mode == 0 ? 1 : 0, qm, c->term));

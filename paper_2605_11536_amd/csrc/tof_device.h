@@ -695,6 +695,34 @@ struct RayQueue {
     }
 };
 
+// A list of u32 work indices in kRaySubQueues sub-lists (same scheme as the
+// ray queue): alloc(n) gives this lane n consecutive slots.
+struct IdxQueue {
+    uint32_t* buf;      // [kRaySubQueues][sub_cap]
+    uint32_t* count;    // count[s * kCounterStride]
+    uint32_t sub_cap;
+
+    __device__ bool alloc(uint32_t n, uint32_t& first) const {
+        const int lane = (int)__lane_id();
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {   // n < 16
+            const uint64_t m = __ballot((n >> b) & 1u);
+            pre += (uint32_t)__popcll(m & lt) << b;
+            tot += (uint32_t)__popcll(m) << b;
+        }
+        const uint64_t act = __ballot(1);
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const uint32_t sub = blockIdx.x % kRaySubQueues;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(count + sub * kCounterStride, tot);
+        base = __shfl(base, leader, 64);
+        first = sub * sub_cap + base + pre;
+        return base + tot <= sub_cap;
+    }
+};
+
 // ---------------------------------------------------------------------------
 // BSDFs: Lambert, GGX (Walter et al. 2007; separable Smith G; Schlick F)
 // ---------------------------------------------------------------------------

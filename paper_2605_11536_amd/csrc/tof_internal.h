@@ -77,9 +77,12 @@ constexpr size_t kChunkQuantum = (size_t)kShiftGrid * 128;
 void launch_fwd(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
                 float4* fwd, float4* shv, const tofd::RayQueue& q, hipStream_t st);
+// MIS shifts of tasks [t_begin, t_end): the pairs (task, neighbour) that need
+// one are listed in lq (at most K per task), then shifted.
 void launch_mis(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t g_begin, size_t g_end,
-                const float4* fwd, const float4* shv, float* term, const tofd::RayQueue& q, hipStream_t st);
+                const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
+                const float4* fwd, const float4* shv, float* term, const tofd::IdxQueue& lq,
+                const tofd::RayQueue& q, hipStream_t st);
 void launch_vis(const FrameArgs& a, int slot, const tofd::RayQueue& q, float* kill, hipStream_t st);
 // Weighted reservoir merge of each item's candidates into `out`.
 void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
