@@ -247,6 +247,62 @@ tof_status tof_get_kernel_times(tof_ctx* ctx, tof_kernel_times* out);
 /* Static string for a status code. */
 const char* tof_status_string(tof_status status);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over render streams on one device.
+ *
+ * Each stream is a full context (scene, sensor, resident reservoirs and the
+ * last two frames' G-buffers and geometry) with its own HIP stream.  A stream
+ * is admitted when its footprint (tof_footprint) fits in what the server's
+ * HBM budget has left, else it waits, first come first served, until a close
+ * frees memory.  Frames of admitted streams are enqueued on submission, so
+ * frames of different streams run concurrently on the device while the
+ * frames of one stream run in order (their temporal reuse depends on it);
+ * frames of a waiting stream are held and enqueued on admission.  Results are
+ * the same as rendering the stream alone with tof_render_frame.  The calls
+ * may come from several host threads; one thread should wait for a ticket.
+ * ------------------------------------------------------------------------ */
+typedef struct tof_server tof_server;
+
+/* Upper bound of the device memory a context with this scene and sensor
+ * allocates (scene upload + sensor set). */
+tof_status tof_footprint(const tof_scene_desc* scene, const tof_sensor_desc* sensor, size_t* bytes);
+
+/* A server on HIP device `device` whose streams together use at most
+ * hbm_budget_bytes (> 0) of device memory. */
+tof_status tof_server_create(tof_server** out, int device, size_t hbm_budget_bytes);
+
+/* Waits for all work, releases every stream. */
+void tof_server_destroy(tof_server* server);
+
+/* Open a stream (scene and sensor are copied; seed keys its random streams).
+ * *stream_id receives its id and *admitted (may be NULL) whether it was
+ * admitted at once.  TOF_ERR_OUT_OF_MEMORY if its footprint exceeds the whole
+ * budget. */
+tof_status tof_server_open(tof_server* server, const tof_scene_desc* scene, const tof_sensor_desc* sensor,
+                           uint64_t seed, int* stream_id, int* admitted);
+
+/* Queue a frame of a stream (the frame description and transforms are
+ * copied); outputs as for tof_render_frame, device buffers that must stay
+ * valid until the frame is done.  *ticket identifies the frame. */
+tof_status tof_server_submit(tof_server* server, int stream_id, const tof_frame_desc* frame, float* out_image,
+                             float* out_hist, float* out_pt_image, float* out_pt_hist, uint64_t* ticket);
+
+/* Non-blocking: *done = 1 once the frame finished (its status is returned and
+ * the ticket is retired), else 0. */
+tof_status tof_server_query(tof_server* server, uint64_t ticket, int* done);
+
+/* Block until the frame finished; returns its status and retires the ticket.
+ * TOF_ERR_NOT_READY while its stream waits for admission. */
+tof_status tof_server_wait(tof_server* server, uint64_t ticket);
+
+/* Close a stream after its queued frames finish; its memory admits waiting
+ * streams.  Frames held by a stream that was never admitted end with
+ * TOF_ERR_NOT_READY. */
+tof_status tof_server_close(tof_server* server, int stream_id);
+
+/* Device memory in use by admitted streams, their number, streams waiting. */
+tof_status tof_server_info(tof_server* server, size_t* used_bytes, int* admitted, int* waiting);
+
 #ifdef __cplusplus
 }
 #endif

@@ -678,17 +678,17 @@ void launch_items(const FrameArgs& a, int mode, const ResSet& first, const ResSe
 }
 void launch_fwd(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
-                float4* fwd, float4* shv, const RayQueue& q, hipStream_t st) {
-    hipLaunchKernelGGL(k_fwd, dim3(kShiftGrid), dim3(kTB), 0, st, a, mode, A, Bp, links,
+                float4* fwd, float4* shv, const RayQueue& q, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_fwd, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links,
                        items, tasks, count, (uint32_t)t_begin, (uint32_t)t_end, fwd, shv, q);
 }
 void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
                 const float4* fwd, const float4* shv, float* term, const IdxQueue& lq, const RayQueue& q,
-                hipStream_t st) {
-    hipLaunchKernelGGL(k_mis_list, dim3(kShiftGrid), dim3(kTB), 0, st, a, mode, links, items, tasks, count,
+                unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_mis_list, dim3(grid), dim3(kTB), 0, st, a, mode, links, items, tasks, count,
                        (uint32_t)t_begin, (uint32_t)t_end, fwd, term, lq);
-    hipLaunchKernelGGL(k_mis, dim3(kShiftGrid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, lq, fwd, shv,
+    hipLaunchKernelGGL(k_mis, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, lq, fwd, shv,
                        term, q);
 }
 void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, hipStream_t st) {

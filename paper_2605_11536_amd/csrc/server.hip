@@ -1,0 +1,299 @@
+// Request loop over render streams on one device (host code).
+//
+// Every stream is a full ToF ReSTIR context (scene, sensor, resident
+// reservoirs, G-buffers and geometry of the last two frames) with its own HIP
+// stream.  A stream is admitted when its footprint fits in what the server's
+// HBM budget has left; otherwise it waits, first come first served, until a
+// close frees memory.  A submitted frame of an admitted stream is enqueued on
+// the stream's HIP stream at once, so frames of different streams run
+// concurrently on the device while frames of one stream stay in order (their
+// temporal reuse depends on it); frames of a waiting stream are held and
+// enqueued when it is admitted.  Completion is tracked with one HIP event per
+// frame.  All calls may come from any host thread (one mutex).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "tof.h"
+
+namespace {
+
+// deep copy of a scene description (the caller's arrays may go away before
+// the stream is admitted)
+struct SceneCopy {
+    std::vector<int32_t> type, material, grid, mtype;
+    std::vector<float> sphere, mparams, vertices;
+    tof_scene_desc desc{};
+
+    explicit SceneCopy(const tof_scene_desc& d) {
+        const size_t O = (size_t)d.num_objects, M = (size_t)d.num_materials, V = (size_t)std::max(d.num_vertices, 0);
+        type.assign(d.object_type, d.object_type + O);
+        material.assign(d.object_material, d.object_material + O);
+        grid.assign(d.object_grid, d.object_grid + 5 * O);
+        sphere.assign(d.object_sphere, d.object_sphere + 4 * O);
+        mtype.assign(d.material_type, d.material_type + M);
+        mparams.assign(d.material_params, d.material_params + 3 * M);
+        if (V) vertices.assign(d.vertices, d.vertices + 3 * V);
+        desc = d;
+        desc.object_type = type.data();
+        desc.object_material = material.data();
+        desc.object_grid = grid.data();
+        desc.object_sphere = sphere.data();
+        desc.material_type = mtype.data();
+        desc.material_params = mparams.data();
+        desc.vertices = V ? vertices.data() : nullptr;
+    }
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    int stream = -1;
+    tof_frame_desc frame{};
+    std::vector<float> xforms;
+    float* out[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t done = nullptr;
+    bool dispatched = false;
+    tof_status status = TOF_OK;
+};
+
+struct Stream {
+    int id = -1;
+    std::unique_ptr<SceneCopy> scene;
+    tof_sensor_desc sensor{};
+    uint64_t seed = 0;
+    size_t footprint = 0;
+    tof_ctx* ctx = nullptr;
+    hipStream_t hs = nullptr;
+    bool admitted = false;
+    std::deque<uint64_t> held;   // frames submitted before admission
+};
+
+}  // namespace
+
+struct tof_server {
+    int device = 0;
+    size_t budget = 0, used = 0;
+    std::mutex mu;
+    int next_stream = 0;
+    uint64_t next_ticket = 1;
+    std::map<int, Stream> streams;
+    std::deque<int> waiting;     // streams in admission order
+    std::map<uint64_t, std::unique_ptr<Request>> requests;
+};
+
+namespace {
+
+tof_status hip_status(hipError_t e) { return e == hipSuccess ? TOF_OK : TOF_ERR_DEVICE; }
+
+tof_status dispatch(tof_server* s, Stream& st, Request& r) {
+    tof_status e = tof_render_frame(st.ctx, &r.frame, r.out[0], r.out[1], r.out[2], r.out[3], (void*)st.hs);
+    if (e == TOF_OK) e = hip_status(hipEventRecord(r.done, st.hs));
+    r.status = e;
+    r.dispatched = true;
+    return e;
+}
+
+// create the context of a stream and enqueue its held frames
+tof_status admit(tof_server* s, Stream& st) {
+    tof_status e = tof_create(&st.ctx, s->device, st.footprint, st.seed);
+    if (e == TOF_OK) e = tof_scene_upload(st.ctx, &st.scene->desc);
+    if (e == TOF_OK) e = tof_sensor_set(st.ctx, &st.sensor);
+    if (e == TOF_OK) e = hip_status(hipStreamCreateWithFlags(&st.hs, hipStreamNonBlocking));
+    if (e != TOF_OK) {
+        if (st.ctx) tof_destroy(st.ctx);
+        st.ctx = nullptr;
+        return e;
+    }
+    st.admitted = true;
+    s->used += st.footprint;
+    while (!st.held.empty()) {
+        Request& r = *s->requests[st.held.front()];
+        st.held.pop_front();
+        dispatch(s, st, r);
+    }
+    return TOF_OK;
+}
+
+// admit waiting streams, in order, while the first one fits
+void admit_waiting(tof_server* s) {
+    while (!s->waiting.empty()) {
+        Stream& st = s->streams[s->waiting.front()];
+        if (s->used + st.footprint > s->budget) break;
+        s->waiting.pop_front();
+        if (admit(s, st) != TOF_OK) {   // its frames fail; the stream stays closed to new work
+            for (uint64_t t : st.held) {
+                s->requests[t]->status = TOF_ERR_DEVICE;
+                s->requests[t]->dispatched = true;
+            }
+            st.held.clear();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+tof_status tof_server_create(tof_server** out, int device, size_t hbm_budget_bytes) {
+    if (!out || hbm_budget_bytes == 0) return TOF_ERR_INVALID_ARG;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TOF_ERR_DEVICE;
+    tof_server* s = new (std::nothrow) tof_server();
+    if (!s) return TOF_ERR_OUT_OF_MEMORY;
+    s->device = device;
+    s->budget = hbm_budget_bytes;
+    *out = s;
+    return TOF_OK;
+}
+
+void tof_server_destroy(tof_server* s) {
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    for (auto& kv : s->requests)
+        if (kv.second->done) {
+            (void)hipEventSynchronize(kv.second->done);
+            (void)hipEventDestroy(kv.second->done);
+        }
+    for (auto& kv : s->streams) {
+        if (kv.second.hs) (void)hipStreamSynchronize(kv.second.hs);
+        if (kv.second.ctx) tof_destroy(kv.second.ctx);
+        if (kv.second.hs) (void)hipStreamDestroy(kv.second.hs);
+    }
+    delete s;
+}
+
+tof_status tof_server_open(tof_server* s, const tof_scene_desc* scene, const tof_sensor_desc* sensor, uint64_t seed,
+                           int* stream_id, int* admitted) {
+    if (!s || !scene || !sensor || !stream_id) return TOF_ERR_INVALID_ARG;
+    size_t fp = 0;
+    tof_status e = tof_footprint(scene, sensor, &fp);
+    if (e != TOF_OK) return e;
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (fp > s->budget) return TOF_ERR_OUT_OF_MEMORY;   // could never be admitted
+    if (hipSetDevice(s->device) != hipSuccess) return TOF_ERR_DEVICE;
+    const int id = s->next_stream++;
+    Stream& st = s->streams[id];
+    st.id = id;
+    st.scene.reset(new SceneCopy(*scene));
+    st.sensor = *sensor;
+    st.seed = seed;
+    st.footprint = fp;
+    s->waiting.push_back(id);
+    admit_waiting(s);
+    if (!st.admitted && (s->waiting.empty() || std::find(s->waiting.begin(), s->waiting.end(), id) == s->waiting.end())) {
+        s->streams.erase(id);   // admission itself failed
+        return TOF_ERR_DEVICE;
+    }
+    *stream_id = id;
+    if (admitted) *admitted = st.admitted ? 1 : 0;
+    return TOF_OK;
+}
+
+tof_status tof_server_submit(tof_server* s, int stream_id, const tof_frame_desc* frame, float* out_image,
+                             float* out_hist, float* out_pt_image, float* out_pt_hist, uint64_t* ticket) {
+    if (!s || !frame || !frame->object_xforms || !ticket) return TOF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->streams.find(stream_id);
+    if (it == s->streams.end()) return TOF_ERR_INVALID_ARG;
+    Stream& st = it->second;
+    if (hipSetDevice(s->device) != hipSuccess) return TOF_ERR_DEVICE;
+    std::unique_ptr<Request> r(new Request());
+    r->ticket = s->next_ticket++;
+    r->stream = stream_id;
+    r->frame = *frame;
+    r->xforms.assign(frame->object_xforms, frame->object_xforms + 12 * (size_t)st.scene->desc.num_objects);
+    r->frame.object_xforms = r->xforms.data();
+    r->out[0] = out_image;
+    r->out[1] = out_hist;
+    r->out[2] = out_pt_image;
+    r->out[3] = out_pt_hist;
+    if (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) return TOF_ERR_DEVICE;
+    Request& rr = *r;
+    s->requests[r->ticket] = std::move(r);
+    *ticket = rr.ticket;
+    if (st.admitted) return dispatch(s, st, rr);
+    st.held.push_back(rr.ticket);
+    return TOF_OK;
+}
+
+tof_status tof_server_query(tof_server* s, uint64_t ticket, int* done) {
+    if (!s || !done) return TOF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return TOF_ERR_INVALID_ARG;
+    Request& r = *it->second;
+    *done = 0;
+    if (!r.dispatched) return TOF_OK;
+    tof_status st = r.status;
+    if (st == TOF_OK) {
+        const hipError_t q = hipEventQuery(r.done);
+        if (q == hipErrorNotReady) return TOF_OK;
+        if (q != hipSuccess) st = TOF_ERR_DEVICE;
+    }
+    *done = 1;
+    (void)hipEventDestroy(r.done);
+    s->requests.erase(it);
+    return st;
+}
+
+tof_status tof_server_wait(tof_server* s, uint64_t ticket) {
+    if (!s) return TOF_ERR_INVALID_ARG;
+    hipEvent_t ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        auto it = s->requests.find(ticket);
+        if (it == s->requests.end()) return TOF_ERR_INVALID_ARG;
+        if (!it->second->dispatched) return TOF_ERR_NOT_READY;   // its stream is not admitted yet
+        ev = it->second->done;
+    }
+    if (hipEventSynchronize(ev) != hipSuccess) return TOF_ERR_DEVICE;
+    int done = 0;
+    return tof_server_query(s, ticket, &done);
+}
+
+tof_status tof_server_close(tof_server* s, int stream_id) {
+    if (!s) return TOF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->streams.find(stream_id);
+    if (it == s->streams.end()) return TOF_ERR_INVALID_ARG;
+    Stream& st = it->second;
+    if (hipSetDevice(s->device) != hipSuccess) return TOF_ERR_DEVICE;
+    if (st.admitted) {
+        if (hipStreamSynchronize(st.hs) != hipSuccess) return TOF_ERR_DEVICE;
+        tof_destroy(st.ctx);
+        (void)hipStreamDestroy(st.hs);
+        s->used -= st.footprint;
+    } else {
+        for (auto w = s->waiting.begin(); w != s->waiting.end(); ++w)
+            if (*w == stream_id) {
+                s->waiting.erase(w);
+                break;
+            }
+        for (uint64_t t : st.held) {   // frames that never ran
+            s->requests[t]->status = TOF_ERR_NOT_READY;
+            s->requests[t]->dispatched = true;
+        }
+    }
+    s->streams.erase(it);
+    admit_waiting(s);
+    return TOF_OK;
+}
+
+tof_status tof_server_info(tof_server* s, size_t* used_bytes, int* admitted, int* waiting) {
+    if (!s) return TOF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(s->mu);
+    int a = 0;
+    for (auto& kv : s->streams) a += kv.second.admitted ? 1 : 0;
+    if (used_bytes) *used_bytes = s->used;
+    if (admitted) *admitted = a;
+    if (waiting) *waiting = (int)s->waiting.size();
+    return TOF_OK;
+}
+
+}  // extern "C"

@@ -179,12 +179,12 @@ constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 
 // Queued visibility rays: enough for every shift of a pass at once when that
 // is at most 2^28 rays (8.6 GB), else the passes run in chunks.  Chunks are
-// multiples of tofh::kChunkQuantum lanes; a shift queues at most 4 rays
+// multiples of the pass's chunk quantum; a shift queues at most 4 rays
 // across frames (temporal) and 2 within one frame (spatial).
 size_t round_up(size_t x, size_t q) { return (x + q - 1) / q * q; }
 // Tasks per chunk of a pass whose shifts queue at most `rays` rays per task.
 size_t task_chunk(size_t max_tasks, size_t rays) {
-    const size_t Q = tofh::kChunkQuantum;
+    const size_t Q = tofh::chunk_quantum(max_tasks);
     return std::min(round_up(std::max<size_t>(max_tasks, 1), Q), std::max(((size_t)1 << 28) / rays / Q, (size_t)1) * Q);
 }
 // temporal: 4 rays per shift, one MIS shift per task; spatial: 2 rays, k
@@ -205,7 +205,23 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
            P * B * ((size_t)std::max(d.spatial_k, 1) + 1) * (8 + 16 + 32 + 4 * (size_t)std::max(d.spatial_k, 1))
            /*tasks, forward terms, shifted fields, MIS terms*/ +
            32 * ray_queue_cap(P * B * ((size_t)std::max(d.spatial_k, 1) + 1), (size_t)std::max(d.spatial_k, 1)) +
+           4 * std::max((size_t)std::max(d.spatial_k, 1) *
+                            task_chunk(P * B * ((size_t)std::max(d.spatial_k, 1) + 1), 2 * (size_t)std::max(d.spatial_k, 1)),
+                        task_chunk(P * B * ((size_t)std::max(d.spatial_k, 1) + 1), 2)) /*work list*/ +
            64 * 1024;
+}
+
+// upper bound of the device memory tof_scene_upload allocates for a scene
+size_t scene_footprint(const tof_scene_desc& d) {
+    size_t T = 0, mesh = 0;
+    for (int o = 0; o < d.num_objects; ++o)
+        if (d.object_type[o] == TOF_OBJ_GRID) {
+            T += 2 * (size_t)std::max(d.object_grid[5 * o], 0) * (size_t)std::max(d.object_grid[5 * o + 1], 0);
+            ++mesh;
+        }
+    const size_t V = (size_t)std::max(d.num_vertices, 1), O = (size_t)d.num_objects, N = mesh + T + 1;
+    return O * (sizeof(Obj) + 4) + (size_t)d.num_materials * sizeof(Mat) + T * (sizeof(TriInfo) + 16 + 4) +
+           V * (16 + 4) + 2 * (48 * O + 16 * V + (sizeof(Node4) + 4) * N + 48 * std::max<size_t>(T, 1)) + 64 * 1024;
 }
 
 tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
@@ -286,6 +302,13 @@ const char* tof_status_string(tof_status s) {
         case TOF_ERR_UNIMPLEMENTED: return "unimplemented";
     }
     return "unknown status";
+}
+
+tof_status tof_footprint(const tof_scene_desc* scene, const tof_sensor_desc* sensor, size_t* bytes) {
+    if (!scene || !sensor || !bytes || scene->num_objects < 1 || !scene->object_type || !scene->object_grid)
+        return TOF_ERR_INVALID_ARG;
+    *bytes = scene_footprint(*scene) + sensor_footprint(*sensor);
+    return TOF_OK;
 }
 
 tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64_t seed) {
@@ -754,6 +777,7 @@ tof_status run_shifts(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A,
     const size_t per_shift = mode == 0 ? 4 : 2;
     const size_t ncounters = (size_t)tofd::kRaySubQueues * tofd::kCounterStride;
     const size_t NQ = tofd::kRaySubQueues;
+    const unsigned grid = (unsigned)(tofh::chunk_quantum(c->max_tasks) / 128);
     auto vis = [&](int slot, const tofd::RayQueue& q, float* kill) -> hipError_t {
         hipError_t e = timer_mark(c, kv, st);
         if (e != hipSuccess) return e;
@@ -769,7 +793,7 @@ tof_status run_shifts(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A,
         tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
         HIP_TRY(timer_mark(c, kf, st));
         a.counters = c->counters + (size_t)kf * kBank;
-        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + tf, c->fwd, c->shv, qf, st);
+        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + tf, c->fwd, c->shv, qf, grid, st);
         HIP_TRY(timer_mark(c, kf, st));
         HIP_TRY(vis(0, qf, (float*)c->fwd));
     }
@@ -783,7 +807,7 @@ tof_status run_shifts(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A,
         HIP_TRY(timer_mark(c, km, st));
         a.counters = c->counters + (size_t)km * kBank;
         tofh::launch_mis(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + tm, c->fwd, c->shv, c->term, lq,
-                         qm, st);
+                         qm, grid, st);
         HIP_TRY(timer_mark(c, km, st));
         HIP_TRY(vis(mode == 0 ? 1 : 0, qm, c->term));
     }

@@ -60,13 +60,18 @@ void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, in
 void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const tofd::ResSet& second,
                   const int* links, int ncand, uint2* items, uint32_t* task0, uint2* tasks, uint32_t* count,
                   uint32_t* out_mask, hipStream_t st);
-// Grids of the shift and visibility launches.  The shift kernels always run
-// kShiftGrid blocks of 128 lanes in a grid-stride loop; with chunks that are
-// multiples of kShiftGrid * 128 lanes every ray sub-queue receives the rays of
-// exactly chunk / kRaySubQueues lanes.
+// Grids of the shift and visibility launches.  The shift kernels run a
+// fixed grid of G blocks of 128 lanes (G a multiple of the 64 queue parts, at
+// most kShiftGrid) in a grid-stride loop over chunks of tasks that are
+// multiples of G * 128 (the chunk quantum): every sub-queue then receives the
+// work of exactly chunk / 64 tasks.  Small passes get a small grid, so that
+// their queues stay small.
 constexpr unsigned kShiftGrid = 8192;
 constexpr unsigned kVisGrid = 8192;
-constexpr size_t kChunkQuantum = (size_t)kShiftGrid * 128;
+inline size_t chunk_quantum(size_t tasks) {
+    const size_t blocks = std::min<size_t>(kShiftGrid, ((tasks + 127) / 128 + 63) / 64 * 64);
+    return std::max<size_t>(blocks, 64) * 128;
+}
 
 // Shifts of a reuse pass, over a chunk of their index range: the forward
 // shifts into q of tasks [t_begin, t_end) (fwd[t], shv[2t..2t+1]), then the MIS
@@ -76,13 +81,13 @@ constexpr size_t kChunkQuantum = (size_t)kShiftGrid * 128;
 // chunk must not queue more rays than q.cap (at most 4 per shift).
 void launch_fwd(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
-                float4* fwd, float4* shv, const tofd::RayQueue& q, hipStream_t st);
+                float4* fwd, float4* shv, const tofd::RayQueue& q, unsigned grid, hipStream_t st);
 // MIS shifts of tasks [t_begin, t_end): the pairs (task, neighbour) that need
 // one are listed in lq (at most K per task), then shifted.
 void launch_mis(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
                 const float4* fwd, const float4* shv, float* term, const tofd::IdxQueue& lq,
-                const tofd::RayQueue& q, hipStream_t st);
+                const tofd::RayQueue& q, unsigned grid, hipStream_t st);
 void launch_vis(const FrameArgs& a, int slot, const tofd::RayQueue& q, float* kill, hipStream_t st);
 // Weighted reservoir merge of each item's candidates into `out`.
 void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,

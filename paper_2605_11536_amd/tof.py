@@ -111,6 +111,21 @@ def lib():
         L.tof_get_kernel_times.restype = C.c_int
         L.tof_status_string.argtypes = [C.c_int]
         L.tof_status_string.restype = C.c_char_p
+        L.tof_footprint.argtypes = [C.POINTER(tof_scene_desc), C.POINTER(tof_sensor_desc), C.POINTER(C.c_size_t)]
+        L.tof_server_create.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_size_t]
+        L.tof_server_destroy.argtypes = [C.c_void_p]
+        L.tof_server_destroy.restype = None
+        L.tof_server_open.argtypes = [C.c_void_p, C.POINTER(tof_scene_desc), C.POINTER(tof_sensor_desc), C.c_uint64,
+                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tof_server_submit.argtypes = [C.c_void_p, C.c_int, C.POINTER(tof_frame_desc), C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]
+        L.tof_server_query.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]
+        L.tof_server_wait.argtypes = [C.c_void_p, C.c_uint64]
+        L.tof_server_close.argtypes = [C.c_void_p, C.c_int]
+        L.tof_server_info.argtypes = [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        for f in ("tof_footprint", "tof_server_create", "tof_server_open", "tof_server_submit", "tof_server_query",
+                  "tof_server_wait", "tof_server_close", "tof_server_info"):
+            getattr(L, f).restype = C.c_int
         for f in ("tof_create", "tof_scene_upload", "tof_sensor_set", "tof_render_frame",
                   "tof_reservoirs_reset", "tof_get_stats"):
             getattr(L, f).restype = C.c_int
@@ -142,7 +157,8 @@ def tof_destroy(h) -> None:
         lib().tof_destroy(h)
 
 
-def tof_scene_upload(h, scene) -> None:
+def scene_desc(scene):
+    """The C description of a scene and the arrays it points into (keep both)."""
     arrs = dict(
         t=np.ascontiguousarray(scene.obj_type, dtype=np.int32),
         m=np.ascontiguousarray(scene.obj_material, dtype=np.int32),
@@ -156,7 +172,20 @@ def tof_scene_upload(h, scene) -> None:
                        _ptr(arrs["g"], _i32p), _ptr(arrs["s"], _f32p), int(arrs["mt"].shape[0]),
                        _ptr(arrs["mt"], _i32p), _ptr(arrs["mp"], _f32p), int(arrs["v"].shape[0]),
                        _ptr(arrs["v"], _f32p), float(scene.scene_scale))
+    return d, arrs
+
+
+def tof_scene_upload(h, scene) -> None:
+    d, _arrs = scene_desc(scene)
     _check("tof_scene_upload", lib().tof_scene_upload(h, C.byref(d)))
+
+
+def tof_footprint(scene, sensor) -> int:
+    d, _arrs = scene_desc(scene)
+    sd = sensor_desc(sensor)
+    n = C.c_size_t(0)
+    _check("tof_footprint", lib().tof_footprint(C.byref(d), C.byref(sd), C.byref(n)))
+    return int(n.value)
 
 
 def sensor_desc(sensor) -> tof_sensor_desc:
@@ -316,6 +345,90 @@ class Renderer:
     def close(self):
         if self.h:
             tof_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# serving (tof_server_*): argument marshalling only
+# ---------------------------------------------------------------------------
+class Server:
+    """Request loop over render streams on one device (see include/tof.h)."""
+
+    def __init__(self, hbm_budget_bytes: int, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the ToF ReSTIR library runs on HIP devices only")
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        _check("tof_server_create", lib().tof_server_create(C.byref(h), device, int(hbm_budget_bytes)))
+        self.h = h
+        self.sensors = {}
+
+    def open(self, scene, sensor):
+        """Returns (stream id, admitted now)."""
+        d, _arrs = scene_desc(scene)
+        sd = sensor_desc(sensor)
+        sid, adm = C.c_int(-1), C.c_int(0)
+        _check("tof_server_open", lib().tof_server_open(self.h, C.byref(d), C.byref(sd), int(sensor.seed),
+                                                         C.byref(sid), C.byref(adm)))
+        self.sensors[sid.value] = sensor
+        return sid.value, bool(adm.value)
+
+    def outputs(self, sid):
+        """Fresh output tensors for a frame of stream sid."""
+        import torch
+        s = self.sensors[sid]
+        P = s.width * s.height
+        z = lambda n: torch.zeros(n, dtype=torch.float32, device=self.device)   # noqa: E731
+        return {"image": z(P) if s.gate_enabled else None, "hist": z(s.n_bins * P) if s.n_bins else None,
+                "pt_image": z(P) if s.gate_enabled else None, "pt_hist": z(s.n_bins * P) if s.n_bins else None}
+
+    def submit(self, sid, frame, out) -> int:
+        d, _xf = frame_desc(frame)
+        t = C.c_uint64(0)
+        _check("tof_server_submit", lib().tof_server_submit(self.h, sid, C.byref(d), _dptr(out["image"]),
+                                                             _dptr(out["hist"]), _dptr(out["pt_image"]),
+                                                             _dptr(out["pt_hist"]), C.byref(t)))
+        return int(t.value)
+
+    def query(self, ticket) -> bool:
+        done = C.c_int(0)
+        _check("tof_server_query", lib().tof_server_query(self.h, C.c_uint64(ticket), C.byref(done)))
+        return bool(done.value)
+
+    def wait(self, ticket) -> None:
+        _check("tof_server_wait", lib().tof_server_wait(self.h, C.c_uint64(ticket)))
+
+    def close_stream(self, sid) -> None:
+        _check("tof_server_close", lib().tof_server_close(self.h, sid))
+        self.sensors.pop(sid, None)
+
+    def info(self) -> dict:
+        used, adm, wait = C.c_size_t(0), C.c_int(0), C.c_int(0)
+        _check("tof_server_info", lib().tof_server_info(self.h, C.byref(used), C.byref(adm), C.byref(wait)))
+        return {"used_bytes": int(used.value), "admitted": adm.value, "waiting": wait.value}
+
+    @staticmethod
+    def fetch(sensor, out) -> dict:
+        shp = (sensor.height, sensor.width)
+        res = {}
+        for k in ("image", "pt_image"):
+            if out[k] is not None:
+                res[k] = out[k].cpu().numpy().reshape(shp)
+        for k in ("hist", "pt_hist"):
+            if out[k] is not None:
+                res[k] = out[k].cpu().numpy().reshape((sensor.n_bins,) + shp)
+        return res
+
+    def close(self):
+        if self.h is not None:
+            lib().tof_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -1,0 +1,89 @@
+"""Serving (tof_server_*): frames of several streams in flight together give
+the same results as each stream rendered alone, and admission by HBM
+footprint holds streams back until memory frees up."""
+import numpy as np
+import pytest
+
+from paper_2605_11536_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+GIB = 1 << 30
+
+
+def _workloads():
+    return {
+        "box": scenes.cornell_box(frames=3),
+        "glossy": scenes.glossy_dynamic(width=64, height=64, full_width=512, full_height=512, crop_x0=224,
+                                        crop_y0=200, frames=3),
+        "nlos": scenes.nlos_confocal(scan=32, frames=3, torus_nu=125, torus_nv=50),
+    }
+
+
+def _alone(w):
+    """Each frame of a stream rendered by itself with tof_render_frame."""
+    from paper_2605_11536_amd.tof import Renderer
+    r = Renderer(w.scene, w.sensor)
+    out = []
+    for fr in w.frames:
+        r.render(fr)
+        out.append(r.fetch())
+    r.close()
+    return out
+
+
+def test_streams_in_the_mix_match_alone():
+    from paper_2605_11536_amd.tof import Server
+    ws = _workloads()
+    alone = {k: _alone(w) for k, w in ws.items()}
+    srv = Server(hbm_budget_bytes=64 * GIB)
+    sids = {}
+    for k, w in ws.items():
+        sid, admitted = srv.open(w.scene, w.sensor)
+        assert admitted
+        sids[k] = sid
+    # interleaved submission, nothing waited for until the end
+    tickets = []
+    for f in range(3):
+        for k, w in ws.items():
+            out = srv.outputs(sids[k])
+            tickets.append((k, f, srv.submit(sids[k], w.frames[f], out), out))
+    for k, f, t, out in tickets:
+        print(f"case serving {k} frame {f}", flush=True)
+        srv.wait(t)
+        got = Server.fetch(ws[k].sensor, out)
+        for key, v in got.items():
+            assert np.array_equal(v, alone[k][f][key]), (k, f, key)
+    for sid in sids.values():
+        srv.close_stream(sid)
+    assert srv.info() == {"used_bytes": 0, "admitted": 0, "waiting": 0}
+    srv.close()
+
+
+def test_admission_waits_for_memory():
+    from paper_2605_11536_amd.tof import Server, TofError, tof_footprint
+    ws = _workloads()
+    a, b = ws["glossy"], ws["box"]
+    fa, fb = tof_footprint(a.scene, a.sensor), tof_footprint(b.scene, b.sensor)
+    srv = Server(hbm_budget_bytes=max(fa, fb) + min(fa, fb) // 2)   # room for one of them
+    sa, adm_a = srv.open(a.scene, a.sensor)
+    sb, adm_b = srv.open(b.scene, b.sensor)
+    assert adm_a and not adm_b
+    assert srv.info()["waiting"] == 1
+    out_b = srv.outputs(sb)
+    tb = srv.submit(sb, b.frames[0], out_b)
+    with pytest.raises(TofError):
+        srv.wait(tb)            # held: its stream is not admitted yet
+    assert not srv.query(tb)
+    out_a = srv.outputs(sa)
+    srv.wait(srv.submit(sa, a.frames[0], out_a))
+    srv.close_stream(sa)        # frees the memory: b is admitted, its held frame runs
+    info = srv.info()
+    assert info["admitted"] == 1 and info["waiting"] == 0
+    srv.wait(tb)
+    got = Server.fetch(b.sensor, out_b)
+    ref = _alone(b)[0]
+    for key, v in got.items():
+        assert np.array_equal(v, ref[key]), key
+    srv.close_stream(sb)
+    srv.close()
