@@ -88,6 +88,18 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=3, help="oracle frames timed for the CPU baseline")
     ap.add_argument("--cpu-crop", type=int, default=64, help="side of the oracle's crop for the CPU baseline")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true", help="run the serving leg alone")
+    ap.add_argument("--serve-streams", type=int, default=64)
+    ap.add_argument("--serve-frames", type=int, default=4, help="frames per stream")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="stream arrivals per second (Poisson); 0: set from --serve-load")
+    ap.add_argument("--serve-load", type=float, default=0.6,
+                    help="offered load (arrival rate x frames x mean solo frame time) that sets the rate")
+    ap.add_argument("--serve-period-ms", type=float, default=33.3, help="interval between a stream's frames")
+    ap.add_argument("--serve-budget-gib", type=float, default=224.0, help="HBM budget of the server")
+    ap.add_argument("--serve-seed", type=int, default=7)
+    ap.add_argument("--serve-timeout-s", type=float, default=240.0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="bytes of a plain device copy run after the timed region (HBM counter calibration)")
     return ap.parse_args()
@@ -143,6 +155,9 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.serving_only:
+        print(json.dumps({"serving": serving(args, torch)}), flush=True)
+        return
     from paper_2605_11536_amd import scenes
     from paper_2605_11536_amd.tof import Renderer
 
@@ -266,6 +281,8 @@ def main():
         result["equal_rmse_gate_only"] = gate_only(wl, frame_at, args, torch, Renderer, scenes)
 
     r.close()
+    if not args.no_serving:
+        result["serving"] = serving(args, torch)
     if args.copy_probe:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
         # the scale from counter units to bytes for the traffic figure
@@ -279,6 +296,122 @@ def main():
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(W, args.warmup, args.cpu_frames, args.cpu_crop)
     print(json.dumps(result), flush=True)
+
+
+SERVE_RES = (128, 256, 512, 1024)
+SERVE_BINS = (1, 64, 256)
+
+
+def serving(args, torch):
+    """Batched serving: render streams arrive as a Poisson process; each is a
+    box scene of the tiny-workload generator with its own seed, a resolution
+    drawn from SERVE_RES, a gate width from U[0.01, 0.2] and a bin count from
+    SERVE_BINS (bins over path lengths [2, 8]), and asks for `serve_frames`
+    frames, one every `serve_period_ms` from its arrival (open loop).  The
+    server admits streams by HBM footprint; a frame's latency runs from its
+    scheduled submission to its completion (admission wait included).  The
+    host loop submits due frames, polls tickets and closes a stream once its
+    last frame is done."""
+    from paper_2605_11536_amd import scenes
+    from paper_2605_11536_amd.tof import Renderer, Server, tof_footprint
+    rng = np.random.default_rng(args.serve_seed)
+    n, F, period = args.serve_streams, args.serve_frames, args.serve_period_ms * 1e-3
+    wls, fps_ = [], []
+    for i in range(n):
+        W = int(rng.choice(SERVE_RES))
+        nb = int(rng.choice(SERVE_BINS))
+        gw = float(rng.uniform(0.01, 0.2))
+        wl = scenes.cornell_box(width=W, height=W, frames=F, seed=1000 + i, gate_width=gw, n_bins=nb,
+                                bin_t0=2.0, bin_width=6.0 / nb)
+        wls.append(wl)
+        fps_.append(tof_footprint(wl.scene, wl.sensor))
+    # solo frame time of every (resolution, bins) class: one stream alone,
+    # frames 1..F-1 timed; the mix draws the classes uniformly
+    solo = {}
+    for W in SERVE_RES:
+        for nb in SERVE_BINS:
+            wl = scenes.cornell_box(width=W, height=W, frames=F, seed=1, gate_width=0.1, n_bins=nb, bin_t0=2.0,
+                                    bin_width=6.0 / nb)
+            r = Renderer(wl.scene, wl.sensor)
+            r.render(wl.frames[0])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for fr in wl.frames[1:]:
+                r.render(fr)
+            torch.cuda.synchronize()
+            solo[f"{W}x{nb}"] = (time.perf_counter() - t0) / max(F - 1, 1)
+            r.close()
+    mean_solo = float(np.mean(list(solo.values())))
+    rate = args.serve_rate if args.serve_rate > 0 else args.serve_load / (F * mean_solo)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, n))
+    arrive -= arrive[0]
+    budget = int(args.serve_budget_gib * (1 << 30))
+    srv = Server(hbm_budget_bytes=budget)
+    due = sorted((arrive[i] + j * period, i, j) for i in range(n) for j in range(F))
+    sid, outs, left = {}, {}, [F] * n
+    pending = {}
+    lat, adm_wait, lat_res = [], [], {}
+    peak_used, peak_adm, used_area = 0, 0, 0.0
+    k = 0
+    t_open = t_close = 0.0
+    t0 = time.perf_counter()
+    last = t0
+    while k < len(due) or pending:
+        now = time.perf_counter() - t0
+        while k < len(due) and due[k][0] <= now:
+            ts, i, j = due[k]
+            k += 1
+            if j == 0:
+                ta = time.perf_counter()
+                sid[i], _ = srv.open(wls[i].scene, wls[i].sensor)
+                outs[i] = srv.outputs(sid[i], pt=False)
+                t_open += time.perf_counter() - ta
+            pending[srv.submit(sid[i], wls[i].frames[j], outs[i])] = (i, j, ts)
+        for t in list(pending):
+            if srv.query(t):
+                i, j, ts = pending.pop(t)
+                done = time.perf_counter() - t0
+                lat.append(done - ts)
+                lat_res.setdefault(wls[i].sensor.width, []).append(done - ts)
+                if j == 0:
+                    adm_wait.append(done - ts)
+                left[i] -= 1
+                if left[i] == 0:
+                    ta = time.perf_counter()
+                    srv.close_stream(sid[i])
+                    t_close += time.perf_counter() - ta
+                    del outs[i]
+        info = srv.info()
+        tn = time.perf_counter()
+        used_area += info["used_bytes"] * (tn - last)
+        last = tn
+        peak_used = max(peak_used, info["used_bytes"])
+        peak_adm = max(peak_adm, info["admitted"])
+        if tn - t0 > args.serve_timeout_s:
+            raise RuntimeError(f"serving leg exceeded {args.serve_timeout_s} s")
+        time.sleep(2e-4)
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat = np.array(lat) * 1e3
+    pp = sum(w.sensor.width * w.sensor.height * w.sensor.b_tot for w in wls) * F
+    return {"streams": n, "frames_per_stream": F, "arrival_rate_per_s": round(rate, 4),
+            "offered_load": round(rate * F * mean_solo, 3),
+            "solo_frame_ms": {k: round(v * 1e3, 3) for k, v in solo.items()},
+            "host_open_s": round(t_open, 3), "host_close_s": round(t_close, 3),
+            "frame_period_ms": args.serve_period_ms, "hbm_budget_gib": args.serve_budget_gib,
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                           "p99": round(float(np.percentile(lat, 99)), 3),
+                           "max": round(float(lat.max()), 3)},
+            "first_frame_latency_ms_p50": round(float(np.percentile(adm_wait, 50)) * 1e3, 3),
+            "latency_ms_p50_by_res": {str(k): round(float(np.percentile(v, 50)) * 1e3, 3)
+                                      for k, v in sorted(lat_res.items())},
+            "frames_per_s": round(n * F / wall, 3), "pixel_planes_per_s": round(pp / wall, 1),
+            "wall_s": round(wall, 3), "peak_admitted": peak_adm,
+            "peak_used_gib": round(peak_used / (1 << 30), 2),
+            "mean_used_gib": round(used_area / wall / (1 << 30), 2),
+            "footprint_gib": {"min": round(min(fps_) / (1 << 30), 3), "max": round(max(fps_) / (1 << 30), 3),
+                              "sum": round(sum(fps_) / (1 << 30), 2)},
+            "mix": {"res": [int(w.sensor.width) for w in wls], "bins": [int(w.sensor.n_bins) for w in wls]}}
 
 
 def gate_only(wl, frame_at, args, torch, Renderer, scenes):

@@ -149,7 +149,12 @@ tof_status tof_scene_upload(tof_ctx* ctx, const tof_scene_desc* scene);
  * history (reservoirs are reset), except a move of gate_center alone: that
  * keeps the history, and the next frame's temporal reuse shifts the previous
  * frame's paths by the move, Delta l = new centre - old centre (Sec. 4.1,
- * time-gate shifting).  Bins never move. */
+ * time-gate shifting).  Bins never move.  TOF_ERR_INVALID_ARG for settings
+ * out of range, including width * height * planes * (spatial_k + 1) >= 2^32
+ * (work lists use 32-bit indices).  Per-(pixel, plane) reservoirs are
+ * allocated densely; the reuse passes run over chunks of work items whose
+ * work space is sized to a ray budget, so the footprint grows with the
+ * planes mainly through the reservoirs. */
 tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
 
 /* Render one frame asynchronously on `stream`: BVH build for the frame's
@@ -169,7 +174,7 @@ tof_status tof_render_frame(tof_ctx* ctx, const tof_frame_desc* frame, float* ou
 /* Drop the temporal history: the next frame renders without temporal reuse. */
 tof_status tof_reservoirs_reset(tof_ctx* ctx);
 
-/* Accumulated counters (synchronizes the device). */
+/* Accumulated counters (waits for the context's last frame). */
 tof_status tof_get_stats(tof_ctx* ctx, tof_stats* out);
 
 /* Reservoir planes of one reservoir set in host memory.  P = width*height,
@@ -295,12 +300,14 @@ tof_status tof_server_query(tof_server* server, uint64_t ticket, int* done);
  * TOF_ERR_NOT_READY while its stream waits for admission. */
 tof_status tof_server_wait(tof_server* server, uint64_t ticket);
 
-/* Close a stream after its queued frames finish; its memory admits waiting
- * streams.  Frames held by a stream that was never admitted end with
- * TOF_ERR_NOT_READY. */
+/* Close a stream; its queued frames still run.  Its memory is freed once no
+ * frame of any stream is in flight, or at once (waiting for the device) when
+ * a waiting stream needs it, and then admits waiting streams.  Frames held by
+ * a stream that was never admitted end with TOF_ERR_NOT_READY. */
 tof_status tof_server_close(tof_server* server, int stream_id);
 
-/* Device memory in use by admitted streams, their number, streams waiting. */
+/* Device memory held by admitted streams and by closed streams not yet
+ * freed, the number of admitted streams, streams waiting. */
 tof_status tof_server_info(tof_server* server, size_t* used_bytes, int* admitted, int* waiting);
 
 #ifdef __cplusplus

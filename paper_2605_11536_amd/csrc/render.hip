@@ -289,8 +289,11 @@ __global__ void k_neighbours(FrameArgs a, int round, const float* __restrict__ M
 // the previous frame's final reservoir at the reprojected pixel.  Mode 1
 // (spatial): the pixel's input reservoir and those of its k neighbours.  For
 // every plane non-empty in any candidate one item (pixel, plane | cmask << 16)
-// is emitted, cmask bit c marking the non-empty candidates, and one task
-// (item, c) per non-empty candidate.  Also clears the output mask.
+// is emitted, cmask bit c marking the non-empty candidates, with task0 = the
+// index of its first task (item, c), one per non-empty candidate; items and
+// tasks are numbered in the same block order, so task0 grows with the item
+// index and the tasks of an item range are contiguous.  count[0] and count[1]
+// receive the totals.  Also clears the output mask.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t cand_word(const FrameArgs& a, int mode, const uint32_t* m1, const uint32_t* m2,
                                               const int* links, int c, int w, int pix) {
@@ -317,8 +320,12 @@ __device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t& ea
         __syncthreads();
     }
     if (threadIdx.x == 255) {
-        s_base[0] = atomicAdd(count, s_a[255]);
-        s_base[1] = atomicAdd(count + 1, s_b[255]);
+        // one 64-bit add for both totals (count[0] the low word), so that the
+        // blocks take their item and task ranges in the same order
+        const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(count),
+                                                 ((unsigned long long)s_b[255] << 32) | s_a[255]);
+        s_base[0] = (uint32_t)old;
+        s_base[1] = (uint32_t)(old >> 32);
     }
     __syncthreads();
     ea = s_base[0] + s_a[threadIdx.x] - a;
@@ -329,8 +336,7 @@ __device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t& ea
 __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint32_t* __restrict__ m1,
                                                const uint32_t* __restrict__ m2, const int* __restrict__ links,
                                                int ncand, uint2* __restrict__ items, uint32_t* __restrict__ task0,
-                                               uint2* __restrict__ tasks, uint32_t* __restrict__ count,
-                                               uint32_t* __restrict__ out_mask) {
+                                               uint32_t* __restrict__ count, uint32_t* __restrict__ out_mask) {
     const int P = a.s.P;
     int pix = blockIdx.x * 256 + threadIdx.x;
     bool valid = pix < P && a.F.g[0].gb_obj[pix] >= 0;
@@ -364,12 +370,35 @@ __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint
                 uint32_t cm = 0;
                 task0[pi] = pt_;
                 for (int c = 0; c < ncand; ++c)
-                    if ((wm[c] >> b) & 1u) {
-                        cm |= 1u << c;
-                        tasks[pt_++] = make_uint2(pi, (uint32_t)c);
-                    }
+                    if ((wm[c] >> b) & 1u) cm |= 1u << c;
+                pt_ += (uint32_t)__popc(cm);
                 items[pi++] = make_uint2((uint32_t)pix, (uint32_t)(32 * w + b) | (cm << 16));
             }
+        }
+    }
+}
+
+// Tasks of the item chunk [i0, i0 + ci): tasks[t - tb] = (item, c), tb =
+// task0[i0]; win = (tb, number of tasks in the chunk) for the later kernels
+// of the chunk (both 0 for a chunk past the last item).
+__global__ void __launch_bounds__(256) k_tasks(const uint2* __restrict__ items, const uint32_t* __restrict__ task0,
+                                               const uint32_t* __restrict__ count, uint32_t i0, uint32_t ci,
+                                               uint2* __restrict__ tasks, uint32_t* __restrict__ win) {
+    const uint32_t ni = count[0];
+    const uint32_t ie = ni - i0 > ci ? i0 + ci : ni;   // used only when i0 < ni
+    const uint32_t tb = i0 < ni ? task0[i0] : 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        win[0] = tb;
+        win[1] = i0 < ni ? (ie < ni ? task0[ie] : count[1]) - tb : 0u;
+    }
+    if (i0 >= ni) return;
+    for (uint32_t i = i0 + blockIdx.x * 256 + threadIdx.x; i < ie; i += gridDim.x * 256) {
+        uint32_t cm = items[i].y >> 16;
+        uint32_t t = task0[i] - tb;
+        while (cm) {
+            const int c = __ffs(cm) - 1;
+            cm &= cm - 1;
+            tasks[t++] = make_uint2(i, (uint32_t)c);
         }
     }
 }
@@ -396,15 +425,15 @@ __device__ __forceinline__ int cand_src(int mode, const int* links, int P, int p
 
 TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
                        const uint2* __restrict__ items, const uint2* __restrict__ tasks,
-                       const uint32_t* __restrict__ count, uint32_t t_begin, uint32_t t_end,
-                       float4* __restrict__ fwd, float4* __restrict__ shv, RayQueue q) {
+                       const uint32_t* __restrict__ win, float4* __restrict__ fwd, float4* __restrict__ shv,
+                       RayQueue q) {
     __shared__ uint32_t stk[kStackDepth * kTB];
     Counters st = {};
     Tracer tr{a.S, stk + threadIdx.x, kTB, kStackDepth, st};
     const Sens& s = a.s;
     const int P = s.P;
-    const uint32_t n = min(count[1], t_end);
-    for (uint32_t t = t_begin + blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
+    const uint32_t n = win[1];
+    for (uint32_t t = blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
         const uint2 task = tasks[t];
         const uint2 item = items[task.x];
         const int c = (int)task.y;
@@ -434,19 +463,18 @@ TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
     flush_counters(st, a.counters);
 }
 
-// MIS work list: for tasks [t_begin, t_end), every (task, neighbour l) pair
+// MIS work list: for the tasks of the chunk, every (task, neighbour l) pair
 // that needs a shift -- all neighbours of a canonical task, the neighbours
 // other than the source of a forward-shifted one, none after a failed forward
 // shift, never an off-screen neighbour -- as g = t * K + l; term[g] = 0 for all.
 __global__ void __launch_bounds__(kTB) k_mis_list(FrameArgs a, int mode, const int* __restrict__ links,
                                                   const uint2* __restrict__ items, const uint2* __restrict__ tasks,
-                                                  const uint32_t* __restrict__ count, uint32_t t_begin,
-                                                  uint32_t t_end, const float4* __restrict__ fwd,
+                                                  const uint32_t* __restrict__ win, const float4* __restrict__ fwd,
                                                   float* __restrict__ term, IdxQueue lq) {
     const int P = a.s.P;
     const uint32_t K = mode == 0 ? 1u : (uint32_t)a.s.k;
-    const uint32_t n = min(count[1], t_end);
-    for (uint32_t t = t_begin + blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
+    const uint32_t n = win[1];
+    for (uint32_t t = blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
         uint32_t valid = 0;
         const uint2 task = tasks[t];
         const int c = (int)task.y;
@@ -549,18 +577,22 @@ __global__ void __launch_bounds__(kTB) k_vis(FrameArgs a, int slot, RayQueue q, 
 __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, ResSet Bp,
                                                const int* __restrict__ links, const uint2* __restrict__ items,
                                                const uint32_t* __restrict__ task0, const uint32_t* __restrict__ count,
+                                               uint32_t i0, uint32_t ci, const uint32_t* __restrict__ win,
                                                const float4* __restrict__ fwd, const float* __restrict__ term,
                                                const float4* __restrict__ shv, int round, ResSet out) {
     const Sens& s = a.s;
     const int P = s.P;
     const int K = mode == 0 ? 1 : s.k;
     const int ncand = K + 1;
-    const uint32_t n = count[0];
-    for (uint32_t it = blockIdx.x * 256 + threadIdx.x; it < n; it += gridDim.x * 256) {
+    const uint32_t ni = count[0];
+    if (i0 >= ni) return;
+    const uint32_t n = ni - i0 > ci ? i0 + ci : ni;
+    const uint32_t tb = win[0];
+    for (uint32_t it = i0 + blockIdx.x * 256 + threadIdx.x; it < n; it += gridDim.x * 256) {
         const uint2 item = items[it];
         const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
         const uint32_t cm = item.y >> 16;
-        const uint32_t t0 = task0[it];
+        const uint32_t t0 = task0[it] - tb;
         const uint64_t fp = full_pixel(s, pix);
         const float mq = A.M[pix];
         Draw ut;
@@ -671,34 +703,36 @@ void launch_neighbours(const FrameArgs& a, int round, const ResSet& in, int* nb,
                        M_out);
 }
 void launch_items(const FrameArgs& a, int mode, const ResSet& first, const ResSet& second, const int* links,
-                  int ncand, uint2* items, uint32_t* task0, uint2* tasks, uint32_t* count, uint32_t* out_mask,
-                  hipStream_t st) {
+                  int ncand, uint2* items, uint32_t* task0, uint32_t* count, uint32_t* out_mask, hipStream_t st) {
     hipLaunchKernelGGL(k_items, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, mode, first.mask,
-                       second.mask, links, ncand, items, task0, tasks, count, out_mask);
+                       second.mask, links, ncand, items, task0, count, out_mask);
+}
+void launch_tasks(const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,
+                  uint2* tasks, uint32_t* win, hipStream_t st) {
+    hipLaunchKernelGGL(k_tasks, dim3(grid_for(ci, 256, 16384)), dim3(256), 0, st, items, task0, count, (uint32_t)i0,
+                       (uint32_t)ci, tasks, win);
 }
 void launch_fwd(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
-                float4* fwd, float4* shv, const RayQueue& q, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_fwd, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links,
-                       items, tasks, count, (uint32_t)t_begin, (uint32_t)t_end, fwd, shv, q);
+                const uint2* items, const uint2* tasks, const uint32_t* win, float4* fwd, float4* shv,
+                const RayQueue& q, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_fwd, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, win, fwd, shv, q);
 }
 void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
-                const float4* fwd, const float4* shv, float* term, const IdxQueue& lq, const RayQueue& q,
-                unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_mis_list, dim3(grid), dim3(kTB), 0, st, a, mode, links, items, tasks, count,
-                       (uint32_t)t_begin, (uint32_t)t_end, fwd, term, lq);
+                const uint2* items, const uint2* tasks, const uint32_t* win, const float4* fwd, const float4* shv,
+                float* term, const IdxQueue& lq, const RayQueue& q, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_mis_list, dim3(grid), dim3(kTB), 0, st, a, mode, links, items, tasks, win, fwd, term, lq);
     hipLaunchKernelGGL(k_mis, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, lq, fwd, shv,
                        term, q);
 }
-void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, hipStream_t st) {
-    hipLaunchKernelGGL(k_vis, dim3(kVisGrid), dim3(kTB), 0, st, a, slot, q, kill);
+void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_vis, dim3(grid), dim3(kTB), 0, st, a, slot, q, kill);
 }
 void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                  const uint2* items, const uint32_t* task0, const uint32_t* count, size_t max_items,
-                  const float4* fwd, const float* term, const float4* shv, int round, ResSet out, hipStream_t st) {
-    hipLaunchKernelGGL(k_merge, dim3(grid_for(max_items, 256, 32768)), dim3(256), 0, st, a, mode, A, Bp, links, items,
-                       task0, count, fwd, term, shv, round, out);
+                  const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,
+                  const uint32_t* win, const float4* fwd, const float* term, const float4* shv, int round, ResSet out,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_merge, dim3(grid_for(ci, 256, 32768)), dim3(256), 0, st, a, mode, A, Bp, links, items,
+                       task0, count, (uint32_t)i0, (uint32_t)ci, win, fwd, term, shv, round, out);
 }
 void launch_splat(const FrameArgs& a, const ResSet& shown, const float* pt, const float2* direct, float* out_image,
                   float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st) {

@@ -10,6 +10,14 @@
 // temporal reuse depends on it); frames of a waiting stream are held and
 // enqueued when it is admitted.  Completion is tracked with one HIP event per
 // frame.  All calls may come from any host thread (one mutex).
+//
+// Memory: the server allocates its whole HBM budget once, as one arena, plus
+// a small pinned host arena for the streams' upload rings.  An admitted
+// stream gets one contiguous region of its footprint (best fit) that its
+// context fills front to back, so admission calls no hipMalloc (whose page
+// clearing costs ~10 ms per GB) and closing calls no hipFree (which waits
+// for the whole device).  A closed stream's region returns to the arena once
+// its HIP stream is idle; waiting streams are then admitted in order.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,8 +29,55 @@
 #include <vector>
 
 #include "tof.h"
+#include "tof_internal.h"
 
 namespace {
+
+// best-fit allocator of [0, size) in 256-byte units (host bookkeeping only)
+class Arena {
+   public:
+    void reset(size_t size) {
+        holes_.clear();
+        if (size) holes_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t& off) {
+        bytes = round(bytes);
+        auto best = holes_.end();
+        for (auto it = holes_.begin(); it != holes_.end(); ++it)
+            if (it->second >= bytes && (best == holes_.end() || it->second < best->second)) best = it;
+        if (best == holes_.end()) return false;
+        off = best->first;
+        const size_t rest = best->second - bytes;
+        holes_.erase(best);
+        if (rest) holes_[off + bytes] = rest;
+        return true;
+    }
+    void free(size_t off, size_t bytes) {
+        bytes = round(bytes);
+        auto it = holes_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != holes_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            holes_.erase(nx);
+        }
+        if (it != holes_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                holes_.erase(it);
+            }
+        }
+    }
+    size_t largest() const {
+        size_t m = 0;
+        for (auto& h : holes_) m = std::max(m, h.second);
+        return m;
+    }
+
+   private:
+    static size_t round(size_t b) { return (b + 255) & ~(size_t)255; }
+    std::map<size_t, size_t> holes_;
+};
 
 // deep copy of a scene description (the caller's arrays may go away before
 // the stream is admitted)
@@ -62,23 +117,41 @@ struct Request {
     tof_status status = TOF_OK;
 };
 
+struct Region {
+    size_t dev_off = 0, dev_bytes = 0, host_off = 0, host_bytes = 0;
+};
+
 struct Stream {
     int id = -1;
     std::unique_ptr<SceneCopy> scene;
     tof_sensor_desc sensor{};
     uint64_t seed = 0;
-    size_t footprint = 0;
+    size_t footprint = 0, pinned = 0;
+    Region region;
     tof_ctx* ctx = nullptr;
     hipStream_t hs = nullptr;
-    bool admitted = false;
+    bool admitted = false, failed = false;
     std::deque<uint64_t> held;   // frames submitted before admission
 };
 
 }  // namespace
 
+struct Closed {
+    tof_ctx* ctx = nullptr;
+    hipStream_t hs = nullptr;
+    size_t footprint = 0;
+    Region region;
+};
+
 struct tof_server {
     int device = 0;
     size_t budget = 0, used = 0;
+    char* dev_base = nullptr;     // the HBM arena
+    char* host_base = nullptr;    // the pinned host arena
+    size_t host_size = 0;
+    Arena dev_arena, host_arena;
+    std::vector<hipStream_t> idle_streams;
+    std::vector<Closed> closed;   // closed streams whose region is not returned yet
     std::mutex mu;
     int next_stream = 0;
     uint64_t next_ticket = 1;
@@ -89,9 +162,12 @@ struct tof_server {
 
 namespace {
 
+constexpr size_t kPinnedArena = (size_t)64 << 20;
+
 tof_status hip_status(hipError_t e) { return e == hipSuccess ? TOF_OK : TOF_ERR_DEVICE; }
 
 tof_status dispatch(tof_server* s, Stream& st, Request& r) {
+    (void)s;
     tof_status e = tof_render_frame(st.ctx, &r.frame, r.out[0], r.out[1], r.out[2], r.out[3], (void*)st.hs);
     if (e == TOF_OK) e = hip_status(hipEventRecord(r.done, st.hs));
     r.status = e;
@@ -99,39 +175,89 @@ tof_status dispatch(tof_server* s, Stream& st, Request& r) {
     return e;
 }
 
-// create the context of a stream and enqueue its held frames
-tof_status admit(tof_server* s, Stream& st) {
-    tof_status e = tof_create(&st.ctx, s->device, st.footprint, st.seed);
+void release(tof_server* s, tof_ctx* ctx, hipStream_t hs, const Region& r) {
+    if (ctx) tof_destroy(ctx);   // region context: waits for its own frames only
+    if (hs) s->idle_streams.push_back(hs);
+    s->dev_arena.free(r.dev_off, r.dev_bytes);
+    s->host_arena.free(r.host_off, r.host_bytes);
+}
+
+// return the regions of closed streams whose HIP stream is idle
+void reap(tof_server* s) {
+    for (size_t i = 0; i < s->closed.size();) {
+        Closed& z = s->closed[i];
+        if (hipStreamQuery(z.hs) != hipSuccess) {
+            ++i;
+            continue;
+        }
+        release(s, z.ctx, z.hs, z.region);
+        s->used -= z.footprint;
+        s->closed[i] = s->closed.back();
+        s->closed.pop_back();
+    }
+}
+
+// Create the context of a stream in a region of the arenas and enqueue its
+// held frames.  *no_room when no hole fits it (nothing changed).
+tof_status admit(tof_server* s, Stream& st, bool* no_room) {
+    *no_room = false;
+    Region r;
+    r.dev_bytes = st.footprint;
+    r.host_bytes = st.pinned;
+    if (!s->dev_arena.alloc(r.dev_bytes, r.dev_off)) {
+        *no_room = true;
+        return TOF_OK;
+    }
+    if (!s->host_arena.alloc(r.host_bytes, r.host_off)) {
+        s->dev_arena.free(r.dev_off, r.dev_bytes);
+        *no_room = true;
+        return TOF_OK;
+    }
+    tof_status e = tofh::create_in_region(&st.ctx, s->device, s->dev_base + r.dev_off, r.dev_bytes,
+                                          s->host_base + r.host_off, r.host_bytes, st.seed);
     if (e == TOF_OK) e = tof_scene_upload(st.ctx, &st.scene->desc);
     if (e == TOF_OK) e = tof_sensor_set(st.ctx, &st.sensor);
-    if (e == TOF_OK) e = hip_status(hipStreamCreateWithFlags(&st.hs, hipStreamNonBlocking));
+    if (e == TOF_OK) {
+        if (!s->idle_streams.empty()) {
+            st.hs = s->idle_streams.back();
+            s->idle_streams.pop_back();
+        } else {
+            e = hip_status(hipStreamCreateWithFlags(&st.hs, hipStreamNonBlocking));
+        }
+    }
     if (e != TOF_OK) {
-        if (st.ctx) tof_destroy(st.ctx);
+        release(s, st.ctx, st.hs, r);
         st.ctx = nullptr;
+        st.hs = nullptr;
         return e;
     }
+    st.region = r;
     st.admitted = true;
     s->used += st.footprint;
     while (!st.held.empty()) {
-        Request& r = *s->requests[st.held.front()];
+        Request& q = *s->requests[st.held.front()];
         st.held.pop_front();
-        dispatch(s, st, r);
+        dispatch(s, st, q);
     }
     return TOF_OK;
 }
 
-// admit waiting streams, in order, while the first one fits
+// admit waiting streams, first come first served, while the first one fits
 void admit_waiting(tof_server* s) {
+    reap(s);
     while (!s->waiting.empty()) {
         Stream& st = s->streams[s->waiting.front()];
-        if (s->used + st.footprint > s->budget) break;
+        bool no_room = false;
+        const tof_status e = admit(s, st, &no_room);
+        if (no_room) break;
         s->waiting.pop_front();
-        if (admit(s, st) != TOF_OK) {   // its frames fail; the stream stays closed to new work
+        if (e != TOF_OK) {   // its frames fail; the stream stays closed to new work
             for (uint64_t t : st.held) {
-                s->requests[t]->status = TOF_ERR_DEVICE;
+                s->requests[t]->status = e;
                 s->requests[t]->dispatched = true;
             }
             st.held.clear();
+            st.failed = true;
         }
     }
 }
@@ -142,12 +268,28 @@ extern "C" {
 
 tof_status tof_server_create(tof_server** out, int device, size_t hbm_budget_bytes) {
     if (!out || hbm_budget_bytes == 0) return TOF_ERR_INVALID_ARG;
+    *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TOF_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return TOF_ERR_DEVICE;
     tof_server* s = new (std::nothrow) tof_server();
     if (!s) return TOF_ERR_OUT_OF_MEMORY;
     s->device = device;
-    s->budget = hbm_budget_bytes;
+    s->budget = (hbm_budget_bytes + 255) & ~(size_t)255;
+    s->host_size = kPinnedArena;
+    if (hipMalloc((void**)&s->dev_base, s->budget) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return TOF_ERR_OUT_OF_MEMORY;
+    }
+    if (hipHostMalloc((void**)&s->host_base, s->host_size) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(s->dev_base);
+        delete s;
+        return TOF_ERR_OUT_OF_MEMORY;
+    }
+    s->dev_arena.reset(s->budget);
+    s->host_arena.reset(s->host_size);
     *out = s;
     return TOF_OK;
 }
@@ -155,16 +297,15 @@ tof_status tof_server_create(tof_server** out, int device, size_t hbm_budget_byt
 void tof_server_destroy(tof_server* s) {
     if (!s) return;
     (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();
     for (auto& kv : s->requests)
-        if (kv.second->done) {
-            (void)hipEventSynchronize(kv.second->done);
-            (void)hipEventDestroy(kv.second->done);
-        }
-    for (auto& kv : s->streams) {
-        if (kv.second.hs) (void)hipStreamSynchronize(kv.second.hs);
-        if (kv.second.ctx) tof_destroy(kv.second.ctx);
-        if (kv.second.hs) (void)hipStreamDestroy(kv.second.hs);
-    }
+        if (kv.second->done) (void)hipEventDestroy(kv.second->done);
+    for (auto& kv : s->streams)
+        if (kv.second.admitted) release(s, kv.second.ctx, kv.second.hs, kv.second.region);
+    for (Closed& z : s->closed) release(s, z.ctx, z.hs, z.region);
+    for (hipStream_t h : s->idle_streams) (void)hipStreamDestroy(h);
+    (void)hipFree(s->dev_base);
+    (void)hipHostFree(s->host_base);
     delete s;
 }
 
@@ -174,8 +315,9 @@ tof_status tof_server_open(tof_server* s, const tof_scene_desc* scene, const tof
     size_t fp = 0;
     tof_status e = tof_footprint(scene, sensor, &fp);
     if (e != TOF_OK) return e;
+    const size_t pinned = tofh::scene_pinned_bytes(*scene);
     std::lock_guard<std::mutex> lock(s->mu);
-    if (fp > s->budget) return TOF_ERR_OUT_OF_MEMORY;   // could never be admitted
+    if (fp > s->budget || pinned > s->host_size) return TOF_ERR_OUT_OF_MEMORY;   // could never be admitted
     if (hipSetDevice(s->device) != hipSuccess) return TOF_ERR_DEVICE;
     const int id = s->next_stream++;
     Stream& st = s->streams[id];
@@ -184,10 +326,11 @@ tof_status tof_server_open(tof_server* s, const tof_scene_desc* scene, const tof
     st.sensor = *sensor;
     st.seed = seed;
     st.footprint = fp;
+    st.pinned = pinned;
     s->waiting.push_back(id);
     admit_waiting(s);
-    if (!st.admitted && (s->waiting.empty() || std::find(s->waiting.begin(), s->waiting.end(), id) == s->waiting.end())) {
-        s->streams.erase(id);   // admission itself failed
+    if (st.failed) {   // admission itself failed (invalid settings, device error)
+        s->streams.erase(id);
         return TOF_ERR_DEVICE;
     }
     *stream_id = id;
@@ -200,7 +343,7 @@ tof_status tof_server_submit(tof_server* s, int stream_id, const tof_frame_desc*
     if (!s || !frame || !frame->object_xforms || !ticket) return TOF_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(s->mu);
     auto it = s->streams.find(stream_id);
-    if (it == s->streams.end()) return TOF_ERR_INVALID_ARG;
+    if (it == s->streams.end() || it->second.failed) return TOF_ERR_INVALID_ARG;
     Stream& st = it->second;
     if (hipSetDevice(s->device) != hipSuccess) return TOF_ERR_DEVICE;
     std::unique_ptr<Request> r(new Request());
@@ -239,6 +382,7 @@ tof_status tof_server_query(tof_server* s, uint64_t ticket, int* done) {
     *done = 1;
     (void)hipEventDestroy(r.done);
     s->requests.erase(it);
+    if (!s->closed.empty()) admit_waiting(s);
     return st;
 }
 
@@ -265,10 +409,8 @@ tof_status tof_server_close(tof_server* s, int stream_id) {
     Stream& st = it->second;
     if (hipSetDevice(s->device) != hipSuccess) return TOF_ERR_DEVICE;
     if (st.admitted) {
-        if (hipStreamSynchronize(st.hs) != hipSuccess) return TOF_ERR_DEVICE;
-        tof_destroy(st.ctx);
-        (void)hipStreamDestroy(st.hs);
-        s->used -= st.footprint;
+        // its region returns once its queued frames are done (see reap)
+        s->closed.push_back(Closed{st.ctx, st.hs, st.footprint, st.region});
     } else {
         for (auto w = s->waiting.begin(); w != s->waiting.end(); ++w)
             if (*w == stream_id) {
@@ -288,6 +430,7 @@ tof_status tof_server_close(tof_server* s, int stream_id) {
 tof_status tof_server_info(tof_server* s, size_t* used_bytes, int* admitted, int* waiting) {
     if (!s) return TOF_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(s->mu);
+    reap(s);
     int a = 0;
     for (auto& kv : s->streams) a += kv.second.admitted ? 1 : 0;
     if (used_bytes) *used_bytes = s->used;

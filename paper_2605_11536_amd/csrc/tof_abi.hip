@@ -22,6 +22,7 @@ constexpr size_t kCounterBytes = (size_t)TOF_K_COUNT * kBank * sizeof(unsigned l
 struct Alloc {
     std::vector<void*> ptrs;
     size_t bytes = 0;
+    size_t off0 = SIZE_MAX;   // in a region: offset of the first allocation
 };
 
 struct GeomBuf {
@@ -46,6 +47,15 @@ struct SlotHost {
     float* gb_xi1 = nullptr;
     float4* gb_p = nullptr;
     float4* gb_n = nullptr;
+};
+
+// A reuse pass runs over chunks of items whose tasks, terms and queued rays
+// fit one workspace: at most `rays` visibility rays per chunk; per mode (0
+// temporal, 1 spatial) ct tasks and ci = ct / (K + 1) items per chunk, the
+// shift kernels on `grid` blocks and the visibility kernel on `vis_grid`.
+struct ChunkPlan {
+    size_t rays = 0, ct[2] = {0, 0}, ci[2] = {0, 0}, task_cap = 0, term_cap = 0, ray_cap = 0;
+    unsigned grid[2] = {0, 0}, vis_grid[2] = {0, 0};
 };
 
 }  // namespace
@@ -89,25 +99,34 @@ struct tof_ctx {
     float2* direct = nullptr;
     int* prev_pix = nullptr;
     int* nb = nullptr;
-    uint2* items = nullptr;
-    uint2* tasks = nullptr;
+    uint2* items = nullptr;    // [max_items]
     uint32_t* task0 = nullptr; // [max_items]: first task of each item
-    float4* fwd = nullptr;     // [max_tasks]: forward-shift terms per task
-    float4* shv = nullptr;     // [2 * max_tasks]: fields rewritten by each forward shift
-    float* term = nullptr;     // [max_tasks * max(k, 1)]: MIS terms per (task, neighbour)
+    // workspace of one item chunk (sizes in plan)
+    uint2* tasks = nullptr;    // [task_cap]
+    float4* fwd = nullptr;     // [task_cap]: forward-shift terms per task
+    float4* shv = nullptr;     // [2 * task_cap]: fields rewritten by each forward shift
+    float* term = nullptr;     // [term_cap]: MIS terms per (task, neighbour)
     float4* rays = nullptr;    // [2 * ray_cap]: queued visibility segments
     uint32_t* ray_count = nullptr;
-    size_t ray_cap = 0;
-    uint32_t* mis_list = nullptr;   // [max(k, 1) * task chunk]: (task, neighbour) pairs of one chunk
+    uint32_t* mis_list = nullptr;   // [term_cap]: (task, neighbour) pairs of one chunk
     uint32_t* mis_count = nullptr;
-    uint32_t* count = nullptr;
-    size_t max_items = 0, max_tasks = 0;
+    uint32_t* count = nullptr;      // [0] items, [1] tasks, [2..3] window of the current chunk
+    size_t max_items = 0;
+    ChunkPlan plan;
     // misc
     unsigned long long* counters = nullptr;
     float* xf_pinned[2] = {nullptr, nullptr};
     hipEvent_t xf_ev[2] = {nullptr, nullptr};
     int xf_ring = 0;
     uint64_t frames = 0;
+    // region mode: device and pinned host memory handed over by the owner,
+    // filled front to back (no hipMalloc / hipFree of its own)
+    char* rbase = nullptr;
+    size_t rsize = 0, rused = 0;
+    char* hbase = nullptr;
+    size_t hsize = 0;
+    hipEvent_t done = nullptr;   // recorded after each frame on its stream
+    bool has_work = false;
     // kernel timing: event pairs recorded in order, reduced on query
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -124,11 +143,23 @@ struct tof_ctx {
 
 namespace {
 
+// wait for the context's own last frame (not for other work on the device)
+hipError_t quiesce(tof_ctx* c) { return c->has_work ? hipEventSynchronize(c->done) : hipSuccess; }
+
 tof_status dev_alloc(tof_ctx* c, Alloc& a, void** out, size_t bytes) {
     *out = nullptr;
     if (bytes == 0) bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
     if (c->budget && c->scene_mem.bytes + c->sensor_mem.bytes + bytes > c->budget) return TOF_ERR_OUT_OF_MEMORY;
+    if (c->rbase) {
+        if (c->rused + bytes > c->rsize) return TOF_ERR_OUT_OF_MEMORY;
+        if (a.off0 == SIZE_MAX) a.off0 = c->rused;
+        *out = c->rbase + c->rused;
+        c->rused += bytes;
+        a.ptrs.push_back(*out);
+        a.bytes += bytes;
+        return TOF_OK;
+    }
     if (hipMalloc(out, bytes) != hipSuccess) {
         *out = nullptr;
         (void)hipGetLastError();
@@ -139,10 +170,16 @@ tof_status dev_alloc(tof_ctx* c, Alloc& a, void** out, size_t bytes) {
     return TOF_OK;
 }
 
-void free_all(Alloc& a) {
-    for (void* p : a.ptrs) (void)hipFree(p);
+// in a region the space is reclaimed when the group is the last one allocated
+void free_all(tof_ctx* c, Alloc& a) {
+    if (c->rbase) {
+        if (a.off0 != SIZE_MAX && a.off0 + a.bytes == c->rused) c->rused = a.off0;
+    } else {
+        for (void* p : a.ptrs) (void)hipFree(p);
+    }
     a.ptrs.clear();
     a.bytes = 0;
+    a.off0 = SIZE_MAX;
 }
 
 template <typename T>
@@ -177,20 +214,28 @@ V3 hcross(V3 a, V3 b) { return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, 
 
 constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 
-// Queued visibility rays: enough for every shift of a pass at once when that
-// is at most 2^28 rays (8.6 GB), else the passes run in chunks.  Chunks are
-// multiples of the pass's chunk quantum; a shift queues at most 4 rays
-// across frames (temporal) and 2 within one frame (spatial).
-size_t round_up(size_t x, size_t q) { return (x + q - 1) / q * q; }
-// Tasks per chunk of a pass whose shifts queue at most `rays` rays per task.
-size_t task_chunk(size_t max_tasks, size_t rays) {
-    const size_t Q = tofh::chunk_quantum(max_tasks);
-    return std::min(round_up(std::max<size_t>(max_tasks, 1), Q), std::max(((size_t)1 << 28) / rays / Q, (size_t)1) * Q);
-}
-// temporal: 4 rays per shift, one MIS shift per task; spatial: 2 rays, k
-size_t ray_queue_cap(size_t max_tasks, size_t k) {
-    k = std::max<size_t>(k, 1);
-    return std::max(4 * task_chunk(max_tasks, 4), 2 * k * task_chunk(max_tasks, 2 * k));
+ChunkPlan plan_chunks(size_t P, size_t B, int k) {
+    ChunkPlan p;
+    const size_t K[2] = {1, (size_t)std::max(k, 1)};
+    const size_t seg[2] = {4, 2};   // visibility segments per shift: across two frames, within one
+    size_t dense = 0;
+    for (int m = 0; m < 2; ++m) dense = std::max(dense, seg[m] * K[m] * P * B * (K[m] + 1));
+    // a sixteenth of the rays of a pass over fully occupied planes, within
+    // [2^22, 2^28] rays (134 MB .. 8.6 GB of queue)
+    p.rays = std::min<size_t>((size_t)1 << 28, std::max<size_t>((size_t)1 << 22, dense / 16));
+    for (int m = 0; m < 2; ++m) {
+        const size_t all = P * B * (K[m] + 1);
+        const size_t raw = std::max<size_t>(1, std::min(p.rays / (seg[m] * K[m]), all));
+        const size_t G = tofh::shift_grid(raw), Q = G * 128;
+        p.ct[m] = std::max(Q, raw / Q * Q);
+        p.ci[m] = std::max<size_t>(1, p.ct[m] / (K[m] + 1));
+        p.grid[m] = (unsigned)G;
+        p.vis_grid[m] = (unsigned)tofh::shift_grid(seg[m] * K[m] * p.ct[m]);
+        p.task_cap = std::max(p.task_cap, p.ct[m]);
+        p.term_cap = std::max(p.term_cap, K[m] * p.ct[m]);
+        p.ray_cap = std::max(p.ray_cap, seg[m] * K[m] * p.ct[m]);
+    }
+    return p;
 }
 
 size_t sensor_footprint(const tof_sensor_desc& d) {
@@ -199,16 +244,17 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t words = (B + 31) / 32;
     size_t per_set = P * B * kRecBytes + P * 4 + P * words * 4;
     size_t gbuf = 2 * P * (4 + 4 + 4 + 16 + 16);
+    const ChunkPlan pl = plan_chunks(P, B, d.spatial_k);
     return 4 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
-           P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ +
-           P * B * 4 /*first task per item*/ +
-           P * B * ((size_t)std::max(d.spatial_k, 1) + 1) * (8 + 16 + 32 + 4 * (size_t)std::max(d.spatial_k, 1))
-           /*tasks, forward terms, shifted fields, MIS terms*/ +
-           32 * ray_queue_cap(P * B * ((size_t)std::max(d.spatial_k, 1) + 1), (size_t)std::max(d.spatial_k, 1)) +
-           4 * std::max((size_t)std::max(d.spatial_k, 1) *
-                            task_chunk(P * B * ((size_t)std::max(d.spatial_k, 1) + 1), 2 * (size_t)std::max(d.spatial_k, 1)),
-                        task_chunk(P * B * ((size_t)std::max(d.spatial_k, 1) + 1), 2)) /*work list*/ +
-           64 * 1024;
+           P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ + P * B * 4 /*first task per item*/ +
+           pl.task_cap * (8 + 16 + 32) /*tasks, forward terms, shifted fields*/ +
+           pl.term_cap * (4 + 4) /*MIS terms, MIS work list*/ + 32 * pl.ray_cap + 64 * 1024;
+}
+
+// one slot of the pinned upload ring: transforms, the tree over the objects
+// (at most one 4-wide node per mesh object) and its refit order
+size_t pinned_slot_bytes(size_t n_obj, size_t n_tlas_cap) {
+    return (sizeof(float) * 12 * n_obj + (sizeof(Node4) + sizeof(uint32_t)) * n_tlas_cap + 255) & ~(size_t)255;
 }
 
 // upper bound of the device memory tof_scene_upload allocates for a scene
@@ -311,7 +357,12 @@ tof_status tof_footprint(const tof_scene_desc* scene, const tof_sensor_desc* sen
     return TOF_OK;
 }
 
-tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64_t seed) {
+}  // extern "C"
+
+namespace {
+
+tof_status make_ctx(tof_ctx** out, int device, size_t budget, uint64_t seed, void* dev, size_t dev_bytes, void* host,
+                    size_t host_bytes) {
     if (!out) return TOF_ERR_INVALID_ARG;
     *out = nullptr;
     int ndev = 0;
@@ -324,10 +375,25 @@ tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64
     tof_ctx* c = new (std::nothrow) tof_ctx();
     if (!c) return TOF_ERR_OUT_OF_MEMORY;
     c->device = device;
-    c->budget = hbm_budget_bytes;
+    c->budget = budget;
     c->seed = seed;
-    if (hipMalloc(&c->counters, kCounterBytes) != hipSuccess || hipMemset(c->counters, 0, kCounterBytes) != hipSuccess) {
+    c->rbase = (char*)dev;
+    c->rsize = dev_bytes;
+    c->hbase = (char*)host;
+    c->hsize = host_bytes;
+    bool ok = true;
+    if (c->rbase) {
+        Alloc own;
+        ok = dev_alloc(c, own, (void**)&c->counters, kCounterBytes) == TOF_OK;
+    } else {
+        ok = hipMalloc(&c->counters, kCounterBytes) == hipSuccess;
+    }
+    // the null-stream fill must be complete before any stream reads the counters
+    ok = ok && hipMemset(c->counters, 0, kCounterBytes) == hipSuccess && hipStreamSynchronize(nullptr) == hipSuccess &&
+         hipEventCreateWithFlags(&c->done, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
         (void)hipGetLastError();
+        if (c->counters && !c->rbase) (void)hipFree(c->counters);
         delete c;
         return TOF_ERR_DEVICE;
     }
@@ -335,18 +401,49 @@ tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64
     return TOF_OK;
 }
 
+}  // namespace
+
+namespace tofh {
+
+tof_status create_in_region(tof_ctx** out, int device, void* dev, size_t dev_bytes, void* host, size_t host_bytes,
+                            uint64_t seed) {
+    if (!dev || !dev_bytes || !host || !host_bytes) return TOF_ERR_INVALID_ARG;
+    return make_ctx(out, device, dev_bytes, seed, dev, dev_bytes, host, host_bytes);
+}
+
+size_t scene_pinned_bytes(const tof_scene_desc& d) {
+    size_t mesh = 0;
+    for (int o = 0; o < d.num_objects; ++o) mesh += d.object_type[o] == TOF_OBJ_GRID ? 1 : 0;
+    return 2 * pinned_slot_bytes((size_t)d.num_objects, std::max<size_t>(mesh, 1));
+}
+
+}  // namespace tofh
+
+extern "C" {
+
+tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64_t seed) {
+    return make_ctx(out, device, hbm_budget_bytes, seed, nullptr, 0, nullptr, 0);
+}
+
 void tof_destroy(tof_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    (void)hipDeviceSynchronize();
-    free_all(c->scene_mem);
-    free_all(c->sensor_mem);
-    if (c->counters) (void)hipFree(c->counters);
+    if (c->rbase) {   // nothing to free: wait for the context's own work only
+        (void)quiesce(c);
+        for (int i = 0; i < 2; ++i)
+            if (c->xf_ev[i]) (void)hipEventSynchronize(c->xf_ev[i]);
+    } else {
+        (void)hipDeviceSynchronize();
+        free_all(c, c->scene_mem);
+        free_all(c, c->sensor_mem);
+        if (c->counters) (void)hipFree(c->counters);
+    }
     for (int i = 0; i < 2; ++i) {
-        if (c->xf_pinned[i]) (void)hipHostFree(c->xf_pinned[i]);
+        if (c->xf_pinned[i] && !c->hbase) (void)hipHostFree(c->xf_pinned[i]);
         if (c->xf_ev[i]) (void)hipEventDestroy(c->xf_ev[i]);
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->done) (void)hipEventDestroy(c->done);
     delete c;
 }
 
@@ -421,8 +518,8 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
             if (vobj[ob.voff + q] != o) return TOF_ERR_INVALID_SCENE;
     }
     HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(hipDeviceSynchronize());
-    free_all(c->scene_mem);
+    HIP_TRY(quiesce(c));
+    free_all(c, c->scene_mem);
     c->has_scene = false;
     c->prev_valid = false;
     c->slot[0].valid = c->slot[1].valid = false;
@@ -523,14 +620,21 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
     c->n_tri = T;
     c->n_sph = (int)sph.size();
     c->scale = d->scene_scale;
+    // per frame: transforms, the tree over the objects and its refit order
+    c->pinned_bytes = pinned_slot_bytes(objs.size(), (size_t)c->n_tlas_cap);
+    if (c->hbase && 2 * c->pinned_bytes > c->hsize) return TOF_ERR_OUT_OF_MEMORY;
     for (int i = 0; i < 2; ++i) {
-        if (c->xf_pinned[i]) (void)hipHostFree(c->xf_pinned[i]);
+        if (c->xf_pinned[i] && !c->hbase) (void)hipHostFree(c->xf_pinned[i]);
         c->xf_pinned[i] = nullptr;
-        // per frame: transforms, the tree over the objects and its refit order
-        c->pinned_bytes = sizeof(float) * 12 * objs.size() + (sizeof(Node4) + sizeof(uint32_t)) * c->n_tlas_cap;
-        HIP_TRY(hipHostMalloc((void**)&c->xf_pinned[i], c->pinned_bytes));
+        if (c->hbase)
+            c->xf_pinned[i] = (float*)(c->hbase + i * c->pinned_bytes);
+        else
+            HIP_TRY(hipHostMalloc((void**)&c->xf_pinned[i], c->pinned_bytes));
         if (!c->xf_ev[i]) HIP_TRY(hipEventCreateWithFlags(&c->xf_ev[i], hipEventDisableTiming));
     }
+    // the null-stream copies and fills must have landed before a frame on
+    // any other stream reads them
+    HIP_TRY(hipStreamSynchronize(nullptr));
     c->has_scene = true;
     return TOF_OK;
 }
@@ -552,6 +656,9 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
               (d->shift_mode == TOF_SHIFT_NAIVE || d->shift_mode == TOF_SHIFT_PATHLEN) &&
               d->debug_stage >= TOF_STAGE_CANONICAL && d->debug_stage <= TOF_STAGE_FINAL &&
               std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
+    // work-list entries (tasks of a pass over fully occupied planes) are 32-bit indices
+    ok = ok && (unsigned long long)d->width * d->height * B * (unsigned long long)(std::max(d->spatial_k, 1) + 1) <
+                   (1ULL << 32);
     if (!ok) return TOF_ERR_INVALID_ARG;
     if (c->has_sensor) {
         // a move of the gate alone keeps the history: the next temporal reuse
@@ -566,8 +673,8 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     }
     if (c->budget && c->scene_mem.bytes + sensor_footprint(*d) > c->budget) return TOF_ERR_OUT_OF_MEMORY;
     HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(hipDeviceSynchronize());
-    free_all(c->sensor_mem);
+    HIP_TRY(quiesce(c));
+    free_all(c, c->sensor_mem);
     c->has_sensor = false;
     c->prev_valid = false;
     c->slot[0].valid = c->slot[1].valid = false;
@@ -587,20 +694,18 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->direct, P));
     TOF_TRY(alloc_t(c, a, &c->prev_pix, P));
     TOF_TRY(alloc_t(c, a, &c->nb, P * (size_t)std::max(d->spatial_k, 1)));
-    const size_t ncand = (size_t)std::max(d->spatial_k, 1) + 1;
+    const ChunkPlan& pl = c->plan = plan_chunks(P, (size_t)B, d->spatial_k);
     TOF_TRY(alloc_t(c, a, &c->items, P * B));
-    TOF_TRY(alloc_t(c, a, &c->tasks, P * B * ncand));
     TOF_TRY(alloc_t(c, a, &c->task0, P * B));
-    TOF_TRY(alloc_t(c, a, &c->fwd, P * B * ncand));
-    TOF_TRY(alloc_t(c, a, &c->shv, 2 * P * B * ncand));
-    TOF_TRY(alloc_t(c, a, &c->term, P * B * ncand * (ncand - 1)));
-    c->ray_cap = ray_queue_cap(P * B * ncand, ncand - 1);
-    TOF_TRY(alloc_t(c, a, &c->rays, 2 * c->ray_cap));
+    TOF_TRY(alloc_t(c, a, &c->tasks, pl.task_cap));
+    TOF_TRY(alloc_t(c, a, &c->fwd, pl.task_cap));
+    TOF_TRY(alloc_t(c, a, &c->shv, 2 * pl.task_cap));
+    TOF_TRY(alloc_t(c, a, &c->term, pl.term_cap));
+    TOF_TRY(alloc_t(c, a, &c->rays, 2 * pl.ray_cap));
     TOF_TRY(alloc_t(c, a, &c->ray_count, (size_t)tofd::kRaySubQueues * tofd::kCounterStride));
-    TOF_TRY(alloc_t(c, a, &c->mis_list, (ncand - 1) * task_chunk(P * B * ncand, 2 * (ncand - 1))));
+    TOF_TRY(alloc_t(c, a, &c->mis_list, pl.term_cap));
     TOF_TRY(alloc_t(c, a, &c->mis_count, (size_t)tofd::kRaySubQueues * tofd::kCounterStride));
     TOF_TRY(alloc_t(c, a, &c->count, 64));
-    c->max_tasks = P * B * ncand;
     c->item_slots = 4 * 4096;
     c->item_used = 0;
     TOF_TRY(alloc_t(c, a, &c->item_hist, c->item_slots));
@@ -661,7 +766,7 @@ tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
         if (((m >> 8) & 15u) > (uint32_t)kMaxVerts || ((m >> 12) & 15u) > (uint32_t)kMaxVerts) return TOF_ERR_INVALID_ARG;
     }
     HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(quiesce(c));
     ResSet& r = c->sets[c->fin_prev];
     std::vector<float> packed(PB * kRecWords, 0.f);
     auto u2f = [](uint32_t u) { float f; std::memcpy(&f, &u, 4); return f; };
@@ -683,6 +788,7 @@ tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
     HIP_TRY(hipMemcpy(r.rec, packed.data(), sizeof(float) * packed.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(r.M, h->M, 4 * P, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(r.mask, h->mask, 4 * P * words, hipMemcpyHostToDevice));
+    HIP_TRY(hipStreamSynchronize(nullptr));
     c->prev_valid = true;
     return TOF_OK;
 }
@@ -690,7 +796,7 @@ tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
 tof_status tof_set_kernel_timing(tof_ctx* c, int enabled) {
     if (!c) return TOF_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(quiesce(c));
     c->timing = enabled != 0;
     c->ev_used = 0;
     for (int k = 0; k < TOF_K_COUNT; ++k) {
@@ -706,7 +812,7 @@ tof_status tof_set_kernel_timing(tof_ctx* c, int enabled) {
 tof_status tof_get_kernel_times(tof_ctx* c, tof_kernel_times* out) {
     if (!c || !out) return TOF_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(quiesce(c));
     timer_reduce(c);
     if (c->item_used) {
         std::vector<uint32_t> h(c->item_used);
@@ -743,7 +849,7 @@ tof_status tof_reservoirs_reset(tof_ctx* c) {
 tof_status tof_get_stats(tof_ctx* c, tof_stats* out) {
     if (!c || !out) return TOF_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(c->device));
-    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(quiesce(c));
     unsigned long long hb[TOF_K_COUNT * kBank];
     HIP_TRY(hipMemcpy(hb, c->counters, kCounterBytes, hipMemcpyDeviceToHost));
     unsigned long long h[kBank] = {};
@@ -764,52 +870,57 @@ tof_status tof_get_stats(tof_ctx* c, tof_stats* out) {
     return TOF_OK;
 }
 
-// Forward shifts, then MIS shifts of a reuse pass (mode 0 temporal, 1
-// spatial), in chunks whose queued visibility rays fit the ray queue; each
-// chunk's rays are traced before the next chunk is queued.
-tof_status run_shifts(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                      hipStream_t st) {
+// A reuse pass (mode 0 temporal, 1 spatial) after its work list is built:
+// for every chunk of plan.ci[mode] items, the chunk's tasks, their forward
+// shifts and the visibility of those, the MIS shifts and their visibility,
+// then the merge of the chunk's items into `out`.  Chunks past the last item
+// find an empty window and do nothing.
+tof_status run_pass(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
+                    int round, const ResSet& out, hipStream_t st) {
     const int kf = mode == 0 ? TOF_K_TEMPORAL_FWD : TOF_K_SPATIAL_FWD;
     const int km = mode == 0 ? TOF_K_TEMPORAL_MIS : TOF_K_SPATIAL_MIS;
     const int kv = mode == 0 ? TOF_K_TEMPORAL_VIS : TOF_K_SPATIAL_VIS;
+    const int kg = mode == 0 ? TOF_K_TEMPORAL_MERGE : TOF_K_SPATIAL_MERGE;
+    const ChunkPlan& pl = c->plan;
     const size_t K = mode == 0 ? 1 : (size_t)c->s.k;
     // at most 4 segments per shift across frames (temporal), 2 within one frame
-    const size_t per_shift = mode == 0 ? 4 : 2;
+    const size_t seg = mode == 0 ? 4 : 2;
+    const size_t ct = pl.ct[mode], ci = pl.ci[mode];
     const size_t ncounters = (size_t)tofd::kRaySubQueues * tofd::kCounterStride;
     const size_t NQ = tofd::kRaySubQueues;
-    const unsigned grid = (unsigned)(tofh::chunk_quantum(c->max_tasks) / 128);
+    uint32_t* win = c->count + 2;
+    // a chunk has at most ct tasks, ct / NQ per sub-queue (fixed grid)
+    const tofd::RayQueue qf{c->rays, c->ray_count, (uint32_t)(seg * ct / NQ)};
+    const tofd::RayQueue qm{c->rays, c->ray_count, (uint32_t)(seg * K * ct / NQ)};
+    const tofd::IdxQueue lq{c->mis_list, c->mis_count, (uint32_t)(K * ct / NQ)};
     auto vis = [&](int slot, const tofd::RayQueue& q, float* kill) -> hipError_t {
         hipError_t e = timer_mark(c, kv, st);
         if (e != hipSuccess) return e;
         a.counters = c->counters + (size_t)kv * kBank;
-        tofh::launch_vis(a, slot, q, kill, st);
+        tofh::launch_vis(a, slot, q, kill, pl.vis_grid[mode], st);
         return timer_mark(c, kv, st);
     };
-    // forward shifts: one per task; a chunk of tc tasks queues at most
-    // per_shift * tc rays, per_shift * tc / NQ in each sub-queue
-    const size_t tf = task_chunk(c->max_tasks, per_shift);
-    const tofd::RayQueue qf{c->rays, c->ray_count, (uint32_t)(per_shift * tf / NQ)};
-    for (size_t b = 0; b < c->max_tasks; b += tf) {
-        tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
+    for (size_t i0 = 0; i0 < c->max_items; i0 += ci) {
         HIP_TRY(timer_mark(c, kf, st));
+        tofh::launch_tasks(c->items, c->task0, c->count, i0, ci, c->tasks, win, st);
+        tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
         a.counters = c->counters + (size_t)kf * kBank;
-        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + tf, c->fwd, c->shv, qf, grid, st);
+        tofh::launch_fwd(a, mode, A, Bp, links, c->items, c->tasks, win, c->fwd, c->shv, qf, pl.grid[mode], st);
         HIP_TRY(timer_mark(c, kf, st));
         HIP_TRY(vis(0, qf, (float*)c->fwd));
-    }
-    // MIS shifts: at most K per task
-    const size_t tm = task_chunk(c->max_tasks, per_shift * K);
-    const tofd::RayQueue qm{c->rays, c->ray_count, (uint32_t)(per_shift * K * tm / NQ)};
-    const tofd::IdxQueue lq{c->mis_list, c->mis_count, (uint32_t)(K * tm / NQ)};
-    for (size_t b = 0; b < c->max_tasks; b += tm) {
+        HIP_TRY(timer_mark(c, km, st));
         tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
         tofh::launch_fill_u32(c->mis_count, 0u, ncounters, st);
-        HIP_TRY(timer_mark(c, km, st));
         a.counters = c->counters + (size_t)km * kBank;
-        tofh::launch_mis(a, mode, A, Bp, links, c->items, c->tasks, c->count, b, b + tm, c->fwd, c->shv, c->term, lq,
-                         qm, grid, st);
+        tofh::launch_mis(a, mode, A, Bp, links, c->items, c->tasks, win, c->fwd, c->shv, c->term, lq, qm,
+                         pl.grid[mode], st);
         HIP_TRY(timer_mark(c, km, st));
         HIP_TRY(vis(mode == 0 ? 1 : 0, qm, c->term));
+        HIP_TRY(timer_mark(c, kg, st));
+        a.counters = c->counters + (size_t)kg * kBank;
+        tofh::launch_merge(a, mode, A, Bp, links, c->items, c->task0, c->count, i0, ci, win, c->fwd, c->term, c->shv,
+                           round, out, st);
+        HIP_TRY(timer_mark(c, kg, st));
     }
     return TOF_OK;
 }
@@ -973,14 +1084,9 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         a.counters = c->counters + (size_t)TOF_K_TEMPORAL_PREP * kBank;
         tofh::launch_reproject(a, can, pf, c->prev_pix, tmp.M, st);
         tofh::launch_fill_u32(c->count, 0u, 2, st);
-        tofh::launch_items(a, 0, can, pf, c->prev_pix, 2, c->items, c->task0, c->tasks, c->count, tmp.mask, st);
+        tofh::launch_items(a, 0, can, pf, c->prev_pix, 2, c->items, c->task0, c->count, tmp.mask, st);
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_PREP, st));
-        TOF_TRY(run_shifts(c, a, 0, can, pf, c->prev_pix, st));
-        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MERGE, st));
-        a.counters = c->counters + (size_t)TOF_K_TEMPORAL_MERGE * kBank;
-        tofh::launch_merge(a, 0, can, pf, c->prev_pix, c->items, c->task0, c->count, c->max_items, c->fwd, c->term,
-                           c->shv, 0, tmp, st);
-        HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_MERGE, st));
+        TOF_TRY(run_pass(c, a, 0, can, pf, c->prev_pix, 0, tmp, st));
         if (item_slot) HIP_TRY(hipMemcpyAsync(item_slot, c->count, 8, hipMemcpyDeviceToDevice, st));
         cur_set = &tmp;
         temporal_done = true;
@@ -1002,14 +1108,9 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         a.counters = c->counters + (size_t)TOF_K_SPATIAL_PREP * kBank;
         tofh::launch_neighbours(a, r, in, c->nb, out.M, st);
         tofh::launch_fill_u32(c->count, 0u, 2, st);
-        tofh::launch_items(a, 1, in, in, c->nb, c->s.k + 1, c->items, c->task0, c->tasks, c->count, out.mask, st);
+        tofh::launch_items(a, 1, in, in, c->nb, c->s.k + 1, c->items, c->task0, c->count, out.mask, st);
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
-        TOF_TRY(run_shifts(c, a, 1, in, in, c->nb, st));
-        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MERGE, st));
-        a.counters = c->counters + (size_t)TOF_K_SPATIAL_MERGE * kBank;
-        tofh::launch_merge(a, 1, in, in, c->nb, c->items, c->task0, c->count, c->max_items, c->fwd, c->term, c->shv, r,
-                           out, st);
-        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_MERGE, st));
+        TOF_TRY(run_pass(c, a, 1, in, in, c->nb, r, out, st));
         if (item_slot && r == 0) HIP_TRY(hipMemcpyAsync(item_slot + 2, c->count, 8, hipMemcpyDeviceToDevice, st));
         cur_idx = out_idx;
     }
@@ -1025,6 +1126,8 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         timer_reduce(c);
     }
     if (hipGetLastError() != hipSuccess) return TOF_ERR_DEVICE;
+    HIP_TRY(hipEventRecord(c->done, st));
+    c->has_work = true;
     c->fin_prev = fin_new;
     c->prev_valid = true;
     c->frames++;

@@ -7,9 +7,20 @@
 #include <algorithm>
 #include <vector>
 
+#include "tof.h"
 #include "tof_device.h"
 
 namespace tofh {
+
+// Contexts whose memory an owner hands over (the serving loop): device memory
+// [dev, dev + dev_bytes) and pinned host memory [host, host + host_bytes) that
+// the context fills front to back (scene, then sensor; a later re-upload or
+// sensor change can reclaim only the group allocated last).  Destroying such
+// a context frees nothing and waits for its own frames only, not for the
+// device.  dev_bytes from tof_footprint, host_bytes from scene_pinned_bytes.
+tof_status create_in_region(tof_ctx** out, int device, void* dev, size_t dev_bytes, void* host, size_t host_bytes,
+                            uint64_t seed);
+size_t scene_pinned_bytes(const tof_scene_desc& d);
 
 struct FrameArgs {
     tofd::Sens s;
@@ -54,46 +65,46 @@ void launch_reproject(const FrameArgs& a, const tofd::ResSet& can, const tofd::R
 void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, int* nb, float* M_out,
                        hipStream_t st);
 // Work items (pixel, plane | cmask << 16) for every plane non-empty in any of
-// the ncand candidates, the index of each item's first task, and one
-// (item, candidate) task per non-empty candidate; count[0] = items,
-// count[1] = tasks.
+// the ncand candidates and the index of each item's first task (one task per
+// non-empty candidate); count[0] = items, count[1] = tasks.  Task indices grow
+// with the item index.
 void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const tofd::ResSet& second,
-                  const int* links, int ncand, uint2* items, uint32_t* task0, uint2* tasks, uint32_t* count,
-                  uint32_t* out_mask, hipStream_t st);
-// Grids of the shift and visibility launches.  The shift kernels run a
-// fixed grid of G blocks of 128 lanes (G a multiple of the 64 queue parts, at
-// most kShiftGrid) in a grid-stride loop over chunks of tasks that are
-// multiples of G * 128 (the chunk quantum): every sub-queue then receives the
-// work of exactly chunk / 64 tasks.  Small passes get a small grid, so that
-// their queues stay small.
+                  const int* links, int ncand, uint2* items, uint32_t* task0, uint32_t* count, uint32_t* out_mask,
+                  hipStream_t st);
+
+// A reuse pass runs over chunks of ci items; the chunk's tasks, forward and
+// MIS terms and queued rays live in a workspace sized for the chunk.  The
+// shift kernels run a fixed grid of G blocks of 128 lanes (G a multiple of
+// the 64 queue parts, at most kShiftGrid) in a grid-stride loop over at most
+// ct tasks, ct a multiple of G * 128, so that every sub-queue receives the
+// work of at most ct / 64 tasks.
 constexpr unsigned kShiftGrid = 8192;
 constexpr unsigned kVisGrid = 8192;
-inline size_t chunk_quantum(size_t tasks) {
-    const size_t blocks = std::min<size_t>(kShiftGrid, ((tasks + 127) / 128 + 63) / 64 * 64);
-    return std::max<size_t>(blocks, 64) * 128;
+inline size_t shift_grid(size_t tasks) {
+    return std::max<size_t>(64, std::min<size_t>(kShiftGrid, ((tasks + 127) / 128 + 63) / 64 * 64));
 }
 
-// Shifts of a reuse pass, over a chunk of their index range: the forward
-// shifts into q of tasks [t_begin, t_end) (fwd[t], shv[2t..2t+1]), then the MIS
-// shifts (task, neighbour) g in [g_begin, g_end) into every neighbour domain
-// (term[g]).  Each shift queues its visibility segments in q; launch_vis traces
-// them in the frame of `slot` and zeroes kill[owner] for blocked ones.  A
-// chunk must not queue more rays than q.cap (at most 4 per shift).
+// Tasks of items [i0, i0 + ci) into tasks[] (chunk-relative), and the
+// chunk's window win = (first task, task count).
+void launch_tasks(const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,
+                  uint2* tasks, uint32_t* win, hipStream_t st);
+// Forward shifts into q of the chunk's tasks t (fwd[t], shv[2t..2t+1]).  Each
+// shift queues its visibility segments in q; launch_vis traces them in the
+// frame of `slot` and zeroes kill[owner] for blocked ones.
 void launch_fwd(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
-                float4* fwd, float4* shv, const tofd::RayQueue& q, unsigned grid, hipStream_t st);
-// MIS shifts of tasks [t_begin, t_end): the pairs (task, neighbour) that need
-// one are listed in lq (at most K per task), then shifted.
-void launch_mis(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
-                const uint2* items, const uint2* tasks, const uint32_t* count, size_t t_begin, size_t t_end,
-                const float4* fwd, const float4* shv, float* term, const tofd::IdxQueue& lq,
+                const uint2* items, const uint2* tasks, const uint32_t* win, float4* fwd, float4* shv,
                 const tofd::RayQueue& q, unsigned grid, hipStream_t st);
-void launch_vis(const FrameArgs& a, int slot, const tofd::RayQueue& q, float* kill, hipStream_t st);
-// Weighted reservoir merge of each item's candidates into `out`.
+// MIS shifts of the chunk's tasks: the pairs (task, neighbour) g = t * K + l
+// that need one are listed in lq (at most K per task), then shifted (term[g]).
+void launch_mis(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
+                const uint2* items, const uint2* tasks, const uint32_t* win, const float4* fwd, const float4* shv,
+                float* term, const tofd::IdxQueue& lq, const tofd::RayQueue& q, unsigned grid, hipStream_t st);
+void launch_vis(const FrameArgs& a, int slot, const tofd::RayQueue& q, float* kill, unsigned grid, hipStream_t st);
+// Weighted reservoir merge of the candidates of items [i0, i0 + ci) into `out`.
 void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
-                  const uint2* items, const uint32_t* task0, const uint32_t* count, size_t max_items,
-                  const float4* fwd, const float* term, const float4* shv, int round, tofd::ResSet out,
-                  hipStream_t st);
+                  const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,
+                  const uint32_t* win, const float4* fwd, const float* term, const float4* shv, int round,
+                  tofd::ResSet out, hipStream_t st);
 void launch_splat(const FrameArgs& a, const tofd::ResSet& shown, const float* pt, const float2* direct,
                   float* out_image, float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st);
 

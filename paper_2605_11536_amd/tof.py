@@ -380,14 +380,22 @@ class Server:
         self.sensors[sid.value] = sensor
         return sid.value, bool(adm.value)
 
-    def outputs(self, sid):
-        """Fresh output tensors for a frame of stream sid."""
+    def outputs(self, sid, pt: bool = True):
+        """Output tensors for frames of stream sid (pt: also the plain-PT
+        outputs).  They are left uninitialised: the splat writes every
+        element, and no fill kernel on torch's stream may race with the
+        server's stream that writes them."""
         import torch
         s = self.sensors[sid]
         P = s.width * s.height
-        z = lambda n: torch.zeros(n, dtype=torch.float32, device=self.device)   # noqa: E731
-        return {"image": z(P) if s.gate_enabled else None, "hist": z(s.n_bins * P) if s.n_bins else None,
-                "pt_image": z(P) if s.gate_enabled else None, "pt_hist": z(s.n_bins * P) if s.n_bins else None}
+        e = lambda n: torch.empty(n, dtype=torch.float32, device=self.device)   # noqa: E731
+        out = {"image": e(P) if s.gate_enabled else None, "hist": e(s.n_bins * P) if s.n_bins else None,
+               "pt_image": e(P) if s.gate_enabled and pt else None,
+               "pt_hist": e(s.n_bins * P) if s.n_bins and pt else None}
+        # the blocks may come back from tensors whose last use is still queued
+        # on torch's stream, which the server's streams do not wait for
+        torch.cuda.current_stream(self.device).synchronize()
+        return out
 
     def submit(self, sid, frame, out) -> int:
         d, _xf = frame_desc(frame)
