@@ -141,7 +141,8 @@ tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64
 /* Release every device allocation of the context (synchronizes the device). */
 void tof_destroy(tof_ctx* ctx);
 
-/* Copy the scene to the device and validate it.  Drops reservoir history. */
+/* Copy the scene to the device and validate it (TOF_ERR_INVALID_SCENE for
+ * malformed objects or 2^28 triangles or more).  Drops reservoir history. */
 tof_status tof_scene_upload(tof_ctx* ctx, const tof_scene_desc* scene);
 
 /* Set sensor and time-domain settings and (re)allocate per-pixel state after

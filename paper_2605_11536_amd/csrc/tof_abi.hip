@@ -486,7 +486,8 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
             if (ob.nu < 1 || ob.nv < 1 || ob.nu > 65535 || ob.nv > 65535 || ob.voff < 0) return TOF_ERR_INVALID_SCENE;
             long long nvtx = (long long)(ob.nu + 1) * (ob.nv + 1);
             if (ob.voff + nvtx > d->num_vertices) return TOF_ERR_INVALID_SCENE;
-            if ((long long)tris.size() + 2LL * ob.nu * ob.nv > (1LL << 30)) return TOF_ERR_INVALID_SCENE;
+            // leaf references hold a 28-bit first slot
+            if ((long long)tris.size() + 2LL * ob.nu * ob.nv >= (1LL << 28)) return TOF_ERR_INVALID_SCENE;
             for (long long q = 0; q < nvtx; ++q) vobj[ob.voff + q] = o;
             int row = ob.nu + 1;
             for (int j = 0; j < ob.nv; ++j)

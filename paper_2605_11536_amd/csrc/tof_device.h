@@ -472,91 +472,134 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
         return false;
     };
     if (T > 0) {
-        int sp = 0;
-        uint32_t node = 0;
+        // Leaves are postponed (Aila and Laine 2009): a lane that meets leaf
+        // children keeps them as pending and, while other lanes of the wave
+        // still look for theirs, goes on through inner nodes, pushing leaves
+        // it meets meanwhile onto its stack; the wave then tests the pending
+        // leaves together, instead of one leaf phase per node visit with few
+        // lanes active.  Visit order does not change a result: closest hit
+        // is the minimum of (t, primitive id) over the triangles whose boxes
+        // the ray enters before the current best t, any hit is any of them.
+        constexpr uint32_t kDone = 0xFFFFFFFFu;   // not a leaf reference: leaves start below 2^28
         constexpr float kInfT = 3.0e38f;
-        auto push = [&](int n) {
+        int sp = 0;
+        uint32_t node = 0;           // inner node, leaf reference (bit 31), or kDone
+        uint32_t pmask = 0;          // pending leaves: bits of pcc
+        int4 pcc = make_int4(0, 0, 0, 0);
+        auto push = [&](uint32_t n) {
             if (sp < depth) {
-                stack[sp * stride] = (uint32_t)n;
+                stack[sp * stride] = n;
                 ++sp;
             } else {
                 st.c[ST_OVERFLOW]++;
             }
         };
+        auto pop = [&]() -> uint32_t {
+            if (sp == 0) return kDone;
+            --sp;
+            return stack[sp * stride];
+        };
         // any valid walk visits each node at most once, so this bound only
         // stops a malformed tree
         int budget = 2 * G.n_nodes + 64;
-        while (--budget > 0) {
-            if (node >= (uint32_t)G.n_nodes) {   // never for a well-formed tree
-                st.c[ST_OVERFLOW]++;
-                break;
+        while (node != kDone || pmask) {
+            // inner nodes until every lane of the wave has a pending leaf or
+            // is done; no speculation once the stack could not take a node's
+            // leaves
+            while (node < 0x80000000u && (pmask == 0 || sp + 4 <= depth)) {
+                if (--budget <= 0 || node >= (uint32_t)G.n_nodes) {   // never for a well-formed tree
+                    st.c[ST_OVERFLOW]++;
+                    node = kDone;
+                    sp = 0;
+                    break;
+                }
+                // the whole 128-byte node, loaded unconditionally
+                const float4* nq = reinterpret_cast<const float4*>(G.nodes + node);
+                const float4 lx = nq[0], ly = nq[1], lz = nq[2], hx = nq[3], hy = nq[4], hz = nq[5];
+                const int4 cc = reinterpret_cast<const int4*>(nq)[6];
+                const int nc = reinterpret_cast<const int4*>(nq)[7].x;
+                st.c[ST_NODES]++;
+                // all four boxes, without branches; children j >= nc are padding
+                float t0, t1, t2, t3;
+                const bool h0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, tb, t0);
+                const bool h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, tb, t1) && nc > 1;
+                const bool h2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, tb, t2) && nc > 2;
+                const bool h3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, tb, t3) && nc > 3;
+                const bool f0 = cc.x < 0, f1 = cc.y < 0, f2 = cc.z < 0, f3 = cc.w < 0;   // leaves
+                const uint32_t leaves = (h0 && f0 ? 1u : 0u) | (h1 && f1 ? 2u : 0u) | (h2 && f2 ? 4u : 0u) |
+                                        (h3 && f3 ? 8u : 0u);
+                if (leaves) {
+                    if (pmask == 0) {
+                        pmask = leaves;
+                        pcc = cc;
+                    } else {   // speculative: keep them for later
+                        if (leaves & 1u) push((uint32_t)cc.x);
+                        if (leaves & 2u) push((uint32_t)cc.y);
+                        if (leaves & 4u) push((uint32_t)cc.z);
+                        if (leaves & 8u) push((uint32_t)cc.w);
+                    }
+                }
+                // key = entry distance of an internal child that is hit, +inf otherwise
+                float k0 = (h0 && !f0) ? t0 : kInfT, k1 = (h1 && !f1) ? t1 : kInfT;
+                float k2 = (h2 && !f2) ? t2 : kInfT, k3 = (h3 && !f3) ? t3 : kInfT;
+                int n0 = cc.x, n1 = cc.y, n2 = cc.z, n3 = cc.w;
+                // sorting network on (key, node): nearest first
+                auto cswap = [](float& ka, int& na, float& kb, int& nb) {
+                    if (kb < ka) {
+                        const float kt = ka;
+                        ka = kb;
+                        kb = kt;
+                        const int nt = na;
+                        na = nb;
+                        nb = nt;
+                    }
+                };
+                if (any_hit) {
+                    // any hit: order does not matter for a ray that is not
+                    // blocked; only bring the nearest to the front
+                    cswap(k0, n0, k1, n1);
+                    cswap(k2, n2, k3, n3);
+                    cswap(k0, n0, k2, n2);
+                } else {
+                    cswap(k0, n0, k1, n1);
+                    cswap(k2, n2, k3, n3);
+                    cswap(k0, n0, k2, n2);
+                    cswap(k1, n1, k3, n3);
+                    cswap(k1, n1, k2, n2);
+                }
+                if (k0 < kInfT) {
+                    // the others onto the stack, farthest deepest
+                    if (k3 < kInfT) push((uint32_t)n3);
+                    if (k2 < kInfT) push((uint32_t)n2);
+                    if (k1 < kInfT) push((uint32_t)n1);
+                    node = (uint32_t)n0;
+                } else {
+                    node = pop();
+                }
+                // a leaf taken from the stack becomes the pending one if there is none
+                if (node != kDone && node >= 0x80000000u && pmask == 0) {
+                    pmask = 1u;
+                    pcc.x = (int)node;
+                    node = pop();
+                }
+                if (__all(pmask != 0)) break;
             }
-            // the whole 128-byte node, loaded unconditionally
-            const float4* nq = reinterpret_cast<const float4*>(G.nodes + node);
-            const float4 lx = nq[0], ly = nq[1], lz = nq[2], hx = nq[3], hy = nq[4], hz = nq[5];
-            const int4 cc = reinterpret_cast<const int4*>(nq)[6];
-            const int nc = reinterpret_cast<const int4*>(nq)[7].x;
-            st.c[ST_NODES]++;
-            // all four boxes, without branches; children j >= nc are padding
-            float t0, t1, t2, t3;
-            const bool h0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, tb, t0);
-            const bool h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, tb, t1) && nc > 1;
-            const bool h2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, tb, t2) && nc > 2;
-            const bool h3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, tb, t3) && nc > 3;
-            const bool f0 = cc.x < 0, f1 = cc.y < 0, f2 = cc.z < 0, f3 = cc.w < 0;   // leaves
-            // key = entry distance of an internal child that is hit, +inf otherwise
-            float k0 = (h0 && !f0) ? t0 : kInfT, k1 = (h1 && !f1) ? t1 : kInfT;
-            float k2 = (h2 && !f2) ? t2 : kInfT, k3 = (h3 && !f3) ? t3 : kInfT;
-            int n0 = cc.x, n1 = cc.y, n2 = cc.z, n3 = cc.w;
-            uint32_t leaf_hits = (h0 && f0 ? 1u : 0u) | (h1 && f1 ? 2u : 0u) | (h2 && f2 ? 4u : 0u) |
-                                 (h3 && f3 ? 8u : 0u);
-            // leaves are tested right away (one call site keeps the code small);
-            // internal children are visited near-first
-            while (leaf_hits) {
-                const int j = __ffs(leaf_hits) - 1;
-                leaf_hits &= leaf_hits - 1;
-                const uint32_t c = (uint32_t)(j == 0 ? cc.x : (j == 1 ? cc.y : (j == 2 ? cc.z : cc.w)));
+            // leaf phase: the pending leaves, then leaves met on the stack
+            // while no inner node is next
+            while (pmask) {
+                const int j = __ffs(pmask) - 1;
+                pmask &= pmask - 1;
+                const uint32_t c = (uint32_t)(j == 0 ? pcc.x : (j == 1 ? pcc.y : (j == 2 ? pcc.z : pcc.w)));
                 const int first = (int)(c & 0x0FFFFFFFu), cnt = (int)((c >> 28) & 7u) + 1;
                 for (int k = first; k < first + cnt; ++k)
                     if (test_leaf(k)) return true;
-            }
-            // sorting network on (key, node): nearest first
-            auto cswap = [](float& ka, int& na, float& kb, int& nb) {
-                if (kb < ka) {
-                    const float kt = ka;
-                    ka = kb;
-                    kb = kt;
-                    const int nt = na;
-                    na = nb;
-                    nb = nt;
+                if (pmask == 0 && node != kDone && node >= 0x80000000u) {
+                    pmask = 1u;
+                    pcc.x = (int)node;
+                    node = pop();
                 }
-            };
-            if (any_hit) {
-                // any hit: order does not matter for a ray that is not blocked;
-                // only bring the nearest to the front
-                cswap(k0, n0, k1, n1);
-                cswap(k2, n2, k3, n3);
-                cswap(k0, n0, k2, n2);
-            } else {
-                cswap(k0, n0, k1, n1);
-                cswap(k2, n2, k3, n3);
-                cswap(k0, n0, k2, n2);
-                cswap(k1, n1, k3, n3);
-                cswap(k1, n1, k2, n2);
             }
-            if (!(k0 < kInfT)) {
-                if (sp == 0) break;
-                --sp;
-                node = stack[sp * stride];
-                continue;
-            }
-            // the others onto the stack, farthest deepest
-            if (k3 < kInfT) push(n3);
-            if (k2 < kInfT) push(n2);
-            if (k1 < kInfT) push(n1);
-            node = (uint32_t)n0;
         }
-        if (budget <= 0) st.c[ST_OVERFLOW]++;
     }
     for (int q = 0; q < S.n_sph; ++q) {
         int ob = S.sphere_ids[q];
