@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-# Algorithmic work model (counted events x fixed per-event costs)
+# Algorithmic work model: counted events x fixed per-event costs
 NODE_BYTES = 128        # one 4-wide BVH node: four child boxes, links and count
 TRI_BYTES = 48          # one leaf: three float4 vertices
 F_NODE = 125            # FP32 ops of one node visit (four slab tests, sorting network of the hits)
@@ -151,7 +151,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md, not built)"}))
+                                   "described in the design notes, not built)"}))
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -242,7 +242,7 @@ def main():
                            "bytes_per_ray": round((NODE_BYTES * dstats["node_visits"] + TRI_BYTES * dstats["tri_tests"])
                                                   / max(dstats["rays"], 1), 1)}
 
-    # roofline of the dominant kernel group (byte and flop models in the design doc)
+    # roofline of the dominant kernel group (the byte and flop models above)
     dom = max(kms, key=lambda k: kms[k])
     avg_s = kms[dom] / max(kl[dom], 1) * 1e-3
     if dom in ("splat",):

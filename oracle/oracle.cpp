@@ -19,9 +19,12 @@
  *   - gradient and Hessian of the length function (Sec. 4.3, "Gradient and
  *     Hessian Evaluation"), including the curvature term Q on sphere charts;
  *   - the four-stage frame: initial, temporal, spatial, final shading
- *     (Sec. 3.2.4).
- * Readings of passages that are ambiguous or garbled are listed in the design doc
- * (section "Readings"); the code states the reading it takes where it matters.
+ *     (Sec. 3.2.4), with an optional reuse along the bin axis between the
+ *     temporal and the spatial stage (Sec. 4.5: a histogram bin takes the
+ *     samples of the bins around it in the same pixel, shifted by the bins'
+ *     distance, Delta l = (b - b') * bin width).
+ * Where a passage is ambiguous or garbled, the code states the reading it
+ * takes.
  *
  * Pins (tests/test_oracle_*.py): Philox against numpy's Philox4x64-10; BVH
  * closest hit against brute force; the closed-form transient of a Lambertian
@@ -89,7 +92,7 @@ void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4 };
+enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4, PASS_BIN = 16 };
 
 struct Draw {
     uint64_t x[4];
@@ -1241,6 +1244,101 @@ struct Oracle {
         for (auto& t : ts) stats.add(t);
     }
 
+    // Bin-axis reuse (Sec. 4.5, transient histograms): the reservoir of bin b
+    // of a pixel resamples its own sample and those of bins b + o, o in
+    // {-1, +1, -2, +2, ...} up to bin_radius, of the same pixel and frame.  A
+    // sample of bin b' enters bin b through the path-length-aware shift with
+    // Delta l = (b - b') * bin width (Sec. 4.1, eq. path_length_constraint);
+    // weights are the generalized balance heuristic over the bin domains
+    // (Sec. 3.2.3), every domain with the pixel's confidence M, which the
+    // pass leaves unchanged.  The gate plane passes through.
+    static int bin_offset(int l) { return (l / 2 + 1) * ((l & 1) ? 1 : -1); }
+
+    void bin_pass(uint64_t frame, const std::vector<PixelRes>& in, const std::vector<double>& Mi,
+                  std::vector<PixelRes>& out, std::vector<double>& Mo) {
+        out.assign(P, PixelRes());
+        Mo = Mi;
+        const int K = 2 * s.bin_radius;
+        const double bw = s.bin_width;
+        std::vector<Stats> ts(nthreads);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+        for (int pix = 0; pix < P; ++pix) {
+#ifdef _OPENMP
+            Stats& st = ts[omp_get_thread_num()];
+#else
+            Stats& st = ts[0];
+#endif
+            if (!gb[0][pix].hit) continue;
+            const double m = Mi[pix];
+            auto itg = in[pix].find(s.n_bins);
+            if (s.gate_enabled && itg != in[pix].end()) out[pix][s.n_bins] = itg->second;
+            std::vector<int> planes;
+            for (auto& kv : in[pix]) {
+                if (kv.first >= s.n_bins) continue;
+                planes.push_back(kv.first);
+                for (int l = 0; l < K; ++l) {
+                    const int b = kv.first - bin_offset(l);   // bins whose domain l is this one
+                    if (b >= 0 && b < s.n_bins) planes.push_back(b);
+                }
+            }
+            std::sort(planes.begin(), planes.end());
+            planes.erase(std::unique(planes.begin(), planes.end()), planes.end());
+            uint64_t fp = full_pixel(pix);
+            for (int b : planes) {
+                auto dom = [&](int l) { const int c = b + bin_offset(l); return c >= 0 && c < s.n_bins ? c : -1; };
+                double ws = 0.0;
+                bool have = false;
+                PathRec sel;
+                auto uni = [&](int cand) {
+                    Draw d = draw(s.seed, fp, frame, PASS_BIN, 0, (uint64_t)(b * 4 + cand / 4));
+                    return d.u(cand % 4);
+                };
+                auto itq = in[pix].find(b);
+                if (itq != in[pix].end()) {
+                    const Res& xr = itq->second;
+                    double ph = xr.y.phat;
+                    double den = m * ph;
+                    for (int l = 0; l < K; ++l) {
+                        const int bl = dom(l);
+                        if (bl < 0) continue;
+                        ShiftOut sh = shift(xr.y, 0, pix, 0, pix, bl, (bl - b) * bw, st);
+                        if (sh.ok) den += m * sh.phat * sh.J;
+                    }
+                    double w = (m * ph / den) * ph * xr.W;
+                    ws += w;
+                    if (uni(0) * ws < w) { sel = xr.y; have = true; }
+                }
+                for (int j = 0; j < K; ++j) {
+                    const int bj = dom(j);
+                    if (bj < 0) continue;
+                    auto itj = in[pix].find(bj);
+                    if (itj == in[pix].end()) continue;
+                    const Res& xr = itj->second;
+                    ShiftOut sh = shift(xr.y, 0, pix, 0, pix, b, (b - bj) * bw, st);
+                    if (!sh.ok) continue;
+                    double a = m * xr.y.phat / sh.J;
+                    double den = a + m * sh.phat;
+                    for (int l = 0; l < K; ++l) {
+                        const int bl = dom(l);
+                        if (l == j || bl < 0) continue;
+                        ShiftOut t2 = shift(sh.y, 0, pix, 0, pix, bl, (bl - b) * bw, st);
+                        if (t2.ok) den += m * t2.phat * t2.J;
+                    }
+                    double w = (a / den) * sh.phat * xr.W * sh.J;
+                    ws += w;
+                    if (uni(j + 1) * ws < w) { sel = sh.y; have = true; }
+                }
+                if (have && ws > 0.0) {
+                    Res r;
+                    r.y = sel;
+                    r.W = ws / sel.phat;
+                    out[pix][b] = r;
+                }
+            }
+        }
+        for (auto& t : ts) stats.add(t);
+    }
+
     // neighbour choice: integer rejection sampling in the disk of radius r
     void neighbours(int pix, uint64_t frame, int round, std::vector<int>& nb) const {
         nb.assign(s.spatial_k, -1);
@@ -1368,8 +1466,13 @@ struct Oracle {
             curM = &Mt;
         }
         const std::vector<PixelRes>* stage_t = cur;
-        std::vector<PixelRes> rin;
-        std::vector<double> rM;
+        std::vector<PixelRes> rin, bins;
+        std::vector<double> rM, bM;
+        if (s.bin_radius > 0 && s.n_bins > 1) {
+            bin_pass(frame, *cur, *curM, bins, bM);
+            cur = &bins;
+            curM = &bM;
+        }
         for (int r = 0; r < s.spatial_rounds; ++r) {
             std::vector<PixelRes> o;
             std::vector<double> oM;

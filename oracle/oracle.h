@@ -48,6 +48,7 @@ typedef struct {
     int32_t newton_max_iter;
     double j_max;
     int32_t shift_mode, include_direct, debug_stage;
+    int32_t bin_radius;           /* bin-axis reuse: bins b +- 1..bin_radius of the same pixel (0 = off) */
     uint64_t seed;
 } orc_sensor;
 

@@ -105,6 +105,7 @@ class Sensor:
     shift_mode: int = SHIFT_PATHLEN
     include_direct: int = 0
     debug_stage: int = STAGE_FINAL
+    bin_radius: int = 0            # bin-axis reuse: bins b +- 1..bin_radius (0 = off)
     seed: int = 0
 
     def __post_init__(self):

@@ -194,3 +194,68 @@ def test_restir_unbiased_with_gate_sweep(oracle_lib):
     r, p = np.array(r), np.array(p)
     z = (r.mean() - p.mean()) / math.sqrt(r.var(ddof=1) / n + p.var(ddof=1) / n)
     assert abs(z) < 3.5, z
+
+
+def test_bin_reuse_shifts_land_in_the_target_bin(oracle_lib):
+    """Bin-axis reuse (Sec. 4.5) alone: a sample of bin b' enters bin b with
+    Delta l = (b - b') * bin width.  Most such shifts land in the target bin
+    on the sphere interior (smooth chart, every length reachable); with the
+    sign of Delta l flipped the target is 2 |b - b'| bins away and none do,
+    so a wrong sign or a dropped Delta l fails this bound."""
+    w = scenes.lambert_sphere_interior(radius=1.0, albedo=0.5, intensity=1.0, width=16, height=16, n_bins=20,
+                                       frames=1, temporal=0, spatial_rounds=0, bin_radius=1)
+    o = oracle_lib.Oracle(w.scene, w.sensor)
+    o.render(w.frames[0])
+    st = o.stats()
+    o.close()
+    assert st["newton_attempts"] > 500
+    assert st["shifts_ok"] / st["newton_attempts"] > 0.5, st
+
+
+@pytest.mark.parametrize("radius", [1, 2])
+def test_sphere_interior_closed_form_restir_bin_reuse(oracle_lib, radius):
+    """ReSTIR with bin-axis reuse (plus temporal and spatial reuse) matches the
+    closed-form transient inside the sphere in expectation over seeds."""
+    R, rho, I = 1.0, 0.5, 1.0
+    nb = 20
+    lo = 2 * R + 0.1 * np.arange(nb)
+    exp = _sphere_expect(rho, I, R, lo, lo + 0.1, 2)
+    per = []
+    for seed in range(16):
+        w = scenes.lambert_sphere_interior(radius=R, albedo=rho, intensity=I, width=24, height=24,
+                                           n_bins=nb, frames=3, seed=seed, bin_radius=radius)
+        o = oracle_lib.Oracle(w.scene, w.sensor)
+        for fr in w.frames:
+            out = o.render(fr)
+        per.append(out["hist"].mean(axis=(1, 2)))
+        o.close()
+    per = np.array(per)
+    mean, se = per.mean(0), per.std(0, ddof=1) / math.sqrt(len(per))
+    assert np.all(np.abs(mean - exp) < 4.5 * se + 1e-3 * exp.max()), (mean - exp) / (se + 1e-15)
+    assert abs(mean.sum() - exp.sum()) < 4 * math.sqrt((se ** 2).sum())
+
+
+def test_restir_unbiased_with_bin_reuse(oracle_lib):
+    """Box scene, 16 bins over the gate's neighbourhood, bin-axis reuse with
+    temporal and spatial reuse: the histogram matches plain PT in expectation
+    over seeds (sensor sum per bin)."""
+    n = 64
+    r, p = [], []
+    for seed in range(n):
+        w = scenes.cornell_box(width=24, height=24, frames=3, seed=seed, gate_width=0.2, spatial_radius=4,
+                               n_bins=16, bin_t0=2.6, bin_width=0.1, bin_radius=2)
+        o = oracle_lib.Oracle(w.scene, w.sensor)
+        pts = []
+        for fr in w.frames:
+            out = o.render(fr)
+            pts.append(out["pt_hist"].sum(axis=(1, 2)))
+        r.append(out["hist"].sum(axis=(1, 2)))
+        p.append(np.mean(pts, 0))
+        o.close()
+    r, p = np.array(r), np.array(p)
+    tot_r, tot_p = r.sum(1), p.sum(1)
+    z = (tot_r.mean() - tot_p.mean()) / math.sqrt(tot_r.var(ddof=1) / n + tot_p.var(ddof=1) / n)
+    assert abs(z) < 3.5, z
+    vr, vp = r.var(0, ddof=1) / n, p.var(0, ddof=1) / n
+    zb = (r.mean(0) - p.mean(0)) / np.sqrt(vr + vp + 1e-30)
+    assert np.all(np.abs(zb[(vr > 0) & (vp > 0)]) < 4.0), zb
