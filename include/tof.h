@@ -105,6 +105,9 @@ typedef struct {
     int32_t shift_mode;              /* TOF_SHIFT_NAIVE (replay+reconnect) or TOF_SHIFT_PATHLEN */
     int32_t include_direct;          /* add the deterministic 1-vertex term */
     int32_t debug_stage;             /* TOF_STAGE_*: which reservoirs the splat shows */
+    int32_t bin_radius;              /* bin-axis reuse (Sec. 4.5) between the temporal and the spatial
+                                        pass: bin b resamples bins b +- 1..bin_radius of the same pixel,
+                                        shifted by Delta l = (b - b') * bin_width; 0 = off, at most 4 */
 } tof_sensor_desc;
 
 /* Per-frame poses.  object_xforms: host [num_objects*12], rigid 3x4 row-major

@@ -295,9 +295,32 @@ __global__ void k_neighbours(FrameArgs a, int round, const float* __restrict__ M
 // index and the tasks of an item range are contiguous.  count[0] and count[1]
 // receive the totals.  Also clears the output mask.
 // ---------------------------------------------------------------------------
+// the bits of mask word w that are planes (not padding)
+__device__ __forceinline__ uint32_t planes_in_word(const Sens& s, int w) {
+    const int lo = 32 * w;
+    return s.B >= lo + 32 ? 0xFFFFFFFFu : (s.B > lo ? (1u << (s.B - lo)) - 1u : 0u);
+}
+// the bits of mask word w that are histogram bins (not the gate plane, not padding)
+__device__ __forceinline__ uint32_t bins_in_word(const Sens& s, int w) {
+    const int lo = 32 * w;
+    if (w < 0 || s.n_bins <= lo) return 0u;
+    return s.n_bins >= lo + 32 ? 0xFFFFFFFFu : (1u << (s.n_bins - lo)) - 1u;
+}
+__device__ __forceinline__ uint32_t bin_word(const Sens& s, const uint32_t* m, int pix, int w) {
+    if (w < 0 || w >= s.mask_words) return 0u;
+    return m[(size_t)w * s.P + pix] & bins_in_word(s, w);
+}
+
 __device__ __forceinline__ uint32_t cand_word(const FrameArgs& a, int mode, const uint32_t* m1, const uint32_t* m2,
                                               const int* links, int c, int w, int pix) {
     const int P = a.s.P;
+    if (mode == 2) {   // bin axis: bit b of candidate c is bin b + o of the pixel; targets are bins too
+        if (c == 0) return bin_word(a.s, m1, pix, w);
+        const int o = bin_offset(c - 1);
+        const uint32_t v = o > 0 ? (bin_word(a.s, m1, pix, w) >> o) | (bin_word(a.s, m1, pix, w + 1) << (32 - o))
+                                 : (bin_word(a.s, m1, pix, w) << -o) | (bin_word(a.s, m1, pix, w - 1) >> (32 + o));
+        return v & bins_in_word(a.s, w);
+    }
     if (c == 0) return m1[(size_t)w * P + pix];
     int q = mode == 0 ? links[pix] : links[(size_t)(c - 1) * P + pix];
     if (q < 0) return 0u;
@@ -346,8 +369,9 @@ __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint
     if (valid) {
         for (int w = 0; w < a.s.mask_words; ++w) {
             uint32_t u = 0;
+            const uint32_t live = planes_in_word(a.s, w);
             for (int c = 0; c < ncand; ++c) {
-                uint32_t m = cand_word(a, mode, m1, m2, links, c, w, pix);
+                uint32_t m = cand_word(a, mode, m1, m2, links, c, w, pix) & live;
                 u |= m;
                 nt += __popc(m);
             }
@@ -360,8 +384,9 @@ __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint
         for (int w = 0; w < a.s.mask_words; ++w) {
             uint32_t wm[kMaxK + 1];
             uint32_t u = 0;
+            const uint32_t live = planes_in_word(a.s, w);
             for (int c = 0; c < ncand; ++c) {
-                wm[c] = cand_word(a, mode, m1, m2, links, c, w, pix);
+                wm[c] = cand_word(a, mode, m1, m2, links, c, w, pix) & live;
                 u |= wm[c];
             }
             while (u) {
@@ -420,7 +445,13 @@ __global__ void __launch_bounds__(256) k_tasks(const uint2* __restrict__ items, 
 // The merge forms m_c = (own or M_q phat_q) / (own + M_q phat_q + sum terms).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int cand_src(int mode, const int* links, int P, int pix, int c) {
-    return mode == 0 ? links[pix] : links[(size_t)(c - 1) * P + pix];
+    return mode == 0 ? links[pix] : (mode == 1 ? links[(size_t)(c - 1) * P + pix] : pix);
+}
+// plane of candidate c of an item in plane pl
+__device__ __forceinline__ int cand_plane(int mode, int pl, int c) { return mode == 2 ? pl + bin_offset(c - 1) : pl; }
+// M of a neighbour domain's pixel
+__device__ __forceinline__ float dom_M(const Sens& s, int mode, const ResSet& A, const ResSet& Bp, int dpix) {
+    return mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
 }
 
 TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
@@ -444,12 +475,14 @@ TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
             continue;
         }
         const int src = cand_src(mode, links, P, pix, c);
+        const int spl = cand_plane(mode, pl, c);
         float Wx;
-        Rec y = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
+        Rec y = load_rec(mode == 0 ? Bp : A, (size_t)spl * P + src, Wx);
         const float xphat = y.phat;
-        const float mc = mode == 0 ? fminf(Bp.M[src], s.m_cap) : A.M[src];
+        const float mc = dom_M(s, mode, A, Bp, src);
         // a blocked visibility ray zeroes phat_q (component x of fwd[t])
-        const float dl = mode == 0 ? gate_shift(s, a.F.g[0], a.F.g[1], pl) : 0.f;
+        const float dl = mode == 0 ? gate_shift(s, a.F.g[0], a.F.g[1], pl)
+                                   : (mode == 2 ? (float)(pl - spl) * s.bw : 0.f);
         const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, mode == 0 ? 1 : 0, src, 0, pix, pl, dl, q, 4u * t);
         if (!sh.ok) {
             fwd[t] = make_float4(0.f, 1.0f, 0.f, Wx);
@@ -472,18 +505,25 @@ __global__ void __launch_bounds__(kTB) k_mis_list(FrameArgs a, int mode, const i
                                                   const uint32_t* __restrict__ win, const float4* __restrict__ fwd,
                                                   float* __restrict__ term, IdxQueue lq) {
     const int P = a.s.P;
-    const uint32_t K = mode == 0 ? 1u : (uint32_t)a.s.k;
+    const uint32_t K = (uint32_t)pass_K(a.s, mode);
     const uint32_t n = win[1];
     for (uint32_t t = blockIdx.x * kTB + threadIdx.x; t < n; t += gridDim.x * kTB) {
         uint32_t valid = 0;
         const uint2 task = tasks[t];
         const int c = (int)task.y;
-        const int pix = (int)items[task.x].x;
+        const uint2 item = items[task.x];
+        const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
         const bool open = c == 0 || fwd[t].x > 0.f;
         for (uint32_t l = 0; l < K; ++l) {
             term[(size_t)t * K + l] = 0.f;
-            const int dpix = mode == 0 ? links[pix] : links[(size_t)l * P + pix];
-            if (open && (int)l != c - 1 && dpix >= 0) valid |= 1u << l;
+            bool dom;
+            if (mode == 2) {
+                const int dpl = pl + bin_offset((int)l);
+                dom = dpl >= 0 && dpl < a.s.n_bins;
+            } else {
+                dom = (mode == 0 ? links[pix] : links[(size_t)l * P + pix]) >= 0;
+            }
+            if (open && (int)l != c - 1 && dom) valid |= 1u << l;
         }
         uint32_t first;
         const bool fits = lq.alloc((uint32_t)__popc(valid), first);   // bounded by the chunk size
@@ -504,7 +544,7 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
     Tracer tr{a.S, stk + threadIdx.x, kTB, kStackDepth, st};
     const Sens& s = a.s;
     const int P = s.P;
-    const uint32_t K = mode == 0 ? 1u : (uint32_t)s.k;
+    const uint32_t K = (uint32_t)pass_K(s, mode);
     const uint32_t sub = blockIdx.x % kRaySubQueues;
     const uint32_t n = min(lq.count[sub * kCounterStride], lq.sub_cap);
     const uint32_t* list = lq.buf + (size_t)sub * lq.sub_cap;
@@ -517,14 +557,15 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
         const int c = (int)task.y;
         const uint2 item = items[task.x];
         const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
-        const int dpix = mode == 0 ? links[pix] : links[(size_t)l * P + pix];
+        const int dpix = mode == 0 ? links[pix] : (mode == 1 ? links[(size_t)l * P + pix] : pix);
+        const int dpl = mode == 2 ? pl + bin_offset(l) : pl;
         float Wx;
         Rec y;
         if (c == 0) {
             y = load_rec(A, (size_t)pl * P + pix, Wx);
         } else {
             const int src = cand_src(mode, links, P, pix, c);
-            y = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
+            y = load_rec(mode == 0 ? Bp : A, (size_t)cand_plane(mode, pl, c) * P + src, Wx);
             const float4 s0 = shv[2 * (size_t)t], s1 = shv[2 * (size_t)t + 1];
             y.v[0] = VRef{__float_as_int(s0.x), s0.y, s0.z};
             y.v[1] = VRef{__float_as_int(s0.w), s1.x, s1.y};
@@ -532,12 +573,10 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
             y.pre_pdf = s1.w;
             y.phat = fwd[t].x;
         }
-        const float dl = mode == 0 ? -gate_shift(s, a.F.g[0], a.F.g[1], pl) : 0.f;
-        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, pl, dl, q, g);
-        if (sh.ok) {
-            const float ml = mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
-            term[g] = ml * sh.phat * sh.J;
-        }
+        const float dl = mode == 0 ? -gate_shift(s, a.F.g[0], a.F.g[1], pl)
+                                   : (mode == 2 ? (float)(dpl - pl) * s.bw : 0.f);
+        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, dpl, dl, q, g);
+        if (sh.ok) term[g] = dom_M(s, mode, A, Bp, dpix) * sh.phat * sh.J;
     }
     flush_counters(st, a.counters);
 }
@@ -582,7 +621,7 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
                                                const float4* __restrict__ shv, int round, ResSet out) {
     const Sens& s = a.s;
     const int P = s.P;
-    const int K = mode == 0 ? 1 : s.k;
+    const int K = pass_K(s, mode);
     const int ncand = K + 1;
     const uint32_t ni = count[0];
     if (i0 >= ni) return;
@@ -612,7 +651,10 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
             if (c > 0 && !(w > 0.f)) continue;
             float u;
             if (mode == 0) u = ut.u(c);
-            else u = philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + c / 4)).u(c % 4);
+            else if (mode == 1)
+                u = philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + c / 4)).u(c % 4);
+            else
+                u = philox(s.seed, fp, a.frame, PASS_BIN, 0, (uint64_t)(pl * 4 + c / 4)).u(c % 4);
             ws += w;
             if (u * ws < w) {
                 sel = c;
@@ -628,7 +670,7 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
                 store_rec(out, oidx, x, ws / sel_phat);
             } else {
                 const int src = cand_src(mode, links, P, pix, sel);
-                Rec x = load_rec(mode == 0 ? Bp : A, (size_t)pl * P + src, Wx);
+                Rec x = load_rec(mode == 0 ? Bp : A, (size_t)cand_plane(mode, pl, sel) * P + src, Wx);
                 const float4 s0 = shv[2 * (size_t)sel_t], s1 = shv[2 * (size_t)sel_t + 1];
                 x.v[0] = VRef{__float_as_int(s0.x), s0.y, s0.z};
                 x.v[1] = VRef{__float_as_int(s0.w), s1.x, s1.y};
@@ -640,6 +682,17 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
             atomicOr(out.mask + (size_t)(pl >> 5) * P + pix, 1u << (pl & 31));
         }
     }
+}
+
+// one plane passed through unchanged (the gate plane across the bin-axis pass)
+__global__ void k_copy_plane(FrameArgs a, ResSet in, ResSet out, int pl) {
+    const int P = a.s.P;
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= P || !mask_bit(in.mask, P, pl, pix)) return;
+    const size_t i = (size_t)pl * P + pix;
+#pragma unroll
+    for (int e = 0; e < 5; ++e) out.rec[5 * i + e] = in.rec[5 * i + e];
+    atomicOr(out.mask + (size_t)(pl >> 5) * P + pix, 1u << (pl & 31));
 }
 
 // ---------------------------------------------------------------------------
@@ -733,6 +786,9 @@ void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& B
                   hipStream_t st) {
     hipLaunchKernelGGL(k_merge, dim3(grid_for(ci, 256, 32768)), dim3(256), 0, st, a, mode, A, Bp, links, items,
                        task0, count, (uint32_t)i0, (uint32_t)ci, win, fwd, term, shv, round, out);
+}
+void launch_copy_plane(const FrameArgs& a, const ResSet& in, const ResSet& out, int pl, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_plane, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, in, out, pl);
 }
 void launch_splat(const FrameArgs& a, const ResSet& shown, const float* pt, const float2* direct, float* out_image,
                   float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st) {

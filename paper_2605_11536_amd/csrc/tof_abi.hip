@@ -51,11 +51,12 @@ struct SlotHost {
 
 // A reuse pass runs over chunks of items whose tasks, terms and queued rays
 // fit one workspace: at most `rays` visibility rays per chunk; per mode (0
-// temporal, 1 spatial) ct tasks and ci = ct / (K + 1) items per chunk, the
-// shift kernels on `grid` blocks and the visibility kernel on `vis_grid`.
+// temporal, 1 spatial, 2 bin axis) ct tasks and ci = ct / (K + 1) items per
+// chunk, the shift kernels on `grid` blocks and the visibility kernel on
+// `vis_grid`.
 struct ChunkPlan {
-    size_t rays = 0, ct[2] = {0, 0}, ci[2] = {0, 0}, task_cap = 0, term_cap = 0, ray_cap = 0;
-    unsigned grid[2] = {0, 0}, vis_grid[2] = {0, 0};
+    size_t rays = 0, ct[3] = {0, 0, 0}, ci[3] = {0, 0, 0}, task_cap = 0, term_cap = 0, ray_cap = 0;
+    unsigned grid[3] = {0, 0, 0}, vis_grid[3] = {0, 0, 0};
 };
 
 }  // namespace
@@ -214,16 +215,17 @@ V3 hcross(V3 a, V3 b) { return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, 
 
 constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 
-ChunkPlan plan_chunks(size_t P, size_t B, int k) {
+ChunkPlan plan_chunks(size_t P, size_t B, int k, int br) {
     ChunkPlan p;
-    const size_t K[2] = {1, (size_t)std::max(k, 1)};
-    const size_t seg[2] = {4, 2};   // visibility segments per shift: across two frames, within one
+    const int modes = br > 0 ? 3 : 2;
+    const size_t K[3] = {1, (size_t)std::max(k, 1), 2 * (size_t)std::max(br, 1)};
+    const size_t seg[3] = {4, 2, 2};   // visibility segments per shift: across two frames, within one
     size_t dense = 0;
-    for (int m = 0; m < 2; ++m) dense = std::max(dense, seg[m] * K[m] * P * B * (K[m] + 1));
+    for (int m = 0; m < modes; ++m) dense = std::max(dense, seg[m] * K[m] * P * B * (K[m] + 1));
     // a sixteenth of the rays of a pass over fully occupied planes, within
     // [2^22, 2^28] rays (134 MB .. 8.6 GB of queue)
     p.rays = std::min<size_t>((size_t)1 << 28, std::max<size_t>((size_t)1 << 22, dense / 16));
-    for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < modes; ++m) {
         const size_t all = P * B * (K[m] + 1);
         const size_t raw = std::max<size_t>(1, std::min(p.rays / (seg[m] * K[m]), all));
         const size_t G = tofh::shift_grid(raw), Q = G * 128;
@@ -244,7 +246,7 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t words = (B + 31) / 32;
     size_t per_set = P * B * kRecBytes + P * 4 + P * words * 4;
     size_t gbuf = 2 * P * (4 + 4 + 4 + 16 + 16);
-    const ChunkPlan pl = plan_chunks(P, B, d.spatial_k);
+    const ChunkPlan pl = plan_chunks(P, B, d.spatial_k, d.bin_radius);
     return 4 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
            P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ + P * B * 4 /*first task per item*/ +
            pl.task_cap * (8 + 16 + 32) /*tasks, forward terms, shifted fields*/ +
@@ -656,9 +658,11 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
               d->newton_max_iter <= 64 && d->j_max >= 1.f &&
               (d->shift_mode == TOF_SHIFT_NAIVE || d->shift_mode == TOF_SHIFT_PATHLEN) &&
               d->debug_stage >= TOF_STAGE_CANONICAL && d->debug_stage <= TOF_STAGE_FINAL &&
+              d->bin_radius >= 0 && d->bin_radius <= 4 &&
               std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
     // work-list entries (tasks of a pass over fully occupied planes) are 32-bit indices
-    ok = ok && (unsigned long long)d->width * d->height * B * (unsigned long long)(std::max(d->spatial_k, 1) + 1) <
+    ok = ok && (unsigned long long)d->width * d->height * B *
+                       (unsigned long long)(std::max(std::max(d->spatial_k, 2 * d->bin_radius), 1) + 1) <
                    (1ULL << 32);
     if (!ok) return TOF_ERR_INVALID_ARG;
     if (c->has_sensor) {
@@ -695,7 +699,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->direct, P));
     TOF_TRY(alloc_t(c, a, &c->prev_pix, P));
     TOF_TRY(alloc_t(c, a, &c->nb, P * (size_t)std::max(d->spatial_k, 1)));
-    const ChunkPlan& pl = c->plan = plan_chunks(P, (size_t)B, d->spatial_k);
+    const ChunkPlan& pl = c->plan = plan_chunks(P, (size_t)B, d->spatial_k, d->bin_radius);
     TOF_TRY(alloc_t(c, a, &c->items, P * B));
     TOF_TRY(alloc_t(c, a, &c->task0, P * B));
     TOF_TRY(alloc_t(c, a, &c->tasks, pl.task_cap));
@@ -744,6 +748,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     s.shift_mode = d->shift_mode;
     s.include_direct = d->include_direct;
     s.debug_stage = d->debug_stage;
+    s.br = d->bin_radius;
     s.P = (int)P;
     s.B = B;
     s.mask_words = (int)words;
@@ -883,7 +888,7 @@ tof_status run_pass(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, c
     const int kv = mode == 0 ? TOF_K_TEMPORAL_VIS : TOF_K_SPATIAL_VIS;
     const int kg = mode == 0 ? TOF_K_TEMPORAL_MERGE : TOF_K_SPATIAL_MERGE;
     const ChunkPlan& pl = c->plan;
-    const size_t K = mode == 0 ? 1 : (size_t)c->s.k;
+    const size_t K = mode == 0 ? 1 : (mode == 1 ? (size_t)c->s.k : 2 * (size_t)c->s.br);
     // at most 4 segments per shift across frames (temporal), 2 within one frame
     const size_t seg = mode == 0 ? 4 : 2;
     const size_t ct = pl.ct[mode], ci = pl.ci[mode];
@@ -1098,11 +1103,30 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     } else if (shown) {
         tofh::launch_splat(a, *shown, c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
     }
-    // spatial rounds alternate between the new final set and the scratch set
+    // the bin-axis pass and the spatial rounds alternate between the new
+    // final set and the scratch set
     int cur_idx = temporal_done ? 1 : 0;
-    for (int r = 0; r < c->s.rounds && c->s.k > 0; ++r) {
+    auto next_out = [&]() {
         int out_idx = (cur_idx == fin_new) ? 1 : fin_new;
         if (out_idx == cur_idx) out_idx = 0;
+        return out_idx;
+    };
+    if (c->s.br > 0 && c->s.n_bins > 1) {
+        const int out_idx = next_out();
+        ResSet& in = c->sets[cur_idx];
+        ResSet& out = c->sets[out_idx];
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
+        a.counters = c->counters + (size_t)TOF_K_SPATIAL_PREP * kBank;
+        HIP_TRY(hipMemcpyAsync(out.M, in.M, sizeof(float) * P, hipMemcpyDeviceToDevice, st));
+        tofh::launch_fill_u32(c->count, 0u, 2, st);
+        tofh::launch_items(a, 2, in, in, nullptr, 2 * c->s.br + 1, c->items, c->task0, c->count, out.mask, st);
+        if (c->s.gate_en) tofh::launch_copy_plane(a, in, out, c->s.n_bins, st);
+        HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
+        TOF_TRY(run_pass(c, a, 2, in, in, nullptr, 0, out, st));
+        cur_idx = out_idx;
+    }
+    for (int r = 0; r < c->s.rounds && c->s.k > 0; ++r) {
+        const int out_idx = next_out();
         ResSet& in = c->sets[cur_idx];
         ResSet& out = c->sets[out_idx];
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));

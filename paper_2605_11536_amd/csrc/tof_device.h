@@ -115,9 +115,16 @@ struct Sens {
     int max_it;
     float j_max;
     int shift_mode, include_direct, debug_stage;
+    int br;                  // bin-axis reuse radius (0 = off)
     int P, B, mask_words;
     uint64_t seed;
 };
+
+// Reuse passes: 0 temporal, 1 spatial, 2 bin axis (Sec. 4.5).  K = the
+// number of other domains per item; bin-axis domain l of bin b is bin
+// b + bin_offset(l), offsets -1, +1, -2, +2, ...
+__device__ __forceinline__ int pass_K(const Sens& s, int mode) { return mode == 0 ? 1 : (mode == 1 ? s.k : 2 * s.br); }
+__host__ __device__ __forceinline__ int bin_offset(int l) { return (l / 2 + 1) * ((l & 1) ? 1 : -1); }
 
 struct VRef {
     int obj;
@@ -183,7 +190,7 @@ __device__ __forceinline__ Rec load_rec(const ResSet& R, size_t idx, float& W) {
 // Philox4x64-10 (Salmon et al., SC'11) and the stream layout
 // counter = (pixel, frame, pass << 56 | a << 32 | b, 0), key = (seed, 0)
 // ---------------------------------------------------------------------------
-enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4 };
+enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4, PASS_BIN = 16 };
 
 struct Draw {
     uint64_t x[4];

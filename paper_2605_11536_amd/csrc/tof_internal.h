@@ -105,6 +105,9 @@ void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tof
                   const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,
                   const uint32_t* win, const float4* fwd, const float* term, const float4* shv, int round,
                   tofd::ResSet out, hipStream_t st);
+// Records and mask bits of plane pl copied from `in` to `out` (the gate plane
+// across the bin-axis pass).
+void launch_copy_plane(const FrameArgs& a, const tofd::ResSet& in, const tofd::ResSet& out, int pl, hipStream_t st);
 void launch_splat(const FrameArgs& a, const tofd::ResSet& shown, const float* pt, const float2* direct,
                   float* out_image, float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st);
 

@@ -131,6 +131,56 @@ def test_nlos_confocal_parity():
     _run_pair(w, check=("hist", "pt_hist"))
 
 
+def test_bin_reuse_parity():
+    """Bin-axis reuse (Sec. 4.5) after temporal reuse, shown directly (no
+    spatial round): 16 bins around the gate, radius 2; the gate plane passes
+    through."""
+    w = scenes.cornell_box(frames=3, n_bins=16, bin_t0=2.6, bin_width=0.1, bin_radius=2, spatial_rounds=0)
+    gs, os_ = _run_pair(w)
+    for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+        assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
+
+
+def _run_chain(w, keys):
+    """Per-frame comparison for three reuse passes chained in one frame
+    (temporal, bin axis, spatial).  FP32 differences of the Newton shift
+    compound over the passes (about 0.05% more discrepant entries per pass),
+    so the bar is the free-running one: every discrete count agrees, sums to
+    1e-3, >= 99.5% of entries within 1e-4, no systematic sign."""
+    from oracle.oracle import Oracle
+    from paper_2605_11536_amd.tof import Renderer
+    gpu = Renderer(w.scene, w.sensor)
+    orc = Oracle(w.scene, w.sensor)
+    for f, fr in enumerate(w.frames):
+        print(f"case {w.name} three-pass chain frame {fr.index}", flush=True)
+        if f > 0:
+            gpu.set_history(orc.export_history())
+        gpu.render(fr)
+        g, o = gpu.fetch(), orc.render(fr)
+        for key in keys:
+            frac, close = _frac_close(g[key], o[key])
+            d = (g[key].astype(np.float64) - o[key])[~close]
+            z = float(d.sum() / math.sqrt(float((d * d).sum()))) if d.size else 0.0
+            print(f"{key}: {frac * 100:.4f}% within {REL}, sign z {z:+.2f}", flush=True)
+            assert frac >= 0.995 and abs(z) <= 3.0
+            assert abs(float(g[key].sum()) - float(o[key].sum())) <= 1e-3 * float(np.abs(o[key]).sum())
+    gs, os_ = gpu.stats(), orc.stats()
+    gpu.close()
+    orc.close()
+    assert gs["bad_records"] == 0 and gs["bvh_overflow"] == 0
+    for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+        assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
+
+
+def test_bin_reuse_chain_parity():
+    """Temporal, bin-axis and spatial reuse in one frame: the box (bins
+    2.6-4.2 over the near-stationary sphere-floor lengths), the sphere
+    interior and the NLOS scan (1024 bins, radius 3)."""
+    _run_chain(scenes.cornell_box(frames=3, n_bins=16, bin_t0=2.6, bin_width=0.1, bin_radius=2), ("image", "hist"))
+    _run_chain(scenes.lambert_sphere_interior(width=40, height=24, frames=3, bin_radius=1), ("image", "hist"))
+    _run_chain(scenes.nlos_confocal(scan=32, frames=2, torus_nu=125, torus_nv=50, bin_radius=3), ("hist",))
+
+
 def test_glossy_dynamic_crop_parity():
     """A 64x64 crop of the 512^2 dynamic glossy scene (256 bins + gate,
     moving spheres, temporal + spatial reuse)."""
