@@ -22,7 +22,10 @@
  *     (Sec. 3.2.4), with an optional reuse along the bin axis between the
  *     temporal and the spatial stage (Sec. 4.5: a histogram bin takes the
  *     samples of the bins around it in the same pixel, shifted by the bins'
- *     distance, Delta l = (b - b') * bin width).
+ *     distance, Delta l = (b - b') * bin width);
+ *   - optionally, initial gate samples drawn in a gate K times wider and the
+ *     RIS winner shrunk into the gate (Sec. 4.4.2, shrink mapping, with all
+ *     samples in the wide gate, R = 1).
  * Where a passage is ambiguous or garbled, the code states the reading it
  * takes.
  *
@@ -670,6 +673,12 @@ struct Oracle {
     bool in_plane(int pl, double len, int slot = 0) const {
         return len >= plane_lo(pl, slot) && len < plane_hi(pl, slot);
     }
+    bool shrink_on() const { return s.gate_enabled && s.shrink_k > 1.0; }
+    // the wide ("rough") gate of the shrink mapping: K times the gate, same centre
+    bool in_rough_gate(double len) const {
+        const double c = fg[0].gate_center, h = 0.5 * s.shrink_k * s.gate_width;
+        return len >= c - h && len < c + h;
+    }
     // Delta l of a temporal shift from the previous frame into the current one
     // (Sec. 4.1, time-gate shifting): the gate's move; bins do not move
     double gate_shift(int pl) const { return pl < s.n_bins ? 0.0 : fg[0].gate_center - fg[1].gate_center; }
@@ -1046,6 +1055,34 @@ struct Oracle {
         }
     }
 
+    // Shrink mapping (Sec. 4.4.2): the gate reservoir's winner x, drawn with
+    // the target f * 1[l in the rough gate], is moved by the path-length-aware
+    // shift of its own pixel with Delta l = (l - l0) / K + l0 - l (l0 the gate
+    // centre), so that its length lands in the gate at the same relative
+    // position; the Jacobian of this map is the shift's times 1/K, and the
+    // sample's contribution weight is multiplied by it.  A path without a
+    // reconnection vertex (or under the naive shift) cannot be shrunk: it is
+    // kept unchanged if it already lies in the gate.  A failed shrink empties
+    // the reservoir (with all samples in the wide gate, R = 1, the estimate is
+    // biased low where shrinks fail, as the paper notes).
+    void shrink_gate_sample(int pix, PixelRes& pr, Stats& st) {
+        auto it = pr.find(s.n_bins);
+        if (it == pr.end()) return;
+        Res& r = it->second;
+        if (s.shift_mode != 1 || r.y.k < 2) {
+            if (!in_plane(s.n_bins, r.y.len)) pr.erase(it);
+            return;
+        }
+        const double l0 = fg[0].gate_center, K = s.shrink_k, l = r.y.len;
+        ShiftOut sh = shift(r.y, 0, pix, 0, pix, s.n_bins, (l - l0) / K + l0 - l, st);
+        if (!sh.ok) {
+            pr.erase(it);
+            return;
+        }
+        r.W *= sh.J / K;
+        r.y = sh.y;
+    }
+
     // initial candidates: path trees with NEE at every vertex, each sub-path
     // deposited into the reservoir of its bin (and the gate) (Sec. 4.5).
     void initial_pass(uint64_t frame, std::vector<PixelRes>& can, std::vector<double>& Mc,
@@ -1118,11 +1155,17 @@ struct Oracle {
                             }
                             Draw u = draw(s.seed, fp, frame, PASS_RIS, (uint64_t)tree, (uint64_t)i);
                             double w = C / ((double)s.m_init * pdf);
-                            int planes[2] = {bin_of(l_i), (s.gate_enabled && in_plane(s.n_bins, l_i)) ? s.n_bins : -1};
+                            // plain PT deposits into the planes; the reservoirs
+                            // take the gate's candidates from the rough gate
+                            // when the shrink mapping is on
+                            const bool gate_pt = s.gate_enabled && in_plane(s.n_bins, l_i);
+                            const bool gate_res = shrink_on() ? in_rough_gate(l_i) : gate_pt;
+                            int planes[2] = {bin_of(l_i), gate_res ? s.n_bins : -1};
+                            if (planes[0] >= 0) pt[(size_t)planes[0] * P + pix] += C / pdf / (double)s.m_init;
+                            if (gate_pt) pt[(size_t)s.n_bins * P + pix] += C / pdf / (double)s.m_init;
                             for (int q = 0; q < 2; ++q) {
                                 int pl = planes[q];
                                 if (pl < 0) continue;
-                                pt[(size_t)pl * P + pix] += C / pdf / (double)s.m_init;
                                 double& ws = wsum[pl];
                                 ws += w;
                                 if (u.u(q) * ws < w) can[pix][pl].y = rec;
@@ -1147,6 +1190,7 @@ struct Oracle {
                 }
             }
             for (auto& kv : can[pix]) kv.second.W = wsum[kv.first] / kv.second.y.phat;
+            if (shrink_on()) shrink_gate_sample(pix, can[pix], st);
         }
         for (auto& t : ts) stats.add(t);
     }

@@ -49,6 +49,7 @@ typedef struct {
     double j_max;
     int32_t shift_mode, include_direct, debug_stage;
     int32_t bin_radius;           /* bin-axis reuse: bins b +- 1..bin_radius of the same pixel (0 = off) */
+    double shrink_k;              /* shrink mapping: initial gate samples from a gate shrink_k times wider (1 = off) */
     uint64_t seed;
 } orc_sensor;
 

@@ -38,7 +38,8 @@ class OrcSensor(C.Structure):
                 ("spatial_radius", C.c_int32), ("m_cap", C.c_double),
                 ("newton_tol_rel", C.c_double), ("newton_max_iter", C.c_int32),
                 ("j_max", C.c_double), ("shift_mode", C.c_int32), ("include_direct", C.c_int32),
-                ("debug_stage", C.c_int32), ("bin_radius", C.c_int32), ("seed", C.c_uint64)]
+                ("debug_stage", C.c_int32), ("bin_radius", C.c_int32),
+                ("shrink_k", C.c_double), ("seed", C.c_uint64)]
 
 
 class OrcFrame(C.Structure):

@@ -106,6 +106,7 @@ class Sensor:
     include_direct: int = 0
     debug_stage: int = STAGE_FINAL
     bin_radius: int = 0            # bin-axis reuse: bins b +- 1..bin_radius (0 = off)
+    shrink_k: float = 1.0          # shrink mapping of initial gate samples: rough gate K x wider (1 = off)
     seed: int = 0
 
     def __post_init__(self):

@@ -259,3 +259,30 @@ def test_restir_unbiased_with_bin_reuse(oracle_lib):
     vr, vp = r.var(0, ddof=1) / n, p.var(0, ddof=1) / n
     zb = (r.mean(0) - p.mean(0)) / np.sqrt(vr + vp + 1e-30)
     assert np.all(np.abs(zb[(vr > 0) & (vp > 0)]) < 4.0), zb
+
+
+@pytest.mark.parametrize("reuse", [False, True])
+def test_shrink_mapping_sphere_closed_form(oracle_lib, reuse):
+    """Shrink mapping (Sec. 4.4.2), all samples in a gate K = 5 times wider:
+    inside the sphere every rough-gate length maps onto the gate and nearly
+    every shrink succeeds, so the gate image matches the gate's closed form
+    in expectation (a dropped 1/K is off by a factor K, a wrong Delta l moves
+    the samples out of the gate)."""
+    R, rho, I = 1.0, 0.5, 1.0
+    kw = {} if reuse else dict(temporal=0, spatial_rounds=0)
+    exp = float(_sphere_expect(rho, I, R, [3.45], [3.55], 2)[0])
+    per = []
+    for seed in range(24):
+        w = scenes.lambert_sphere_interior(radius=R, albedo=rho, intensity=I, width=24, height=24, n_bins=0,
+                                           frames=2, seed=seed, shrink_k=5.0, **kw)
+        o = oracle_lib.Oracle(w.scene, w.sensor)
+        for fr in w.frames:
+            out = o.render(fr)
+        per.append(out["image"].mean())
+        st = o.stats()
+        o.close()
+        if not reuse:   # every shift is a shrink (a third of the pixels hold a rough-gate sample); nearly all succeed
+            assert st["shifts"] > 0.25 * 24 * 24 * 2 and st["shifts_ok"] > 0.95 * st["shifts"], st
+    per = np.array(per)
+    mean, se = per.mean(), per.std(ddof=1) / math.sqrt(len(per))
+    assert abs(mean - exp) < 4 * se + 2e-3 * exp, ((mean - exp) / se, mean, exp)
