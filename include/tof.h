@@ -108,6 +108,12 @@ typedef struct {
     int32_t bin_radius;              /* bin-axis reuse (Sec. 4.5) between the temporal and the spatial
                                         pass: bin b resamples bins b +- 1..bin_radius of the same pixel,
                                         shifted by Delta l = (b - b') * bin_width; 0 = off, at most 4 */
+    float shrink_k;                  /* shrink mapping of initial gate samples (Sec. 4.4.2): candidates come
+                                        from a gate shrink_k times wider (same centre) and the RIS winner
+                                        is moved into the gate by the path-length-aware shift with
+                                        Delta l = (l - l0) / K + l0 - l, its weight scaled by the shift's
+                                        Jacobian / K; all samples in the wide gate (the paper's R = 1,
+                                        biased low where shrinks fail).  1 = off, at most 1000 */
 } tof_sensor_desc;
 
 /* Per-frame poses.  object_xforms: host [num_objects*12], rigid 3x4 row-major

@@ -152,12 +152,18 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                             }
                             Draw u = philox(s.seed, fp, a.frame, PASS_RIS, (uint64_t)tree, (uint64_t)i);
                             float w = C / ((float)s.m_init * pdf);
-                            int planes[2] = {bin_of(s, li), (s.gate_en && in_plane(s, s.n_bins, li)) ? s.n_bins : -1};
+                            // plain PT deposits into the planes; the reservoirs take
+                            // the gate's candidates from the wide gate when the
+                            // shrink mapping is on
+                            const bool gate_pt = s.gate_en && in_plane(s, s.n_bins, li);
+                            const bool gate_res = s.gate_en && s.shrink_k > 1.f ? in_rough_gate(s, li) : gate_pt;
+                            int planes[2] = {bin_of(s, li), gate_res ? s.n_bins : -1};
+                            if (planes[0] >= 0) pt[(size_t)planes[0] * P + pix] += C / pdf / (float)s.m_init;
+                            if (gate_pt) pt[(size_t)s.n_bins * P + pix] += C / pdf / (float)s.m_init;
                             for (int q = 0; q < 2; ++q) {
                                 int pl = planes[q];
                                 if (pl < 0) continue;
                                 size_t idx = (size_t)pl * P + pix;
-                                pt[idx] += C / pdf / (float)s.m_init;
                                 uint32_t* mw = can.mask + (size_t)(pl >> 5) * P + pix;
                                 uint32_t bit = 1u << (pl & 31);
                                 uint32_t m = *mw;
@@ -684,6 +690,52 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
     }
 }
 
+// Shrink mapping (Sec. 4.4.2) of the gate reservoirs of pixels [p0, p0 + np):
+// the winner x, drawn with the target f * 1[l in the wide gate], is moved by
+// the path-length-aware shift of its own pixel with Delta l = (l - l0) / K +
+// l0 - l; its contribution weight is multiplied by the shift's Jacobian / K.
+// A path without a reconnection vertex (or under the naive shift) is kept
+// only if it already lies in the gate.  A failed shrink, or a blocked
+// visibility ray (which zeroes the record's W), leaves W = 0 for k_shrink_fin.
+TOF_TRACE_KERNEL k_shrink(FrameArgs a, ResSet can, uint32_t p0, uint32_t np, RayQueue q) {
+    __shared__ uint32_t stk[kStackDepth * kTB];
+    Counters st = {};
+    Tracer tr{a.S, stk + threadIdx.x, kTB, kStackDepth, st};
+    const Sens& s = a.s;
+    const int P = s.P, gp = s.n_bins;
+    for (uint32_t t = blockIdx.x * kTB + threadIdx.x; t < np; t += gridDim.x * kTB) {
+        const int pix = (int)(p0 + t);
+        if (!mask_bit(can.mask, P, gp, pix)) continue;
+        const size_t idx = (size_t)gp * P + pix;
+        float W;
+        Rec y = load_rec(can, idx, W);
+        if (s.shift_mode != TOF_SHIFT_PATHLEN || y.k < 2) {
+            if (!in_plane(s, gp, y.len)) rec_W(can, idx) = 0.f;
+            continue;
+        }
+        const float l0 = s.gate_c, K = s.shrink_k, l = y.len;
+        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, 0, pix, gp, (l - l0) / K + l0 - l, q,
+                                       (uint32_t)pix * kRecWords);
+        if (!sh.ok) {
+            rec_W(can, idx) = 0.f;
+            continue;
+        }
+        apply_shift(y, sh);
+        y.phat = sh.phat;
+        store_rec(can, idx, y, W * (sh.J / K));
+    }
+    flush_counters(st, a.counters);
+}
+
+// gate reservoirs left with W = 0 by the shrink mapping become empty
+__global__ void k_shrink_fin(FrameArgs a, ResSet can) {
+    const int P = a.s.P, gp = a.s.n_bins;
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= P || !mask_bit(can.mask, P, gp, pix)) return;
+    if (rec_W(can, (size_t)gp * P + pix) == 0.f)
+        atomicAnd(can.mask + (size_t)(gp >> 5) * P + pix, ~(1u << (gp & 31)));
+}
+
 // one plane passed through unchanged (the gate plane across the bin-axis pass)
 __global__ void k_copy_plane(FrameArgs a, ResSet in, ResSet out, int pl) {
     const int P = a.s.P;
@@ -786,6 +838,13 @@ void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& B
                   hipStream_t st) {
     hipLaunchKernelGGL(k_merge, dim3(grid_for(ci, 256, 32768)), dim3(256), 0, st, a, mode, A, Bp, links, items,
                        task0, count, (uint32_t)i0, (uint32_t)ci, win, fwd, term, shv, round, out);
+}
+void launch_shrink(const FrameArgs& a, const ResSet& can, size_t p0, size_t np, const RayQueue& q, unsigned grid,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_shrink, dim3(grid), dim3(kTB), 0, st, a, can, (uint32_t)p0, (uint32_t)np, q);
+}
+void launch_shrink_fin(const FrameArgs& a, const ResSet& can, hipStream_t st) {
+    hipLaunchKernelGGL(k_shrink_fin, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, can);
 }
 void launch_copy_plane(const FrameArgs& a, const ResSet& in, const ResSet& out, int pl, hipStream_t st) {
     hipLaunchKernelGGL(k_copy_plane, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, in, out, pl);

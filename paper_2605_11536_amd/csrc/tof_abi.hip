@@ -658,7 +658,8 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
               d->newton_max_iter <= 64 && d->j_max >= 1.f &&
               (d->shift_mode == TOF_SHIFT_NAIVE || d->shift_mode == TOF_SHIFT_PATHLEN) &&
               d->debug_stage >= TOF_STAGE_CANONICAL && d->debug_stage <= TOF_STAGE_FINAL &&
-              d->bin_radius >= 0 && d->bin_radius <= 4 &&
+              d->bin_radius >= 0 && d->bin_radius <= 4 && std::isfinite(d->shrink_k) && d->shrink_k >= 1.f &&
+              d->shrink_k <= 1000.f &&
               std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
     // work-list entries (tasks of a pass over fully occupied planes) are 32-bit indices
     ok = ok && (unsigned long long)d->width * d->height * B *
@@ -749,6 +750,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     s.include_direct = d->include_direct;
     s.debug_stage = d->debug_stage;
     s.br = d->bin_radius;
+    s.shrink_k = d->shrink_k;
     s.P = (int)P;
     s.B = B;
     s.mask_words = (int)words;
@@ -1073,6 +1075,20 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
     a.counters = c->counters + (size_t)TOF_K_INITIAL * kBank;
     tofh::launch_initial(a, can, c->pt, c->direct, st);
+    if (c->s.gate_en && c->s.shrink_k > 1.f) {
+        // shrink mapping of the gate reservoirs, in chunks of the spatial
+        // pass's task count (at most 2 visibility segments per pixel)
+        const ChunkPlan& pl = c->plan;
+        const size_t ct = pl.ct[1], NQ = tofd::kRaySubQueues;
+        const tofd::RayQueue qs{c->rays, c->ray_count, (uint32_t)(2 * ct / NQ)};
+        float* kill = (float*)(can.rec + (size_t)c->s.n_bins * P * 5);
+        for (size_t p0 = 0; p0 < P; p0 += ct) {
+            tofh::launch_fill_u32(c->ray_count, 0u, (size_t)tofd::kRaySubQueues * tofd::kCounterStride, st);
+            tofh::launch_shrink(a, can, p0, std::min(ct, P - p0), qs, pl.grid[1], st);
+            tofh::launch_vis(a, 0, qs, kill, pl.vis_grid[1], st);
+        }
+        tofh::launch_shrink_fin(a, can, st);
+    }
     HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
     const bool record_items = c->timing && c->item_used + 4 <= c->item_slots;
     uint32_t* item_slot = record_items ? c->item_hist + c->item_used : nullptr;

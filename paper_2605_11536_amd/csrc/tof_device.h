@@ -116,6 +116,7 @@ struct Sens {
     float j_max;
     int shift_mode, include_direct, debug_stage;
     int br;                  // bin-axis reuse radius (0 = off)
+    float shrink_k;          // shrink mapping of initial gate samples (1 = off)
     int P, B, mask_words;
     uint64_t seed;
 };
@@ -860,6 +861,11 @@ __device__ __forceinline__ float plane_hi(const Sens& s, int pl) {
     return pl < s.n_bins ? s.t0 + (float)(pl + 1) * s.bw : s.gate_c + 0.5f * s.gate_w;
 }
 __device__ __forceinline__ float plane_width(const Sens& s, int pl) { return pl < s.n_bins ? s.bw : s.gate_w; }
+// the wide gate of the shrink mapping: shrink_k times the gate, same centre
+__device__ __forceinline__ bool in_rough_gate(const Sens& s, float l) {
+    const float h = 0.5f * s.shrink_k * s.gate_w;
+    return l >= s.gate_c - h && l < s.gate_c + h;
+}
 __device__ __forceinline__ bool in_plane(const Sens& s, int pl, float l) {
     return l >= plane_lo(s, pl) && l < plane_hi(s, pl);
 }

@@ -105,6 +105,12 @@ void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tof
                   const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,
                   const uint32_t* win, const float4* fwd, const float* term, const float4* shv, int round,
                   tofd::ResSet out, hipStream_t st);
+// Shrink mapping of the gate reservoirs of pixels [p0, p0 + np) (at most 2
+// visibility segments each, queued in q) and, after their visibility, the
+// emptying of the failed ones.
+void launch_shrink(const FrameArgs& a, const tofd::ResSet& can, size_t p0, size_t np, const tofd::RayQueue& q,
+                   unsigned grid, hipStream_t st);
+void launch_shrink_fin(const FrameArgs& a, const tofd::ResSet& can, hipStream_t st);
 // Records and mask bits of plane pl copied from `in` to `out` (the gate plane
 // across the bin-axis pass).
 void launch_copy_plane(const FrameArgs& a, const tofd::ResSet& in, const tofd::ResSet& out, int pl, hipStream_t st);

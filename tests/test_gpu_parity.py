@@ -181,6 +181,18 @@ def test_bin_reuse_chain_parity():
     _run_chain(scenes.nlos_confocal(scan=32, frames=2, torus_nu=125, torus_nv=50, bin_radius=3), ("hist",))
 
 
+def test_shrink_mapping_parity():
+    """Shrink mapping of initial gate samples (Sec. 4.4.2): candidates from a
+    gate K times wider, the winner shifted into the gate; alone (sphere,
+    canonical stage) and followed by temporal and spatial reuse (box)."""
+    gs, os_ = _run_pair(scenes.lambert_sphere_interior(width=40, height=24, frames=2, shrink_k=5.0,
+                                                       debug_stage=scenes.STAGE_CANONICAL))
+    assert gs["shifts"] > 0 and abs(gs["shifts"] - os_["shifts"]) <= 0.002 * os_["shifts"] + 2
+    gs, os_ = _run_pair(scenes.cornell_box(frames=3, shrink_k=10.0))
+    for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+        assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
+
+
 def test_glossy_dynamic_crop_parity():
     """A 64x64 crop of the 512^2 dynamic glossy scene (256 bins + gate,
     moving spheres, temporal + spatial reuse)."""
