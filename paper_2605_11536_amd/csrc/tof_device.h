@@ -17,7 +17,7 @@ constexpr float kPi = 3.14159265358979323846f;
 #define TOF_STACK_DEPTH 48
 #endif
 #ifndef TOF_VIS_STACK_DEPTH
-#define TOF_VIS_STACK_DEPTH 32
+#define TOF_VIS_STACK_DEPTH 24
 #endif
 constexpr int kStackDepth = TOF_STACK_DEPTH;           // per-lane traversal stack entries (LDS)
 constexpr int kVisStackDepth = TOF_VIS_STACK_DEPTH;    // the same for the visibility pass
