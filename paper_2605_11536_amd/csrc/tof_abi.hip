@@ -223,8 +223,9 @@ ChunkPlan plan_chunks(size_t P, size_t B, int k, int br) {
     size_t dense = 0;
     for (int m = 0; m < modes; ++m) dense = std::max(dense, seg[m] * K[m] * P * B * (K[m] + 1));
     // a sixteenth of the rays of a pass over fully occupied planes, within
-    // [2^22, 2^28] rays (134 MB .. 8.6 GB of queue)
-    p.rays = std::min<size_t>((size_t)1 << 28, std::max<size_t>((size_t)1 << 22, dense / 16));
+    // [2^24, 2^28] rays (0.5 .. 8.6 GB of queue); a pass that needs fewer
+    // than 2^24 rays in all runs as one chunk
+    p.rays = std::min<size_t>((size_t)1 << 28, std::max<size_t>(std::min<size_t>(dense, (size_t)1 << 24), dense / 16));
     for (int m = 0; m < modes; ++m) {
         const size_t all = P * B * (K[m] + 1);
         const size_t raw = std::max<size_t>(1, std::min(p.rays / (seg[m] * K[m]), all));
