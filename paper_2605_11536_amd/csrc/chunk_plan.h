@@ -1,0 +1,56 @@
+// Work plan of the reuse passes (host code).
+#pragma once
+
+#include <stddef.h>
+
+#include <algorithm>
+
+namespace tofh {
+
+// Grids of the shift and visibility launches: multiples of the 64 queue
+// parts, at most kShiftGrid / kVisGrid blocks of 128 lanes.
+constexpr unsigned kShiftGrid = 8192;
+constexpr unsigned kVisGrid = 8192;
+inline size_t shift_grid(size_t tasks) {
+    return std::max<size_t>(64, std::min<size_t>(kShiftGrid, ((tasks + 127) / 128 + 63) / 64 * 64));
+}
+
+// A reuse pass runs over chunks of items whose tasks, terms and queued rays
+// fit one workspace: at most `rays` visibility rays per chunk; per mode (0
+// temporal, 1 spatial, 2 bin axis) ct tasks and ci = ct / (K + 1) items per
+// chunk, the shift kernels on `grid` blocks and the visibility kernel on
+// `vis_grid`.
+struct ChunkPlan {
+    size_t rays = 0, ct[3] = {0, 0, 0}, ci[3] = {0, 0, 0}, task_cap = 0, term_cap = 0, ray_cap = 0;
+    unsigned grid[3] = {0, 0, 0}, vis_grid[3] = {0, 0, 0};
+};
+
+inline ChunkPlan plan_chunks(size_t P, size_t B, int k, int br) {
+    ChunkPlan p;
+    const int modes = br > 0 ? 3 : 2;
+    const size_t K[3] = {1, (size_t)std::max(k, 1), 2 * (size_t)std::max(br, 1)};
+    const size_t seg[3] = {4, 2, 2};   // visibility segments per shift: across two frames, within one
+    size_t dense = 0;
+    for (int m = 0; m < modes; ++m) dense = std::max(dense, seg[m] * K[m] * P * B * (K[m] + 1));
+    // a sixteenth of the rays of a pass over fully occupied planes, within
+    // [2^24, 2^28] rays (0.5 .. 8.6 GB of queue); a pass that needs fewer
+    // than 2^24 rays in all runs as one chunk
+    p.rays = std::min<size_t>((size_t)1 << 28, std::max<size_t>(std::min<size_t>(dense, (size_t)1 << 24), dense / 16));
+    for (int m = 0; m < modes; ++m) {
+        const size_t all = P * B * (K[m] + 1);
+        const size_t raw = std::max<size_t>(1, std::min(p.rays / (seg[m] * K[m]), all));
+        const size_t G = tofh::shift_grid(raw), Q = G * 128;
+        // a pass whose every task fits takes one chunk (rounded up to the
+        // grid), else whole grid sweeps within the budget
+        p.ct[m] = raw >= all ? (all + Q - 1) / Q * Q : std::max(Q, raw / Q * Q);
+        p.ci[m] = std::max<size_t>(1, p.ct[m] / (K[m] + 1));
+        p.grid[m] = (unsigned)G;
+        p.vis_grid[m] = (unsigned)tofh::shift_grid(seg[m] * K[m] * p.ct[m]);
+        p.task_cap = std::max(p.task_cap, p.ct[m]);
+        p.term_cap = std::max(p.term_cap, K[m] * p.ct[m]);
+        p.ray_cap = std::max(p.ray_cap, seg[m] * K[m] * p.ct[m]);
+    }
+    return p;
+}
+
+}  // namespace tofh

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "tof.h"
+#include "chunk_plan.h"
 #include "tof_internal.h"
 
 using namespace tofd;
@@ -47,16 +48,6 @@ struct SlotHost {
     float* gb_xi1 = nullptr;
     float4* gb_p = nullptr;
     float4* gb_n = nullptr;
-};
-
-// A reuse pass runs over chunks of items whose tasks, terms and queued rays
-// fit one workspace: at most `rays` visibility rays per chunk; per mode (0
-// temporal, 1 spatial, 2 bin axis) ct tasks and ci = ct / (K + 1) items per
-// chunk, the shift kernels on `grid` blocks and the visibility kernel on
-// `vis_grid`.
-struct ChunkPlan {
-    size_t rays = 0, ct[3] = {0, 0, 0}, ci[3] = {0, 0, 0}, task_cap = 0, term_cap = 0, ray_cap = 0;
-    unsigned grid[3] = {0, 0, 0}, vis_grid[3] = {0, 0, 0};
 };
 
 }  // namespace
@@ -113,7 +104,7 @@ struct tof_ctx {
     uint32_t* mis_count = nullptr;
     uint32_t* count = nullptr;      // [0] items, [1] tasks, [2..3] window of the current chunk
     size_t max_items = 0;
-    ChunkPlan plan;
+    tofh::ChunkPlan plan;
     // misc
     unsigned long long* counters = nullptr;
     float* xf_pinned[2] = {nullptr, nullptr};
@@ -215,31 +206,6 @@ V3 hcross(V3 a, V3 b) { return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, 
 
 constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 
-ChunkPlan plan_chunks(size_t P, size_t B, int k, int br) {
-    ChunkPlan p;
-    const int modes = br > 0 ? 3 : 2;
-    const size_t K[3] = {1, (size_t)std::max(k, 1), 2 * (size_t)std::max(br, 1)};
-    const size_t seg[3] = {4, 2, 2};   // visibility segments per shift: across two frames, within one
-    size_t dense = 0;
-    for (int m = 0; m < modes; ++m) dense = std::max(dense, seg[m] * K[m] * P * B * (K[m] + 1));
-    // a sixteenth of the rays of a pass over fully occupied planes, within
-    // [2^24, 2^28] rays (0.5 .. 8.6 GB of queue); a pass that needs fewer
-    // than 2^24 rays in all runs as one chunk
-    p.rays = std::min<size_t>((size_t)1 << 28, std::max<size_t>(std::min<size_t>(dense, (size_t)1 << 24), dense / 16));
-    for (int m = 0; m < modes; ++m) {
-        const size_t all = P * B * (K[m] + 1);
-        const size_t raw = std::max<size_t>(1, std::min(p.rays / (seg[m] * K[m]), all));
-        const size_t G = tofh::shift_grid(raw), Q = G * 128;
-        p.ct[m] = std::max(Q, raw / Q * Q);
-        p.ci[m] = std::max<size_t>(1, p.ct[m] / (K[m] + 1));
-        p.grid[m] = (unsigned)G;
-        p.vis_grid[m] = (unsigned)tofh::shift_grid(seg[m] * K[m] * p.ct[m]);
-        p.task_cap = std::max(p.task_cap, p.ct[m]);
-        p.term_cap = std::max(p.term_cap, K[m] * p.ct[m]);
-        p.ray_cap = std::max(p.ray_cap, seg[m] * K[m] * p.ct[m]);
-    }
-    return p;
-}
 
 size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t P = (size_t)d.width * d.height;
@@ -247,7 +213,7 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t words = (B + 31) / 32;
     size_t per_set = P * B * kRecBytes + P * 4 + P * words * 4;
     size_t gbuf = 2 * P * (4 + 4 + 4 + 16 + 16);
-    const ChunkPlan pl = plan_chunks(P, B, d.spatial_k, d.bin_radius);
+    const tofh::ChunkPlan pl = tofh::plan_chunks(P, B, d.spatial_k, d.bin_radius);
     return 4 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
            P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ + P * B * 4 /*first task per item*/ +
            pl.task_cap * (8 + 16 + 32) /*tasks, forward terms, shifted fields*/ +
@@ -701,7 +667,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->direct, P));
     TOF_TRY(alloc_t(c, a, &c->prev_pix, P));
     TOF_TRY(alloc_t(c, a, &c->nb, P * (size_t)std::max(d->spatial_k, 1)));
-    const ChunkPlan& pl = c->plan = plan_chunks(P, (size_t)B, d->spatial_k, d->bin_radius);
+    const tofh::ChunkPlan& pl = c->plan = tofh::plan_chunks(P, (size_t)B, d->spatial_k, d->bin_radius);
     TOF_TRY(alloc_t(c, a, &c->items, P * B));
     TOF_TRY(alloc_t(c, a, &c->task0, P * B));
     TOF_TRY(alloc_t(c, a, &c->tasks, pl.task_cap));
@@ -890,7 +856,7 @@ tof_status run_pass(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, c
     const int km = mode == 0 ? TOF_K_TEMPORAL_MIS : TOF_K_SPATIAL_MIS;
     const int kv = mode == 0 ? TOF_K_TEMPORAL_VIS : TOF_K_SPATIAL_VIS;
     const int kg = mode == 0 ? TOF_K_TEMPORAL_MERGE : TOF_K_SPATIAL_MERGE;
-    const ChunkPlan& pl = c->plan;
+    const tofh::ChunkPlan& pl = c->plan;
     const size_t K = mode == 0 ? 1 : (mode == 1 ? (size_t)c->s.k : 2 * (size_t)c->s.br);
     // at most 4 segments per shift across frames (temporal), 2 within one frame
     const size_t seg = mode == 0 ? 4 : 2;
@@ -1079,7 +1045,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     if (c->s.gate_en && c->s.shrink_k > 1.f) {
         // shrink mapping of the gate reservoirs, in chunks of the spatial
         // pass's task count (at most 2 visibility segments per pixel)
-        const ChunkPlan& pl = c->plan;
+        const tofh::ChunkPlan& pl = c->plan;
         const size_t ct = pl.ct[1], NQ = tofd::kRaySubQueues;
         const tofd::RayQueue qs{c->rays, c->ray_count, (uint32_t)(2 * ct / NQ)};
         float* kill = (float*)(can.rec + (size_t)c->s.n_bins * P * 5);

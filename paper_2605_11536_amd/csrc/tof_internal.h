@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "chunk_plan.h"
 #include "tof.h"
 #include "tof_device.h"
 
@@ -73,16 +74,11 @@ void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const
                   hipStream_t st);
 
 // A reuse pass runs over chunks of ci items; the chunk's tasks, forward and
-// MIS terms and queued rays live in a workspace sized for the chunk.  The
-// shift kernels run a fixed grid of G blocks of 128 lanes (G a multiple of
-// the 64 queue parts, at most kShiftGrid) in a grid-stride loop over at most
-// ct tasks, ct a multiple of G * 128, so that every sub-queue receives the
-// work of at most ct / 64 tasks.
-constexpr unsigned kShiftGrid = 8192;
-constexpr unsigned kVisGrid = 8192;
-inline size_t shift_grid(size_t tasks) {
-    return std::max<size_t>(64, std::min<size_t>(kShiftGrid, ((tasks + 127) / 128 + 63) / 64 * 64));
-}
+// MIS terms and queued rays live in a workspace sized for the chunk
+// (chunk_plan.h).  The shift kernels run a fixed grid of G blocks of 128
+// lanes (G a multiple of the 64 queue parts) in a grid-stride loop over at
+// most ct tasks, ct a multiple of G * 128, so that every sub-queue receives
+// the work of at most ct / 64 tasks.
 
 // Tasks of items [i0, i0 + ci) into tasks[] (chunk-relative), and the
 // chunk's window win = (first task, task count).
