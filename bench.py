@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 # Algorithmic work model: counted events x fixed per-event costs
-NODE_BYTES = 128        # one 4-wide BVH node: four child boxes, links and count
+NODE_BYTES = 64         # one 4-wide BVH node as traversal reads it: four quantized child boxes, links, count
 TRI_BYTES = 48          # one leaf: three float4 vertices
 F_NODE = 125            # FP32 ops of one node visit (four slab tests, sorting network of the hits)
 F_TRI = 47              # FP32 ops of one watertight ray/triangle test

@@ -43,9 +43,37 @@ __global__ void k_leaf_gather(const int* __restrict__ leaf_tri, const int4* __re
 __device__ __forceinline__ float pad_lo(float x) { return x - (fabsf(x) + 1.0f) * 9.5367431640625e-7f; }
 __device__ __forceinline__ float pad_hi(float x) { return x + (fabsf(x) + 1.0f) * 9.5367431640625e-7f; }
 
-// one height level: every child box of the listed nodes from the level below
-__global__ void k_refit(Node4* nodes, const uint32_t* __restrict__ order, int n, const float4* __restrict__ leaves,
-                        int T) {
+// smallest biased exponent b (scale 2^(b - 127)) with 255 * scale >= extent
+__device__ __forceinline__ uint32_t quant_exp(float extent) {
+    uint32_t b = 1;
+    if (extent > 0.f) {
+        const float need = extent * (1.0f / 255.0f);
+        b = ((uint32_t)__float_as_int(need) >> 23) & 0xFFu;   // 2^(b-127) <= need (need normal, positive)
+        if (__int_as_float((int)(b << 23)) < need) ++b;
+        while (255.0f * __int_as_float((int)(b << 23)) < extent) ++b;   // the product rounds; at most a step
+        b = b < 1 ? 1 : (b > 254 ? 254 : b);
+    }
+    return b;
+}
+// plane lo (down) or hi (up) of a child box in units of `scale` from org, 0..255
+__device__ __forceinline__ uint32_t quant_lo(float x, float org, float scale) {
+    const float q = floorf((x - org) / scale);
+    float v = fminf(fmaxf(q, 0.f), 255.f);
+    while (v > 0.f && fmaf(v, scale, org) > x) v -= 1.f;   // the decoded plane must not exceed x
+    return (uint32_t)v;
+}
+__device__ __forceinline__ uint32_t quant_hi(float x, float org, float scale) {
+    const float q = ceilf((x - org) / scale);
+    float v = fminf(fmaxf(q, 0.f), 255.f);
+    while (v < 255.f && fmaf(v, scale, org) < x) v += 1.f;   // the decoded plane must not fall below x
+    return (uint32_t)v;
+}
+
+// one height level: every child box of the listed nodes from the level below;
+// the exact boxes go to `nodes` (for the parents' refit), the quantized node
+// that traversal reads to `nq`
+__global__ void k_refit(Node4* nodes, NodeQ* __restrict__ nq, const uint32_t* __restrict__ order, int n,
+                        const float4* __restrict__ leaves, int T) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     Node4* nd = nodes + order[i];
@@ -106,6 +134,33 @@ __global__ void k_refit(Node4* nodes, const uint32_t* __restrict__ order, int n,
     nd->hix = make_float4(hi[0][0], hi[1][0], hi[2][0], hi[3][0]);
     nd->hiy = make_float4(hi[0][1], hi[1][1], hi[2][1], hi[3][1]);
     nd->hiz = make_float4(hi[0][2], hi[1][2], hi[2][2], hi[3][2]);
+    // quantized copy relative to the union of the children
+    float org[3], sc[3];
+    uint32_t eb[3], wl[3] = {0, 0, 0}, wh[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+        float l = 3e38f, h = -3e38f;
+        for (int j = 0; j < 4; ++j)
+            if (j < nc) {
+                l = fminf(l, lo[j][k]);
+                h = fmaxf(h, hi[j][k]);
+            }
+        if (!(l <= h)) l = h = 0.f;
+        org[k] = l;
+        eb[k] = quant_exp(h - l);
+        sc[k] = __int_as_float((int)(eb[k] << 23));
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t ql = j < nc ? quant_lo(lo[j][k], l, sc[k]) : 0u;
+            const uint32_t qh = j < nc ? quant_hi(hi[j][k], l, sc[k]) : 0u;
+            wl[k] |= ql << (8 * j);
+            wh[k] |= qh << (8 * j);
+        }
+    }
+    NodeQ q;
+    q.org = make_float4(org[0], org[1], org[2], 0.f);
+    q.q0 = make_uint4(wl[0], wh[0], wl[1], wh[1]);
+    q.q1 = make_uint4(wl[2], wh[2], eb[0] | (eb[1] << 8) | (eb[2] << 16), (uint32_t)nc);
+    q.child = cc;
+    nq[order[i]] = q;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
@@ -137,12 +192,12 @@ void launch_leaf_gather(const int* leaf_tri, const int4* tv, const float4* wv, i
     hipLaunchKernelGGL(k_leaf_gather, dim3(blocks_for(T, 256)), dim3(256), 0, st, leaf_tri, tv, wv, T, leaves);
 }
 
-void launch_refit(tofd::Node4* nodes, const uint32_t* order, const std::vector<int>& level_off,
+void launch_refit(tofd::Node4* nodes, tofd::NodeQ* nq, const uint32_t* order, const std::vector<int>& level_off,
                   const float4* leaves, int T, hipStream_t st) {
     for (size_t l = 0; l + 1 < level_off.size(); ++l) {
         const int n = level_off[l + 1] - level_off[l];
         if (n <= 0) continue;
-        hipLaunchKernelGGL(k_refit, dim3(blocks_for(n, 128)), dim3(128), 0, st, nodes, order + level_off[l], n,
+        hipLaunchKernelGGL(k_refit, dim3(blocks_for(n, 128)), dim3(128), 0, st, nodes, nq, order + level_off[l], n,
                            leaves, T);
     }
 }

@@ -30,6 +30,7 @@ struct GeomBuf {
     float* xf = nullptr;
     float4* wv = nullptr;
     Node4* nodes = nullptr;      // [n_nodes]: the tree over the objects, then the objects' trees
+    NodeQ* nodesq = nullptr;     // [n_nodes]: the same nodes quantized, as traversal reads them
     uint32_t* order = nullptr;   // refit order: object-tree nodes by height, then the top tree's
     float4* leaves = nullptr;
     std::vector<float> xf_host;
@@ -236,7 +237,8 @@ size_t scene_footprint(const tof_scene_desc& d) {
         }
     const size_t V = (size_t)std::max(d.num_vertices, 1), O = (size_t)d.num_objects, N = mesh + T + 1;
     return O * (sizeof(Obj) + 4) + (size_t)d.num_materials * sizeof(Mat) + T * (sizeof(TriInfo) + 16 + 4) +
-           V * (16 + 4) + 2 * (48 * O + 16 * V + (sizeof(Node4) + 4) * N + 48 * std::max<size_t>(T, 1)) + 64 * 1024;
+           V * (16 + 4) + 2 * (48 * O + 16 * V + (sizeof(Node4) + sizeof(NodeQ) + 4) * N + 48 * std::max<size_t>(T, 1)) +
+           64 * 1024;
 }
 
 tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
@@ -280,7 +282,7 @@ SlotDev slot_dev(const tof_ctx* c, int i) {
     SlotDev d;
     d.wv = g.wv;
     d.xf = g.xf;
-    d.nodes = g.nodes;
+    d.nodes = g.nodesq;
     d.n_nodes = c->n_nodes;
     d.leaves = g.leaves;
     d.n_tri = c->n_tri;
@@ -575,9 +577,11 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
         TOF_TRY(alloc_t(c, a, &g.xf, 12 * (size_t)objs.size()));
         TOF_TRY(alloc_t(c, a, &g.wv, std::max(d->num_vertices, 1)));
         TOF_TRY(alloc_t(c, a, &g.nodes, (size_t)c->n_nodes));
+        TOF_TRY(alloc_t(c, a, &g.nodesq, (size_t)c->n_nodes));
         TOF_TRY(alloc_t(c, a, &g.order, (size_t)c->n_nodes));
         TOF_TRY(alloc_t(c, a, &g.leaves, 3 * (size_t)std::max(T, 1)));
         HIP_TRY(hipMemset(g.nodes, 0, sizeof(Node4) * (size_t)c->n_nodes));
+        HIP_TRY(hipMemset(g.nodesq, 0, sizeof(NodeQ) * (size_t)c->n_nodes));
         if (c->n_blas) {
             HIP_TRY(hipMemcpy(g.nodes + c->n_tlas_cap, blas.data(), sizeof(Node4) * blas.size(), hipMemcpyHostToDevice));
             HIP_TRY(hipMemcpy(g.order, border.data(), sizeof(uint32_t) * border.size(), hipMemcpyHostToDevice));
@@ -998,7 +1002,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, c->n_vert, st);
         tofh::launch_leaf_gather(c->d_leaf_tri, c->d_tv, g.wv, c->n_tri, g.leaves, st);
-        tofh::launch_refit(g.nodes, g.order, levels, g.leaves, c->n_tri, st);
+        tofh::launch_refit(g.nodes, g.nodesq, g.order, levels, g.leaves, c->n_tri, st);
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         g.built = true;
     }

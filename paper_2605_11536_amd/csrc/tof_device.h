@@ -74,6 +74,19 @@ struct Node4 {
     int4 meta;
 };
 
+// The node as traversal reads it: 64 bytes, four 16-byte loads instead of
+// eight.  Child boxes are quantized to 8 bits per plane relative to the
+// node's box: plane = org + q * 2^e per axis, with lower planes rounded down
+// and upper planes up, so every child box contains its exact (padded) box.
+// q0 = (lo_x, hi_x, lo_y, hi_y), q1 = (lo_z, hi_z, exponents, child count),
+// one byte per child in each word, exponents biased by 127 in bytes 0..2.
+struct NodeQ {
+    float4 org;
+    uint4 q0, q1;
+    int4 child;
+};
+static_assert(sizeof(NodeQ) == 64, "NodeQ is one 64-byte line");
+
 struct SceneDev {
     const Obj* objs;
     const Mat* mats;
@@ -87,7 +100,7 @@ struct SceneDev {
 struct SlotDev {
     const float4* wv;       // world vertices
     const float* xf;        // object transforms, 12 floats each
-    const Node4* nodes;     // 4-wide traversal nodes, root at 0
+    const NodeQ* nodes;     // 4-wide traversal nodes (quantized), root at 0
     int n_nodes;
     const float4* leaves;   // 3 float4 per sorted triangle: v0 (w = tri id bits), v1, v2
     int n_tri;
@@ -521,11 +534,22 @@ __device__ inline bool traverse(const SceneDev& S, const SlotDev& G, V3 o, V3 d,
                     sp = 0;
                     break;
                 }
-                // the whole 128-byte node, loaded unconditionally
-                const float4* nq = reinterpret_cast<const float4*>(G.nodes + node);
-                const float4 lx = nq[0], ly = nq[1], lz = nq[2], hx = nq[3], hy = nq[4], hz = nq[5];
-                const int4 cc = reinterpret_cast<const int4*>(nq)[6];
-                const int nc = reinterpret_cast<const int4*>(nq)[7].x;
+                // the whole 64-byte node, loaded unconditionally, boxes decoded
+                const NodeQ* nq = G.nodes + node;
+                const float4 org = nq->org;
+                const uint4 q0 = nq->q0, q1 = nq->q1;
+                const int4 cc = nq->child;
+                const int nc = (int)q1.w;
+                const float sx = __int_as_float((int)((q1.z & 0xFFu) << 23));
+                const float sy = __int_as_float((int)(((q1.z >> 8) & 0xFFu) << 23));
+                const float sz = __int_as_float((int)(((q1.z >> 16) & 0xFFu) << 23));
+                auto deq = [](uint32_t w, float o, float sc) {
+                    return make_float4(fmaf((float)(w & 0xFFu), sc, o), fmaf((float)((w >> 8) & 0xFFu), sc, o),
+                                       fmaf((float)((w >> 16) & 0xFFu), sc, o), fmaf((float)(w >> 24), sc, o));
+                };
+                const float4 lx = deq(q0.x, org.x, sx), hx = deq(q0.y, org.x, sx);
+                const float4 ly = deq(q0.z, org.y, sy), hy = deq(q0.w, org.y, sy);
+                const float4 lz = deq(q1.x, org.z, sz), hz = deq(q1.y, org.z, sz);
                 st.c[ST_NODES]++;
                 // all four boxes, without branches; children j >= nc are padding
                 float t0, t1, t2, t3;

@@ -48,7 +48,7 @@ void launch_leaf_gather(const int* leaf_tri, const int4* tv, const float4* wv, i
                         hipStream_t st);
 // boxes of the nodes order[level_off[l] .. level_off[l+1]) for l = 0, 1, ...
 // (children before parents)
-void launch_refit(tofd::Node4* nodes, const uint32_t* order, const std::vector<int>& level_off,
+void launch_refit(tofd::Node4* nodes, tofd::NodeQ* nq, const uint32_t* order, const std::vector<int>& level_off,
                   const float4* leaves, int T, hipStream_t st);
 
 // render.hip
