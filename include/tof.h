@@ -175,6 +175,12 @@ tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
  *   out_image    [height*width]           ReSTIR gate image
  *   out_hist     [n_bins*height*width]    ReSTIR transient histogram
  *   out_pt_image / out_pt_hist            plain ToF path tracing of the same frame
+ * The frames of one context depend on each other (temporal reuse, scratch
+ * work lists): issue them on one stream, or order the streams.  Calls that
+ * read or replace the context's state (stats, timing, history, scene, sensor)
+ * wait for the last frame issued, not for the whole device.  The bin-axis
+ * pass and the shrink mapping count into the spatial and initial kernel
+ * groups of tof_kernel_times.
  * Errors: TOF_ERR_NOT_READY without scene+sensor; TOF_ERR_INVALID_ARG for a
  * NULL frame/xforms or an image requested without a gate; TOF_ERR_DEVICE on a
  * HIP error. */
