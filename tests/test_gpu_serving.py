@@ -17,6 +17,9 @@ def _workloads():
         "glossy": scenes.glossy_dynamic(width=64, height=64, full_width=512, full_height=512, crop_x0=224,
                                         crop_y0=200, frames=3),
         "nlos": scenes.nlos_confocal(scan=32, frames=3, torus_nu=125, torus_nv=50),
+        # bins around the gate with bin-axis reuse, and the shrink mapping
+        "box_bins": scenes.cornell_box(frames=3, n_bins=16, bin_t0=2.6, bin_width=0.1, bin_radius=2, seed=3),
+        "box_shrink": scenes.cornell_box(frames=3, shrink_k=10.0, seed=5),
     }
 
 
