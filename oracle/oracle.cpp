@@ -25,7 +25,12 @@
  *     distance, Delta l = (b - b') * bin width);
  *   - optionally, initial gate samples drawn in a gate K times wider and the
  *     RIS winner shrunk into the gate (Sec. 4.4.2, shrink mapping, with all
- *     samples in the wide gate, R = 1).
+ *     samples in the wide gate, R = 1);
+ *   - the Doppler domain (Sec. 4.6): planes over the path velocity
+ *     u = -dl/dt (eq. optical_path_velocity, refractive index 1) with the
+ *     vertices moving rigidly with their objects, and the same shift under a
+ *     path-velocity constraint; its gradient and Hessian are derived here
+ *     (the supplement that holds them is not available).
  * Where a passage is ambiguous or garbled, the code states the reading it
  * takes.
  *
@@ -34,7 +39,10 @@
  * plane; the confocal radial closed form of the Newton shift; finite-difference
  * Jacobians; the gate constraint; the identity shift; bijectivity; WRS
  * selection frequencies; unbiasedness of the full ReSTIR estimator against
- * plain path tracing.  Parity of the complete multi-pass image beyond these
+ * plain path tracing; the path velocity against a time difference of the
+ * path length of the moved scene, its chart gradient and Hessian against
+ * finite differences, and the closed-form Doppler spectrum of a receding
+ * Lambertian plane.  Parity of the complete multi-pass image beyond these
  * properties is "parity unpinned" (no per-pixel values exist in the paper).
  */
 #include "oracle.h"
@@ -147,6 +155,8 @@ struct FrameGeom {
     V3 cam_pos, cam_fwd, cam_right, cam_up;
     double tan_half = 0, aspect = 1, ortho_hx = 0, ortho_hy = 0;
     V3 light_pos;
+    std::vector<double> ov;      // per object: linear velocity v, angular velocity w
+    V3 cam_vel, light_vel;
 };
 
 struct GBuf { bool hit = false; Vertex v; };
@@ -311,6 +321,11 @@ struct Oracle {
         F.ortho_hx = fr->ortho_half[0];
         F.ortho_hy = fr->ortho_half[1];
         F.light_pos = {fr->light_pos[0], fr->light_pos[1], fr->light_pos[2]};
+        F.ov.assign(6 * O, 0.0);
+        if (fr->velocities)
+            for (int k = 0; k < 6 * O; ++k) F.ov[k] = (double)fr->velocities[k];
+        F.cam_vel = {fr->cam_vel[0], fr->cam_vel[1], fr->cam_vel[2]};
+        F.light_vel = {fr->light_vel[0], fr->light_vel[1], fr->light_vel[2]};
     }
 
     // -------------------------------------------------------------------
@@ -565,9 +580,35 @@ struct Oracle {
         if (s.camera_model == 0) return normalize(F.cam_pos - y1.p);
         return -F.cam_fwd;
     }
+    // -------------------------------------------------------------------
+    // The quantity the planes measure (Sec. 3.1 for time, Sec. 4.6 for
+    // Doppler): the optical path length l, or the path velocity
+    // u = -dl/dt = sum over segments of (v_from - v_to) . w, w the unit vector
+    // of the segment (eq. optical_path_velocity), with the vertices moving
+    // with their objects' instantaneous rigid motion.
+    // -------------------------------------------------------------------
+    struct EP { V3 p, v; };   // a path vertex: position and velocity
+    V3 vel_at(const FrameGeom& F, int obj, V3 x) const {
+        if (obj < 0 || F.ov.empty()) return V3();
+        const double* q = &F.ov[6 * obj];
+        V3 t = {F.xf[12 * obj + 3], F.xf[12 * obj + 7], F.xf[12 * obj + 11]};
+        return V3(q[0], q[1], q[2]) + cross(V3(q[3], q[4], q[5]), x - t);
+    }
+    EP ep(const FrameGeom& F, const Vertex& y) const { return EP{y.p, vel_at(F, y.obj, y.p)}; }
+    // contribution of the segment from -> to
+    double seg_q(const EP& from, const EP& to) const {
+        V3 d = to.p - from.p;
+        double l = length(d);
+        if (s.domain == 0) return l;
+        return dot(from.v - to.v, (1.0 / l) * d);
+    }
     double camera_leg(int slot, const Vertex& y1) const {
         if (!s.count_camera_leg) return 0.0;
         const FrameGeom& F = fg[slot];
+        if (s.domain == 1) {
+            V3 dir = s.camera_model == 0 ? normalize(y1.p - F.cam_pos) : F.cam_fwd;
+            return dot(F.cam_vel - vel_at(F, y1.obj, y1.p), dir);
+        }
         if (s.camera_model == 0) return length(y1.p - F.cam_pos);
         return dot(y1.p - F.cam_pos, F.cam_fwd);
     }
@@ -577,6 +618,10 @@ struct Oracle {
     V3 light_pos(int slot, int pix) const {
         if (s.light_model == 0) return fg[slot].light_pos;
         return gb[slot][pix].v.p;
+    }
+    EP light_ep(int slot, int pix) const {
+        if (s.light_model == 0) return EP{fg[slot].light_pos, fg[slot].light_vel};
+        return ep(fg[slot], gb[slot][pix].v);
     }
     double light_emit(int slot, int pix, V3 x) const {
         if (s.light_model == 0) return s.light_intensity;
@@ -702,7 +747,10 @@ struct Oracle {
     // path contribution f(y) in the product solid-angle measure of the
     // sampled directions, with NEE to the delta light (no visibility).
     // -------------------------------------------------------------------
+    // throughput of the path ys -> light in a frame slot; len receives the
+    // plane quantity (path length or path velocity)
     double path_eval(int slot, int pix, const std::vector<Vertex>& ys, double& len) const {
+        const FrameGeom& F = fg[slot];
         V3 wi = toward_camera(slot, ys[0]);
         double f = 1.0;
         len = camera_leg(slot, ys[0]);
@@ -711,7 +759,7 @@ struct Oracle {
             double dl = length(dv);
             V3 wo = (1.0 / dl) * dv;
             f *= bsdf(ys[j].obj, ys[j].n, wi, wo) * std::fabs(dot(ys[j].n, wo));
-            len += dl;
+            len += seg_q(ep(F, ys[j]), ep(F, ys[j + 1]));
             wi = -wo;
         }
         const Vertex& y = ys.back();
@@ -720,38 +768,77 @@ struct Oracle {
         double dl = length(dv);
         V3 wo = (1.0 / dl) * dv;
         f *= bsdf(y.obj, y.n, wi, wo) * std::fabs(dot(y.n, wo)) * light_emit(slot, pix, y.p) / (dl * dl);
-        len += dl;
+        len += seg_q(ep(F, y), light_ep(slot, pix));
         return f;
     }
 
     // -------------------------------------------------------------------
-    // Newton solve of the path-length constraint with the average-gradient
-    // gauge (Sec. 4.3).  Reading: the length functions use the source
-    // endpoints at xi and the destination endpoints at xi', and dF2/dxi' is
-    // derived by differentiating F2 (the printed sign of its Hessian term is
-    // not used).
+    // Newton solve of the path constraint with the average-gradient gauge
+    // (Sec. 4.3; Sec. 4.6 swaps the path length for the path velocity).
+    // Reading: the constraint functions use the source endpoints at xi and
+    // the destination endpoints at xi', and dF2/dxi' is derived by
+    // differentiating F2 (the printed sign of its Hessian term is not used).
+    //
+    // The constraint function of the reconnection vertex p = p(xi) with fixed
+    // neighbours a and b is c + phi_a(p) + phi_b(p), where
+    //   time:     phi_a(p) = |p - a|
+    //   velocity: phi_a(p) = (v_a - v(p)) . d,  d = (p - a) / |p - a|,
+    // the second being the two segments' terms of the path velocity written
+    // from a's side (a segment's term does not depend on its direction).  With
+    // the rigid motion v(p) = V + W x (p - t), l = |p - a|, w = v_a - v(p) and
+    // P = I - d d^T (the supplement with these derivations is not available;
+    // they are derived here and pinned by finite differences):
+    //   grad phi_a = W x d + P w / l
+    //   Hess phi_a x = (d (d.(W x x)) - (d.x) (W x d)) / l
+    //                  - ((d.w) P x + d (P w . x) + P w (d.x)) / l^2
+    // and in chart coordinates g = J^T grad, H = J^T Hess J + grad . p_ij.
     // -------------------------------------------------------------------
     struct LenEval { bool ok = false; double L = 0, g[2] = {0, 0}, H[2][2] = {{0, 0}, {0, 0}}; double area = 0; };
-    LenEval len_eval(const FrameGeom& F, int obj, double u, double v, V3 a, V3 b, double c) const {
+    LenEval len_eval(const FrameGeom& F, int obj, double u, double v, const EP& a, const EP& b, double c) const {
+        return constraint_eval(F, obj, u, v, a, b, c, s.domain);
+    }
+    LenEval constraint_eval(const FrameGeom& F, int obj, double u, double v, const EP& a, const EP& b, double c,
+                            int domain) const {
         LenEval e;
         ChartEval ch = chart(F, obj, u, v);
         if (!ch.ok) return e;
-        V3 r1 = a - ch.p, r2 = b - ch.p;
-        double l1 = length(r1), l2 = length(r2);
-        if (!(l1 > 0.0 && l2 > 0.0)) return e;
-        V3 d1 = (1.0 / l1) * r1, d2 = (1.0 / l2) * r2;
-        V3 sv = d1 + d2;
-        e.L = c + l1 + l2;
-        // grad_p l = -s; grad_xi l = J^T (-s)
-        e.g[0] = -dot(sv, ch.ju);
-        e.g[1] = -dot(sv, ch.jv);
-        // Hessian: J^T A J + Q with A = sum (I - d d^T)/|p_i - p|, Q_ij = (-s).p_ij
-        auto A = [&](V3 x) { return (1.0 / l1) * (x - dot(d1, x) * d1) + (1.0 / l2) * (x - dot(d2, x) * d2); };
-        V3 Aju = A(ch.ju), Ajv = A(ch.jv);
-        e.H[0][0] = dot(ch.ju, Aju) - dot(sv, ch.puu);
-        e.H[0][1] = dot(ch.ju, Ajv) - dot(sv, ch.puv);
+        const V3 vp = vel_at(F, obj, ch.p);
+        const V3 W = F.ov.empty() ? V3() : V3(F.ov[6 * obj + 3], F.ov[6 * obj + 4], F.ov[6 * obj + 5]);
+        double val = c;
+        V3 grad;
+        V3 Hju, Hjv;   // Hess_p applied to the chart tangents
+        for (const EP* e2 : {&a, &b}) {
+            V3 r = ch.p - e2->p;
+            double l = length(r);
+            if (!(l > 0.0)) return e;
+            V3 d = (1.0 / l) * r;
+            if (domain == 0) {
+                val += l;
+                grad = grad + d;
+                auto Hx = [&](V3 x) { return (1.0 / l) * (x - dot(d, x) * d); };
+                Hju = Hju + Hx(ch.ju);
+                Hjv = Hjv + Hx(ch.jv);
+            } else {
+                V3 w = e2->v - vp;
+                V3 Pw = w - dot(d, w) * d;
+                val += dot(w, d);
+                grad = grad + cross(W, d) + (1.0 / l) * Pw;
+                auto Hx = [&](V3 x) {
+                    V3 t1 = (1.0 / l) * (dot(d, cross(W, x)) * d - dot(d, x) * cross(W, d));
+                    V3 t2 = dot(d, w) * (x - dot(d, x) * d) + dot(Pw, x) * d + dot(d, x) * Pw;
+                    return t1 - (1.0 / (l * l)) * t2;
+                };
+                Hju = Hju + Hx(ch.ju);
+                Hjv = Hjv + Hx(ch.jv);
+            }
+        }
+        e.L = val;
+        e.g[0] = dot(grad, ch.ju);
+        e.g[1] = dot(grad, ch.jv);
+        e.H[0][0] = dot(ch.ju, Hju) + dot(grad, ch.puu);
+        e.H[0][1] = dot(ch.ju, Hjv) + dot(grad, ch.puv);
         e.H[1][0] = e.H[0][1];
-        e.H[1][1] = dot(ch.jv, Ajv) - dot(sv, ch.pvv);
+        e.H[1][1] = dot(ch.jv, Hjv) + dot(grad, ch.pvv);
         e.area = length(cross(ch.ju, ch.jv));
         e.ok = true;
         return e;
@@ -759,8 +846,9 @@ struct Oracle {
 
     struct NewtonOut { bool conv = false; double xi[2] = {0, 0}; int iters = 0; double det_dxi = 0, det_area = 0, F[2] = {0, 0}; int status = 0; };
 
-    NewtonOut newton(const FrameGeom& FS, const FrameGeom& FD, int obj, const double xi[2], V3 as, V3 bs,
-                     double cs, V3 ad, V3 bd, double cd, double dl0, double tol, int maxit) const {
+    NewtonOut newton(const FrameGeom& FS, const FrameGeom& FD, int obj, const double xi[2], const EP& as,
+                     const EP& bs, double cs, const EP& ad, const EP& bd, double cd, double dl0, double tol,
+                     int maxit) const {
         NewtonOut out;
         LenEval S = len_eval(FS, obj, xi[0], xi[1], as, bs, cs);
         if (!S.ok) { out.status = 1; return out; }
@@ -906,32 +994,34 @@ struct Oracle {
         Vertex p_s = vertex_at(FS, x.p);
         const bool p2light = x.p2.obj < 0;
         Vertex p2_s, p2_d;
-        V3 p2s_pos, p2d_pos;
+        EP p2s_ep, p2d_ep;
         if (p2light) {
-            p2s_pos = light_pos(src_slot, src_pix);
-            p2d_pos = light_pos(dst_slot, dst_pix);
+            p2s_ep = light_ep(src_slot, src_pix);
+            p2d_ep = light_ep(dst_slot, dst_pix);
         } else {
             p2_s = vertex_at(FS, x.p2);
             p2_d = vertex_at(FD, x.p2);
-            p2s_pos = p2_s.p;
-            p2d_pos = p2_d.p;
+            p2s_ep = ep(FS, p2_s);
+            p2d_ep = ep(FD, p2_d);
         }
         std::vector<Vertex> sfx_d;
         for (int q = 0; q < x.nsfx; ++q) sfx_d.push_back(vertex_at(FD, x.sfx[q]));
-        double c_src = x.len - length(xkm1_s.p - p_s.p) - length(p2s_pos - p_s.p);
+        // the rest of the path's quantity, fixed while p moves
+        const EP xkm1_ep = ep(FS, xkm1_s), p_ep = ep(FS, p_s), ykm1_ep = ep(FD, ykm1);
+        double c_src = x.len - seg_q(xkm1_ep, p_ep) - seg_q(p_ep, p2s_ep);
         double c_dst = camera_leg(dst_slot, ys[0]);
-        for (size_t j = 0; j + 1 < ys.size(); ++j) c_dst += length(ys[j + 1].p - ys[j].p);
+        for (size_t j = 0; j + 1 < ys.size(); ++j) c_dst += seg_q(ep(FD, ys[j]), ep(FD, ys[j + 1]));
         if (!p2light) {
-            V3 prev = p2d_pos;
-            for (const Vertex& v : sfx_d) { c_dst += length(v.p - prev); prev = v.p; }
-            c_dst += length(light_pos(dst_slot, dst_pix) - prev);
+            EP prev = p2d_ep;
+            for (const Vertex& v : sfx_d) { c_dst += seg_q(prev, ep(FD, v)); prev = ep(FD, v); }
+            c_dst += seg_q(prev, light_ep(dst_slot, dst_pix));
         }
         double xi2[2] = {x.p.xi[0], x.p.xi[1]};
         double det_area;
         if (s.shift_mode == 1) {
             st.c[ST_NEWTON_ATT]++;
             double tol = s.newton_tol_rel * plane_width(plane);
-            NewtonOut no = newton(FS, FD, obj, x.p.xi, xkm1_s.p, p2s_pos, c_src, ykm1.p, p2d_pos, c_dst, dl0, tol,
+            NewtonOut no = newton(FS, FD, obj, x.p.xi, xkm1_ep, p2s_ep, c_src, ykm1_ep, p2d_ep, c_dst, dl0, tol,
                                   s.newton_max_iter);
             if (!no.conv) return R;
             st.c[ST_NEWTON_CONV]++;
@@ -1128,7 +1218,7 @@ struct Oracle {
                             st.c[ST_RAYS]++;
                             if (!light_visible(0, pix, xi)) C = 0.0;
                         }
-                        double l_i = len + dl;
+                        double l_i = len + seg_q(ep(F, xi), light_ep(0, pix));
                         if (C > 0.0 && i == 1) {
                             if (tree == 0) { direct_c[pix] = C; direct_l[pix] = l_i; }
                         } else if (C > 0.0) {
@@ -1184,7 +1274,7 @@ struct Oracle {
                     beta *= fcos;
                     pdf *= pw;
                     pdfs.push_back(pw);
-                    len += length(nx.p - xi.p);
+                    len += seg_q(ep(F, xi), ep(F, nx));
                     vs.push_back(nx);
                     wi = -wo;
                 }
@@ -1565,6 +1655,9 @@ struct Oracle {
 extern "C" {
 
 void* orc_create(const orc_scene* sc, const orc_sensor* sn, int num_threads) {
+    // the bin-axis and shrink shifts are defined here for path lengths only
+    if (sn->domain < 0 || sn->domain > 1) return nullptr;
+    if (sn->domain == 1 && (sn->bin_radius > 0 || sn->shrink_k > 1.0)) return nullptr;
     Oracle* o = new Oracle();
     o->s = *sn;
     o->nthreads = num_threads > 0 ? num_threads : 1;
@@ -1689,8 +1782,9 @@ int orc_newton(void* ctx, int obj, const double xi[2], const double as[3], const
                const double ad[3], const double bd[3], double cd, double dl0, double tol, int max_iter,
                double out[8]) {
     Oracle* o = (Oracle*)ctx;
-    Oracle::NewtonOut no = o->newton(o->fg[0], o->fg[0], obj, xi, V3(as[0], as[1], as[2]), V3(bs[0], bs[1], bs[2]),
-                                     cs, V3(ad[0], ad[1], ad[2]), V3(bd[0], bd[1], bd[2]), cd, dl0, tol, max_iter);
+    auto at_rest = [](const double* q) { return Oracle::EP{V3(q[0], q[1], q[2]), V3()}; };
+    Oracle::NewtonOut no = o->newton(o->fg[0], o->fg[0], obj, xi, at_rest(as), at_rest(bs), cs, at_rest(ad),
+                                     at_rest(bd), cd, dl0, tol, max_iter);
     out[0] = no.xi[0];
     out[1] = no.xi[1];
     out[2] = no.iters;
@@ -1700,6 +1794,20 @@ int orc_newton(void* ctx, int obj, const double xi[2], const double as[3], const
     out[6] = no.F[1];
     out[7] = no.status;
     return no.conv ? 1 : 0;
+}
+
+int orc_vel_eval(void* ctx, int obj, const double xi[2], const double a[3], const double va[3], const double b[3],
+                 const double vb[3], double c, double out[6]) {
+    Oracle* o = (Oracle*)ctx;
+    Oracle::EP ea{V3(a[0], a[1], a[2]), V3(va[0], va[1], va[2])}, eb{V3(b[0], b[1], b[2]), V3(vb[0], vb[1], vb[2])};
+    Oracle::LenEval e = o->constraint_eval(o->fg[0], obj, xi[0], xi[1], ea, eb, c, 1);
+    out[0] = e.L;
+    out[1] = e.g[0];
+    out[2] = e.g[1];
+    out[3] = e.H[0][0];
+    out[4] = e.H[0][1];
+    out[5] = e.H[1][1];
+    return e.ok ? 1 : 0;
 }
 
 int orc_wrs(const double* w, const double* u, int n, double* w_sum) {

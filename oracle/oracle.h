@@ -50,6 +50,7 @@ typedef struct {
     int32_t shift_mode, include_direct, debug_stage;
     int32_t bin_radius;           /* bin-axis reuse: bins b +- 1..bin_radius of the same pixel (0 = off) */
     double shrink_k;              /* shrink mapping: initial gate samples from a gate shrink_k times wider (1 = off) */
+    int32_t domain;               /* 0: planes over path length; 1: over path velocity u = -dl/dt (Doppler) */
     uint64_t seed;
 } orc_sensor;
 
@@ -60,6 +61,8 @@ typedef struct {
     float ortho_half[2];
     float light_pos[3];
     const float* xforms;          /* [num_objects*12], rigid 3x4 row-major */
+    const float* velocities;      /* [num_objects*6] or NULL: linear v, angular w (point x moves at v + w x (x - t)) */
+    float cam_vel[3], light_vel[3];
 } orc_frame;
 
 /* lifecycle */
@@ -112,6 +115,13 @@ int orc_chart(void* ctx, int obj, const double xi[2], double out[12]);
 int orc_newton(void* ctx, int obj, const double xi[2], const double a_src[3], const double b_src[3],
                double c_src, const double a_dst[3], const double b_dst[3], double c_dst,
                double dl0, double tol, int max_iter, double out[8]);
+
+/* The path-velocity function of the reconnection vertex on object obj's chart
+ * in the loaded frame (velocity domain): U(xi) = c + (va - v(p)).w_a +
+ * (v(p) - vb).w_b, w_a the unit vector a -> p, w_b p -> b.  out = {U, dU/du,
+ * dU/dv, d2U/du2, d2U/dudv, d2U/dv2}.  Returns 1 if the chart point exists. */
+int orc_vel_eval(void* ctx, int obj, const double xi[2], const double a[3], const double va[3], const double b[3],
+                 const double vb[3], double c, double out[6]);
 
 /* Weighted reservoir streaming of n candidate weights with uniforms u. */
 int orc_wrs(const double* w, const double* u, int n, double* w_sum);

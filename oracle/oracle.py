@@ -39,13 +39,14 @@ class OrcSensor(C.Structure):
                 ("newton_tol_rel", C.c_double), ("newton_max_iter", C.c_int32),
                 ("j_max", C.c_double), ("shift_mode", C.c_int32), ("include_direct", C.c_int32),
                 ("debug_stage", C.c_int32), ("bin_radius", C.c_int32),
-                ("shrink_k", C.c_double), ("seed", C.c_uint64)]
+                ("shrink_k", C.c_double), ("domain", C.c_int32), ("seed", C.c_uint64)]
 
 
 class OrcFrame(C.Structure):
     _fields_ = [("index", C.c_int32), ("cam_pos", C.c_float * 3), ("cam_fwd", C.c_float * 3),
                 ("cam_up", C.c_float * 3), ("fov_y_deg", C.c_float), ("ortho_half", C.c_float * 2),
-                ("light_pos", C.c_float * 3), ("xforms", _f32p)]
+                ("light_pos", C.c_float * 3), ("xforms", _f32p), ("velocities", _f32p),
+                ("cam_vel", C.c_float * 3), ("light_vel", C.c_float * 3)]
 
 
 _lib = None
@@ -74,6 +75,8 @@ def lib():
         _u32p = C.POINTER(C.c_uint32)
         _lib.orc_export_history.argtypes = [C.c_void_p, _f32p, _f32p, _f32p, _f32p, _u32p, _u32p, _u32p, _i32p,
                                             _f32p, _f32p, _u32p]
+        _lib.orc_vel_eval.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p, _f64p, _f64p, _f64p, C.c_double,
+                                      _f64p]
         _lib.orc_wrs.restype = C.c_int
         _lib.orc_wrs.argtypes = [_f64p, _f64p, C.c_int, _f64p]
     return _lib
@@ -116,7 +119,14 @@ def make_frame(fr):
     f.ortho_half[1] = float(fr.ortho_half[1])
     xf = np.ascontiguousarray(fr.xforms, dtype=np.float32)
     f.xforms = _p(xf, _f32p)
-    return f, xf
+    vel = None
+    if getattr(fr, "velocities", None) is not None:
+        vel = np.ascontiguousarray(fr.velocities, dtype=np.float32)
+        f.velocities = _p(vel, _f32p)
+    for i in range(3):
+        f.cam_vel[i] = float(getattr(fr, "cam_vel", (0.0, 0.0, 0.0))[i])
+        f.light_vel[i] = float(getattr(fr, "light_vel", (0.0, 0.0, 0.0))[i])
+    return f, (xf, vel)
 
 
 class Oracle:
@@ -156,6 +166,8 @@ class Oracle:
         nt = num_threads or os.cpu_count() or 1
         self.num_threads = nt
         self.h = lib().orc_create(C.byref(sc), C.byref(sn), int(nt))
+        if not self.h:
+            raise ValueError("sensor rejected by the oracle (an unsupported combination of settings)")
 
     def close(self):
         if self.h:
@@ -248,3 +260,12 @@ class Oracle:
                               float(tol), int(max_iter), _p(out, _f64p))
         return dict(ok=bool(ok), xi=out[0:2].copy(), iters=int(out[2]), det_dxi=out[3],
                     det_area=out[4], F=out[5:7].copy(), status=int(out[7]))
+
+    def vel_eval(self, obj, xi, a, va, b, vb, c=0.0):
+        """Path-velocity constraint function of the reconnection vertex on
+        object obj's chart in the loaded frame: (U, gradient[2], Hessian[2x2])."""
+        v = [np.ascontiguousarray(x, dtype=np.float64) for x in (xi, a, va, b, vb)]
+        out = np.zeros(6)
+        ok = lib().orc_vel_eval(self.h, int(obj), *[_p(x, _f64p) for x in v], float(c), _p(out, _f64p))
+        H = np.array([[out[3], out[4]], [out[4], out[5]]])
+        return bool(ok), out[0], out[1:3].copy(), H
