@@ -54,6 +54,10 @@ enum { TOF_MAT_LAMBERT = 0, TOF_MAT_GGX = 1 };
 enum { TOF_CAMERA_PINHOLE = 0, TOF_CAMERA_ORTHO = 1 };
 enum { TOF_LIGHT_POINT = 0, TOF_LIGHT_CONFOCAL = 1 };
 enum { TOF_SHIFT_NAIVE = 0, TOF_SHIFT_PATHLEN = 1 };
+/* What the planes measure: the optical path length l (Sec. 3.1), or the path
+ * velocity u = -dl/dt (Sec. 4.6, eq. optical_path_velocity; the Doppler
+ * frequency shift is f0 u / c) in scene units per second. */
+enum { TOF_DOMAIN_TIME = 0, TOF_DOMAIN_VELOCITY = 1 };
 enum { TOF_STAGE_CANONICAL = 0, TOF_STAGE_TEMPORAL = 1, TOF_STAGE_FINAL = 2 };
 
 /* Scene: rigid objects made of a regular vertex lattice ("grid": cell (i,j)
@@ -80,7 +84,9 @@ typedef struct {
 /* Sensor, time domain and reuse settings.  The time domain is a gate
  * [gate_center - gate_width/2, gate_center + gate_width/2) and/or n_bins
  * histogram bins [bin_t0 + b*bin_width, bin_t0 + (b+1)*bin_width); each has its
- * own reservoir plane per pixel (Sec. 4.5).  Rendering may be restricted to a
+ * own reservoir plane per pixel (Sec. 4.5).  In the velocity domain the same
+ * gate and bins lie on the path-velocity axis, and the reconnection shift keeps
+ * the path velocity instead of the length (Sec. 4.6).  Rendering may be restricted to a
  * crop [crop_x0, crop_x0+width) x [crop_y0, crop_y0+height) of a full_width x
  * full_height image (random streams are keyed by full-image pixel index). */
 typedef struct {
@@ -114,10 +120,17 @@ typedef struct {
                                         Delta l = (l - l0) / K + l0 - l, its weight scaled by the shift's
                                         Jacobian / K; all samples in the wide gate (the paper's R = 1,
                                         biased low where shrinks fail).  1 = off, at most 1000 */
+    int32_t domain;                  /* TOF_DOMAIN_*; the velocity domain requires bin_radius 0 and
+                                        shrink_k 1 (both shifts are defined on path lengths) */
 } tof_sensor_desc;
 
 /* Per-frame poses.  object_xforms: host [num_objects*12], rigid 3x4 row-major
- * [R | t] mapping object-local to world coordinates for this frame. */
+ * [R | t] mapping object-local to world coordinates for this frame.  The
+ * velocities are read in the velocity domain only (all finite, else
+ * TOF_ERR_INVALID_ARG): object_velocities is host [num_objects*6] or NULL (all
+ * at rest), linear v then angular w per object, so that a point x of the
+ * object moves at v + w x (x - t); cam_vel and light_vel move the camera and
+ * the point light (the confocal spot moves with the surface it lies on). */
 typedef struct {
     int32_t frame_index;             /* keys the random streams of this frame */
     float cam_pos[3], cam_fwd[3], cam_up[3];
@@ -125,6 +138,8 @@ typedef struct {
     float ortho_half[2];             /* orthographic half extents */
     float light_pos[3];              /* point light position */
     const float* object_xforms;
+    const float* object_velocities;
+    float cam_vel[3], light_vel[3];
 } tof_frame_desc;
 
 typedef struct {

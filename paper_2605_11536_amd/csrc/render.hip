@@ -78,8 +78,10 @@ __global__ void __launch_bounds__(kTB) k_gbuffer(FrameArgs a, GBufOut out) {
 // ---------------------------------------------------------------------------
 // path trees with NEE at every vertex; each complete sub-path is a candidate
 // of the reservoir of its time bin and of the gate (Sec. 4.5 per-bin deposit),
-// and is splatted into the plain path-tracing buffer.
+// and is splatted into the plain path-tracing buffer.  VEL: the planes
+// measure the path velocity (Sec. 4.6) instead of the path length.
 // ---------------------------------------------------------------------------
+template <bool VEL>
 TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                                                  float2* __restrict__ direct) {
     __shared__ uint32_t stk[kStackDepth * kTB];
@@ -103,7 +105,8 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                 Vtx vs[kMaxVerts];
                 float pdfs[kMaxVerts];
                 vs[0] = g;
-                float beta = 1.0f, pdf = 1.0f, plen = camera_leg(s, G, g);
+                float beta = 1.0f, pdf = 1.0f, plen = camera_leg<VEL>(s, G, g);
+                V3 vcur = VEL ? vel_at(G, g.obj, g.p) : mk(0.f, 0.f, 0.f);   // velocity of the last vertex
                 V3 wi = toward_camera(s, G, g);
                 int kfound = 0;
                 for (int i = 1; i <= s.n_max; ++i) {
@@ -121,7 +124,7 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                             Seg sg = seg_light(s, S, G, pix, xi);
                             if (!tr.visible(G, sg)) C = 0.f;
                         }
-                        float li = plen + dl;
+                        const float li = plen + (VEL ? dot(vcur - light_vel(s, G, pix), wl) : dl);
                         if (C > 0.f && i == 1) {
                             if (tree == 0) dterm = make_float2(C, li);
                         } else if (C > 0.f) {
@@ -189,7 +192,13 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                     beta *= fcos;
                     pdf *= pw;
                     pdfs[i - 1] = pw;
-                    plen += len(nx.p - xi.p);
+                    if (VEL) {
+                        const V3 vn = vel_at(G, nx.obj, nx.p);
+                        plen += seg_u(xi.p, vcur, nx.p, vn);
+                        vcur = vn;
+                    } else {
+                        plen += len(nx.p - xi.p);
+                    }
                     vs[i] = nx;
                     wi = -wo;
                 }
@@ -460,6 +469,7 @@ __device__ __forceinline__ float dom_M(const Sens& s, int mode, const ResSet& A,
     return mode == 0 ? fminf(Bp.M[dpix], s.m_cap) : A.M[dpix];
 }
 
+template <bool VEL>
 TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
                        const uint2* __restrict__ items, const uint2* __restrict__ tasks,
                        const uint32_t* __restrict__ win, float4* __restrict__ fwd, float4* __restrict__ shv,
@@ -489,7 +499,7 @@ TOF_TRACE_KERNEL k_fwd(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
         // a blocked visibility ray zeroes phat_q (component x of fwd[t])
         const float dl = mode == 0 ? gate_shift(s, a.F.g[0], a.F.g[1], pl)
                                    : (mode == 2 ? (float)(pl - spl) * s.bw : 0.f);
-        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, mode == 0 ? 1 : 0, src, 0, pix, pl, dl, q, 4u * t);
+        const ShiftOut sh = shift_path<VEL>(s, a.S, a.F, tr, y, mode == 0 ? 1 : 0, src, 0, pix, pl, dl, q, 4u * t);
         if (!sh.ok) {
             fwd[t] = make_float4(0.f, 1.0f, 0.f, Wx);
             continue;
@@ -541,6 +551,7 @@ __global__ void __launch_bounds__(kTB) k_mis_list(FrameArgs a, int mode, const i
 
 // MIS shifts of the listed pairs; blocks are dealt to the sub-lists round
 // robin (and so append their rays to the ray sub-queue of the same index)
+template <bool VEL>
 TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __restrict__ links,
                        const uint2* __restrict__ items, const uint2* __restrict__ tasks, IdxQueue lq,
                        const float4* __restrict__ fwd, const float4* __restrict__ shv, float* __restrict__ term,
@@ -581,7 +592,7 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
         }
         const float dl = mode == 0 ? -gate_shift(s, a.F.g[0], a.F.g[1], pl)
                                    : (mode == 2 ? (float)(dpl - pl) * s.bw : 0.f);
-        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, dpl, dl, q, g);
+        const ShiftOut sh = shift_path<VEL>(s, a.S, a.F, tr, y, 0, pix, mode == 0 ? 1 : 0, dpix, dpl, dl, q, g);
         if (sh.ok) term[g] = dom_M(s, mode, A, Bp, dpix) * sh.phat * sh.J;
     }
     flush_counters(st, a.counters);
@@ -714,7 +725,8 @@ TOF_TRACE_KERNEL k_shrink(FrameArgs a, ResSet can, uint32_t p0, uint32_t np, Ray
             continue;
         }
         const float l0 = s.gate_c, K = s.shrink_k, l = y.len;
-        const ShiftOut sh = shift_path(s, a.S, a.F, tr, y, 0, pix, 0, pix, gp, (l - l0) / K + l0 - l, q,
+        // (the shrink mapping is defined for path lengths only)
+        const ShiftOut sh = shift_path<false>(s, a.S, a.F, tr, y, 0, pix, 0, pix, gp, (l - l0) / K + l0 - l, q,
                                        (uint32_t)pix * kRecWords);
         if (!sh.ok) {
             rec_W(can, idx) = 0.f;
@@ -796,7 +808,11 @@ void launch_gbuffer(const FrameArgs& a, GBufOut out, hipStream_t st) {
     hipLaunchKernelGGL(k_gbuffer, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, out);
 }
 void launch_initial(const FrameArgs& a, ResSet can, float* pt, float2* direct, hipStream_t st) {
-    hipLaunchKernelGGL(k_initial, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, pt, direct);
+    if (a.s.domain)
+        hipLaunchKernelGGL(k_initial<true>, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, pt, direct);
+    else
+        hipLaunchKernelGGL(k_initial<false>, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, pt,
+                           direct);
 }
 void launch_reproject(const FrameArgs& a, const ResSet& can, const ResSet& prev, int* prev_pix, float* M_out,
                       hipStream_t st) {
@@ -820,14 +836,23 @@ void launch_tasks(const uint2* items, const uint32_t* task0, const uint32_t* cou
 void launch_fwd(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* win, float4* fwd, float4* shv,
                 const RayQueue& q, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_fwd, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, win, fwd, shv, q);
+    if (a.s.domain)
+        hipLaunchKernelGGL(k_fwd<true>, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, win, fwd, shv,
+                           q);
+    else
+        hipLaunchKernelGGL(k_fwd<false>, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, win, fwd,
+                           shv, q);
 }
 void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* win, const float4* fwd, const float4* shv,
                 float* term, const IdxQueue& lq, const RayQueue& q, unsigned grid, hipStream_t st) {
     hipLaunchKernelGGL(k_mis_list, dim3(grid), dim3(kTB), 0, st, a, mode, links, items, tasks, win, fwd, term, lq);
-    hipLaunchKernelGGL(k_mis, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, lq, fwd, shv,
-                       term, q);
+    if (a.s.domain)
+        hipLaunchKernelGGL(k_mis<true>, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, lq, fwd, shv,
+                           term, q);
+    else
+        hipLaunchKernelGGL(k_mis<false>, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, lq, fwd, shv,
+                           term, q);
 }
 void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, unsigned grid, hipStream_t st) {
     hipLaunchKernelGGL(k_vis, dim3(grid), dim3(kTB), 0, st, a, slot, q, kill);

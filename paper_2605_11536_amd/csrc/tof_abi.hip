@@ -28,12 +28,14 @@ struct Alloc {
 
 struct GeomBuf {
     float* xf = nullptr;
+    float* vel = nullptr;        // [6 * objects]: linear and angular velocity (velocity domain)
     float4* wv = nullptr;
     Node4* nodes = nullptr;      // [n_nodes]: the tree over the objects, then the objects' trees
     NodeQ* nodesq = nullptr;     // [n_nodes]: the same nodes quantized, as traversal reads them
     uint32_t* order = nullptr;   // refit order: object-tree nodes by height, then the top tree's
     float4* leaves = nullptr;
     std::vector<float> xf_host;
+    std::vector<float> vel_host;   // velocity domain: what vel holds
     bool built = false;
 };
 
@@ -44,6 +46,7 @@ struct SlotHost {
     V3 cam_pos, cam_fwd, cam_right, cam_up;
     float tan_half = 0, aspect = 1, ohx = 0, ohy = 0;
     V3 light_pos;
+    V3 cam_vel, light_vel;
     int* gb_obj = nullptr;
     float* gb_xi0 = nullptr;
     float* gb_xi1 = nullptr;
@@ -223,8 +226,10 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
 
 // one slot of the pinned upload ring: transforms, the tree over the objects
 // (at most one 4-wide node per mesh object) and its refit order
+// pinned staging of one frame: transforms, the tree over the objects and its
+// refit order, then the velocities
 size_t pinned_slot_bytes(size_t n_obj, size_t n_tlas_cap) {
-    return (sizeof(float) * 12 * n_obj + (sizeof(Node4) + sizeof(uint32_t)) * n_tlas_cap + 255) & ~(size_t)255;
+    return (sizeof(float) * 18 * n_obj + (sizeof(Node4) + sizeof(uint32_t)) * n_tlas_cap + 255) & ~(size_t)255;
 }
 
 // upper bound of the device memory tof_scene_upload allocates for a scene
@@ -237,7 +242,7 @@ size_t scene_footprint(const tof_scene_desc& d) {
         }
     const size_t V = (size_t)std::max(d.num_vertices, 1), O = (size_t)d.num_objects, N = mesh + T + 1;
     return O * (sizeof(Obj) + 4) + (size_t)d.num_materials * sizeof(Mat) + T * (sizeof(TriInfo) + 16 + 4) +
-           V * (16 + 4) + 2 * (48 * O + 16 * V + (sizeof(Node4) + sizeof(NodeQ) + 4) * N + 48 * std::max<size_t>(T, 1)) +
+           V * (16 + 4) + 2 * (72 * O + 16 * V + (sizeof(Node4) + sizeof(NodeQ) + 4) * N + 48 * std::max<size_t>(T, 1)) +
            64 * 1024;
 }
 
@@ -295,6 +300,9 @@ SlotDev slot_dev(const tof_ctx* c, int i) {
     d.ohx = h.ohx;
     d.ohy = h.ohy;
     d.light_pos = h.light_pos;
+    d.vel = g.vel;
+    d.cam_vel = h.cam_vel;
+    d.light_vel = h.light_vel;
     d.gate_c = h.gate_c;
     d.gb_obj = h.gb_obj;
     d.gb_xi0 = h.gb_xi0;
@@ -575,6 +583,9 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
     if (T) HIP_TRY(hipMemcpy(c->d_leaf_tri, leaf_tri.data(), sizeof(int) * T, hipMemcpyHostToDevice));
     for (auto& g : c->geom) {
         TOF_TRY(alloc_t(c, a, &g.xf, 12 * (size_t)objs.size()));
+        TOF_TRY(alloc_t(c, a, &g.vel, 6 * (size_t)objs.size()));
+        HIP_TRY(hipMemset(g.vel, 0, sizeof(float) * 6 * objs.size()));
+        g.vel_host.assign(6 * objs.size(), 0.f);
         TOF_TRY(alloc_t(c, a, &g.wv, std::max(d->num_vertices, 1)));
         TOF_TRY(alloc_t(c, a, &g.nodes, (size_t)c->n_nodes));
         TOF_TRY(alloc_t(c, a, &g.nodesq, (size_t)c->n_nodes));
@@ -630,7 +641,8 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
               (d->shift_mode == TOF_SHIFT_NAIVE || d->shift_mode == TOF_SHIFT_PATHLEN) &&
               d->debug_stage >= TOF_STAGE_CANONICAL && d->debug_stage <= TOF_STAGE_FINAL &&
               d->bin_radius >= 0 && d->bin_radius <= 4 && std::isfinite(d->shrink_k) && d->shrink_k >= 1.f &&
-              d->shrink_k <= 1000.f &&
+              d->shrink_k <= 1000.f && (d->domain == TOF_DOMAIN_TIME || d->domain == TOF_DOMAIN_VELOCITY) &&
+              (d->domain == TOF_DOMAIN_TIME || (d->bin_radius == 0 && d->shrink_k == 1.f)) &&
               std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
     // work-list entries (tasks of a pass over fully occupied planes) are 32-bit indices
     ok = ok && (unsigned long long)d->width * d->height * B *
@@ -722,6 +734,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     s.debug_stage = d->debug_stage;
     s.br = d->bin_radius;
     s.shrink_k = d->shrink_k;
+    s.domain = d->domain;
     s.P = (int)P;
     s.B = B;
     s.mask_words = (int)words;
@@ -915,6 +928,13 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         if (!std::isfinite(fr->object_xforms[k])) return TOF_ERR_INVALID_ARG;
     if (!finite3(fr->cam_pos) || !finite3(fr->cam_fwd) || !finite3(fr->cam_up) || !finite3(fr->light_pos))
         return TOF_ERR_INVALID_ARG;
+    const bool vel = c->s.domain == TOF_DOMAIN_VELOCITY;
+    if (vel) {
+        if (!finite3(fr->cam_vel) || !finite3(fr->light_vel)) return TOF_ERR_INVALID_ARG;
+        if (fr->object_velocities)
+            for (int k = 0; k < 6 * c->n_obj; ++k)
+                if (!std::isfinite(fr->object_velocities[k])) return TOF_ERR_INVALID_ARG;
+    }
     V3 fwd = hv(fr->cam_fwd[0], fr->cam_fwd[1], fr->cam_fwd[2]);
     V3 up = hv(fr->cam_up[0], fr->cam_up[1], fr->cam_up[2]);
     V3 rc = hcross(fwd, up);
@@ -930,8 +950,15 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     if (c->slot[0].valid) std::swap(c->slot[0], c->slot[1]);
     SlotHost& cur = c->slot[0];
     const SlotHost& prev = c->slot[1];
+    // this frame's velocities (velocity domain; none = at rest)
+    std::vector<float> vel_now;
+    if (vel) {
+        vel_now.assign(6 * O, 0.f);
+        if (fr->object_velocities) std::memcpy(vel_now.data(), fr->object_velocities, sizeof(float) * 6 * O);
+    }
     bool same = prev.valid && c->geom[prev.geom].built &&
-                std::memcmp(c->geom[prev.geom].xf_host.data(), fr->object_xforms, sizeof(float) * 12 * O) == 0;
+                std::memcmp(c->geom[prev.geom].xf_host.data(), fr->object_xforms, sizeof(float) * 12 * O) == 0 &&
+                (!vel || c->geom[prev.geom].vel_host == vel_now);
     if (same) {
         cur.geom = prev.geom;
     } else {
@@ -998,6 +1025,12 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
             HIP_TRY(hipMemcpyAsync(g.nodes, pn, sizeof(Node4) * nt, hipMemcpyHostToDevice, st));
             HIP_TRY(hipMemcpyAsync(g.order + c->n_blas, po, sizeof(uint32_t) * nt, hipMemcpyHostToDevice, st));
         }
+        if (vel) {
+            char* pv = pin + sizeof(float) * 12 * O + (sizeof(Node4) + sizeof(uint32_t)) * c->n_tlas_cap;
+            std::memcpy(pv, vel_now.data(), sizeof(float) * 6 * O);
+            HIP_TRY(hipMemcpyAsync(g.vel, pv, sizeof(float) * 6 * O, hipMemcpyHostToDevice, st));
+            g.vel_host = vel_now;
+        }
         HIP_TRY(hipEventRecord(c->xf_ev[ring], st));
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, c->n_vert, st);
@@ -1017,6 +1050,8 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     cur.ohy = fr->ortho_half[1];
     cur.gate_c = c->s.gate_c;
     cur.light_pos = hv(fr->light_pos[0], fr->light_pos[1], fr->light_pos[2]);
+    cur.cam_vel = vel ? hv(fr->cam_vel[0], fr->cam_vel[1], fr->cam_vel[2]) : hv(0.f, 0.f, 0.f);
+    cur.light_vel = vel ? hv(fr->light_vel[0], fr->light_vel[1], fr->light_vel[2]) : hv(0.f, 0.f, 0.f);
 
     tofh::FrameArgs a;
     a.s = c->s;

@@ -107,6 +107,10 @@ struct SlotDev {
     V3 cam_pos, cam_fwd, cam_right, cam_up;
     float tan_half, aspect, ohx, ohy;
     V3 light_pos;
+    // instantaneous velocities (velocity domain only): per object linear v and
+    // angular w, 6 floats each; camera and point light
+    const float* vel;
+    V3 cam_vel, light_vel;
     float gate_c;           // the time gate's centre when the frame was rendered
     // G-buffer (obj = -1: no primary hit)
     const int* gb_obj;
@@ -130,6 +134,7 @@ struct Sens {
     int shift_mode, include_direct, debug_stage;
     int br;                  // bin-axis reuse radius (0 = off)
     float shrink_k;          // shrink mapping of initial gate samples (1 = off)
+    int domain;              // planes over 0: path length, 1: path velocity
     int P, B, mask_words;
     uint64_t seed;
 };
@@ -929,8 +934,32 @@ __device__ __forceinline__ V3 toward_camera(const Sens& s, const SlotDev& G, con
     if (s.cam_model == 0) return nrm(G.cam_pos - y1.p);
     return -G.cam_fwd;
 }
+// ---------------------------------------------------------------------------
+// Path velocity (Sec. 4.6, eq. optical_path_velocity, refractive index 1):
+// u = -dl/dt = sum over segments of (v_from - v_to) . w, w the segment's unit
+// vector.  A point p of object o moves rigidly at v_o + w_o x (p - t_o), t_o
+// the translation of the object's transform.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ V3 vel_at(const SlotDev& G, int obj, V3 p) {
+    if (obj < 0) return mk(0.f, 0.f, 0.f);
+    const float* q = G.vel + 6 * obj;
+    const float* m = G.xf + 12 * obj;
+    return mk(q[0], q[1], q[2]) + cross(mk(q[3], q[4], q[5]), p - mk(m[3], m[7], m[11]));
+}
+// the term of the segment from (pa, va) to (pb, vb)
+__device__ __forceinline__ float seg_u(V3 pa, V3 va, V3 pb, V3 vb) {
+    const V3 d = pb - pa;
+    return dot(va - vb, (1.0f / len(d)) * d);
+}
+// the plane quantity of the camera leg: its length (to the image plane for
+// the orthographic camera), or its term of u
+template <bool VEL>
 __device__ __forceinline__ float camera_leg(const Sens& s, const SlotDev& G, const Vtx& y1) {
     if (!s.count_leg) return 0.f;
+    if (VEL) {
+        const V3 dir = s.cam_model == 0 ? nrm(y1.p - G.cam_pos) : G.cam_fwd;
+        return dot(G.cam_vel - vel_at(G, y1.obj, y1.p), dir);
+    }
     if (s.cam_model == 0) return len(y1.p - G.cam_pos);
     return dot(y1.p - G.cam_pos, G.cam_fwd);
 }
@@ -940,6 +969,11 @@ __device__ __forceinline__ V3 light_pos(const Sens& s, const SlotDev& G, int pix
     if (s.light_model == 0) return G.light_pos;
     float4 p = G.gb_p[pix];
     return mk(p.x, p.y, p.z);
+}
+__device__ __forceinline__ V3 light_vel(const Sens& s, const SlotDev& G, int pix) {
+    if (s.light_model == 0) return G.light_vel;
+    float4 p = G.gb_p[pix];
+    return vel_at(G, G.gb_obj[pix], mk(p.x, p.y, p.z));
 }
 __device__ __forceinline__ float light_emit(const Sens& s, const SceneDev& S, const SlotDev& G, int pix, V3 x) {
     if (s.light_model == 0) return s.light_I;
@@ -1092,6 +1126,81 @@ __device__ __forceinline__ LenEvalT<T> len_eval_t(const SceneDev& S, const SlotD
     return e;
 }
 
+template <typename T>
+__device__ __forceinline__ T seg_u_t(T3<T> pa, T3<T> va, T3<T> pb, T3<T> vb) {
+    const T3<T> d = pb - pa;
+    return tdot(va - vb, ((T)1 / tlen(d)) * d);
+}
+
+// The path-velocity counterpart of len_eval_t (Sec. 4.6): U(xi) = c +
+// phi_a(p) + phi_b(p) with phi_a(p) = (v_a - v(p)) . d, d = (p - a) / |p - a|
+// (a segment's term does not depend on its direction) and v(p) = V + W x
+// (p - t) the object's rigid motion.  With l = |p - a|, w = v_a - v(p) and
+// P = I - d d^T:
+//   grad phi_a = W x d + P w / l
+//   Hess phi_a x = (d (d.(W x x)) - (d.x)(W x d)) / l
+//                  - ((d.w) P x + d (P w . x) + P w (d.x)) / l^2
+// (derived from the definition; the supplement that holds the paper's own
+// derivation is not available), and in the chart g = J^T grad,
+// H = J^T Hess J + grad . p_ij.
+template <typename T>
+__device__ __forceinline__ LenEvalT<T> vel_eval_t(const SceneDev& S, const SlotDev& G, int obj, T u, T v, T3<T> a,
+                                                  T3<T> va, T3<T> b, T3<T> vb, T c) {
+    LenEvalT<T> e;
+    e.ok = false;
+    ChartT<T> ch = chart_eval_t<T>(S, G, obj, u, v);
+    if (!ch.ok) return e;
+    const float* q = G.vel + 6 * obj;
+    const float* m = G.xf + 12 * obj;
+    const T3<T> W = T3<T>{(T)q[3], (T)q[4], (T)q[5]};
+    const T3<T> vp = T3<T>{(T)q[0], (T)q[1], (T)q[2]} + tcross(W, ch.p - T3<T>{(T)m[3], (T)m[7], (T)m[11]});
+    const T3<T> z = T3<T>{0, 0, 0};
+    T val = c;
+    T3<T> grad = z, Hju = z, Hjv = z;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const T3<T> ep = side ? b : a, ev = side ? vb : va;
+        const T3<T> r = ch.p - ep;
+        const T l = tlen(r);
+        if (!(l > (T)0)) return e;
+        const T il = (T)1 / l;
+        const T3<T> d = il * r;
+        const T3<T> w = ev - vp;
+        const T dw = tdot(d, w);
+        const T3<T> Pw = w - dw * d;
+        const T3<T> Wd = tcross(W, d);
+        val = val + dw;
+        grad = grad + Wd + il * Pw;
+        const T3<T> xs[2] = {ch.ju, ch.jv};
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const T3<T> x = xs[k];
+            const T dx = tdot(d, x);
+            const T3<T> t1 = il * (tdot(d, tcross(W, x)) * d - dx * Wd);
+            const T3<T> t2 = dw * (x - dx * d) + tdot(Pw, x) * d + dx * Pw;
+            const T3<T> hx = t1 - (il * il) * t2;
+            if (k == 0) Hju = Hju + hx;
+            else Hjv = Hjv + hx;
+        }
+    }
+    e.L = val;
+    e.g0 = tdot(grad, ch.ju);
+    e.g1 = tdot(grad, ch.jv);
+    e.h00 = tdot(ch.ju, Hju) + tdot(grad, ch.puu);
+    e.h01 = tdot(ch.ju, Hjv) + tdot(grad, ch.puv);
+    e.h11 = tdot(ch.jv, Hjv) + tdot(grad, ch.pvv);
+    e.ok = true;
+    return e;
+}
+
+// the constraint function of the plane quantity (length or velocity)
+template <typename T, bool VEL>
+__device__ __forceinline__ LenEvalT<T> con_eval_t(const SceneDev& S, const SlotDev& G, int obj, T u, T v, T3<T> a,
+                                                  T3<T> va, T3<T> b, T3<T> vb, T c) {
+    if (VEL) return vel_eval_t<T>(S, G, obj, u, v, a, va, b, vb, c);
+    return len_eval_t<T>(S, G, obj, u, v, a, b, c);
+}
+
 struct NewtonOut {
     bool conv;
     float xi0, xi1;
@@ -1099,17 +1208,18 @@ struct NewtonOut {
     double det_area;
 };
 
-template <typename T>
+// Endpoints a, b carry velocities va, vb (read in the velocity domain only).
+template <typename T, bool VEL>
 __device__ inline NewtonOut newton_solve(const SceneDev& S, const SlotDev& GS, const SlotDev& GD, int obj, T xs0,
-                                         T xs1, T3<T> as, T3<T> bs, T cs, T3<T> ad, T3<T> bd, T cd, T dl0, T tol,
-                                         int maxit) {
+                                         T xs1, T3<T> as, T3<T> vas, T3<T> bs, T3<T> vbs, T cs, T3<T> ad, T3<T> vad,
+                                         T3<T> bd, T3<T> vbd, T cd, T dl0, T tol, int maxit) {
     NewtonOut out;
     out.conv = false;
     out.iters = 0;
-    const LenEvalT<T> Sv = len_eval_t<T>(S, GS, obj, xs0, xs1, as, bs, cs);
+    const LenEvalT<T> Sv = con_eval_t<T, VEL>(S, GS, obj, xs0, xs1, as, vas, bs, vbs, cs);
     if (!Sv.ok) return out;
     T xp0 = xs0, xp1 = xs1;
-    LenEvalT<T> D = len_eval_t<T>(S, GD, obj, xp0, xp1, ad, bd, cd);
+    LenEvalT<T> D = con_eval_t<T, VEL>(S, GD, obj, xp0, xp1, ad, vad, bd, vbd, cd);
     if (!D.ok) return out;
     // F = [L_dst(xi') - L_src(xi) - dl ; (R m)^T (xi' - xi)], R = 90 degree rotation
     T F0 = D.L - Sv.L - dl0;
@@ -1133,7 +1243,7 @@ __device__ inline NewtonOut newton_solve(const SceneDev& S, const SlotDev& GS, c
         T alpha = (T)1;
         for (int ls = 0; ls < 4; ++ls, alpha *= (T)0.5) {   // backtracking line search
             const T x0 = xp0 + alpha * (T)s0, x1 = xp1 + alpha * (T)s1;
-            const LenEvalT<T> Dt = len_eval_t<T>(S, GD, obj, x0, x1, ad, bd, cd);
+            const LenEvalT<T> Dt = con_eval_t<T, VEL>(S, GD, obj, x0, x1, ad, vad, bd, vbd, cd);
             if (!Dt.ok) continue;
             const T n0 = (T)0.5 * (Sv.g0 + Dt.g0), n1 = (T)0.5 * (Sv.g1 + Dt.g1);
             const T G0 = Dt.L - Sv.L - dl0;
@@ -1210,7 +1320,9 @@ __device__ __forceinline__ bool rec_valid(const SceneDev& S, const Rec& x) {
 }
 
 // The returned ok is provisional: the shift's visibility segments are queued
-// under `owner` and a blocked one zeroes the owner's weight later.
+// under `owner` and a blocked one zeroes the owner's weight later.  VEL: the
+// planes measure the path velocity and the perturbation keeps it (Sec. 4.6).
+template <bool VEL>
 __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S, const Frames& F, Tracer& tr, const Rec& x,
                                       int src_slot, int src_pix, int dst_slot, int dst_pix, int plane, float dl0,
                                       const RayQueue& q, uint32_t owner) {
@@ -1229,8 +1341,9 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
     Vtx cur = gbuf_vertex(GD, dst_pix);
     V3 wi_s = toward_camera(s, GD, cur);   // incoming direction for sampling
     V3 wi_e = wi_s;                        // incoming direction for evaluation (from positions)
-    float plen = camera_leg(s, GD, cur);
+    float plen = camera_leg<VEL>(s, GD, cur);
     NReal cpre = (NReal)plen;   // prefix length in the Newton precision
+    V3 vc = VEL ? vel_at(GD, cur.obj, cur.p) : mk(0.f, 0.f, 0.f);   // velocity of cur
     float beta = 1.0f, pdf_y = 1.0f;
     const int nrep = (x.k == 0) ? x.n - 1 : x.k - 2;
     for (int i = 1; i <= nrep; ++i) {
@@ -1246,8 +1359,16 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
         float dl = len(dv);
         V3 we = (1.0f / dl) * dv;
         beta *= bsdf_eval(S, cur.obj, cur.n, wi_e, we) * fabsf(dot(cur.n, we));
-        plen += dl;
-        cpre += tlen(tof3<NReal>(nx.p) - tof3<NReal>(cur.p));
+        if (VEL) {
+            const V3 vn = vel_at(GD, nx.obj, nx.p);
+            const float du = dot(vc - vn, we);
+            plen += du;
+            cpre += (NReal)du;
+            vc = vn;
+        } else {
+            plen += dl;
+            cpre += tlen(tof3<NReal>(nx.p) - tof3<NReal>(cur.p));
+        }
         pdf_y *= pdf;
         wi_s = -wo;
         wi_e = -we;
@@ -1266,7 +1387,7 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
         V3 wo = (1.0f / dl) * dv;
         C = beta * (bsdf_eval(S, cur.obj, cur.n, wi_e, wo) * fabsf(dot(cur.n, wo)) *
                     light_emit(s, S, GD, dst_pix, cur.p) / (dl * dl));
-        plen += dl;
+        plen += VEL ? dot(vc - light_vel(s, GD, dst_pix), wo) : dl;
         R.v0 = x.v[0];
         R.v1 = x.v[1];
     } else {
@@ -1285,6 +1406,10 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
             p2d_pos = p2_d.p;
         }
         if (x.nsfx > 0) sfx_d = vertex_at(S, GD, x.v[3].obj, x.v[3].xi0, x.v[3].xi1);
+        // destination velocities of the fixed vertices after p (velocity domain)
+        const V3 vp2d = !VEL ? mk(0.f, 0.f, 0.f) : (p2light ? light_vel(s, GD, dst_pix) : vel_at(GD, p2_d.obj, p2_d.p));
+        const V3 vsfx = (VEL && x.nsfx > 0) ? vel_at(GD, sfx_d.obj, sfx_d.p) : mk(0.f, 0.f, 0.f);
+        const V3 vlight = VEL ? light_vel(s, GD, dst_pix) : mk(0.f, 0.f, 0.f);
         float xi0 = x.v[1].xi0, xi1 = x.v[1].xi1;
         double det_area;
         if (s.shift_mode == 1) {
@@ -1293,12 +1418,14 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
             // suffix after p2 (so that L_src(xi) reproduces the stored length)
             NReal c_dst = cpre;
             if (!p2light) {
-                V3 prev = p2d_pos;
+                V3 prev = p2d_pos, vprev = vp2d;
                 if (x.nsfx > 0) {
-                    c_dst += (NReal)len(sfx_d.p - prev);
+                    c_dst += VEL ? (NReal)seg_u(prev, vprev, sfx_d.p, vsfx) : (NReal)len(sfx_d.p - prev);
                     prev = sfx_d.p;
+                    vprev = vsfx;
                 }
-                c_dst += (NReal)len(light_pos(s, GD, dst_pix) - prev);
+                const V3 L = light_pos(s, GD, dst_pix);
+                c_dst += VEL ? (NReal)seg_u(prev, vprev, L, vlight) : (NReal)len(L - prev);
             }
             const T3<NReal> xk = chart_eval_t<NReal>(S, GS, x.v[0].obj, x.v[0].xi0, x.v[0].xi1).p;
             const T3<NReal> pp = chart_eval_t<NReal>(S, GS, obj, xi0, xi1).p;
@@ -1306,11 +1433,23 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
                                           : chart_eval_t<NReal>(S, GS, x.v[2].obj, x.v[2].xi0, x.v[2].xi1).p;
             const T3<NReal> p2d = p2light ? tof3<NReal>(p2d_pos)
                                           : chart_eval_t<NReal>(S, GD, x.v[2].obj, x.v[2].xi0, x.v[2].xi1).p;
-            const NReal c_src = (NReal)x.len - tlen(xk - pp) - tlen(p2s - pp);
             const T3<NReal> yk = chart_eval_t<NReal>(S, GD, cur.obj, cur.xi0, cur.xi1).p;
+            // endpoint velocities (velocity domain): x_{k-1} and p2 in the
+            // source, y_{k-1} and p2 in the destination
+            T3<NReal> vxk{0, 0, 0}, vp2s{0, 0, 0}, vyk{0, 0, 0}, vp2dn{0, 0, 0}, vpp{0, 0, 0};
+            if (VEL) {
+                auto fv = [](T3<NReal> a) { return mk((float)a.x, (float)a.y, (float)a.z); };
+                vxk = tof3<NReal>(vel_at(GS, x.v[0].obj, fv(xk)));
+                vpp = tof3<NReal>(vel_at(GS, obj, fv(pp)));
+                vp2s = tof3<NReal>(p2light ? light_vel(s, GS, src_pix) : vel_at(GS, x.v[2].obj, fv(p2s)));
+                vp2dn = tof3<NReal>(p2light ? vlight : vel_at(GD, x.v[2].obj, fv(p2d)));
+                vyk = tof3<NReal>(vel_at(GD, cur.obj, fv(yk)));
+            }
+            const NReal c_src = VEL ? (NReal)x.len - seg_u_t<NReal>(xk, vxk, pp, vpp) - seg_u_t<NReal>(pp, vpp, p2s, vp2s)
+                                    : (NReal)x.len - tlen(xk - pp) - tlen(p2s - pp);
             const NReal tol = (NReal)s.tol_rel * (NReal)plane_width(s, plane);
-            NewtonOut no = newton_solve<NReal>(S, GS, GD, obj, (NReal)xi0, (NReal)xi1, xk, p2s, c_src, yk, p2d, c_dst,
-                                              (NReal)dl0, tol, s.max_it);
+            NewtonOut no = newton_solve<NReal, VEL>(S, GS, GD, obj, (NReal)xi0, (NReal)xi1, xk, vxk, p2s, vp2s, c_src,
+                                                    yk, vyk, p2d, vp2dn, c_dst, (NReal)dl0, tol, s.max_it);
             if (!no.conv) return R;
             st.c[ST_NEWTON_CONV]++;
             st.c[ST_NEWTON_ITERS] += (uint32_t)no.iters;
@@ -1335,7 +1474,8 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
         // contribution of the offset path beyond y_{k-1}
         V3 w1 = (1.0f / l1) * e1;
         C = beta * (bsdf_eval(S, cur.obj, cur.n, wi_e, w1) * fabsf(dot(cur.n, w1)));
-        plen += l1;
+        const V3 vpd = VEL ? vel_at(GD, obj, pd.p) : mk(0.f, 0.f, 0.f);
+        plen += VEL ? dot(vc - vpd, w1) : l1;
         V3 wi2 = -w1;
         if (p2light) {
             V3 e2 = light_pos(s, GD, dst_pix) - pd.p;
@@ -1343,22 +1483,24 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
             V3 w2 = (1.0f / l2) * e2;
             C *= bsdf_eval(S, obj, pd.n, wi2, w2) * fabsf(dot(pd.n, w2)) * light_emit(s, S, GD, dst_pix, pd.p) /
                  (l2 * l2);
-            plen += l2;
+            plen += VEL ? dot(vpd - vlight, w2) : l2;
         } else {
             V3 e2 = p2_d.p - pd.p;
             float l2 = len(e2);
             V3 w2 = (1.0f / l2) * e2;
             C *= bsdf_eval(S, obj, pd.n, wi2, w2) * fabsf(dot(pd.n, w2));
-            plen += l2;
+            plen += VEL ? dot(vpd - vp2d, w2) : l2;
             Vtx last = p2_d;
+            V3 vlast = vp2d;
             V3 wil = -w2;
             if (x.nsfx > 0) {
                 V3 e3 = sfx_d.p - p2_d.p;
                 float l3 = len(e3);
                 V3 w3 = (1.0f / l3) * e3;
                 C *= bsdf_eval(S, p2_d.obj, p2_d.n, wil, w3) * fabsf(dot(p2_d.n, w3));
-                plen += l3;
+                plen += VEL ? dot(vp2d - vsfx, w3) : l3;
                 last = sfx_d;
+                vlast = vsfx;
                 wil = -w3;
             }
             V3 e4 = light_pos(s, GD, dst_pix) - last.p;
@@ -1366,7 +1508,7 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
             V3 w4 = (1.0f / l4) * e4;
             C *= bsdf_eval(S, last.obj, last.n, wil, w4) * fabsf(dot(last.n, w4)) *
                  light_emit(s, S, GD, dst_pix, last.p) / (l4 * l4);
-            plen += l4;
+            plen += VEL ? dot(vlast - vlight, w4) : l4;
         }
         // Jacobian: replayed directions, reconnection edge, chart area, next edge
         V3 ex = xkm1_s.p - p_s.p;

@@ -47,13 +47,14 @@ class tof_sensor_desc(C.Structure):
                 ("spatial_k", C.c_int32), ("spatial_radius", C.c_int32), ("m_cap", C.c_float),
                 ("newton_tol_rel", C.c_float), ("newton_max_iter", C.c_int32), ("j_max", C.c_float),
                 ("shift_mode", C.c_int32), ("include_direct", C.c_int32), ("debug_stage", C.c_int32), ("bin_radius", C.c_int32),
-                ("shrink_k", C.c_float)]
+                ("shrink_k", C.c_float), ("domain", C.c_int32)]
 
 
 class tof_frame_desc(C.Structure):
     _fields_ = [("frame_index", C.c_int32), ("cam_pos", C.c_float * 3), ("cam_fwd", C.c_float * 3),
                 ("cam_up", C.c_float * 3), ("fov_y_deg", C.c_float), ("ortho_half", C.c_float * 2),
-                ("light_pos", C.c_float * 3), ("object_xforms", _f32p)]
+                ("light_pos", C.c_float * 3), ("object_xforms", _f32p), ("object_velocities", _f32p),
+                ("cam_vel", C.c_float * 3), ("light_vel", C.c_float * 3)]
 
 
 class tof_history_desc(C.Structure):
@@ -214,7 +215,14 @@ def frame_desc(frame):
     d.ortho_half[1] = float(frame.ortho_half[1])
     xf = np.ascontiguousarray(frame.xforms, dtype=np.float32)
     d.object_xforms = _ptr(xf, _f32p)
-    return d, xf
+    vel = None
+    if getattr(frame, "velocities", None) is not None:
+        vel = np.ascontiguousarray(frame.velocities, dtype=np.float32)
+        d.object_velocities = _ptr(vel, _f32p)
+    for i in range(3):
+        d.cam_vel[i] = float(getattr(frame, "cam_vel", (0.0, 0.0, 0.0))[i])
+        d.light_vel[i] = float(getattr(frame, "light_vel", (0.0, 0.0, 0.0))[i])
+    return d, (xf, vel)
 
 
 def _dptr(t) -> Optional[int]:

@@ -258,6 +258,59 @@ def test_plane_direct_parity_and_closed_form():
     gpu.close()
 
 
+def test_doppler_parity():
+    """Velocity domain (Sec. 4.6): planes over the path velocity and the shift
+    under the path-velocity constraint, on the Doppler boxes (a receding and
+    an approaching box, a spinning sphere); canonical samples, then spatial
+    reuse only as in the paper's Doppler demo, then temporal + spatial."""
+    for stage in (scenes.STAGE_CANONICAL, scenes.STAGE_FINAL):
+        gs, os_ = _run_pair(scenes.doppler_boxes(frames=2, debug_stage=stage))
+    assert gs["newton_converged"] > 0
+    for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+        assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
+    gs, os_ = _run_pair(scenes.doppler_boxes(width=40, height=24, frames=3, temporal=1))   # ragged
+    for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+        assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
+
+
+def test_doppler_receding_plane_closed_form():
+    """A Lambertian plane at depth d receding at speed s under a co-located
+    camera and light: every velocity bin of width du whose ring lies in the
+    view holds rho I du / (s d^2) (a flat Doppler spectrum)."""
+    d, rho, I, s, du = 1.0, 0.5, 1.0, 1.0, 0.025
+    w = scenes.lambert_plane(depth=d, albedo=rho, intensity=I, width=256, height=256, fov=60.0,
+                             n_bins=10, bin_t0=-2.0, bin_width=du, gate_enabled=0,
+                             domain=scenes.DOMAIN_VELOCITY)
+    from paper_2605_11536_amd.tof import Renderer
+    gpu = Renderer(w.scene, w.sensor)
+    a_p = (2 * math.tan(math.radians(30.0)) / 256) ** 2
+    fr = w.frames[0]
+    fr.velocities = np.array([[0.0, 0.0, -s, 0.0, 0.0, 0.0]], dtype=np.float32)
+    sums = []
+    for f in range(8):
+        fr.index = f
+        gpu.render(fr)
+        sums.append(gpu.fetch()["pt_hist"].astype(np.float64).sum(axis=(1, 2)) * a_p * du)
+    mean = np.mean(sums, 0)
+    assert np.all(np.abs(mean / (rho * I * du / (s * d * d)) - 1) < 5e-3), mean
+    gpu.close()
+
+
+def test_doppler_settings_rejected():
+    from paper_2605_11536_amd import tof
+    w = scenes.doppler_boxes(width=16, height=16, frames=1)
+    gpu = tof.Renderer(w.scene, w.sensor)
+    for bad in (dict(bin_radius=1), dict(shrink_k=2.0), dict(domain=2)):
+        with pytest.raises(tof.TofError):
+            tof.tof_sensor_set(gpu.h, scenes.dataclasses.replace(w.sensor, **bad))
+    fr = w.frames[0]
+    fr.velocities = fr.velocities.copy()
+    fr.velocities[3, 1] = np.nan
+    with pytest.raises(tof.TofError):
+        gpu.render(fr)
+    gpu.close()
+
+
 def test_error_paths_forced_from_host():
     from paper_2605_11536_amd import tof
     w = scenes.cornell_box(width=16, height=16)
