@@ -599,11 +599,16 @@ TOF_TRACE_KERNEL k_mis(FrameArgs a, int mode, ResSet A, ResSet Bp, const int* __
 }
 
 // ---------------------------------------------------------------------------
-// visibility of queued shift segments in the frame of `slot`, one ray per
-// lane; a blocked ray zeroes kill[owner] (the first one counts the shift as
-// failed).
+// visibility of queued shift segments in the frame of `slot`; a blocked ray
+// zeroes kill[owner] (the first one counts the shift as failed).  Two forms:
+// persistent lanes that refill from the wave's share of the queue (k_vis),
+// for trees deep enough that rays of one wave take very different numbers of
+// steps, and one ray per lane (k_vis_lanes) for small scenes, where a ray is
+// a few node visits and the refill bookkeeping costs more than the idle
+// lanes it saves.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kTB) k_vis(FrameArgs a, int slot, RayQueue q, float* __restrict__ kill) {
+constexpr uint32_t kVisChunk = 128;   // rays per chunk of the persistent visibility waves
+__global__ void __launch_bounds__(kTB) k_vis_lanes(FrameArgs a, int slot, RayQueue q, float* __restrict__ kill) {
     __shared__ uint32_t stk[kVisStackDepth * kTB];
     Counters st = {};
     Tracer tr{a.S, stk + threadIdx.x, kTB, kVisStackDepth, st};
@@ -620,6 +625,26 @@ __global__ void __launch_bounds__(kTB) k_vis(FrameArgs a, int slot, RayQueue q, 
             const float old = atomicExch(kill + __float_as_uint(r1.w), 0.f);
             if (old != 0.f) st.c[ST_VISFAIL]++;
         }
+    }
+    flush_counters(st, a.counters);
+}
+
+__global__ void __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(6))) k_vis(FrameArgs a, int slot, RayQueue q,
+                                                                                  float* __restrict__ kill) {
+    __shared__ uint32_t stk[kVisStackDepth * kTB];
+    Counters st = {};
+    const SlotDev& G = slot ? a.F.g[1] : a.F.g[0];
+    // blocks are dealt to the sub-queues round robin; the waves of a
+    // sub-queue's blocks take its chunks of kVisChunk rays round robin (a
+    // short queue leaves the later waves without a chunk)
+    constexpr uint32_t kWaves = kTB / 64;
+    const uint32_t sub = blockIdx.x % kRaySubQueues;
+    const uint32_t n = min(q.count[sub * kCounterStride], q.sub_cap);
+    const uint32_t W = (gridDim.x / kRaySubQueues) * kWaves;
+    const uint32_t w = (blockIdx.x / kRaySubQueues) * kWaves + threadIdx.x / 64;
+    if ((uint64_t)w * kVisChunk < n) {
+        const float4* buf = q.buf + 2 * (size_t)sub * q.sub_cap;
+        trace_vis_chunks(a.S, G, buf, n, w, W, kVisChunk, kill, stk + threadIdx.x, kTB, kVisStackDepth, st);
     }
     flush_counters(st, a.counters);
 }
@@ -855,7 +880,10 @@ void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp,
                            term, q);
 }
 void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_vis, dim3(grid), dim3(kTB), 0, st, a, slot, q, kill);
+    if (a.S.n_tri >= kVisPersistentMinTris)
+        hipLaunchKernelGGL(k_vis, dim3(grid), dim3(kTB), 0, st, a, slot, q, kill);
+    else
+        hipLaunchKernelGGL(k_vis_lanes, dim3(std::min(grid, kShiftGrid)), dim3(kTB), 0, st, a, slot, q, kill);
 }
 void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                   const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,

@@ -731,8 +731,8 @@ struct Tracer {
 // ---------------------------------------------------------------------------
 // Deferred visibility.  A shift appends its visibility segments to a queue
 // (two float4 per ray: origin and length, direction and owner); a separate
-// pass traces them one ray per lane and zeroes kill[owner] when one is
-// blocked.  The queue is split into kRaySubQueues parts, each with its own
+// pass traces them (persistent lanes, or one ray per lane in small scenes)
+// and zeroes kill[owner] when one is blocked.  The queue is split into kRaySubQueues parts, each with its own
 // counter on its own cache line, chosen by block index: appends take one
 // atomic per wave on one of 64 addresses (atomics on a single address
 // serialize in L2).  Within a wave's allocation, segment e of every lane is
@@ -774,6 +774,227 @@ struct RayQueue {
         buf[2 * (size_t)i + 1] = make_float4(sg.d.x, sg.d.y, sg.d.z, __uint_as_float(owner));
     }
 };
+
+// Any-hit tracing of queued segments by one wave with persistent lanes (Aila
+// and Laine 2009, "dynamic fetch"): the wave owns the chunks c0, c0 + cstep,
+// c0 + 2 cstep, ... of `chunk` rays each of a sub-queue of n rays, and a lane
+// whose ray is finished takes the next ray of those chunks before the next
+// traversal phase, so that the wave does not idle behind its longest ray.
+// Chunks dealt round robin spread costly regions of the queue over many
+// waves.  Rays go to lanes in queue order; a blocked segment zeroes
+// kill[owner].
+// The traversal is the any-hit case of traverse(): the same 64-byte nodes,
+// postponed leaves and stack discipline, and the same triangle and sphere
+// tests, so each segment's result does not depend on which lane traces it or
+// in which order.  Every phase moves each active lane by at least one node
+// or leaf, a ray's node visits are bounded by its budget, and the wave
+// leaves once its range is taken and every lane is idle.
+__device__ inline void trace_vis_chunks(const SceneDev& S, const SlotDev& G, const float4* __restrict__ buf,
+                                        uint32_t n, uint32_t c0, uint32_t cstep, uint32_t chunk,
+                                        float* __restrict__ kill, uint32_t* stack, int stride, int depth,
+                                        Counters& st) {
+    constexpr uint32_t kDone = 0xFFFFFFFFu;
+    const int T = G.n_tri;
+    const int lane = (int)__lane_id();
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // wave-uniform: next ray and end of the current chunk
+    uint64_t c = c0;
+    uint32_t cursor = (uint32_t)min((uint64_t)n, c * chunk);
+    uint32_t end = (uint32_t)min((uint64_t)n, c * chunk + chunk);
+    bool have = false;         // this lane traces a ray
+    RayPre r;
+    r.o = r.d = r.inv = mk(0.f, 0.f, 0.f);
+    r.kx = r.ky = r.kz = 0;
+    r.sx = r.sy = r.sz = 0.f;
+    float tmax = 0.f;
+    uint32_t owner = 0;
+    int sp = 0, budget = 0;
+    uint32_t node = kDone, pmask = 0;
+    int4 pcc = make_int4(0, 0, 0, 0);
+    auto blocked = [&]() {
+        const float old = atomicExch(kill + owner, 0.f);
+        if (old != 0.f) st.c[ST_VISFAIL]++;
+    };
+    auto push = [&](uint32_t n) {
+        if (sp < depth) {
+            stack[sp * stride] = n;
+            ++sp;
+        } else {
+            st.c[ST_OVERFLOW]++;
+        }
+    };
+    auto pop = [&]() -> uint32_t {
+        if (sp == 0) return kDone;
+        --sp;
+        return stack[sp * stride];
+    };
+    while (true) {
+        // refill: idle lanes take the next rays of the wave's chunks in lane
+        // order, across the end of a chunk into the next one
+        const uint64_t idle = __ballot(!have);
+        if (idle && cursor < end) {
+            const uint32_t rank = (uint32_t)__popcll(idle & lt), tot = (uint32_t)__popcll(idle);
+            const uint32_t rem = end - cursor;
+            const uint64_t cn = c + cstep;   // the next chunk
+            const uint32_t nb = (uint32_t)min((uint64_t)n, cn * chunk), ne = (uint32_t)min((uint64_t)n, cn * chunk + chunk);
+            const uint32_t i = rank < rem ? cursor + rank : nb + (rank - rem);
+            const bool take = rank < rem || i < ne;
+            if (tot < rem) {
+                cursor += tot;
+            } else {   // this chunk is taken: go on in the next (empty when past the queue)
+                c = cn;
+                cursor = min(ne, nb + (tot - rem));
+                end = ne;
+            }
+            if (!have && take) {
+                const float4 r0 = buf[2 * (size_t)i], r1 = buf[2 * (size_t)i + 1];
+                st.c[ST_RAYS]++;
+                r = ray_pre(mk(r0.x, r0.y, r0.z), mk(r1.x, r1.y, r1.z));
+                tmax = r0.w;
+                owner = __float_as_uint(r1.w);
+                // analytic spheres first (any hit: the order of tests is free)
+                bool hit = false;
+                for (int q = 0; q < S.n_sph && !hit; ++q) {
+                    const int ob = S.sphere_ids[q];
+                    const Obj& O = S.objs[ob];
+                    float t;
+                    hit = isect_sphere(r.o, r.d, xf_point(G.xf + 12 * ob, mk(O.cx, O.cy, O.cz)), O.r, tmax, t);
+                }
+                if (hit) {
+                    blocked();
+                } else if (T > 0) {
+                    have = true;
+                    sp = 0;
+                    node = 0;
+                    pmask = 0;
+                    budget = 2 * G.n_nodes + 64;
+                }
+            }
+        }
+        if (cursor >= end && c * chunk < n) {   // an exhausted chunk: on to the next one
+            c += cstep;
+            cursor = (uint32_t)min((uint64_t)n, c * chunk);
+            end = (uint32_t)min((uint64_t)n, c * chunk + chunk);
+        }
+        if (!__any(have)) {
+            if (cursor >= end) break;
+            continue;
+        }
+        if (!have) continue;
+        // inner nodes until every active lane has a pending leaf or is done
+        while (node < 0x80000000u && (pmask == 0 || sp + 4 <= depth)) {
+            if (--budget <= 0 || node >= (uint32_t)G.n_nodes) {   // never for a well-formed tree
+                st.c[ST_OVERFLOW]++;
+                node = kDone;
+                sp = 0;
+                break;
+            }
+            const NodeQ* nq = G.nodes + node;
+            const float4 org = nq->org;
+            const uint4 q0 = nq->q0, q1 = nq->q1;
+            const int4 cc = nq->child;
+            const int nc = (int)q1.w;
+            const float sx = __int_as_float((int)((q1.z & 0xFFu) << 23));
+            const float sy = __int_as_float((int)(((q1.z >> 8) & 0xFFu) << 23));
+            const float sz = __int_as_float((int)(((q1.z >> 16) & 0xFFu) << 23));
+            auto deq = [](uint32_t w, float o, float sc) {
+                return make_float4(fmaf((float)(w & 0xFFu), sc, o), fmaf((float)((w >> 8) & 0xFFu), sc, o),
+                                   fmaf((float)((w >> 16) & 0xFFu), sc, o), fmaf((float)(w >> 24), sc, o));
+            };
+            const float4 lx = deq(q0.x, org.x, sx), hx = deq(q0.y, org.x, sx);
+            const float4 ly = deq(q0.z, org.y, sy), hy = deq(q0.w, org.y, sy);
+            const float4 lz = deq(q1.x, org.z, sz), hz = deq(q1.y, org.z, sz);
+            st.c[ST_NODES]++;
+            float t0, t1, t2, t3;
+            const bool h0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, r, tmax, t0);
+            const bool h1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, r, tmax, t1) && nc > 1;
+            const bool h2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, r, tmax, t2) && nc > 2;
+            const bool h3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, r, tmax, t3) && nc > 3;
+            const bool f0 = cc.x < 0, f1 = cc.y < 0, f2 = cc.z < 0, f3 = cc.w < 0;
+            const uint32_t leaves = (h0 && f0 ? 1u : 0u) | (h1 && f1 ? 2u : 0u) | (h2 && f2 ? 4u : 0u) |
+                                    (h3 && f3 ? 8u : 0u);
+            if (leaves) {
+                if (pmask == 0) {
+                    pmask = leaves;
+                    pcc = cc;
+                } else {
+                    if (leaves & 1u) push((uint32_t)cc.x);
+                    if (leaves & 2u) push((uint32_t)cc.y);
+                    if (leaves & 4u) push((uint32_t)cc.z);
+                    if (leaves & 8u) push((uint32_t)cc.w);
+                }
+            }
+            constexpr float kInfT = 3.0e38f;
+            float k0 = (h0 && !f0) ? t0 : kInfT, k1 = (h1 && !f1) ? t1 : kInfT;
+            float k2 = (h2 && !f2) ? t2 : kInfT, k3 = (h3 && !f3) ? t3 : kInfT;
+            int n0 = cc.x, n1 = cc.y, n2 = cc.z, n3 = cc.w;
+            auto cswap = [](float& ka, int& na, float& kb, int& nb) {
+                if (kb < ka) {
+                    const float kt = ka;
+                    ka = kb;
+                    kb = kt;
+                    const int nt = na;
+                    na = nb;
+                    nb = nt;
+                }
+            };
+            // only the nearest child to the front
+            cswap(k0, n0, k1, n1);
+            cswap(k2, n2, k3, n3);
+            cswap(k0, n0, k2, n2);
+            if (k0 < kInfT) {
+                if (k3 < kInfT) push((uint32_t)n3);
+                if (k2 < kInfT) push((uint32_t)n2);
+                if (k1 < kInfT) push((uint32_t)n1);
+                node = (uint32_t)n0;
+            } else {
+                node = pop();
+            }
+            if (node != kDone && node >= 0x80000000u && pmask == 0) {
+                pmask = 1u;
+                pcc.x = (int)node;
+                node = pop();
+            }
+            if (__all(pmask != 0)) break;
+        }
+        // leaf phase: the pending leaves, then leaves met on the stack while
+        // no inner node is next
+        bool hit = false;
+        while (pmask && !hit) {
+            const int j = __ffs(pmask) - 1;
+            pmask &= pmask - 1;
+            const uint32_t c = (uint32_t)(j == 0 ? pcc.x : (j == 1 ? pcc.y : (j == 2 ? pcc.z : pcc.w)));
+            const int first = (int)(c & 0x0FFFFFFFu), cnt = (int)((c >> 28) & 7u) + 1;
+            for (int k = first; k < first + cnt; ++k) {
+                if ((unsigned)k >= (unsigned)T) {   // never for a well-formed tree
+                    st.c[ST_OVERFLOW]++;
+                    break;
+                }
+                st.c[ST_TRIS]++;
+                const float4 a = G.leaves[3 * k], b = G.leaves[3 * k + 1], cv = G.leaves[3 * k + 2];
+                float t, b1, b2;
+                if (isect_tri(r.o, r.d, r.kx, r.ky, r.kz, r.sx, r.sy, r.sz, mk(a.x, a.y, a.z), mk(b.x, b.y, b.z),
+                              mk(cv.x, cv.y, cv.z), tmax, t, b1, b2)) {
+                    hit = true;
+                    break;
+                }
+            }
+            if (!hit && pmask == 0 && node != kDone && node >= 0x80000000u) {
+                pmask = 1u;
+                pcc.x = (int)node;
+                node = pop();
+            }
+        }
+        if (hit) {
+            blocked();
+            have = false;
+            pmask = 0;
+            node = kDone;
+        } else if (node == kDone && pmask == 0) {
+            have = false;
+        }
+    }
+}
 
 // A list of u32 work indices in kRaySubQueues sub-lists (same scheme as the
 // ray queue): alloc(n) gives this lane n consecutive slots.
