@@ -25,7 +25,9 @@
  *     distance, Delta l = (b - b') * bin width);
  *   - optionally, initial gate samples drawn in a gate K times wider and the
  *     RIS winner shrunk into the gate (Sec. 4.4.2, shrink mapping, with all
- *     samples in the wide gate, R = 1);
+ *     samples in the wide gate, R = 1, or a fraction R < 1 of the path trees
+ *     there and the rest in the gate, the two reservoirs merged by GRIS with
+ *     the generalized balance heuristic, which is unbiased);
  *   - the Doppler domain (Sec. 4.6): planes over the path velocity
  *     u = -dl/dt (eq. optical_path_velocity, refractive index 1) with the
  *     vertices moving rigidly with their objects, and the same shift under a
@@ -103,7 +105,8 @@ void philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4, PASS_BIN = 16 };
+enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4, PASS_BIN = 16,
+       PASS_SHRINK_MIX = 17 };
 
 struct Draw {
     uint64_t x[4];
@@ -707,18 +710,28 @@ struct Oracle {
     // -------------------------------------------------------------------
     // time gate / bins (Sec. 3.1 W_tau; half-open boxes)
     // -------------------------------------------------------------------
-    // the gate plane of a frame slot uses the gate centre of that frame
+    // the gate plane of a frame slot uses the gate centre of that frame;
+    // index n_bins + 1 stands for the wide gate of the shrink mapping (K
+    // times the gate, same centre), the domain of its wide-gate samples
+    double gate_half(int pl) const { return 0.5 * s.gate_width * (pl == s.n_bins + 1 ? s.shrink_k : 1.0); }
     double plane_lo(int pl, int slot = 0) const {
-        return pl < s.n_bins ? s.bin_t0 + pl * s.bin_width : fg[slot].gate_center - 0.5 * s.gate_width;
+        return pl < s.n_bins ? s.bin_t0 + pl * s.bin_width : fg[slot].gate_center - gate_half(pl);
     }
     double plane_hi(int pl, int slot = 0) const {
-        return pl < s.n_bins ? s.bin_t0 + (pl + 1) * s.bin_width : fg[slot].gate_center + 0.5 * s.gate_width;
+        return pl < s.n_bins ? s.bin_t0 + (pl + 1) * s.bin_width : fg[slot].gate_center + gate_half(pl);
     }
-    double plane_width(int pl) const { return pl < s.n_bins ? s.bin_width : s.gate_width; }
+    double plane_width(int pl) const { return pl < s.n_bins ? s.bin_width : 2.0 * gate_half(pl); }
     bool in_plane(int pl, double len, int slot = 0) const {
         return len >= plane_lo(pl, slot) && len < plane_hi(pl, slot);
     }
-    bool shrink_on() const { return s.gate_enabled && s.shrink_k > 1.0; }
+    // path trees whose gate candidates come from the wide gate: R x M_init
+    int wide_trees() const {
+        const double r = std::min(1.0, std::max(0.0, s.shrink_r));
+        return (int)std::lround(r * (double)s.m_init);
+    }
+    bool shrink_on() const { return s.gate_enabled && s.shrink_k > 1.0 && wide_trees() > 0; }
+    // R < 1: wide-gate and gate samples, combined with MIS
+    bool shrink_mix() const { return shrink_on() && wide_trees() < s.m_init; }
     // the wide ("rough") gate of the shrink mapping: K times the gate, same centre
     bool in_rough_gate(double len) const {
         const double c = fg[0].gate_center, h = 0.5 * s.shrink_k * s.gate_width;
@@ -1173,6 +1186,77 @@ struct Oracle {
         r.y = sh.y;
     }
 
+    // R < 1 (Sec. 4.4.2): the gate's canonical reservoir (gate samples of the
+    // last (1 - R) M_init trees, confidence M_n) and the wide-gate reservoir
+    // (the first R M_init trees, confidence M_w) are merged by GRIS with the
+    // generalized balance heuristic (eq. GRIS_MIS_weight, eq.
+    // GRIS_resampling_weight) into the gate: the wide sample y_w enters
+    // shrunk, y' = T(y_w) with |J| = |J_shift| / K, and the density of the
+    // wide technique at a gate path y is p_w(T^-1(y)) |J_{T^-1}(y)|, with
+    // T^-1 the expansion Delta l = K (l - l0) + l0 - l into the wide gate and
+    // |J_{T^-1}| = K |J_shift|; a failed expansion means the wide technique
+    // cannot produce y.  Paths that cannot be moved (no reconnection vertex,
+    // or the naive shift) map by the identity where they lie in the gate.
+    // One uniform (pass 17) selects between the two candidates.
+    void shrink_mix_sample(int pix, uint64_t frame, PixelRes& pr, Stats& st) {
+        const int gp = s.n_bins, wp = s.n_bins + 1;
+        const double Mw = (double)wide_trees(), Mn = (double)(s.m_init - wide_trees());
+        const double l0 = fg[0].gate_center, K = s.shrink_k;
+        auto movable = [&](const PathRec& y) { return s.shift_mode == 1 && y.k >= 2; };
+        double wa = 0.0, wb = 0.0, pa = 0.0, pb = 0.0;
+        PathRec ya, yb;
+        auto itn = pr.find(gp);
+        if (itn != pr.end()) {   // the canonical gate sample
+            const Res& r = itn->second;
+            ya = r.y;
+            pa = r.y.phat;
+            double p_wide = 0.0;
+            if (!movable(r.y)) {
+                p_wide = pa;
+            } else {
+                const double l = r.y.len;
+                ShiftOut e = shift(r.y, 0, pix, 0, pix, wp, K * (l - l0) + l0 - l, st);
+                if (e.ok) p_wide = e.phat * e.J * K;
+            }
+            wa = Mn * pa / (Mn * pa + Mw * p_wide) * pa * r.W;
+        }
+        auto itw = pr.find(wp);
+        if (itw != pr.end()) {   // the wide-gate sample, shrunk
+            const Res& r = itw->second;
+            double J = 0.0;
+            if (!movable(r.y)) {
+                if (in_plane(gp, r.y.len)) {
+                    yb = r.y;
+                    pb = r.y.phat;
+                    J = 1.0;
+                }
+            } else {
+                const double l = r.y.len;
+                ShiftOut sh = shift(r.y, 0, pix, 0, pix, gp, (l - l0) / K + l0 - l, st);
+                if (sh.ok) {
+                    yb = sh.y;
+                    pb = sh.phat;
+                    J = sh.J / K;
+                }
+            }
+            if (J > 0.0) {
+                const double p_wide = r.y.phat / J;   // p_w(y_w) |J_{T^-1}(y')|
+                wb = Mw * p_wide / (Mn * pb + Mw * p_wide) * pb * r.W * J;
+            }
+            pr.erase(itw);
+        }
+        const double ws = wa + wb;
+        if (!(ws > 0.0)) {
+            pr.erase(gp);
+            return;
+        }
+        const Draw u = draw(s.seed, full_pixel(pix), frame, PASS_SHRINK_MIX, 0, 0);
+        const bool pick_b = u.u(0) * ws < wb;
+        Res& out = pr[gp];
+        out.y = pick_b ? yb : ya;
+        out.W = ws / (pick_b ? pb : pa);
+    }
+
     // initial candidates: path trees with NEE at every vertex, each sub-path
     // deposited into the reservoir of its bin (and the gate) (Sec. 4.5).
     void initial_pass(uint64_t frame, std::vector<PixelRes>& can, std::vector<double>& Mc,
@@ -1244,18 +1328,27 @@ struct Oracle {
                                 rec.pre_pdf = pdf;
                             }
                             Draw u = draw(s.seed, fp, frame, PASS_RIS, (uint64_t)tree, (uint64_t)i);
-                            double w = C / ((double)s.m_init * pdf);
                             // plain PT deposits into the planes; the reservoirs
-                            // take the gate's candidates from the rough gate
-                            // when the shrink mapping is on
+                            // take the gate's candidates from the wide gate
+                            // when the shrink mapping is on (all trees, R = 1;
+                            // the first R x M_init trees with R < 1, whose
+                            // wide-gate reservoir is kept apart, and the
+                            // others from the gate).  Each sampling technique
+                            // normalizes by its own number of trees.
                             const bool gate_pt = s.gate_enabled && in_plane(s.n_bins, l_i);
-                            const bool gate_res = shrink_on() ? in_rough_gate(l_i) : gate_pt;
-                            int planes[2] = {bin_of(l_i), gate_res ? s.n_bins : -1};
+                            const bool wide_tree = shrink_on() && tree < wide_trees();
+                            const bool gate_res = wide_tree ? in_rough_gate(l_i) : gate_pt;
+                            const int gate_key = wide_tree && shrink_mix() ? s.n_bins + 1 : s.n_bins;
+                            const double m_gate = !shrink_mix() ? (double)s.m_init
+                                                  : (wide_tree ? (double)wide_trees()
+                                                               : (double)(s.m_init - wide_trees()));
+                            int planes[2] = {bin_of(l_i), gate_res ? gate_key : -1};
                             if (planes[0] >= 0) pt[(size_t)planes[0] * P + pix] += C / pdf / (double)s.m_init;
                             if (gate_pt) pt[(size_t)s.n_bins * P + pix] += C / pdf / (double)s.m_init;
                             for (int q = 0; q < 2; ++q) {
                                 int pl = planes[q];
                                 if (pl < 0) continue;
+                                const double w = C / ((q == 0 ? (double)s.m_init : m_gate) * pdf);
                                 double& ws = wsum[pl];
                                 ws += w;
                                 if (u.u(q) * ws < w) can[pix][pl].y = rec;
@@ -1280,7 +1373,8 @@ struct Oracle {
                 }
             }
             for (auto& kv : can[pix]) kv.second.W = wsum[kv.first] / kv.second.y.phat;
-            if (shrink_on()) shrink_gate_sample(pix, can[pix], st);
+            if (shrink_mix()) shrink_mix_sample(pix, frame, can[pix], st);
+            else if (shrink_on()) shrink_gate_sample(pix, can[pix], st);
         }
         for (auto& t : ts) stats.add(t);
     }

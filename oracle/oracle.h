@@ -50,6 +50,7 @@ typedef struct {
     int32_t shift_mode, include_direct, debug_stage;
     int32_t bin_radius;           /* bin-axis reuse: bins b +- 1..bin_radius of the same pixel (0 = off) */
     double shrink_k;              /* shrink mapping: initial gate samples from a gate shrink_k times wider (1 = off) */
+    double shrink_r;              /* fraction R of the path trees sampled from the wide gate (1 = all) */
     int32_t domain;               /* 0: planes over path length; 1: over path velocity u = -dl/dt (Doppler) */
     uint64_t seed;
 } orc_sensor;

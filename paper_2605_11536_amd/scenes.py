@@ -109,6 +109,7 @@ class Sensor:
     debug_stage: int = STAGE_FINAL
     bin_radius: int = 0            # bin-axis reuse: bins b +- 1..bin_radius (0 = off)
     shrink_k: float = 1.0          # shrink mapping of initial gate samples: rough gate K x wider (1 = off)
+    shrink_r: float = 1.0          # fraction of the path trees sampled from the wide gate (R < 1: MIS with the gate)
     domain: int = DOMAIN_TIME      # planes over path length (time) or path velocity (Doppler)
     seed: int = 0
 

@@ -286,3 +286,74 @@ def test_shrink_mapping_sphere_closed_form(oracle_lib, reuse):
     per = np.array(per)
     mean, se = per.mean(), per.std(ddof=1) / math.sqrt(len(per))
     assert abs(mean - exp) < 4 * se + 2e-3 * exp, ((mean - exp) / se, mean, exp)
+
+
+def _shrink_r_sums(oracle_lib, r, seeds, **kw):
+    rs, ps = [], []
+    for seed in range(seeds):
+        w = scenes.cornell_box(width=32, height=32, frames=1, seed=seed, gate_width=0.05, m_init=3, shrink_k=20.0,
+                               shrink_r=r, temporal=0, spatial_rounds=0, **kw)
+        o = oracle_lib.Oracle(w.scene, w.sensor)
+        out = o.render(w.frames[0])
+        rs.append(out["image"].sum())
+        ps.append(out["pt_image"].sum())
+        o.close()
+    return np.array(rs), np.array(ps)
+
+
+def test_shrink_mapping_with_canonical_samples_is_unbiased(oracle_lib):
+    """Shrink mapping with R < 1 (Sec. 4.4.2): of three path trees per pixel
+    two sample the gate and one a gate K = 20 times wider whose winner is
+    shrunk; GRIS with the generalized balance heuristic over the two
+    techniques (confidences 2 and 1) is unbiased, while R = 1 (all trees in
+    the wide gate) is biased dark where shrinks fail, as the paper notes."""
+    n = 96
+    rs, ps = _shrink_r_sums(oracle_lib, 1.0 / 3.0, n)
+    z = (rs.mean() - ps.mean()) / math.sqrt(rs.var(ddof=1) / n + ps.var(ddof=1) / n)
+    assert abs(z) < 3.5, (z, rs.mean(), ps.mean())
+    r1, p1 = _shrink_r_sums(oracle_lib, 1.0, n)
+    z1 = (r1.mean() - p1.mean()) / math.sqrt(r1.var(ddof=1) / n + p1.var(ddof=1) / n)
+    assert z1 < -4.0, z1   # the R = 1 bias this test would miss if it had no power
+
+
+
+def test_shrink_mapping_with_canonical_samples_identity_is_exact(oracle_lib):
+    """Under the naive shift no path is moved: a wide-gate sample enters the
+    gate by the identity when it lies there, and the balance weights of the
+    two techniques are their confidences, 2/3 (two gate trees) and 1/3 (one
+    wide tree).  With one candidate per tree (n = 2 only) and no reuse the
+    merged estimate then equals plain path tracing exactly, per seed (equal
+    weights would lose a sixth)."""
+    rs, ps = [], []
+    for seed in range(16):
+        w = scenes.cornell_box(width=32, height=32, frames=1, seed=seed, gate_width=0.2, m_init=3, shrink_k=5.0,
+                               shrink_r=1.0 / 3.0, temporal=0, spatial_rounds=0, shift_mode=scenes.SHIFT_NAIVE)
+        o = oracle_lib.Oracle(w.scene, w.sensor)
+        out = o.render(w.frames[0])
+        rs.append(out["image"])
+        ps.append(out["pt_image"])
+        o.close()
+    assert np.sum(ps) > 0
+    assert np.allclose(np.array(rs), np.array(ps), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("reuse", [False, True])
+def test_shrink_mapping_with_canonical_samples_sphere_closed_form(oracle_lib, reuse):
+    """R = 1/2 (one of two path trees per pixel in a gate K = 5 times wider)
+    inside the sphere: the gate image matches the gate's closed form in
+    expectation, alone and followed by temporal and spatial reuse."""
+    R, rho, I = 1.0, 0.5, 1.0
+    kw = {} if reuse else dict(temporal=0, spatial_rounds=0)
+    exp = float(_sphere_expect(rho, I, R, [3.45], [3.55], 2)[0])
+    per = []
+    for seed in range(24):
+        w = scenes.lambert_sphere_interior(radius=R, albedo=rho, intensity=I, width=24, height=24, n_bins=0,
+                                           frames=2, seed=seed, shrink_k=5.0, shrink_r=0.5, m_init=2, **kw)
+        o = oracle_lib.Oracle(w.scene, w.sensor)
+        for fr in w.frames:
+            out = o.render(fr)
+        per.append(out["image"].mean())
+        o.close()
+    per = np.array(per)
+    mean, se = per.mean(), per.std(ddof=1) / math.sqrt(len(per))
+    assert abs(mean - exp) < 4 * se + 2e-3 * exp, ((mean - exp) / se, mean, exp)
