@@ -122,6 +122,15 @@ typedef struct {
                                         biased low where shrinks fail).  1 = off, at most 1000 */
     int32_t domain;                  /* TOF_DOMAIN_*; the velocity domain requires bin_radius 0 and
                                         shrink_k 1 (both shifts are defined on path lengths) */
+    float shrink_r;                  /* with shrink_k > 1: the fraction R in [0, 1] of the m_init path trees
+                                        whose gate candidates come from the wide gate (the first
+                                        round(R m_init) trees).  R = 1: all, as described at shrink_k.
+                                        0 < round(R m_init) < m_init: the others sample the gate itself
+                                        and the two reservoirs are merged into the gate by GRIS with the
+                                        generalized balance heuristic (Sec. 4.4.2), unbiased; the wide
+                                        technique's density at a gate path comes through the inverse
+                                        map, Delta l = K (l - l0) + l0 - l.  round(R m_init) = 0: no
+                                        shrink mapping */
 } tof_sensor_desc;
 
 /* Per-frame poses.  object_xforms: host [num_objects*12], rigid 3x4 row-major

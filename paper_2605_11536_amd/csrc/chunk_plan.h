@@ -59,6 +59,9 @@ inline ChunkPlan plan_chunks(size_t P, size_t B, int k, int br) {
         p.term_cap = std::max(p.term_cap, K[m] * p.ct[m]);
         p.ray_cap = std::max(p.ray_cap, seg[m] * K[m] * p.ct[m]);
     }
+    // the shrink mapping with R < 1 runs over chunks of the spatial pass's
+    // task count with two shifts, at most 4 segments, per pixel
+    p.ray_cap = std::max(p.ray_cap, 4 * p.ct[1]);
     return p;
 }
 

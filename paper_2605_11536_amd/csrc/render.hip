@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(kTB) k_gbuffer(FrameArgs a, GBufOut out) {
 // measure the path velocity (Sec. 4.6) instead of the path length.
 // ---------------------------------------------------------------------------
 template <bool VEL>
-TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
+TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, ResSet wide, float* __restrict__ pt,
                                                  float2* __restrict__ direct) {
     __shared__ uint32_t stk[kStackDepth * kTB];
     Counters st = {};
@@ -94,6 +94,9 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
         const SlotDev& G = a.F.g[0];
         const int P = s.P;
         for (int w = 0; w < s.mask_words; ++w) can.mask[(size_t)w * P + pix] = 0u;
+        // the wide-gate reservoir of the shrink mapping with R < 1 (W = 0: empty)
+        const bool mix = wide.rec != nullptr;
+        if (mix) rec_W(wide, pix) = 0.f;
         float2 dterm = make_float2(0.f, 0.f);
         if (G.gb_obj[pix] < 0) {
             can.M[pix] = 0.f;
@@ -154,18 +157,35 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                                 rec.pre_pdf = pdf;
                             }
                             Draw u = philox(s.seed, fp, a.frame, PASS_RIS, (uint64_t)tree, (uint64_t)i);
-                            float w = C / ((float)s.m_init * pdf);
                             // plain PT deposits into the planes; the reservoirs take
                             // the gate's candidates from the wide gate when the
-                            // shrink mapping is on
+                            // shrink mapping is on (every tree with R = 1; with
+                            // R < 1 the first R x M_init trees, into a reservoir
+                            // of their own, and the others from the gate), each
+                            // sampling technique normalized by its own tree count
                             const bool gate_pt = s.gate_en && in_plane(s, s.n_bins, li);
-                            const bool gate_res = s.gate_en && s.shrink_k > 1.f ? in_rough_gate(s, li) : gate_pt;
+                            const bool wide_tree = s.gate_en && s.shrink_k > 1.f && tree < s.mw;
+                            const bool gate_res = wide_tree ? in_rough_gate(s, li) : gate_pt;
+                            const float m_gate = !mix ? (float)s.m_init
+                                                      : (wide_tree ? (float)s.mw : (float)(s.m_init - s.mw));
                             int planes[2] = {bin_of(s, li), gate_res ? s.n_bins : -1};
                             if (planes[0] >= 0) pt[(size_t)planes[0] * P + pix] += C / pdf / (float)s.m_init;
                             if (gate_pt) pt[(size_t)s.n_bins * P + pix] += C / pdf / (float)s.m_init;
                             for (int q = 0; q < 2; ++q) {
                                 int pl = planes[q];
                                 if (pl < 0) continue;
+                                const float w = C / ((q == 0 ? (float)s.m_init : m_gate) * pdf);
+                                if (q == 1 && mix && wide_tree) {
+                                    const float ws0 = rec_W(wide, pix);
+                                    if (ws0 == 0.f) {
+                                        store_rec(wide, pix, rec, w);
+                                    } else {
+                                        const float ws = ws0 + w;
+                                        if (u.u(q) * ws < w) store_rec(wide, pix, rec, ws);
+                                        else rec_W(wide, pix) = ws;
+                                    }
+                                    continue;
+                                }
                                 size_t idx = (size_t)pl * P + pix;
                                 uint32_t* mw = can.mask + (size_t)(pl >> 5) * P + pix;
                                 uint32_t bit = 1u << (pl & 31);
@@ -213,6 +233,7 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, float* __restrict__ pt,
                     rec_W(can, idx) = rec_W(can, idx) / rec_phat(can, idx);
                 }
             }
+            if (mix && rec_W(wide, pix) > 0.f) rec_W(wide, pix) = rec_W(wide, pix) / rec_phat(wide, pix);
         }
         direct[pix] = dterm;
     }
@@ -773,6 +794,105 @@ __global__ void k_shrink_fin(FrameArgs a, ResSet can) {
         atomicAnd(can.mask + (size_t)(gp >> 5) * P + pix, ~(1u << (gp & 31)));
 }
 
+// ---------------------------------------------------------------------------
+// Shrink mapping with R < 1 (Sec. 4.4.2): the gate's canonical reservoir
+// (confidence M_n = M_init - M_w) and the wide-gate reservoir (M_w) are
+// merged into the gate by GRIS with the generalized balance heuristic.
+// k_shrink_mix shifts, per pixel of [p0, p0 + np): the gate sample into the
+// wide gate (the expansion Delta l = K (l - l0) + l0 - l, the inverse of the
+// shrink), whose |J| K p_hat gives the wide technique's density at it, and
+// the wide sample into the gate (the shrink, |J| / K).  Paths that cannot be
+// moved map by the identity where they lie in the gate.  scr[t] = (density
+// of the wide technique at the gate sample, |J| of the shrunk wide sample,
+// p_hat of the wide sample before the shrink); a blocked visibility ray of
+// either shift zeroes its component (its owner).  After the rays,
+// k_shrink_mix_fin forms the two resampling weights and selects one with a
+// uniform of pass 17.
+// ---------------------------------------------------------------------------
+TOF_TRACE_KERNEL k_shrink_mix(FrameArgs a, ResSet can, ResSet wide, uint32_t p0, uint32_t np, RayQueue q,
+                              float4* __restrict__ scr) {
+    __shared__ uint32_t stk[kStackDepth * kTB];
+    Counters st = {};
+    Tracer tr{a.S, stk + threadIdx.x, kTB, kStackDepth, st};
+    const Sens& s = a.s;
+    const int P = s.P, gp = s.n_bins, wp = s.n_bins + 1;
+    const float l0 = s.gate_c, K = s.shrink_k;
+    for (uint32_t t = blockIdx.x * kTB + threadIdx.x; t < np; t += gridDim.x * kTB) {
+        const int pix = (int)(p0 + t);
+        float4 o = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (mask_bit(can.mask, P, gp, pix)) {   // the gate sample, expanded
+            float W;
+            const Rec y = load_rec(can, (size_t)gp * P + pix, W);
+            if (s.shift_mode != TOF_SHIFT_PATHLEN || y.k < 2) {
+                o.x = y.phat;
+            } else {
+                const float l = y.len;
+                const ShiftOut e = shift_path<false>(s, a.S, a.F, tr, y, 0, pix, 0, pix, wp, K * (l - l0) + l0 - l, q,
+                                                     4u * t);
+                if (e.ok) o.x = e.phat * e.J * K;
+            }
+        }
+        if (rec_W(wide, pix) > 0.f) {   // the wide sample, shrunk
+            float W;
+            Rec y = load_rec(wide, pix, W);
+            o.z = y.phat;
+            if (s.shift_mode != TOF_SHIFT_PATHLEN || y.k < 2) {
+                if (in_plane(s, gp, y.len)) o.y = 1.f;
+            } else {
+                const float l = y.len;
+                const ShiftOut sh = shift_path<false>(s, a.S, a.F, tr, y, 0, pix, 0, pix, gp, (l - l0) / K + l0 - l,
+                                                      q, 4u * t + 1u);
+                if (sh.ok) {
+                    apply_shift(y, sh);
+                    store_rec(wide, pix, y, W);
+                    o.y = sh.J / K;
+                }
+            }
+        }
+        scr[t] = o;
+    }
+    flush_counters(st, a.counters);
+}
+
+__global__ void k_shrink_mix_fin(FrameArgs a, ResSet can, ResSet wide, uint32_t p0, uint32_t np,
+                                 const float4* __restrict__ scr) {
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= np) return;
+    const Sens& s = a.s;
+    const int P = s.P, gp = s.n_bins;
+    const int pix = (int)(p0 + t);
+    const float Mw = (float)s.mw, Mn = (float)(s.m_init - s.mw);
+    const float4 o = scr[t];
+    const size_t ia = (size_t)gp * P + pix;
+    const bool has_a = mask_bit(can.mask, P, gp, pix);
+    float wa = 0.f, wb = 0.f, pa = 0.f, pb = 0.f;
+    if (has_a) {
+        pa = rec_phat(can, ia);
+        wa = Mn * pa / (Mn * pa + Mw * o.x) * pa * rec_W(can, ia);
+    }
+    if (rec_W(wide, pix) > 0.f && o.y > 0.f) {
+        pb = rec_phat(wide, pix);
+        const float pw = o.z / o.y;   // the wide technique's density at the shrunk sample
+        wb = Mw * pw / (Mn * pb + Mw * pw) * pb * rec_W(wide, pix) * o.y;
+    }
+    const float ws = wa + wb;
+    uint32_t* mword = can.mask + (size_t)(gp >> 5) * P + pix;
+    const uint32_t bit = 1u << (gp & 31);
+    if (!(ws > 0.f)) {
+        if (has_a) atomicAnd(mword, ~bit);
+        return;
+    }
+    const Draw u = philox(s.seed, full_pixel(s, pix), a.frame, PASS_SHRINK_MIX, 0, 0);
+    if (u.u(0) * ws < wb) {
+        float W;
+        const Rec y = load_rec(wide, pix, W);
+        store_rec(can, ia, y, ws / pb);
+        if (!has_a) atomicOr(mword, bit);
+    } else {
+        rec_W(can, ia) = ws / pa;
+    }
+}
+
 // one plane passed through unchanged (the gate plane across the bin-axis pass)
 __global__ void k_copy_plane(FrameArgs a, ResSet in, ResSet out, int pl) {
     const int P = a.s.P;
@@ -832,12 +952,13 @@ namespace tofh {
 void launch_gbuffer(const FrameArgs& a, GBufOut out, hipStream_t st) {
     hipLaunchKernelGGL(k_gbuffer, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, out);
 }
-void launch_initial(const FrameArgs& a, ResSet can, float* pt, float2* direct, hipStream_t st) {
+void launch_initial(const FrameArgs& a, ResSet can, ResSet wide, float* pt, float2* direct, hipStream_t st) {
     if (a.s.domain)
-        hipLaunchKernelGGL(k_initial<true>, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, pt, direct);
-    else
-        hipLaunchKernelGGL(k_initial<false>, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, pt,
+        hipLaunchKernelGGL(k_initial<true>, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, wide, pt,
                            direct);
+    else
+        hipLaunchKernelGGL(k_initial<false>, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, wide,
+                           pt, direct);
 }
 void launch_reproject(const FrameArgs& a, const ResSet& can, const ResSet& prev, int* prev_pix, float* M_out,
                       hipStream_t st) {
@@ -895,6 +1016,15 @@ void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& B
 void launch_shrink(const FrameArgs& a, const ResSet& can, size_t p0, size_t np, const RayQueue& q, unsigned grid,
                    hipStream_t st) {
     hipLaunchKernelGGL(k_shrink, dim3(grid), dim3(kTB), 0, st, a, can, (uint32_t)p0, (uint32_t)np, q);
+}
+void launch_shrink_mix(const FrameArgs& a, const ResSet& can, const ResSet& wide, size_t p0, size_t np,
+                       const RayQueue& q, float4* scr, unsigned grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_shrink_mix, dim3(grid), dim3(kTB), 0, st, a, can, wide, (uint32_t)p0, (uint32_t)np, q, scr);
+}
+void launch_shrink_mix_fin(const FrameArgs& a, const ResSet& can, const ResSet& wide, size_t p0, size_t np,
+                           const float4* scr, hipStream_t st) {
+    hipLaunchKernelGGL(k_shrink_mix_fin, dim3(grid_for(np, 256, 1u << 30)), dim3(256), 0, st, a, can, wide,
+                       (uint32_t)p0, (uint32_t)np, scr);
 }
 void launch_shrink_fin(const FrameArgs& a, const ResSet& can, hipStream_t st) {
     hipLaunchKernelGGL(k_shrink_fin, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, can);

@@ -100,6 +100,7 @@ struct tof_ctx {
     // workspace of one item chunk (sizes in plan)
     uint2* tasks = nullptr;    // [task_cap]
     float4* fwd = nullptr;     // [task_cap]: forward-shift terms per task
+    float4* wide = nullptr;    // [5 P]: wide-gate reservoirs of the shrink mapping with R < 1, else none
     float4* shv = nullptr;     // [2 * task_cap]: fields rewritten by each forward shift
     float* term = nullptr;     // [term_cap]: MIS terms per (task, neighbour)
     float4* rays = nullptr;    // [2 * ray_cap]: queued visibility segments
@@ -211,6 +212,18 @@ V3 hcross(V3 a, V3 b) { return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, 
 constexpr size_t kRecBytes = 4 * kRecWords;   // one reservoir record
 
 
+// path trees whose gate candidates come from the wide gate of the shrink
+// mapping (R x M_init), 0 when the shrink mapping is off
+int wide_trees(const tof_sensor_desc& d) {
+    if (!d.gate_enabled || !(d.shrink_k > 1.f)) return 0;
+    return (int)std::lround(std::min(1.0, std::max(0.0, (double)d.shrink_r)) * (double)d.m_init);
+}
+// R < 1: a wide-gate reservoir per pixel besides the gate's own
+bool shrink_mix(const tof_sensor_desc& d) {
+    const int w = wide_trees(d);
+    return w > 0 && w < d.m_init;
+}
+
 size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t P = (size_t)d.width * d.height;
     size_t B = (size_t)d.n_bins + (d.gate_enabled ? 1 : 0);
@@ -221,11 +234,10 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
     return 4 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
            P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ + P * B * 4 /*first task per item*/ +
            pl.task_cap * (8 + 16 + 32) /*tasks, forward terms, shifted fields*/ +
-           pl.term_cap * (4 + 4) /*MIS terms, MIS work list*/ + 32 * pl.ray_cap + 64 * 1024;
+           pl.term_cap * (4 + 4) /*MIS terms, MIS work list*/ + 32 * pl.ray_cap +
+           (shrink_mix(d) ? P * kRecBytes : 0) /*wide-gate reservoirs*/ + 64 * 1024;
 }
 
-// one slot of the pinned upload ring: transforms, the tree over the objects
-// (at most one 4-wide node per mesh object) and its refit order
 // pinned staging of one frame: transforms, the tree over the objects and its
 // refit order, then the velocities
 size_t pinned_slot_bytes(size_t n_obj, size_t n_tlas_cap) {
@@ -641,7 +653,8 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
               (d->shift_mode == TOF_SHIFT_NAIVE || d->shift_mode == TOF_SHIFT_PATHLEN) &&
               d->debug_stage >= TOF_STAGE_CANONICAL && d->debug_stage <= TOF_STAGE_FINAL &&
               d->bin_radius >= 0 && d->bin_radius <= 4 && std::isfinite(d->shrink_k) && d->shrink_k >= 1.f &&
-              d->shrink_k <= 1000.f && (d->domain == TOF_DOMAIN_TIME || d->domain == TOF_DOMAIN_VELOCITY) &&
+              d->shrink_k <= 1000.f && std::isfinite(d->shrink_r) && d->shrink_r >= 0.f && d->shrink_r <= 1.f &&
+              (d->domain == TOF_DOMAIN_TIME || d->domain == TOF_DOMAIN_VELOCITY) &&
               (d->domain == TOF_DOMAIN_TIME || (d->bin_radius == 0 && d->shrink_k == 1.f)) &&
               std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
     // work-list entries (tasks of a pass over fully occupied planes) are 32-bit indices
@@ -688,6 +701,8 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->task0, P * B));
     TOF_TRY(alloc_t(c, a, &c->tasks, pl.task_cap));
     TOF_TRY(alloc_t(c, a, &c->fwd, pl.task_cap));
+    c->wide = nullptr;
+    if (shrink_mix(*d)) TOF_TRY(alloc_t(c, a, &c->wide, 5 * P));
     TOF_TRY(alloc_t(c, a, &c->shv, 2 * pl.task_cap));
     TOF_TRY(alloc_t(c, a, &c->term, pl.term_cap));
     TOF_TRY(alloc_t(c, a, &c->rays, 2 * pl.ray_cap));
@@ -733,7 +748,8 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     s.include_direct = d->include_direct;
     s.debug_stage = d->debug_stage;
     s.br = d->bin_radius;
-    s.shrink_k = d->shrink_k;
+    s.mw = wide_trees(*d);
+    s.shrink_k = s.mw > 0 ? d->shrink_k : 1.f;   // R = 0: no tree samples the wide gate
     s.domain = d->domain;
     s.P = (int)P;
     s.B = B;
@@ -1080,7 +1096,9 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     const int fin_new = c->fin_prev == 2 ? 3 : 2;
     HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
     a.counters = c->counters + (size_t)TOF_K_INITIAL * kBank;
-    tofh::launch_initial(a, can, c->pt, c->direct, st);
+    ResSet wide{};
+    wide.rec = c->wide;
+    tofh::launch_initial(a, can, wide, c->pt, c->direct, st);
     if (c->s.gate_en && c->s.shrink_k > 1.f) {
         // shrink mapping of the gate reservoirs, in chunks of the spatial
         // pass's task count (at most 2 visibility segments per pixel)
@@ -1088,12 +1106,23 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         const size_t ct = pl.ct[1], NQ = tofd::kRaySubQueues;
         const tofd::RayQueue qs{c->rays, c->ray_count, (uint32_t)(2 * ct / NQ)};
         float* kill = (float*)(can.rec + (size_t)c->s.n_bins * P * 5);
-        for (size_t p0 = 0; p0 < P; p0 += ct) {
-            tofh::launch_fill_u32(c->ray_count, 0u, (size_t)tofd::kRaySubQueues * tofd::kCounterStride, st);
-            tofh::launch_shrink(a, can, p0, std::min(ct, P - p0), qs, pl.grid[1], st);
-            tofh::launch_vis(a, 0, qs, kill, pl.vis_grid[1], st);
+        if (c->wide) {   // R < 1: merge of the gate and the shrunk wide-gate samples
+            const tofd::RayQueue q4{c->rays, c->ray_count, (uint32_t)(4 * ct / NQ)};
+            for (size_t p0 = 0; p0 < P; p0 += ct) {
+                const size_t np = std::min(ct, P - p0);
+                tofh::launch_fill_u32(c->ray_count, 0u, (size_t)tofd::kRaySubQueues * tofd::kCounterStride, st);
+                tofh::launch_shrink_mix(a, can, wide, p0, np, q4, c->fwd, pl.grid[1], st);
+                tofh::launch_vis(a, 0, q4, (float*)c->fwd, pl.vis_grid[1], st);
+                tofh::launch_shrink_mix_fin(a, can, wide, p0, np, c->fwd, st);
+            }
+        } else {
+            for (size_t p0 = 0; p0 < P; p0 += ct) {
+                tofh::launch_fill_u32(c->ray_count, 0u, (size_t)tofd::kRaySubQueues * tofd::kCounterStride, st);
+                tofh::launch_shrink(a, can, p0, std::min(ct, P - p0), qs, pl.grid[1], st);
+                tofh::launch_vis(a, 0, qs, kill, pl.vis_grid[1], st);
+            }
+            tofh::launch_shrink_fin(a, can, st);
         }
-        tofh::launch_shrink_fin(a, can, st);
     }
     HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
     const bool record_items = c->timing && c->item_used + 4 <= c->item_slots;

@@ -134,6 +134,7 @@ struct Sens {
     int shift_mode, include_direct, debug_stage;
     int br;                  // bin-axis reuse radius (0 = off)
     float shrink_k;          // shrink mapping of initial gate samples (1 = off)
+    int mw;                  // path trees sampling the wide gate (R x M_init; all = R 1, shrink only)
     int domain;              // planes over 0: path length, 1: path velocity
     int P, B, mask_words;
     uint64_t seed;
@@ -209,7 +210,8 @@ __device__ __forceinline__ Rec load_rec(const ResSet& R, size_t idx, float& W) {
 // Philox4x64-10 (Salmon et al., SC'11) and the stream layout
 // counter = (pixel, frame, pass << 56 | a << 32 | b, 0), key = (seed, 0)
 // ---------------------------------------------------------------------------
-enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4, PASS_BIN = 16 };
+enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPATIAL = 4, PASS_BIN = 16,
+       PASS_SHRINK_MIX = 17 };
 
 struct Draw {
     uint64_t x[4];
@@ -1110,7 +1112,11 @@ __device__ __forceinline__ float plane_lo(const Sens& s, int pl) {
 __device__ __forceinline__ float plane_hi(const Sens& s, int pl) {
     return pl < s.n_bins ? s.t0 + (float)(pl + 1) * s.bw : s.gate_c + 0.5f * s.gate_w;
 }
-__device__ __forceinline__ float plane_width(const Sens& s, int pl) { return pl < s.n_bins ? s.bw : s.gate_w; }
+// plane n_bins + 1 stands for the wide gate of the shrink mapping (shrink_k
+// times the gate, same centre), the domain of the wide-gate samples
+__device__ __forceinline__ float plane_width(const Sens& s, int pl) {
+    return pl < s.n_bins ? s.bw : (pl == s.n_bins + 1 ? s.shrink_k * s.gate_w : s.gate_w);
+}
 // the wide gate of the shrink mapping: shrink_k times the gate, same centre
 __device__ __forceinline__ bool in_rough_gate(const Sens& s, float l) {
     const float h = 0.5f * s.shrink_k * s.gate_w;
@@ -1122,7 +1128,8 @@ __device__ __forceinline__ bool in_plane(const Sens& s, int pl, float l) {
 // the same, with the gate plane of the frame held in slot G
 __device__ __forceinline__ bool in_plane_at(const Sens& s, const SlotDev& G, int pl, float l) {
     if (pl < s.n_bins) return in_plane(s, pl, l);
-    return l >= G.gate_c - 0.5f * s.gate_w && l < G.gate_c + 0.5f * s.gate_w;
+    const float h = pl == s.n_bins + 1 ? 0.5f * s.shrink_k * s.gate_w : 0.5f * s.gate_w;
+    return l >= G.gate_c - h && l < G.gate_c + h;
 }
 // Delta l of a temporal shift from the previous frame into the current one
 // (Sec. 4.1, time-gate shifting): the gate's move; bins do not move

@@ -60,7 +60,10 @@ struct GBufOut {
     float4* n;
 };
 void launch_gbuffer(const FrameArgs& a, GBufOut out, hipStream_t st);
-void launch_initial(const FrameArgs& a, tofd::ResSet can, float* pt, float2* direct, hipStream_t st);
+// wide: the wide-gate reservoirs of the shrink mapping with R < 1 (rec only,
+// P records), or rec == nullptr
+void launch_initial(const FrameArgs& a, tofd::ResSet can, tofd::ResSet wide, float* pt, float2* direct,
+                    hipStream_t st);
 void launch_reproject(const FrameArgs& a, const tofd::ResSet& can, const tofd::ResSet& prev, int* prev_pix,
                       float* M_out, hipStream_t st);
 void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, int* nb, float* M_out,
@@ -107,6 +110,14 @@ void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tof
 void launch_shrink(const FrameArgs& a, const tofd::ResSet& can, size_t p0, size_t np, const tofd::RayQueue& q,
                    unsigned grid, hipStream_t st);
 void launch_shrink_fin(const FrameArgs& a, const tofd::ResSet& can, hipStream_t st);
+// Shrink mapping with R < 1: per pixel of [p0, p0 + np) the expansion of the
+// gate sample and the shrink of the wide sample (at most 4 visibility
+// segments, owners 4 t and 4 t + 1 in scr as floats), then, after their
+// visibility, the GRIS merge of the two into the gate.
+void launch_shrink_mix(const FrameArgs& a, const tofd::ResSet& can, const tofd::ResSet& wide, size_t p0, size_t np,
+                       const tofd::RayQueue& q, float4* scr, unsigned grid, hipStream_t st);
+void launch_shrink_mix_fin(const FrameArgs& a, const tofd::ResSet& can, const tofd::ResSet& wide, size_t p0,
+                           size_t np, const float4* scr, hipStream_t st);
 // Records and mask bits of plane pl copied from `in` to `out` (the gate plane
 // across the bin-axis pass).
 void launch_copy_plane(const FrameArgs& a, const tofd::ResSet& in, const tofd::ResSet& out, int pl, hipStream_t st);

@@ -193,6 +193,22 @@ def test_shrink_mapping_parity():
         assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
 
 
+def test_shrink_mapping_mix_parity():
+    """Shrink mapping with R < 1 (Sec. 4.4.2): a fraction of the path trees
+    samples the wide gate, the rest the gate; the GRIS merge of the gate
+    sample (expanded into the wide gate for its MIS weight) and the shrunk
+    wide sample.  Sphere (R = 1/2, canonical stage), box (K = 20, R = 1/3,
+    then temporal and spatial reuse) and the box under the naive shift
+    (identity map)."""
+    gs, os_ = _run_pair(scenes.lambert_sphere_interior(width=40, height=24, frames=2, shrink_k=5.0, shrink_r=0.5,
+                                                       m_init=2, debug_stage=scenes.STAGE_CANONICAL))
+    assert gs["shifts"] > 0 and abs(gs["shifts"] - os_["shifts"]) <= 0.002 * os_["shifts"] + 2
+    for kw in (dict(gate_width=0.2, shrink_k=20.0), dict(shrink_k=5.0, gate_width=0.2, shift_mode=scenes.SHIFT_NAIVE)):
+        gs, os_ = _run_pair(scenes.cornell_box(frames=3, m_init=3, shrink_r=1.0 / 3.0, **kw))
+        for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+            assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
+
+
 def test_glossy_dynamic_crop_parity():
     """A 64x64 crop of the 512^2 dynamic glossy scene (256 bins + gate,
     moving spheres, temporal + spatial reuse)."""
