@@ -289,6 +289,23 @@ def test_doppler_parity():
         assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
 
 
+def test_doppler_nlos_parity():
+    """Velocity domain with the orthographic scan and the confocal laser
+    spot (its velocity is that of the relay-wall point it lies on): the
+    hidden torus translates and spins, the wall is at rest; 64 bins over
+    u in [-0.5, 0.5), temporal and spatial reuse."""
+    w = scenes.nlos_confocal(scan=32, frames=2, torus_nu=125, torus_nv=50, domain=scenes.DOMAIN_VELOCITY,
+                             n_bins=64, bin_t0=-0.5, bin_width=1.0 / 64.0)
+    vel = np.zeros((w.scene.num_objects, 6), dtype=np.float32)
+    vel[1] = (0.15, 0.0, -0.1, 0.0, 0.5, 0.0)
+    for fr in w.frames:
+        fr.velocities = vel
+    gs, os_ = _run_pair(w, check=("hist", "pt_hist"))
+    assert gs["shifts"] > 0
+    for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+        assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
+
+
 def test_doppler_receding_plane_closed_form():
     """A Lambertian plane at depth d receding at speed s under a co-located
     camera and light: every velocity bin of width du whose ring lies in the
