@@ -150,8 +150,8 @@ def cpu_baseline(width, first, count, crop):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in the design notes, not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (sharding across GPUs "
+                                   "is not built)"}))
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
