@@ -40,6 +40,11 @@ F_NEWTON_SETUP = 600    # per solve: chart points, source/destination evaluation
 F_SHIFT = 300           # per shift: replayed BSDF sampling/evaluation, Jacobian and target
 SPLAT_BYTES = 4 + 4 + 4 + 0.125   # per (pixel, plane): PT deposit read, two histogram writes, mask bits
 REC_HEAD_BYTES = 8      # per non-empty (pixel, plane): W and phat
+# k_merge per item: the item, its first task, the winner's record read and
+# written, the winner's shifted fields; per task: its forward terms and its K
+# MIS terms (4 B each)
+MERGE_ITEM_BYTES = 8 + 4 + 80 + 80 + 32
+MERGE_TASK_BYTES = 16
 
 
 def sources_digest():
@@ -274,6 +279,20 @@ def main():
                                "frac": round(sp_bytes / sp_s / 1e9 / HBM_PEAK_GBS, 4),
                                "bytes_per_launch": int(sp_bytes), "occupancy": round(occ, 5),
                                "avg_launch_ms": round(sp_s * 1e3, 4)}
+
+    # ... and the resampling merge, from its algorithmic bytes per item and task
+    merge = {}
+    for pas, K in (("temporal", 1), ("spatial", max(int(sensor.spatial_k), 1))):
+        g = pas + "_merge"
+        items, tasks = wi.get(pas + "_items", 0), wi.get(pas + "_tasks", 0)
+        if kms.get(g) and items:
+            mb = items * MERGE_ITEM_BYTES + tasks * (MERGE_TASK_BYTES + 4 * K)
+            gbs = mb / (kms[g] * 1e-3) / 1e9
+            merge[pas] = {"achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "bytes_per_frame": int(mb / max(args.steps, 1)),
+                          "ms_per_frame": round(kms[g] / max(args.steps, 1), 3)}
+    if merge:
+        result["merge_hbm"] = merge
 
     # equal RMSE against plain ToF PT on the same GPU
     if not args.no_equal_rmse:

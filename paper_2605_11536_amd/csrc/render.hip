@@ -690,7 +690,13 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
     if (i0 >= ni) return;
     const uint32_t n = ni - i0 > ci ? i0 + ci : ni;
     const uint32_t tb = win[0];
-    for (uint32_t it = i0 + blockIdx.x * 256 + threadIdx.x; it < n; it += gridDim.x * 256) {
+    const int lane = (int)__lane_id();
+    // wave-uniform loop (the mask reduction below needs every lane)
+    for (uint32_t it0 = i0 + blockIdx.x * 256 + (threadIdx.x & ~63u); it0 < n; it0 += gridDim.x * 256) {
+        const uint32_t it = it0 + (uint32_t)lane;
+        // mask word and bit this lane sets (0xFFFFFFFF: none)
+        uint32_t mkey = 0xFFFFFFFFu, mbit = 0u;
+        if (it < n) {
         const uint2 item = items[it];
         const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
         const uint32_t cm = item.y >> 16;
@@ -702,6 +708,10 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
         float ws = 0.f, sel_phat = 0.f;
         int sel = -1;
         uint32_t sel_t = 0;
+        // one Philox draw serves four candidates: drawn when its first
+        // candidate with a weight needs it
+        Draw ug;
+        int ug_id = -1;
         for (int c = 0; c < ncand; ++c) {
             if (!((cm >> c) & 1u)) continue;
             const uint32_t t = t0 + (uint32_t)__popc(cm & ((1u << c) - 1u));
@@ -713,11 +723,17 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
             const float w = ((c == 0 ? mq * phq : fw.z) / den) * phq * fw.w * fw.y;
             if (c > 0 && !(w > 0.f)) continue;
             float u;
-            if (mode == 0) u = ut.u(c);
-            else if (mode == 1)
-                u = philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + c / 4)).u(c % 4);
-            else
-                u = philox(s.seed, fp, a.frame, PASS_BIN, 0, (uint64_t)(pl * 4 + c / 4)).u(c % 4);
+            if (mode == 0) {
+                u = ut.u_sel(c);
+            } else {
+                if (c / 4 != ug_id) {
+                    ug_id = c / 4;
+                    ug = mode == 1 ? philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2,
+                                            (uint64_t)(pl * 2 + ug_id))
+                                   : philox(s.seed, fp, a.frame, PASS_BIN, 0, (uint64_t)(pl * 4 + ug_id));
+                }
+                u = ug.u_sel(c % 4);
+            }
             ws += w;
             if (u * ws < w) {
                 sel = c;
@@ -742,8 +758,21 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
                 x.phat = sel_phat;
                 store_rec(out, oidx, x, ws / sel_phat);
             }
-            atomicOr(out.mask + (size_t)(pl >> 5) * P + pix, 1u << (pl & 31));
+            mkey = (uint32_t)(pl >> 5) * (uint32_t)P + (uint32_t)pix;
+            mbit = 1u << (pl & 31);
         }
+        }
+        // Items of one pixel are consecutive, so lanes that set bits of the
+        // same mask word form runs: OR the bits down each run (a segmented
+        // reduction over equal keys) and let its first lane write them with
+        // one atomic instead of one per item.
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t k2 = __shfl_down(mkey, d, 64);
+            const uint32_t b2 = __shfl_down(mbit, d, 64);
+            if (lane + d < 64 && k2 == mkey) mbit |= b2;
+        }
+        const uint32_t kprev = __shfl_up(mkey, 1, 64);
+        if (mbit && (lane == 0 || kprev != mkey)) atomicOr(out.mask + mkey, mbit);
     }
 }
 

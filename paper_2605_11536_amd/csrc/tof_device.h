@@ -216,6 +216,12 @@ enum { PASS_JITTER = 0, PASS_BSDF = 1, PASS_RIS = 2, PASS_TEMPORAL = 3, PASS_SPA
 struct Draw {
     uint64_t x[4];
     __device__ __forceinline__ float u(int i) const { return (float)(x[i] >> 40) * (1.0f / 16777216.0f); }
+    // the same for an index known only at run time, by selects (an indexed
+    // read of x would put the draw in scratch memory)
+    __device__ __forceinline__ float u_sel(int i) const {
+        const uint64_t v = i == 0 ? x[0] : (i == 1 ? x[1] : (i == 2 ? x[2] : x[3]));
+        return (float)(v >> 40) * (1.0f / 16777216.0f);
+    }
 };
 
 __device__ __forceinline__ Draw philox(uint64_t seed, uint64_t c0, uint64_t c1, uint64_t pass, uint64_t a,
