@@ -20,6 +20,10 @@ def _workloads():
         # bins around the gate with bin-axis reuse, and the shrink mapping
         "box_bins": scenes.cornell_box(frames=3, n_bins=16, bin_t0=2.6, bin_width=0.1, bin_radius=2, seed=3),
         "box_shrink": scenes.cornell_box(frames=3, shrink_k=10.0, seed=5),
+        # the shrink mapping with R < 1, and a Doppler (path-velocity) stream
+        "box_shrink_mix": scenes.cornell_box(frames=3, m_init=3, shrink_k=20.0, shrink_r=1.0 / 3.0, gate_width=0.2,
+                                             seed=9),
+        "doppler": scenes.doppler_boxes(frames=3, temporal=1, seed=7),
     }
 
 
