@@ -161,7 +161,7 @@ typedef struct {
     uint64_t rays;                   /* closest-hit + shadow rays traced */
     uint64_t frames;                 /* frames rendered */
     uint64_t bvh_overflow;           /* traversal stack overflows (must be 0) */
-    uint64_t node_visits;            /* BVH internal nodes visited (two box tests each) */
+    uint64_t node_visits;            /* BVH internal nodes visited (four child-box tests each) */
     uint64_t tri_tests;              /* ray/triangle tests */
     uint64_t bad_records;            /* reservoir records rejected as malformed (must be 0) */
 } tof_stats;
@@ -191,7 +191,9 @@ tof_status tof_scene_upload(tof_ctx* ctx, const tof_scene_desc* scene);
  * planes mainly through the reservoirs. */
 tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
 
-/* Render one frame asynchronously on `stream`: BVH build for the frame's
+/* Render one frame asynchronously on `stream`, in the order of the ReSTIR
+ * pipeline (Sec. 3.2.4: initial candidates, temporal reuse, spatial reuse,
+ * final shading; Sec. 6 real-time temporal reuse): BVH refit for the frame's
  * transforms, G-buffer, path trees + initial RIS, temporal reuse (when a
  * previous frame exists), spatial rounds, splat.  Outputs are device float32
  * arrays owned by the caller, plane-major, each value divided by its gate or
@@ -211,7 +213,9 @@ tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
 tof_status tof_render_frame(tof_ctx* ctx, const tof_frame_desc* frame, float* out_image, float* out_hist,
                             float* out_pt_image, float* out_pt_hist, void* stream);
 
-/* Drop the temporal history: the next frame renders without temporal reuse. */
+/* Drop the temporal history (the previous frame's final reservoirs that
+ * temporal reuse resamples, Sec. 3.2.4 and Sec. 6): the next frame renders
+ * without temporal reuse.  Waits for the context's last frame. */
 tof_status tof_reservoirs_reset(tof_ctx* ctx);
 
 /* Accumulated counters (waits for the context's last frame). */
@@ -249,7 +253,7 @@ tof_status tof_debug_set_history(tof_ctx* ctx, const tof_history_desc* history);
 /* Per-kernel GPU timing with HIP events recorded on the render stream around
  * each launch (off by default).  Kernel ids index tof_kernel_times. */
 enum {
-    TOF_K_BVH = 0,        /* world transform + LBVH build of a moved frame */
+    TOF_K_BVH = 0,        /* world vertices + refit of the two-level BVH of a moved frame */
     TOF_K_GBUFFER,
     TOF_K_INITIAL,        /* path trees + per-plane RIS + plain PT deposit */
     TOF_K_TEMPORAL_PREP,  /* reprojection + work list */
@@ -337,7 +341,9 @@ tof_status tof_server_submit(tof_server* server, int stream_id, const tof_frame_
 tof_status tof_server_query(tof_server* server, uint64_t ticket, int* done);
 
 /* Block until the frame finished; returns its status and retires the ticket.
- * TOF_ERR_NOT_READY while its stream waits for admission. */
+ * TOF_ERR_NOT_READY while its stream waits for admission.  While a wait is
+ * blocked on a ticket, tof_server_query on it reports the state but leaves the
+ * ticket to the wait, which retires it. */
 tof_status tof_server_wait(tof_server* server, uint64_t ticket);
 
 /* Close a stream; its queued frames still run.  Its memory is freed once no

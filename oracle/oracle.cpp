@@ -1860,6 +1860,35 @@ int orc_trace(void* ctx, const double o3[3], const double d3[3], int brute_force
     return h.prim;
 }
 
+int orc_occluded(void* ctx, const double o3[3], const double d3[3], double tmax) {
+    Oracle* o = (Oracle*)ctx;
+    V3 org(o3[0], o3[1], o3[2]), dir = normalize(V3(d3[0], d3[1], d3[2]));
+    return o->occluded(o->fg[0], org, dir, tmax) ? 1 : 0;
+}
+
+void orc_bsdf(void* ctx, int obj, const double n[3], const double wi[3], const double* wo, int count, double* out) {
+    Oracle* o = (Oracle*)ctx;
+    const V3 nn = normalize(V3(n[0], n[1], n[2])), wn = normalize(V3(wi[0], wi[1], wi[2]));
+    for (int i = 0; i < count; ++i)
+        out[i] = o->bsdf(obj, nn, wn, normalize(V3(wo[3 * i], wo[3 * i + 1], wo[3 * i + 2])));
+}
+
+int orc_bsdf_sample(void* ctx, int obj, const double n[3], const double wi[3], const double* u, int count, double* wo,
+                    double* pdf) {
+    Oracle* o = (Oracle*)ctx;
+    const V3 nn = normalize(V3(n[0], n[1], n[2])), wn = normalize(V3(wi[0], wi[1], wi[2]));
+    int accepted = 0;
+    for (int i = 0; i < count; ++i) {
+        V3 w;
+        double p = 0.0;
+        const bool ok = o->bsdf_sample(obj, nn, wn, u[2 * i], u[2 * i + 1], w, p);
+        wo[3 * i] = w.x; wo[3 * i + 1] = w.y; wo[3 * i + 2] = w.z;
+        pdf[i] = ok ? p : 0.0;
+        accepted += ok ? 1 : 0;
+    }
+    return accepted;
+}
+
 int orc_chart(void* ctx, int obj, const double xi[2], double out[12]) {
     Oracle* o = (Oracle*)ctx;
     ChartEval c = o->chart(o->fg[0], obj, xi[0], xi[1]);

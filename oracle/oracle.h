@@ -105,6 +105,21 @@ int orc_load_frame(void* ctx, const orc_frame* frame);
  * first, then spheres) or -1; out = {t, object, xi0, xi1}. */
 int orc_trace(void* ctx, const double o[3], const double d[3], int brute_force, double out[4]);
 
+/* Any-hit query in the current frame, the one shadow rays use: 1 if a
+ * primitive is hit at t in (0, tmax) along the normalized direction d. */
+int orc_occluded(void* ctx, const double o[3], const double d[3], double tmax);
+
+/* BSDF values f_s(wi, wo[i]) of object obj's material at a point with normal
+ * n, for count directions wo [count*3] (directions normalized inside; wi
+ * points away from the surface). */
+void orc_bsdf(void* ctx, int obj, const double n[3], const double wi[3], const double* wo, int count, double* out);
+
+/* The BSDF sampler of the path trees and the random replay, applied to count
+ * uniform pairs u [count*2]: wo [count*3] and its solid-angle density pdf
+ * [count] (0 where the sample is rejected).  Returns the accepted count. */
+int orc_bsdf_sample(void* ctx, int obj, const double n[3], const double wi[3], const double* u, int count, double* wo,
+                    double* pdf);
+
 /* Position, chart Jacobian and normal of chart point (obj, xi) in the current
  * frame.  out = {p(3), J_u(3), J_v(3), n(3)}.  Returns 1 if xi is on the chart. */
 int orc_chart(void* ctx, int obj, const double xi[2], double out[12]);

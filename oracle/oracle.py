@@ -78,6 +78,12 @@ def lib():
                                             _f32p, _f32p, _u32p]
         _lib.orc_vel_eval.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p, _f64p, _f64p, _f64p, C.c_double,
                                       _f64p]
+        _lib.orc_occluded.restype = C.c_int
+        _lib.orc_occluded.argtypes = [C.c_void_p, _f64p, _f64p, C.c_double]
+        _lib.orc_bsdf.restype = None
+        _lib.orc_bsdf.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p, _f64p, C.c_int, _f64p]
+        _lib.orc_bsdf_sample.restype = C.c_int
+        _lib.orc_bsdf_sample.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p, _f64p, C.c_int, _f64p, _f64p]
         _lib.orc_wrs.restype = C.c_int
         _lib.orc_wrs.argtypes = [_f64p, _f64p, C.c_int, _f64p]
     return _lib
@@ -246,6 +252,31 @@ class Oracle:
         out = np.zeros(4)
         prim = lib().orc_trace(self.h, _p(o, _f64p), _p(d, _f64p), int(brute), _p(out, _f64p))
         return prim, out
+
+    def occluded(self, o, d, tmax):
+        o = np.ascontiguousarray(o, dtype=np.float64)
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        return bool(lib().orc_occluded(self.h, _p(o, _f64p), _p(d, _f64p), float(tmax)))
+
+    def bsdf(self, obj, n, wi, wo):
+        """f_s(wi, wo) for directions wo [N, 3]."""
+        n = np.ascontiguousarray(n, dtype=np.float64)
+        wi = np.ascontiguousarray(wi, dtype=np.float64)
+        wo = np.ascontiguousarray(np.reshape(wo, (-1, 3)), dtype=np.float64)
+        out = np.zeros(wo.shape[0])
+        lib().orc_bsdf(self.h, int(obj), _p(n, _f64p), _p(wi, _f64p), _p(wo, _f64p), wo.shape[0], _p(out, _f64p))
+        return out
+
+    def bsdf_sample(self, obj, n, wi, u):
+        """Sampled directions [N, 3] and densities [N] (0 = rejected) for uniforms u [N, 2]."""
+        n = np.ascontiguousarray(n, dtype=np.float64)
+        wi = np.ascontiguousarray(wi, dtype=np.float64)
+        u = np.ascontiguousarray(np.reshape(u, (-1, 2)), dtype=np.float64)
+        wo = np.zeros((u.shape[0], 3))
+        pdf = np.zeros(u.shape[0])
+        lib().orc_bsdf_sample(self.h, int(obj), _p(n, _f64p), _p(wi, _f64p), _p(u, _f64p), u.shape[0],
+                              _p(wo, _f64p), _p(pdf, _f64p))
+        return wo, pdf
 
     def chart(self, obj, xi):
         xi = np.ascontiguousarray(xi, dtype=np.float64)

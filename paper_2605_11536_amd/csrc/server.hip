@@ -66,9 +66,11 @@ struct Request {
     int stream = -1;
     tof_frame_desc frame{};
     std::vector<float> xforms;
+    std::vector<float> velocities;   // copy of the caller's array (empty = NULL): a held frame outlives it
     float* out[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t done = nullptr;
     bool dispatched = false;
+    int waiters = 0;                 // tof_server_wait calls blocked on `done`: only they retire the ticket
     tof_status status = TOF_OK;
 };
 
@@ -307,6 +309,11 @@ tof_status tof_server_submit(tof_server* s, int stream_id, const tof_frame_desc*
     r->frame = *frame;
     r->xforms.assign(frame->object_xforms, frame->object_xforms + 12 * (size_t)st.scene->desc.num_objects);
     r->frame.object_xforms = r->xforms.data();
+    if (frame->object_velocities) {
+        r->velocities.assign(frame->object_velocities,
+                             frame->object_velocities + 6 * (size_t)st.scene->desc.num_objects);
+        r->frame.object_velocities = r->velocities.data();
+    }
     r->out[0] = out_image;
     r->out[1] = out_hist;
     r->out[2] = out_pt_image;
@@ -320,11 +327,11 @@ tof_status tof_server_submit(tof_server* s, int stream_id, const tof_frame_desc*
     return TOF_OK;
 }
 
-tof_status tof_server_query(tof_server* s, uint64_t ticket, int* done) {
-    if (!s || !done) return TOF_ERR_INVALID_ARG;
-    std::lock_guard<std::mutex> lock(s->mu);
-    auto it = s->requests.find(ticket);
-    if (it == s->requests.end()) return TOF_ERR_INVALID_ARG;
+// Poll a dispatched request under the server lock.  A finished request is
+// retired (event destroyed, ticket erased) unless a tof_server_wait is blocked
+// on its event, or `retire` is false: the waiter retires it.
+static tof_status poll_locked(tof_server* s, std::map<uint64_t, std::unique_ptr<Request>>::iterator it, int* done,
+                              bool retire) {
     Request& r = *it->second;
     *done = 0;
     if (!r.dispatched) return TOF_OK;
@@ -335,10 +342,19 @@ tof_status tof_server_query(tof_server* s, uint64_t ticket, int* done) {
         if (q != hipSuccess) st = TOF_ERR_DEVICE;
     }
     *done = 1;
+    if (!retire || r.waiters > 0) return st;
     (void)hipEventDestroy(r.done);
     s->requests.erase(it);
     if (!s->closed.empty()) admit_waiting(s);
     return st;
+}
+
+tof_status tof_server_query(tof_server* s, uint64_t ticket, int* done) {
+    if (!s || !done) return TOF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return TOF_ERR_INVALID_ARG;
+    return poll_locked(s, it, done, true);
 }
 
 tof_status tof_server_wait(tof_server* s, uint64_t ticket) {
@@ -349,11 +365,18 @@ tof_status tof_server_wait(tof_server* s, uint64_t ticket) {
         auto it = s->requests.find(ticket);
         if (it == s->requests.end()) return TOF_ERR_INVALID_ARG;
         if (!it->second->dispatched) return TOF_ERR_NOT_READY;   // its stream is not admitted yet
+        it->second->waiters++;    // keeps the event alive while this thread blocks on it
         ev = it->second->done;
     }
-    if (hipEventSynchronize(ev) != hipSuccess) return TOF_ERR_DEVICE;
+    const hipError_t e = hipEventSynchronize(ev);
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return TOF_ERR_INVALID_ARG;   // cannot happen: only waiters retire it now
+    it->second->waiters--;
     int done = 0;
-    return tof_server_query(s, ticket, &done);
+    const tof_status st = poll_locked(s, it, &done, it->second->waiters == 0);
+    if (e != hipSuccess) return TOF_ERR_DEVICE;
+    return st;
 }
 
 tof_status tof_server_close(tof_server* s, int stream_id) {

@@ -25,27 +25,16 @@ from paper_2605_11536_amd import scenes
 
 pytestmark = pytest.mark.gpu
 
-REL = 1e-4
+from parity_util import REL, compare, describe
+
 MIN_FRAC = 0.999
 
 
-def _frac_close(g, o):
-    g = np.asarray(g, dtype=np.float64)
-    o = np.asarray(o, dtype=np.float64)
-    scale = max(float(np.abs(o).max()), 1e-30)
-    close = np.abs(g - o) <= REL * np.maximum(np.abs(o), 1e-3 * scale)
-    return float(close.mean()), close
-
-
 def _assert_parity(g, o, what):
-    frac, close = _frac_close(g, o)
-    gs, os_ = float(np.sum(g)), float(np.sum(o))
-    d = (np.asarray(g, dtype=np.float64) - np.asarray(o, dtype=np.float64))[~close]
-    z = float(d.sum() / math.sqrt(float((d * d).sum()))) if d.size else 0.0
-    print(f"{what}: {frac * 100:.4f}% within {REL} ({d.size} outside, sign z {z:+.2f}), "
-          f"sums gpu {gs:.6g} oracle {os_:.6g}", flush=True)
-    assert frac >= MIN_FRAC, f"{what}: only {frac:.5f} of pixels within {REL}"
-    assert abs(z) <= 3.0, f"{what}: discrepant entries biased (z = {z})"
+    r = compare(g, o)
+    print(describe(what, r), flush=True)
+    assert r["frac_support"] >= MIN_FRAC, f"{what}: only {r['frac_support']:.5f} of the support within {REL}"
+    assert abs(r["z"]) <= 3.0, f"{what}: discrepant entries biased (z = {r['z']})"
 
 
 def _run_pair(w, nframes=None, check=("image", "pt_image", "hist", "pt_hist"), inject=True, gate_step=0.0):
@@ -96,8 +85,9 @@ def test_free_running_drift_is_small():
     for fr in w.frames:
         gpu.render(fr)
         g, o = gpu.fetch()["image"], orc.render(fr)["image"]
-        frac, _ = _frac_close(g, o)
-        print(f"free-running f{fr.index}: {frac * 100:.3f}% within {REL}", flush=True)
+        r = compare(g, o)
+        print(describe(f"free-running f{fr.index}", r), flush=True)
+        frac = r["frac_support"]
         assert frac >= 0.99
         assert abs(float(g.sum()) - float(o.sum())) <= 1e-3 * float(o.sum())
     gs, os_ = gpu.stats(), orc.stats()
@@ -158,10 +148,9 @@ def _run_chain(w, keys):
         gpu.render(fr)
         g, o = gpu.fetch(), orc.render(fr)
         for key in keys:
-            frac, close = _frac_close(g[key], o[key])
-            d = (g[key].astype(np.float64) - o[key])[~close]
-            z = float(d.sum() / math.sqrt(float((d * d).sum()))) if d.size else 0.0
-            print(f"{key}: {frac * 100:.4f}% within {REL}, sign z {z:+.2f}", flush=True)
+            r = compare(g[key], o[key])
+            print(describe(key, r), flush=True)
+            frac, z = r["frac_support"], r["z"]
             assert frac >= 0.995 and abs(z) <= 3.0
             assert abs(float(g[key].sum()) - float(o[key].sum())) <= 1e-3 * float(np.abs(o[key]).sum())
     gs, os_ = gpu.stats(), orc.stats()
@@ -244,9 +233,9 @@ def test_glossy_dynamic_full_size_sampled_parity():
             if f == 0:
                 _assert_parity(gv, ov, f"glossy full f{f} {key}")
             else:
-                frac, _ = _frac_close(gv, ov)
-                print(f"glossy full f{f} {key}: {frac * 100:.4f}% within {REL} (free running)", flush=True)
-                assert frac >= 0.99
+                r = compare(gv, ov)
+                print(describe(f"glossy full f{f} {key} (free running)", r), flush=True)
+                assert r["frac_support"] >= 0.99
                 assert abs(float(gv.sum()) - float(ov.sum())) <= 1e-3 * abs(float(ov.sum())) + 1e-9
     st = gpu.stats()
     assert st["bvh_overflow"] == 0 and st["bad_records"] == 0

@@ -1,6 +1,8 @@
 """Serving (tof_server_*): frames of several streams in flight together give
 the same results as each stream rendered alone, and admission by HBM
 footprint holds streams back until memory frees up."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -68,29 +70,43 @@ def test_streams_in_the_mix_match_alone():
 
 
 def test_admission_waits_for_memory():
+    """Two streams wait for memory with frames held: a box stream and a
+    Doppler stream, whose per-object velocities must outlive the caller's
+    arrays until the held frame is dispatched."""
+    import gc
     from paper_2605_11536_amd.tof import Server, TofError, tof_footprint
     ws = _workloads()
-    a, b = ws["glossy"], ws["box"]
-    fa, fb = tof_footprint(a.scene, a.sensor), tof_footprint(b.scene, b.sensor)
-    srv = Server(hbm_budget_bytes=max(fa, fb) + min(fa, fb) // 2)   # room for one of them
+    a, b, c = ws["glossy"], ws["box"], ws["doppler"]
+    fa, fb, fc = (tof_footprint(w.scene, w.sensor) for w in (a, b, c))
+    assert fb + fc <= fa
+    srv = Server(hbm_budget_bytes=fa + min(fb, fc) // 2)   # room for a, or for b and c
     sa, adm_a = srv.open(a.scene, a.sensor)
     sb, adm_b = srv.open(b.scene, b.sensor)
-    assert adm_a and not adm_b
-    assert srv.info()["waiting"] == 1
-    out_b = srv.outputs(sb)
+    sc, adm_c = srv.open(c.scene, c.sensor)
+    assert adm_a and not adm_b and not adm_c
+    assert srv.info()["waiting"] == 2
+    out_b, out_c = srv.outputs(sb), srv.outputs(sc)
     tb = srv.submit(sb, b.frames[0], out_b)
+    fr_c = dataclasses.replace(c.frames[0], velocities=c.frames[0].velocities.copy())
+    tc = srv.submit(sc, fr_c, out_c)
+    fr_c.velocities[:] = np.nan   # the caller's array is gone or overwritten before the frame runs
+    del fr_c
+    gc.collect()
     with pytest.raises(TofError):
         srv.wait(tb)            # held: its stream is not admitted yet
-    assert not srv.query(tb)
+    assert not srv.query(tb) and not srv.query(tc)
     out_a = srv.outputs(sa)
     srv.wait(srv.submit(sa, a.frames[0], out_a))
-    srv.close_stream(sa)        # frees the memory: b is admitted, its held frame runs
+    srv.close_stream(sa)        # frees the memory: b and c are admitted, their held frames run
     info = srv.info()
-    assert info["admitted"] == 1 and info["waiting"] == 0
-    srv.wait(tb)
-    got = Server.fetch(b.sensor, out_b)
-    ref = _alone(b)[0]
-    for key, v in got.items():
-        assert np.array_equal(v, ref[key]), key
+    assert info["admitted"] == 2 and info["waiting"] == 0
+    for t, w, out, what in ((tb, b, out_b, "box"), (tc, c, out_c, "doppler")):
+        print(f"case held {what} frame 0", flush=True)
+        srv.wait(t)
+        got = Server.fetch(w.sensor, out)
+        ref = _alone(w)[0]
+        for key, v in got.items():
+            assert np.array_equal(v, ref[key]), (what, key)
     srv.close_stream(sb)
+    srv.close_stream(sc)
     srv.close()
