@@ -131,6 +131,15 @@ typedef struct {
                                         technique's density at a gate path comes through the inverse
                                         map, Delta l = K (l - l0) + l0 - l.  round(R m_init) = 0: no
                                         shrink mapping */
+    int32_t round_trip;              /* 1: a path-length-aware shift is kept only if the inverse shift of its
+                                        result (the same Newton iteration from the shifted vertex, Delta l
+                                        negated) converges back to within the reconnection distance
+                                        0.01 s_c of the source's reconnection vertex.  GRIS is unbiased only
+                                        if each shift is a bijection (Sec. 3.2.3); the gauge of Sec. 4.3
+                                        makes the exact root reversible, but the iteration can land on
+                                        another root or fail one way only near paths whose length is
+                                        stationary on the chart (the first return of a confocal scan), which
+                                        biases the reuse upward there.  0: no check; 0 or 1 */
 } tof_sensor_desc;
 
 /* Per-frame poses.  object_xforms: host [num_objects*12], rigid 3x4 row-major

@@ -1037,6 +1037,19 @@ struct Oracle {
             NewtonOut no = newton(FS, FD, obj, x.p.xi, xkm1_ep, p2s_ep, c_src, ykm1_ep, p2d_ep, c_dst, dl0, tol,
                                   s.newton_max_iter);
             if (!no.conv) return R;
+            if (s.round_trip) {
+                // GRIS needs every shift to be a bijection (Sec. 3.2.3); the
+                // gauge makes the exact root reversible (Sec. 4.3), but near a
+                // stationary length the iteration can reach another root or
+                // fail in one direction only.  Keep the shift only if the
+                // inverse shift (destination and source swapped, Delta l
+                // negated) brings the vertex back to the source vertex.
+                NewtonOut bk = newton(FD, FS, obj, no.xi, ykm1_ep, p2d_ep, c_dst, xkm1_ep, p2s_ep, c_src, -dl0, tol,
+                                      s.newton_max_iter);
+                if (!bk.conv) return R;
+                ChartEval cb = chart(FS, obj, bk.xi[0], bk.xi[1]);
+                if (!cb.ok || length(cb.p - p_s.p) > dmin) return R;
+            }
             st.c[ST_NEWTON_CONV]++;
             st.c[ST_NEWTON_ITERS] += (uint64_t)no.iters;
             xi2[0] = no.xi[0];

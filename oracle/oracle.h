@@ -52,6 +52,7 @@ typedef struct {
     double shrink_k;              /* shrink mapping: initial gate samples from a gate shrink_k times wider (1 = off) */
     double shrink_r;              /* fraction R of the path trees sampled from the wide gate (1 = all) */
     int32_t domain;               /* 0: planes over path length; 1: over path velocity u = -dl/dt (Doppler) */
+    int32_t round_trip;           /* keep a Newton shift only if the inverse shift returns to the source vertex */
     uint64_t seed;
 } orc_sensor;
 

@@ -39,7 +39,7 @@ class OrcSensor(C.Structure):
                 ("newton_tol_rel", C.c_double), ("newton_max_iter", C.c_int32),
                 ("j_max", C.c_double), ("shift_mode", C.c_int32), ("include_direct", C.c_int32),
                 ("debug_stage", C.c_int32), ("bin_radius", C.c_int32),
-                ("shrink_k", C.c_double), ("shrink_r", C.c_double), ("domain", C.c_int32),
+                ("shrink_k", C.c_double), ("shrink_r", C.c_double), ("domain", C.c_int32), ("round_trip", C.c_int32),
                 ("seed", C.c_uint64)]
 
 

@@ -136,6 +136,7 @@ struct Sens {
     float shrink_k;          // shrink mapping of initial gate samples (1 = off)
     int mw;                  // path trees sampling the wide gate (R x M_init; all = R 1, shrink only)
     int domain;              // planes over 0: path length, 1: path velocity
+    int round_trip;          // keep a Newton shift only if its inverse returns to the source vertex
     int P, B, mask_words;
     uint64_t seed;
 };
@@ -1685,6 +1686,18 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
             NewtonOut no = newton_solve<NReal, VEL>(S, GS, GD, obj, (NReal)xi0, (NReal)xi1, xk, vxk, p2s, vp2s, c_src,
                                                     yk, vyk, p2d, vp2dn, c_dst, (NReal)dl0, tol, s.max_it);
             if (!no.conv) return R;
+            if (s.round_trip) {
+                // GRIS needs the shift to be a bijection (Sec. 3.2.3): keep it
+                // only if the inverse shift (source and destination swapped,
+                // Delta l negated) brings the vertex back to the source's
+                // reconnection vertex, within the reconnection distance
+                const NewtonOut bk = newton_solve<NReal, VEL>(S, GD, GS, obj, (NReal)no.xi0, (NReal)no.xi1, yk, vyk,
+                                                              p2d, vp2dn, c_dst, xk, vxk, p2s, vp2s, c_src,
+                                                              -(NReal)dl0, tol, s.max_it);
+                if (!bk.conv) return R;
+                const ChartT<NReal> cb = chart_eval_t<NReal>(S, GS, obj, (NReal)bk.xi0, (NReal)bk.xi1);
+                if (!cb.ok || tlen(cb.p - pp) > (NReal)S.dmin) return R;
+            }
             st.c[ST_NEWTON_CONV]++;
             st.c[ST_NEWTON_ITERS] += (uint32_t)no.iters;
             xi0 = no.xi0;

@@ -111,6 +111,7 @@ class Sensor:
     shrink_k: float = 1.0          # shrink mapping of initial gate samples: rough gate K x wider (1 = off)
     shrink_r: float = 1.0          # fraction of the path trees sampled from the wide gate (R < 1: MIS with the gate)
     domain: int = DOMAIN_TIME      # planes over path length (time) or path velocity (Doppler)
+    round_trip: int = 1            # keep a Newton shift only if its inverse returns to the source vertex
     seed: int = 0
 
     def __post_init__(self):
@@ -499,6 +500,33 @@ def nlos_confocal(scan=64, frames=32, seed=0, torus_nu=250, torus_nv=100,
                         ortho_half=np.array([half, half], dtype=f32),
                         light_pos=np.zeros(3, dtype=f32), xforms=xforms_at(f)))
     return Workload(f"nlos_confocal_{scan}", scene, sensor, fr)
+
+
+def nlos_plane(depth=1.0, wall_albedo=0.8, albedo=0.5, intensity=1.0, scan=32, frames=1, seed=0,
+               half_size=5.0, **sensor_kw) -> Workload:
+    """Confocal scan of the relay wall z=0 (2x2, as in nlos_confocal) with a
+    large Lambertian plane z=depth facing it in place of the hidden object:
+    every scan point sees the same wall-plane-wall transient, which has a
+    closed form."""
+    b = _Builder()
+    wall_m = b.material(MAT_LAMBERT, albedo=wall_albedo)
+    hid_m = b.material(MAT_LAMBERT, albedo=albedo)
+    b.grid(_quad((-1, -1, 0), (2, 0, 0), (0, 2, 0)), wall_m)
+    h = half_size
+    b.grid(_quad((-h, -h, depth), (0, 2 * h, 0), (2 * h, 0, 0)), hid_m)
+    xf = np.stack([_identity_xform()] * 2)
+    scene = b.build(xf)
+    kw = dict(width=scan, height=scan, camera_model=CAM_ORTHO, light_model=LIGHT_CONFOCAL,
+              count_camera_leg=0, jitter=0, gate_enabled=0, n_bins=8, bin_t0=2.0 * depth,
+              bin_width=0.1 * depth, n_min=2, n_max=2, m_init=1, light_intensity=intensity, temporal=1,
+              spatial_rounds=1, spatial_k=5, spatial_radius=4, seed=seed)
+    kw.update(sensor_kw)
+    sensor = Sensor(**kw)
+    half = 0.9 * scan / (scan - 1)
+    fr = [Frame(index=f, cam_pos=np.array([0, 0, 0.5 * depth], dtype=f32), cam_fwd=np.array([0, 0, -1], dtype=f32),
+                cam_up=np.array([0, 1, 0], dtype=f32), fov_y_deg=0.0, ortho_half=np.array([half, half], dtype=f32),
+                light_pos=np.zeros(3, dtype=f32), xforms=xf) for f in range(frames)]
+    return Workload(f"nlos_plane_{scan}", scene, sensor, fr)
 
 
 def lambert_sphere_interior(radius=1.0, albedo=0.5, intensity=1.0, width=32, height=32,
