@@ -643,8 +643,12 @@ __global__ void __launch_bounds__(kTB) k_vis_lanes(FrameArgs a, int slot, RayQue
         const float4 r0 = buf[2 * (size_t)i], r1 = buf[2 * (size_t)i + 1];
         const Seg sg{mk(r0.x, r0.y, r0.z), mk(r1.x, r1.y, r1.z), r0.w};
         if (!tr.visible(G, sg)) {
-            const float old = atomicExch(kill + __float_as_uint(r1.w), 0.f);
-            if (old != 0.f) st.c[ST_VISFAIL]++;
+            const uint32_t owner = __float_as_uint(r1.w);
+            const float old = atomicExch(kill + (owner & ~kOwnerNewton), 0.f);
+            if (old != 0.f) {
+                st.c[ST_VISFAIL]++;
+                if (owner & kOwnerNewton) st.c[ST_VISFAIL_NEWTON]++;
+            }
         }
     }
     flush_counters(st, a.counters);

@@ -662,6 +662,14 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     ok = ok && (unsigned long long)d->width * d->height * B *
                        (unsigned long long)(std::max(std::max(d->spatial_k, 2 * d->bin_radius), 1) + 1) <
                    (1ULL << 32);
+    if (ok) {
+        // owners of queued visibility segments (indices of the floats a blocked
+        // ray zeroes: 4 per task, one per MIS term, 20 per pixel) stay below 2^31
+        const size_t P = (size_t)d->width * d->height;
+        const tofh::ChunkPlan pc = tofh::plan_chunks(P, (size_t)B, d->spatial_k, d->bin_radius);
+        ok = 4 * pc.task_cap < ((size_t)1 << 31) && pc.term_cap < ((size_t)1 << 31) &&
+             P * kRecWords < ((size_t)1 << 31);
+    }
     if (!ok) return TOF_ERR_INVALID_ARG;
     if (c->has_sensor) {
         // a move of the gate alone keeps the history: the next temporal reuse
@@ -870,7 +878,7 @@ tof_status tof_get_stats(tof_ctx* c, tof_stats* out) {
     out->newton_attempts = h[ST_NEWTON_ATT];
     out->newton_converged = h[ST_NEWTON_CONV];
     out->newton_iters = h[ST_NEWTON_ITERS];
-    out->newton_paths_ok = h[ST_NEWTON_OK] - (c->s.shift_mode == 1 ? h[ST_VISFAIL] : 0);
+    out->newton_paths_ok = h[ST_NEWTON_OK] - h[ST_VISFAIL_NEWTON];
     out->rays = h[ST_RAYS];
     out->frames = c->frames;
     out->bvh_overflow = h[ST_OVERFLOW];

@@ -466,12 +466,17 @@ struct Hit {
 };
 
 // per-lane event counters; one lane's share of a launch fits 32 bits
-constexpr int kNumCounters = 13;
+constexpr int kNumCounters = 14;
 struct Counters {
     uint32_t c[kNumCounters];
 };
 enum { ST_SHIFTS = 0, ST_SHIFTS_OK, ST_NEWTON_ATT, ST_NEWTON_CONV, ST_NEWTON_ITERS, ST_NEWTON_OK, ST_RAYS, ST_FRAMES,
-       ST_OVERFLOW, ST_NODES, ST_TRIS, ST_BADREC, ST_VISFAIL };
+       ST_OVERFLOW, ST_NODES, ST_TRIS, ST_BADREC, ST_VISFAIL, ST_VISFAIL_NEWTON };
+// A queued segment's owner (the index of the float its blocking zeroes) carries
+// this flag when the shift moved its reconnection vertex by Newton: blocked
+// Newton shifts are counted apart ("actual SR" of the Newton statistics).
+// Owners stay below 2^31 (tof_sensor_set checks the sizes that bound them).
+constexpr uint32_t kOwnerNewton = 0x80000000u;
 
 // Closest hit (any_hit = false; ties in t go to the smaller primitive id) or
 // any hit in (0, tmax) (any_hit = true).  `stack` points at this lane's LDS
@@ -821,8 +826,11 @@ __device__ inline void trace_vis_chunks(const SceneDev& S, const SlotDev& G, con
     uint32_t node = kDone, pmask = 0;
     int4 pcc = make_int4(0, 0, 0, 0);
     auto blocked = [&]() {
-        const float old = atomicExch(kill + owner, 0.f);
-        if (old != 0.f) st.c[ST_VISFAIL]++;
+        const float old = atomicExch(kill + (owner & ~kOwnerNewton), 0.f);
+        if (old != 0.f) {
+            st.c[ST_VISFAIL]++;
+            if (owner & kOwnerNewton) st.c[ST_VISFAIL_NEWTON]++;
+        }
     };
     auto push = [&](uint32_t n) {
         if (sp < depth) {
@@ -1779,6 +1787,8 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
     const float ph = in_plane_at(s, GD, plane, plen) ? C : 0.f;
     if (!(ph > 0.f)) return R;
     // visibility last: only shifts that would contribute pay for rays
+    const bool newton = s.shift_mode == 1 && !replay_only;
+    const uint32_t tag = newton ? kOwnerNewton : 0u;
     const int nseg = replay_only ? 1 : 2 + ((!p2light && src_slot != dst_slot) ? (x.nsfx > 0 ? 2 : 1) : 0);
     uint32_t slot_e[4];
     if (!q.alloc((uint32_t)nseg, slot_e)) {   // the launch sizes its chunk so that this never happens
@@ -1792,7 +1802,7 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
         else if (e == 1) sg = p2light ? seg_light(s, S, GD, dst_pix, pd) : seg_pts(S, pd, p2_d);
         else if (e == 2 && x.nsfx > 0) sg = seg_pts(S, p2_d, sfx_d);
         else sg = seg_light(s, S, GD, dst_pix, x.nsfx > 0 ? sfx_d : p2_d);
-        q.put(e == 0 ? slot_e[0] : (e == 1 ? slot_e[1] : (e == 2 ? slot_e[2] : slot_e[3])), sg, owner);
+        q.put(e == 0 ? slot_e[0] : (e == 1 ? slot_e[1] : (e == 2 ? slot_e[2] : slot_e[3])), sg, owner | tag);
     }
     R.len = plen;
     R.pre_pdf = pdf_y;
@@ -1800,7 +1810,7 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
     R.J = Jf;
     R.ok = true;
     st.c[ST_SHIFTS_OK]++;
-    if (s.shift_mode == 1) st.c[ST_NEWTON_OK]++;
+    if (newton) st.c[ST_NEWTON_OK]++;
     return R;
 }
 

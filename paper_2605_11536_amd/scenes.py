@@ -359,6 +359,39 @@ def cornell_box(width=64, height=64, frames=4, seed=0, **sensor_kw) -> Workload:
     return Workload("cornell_box_64", scene, sensor, fr)
 
 
+def glossy_box(width=32, height=32, frames=3, seed=0, wall_alpha=0.3, floor_alpha=0.12, ball_alpha=0.25,
+               move=1.0, **sensor_kw) -> Workload:
+    """The tiny box with GGX surfaces on both sides of the reconnection
+    roughness 0.2 and a moving sphere: back, ceiling and side walls GGX with
+    wall_alpha and the sphere with ball_alpha (rough: reconnectable), the
+    floor with floor_alpha (smooth: replayed), F0 0.8; the sphere moves
+    +0.05 move in x and turns 5 move degrees about the vertical per frame."""
+    b = _Builder()
+    wall = b.material(MAT_GGX, alpha=wall_alpha, f0=0.8)
+    floor = b.material(MAT_GGX, alpha=floor_alpha, f0=0.8)
+    ball = b.material(MAT_GGX, alpha=ball_alpha, f0=0.8)
+    b.grid(_quad((-1, -1, -1), (2, 0, 0), (0, 2, 0)), wall)    # back
+    b.grid(_quad((-1, -1, -1), (0, 0, 2), (2, 0, 0)), floor)   # floor
+    b.grid(_quad((-1, 1, -1), (2, 0, 0), (0, 0, 2)), wall)     # ceiling
+    b.grid(_quad((-1, -1, -1), (0, 2, 0), (0, 0, 2)), wall)    # left
+    b.grid(_quad((1, -1, -1), (0, 0, 2), (0, 2, 0)), wall)     # right
+    b.sphere((0.0, 0.0, 0.0), 0.3, ball)
+    base = np.array([[0, 0, 1], [0, 1, 0], [-1, 0, 0]], dtype=np.float64)
+
+    def xforms_at(f):
+        xf = np.stack([_identity_xform()] * 6)
+        xf[5] = _xform(_rot_axis_angle((0, 1, 0), 5.0 * move * f) @ base, (-0.1 + 0.05 * move * f, -0.7, -0.3))
+        return xf
+
+    scene = b.build(xforms_at(0))
+    kw = dict(width=width, height=height, gate_center=4.0, gate_width=0.4, n_min=2, n_max=3, m_init=1,
+              temporal=1, spatial_rounds=1, spatial_k=5, spatial_radius=4, seed=seed)
+    kw.update(sensor_kw)
+    sensor = Sensor(**kw)
+    fr = [_pinhole_frame(f, (0, 0, 1), (0, 0, 0), (0, 1, 0), 90.0, (0, 0, 1), xforms_at(f)) for f in range(frames)]
+    return Workload("glossy_box", scene, sensor, fr)
+
+
 def lambert_plane(depth=1.0, albedo=0.5, intensity=1.0, width=64, height=64,
                   fov=60.0, half_size=50.0, **sensor_kw) -> Workload:
     """A single Lambertian plane z=-depth facing a pinhole at the origin with
