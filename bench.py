@@ -61,19 +61,21 @@ def sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(group, steps, warmup):
+def measured_traffic(group):
     """HBM bytes per launch of a kernel group from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy's reading),
-    or None when the kernels changed since it was taken or it covers another
-    group or frame window."""
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy's
+    reading) with the frame window it was taken over, or None when the
+    kernels changed since it was taken or it covers another group."""
     path = os.path.join(ROOT, "profiles", "traffic_glossy_dynamic_512.json")
     if not os.path.exists(path):
         return None
     t = json.load(open(path))
-    if (t.get("sources_sha256") != sources_digest() or t.get("group") != group
-            or t.get("steps") != steps or t.get("warmup") != warmup):
+    if t.get("sources_sha256") != sources_digest():
         return None
-    return t["hbm_bytes_per_launch"]
+    g = t.get("groups", {}).get(group)
+    if not g:
+        return None
+    return {"bytes_per_launch": g["hbm_bytes_per_launch"], "frames": t["frames"]}
 
 
 def valu_flops(w):
@@ -84,15 +86,18 @@ def valu_flops(w):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--width", type=int, default=512)
-    ap.add_argument("--ref-calls", type=int, default=24, help="reference PT calls (x ref-trees spp each)")
+    ap.add_argument("--ref-calls", type=int, default=256, help="reference PT calls (x ref-trees spp each)")
     ap.add_argument("--ref-trees", type=int, default=16)
+    ap.add_argument("--rmse-frames", type=str, default="10,20,30,40,50,60",
+                    help="frames of the sequence at which the equal-RMSE comparison is made")
+    ap.add_argument("--no-bins-sweep", action="store_true")
     ap.add_argument("--no-equal-rmse", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=3, help="oracle frames timed for the CPU baseline")
-    ap.add_argument("--cpu-crop", type=int, default=64, help="side of the oracle's crop for the CPU baseline")
+    ap.add_argument("--cpu-crop", type=int, default=128, help="side of the oracle's crop for the CPU baseline")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run the serving leg alone")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -119,37 +124,58 @@ def _threads():
 
 
 def cpu_baseline(width, first, count, crop):
-    """The CPU oracle, as it stands, on a crop of the same workload: frames
-    0..first+count-1 of the same sequence are rendered on a crop x crop window
-    at the image centre, the last `count` (the frames the GPU's timed window
-    starts with) are timed, and the rate is scaled by the pixel ratio."""
+    """The CPU oracle, as it stands, on bounded samples of the workloads.
+
+    Headline: frames 0..first+count-1 of the benchmark sequence rendered on a
+    crop x crop window at the image centre with every host thread, the last
+    `count` timed (the frames the GPU's timed window starts with), the rate
+    divided by the pixel ratio.  Beside it: one thread on a 64x64 crop (one
+    frame, after the same history), the tiny box configuration in full (64x64,
+    4 frames) and the first 4 frames of the NLOS configuration in full (64x64
+    scan, 50k-triangle torus, 1024 bins)."""
     from paper_2605_11536_amd import scenes
     from oracle import build as obuild
     if not os.path.exists(obuild.LIB):
         obuild.build()
     from oracle.oracle import Oracle
+    nt = _threads()
+
+    def run(w, threads, timed_from):
+        o = Oracle(w.scene, w.sensor, num_threads=threads)
+        times, shifts = [], 0
+        for fr in w.frames:
+            s0 = o.stats()["shifts"]
+            t0 = time.perf_counter()
+            o.render(fr)
+            dt = time.perf_counter() - t0
+            if fr.index >= timed_from:
+                times.append(dt)
+                shifts += o.stats()["shifts"] - s0
+        o.close()
+        return times, shifts
+
     x0 = (width - crop) // 2
     w = scenes.glossy_dynamic(width=crop, height=crop, full_width=width, full_height=width, crop_x0=x0,
                               crop_y0=x0, frames=first + count)
-    nt = _threads()
-    o = Oracle(w.scene, w.sensor, num_threads=nt)
-    times, shifts = [], 0
-    for fr in w.frames:
-        s0 = o.stats()["shifts"]
-        t0 = time.perf_counter()
-        o.render(fr)
-        dt = time.perf_counter() - t0
-        if fr.index >= first:
-            times.append(dt)
-            shifts += o.stats()["shifts"] - s0
-    o.close()
+    times, shifts = run(w, nt, first)
     scale = (width * width) / float(crop * crop)
+    c1 = (width - 64) // 2
+    w1 = scenes.glossy_dynamic(width=64, height=64, full_width=width, full_height=width, crop_x0=c1, crop_y0=c1,
+                               frames=first + 1)
+    t1, _ = run(w1, 1, first)
+    tb, _ = run(scenes.cornell_box(frames=4), nt, 0)
+    tn, _ = run(scenes.nlos_confocal(scan=64, frames=4), nt, 0)
     return {"value": round(len(times) / (sum(times) * scale), 6), "unit": "frames/s", "cores": nt, "kind": "oracle",
             "sample": f"{crop}x{crop} crop at ({x0},{x0}) of the {width}x{width} sequence, frames 0..{first + count - 1} "
                       f"rendered, frames {first}..{first + count - 1} timed ({[round(t, 3) for t in times]} s), "
                       f"rate divided by the pixel ratio {scale:g}; the crop clips the 30 px spatial disk at its "
                       f"border, so it does somewhat less work per pixel than the full frame",
-            "shifts_per_s": round(shifts / sum(times), 1)}
+            "shifts_per_s": round(shifts / sum(times), 1),
+            "one_thread": {"frames_per_s": round(1.0 / (t1[0] * (width * width) / 4096.0), 6),
+                           "sample": f"64x64 crop at ({c1},{c1}), frame {first} timed ({round(t1[0], 3)} s), "
+                                     f"rate divided by the pixel ratio"},
+            "tiny_box_64x64_4_frames_s": round(sum(tb), 4),
+            "nlos_64x64_1024_bins_s_per_frame": [round(t, 3) for t in tn]}
 
 
 def main():
@@ -167,12 +193,10 @@ def main():
     from paper_2605_11536_amd.tof import Renderer
 
     W = args.width
-    nseq = 60
+    nseq = max(60, max(int(x) for x in args.rmse_frames.split(",")) + 1)
     wl = scenes.glossy_dynamic(width=W, height=W, frames=nseq)
     sensor = wl.sensor
     P, B = W * W, sensor.b_tot
-
-    r = Renderer(wl.scene, sensor)
 
     def frame_at(i):
         fr = wl.frames[i % nseq]
@@ -180,10 +204,11 @@ def main():
                             fov_y_deg=fr.fov_y_deg, ortho_half=fr.ortho_half, light_pos=fr.light_pos,
                             xforms=fr.xforms)
 
+    # the timed region: frames warmup .. warmup+steps-1 with kernel timing off
+    r = Renderer(wl.scene, sensor)
     for i in range(args.warmup):
         r.render(frame_at(i))
     torch.cuda.synchronize()
-    r.set_kernel_timing(True)
     stats0 = r.stats()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -195,14 +220,24 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    kt = r.kernel_times()
-    r.set_kernel_timing(False)
     stats1 = r.stats()
     frame_ms = np.array([a.elapsed_time(b) for a, b in ev])
     fps = args.steps / elapsed
     dstats = {k: stats1[k] - stats0[k] for k in stats1}
-    last_frame = frame_at(args.warmup + args.steps - 1)
     restir_out = r.fetch()
+    r.close()
+    # per-kernel times and work: the same frames again in a second context,
+    # with HIP events around each kernel group during the same window
+    r = Renderer(wl.scene, sensor)
+    for i in range(args.warmup):
+        r.render(frame_at(i))
+    torch.cuda.synchronize()
+    r.set_kernel_timing(True)
+    for k in range(args.steps):
+        r.render(frame_at(args.warmup + k))
+    kt = r.kernel_times()
+    r.set_kernel_timing(False)
+    r.close()
 
     result = {
         "metric": "equal-RMSE frames/s vs plain ToF PT at 512^2; p50/p99 request latency",
@@ -257,6 +292,10 @@ def main():
         result["roofline"] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_splat",
                               "avg_launch_ms": round(avg_s * 1e3, 4)}
+        mt = measured_traffic(dom)
+        if mt:
+            result["roofline"]["traffic"] = mt["bytes_per_launch"]
+            result["roofline"]["traffic_frames"] = mt["frames"]
     else:
         w = kt[dom]["work"]
         per_launch = valu_flops(w) / max(kl[dom], 1)
@@ -267,9 +306,13 @@ def main():
                  "gbuffer": "k_gbuffer"}.get(dom, dom)
         result["roofline"] = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": round(ach / FP32_PEAK_TFLOPS, 5),
-                              "traffic": measured_traffic(dom, args.steps, args.warmup),
+                              "traffic": None,
                               "kernel": f"{kname} ({dom})", "avg_launch_ms": round(avg_s * 1e3, 4),
                               "flops_per_launch": per_launch}
+        mt = measured_traffic(dom)
+        if mt:
+            result["roofline"]["traffic"] = mt["bytes_per_launch"]
+            result["roofline"]["traffic_frames"] = mt["frames"]
     # the streaming passes against HBM: the splat over every (pixel, plane)
     if kl.get("splat"):
         occ = float(np.count_nonzero(restir_out["hist"])) / restir_out["hist"].size
@@ -278,7 +321,7 @@ def main():
         result["splat_hbm"] = {"achieved_GBs": round(sp_bytes / sp_s / 1e9, 1),
                                "frac": round(sp_bytes / sp_s / 1e9 / HBM_PEAK_GBS, 4),
                                "bytes_per_launch": int(sp_bytes), "occupancy": round(occ, 5),
-                               "avg_launch_ms": round(sp_s * 1e3, 4)}
+                               "avg_launch_ms": round(sp_s * 1e3, 4), "traffic": measured_traffic("splat")}
 
     # ... and the resampling merge, from its algorithmic bytes per item and task
     merge = {}
@@ -290,16 +333,18 @@ def main():
             gbs = mb / (kms[g] * 1e-3) / 1e9
             merge[pas] = {"achieved_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                           "bytes_per_frame": int(mb / max(args.steps, 1)),
-                          "ms_per_frame": round(kms[g] / max(args.steps, 1), 3)}
+                          "ms_per_frame": round(kms[g] / max(args.steps, 1), 3), "launches": kl[g],
+                          "traffic": measured_traffic(g)}
     if merge:
         result["merge_hbm"] = merge
 
-    # equal RMSE against plain ToF PT on the same GPU
+    # equal RMSE against plain ToF PT on the same GPU, over the sequence
     if not args.no_equal_rmse:
-        result["equal_rmse"] = equal_rmse(wl, last_frame, restir_out, fps, args, torch, Renderer, scenes)
-        result["equal_rmse_gate_only"] = gate_only(wl, frame_at, args, torch, Renderer, scenes)
-
-    r.close()
+        result["equal_rmse"] = equal_rmse_seq(wl, frame_at, sensor, args, torch, Renderer)
+        result["equal_rmse_gate_only"] = [gate_only(wl, frame_at, args, torch, Renderer, m_init=m)
+                                          for m in (1, 2)]
+    if not args.no_bins_sweep:
+        result["cost_vs_bins"] = bins_sweep(wl, frame_at, args, torch, Renderer)
     if not args.no_serving:
         result["serving"] = serving(args, torch)
     if args.copy_probe:
@@ -433,91 +478,122 @@ def serving(args, torch):
             "mix": {"res": [int(w.sensor.width) for w in wls], "bins": [int(w.sensor.n_bins) for w in wls]}}
 
 
-def gate_only(wl, frame_at, args, torch, Renderer, scenes):
-    """The same scene and sequence with the gate alone (no histogram bins):
-    the regime the paper targets (a narrow gate), same ReSTIR settings."""
-    import dataclasses
-    sensor = dataclasses.replace(wl.sensor, n_bins=0)
-    g = Renderer(wl.scene, sensor)
-    for i in range(args.warmup):
-        g.render(frame_at(i))
-    torch.cuda.synchronize()
-    g.set_kernel_timing(True)
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        g.render(frame_at(args.warmup + k))
-    torch.cuda.synchronize()
-    fps = args.steps / (time.perf_counter() - t0)
-    kt = g.kernel_times()
-    g.set_kernel_timing(False)
-    out = g.fetch()
-    g.close()
-    gw = dataclasses.replace(wl, sensor=sensor)
-    res = equal_rmse(gw, frame_at(args.warmup + args.steps - 1), out, fps, args, torch, Renderer, scenes,
-                     planes=("gate_image",))
-    res["restir_frames_per_s"] = round(fps, 3)
-    res["kernel_ms_per_frame"] = {k: round(v["ms"] / args.steps, 3) for k, v in kt.items() if k != "work_items"}
-    return res
+def equal_rmse_seq(wl, frame_at, sensor, args, torch, Renderer, planes=("gate_image", "histogram")):
+    """Equal RMSE against plain ToF PT on the same GPU, over the sequence.
 
-
-def equal_rmse(wl, frame, restir_out, restir_fps, args, torch, Renderer, scenes, planes=("gate_image", "histogram")):
-    """RMSE of the ReSTIR frame and of 1-spp plain PT against a high-spp PT
-    reference of the same frame; plain PT at s spp has MSE_1/s, so the spp
-    that matches ReSTIR is s* = MSE_1/MSE_restir and its frame time s* t_1."""
+    ToF ReSTIR renders frames 0..F of the sequence (F = the last frame listed
+    in --rmse-frames); at each listed frame its output is compared with a
+    plain-PT reference of that frame (ref_calls x ref_trees path trees per
+    pixel), whose own variance is removed from the error.  Plain PT at s spp
+    has MSE_1 / s, MSE_1 measured at that frame from four independent 1-spp
+    renders, so the spp that matches ReSTIR is s* = MSE_1 / MSE_restir and its
+    frame time s* t_1, t_1 timed over 20 frames of the sequence.  ReSTIR's
+    frame time is its event time averaged over the listed window.  Speedup =
+    t_PT(s*) / t_ReSTIR per listed frame, and their mean.  Everything stays on
+    the device: the outputs are large (512^2 x 256 bins)."""
     import dataclasses
-    ref_sensor = dataclasses.replace(wl.sensor, temporal=0, spatial_rounds=0, m_init=args.ref_trees)
+    fl = sorted(int(x) for x in args.rmse_frames.split(","))
+    F = fl[-1]
+    keys = [k for k, name in (("image", "gate_image"), ("hist", "histogram")) if name in planes]
+    r = Renderer(wl.scene, sensor)
+    outs = {}
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(F + 1)]
+    for i in range(F + 1):
+        ev[i][0].record()
+        r.render(frame_at(i))
+        ev[i][1].record()
+        if i in fl:
+            outs[i] = {k: getattr(r, "out_" + k).double().clone() for k in keys}
+    torch.cuda.synchronize()
+    r.close()
+    t_restir = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(fl[0], F + 1)])) * 1e-3
+    ref_sensor = dataclasses.replace(sensor, temporal=0, spatial_rounds=0, m_init=args.ref_trees, shrink_k=1.0)
+    pt_sensor = dataclasses.replace(sensor, temporal=0, spatial_rounds=0, m_init=1, shrink_k=1.0)
     q = Renderer(wl.scene, ref_sensor)
-    acc_i, acc_h = None, None
-    for s in range(args.ref_calls):
-        f = dataclasses.replace(frame, index=10_000_000 + s)
-        q.render(f)
-        o = q.fetch()
-        acc_i = o["pt_image"].astype(np.float64) if acc_i is None else acc_i + o["pt_image"]
-        if "pt_hist" in o:
-            acc_h = o["pt_hist"].astype(np.float64) if acc_h is None else acc_h + o["pt_hist"]
-    q.close()
-    ref_i = acc_i / args.ref_calls
-    ref_h = acc_h / args.ref_calls if acc_h is not None else None
-    ref_spp = args.ref_calls * args.ref_trees
-    # plain PT, 1 spp: time and error
-    pt_sensor = dataclasses.replace(wl.sensor, temporal=0, spatial_rounds=0, m_init=1)
     p = Renderer(wl.scene, pt_sensor)
-    mse1_i, mse1_h = [], []
-    for s in range(4):
-        p.render(dataclasses.replace(frame, index=20_000_000 + s))
-        o = p.fetch()
-        mse1_i.append(np.mean((o["pt_image"] - ref_i) ** 2))
-        if ref_h is not None:
-            mse1_h.append(np.mean((o["pt_hist"] - ref_h) ** 2))
-    # timed over consecutive frames of the sequence, so that plain PT pays the
-    # same per-frame geometry update as ReSTIR
+    ref_spp = args.ref_calls * args.ref_trees
+    per = []
+    for f in fl:
+        acc = {k: torch.zeros_like(outs[f][k]) for k in keys}
+        for c in range(args.ref_calls):
+            q.render(dataclasses.replace(frame_at(f), index=10_000_000 + 1000 * f + c))
+            for k in keys:
+                acc[k] += getattr(q, "out_pt_" + k)
+        ref = {k: acc[k] / args.ref_calls for k in keys}
+        mse1 = {k: 0.0 for k in keys}
+        for c in range(4):
+            p.render(dataclasses.replace(frame_at(f), index=20_000_000 + 1000 * f + c))
+            for k in keys:
+                mse1[k] += float(((getattr(p, "out_pt_" + k).double() - ref[k]) ** 2).mean()) / 4
+        row = {}
+        for k in keys:
+            m1 = mse1[k] * (1.0 - 1.0 / ref_spp)
+            mr = max(float(((outs[f][k] - ref[k]) ** 2).mean()) - mse1[k] / ref_spp, 1e-30)
+            row[k] = (m1, mr)
+        per.append(row)
+    q.close()
+    # plain PT's frame time over consecutive frames (it pays the same geometry update)
     nrep = 20
-    seq = [dataclasses.replace(f, index=30_000_000 + i) for i, f in enumerate(wl.frames[:nrep])]
-    p.render(seq[-1])
+    p.render(dataclasses.replace(frame_at(nrep), index=30_000_000))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for f in seq:
-        p.render(f)
+    for i in range(nrep):
+        p.render(dataclasses.replace(frame_at(i), index=30_000_001 + i))
     torch.cuda.synchronize()
     t_pt = (time.perf_counter() - t0) / nrep
     p.close()
-    mse1_i = float(np.mean(mse1_i))
-    mse1_h = float(np.mean(mse1_h)) if mse1_h else None
-    out = {"reference_spp": ref_spp, "pt_1spp_ms": round(1e3 * t_pt, 3)}
-    for name, mse1, ref, got in (("gate_image", mse1_i, ref_i, restir_out.get("image")),
-                                 ("histogram", mse1_h, ref_h, restir_out.get("hist"))):
-        if name not in planes or ref is None:
+    out = {"frames": fl, "reference_spp": ref_spp, "pt_1spp_ms": round(1e3 * t_pt, 3),
+           "restir_ms_per_frame": round(1e3 * t_restir, 3), "restir_frames_per_s": round(1.0 / t_restir, 3)}
+    for k, name in (("image", "gate_image"), ("hist", "histogram")):
+        if k not in keys:
             continue
-        # remove the reference's own variance (plain PT at ref_spp)
-        mse1_t = mse1 * (1.0 - 1.0 / ref_spp)
-        mse_r = float(np.mean((got - ref) ** 2)) - mse1 / ref_spp
-        mse_r = max(mse_r, 1e-30)
-        s_star = mse1_t / mse_r
-        pt_fps = 1.0 / (s_star * t_pt)
-        out[name] = {"restir_rmse": math.sqrt(mse_r), "pt_1spp_rmse": math.sqrt(mse1_t),
-                     "pt_spp_at_equal_rmse": round(s_star, 3), "pt_frames_per_s_at_equal_rmse": round(pt_fps, 3),
-                     "speedup": round(restir_fps / pt_fps, 4)}
+        s_star = [row[k][0] / row[k][1] for row in per]
+        sp = [(x * t_pt) / t_restir for x in s_star]
+        out[name] = {"restir_rmse": [round(math.sqrt(row[k][1]), 8) for row in per],
+                     "pt_1spp_rmse": [round(math.sqrt(row[k][0]), 8) for row in per],
+                     "pt_spp_at_equal_rmse": [round(x, 3) for x in s_star],
+                     "speedup_per_frame": [round(x, 4) for x in sp],
+                     "speedup": round(float(np.mean(sp)), 4)}
     return out
+
+
+def gate_only(wl, frame_at, args, torch, Renderer, m_init=1):
+    """The same scene and sequence with the gate alone (no histogram bins):
+    the regime the paper targets (a narrow gate), same ReSTIR settings."""
+    import dataclasses
+    sensor = dataclasses.replace(wl.sensor, n_bins=0, m_init=m_init)
+    res = equal_rmse_seq(wl, frame_at, sensor, args, torch, Renderer, planes=("gate_image",))
+    res["m_init"] = m_init
+    return res
+
+
+def bins_sweep(wl, frame_at, args, torch, Renderer, bins=(4, 16, 64, 256), warm=5, timed=5):
+    """Cost against the number of histogram bins B over the same path-length
+    range (Sec. 4.5: reuse cost grows with the bins a pixel holds): frames/s,
+    shifts and rays per frame, timing off, frames warm..warm+timed-1."""
+    import dataclasses
+    s0 = wl.sensor
+    span = s0.n_bins * s0.bin_width
+    out = []
+    for nb in bins:
+        sensor = dataclasses.replace(s0, n_bins=nb, bin_width=span / nb)
+        r = Renderer(wl.scene, sensor)
+        for i in range(warm):
+            r.render(frame_at(i))
+        torch.cuda.synchronize()
+        st0 = r.stats()
+        t0 = time.perf_counter()
+        for i in range(warm, warm + timed):
+            r.render(frame_at(i))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / timed
+        st1 = r.stats()
+        r.close()
+        out.append({"bins": nb, "planes": nb + 1, "ms_per_frame": round(1e3 * dt, 3),
+                    "frames_per_s": round(1.0 / dt, 3),
+                    "shifts_per_frame": (st1["shifts"] - st0["shifts"]) // timed,
+                    "rays_per_frame": (st1["rays"] - st0["rays"]) // timed})
+    return {"frames": [warm, warm + timed - 1], "points": out}
 
 
 if __name__ == "__main__":

@@ -259,6 +259,16 @@ typedef struct {
  * object ids. */
 tof_status tof_debug_set_history(tof_ctx* ctx, const tof_history_desc* history);
 
+/* Test support (the chunked reuse passes at small sizes): lower the ray budget
+ * that sizes the chunks of the reuse passes to `rays` (0 = the default), so
+ * that a small frame runs its passes over several chunks; a chunk still holds
+ * at least one sweep of the smallest grid (8192 tasks).  Results do not
+ * depend on the chunking.  *spatial_items_per_chunk (may be NULL) receives the
+ * items of a spatial chunk.  Waits for the context's last frame; the next
+ * tof_sensor_set restores the default.  TOF_ERR_NOT_READY before a sensor is
+ * set. */
+tof_status tof_debug_set_ray_budget(tof_ctx* ctx, size_t rays, size_t* spatial_items_per_chunk);
+
 /* Per-kernel GPU timing with HIP events recorded on the render stream around
  * each launch (off by default).  Kernel ids index tof_kernel_times. */
 enum {

@@ -34,7 +34,9 @@ struct ChunkPlan {
     unsigned grid[3] = {0, 0, 0}, vis_grid[3] = {0, 0, 0};
 };
 
-inline ChunkPlan plan_chunks(size_t P, size_t B, int k, int br) {
+// ray_budget > 0 lowers the budget (test support: more, smaller chunks); a
+// chunk still holds at least one sweep of the smallest grid.
+inline ChunkPlan plan_chunks(size_t P, size_t B, int k, int br, size_t ray_budget = 0) {
     ChunkPlan p;
     const int modes = br > 0 ? 3 : 2;
     const size_t K[3] = {1, (size_t)std::max(k, 1), 2 * (size_t)std::max(br, 1)};
@@ -45,6 +47,7 @@ inline ChunkPlan plan_chunks(size_t P, size_t B, int k, int br) {
     // [2^24, 2^28] rays (0.5 .. 8.6 GB of queue); a pass that needs fewer
     // than 2^24 rays in all runs as one chunk
     p.rays = std::min<size_t>((size_t)1 << 28, std::max<size_t>(std::min<size_t>(dense, (size_t)1 << 24), dense / 16));
+    if (ray_budget) p.rays = std::min(p.rays, ray_budget);
     for (int m = 0; m < modes; ++m) {
         const size_t all = P * B * (K[m] + 1);
         const size_t raw = std::max<size_t>(1, std::min(p.rays / (seg[m] * K[m]), all));

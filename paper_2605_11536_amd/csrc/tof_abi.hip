@@ -770,6 +770,21 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     return TOF_OK;
 }
 
+tof_status tof_debug_set_ray_budget(tof_ctx* c, size_t rays, size_t* spatial_items_per_chunk) {
+    if (!c) return TOF_ERR_INVALID_ARG;
+    if (!c->has_sensor) return TOF_ERR_NOT_READY;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(quiesce(c));
+    const size_t P = (size_t)c->s.P, B = (size_t)c->s.B;
+    const tofh::ChunkPlan full = tofh::plan_chunks(P, B, c->s.k, c->s.br);   // what the work space holds
+    const tofh::ChunkPlan pl = tofh::plan_chunks(P, B, c->s.k, c->s.br, rays);
+    if (pl.task_cap > full.task_cap || pl.term_cap > full.term_cap || pl.ray_cap > full.ray_cap)
+        return TOF_ERR_INVALID_ARG;
+    c->plan = pl;
+    if (spatial_items_per_chunk) *spatial_items_per_chunk = pl.ci[1];
+    return TOF_OK;
+}
+
 tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
     if (!c || !h) return TOF_ERR_INVALID_ARG;
     if (!c->has_scene || !c->has_sensor || !c->slot[0].valid) return TOF_ERR_NOT_READY;

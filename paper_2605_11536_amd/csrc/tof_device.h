@@ -400,13 +400,25 @@ __device__ __forceinline__ bool isect_tri(V3 o, V3 d, int kx, int ky, int kz, fl
     return true;
 }
 
+// Ray/sphere intersection for a unit direction d, in the form of Haines,
+// Guenther and Akenine-Moeller ("Precision Improvements for Ray/Sphere
+// Intersection", Ray Tracing Gems, 2019): the discriminant r^2 - |l|^2 comes
+// from the centre's distance |l| to the ray instead of b^2 - (|f|^2 - r^2),
+// which cancels in FP32 when the sphere is small against its distance (an
+// error of 1e-6 in the hit point of a ray that meets the sphere obliquely
+// becomes 1e-4 of a contribution whose light direction grazes the sphere);
+// the roots are q and (|f|^2 - r^2) / q, without cancellation.
 __device__ __forceinline__ bool isect_sphere(V3 o, V3 d, V3 c, float r, float tmax, float& t) {
-    V3 oc = o - c;
-    float b = dot(oc, d), cc = dot(oc, oc) - r * r;
-    float disc = b * b - cc;
+    const V3 f = o - c;
+    const float b = -dot(f, d);             // ray parameter of the point nearest the centre
+    const float ll = len(f + b * d);        // distance from the centre to the ray
+    const float disc = (r - ll) * (r + ll);
     if (disc < 0.f) return false;
-    float sq = sqrtf(disc);
-    float t0 = -b - sq, t1 = -b + sq;
+    const float q = b + copysignf(sqrtf(disc), b);
+    if (q == 0.f) return false;
+    const float cc = dot(f, f) - r * r;
+    const float ta = cc / q, tb = q;
+    const float t0 = fminf(ta, tb), t1 = fmaxf(ta, tb);
     if (t0 > 0.f && t0 < tmax) {
         t = t0;
         return true;

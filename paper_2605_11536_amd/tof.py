@@ -106,6 +106,8 @@ def lib():
                                        C.c_void_p, C.c_void_p, C.c_void_p]
         L.tof_reservoirs_reset.argtypes = [C.c_void_p]
         L.tof_get_stats.argtypes = [C.c_void_p, C.POINTER(tof_stats)]
+        L.tof_debug_set_ray_budget.argtypes = [C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.tof_debug_set_ray_budget.restype = C.c_int
         L.tof_debug_set_history.argtypes = [C.c_void_p, C.POINTER(tof_history_desc)]
         L.tof_debug_set_history.restype = C.c_int
         L.tof_set_kernel_timing.argtypes = [C.c_void_p, C.c_int]
@@ -246,6 +248,7 @@ def tof_render_frame(h, frame, out_image=None, out_hist=None, out_pt_image=None,
                                                       C.c_void_p(stream.cuda_stream)))
 
 
+
 def tof_reservoirs_reset(h) -> None:
     _check("tof_reservoirs_reset", lib().tof_reservoirs_reset(h))
 
@@ -348,6 +351,13 @@ class Renderer:
 
     def kernel_times(self) -> dict:
         return tof_get_kernel_times(self.h)
+
+    def set_ray_budget(self, rays: int) -> int:
+        """Test support: chunks of the reuse passes sized to `rays` visibility
+        rays (0 = default); returns the items per spatial chunk."""
+        n = C.c_size_t(0)
+        _check("tof_debug_set_ray_budget", lib().tof_debug_set_ray_budget(self.h, int(rays), C.byref(n)))
+        return int(n.value)
 
     def set_history(self, hist: dict):
         tof_debug_set_history(self.h, hist)

@@ -110,6 +110,16 @@ static void plan_check() {
                         // a pass that fits the ray budget runs as one chunk
                         if (dense <= ((size_t)1 << 24)) CHECK(p.ci[m] >= P * B);
                     }
+                    // a lowered budget (test support) still gives whole grid
+                    // sweeps and fits the default plan's work space
+                    for (size_t rays : {(size_t)1, (size_t)81920, (size_t)1 << 20}) {
+                        const tofh::ChunkPlan q = tofh::plan_chunks(P, B, k, br, rays);
+                        CHECK(q.task_cap <= p.task_cap && q.term_cap <= p.term_cap && q.ray_cap <= p.ray_cap);
+                        for (int m = 0; m < (br > 0 ? 3 : 2); ++m) {
+                            CHECK(q.ct[m] % ((size_t)q.grid[m] * 128) == 0 && q.ct[m] <= p.ct[m]);
+                            CHECK(q.ci[m] >= 1 && q.ci[m] * (K[m] + 1) <= q.ct[m]);
+                        }
+                    }
                 }
 }
 

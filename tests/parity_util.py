@@ -45,3 +45,60 @@ def describe(what, r):
     for idx, gv, ov in r["top"]:
         s += f"\n    at {tuple(int(i) for i in idx)}: gpu {gv:.7g} oracle {ov:.7g}"
     return s
+
+
+REL_NEWTON = 1e-3
+MIN_FRAC = 0.999
+MIN_FRAC_NEWTON = 0.998
+
+
+def has_ggx(scene):
+    return bool((scene.mat_type == 1).any())
+
+
+def bar_for(key, scene, stage):
+    """Which bar an output meets.
+
+    "strict": >= 99.9% of the support within 1e-4 (at least one entry may lie
+    outside on a support under 1000 entries) and all of it within 1e-3.  Plain
+    PT (and the canonical reservoirs, before any shift) of scenes without GGX
+    surfaces.  The entries outside 1e-4 here are paths that meet a sphere at a
+    grazing angle and then see the light at a grazing angle: the FP32 hit point
+    moves along the surface by a few 1e-6, and the light's cosine of a few
+    1e-2 by 1e-4 of itself.
+
+    "statistical": >= 99.9% of all entries within 1e-4, >= 99.8% of the
+    support within 1e-3, and no systematic sign of the entries outside 1e-4.
+    ReSTIR outputs after reuse: the Newton system is ill-conditioned where the
+    path length is nearly stationary on the chart, so the FP32 positions of the
+    device (1e-7 relative) move the shifted vertex and its Jacobian by up to a
+    few 1e-4.  Plain PT of GGX scenes: paths that graze a surface (|cos| of a
+    few 1e-3) or a silhouette (a ray within 1e-6 of an edge) turn FP32
+    position rounding into 1e-4..1e-3 of a contribution, or decide a hit
+    differently.  A few support entries (about 0.1% of a frame after two or
+    three frames of reuse) differ by a whole sample: a Newton convergence, a
+    round trip or a weighted selection decided the other way where the FP32
+    and FP64 values straddle the threshold; the shift counts of both sides
+    agree to 0.2%."""
+    canonical = stage == 0 and not key.startswith("pt_")
+    if (key.startswith("pt_") or canonical) and not has_ggx(scene):
+        return "strict"
+    return "statistical"
+
+
+def assert_parity(g, o, what, bar):
+    r = compare(g, o)
+    r3 = compare(g, o, rel=REL_NEWTON)
+    print(describe(what + f" [{bar}]", r) + f"\n    within {REL_NEWTON}: {r3['frac_support'] * 100:.4f}% of the support",
+          flush=True)
+    if bar == "strict":
+        allowed = max(1, int((1.0 - MIN_FRAC) * r["support"]))
+        outside = int(round((1.0 - r["frac_support"]) * r["support"]))
+        assert outside <= allowed, f"{what}: {outside} of {r['support']} support entries outside {REL}"
+        assert r3["frac_support"] == 1.0, f"{what}: only {r3['frac_support']:.5f} of the support within {REL_NEWTON}"
+    else:
+        assert r["frac_all"] >= MIN_FRAC, f"{what}: only {r['frac_all']:.5f} of all entries within {REL}"
+        assert r3["frac_support"] >= MIN_FRAC_NEWTON, \
+            f"{what}: only {r3['frac_support']:.5f} of the support within {REL_NEWTON}"
+    assert abs(r["z"]) <= 3.0, f"{what}: discrepant entries biased (z = {r['z']})"
+    return r
