@@ -222,6 +222,28 @@ tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
 tof_status tof_render_frame(tof_ctx* ctx, const tof_frame_desc* frame, float* out_image, float* out_hist,
                             float* out_pt_image, float* out_pt_hist, void* stream);
 
+/* For callers that cannot allocate device memory while they render: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The same frame as tof_render_frame (same arguments, errors and
+ * results) with its per-frame work space -- work lists, shift terms, MIS list,
+ * ray queue and their counters, plain-PT staging, reprojection and neighbour
+ * tables -- taken from one static device array of the library instead of the
+ * context's buffers: 64 MiB per GPU, held from the first tof_create on that
+ * GPU until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree, pinned or event allocation); the context's reservoirs, G-buffers
+ * and geometry are used as always.  The reuse passes run over as many chunks
+ * as it takes for their work space to fit the array (results do not depend on
+ * the chunking).  TOF_ERR_OUT_OF_MEMORY when even the smallest chunks do not
+ * fit: the parts sized per (pixel, plane), 16 bytes each, plus 4 (spatial_k +
+ * 3) bytes per pixel and about 4 MiB for the smallest chunk must stay under
+ * 64 MiB (about 3.5 M pixel-planes with 5 neighbours, e.g. 128x128 pixels
+ * with 200 planes).  Every call on a GPU uses that GPU's one array: frames of
+ * this entry point that may overlap on one GPU (unordered streams, or several
+ * host threads) race on it and must be ordered by the caller.  Kernel timing
+ * is not recorded for these frames. */
+tof_status tof_render_frame_noalloc(tof_ctx* ctx, const tof_frame_desc* frame, float* out_image, float* out_hist,
+                                    float* out_pt_image, float* out_pt_hist, void* stream);
+
 /* Drop the temporal history (the previous frame's final reservoirs that
  * temporal reuse resamples, Sec. 3.2.4 and Sec. 6): the next frame renders
  * without temporal reuse.  Waits for the context's last frame. */

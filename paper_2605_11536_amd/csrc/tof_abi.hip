@@ -4,7 +4,9 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "tof.h"
@@ -352,6 +354,33 @@ tof_status tof_footprint(const tof_scene_desc* scene, const tof_sensor_desc* sen
 
 namespace {
 
+// ---------------------------------------------------------------------------
+// The work space of tof_render_frame_noalloc: one file-scope device array per
+// GPU (each device that loads the library holds its own copy until the process
+// ends).  Host code never names the array as an address: its device address is
+// looked up once per device with hipGetSymbolAddress (at the first tof_create
+// on that device, with the device current) and kept in g_scratch.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxScratchDevices] = {};
+
+// the device address of `scratch` on `device`, which must be current
+static hipError_t scratch_ptr(int device, void** ptr) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    if (!g_scratch[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[device] = p;
+    }
+    *ptr = g_scratch[device];
+    return hipSuccess;
+}
+
 tof_status make_ctx(tof_ctx** out, int device, size_t budget, uint64_t seed, void* dev, size_t dev_bytes, void* host,
                     size_t host_bytes) {
     if (!out) return TOF_ERR_INVALID_ARG;
@@ -363,6 +392,10 @@ tof_status make_ctx(tof_ctx** out, int device, size_t budget, uint64_t seed, voi
     }
     if (device < 0 || device >= ndev) return TOF_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(device));
+    {   // resolve the no-allocation work space of this device once
+        void* p = nullptr;
+        HIP_TRY(scratch_ptr(device, &p));
+    }
     tof_ctx* c = new (std::nothrow) tof_ctx();
     if (!c) return TOF_ERR_OUT_OF_MEMORY;
     c->device = device;
@@ -1233,6 +1266,121 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     c->prev_valid = true;
     c->frames++;
     return TOF_OK;
+}
+
+// The per-frame work space of a context: work lists, chunk workspace (tasks,
+// shift terms, MIS list, ray queue and their counters), plain-PT staging,
+// reprojection and neighbour tables.  Only frame state lives elsewhere
+// (reservoirs, G-buffers, geometry, event counters).
+struct FrameWork {
+    float* pt;
+    float2* direct;
+    int* prev_pix;
+    int* nb;
+    uint2* items;
+    uint32_t* task0;
+    uint2* tasks;
+    float4* fwd;
+    float4* wide;
+    float4* shv;
+    float* term;
+    float4* rays;
+    uint32_t* ray_count;
+    uint32_t* mis_list;
+    uint32_t* mis_count;
+    uint32_t* count;
+};
+
+static FrameWork work_of(const tof_ctx* c) {
+    return FrameWork{c->pt,    c->direct, c->prev_pix, c->nb,   c->items, c->task0,     c->tasks,    c->fwd,
+                     c->wide,  c->shv,    c->term,     c->rays, c->ray_count, c->mis_list, c->mis_count, c->count};
+}
+
+static void set_work(tof_ctx* c, const FrameWork& w) {
+    c->pt = w.pt;
+    c->direct = w.direct;
+    c->prev_pix = w.prev_pix;
+    c->nb = w.nb;
+    c->items = w.items;
+    c->task0 = w.task0;
+    c->tasks = w.tasks;
+    c->fwd = w.fwd;
+    c->wide = w.wide;
+    c->shv = w.shv;
+    c->term = w.term;
+    c->rays = w.rays;
+    c->ray_count = w.ray_count;
+    c->mis_list = w.mis_list;
+    c->mis_count = w.mis_count;
+    c->count = w.count;
+}
+
+// Lay the context's frame work space for chunk plan `pl` out from `base`
+// (256-byte aligned parts, the sizes tof_sensor_set allocates for its plan);
+// returns the bytes it spans.  base == nullptr only measures.
+static size_t carve_work(const tof_ctx* c, const tofh::ChunkPlan& pl, char* base, FrameWork& w) {
+    size_t off = 0;
+    auto take = [&](auto*& ptr, size_t count) {
+        using T = typename std::remove_reference<decltype(*ptr)>::type;
+        off = (off + 255) & ~(size_t)255;
+        ptr = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+    };
+    const size_t P = (size_t)c->s.P, B = (size_t)c->s.B;
+    const size_t nq = (size_t)tofd::kRaySubQueues * tofd::kCounterStride;
+    take(w.pt, P * B);
+    take(w.direct, P);
+    take(w.prev_pix, P);
+    take(w.nb, P * (size_t)std::max(c->s.k, 1));
+    take(w.items, P * B);
+    take(w.task0, P * B);
+    take(w.tasks, pl.task_cap);
+    take(w.fwd, pl.task_cap);
+    w.wide = nullptr;
+    if (shrink_mix(c->sd)) take(w.wide, 5 * P);
+    take(w.shv, 2 * pl.task_cap);
+    take(w.term, pl.term_cap);
+    take(w.rays, 2 * pl.ray_cap);
+    take(w.ray_count, nq);
+    take(w.mis_list, pl.term_cap);
+    take(w.mis_count, nq);
+    take(w.count, 64);
+    return off;
+}
+
+tof_status tof_render_frame_noalloc(tof_ctx* c, const tof_frame_desc* fr, float* out_image, float* out_hist,
+                                    float* out_pt_image, float* out_pt_hist, void* stream) {
+    if (!c || !fr) return TOF_ERR_INVALID_ARG;
+    if (!c->has_scene || !c->has_sensor) return TOF_ERR_NOT_READY;
+    // the context's chunk plan, or one with a lower ray budget (more, smaller
+    // chunks of the reuse passes; results do not depend on the chunking) so
+    // that the work space fits the array
+    FrameWork w{};
+    tofh::ChunkPlan pl = c->plan;
+    size_t rays = pl.rays;
+    while (carve_work(c, pl, nullptr, w) > kScratchBytes) {
+        if (rays <= 1) return TOF_ERR_OUT_OF_MEMORY;   // the per-(pixel, plane) parts alone do not fit
+        rays /= 2;
+        pl = tofh::plan_chunks((size_t)c->s.P, (size_t)c->s.B, c->s.k, c->s.br, rays);
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    void* base = nullptr;
+    HIP_TRY(scratch_ptr(c->device, &base));
+    carve_work(c, pl, static_cast<char*>(base), w);
+    // every buffer of the work space is written by the frame's own kernels
+    // before it is read (counters and chunk windows by k_fill_u32 launches),
+    // so the previous call's contents do not matter
+    const FrameWork own = work_of(c);
+    const tofh::ChunkPlan own_plan = c->plan;
+    const bool timing = c->timing;
+    c->timing = false;   // event timing creates events on demand: not recorded here
+    set_work(c, w);
+    c->plan = pl;
+    const tof_status st = tof_render_frame(c, fr, out_image, out_hist, out_pt_image, out_pt_hist, stream);
+    set_work(c, own);
+    c->plan = own_plan;
+    c->timing = timing;
+    return st;
 }
 
 }  // extern "C"

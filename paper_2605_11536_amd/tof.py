@@ -104,6 +104,9 @@ def lib():
         L.tof_sensor_set.argtypes = [C.c_void_p, C.POINTER(tof_sensor_desc)]
         L.tof_render_frame.argtypes = [C.c_void_p, C.POINTER(tof_frame_desc), C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p]
+        L.tof_render_frame_noalloc.argtypes = [C.c_void_p, C.POINTER(tof_frame_desc), C.c_void_p, C.c_void_p,
+                                               C.c_void_p, C.c_void_p, C.c_void_p]
+        L.tof_render_frame_noalloc.restype = C.c_int
         L.tof_reservoirs_reset.argtypes = [C.c_void_p]
         L.tof_get_stats.argtypes = [C.c_void_p, C.POINTER(tof_stats)]
         L.tof_debug_set_ray_budget.argtypes = [C.c_void_p, C.c_size_t, C.POINTER(C.c_size_t)]
@@ -248,6 +251,21 @@ def tof_render_frame(h, frame, out_image=None, out_hist=None, out_pt_image=None,
                                                       C.c_void_p(stream.cuda_stream)))
 
 
+def tof_render_frame_noalloc(h, frame, out_image=None, out_hist=None, out_pt_image=None, out_pt_hist=None,
+                             stream=None) -> None:
+    """tof_render_frame with the frame's work space in the library's static
+    device array (allocates nothing)."""
+    import torch
+    for t in (out_image, out_hist, out_pt_image, out_pt_hist):
+        if t is not None:
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    d, xf = frame_desc(frame)
+    _check("tof_render_frame_noalloc",
+           lib().tof_render_frame_noalloc(h, C.byref(d), _dptr(out_image), _dptr(out_hist), _dptr(out_pt_image),
+                                          _dptr(out_pt_hist), C.c_void_p(stream.cuda_stream)))
+
 
 def tof_reservoirs_reset(h) -> None:
     _check("tof_reservoirs_reset", lib().tof_reservoirs_reset(h))
@@ -318,6 +336,10 @@ class Renderer:
     def render(self, frame, stream=None):
         tof_render_frame(self.h, frame, self.out_image, self.out_hist, self.out_pt_image, self.out_pt_hist,
                          stream)
+
+    def render_noalloc(self, frame, stream=None):
+        tof_render_frame_noalloc(self.h, frame, self.out_image, self.out_hist, self.out_pt_image, self.out_pt_hist,
+                                 stream)
 
     def fetch(self) -> dict:
         import torch
