@@ -94,6 +94,7 @@ def parse():
     ap.add_argument("--rmse-frames", type=str, default="10,20,30,40,50,60",
                     help="frames of the sequence at which the equal-RMSE comparison is made")
     ap.add_argument("--no-bins-sweep", action="store_true")
+    ap.add_argument("--no-pairwise", action="store_true", help="skip the pairwise-MIS timing leg")
     ap.add_argument("--no-equal-rmse", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=3, help="oracle frames timed for the CPU baseline")
@@ -338,11 +339,45 @@ def main():
     if merge:
         result["merge_hbm"] = merge
 
+    # the same window with pairwise MIS in the spatial pass: frames/s with
+    # timing off, then the kernel groups over the window in a second context
+    if not args.no_pairwise:
+        import dataclasses
+        ps = dataclasses.replace(sensor, mis_mode=1)
+        r = Renderer(wl.scene, ps)
+        for i in range(args.warmup):
+            r.render(frame_at(i))
+        torch.cuda.synchronize()
+        st0 = r.stats()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            r.render(frame_at(args.warmup + k))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st1 = r.stats()
+        r.close()
+        r = Renderer(wl.scene, ps)
+        for i in range(args.warmup):
+            r.render(frame_at(i))
+        torch.cuda.synchronize()
+        r.set_kernel_timing(True)
+        for k in range(args.steps):
+            r.render(frame_at(args.warmup + k))
+        ktp = r.kernel_times()
+        r.close()
+        result["pairwise"] = {"frames_per_s": round(args.steps / el, 3), "ms_per_step": round(1e3 * el / args.steps, 3),
+                              "shifts_per_frame": (st1["shifts"] - st0["shifts"]) // args.steps,
+                              "rays_per_frame": (st1["rays"] - st0["rays"]) // args.steps,
+                              "kernel_ms_per_frame": {k: round(v["ms"] / args.steps, 3) for k, v in ktp.items()
+                                                      if k != "work_items"}}
+
     # equal RMSE against plain ToF PT on the same GPU, over the sequence
     if not args.no_equal_rmse:
-        result["equal_rmse"] = equal_rmse_seq(wl, frame_at, sensor, args, torch, Renderer)
-        result["equal_rmse_gate_only"] = [gate_only(wl, frame_at, args, torch, Renderer, m_init=m)
-                                          for m in (1, 2)]
+        import dataclasses
+        result["equal_rmse"] = equal_rmse_seq(
+            wl, frame_at, [("gbh", sensor), ("pairwise", dataclasses.replace(sensor, mis_mode=1))], args, torch,
+            Renderer)
+        result["equal_rmse_gate_only"] = gate_only(wl, frame_at, args, torch, Renderer)
     if not args.no_bins_sweep:
         result["cost_vs_bins"] = bins_sweep(wl, frame_at, args, torch, Renderer)
     if not args.no_serving:
@@ -478,43 +513,47 @@ def serving(args, torch):
             "mix": {"res": [int(w.sensor.width) for w in wls], "bins": [int(w.sensor.n_bins) for w in wls]}}
 
 
-def equal_rmse_seq(wl, frame_at, sensor, args, torch, Renderer, planes=("gate_image", "histogram")):
+def equal_rmse_seq(wl, frame_at, variants, args, torch, Renderer, planes=("gate_image", "histogram")):
     """Equal RMSE against plain ToF PT on the same GPU, over the sequence.
 
-    ToF ReSTIR renders frames 0..F of the sequence (F = the last frame listed
-    in --rmse-frames); at each listed frame its output is compared with a
-    plain-PT reference of that frame (ref_calls x ref_trees path trees per
-    pixel), whose own variance is removed from the error.  Plain PT at s spp
-    has MSE_1 / s, MSE_1 measured at that frame from four independent 1-spp
-    renders, so the spp that matches ReSTIR is s* = MSE_1 / MSE_restir and its
-    frame time s* t_1, t_1 timed over 20 frames of the sequence.  ReSTIR's
-    frame time is its event time averaged over the listed window.  Speedup =
-    t_PT(s*) / t_ReSTIR per listed frame, and their mean.  Everything stays on
-    the device: the outputs are large (512^2 x 256 bins)."""
+    Each ReSTIR variant (name, sensor) renders frames 0..F of the sequence (F
+    = the last frame listed in --rmse-frames); at each listed frame its output
+    is compared with a plain-PT reference of that frame (ref_calls x
+    ref_trees path trees per pixel), whose own variance is removed from the
+    error.  Plain PT at s spp has MSE_1 / s, MSE_1 measured at that frame from
+    four independent 1-spp renders, so the spp that matches ReSTIR is s* =
+    MSE_1 / MSE_restir and its frame time s* t_1, t_1 timed over 20 frames of
+    the sequence.  ReSTIR's frame time is its event time averaged over the
+    listed window.  Speedup = t_PT(s*) / t_ReSTIR per listed frame, and their
+    mean.  Everything stays on the device: the outputs are large (512^2 x 256
+    bins)."""
     import dataclasses
     fl = sorted(int(x) for x in args.rmse_frames.split(","))
     F = fl[-1]
     keys = [k for k, name in (("image", "gate_image"), ("hist", "histogram")) if name in planes]
-    r = Renderer(wl.scene, sensor)
-    outs = {}
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(F + 1)]
-    for i in range(F + 1):
-        ev[i][0].record()
-        r.render(frame_at(i))
-        ev[i][1].record()
-        if i in fl:
-            outs[i] = {k: getattr(r, "out_" + k).double().clone() for k in keys}
-    torch.cuda.synchronize()
-    r.close()
-    t_restir = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(fl[0], F + 1)])) * 1e-3
-    ref_sensor = dataclasses.replace(sensor, temporal=0, spatial_rounds=0, m_init=args.ref_trees, shrink_k=1.0)
-    pt_sensor = dataclasses.replace(sensor, temporal=0, spatial_rounds=0, m_init=1, shrink_k=1.0)
+    outs, t_restir = {}, {}
+    for name, sensor in variants:
+        r = Renderer(wl.scene, sensor)
+        outs[name] = {}
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(F + 1)]
+        for i in range(F + 1):
+            ev[i][0].record()
+            r.render(frame_at(i))
+            ev[i][1].record()
+            if i in fl:
+                outs[name][i] = {k: getattr(r, "out_" + k).double().clone() for k in keys}
+        torch.cuda.synchronize()
+        r.close()
+        t_restir[name] = float(np.mean([ev[i][0].elapsed_time(ev[i][1]) for i in range(fl[0], F + 1)])) * 1e-3
+    base = variants[0][1]
+    ref_sensor = dataclasses.replace(base, temporal=0, spatial_rounds=0, m_init=args.ref_trees, shrink_k=1.0)
+    pt_sensor = dataclasses.replace(base, temporal=0, spatial_rounds=0, m_init=1, shrink_k=1.0)
     q = Renderer(wl.scene, ref_sensor)
     p = Renderer(wl.scene, pt_sensor)
     ref_spp = args.ref_calls * args.ref_trees
-    per = []
+    mse = {name: [] for name, _ in variants}
     for f in fl:
-        acc = {k: torch.zeros_like(outs[f][k]) for k in keys}
+        acc = {k: torch.zeros_like(outs[variants[0][0]][f][k]) for k in keys}
         for c in range(args.ref_calls):
             q.render(dataclasses.replace(frame_at(f), index=10_000_000 + 1000 * f + c))
             for k in keys:
@@ -525,12 +564,14 @@ def equal_rmse_seq(wl, frame_at, sensor, args, torch, Renderer, planes=("gate_im
             p.render(dataclasses.replace(frame_at(f), index=20_000_000 + 1000 * f + c))
             for k in keys:
                 mse1[k] += float(((getattr(p, "out_pt_" + k).double() - ref[k]) ** 2).mean()) / 4
-        row = {}
-        for k in keys:
-            m1 = mse1[k] * (1.0 - 1.0 / ref_spp)
-            mr = max(float(((outs[f][k] - ref[k]) ** 2).mean()) - mse1[k] / ref_spp, 1e-30)
-            row[k] = (m1, mr)
-        per.append(row)
+        for name, _ in variants:
+            row = {}
+            for k in keys:
+                m1 = mse1[k] * (1.0 - 1.0 / ref_spp)
+                mr = max(float(((outs[name][f][k] - ref[k]) ** 2).mean()) - mse1[k] / ref_spp, 1e-30)
+                row[k] = (m1, mr)
+            mse[name].append(row)
+        del ref, acc
     q.close()
     # plain PT's frame time over consecutive frames (it pays the same geometry update)
     nrep = 20
@@ -542,29 +583,35 @@ def equal_rmse_seq(wl, frame_at, sensor, args, torch, Renderer, planes=("gate_im
     torch.cuda.synchronize()
     t_pt = (time.perf_counter() - t0) / nrep
     p.close()
-    out = {"frames": fl, "reference_spp": ref_spp, "pt_1spp_ms": round(1e3 * t_pt, 3),
-           "restir_ms_per_frame": round(1e3 * t_restir, 3), "restir_frames_per_s": round(1.0 / t_restir, 3)}
-    for k, name in (("image", "gate_image"), ("hist", "histogram")):
-        if k not in keys:
-            continue
-        s_star = [row[k][0] / row[k][1] for row in per]
-        sp = [(x * t_pt) / t_restir for x in s_star]
-        out[name] = {"restir_rmse": [round(math.sqrt(row[k][1]), 8) for row in per],
-                     "pt_1spp_rmse": [round(math.sqrt(row[k][0]), 8) for row in per],
-                     "pt_spp_at_equal_rmse": [round(x, 3) for x in s_star],
-                     "speedup_per_frame": [round(x, 4) for x in sp],
-                     "speedup": round(float(np.mean(sp)), 4)}
-    return out
-
-
-def gate_only(wl, frame_at, args, torch, Renderer, m_init=1):
-    """The same scene and sequence with the gate alone (no histogram bins):
-    the regime the paper targets (a narrow gate), same ReSTIR settings."""
-    import dataclasses
-    sensor = dataclasses.replace(wl.sensor, n_bins=0, m_init=m_init)
-    res = equal_rmse_seq(wl, frame_at, sensor, args, torch, Renderer, planes=("gate_image",))
-    res["m_init"] = m_init
+    res = {"frames": fl, "reference_spp": ref_spp, "pt_1spp_ms": round(1e3 * t_pt, 3)}
+    for name, _ in variants:
+        out = {"restir_ms_per_frame": round(1e3 * t_restir[name], 3),
+               "restir_frames_per_s": round(1.0 / t_restir[name], 3)}
+        for k, pname in (("image", "gate_image"), ("hist", "histogram")):
+            if k not in keys:
+                continue
+            s_star = [row[k][0] / row[k][1] for row in mse[name]]
+            sp = [(x * t_pt) / t_restir[name] for x in s_star]
+            out[pname] = {"restir_rmse": [round(math.sqrt(row[k][1]), 8) for row in mse[name]],
+                          "pt_1spp_rmse": [round(math.sqrt(row[k][0]), 8) for row in mse[name]],
+                          "pt_spp_at_equal_rmse": [round(x, 3) for x in s_star],
+                          "speedup_per_frame": [round(x, 4) for x in sp],
+                          "speedup": round(float(np.mean(sp)), 4)}
+        res[name] = out
     return res
+
+
+def gate_only(wl, frame_at, args, torch, Renderer):
+    """The same scene and sequence with the gate alone (no histogram bins):
+    the regime the paper targets (a narrow gate), same reuse settings, with 1
+    and 2 path trees per pixel and with either MIS of the spatial pass."""
+    import dataclasses
+    variants = []
+    for m_init in (1, 2):
+        for mis in (0, 1):
+            name = f"m_init{m_init}_" + ("pairwise" if mis else "gbh")
+            variants.append((name, dataclasses.replace(wl.sensor, n_bins=0, m_init=m_init, mis_mode=mis)))
+    return equal_rmse_seq(wl, frame_at, variants, args, torch, Renderer, planes=("gate_image",))
 
 
 def bins_sweep(wl, frame_at, args, torch, Renderer, bins=(4, 16, 64, 256), warm=5, timed=5):

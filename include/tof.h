@@ -140,6 +140,13 @@ typedef struct {
                                         another root or fail one way only near paths whose length is
                                         stationary on the chart (the first return of a confocal scan), which
                                         biases the reuse upward there.  0: no check; 0 or 1 */
+    int32_t mis_mode;                /* MIS weights of the spatial reuse passes: 0 the generalized balance
+                                        heuristic (Sec. 3.2.3, eq. GRIS_MIS_weight); 1 pairwise MIS, the
+                                        canonical technique split into as many parts as there are
+                                        neighbours, each part paired with one neighbour under the balance
+                                        heuristic and the pair weighted by its share of the confidence
+                                        (also unbiased; K MIS shifts per pixel-plane instead of K (K + 1)).
+                                        Temporal and bin-axis reuse use the former in both */
 } tof_sensor_desc;
 
 /* Per-frame poses.  object_xforms: host [num_objects*12], rigid 3x4 row-major

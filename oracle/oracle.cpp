@@ -147,6 +147,40 @@ struct ChartEval {
 
 struct BNode { double lo[3], hi[3]; int left, right, first, count; };
 
+// ---------------------------------------------------------------------------
+// MIS weight of technique t at a path y of the pixel's domain (Sec. 3.2.3,
+// eq. GRIS_MIS_weight): t = -1 the canonical technique, t = j a neighbour's.
+// M[l] < 0 marks a neighbour without a pixel; d[l] is domain l's density term
+// at y (phat_l of y shifted into l, times |J|; for t = j the stored
+// phat_j(x_j) / |J_{j->q}|), dc = phat_q(y), mq the canonical confidence.
+// Generalized balance heuristic: M_t d_t / (mq dc + sum_l M_l d_l).  Pairwise
+// (opt-in): the canonical technique is split into Kv parts of confidence
+// mq / Kv, part l paired with neighbour l under the balance heuristic, pair l
+// weighted by (M_l + mq / Kv) / (mq + sum_l M_l); a neighbour's weight needs
+// only its own term and dc.
+// ---------------------------------------------------------------------------
+double mis_weight(int mode, int t, int K, const double* M, double mq, const double* d, double dc) {
+    int kv = 0;
+    double mtot = mq;
+    for (int l = 0; l < K; ++l)
+        if (M[l] >= 0.0) {
+            ++kv;
+            mtot += M[l];
+        }
+    if (mode == 1 && kv > 0) {
+        const double mqk = mq / kv;
+        if (t >= 0) return (M[t] + mqk) / mtot * (M[t] * d[t] / (M[t] * d[t] + mqk * dc));
+        double m = 0.0;
+        for (int l = 0; l < K; ++l)
+            if (M[l] >= 0.0) m += (M[l] + mqk) / mtot * (mqk * dc / (mqk * dc + M[l] * d[l]));
+        return m;
+    }
+    double den = mq * dc;
+    for (int l = 0; l < K; ++l)
+        if (M[l] >= 0.0) den += M[l] * d[l];
+    return (t >= 0 ? M[t] * d[t] : mq * dc) / den;
+}
+
 struct FrameGeom {
     bool valid = false;
     int index = 0;
@@ -1636,6 +1670,12 @@ struct Oracle {
             std::sort(planes.begin(), planes.end());
             planes.erase(std::unique(planes.begin(), planes.end()), planes.end());
             uint64_t fp = full_pixel(pix);
+            // confidences of the domains (-1: no neighbour pixel); pairwise
+            // MIS shifts only the canonical sample into the neighbours
+            std::vector<double> Ml(K, -1.0), dl(K, 0.0);
+            for (int l = 0; l < K; ++l)
+                if (nb[l] >= 0) Ml[l] = ms[l];
+            const bool pairwise = s.mis_mode == 1;
             for (int pl : planes) {
                 double ws = 0.0;
                 bool have = false;
@@ -1648,13 +1688,13 @@ struct Oracle {
                 if (itq != in[pix].end()) {
                     const Res& xr = itq->second;
                     double ph = xr.y.phat;
-                    double den = mq * ph;
                     for (int l = 0; l < K; ++l) {
+                        dl[l] = 0.0;
                         if (nb[l] < 0) continue;
                         ShiftOut sh = shift(xr.y, 0, pix, 0, nb[l], pl, 0.0, st);
-                        if (sh.ok) den += ms[l] * sh.phat * sh.J;
+                        if (sh.ok) dl[l] = sh.phat * sh.J;
                     }
-                    double w = (mq * ph / den) * ph * xr.W;
+                    double w = mis_weight(s.mis_mode, -1, K, Ml.data(), mq, dl.data(), ph) * ph * xr.W;
                     ws += w;
                     if (uni(0) * ws < w) { sel = xr.y; have = true; }
                 }
@@ -1665,14 +1705,14 @@ struct Oracle {
                     const Res& xr = itj->second;
                     ShiftOut sh = shift(xr.y, 0, nb[j], 0, pix, pl, 0.0, st);
                     if (!sh.ok) continue;
-                    double a = ms[j] * xr.y.phat / sh.J;
-                    double den = a + mq * sh.phat;
                     for (int l = 0; l < K; ++l) {
-                        if (l == j || nb[l] < 0) continue;
+                        dl[l] = 0.0;
+                        if (l == j || nb[l] < 0 || pairwise) continue;
                         ShiftOut t2 = shift(sh.y, 0, pix, 0, nb[l], pl, 0.0, st);
-                        if (t2.ok) den += ms[l] * t2.phat * t2.J;
+                        if (t2.ok) dl[l] = t2.phat * t2.J;
                     }
-                    double w = (a / den) * sh.phat * xr.W * sh.J;
+                    dl[j] = xr.y.phat / sh.J;
+                    double w = mis_weight(s.mis_mode, j, K, Ml.data(), mq, dl.data(), sh.phat) * sh.phat * xr.W * sh.J;
                     ws += w;
                     if (uni(j + 1) * ws < w) { sel = sh.y; have = true; }
                 }
@@ -1871,6 +1911,11 @@ int orc_trace(void* ctx, const double o3[3], const double d3[3], int brute_force
     out[2] = v.xi[0];
     out[3] = v.xi[1];
     return h.prim;
+}
+
+void orc_mis_weights(int mode, int K, const double* M, double mq, const double* d, double dc, double* out) {
+    out[0] = mis_weight(mode, -1, K, M, mq, d, dc);
+    for (int j = 0; j < K; ++j) out[1 + j] = M[j] >= 0.0 ? mis_weight(mode, j, K, M, mq, d, dc) : 0.0;
 }
 
 int orc_occluded(void* ctx, const double o3[3], const double d3[3], double tmax) {

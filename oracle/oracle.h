@@ -53,6 +53,7 @@ typedef struct {
     double shrink_r;              /* fraction R of the path trees sampled from the wide gate (1 = all) */
     int32_t domain;               /* 0: planes over path length; 1: over path velocity u = -dl/dt (Doppler) */
     int32_t round_trip;           /* keep a Newton shift only if the inverse shift returns to the source vertex */
+    int32_t mis_mode;             /* spatial reuse: 0 generalized balance heuristic, 1 pairwise MIS */
     uint64_t seed;
 } orc_sensor;
 
@@ -139,6 +140,13 @@ int orc_newton(void* ctx, int obj, const double xi[2], const double a_src[3], co
  * dU/dv, d2U/du2, d2U/dudv, d2U/dv2}.  Returns 1 if the chart point exists. */
 int orc_vel_eval(void* ctx, int obj, const double xi[2], const double a[3], const double va[3], const double b[3],
                  const double vb[3], double c, double out[6]);
+
+/* MIS weights of the spatial reuse at one path y of the pixel's domain
+ * (mode 0 generalized balance heuristic, 1 pairwise): out[0] the canonical
+ * technique's, out[1 + j] neighbour j's; M[j] < 0 marks a neighbour without
+ * a pixel (weight 0), d[j] domain j's density term at y, dc the canonical
+ * target at y, mq the canonical confidence. */
+void orc_mis_weights(int mode, int K, const double* M, double mq, const double* d, double dc, double* out);
 
 /* Weighted reservoir streaming of n candidate weights with uniforms u. */
 int orc_wrs(const double* w, const double* u, int n, double* w_sum);

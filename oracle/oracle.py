@@ -39,7 +39,7 @@ class OrcSensor(C.Structure):
                 ("newton_tol_rel", C.c_double), ("newton_max_iter", C.c_int32),
                 ("j_max", C.c_double), ("shift_mode", C.c_int32), ("include_direct", C.c_int32),
                 ("debug_stage", C.c_int32), ("bin_radius", C.c_int32),
-                ("shrink_k", C.c_double), ("shrink_r", C.c_double), ("domain", C.c_int32), ("round_trip", C.c_int32),
+                ("shrink_k", C.c_double), ("shrink_r", C.c_double), ("domain", C.c_int32), ("round_trip", C.c_int32), ("mis_mode", C.c_int32),
                 ("seed", C.c_uint64)]
 
 
@@ -84,6 +84,8 @@ def lib():
         _lib.orc_bsdf.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p, _f64p, C.c_int, _f64p]
         _lib.orc_bsdf_sample.restype = C.c_int
         _lib.orc_bsdf_sample.argtypes = [C.c_void_p, C.c_int, _f64p, _f64p, _f64p, C.c_int, _f64p, _f64p]
+        _lib.orc_mis_weights.restype = None
+        _lib.orc_mis_weights.argtypes = [C.c_int, C.c_int, _f64p, C.c_double, _f64p, C.c_double, _f64p]
         _lib.orc_wrs.restype = C.c_int
         _lib.orc_wrs.argtypes = [_f64p, _f64p, C.c_int, _f64p]
     return _lib
@@ -111,6 +113,15 @@ def wrs(w, u):
     ws = C.c_double(0.0)
     sel = lib().orc_wrs(_p(w, _f64p), _p(u, _f64p), len(w), C.byref(ws))
     return sel, ws.value
+
+
+def mis_weights(mode, M, mq, d, dc):
+    """MIS weights [canonical, neighbour 0..K-1] of the spatial reuse at one path."""
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    out = np.zeros(len(M) + 1)
+    lib().orc_mis_weights(int(mode), len(M), _p(M, _f64p), float(mq), _p(d, _f64p), float(dc), _p(out, _f64p))
+    return out
 
 
 def make_frame(fr):

@@ -479,6 +479,13 @@ __global__ void __launch_bounds__(256) k_tasks(const uint2* __restrict__ items, 
 // l has no pixel, or for the candidate's own domain l = c - 1).
 //
 // The merge forms m_c = (own or M_q phat_q) / (own + M_q phat_q + sum terms).
+//
+// Pairwise MIS (spatial pass, opt-in): the canonical technique is split into
+// Kv parts of confidence M_q / Kv (Kv = neighbours with a pixel), part l
+// paired with neighbour l under the balance heuristic and the pair weighted
+// by (M_l + M_q / Kv) / M_total.  A neighbour's candidate needs only its own
+// forward terms, so only the canonical task has MIS shifts (K per item in
+// place of K (K + 1)).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int cand_src(int mode, const int* links, int P, int pix, int c) {
     return mode == 0 ? links[pix] : (mode == 1 ? links[(size_t)(c - 1) * P + pix] : pix);
@@ -550,7 +557,8 @@ __global__ void __launch_bounds__(kTB) k_mis_list(FrameArgs a, int mode, const i
         const int c = (int)task.y;
         const uint2 item = items[task.x];
         const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
-        const bool open = c == 0 || fwd[t].x > 0.f;
+        // pairwise MIS: only the canonical sample is shifted into the neighbours
+        const bool open = c == 0 || (fwd[t].x > 0.f && !(mode == 1 && a.s.mis_mode == 1));
         for (uint32_t l = 0; l < K; ++l) {
             term[(size_t)t * K + l] = 0.f;
             bool dom;
@@ -707,6 +715,23 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
         const uint32_t t0 = task0[it] - tb;
         const uint64_t fp = full_pixel(s, pix);
         const float mq = A.M[pix];
+        // pairwise MIS: the neighbours' confidences and the canonical share
+        const bool pw = mode == 1 && s.mis_mode == 1;
+        float ml[kMaxK];
+        float mtot = mq, mqk = mq;
+        int kv = 0;
+        if (pw) {
+            for (int l = 0; l < K; ++l) {
+                const int dp = links[(size_t)l * P + pix];
+                ml[l] = dp >= 0 ? A.M[dp] : -1.f;   // -1: no neighbour pixel
+                if (dp >= 0) {
+                    mtot += ml[l];
+                    ++kv;
+                }
+            }
+            if (kv > 0) mqk = mq / (float)kv;
+        }
+        const bool pairwise = pw && kv > 0;
         Draw ut;
         if (mode == 0) ut = philox(s.seed, fp, a.frame, PASS_TEMPORAL, 0, (uint64_t)pl);
         float ws = 0.f, sel_phat = 0.f;
@@ -722,9 +747,22 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
             const float4 fw = fwd[t];
             const float phq = fw.x;
             if (c > 0 && !(phq > 0.f)) continue;   // the shift into q failed
-            float den = fw.z + mq * phq;
-            for (int l = 0; l < K; ++l) den += term[(size_t)t * K + l];
-            const float w = ((c == 0 ? mq * phq : fw.z) / den) * phq * fw.w * fw.y;
+            float m;
+            if (pairwise) {
+                if (c == 0) {
+                    m = 0.f;
+                    const float qk = mqk * phq;
+                    for (int l = 0; l < K; ++l)
+                        if (ml[l] >= 0.f) m += (ml[l] + mqk) / mtot * (qk / (qk + term[(size_t)t * K + l]));
+                } else {
+                    m = (ml[c - 1] + mqk) / mtot * (fw.z / (fw.z + mqk * phq));
+                }
+            } else {
+                float den = fw.z + mq * phq;
+                for (int l = 0; l < K; ++l) den += term[(size_t)t * K + l];
+                m = (c == 0 ? mq * phq : fw.z) / den;
+            }
+            const float w = m * phq * fw.w * fw.y;
             if (c > 0 && !(w > 0.f)) continue;
             float u;
             if (mode == 0) {

@@ -688,7 +688,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
               d->bin_radius >= 0 && d->bin_radius <= 4 && std::isfinite(d->shrink_k) && d->shrink_k >= 1.f &&
               d->shrink_k <= 1000.f && std::isfinite(d->shrink_r) && d->shrink_r >= 0.f && d->shrink_r <= 1.f &&
               (d->domain == TOF_DOMAIN_TIME || d->domain == TOF_DOMAIN_VELOCITY) &&
-              (d->round_trip == 0 || d->round_trip == 1) &&
+              (d->round_trip == 0 || d->round_trip == 1) && (d->mis_mode == 0 || d->mis_mode == 1) &&
               (d->domain == TOF_DOMAIN_TIME || (d->bin_radius == 0 && d->shrink_k == 1.f)) &&
               std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
     // work-list entries (tasks of a pass over fully occupied planes) are 32-bit indices
@@ -788,6 +788,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     s.j_max = d->j_max;
     s.shift_mode = d->shift_mode;
     s.round_trip = d->round_trip;
+    s.mis_mode = d->mis_mode;
     s.include_direct = d->include_direct;
     s.debug_stage = d->debug_stage;
     s.br = d->bin_radius;

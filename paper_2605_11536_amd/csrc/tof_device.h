@@ -137,6 +137,7 @@ struct Sens {
     int mw;                  // path trees sampling the wide gate (R x M_init; all = R 1, shrink only)
     int domain;              // planes over 0: path length, 1: path velocity
     int round_trip;          // keep a Newton shift only if its inverse returns to the source vertex
+    int mis_mode;            // spatial reuse: 0 generalized balance heuristic, 1 pairwise MIS
     int P, B, mask_words;
     uint64_t seed;
 };

@@ -44,6 +44,8 @@ STAGE_TEMPORAL = 1
 STAGE_CANONICAL = 0
 DOMAIN_TIME = 0
 DOMAIN_VELOCITY = 1
+MIS_GBH = 0
+MIS_PAIRWISE = 1
 
 f32 = np.float32
 
@@ -112,6 +114,7 @@ class Sensor:
     shrink_r: float = 1.0          # fraction of the path trees sampled from the wide gate (R < 1: MIS with the gate)
     domain: int = DOMAIN_TIME      # planes over path length (time) or path velocity (Doppler)
     round_trip: int = 1            # keep a Newton shift only if its inverse returns to the source vertex
+    mis_mode: int = MIS_GBH        # spatial reuse weights: generalized balance heuristic or pairwise
     seed: int = 0
 
     def __post_init__(self):

@@ -48,7 +48,7 @@ class tof_sensor_desc(C.Structure):
                 ("newton_tol_rel", C.c_float), ("newton_max_iter", C.c_int32), ("j_max", C.c_float),
                 ("shift_mode", C.c_int32), ("include_direct", C.c_int32), ("debug_stage", C.c_int32), ("bin_radius", C.c_int32),
                 ("shrink_k", C.c_float), ("domain", C.c_int32), ("shrink_r", C.c_float),
-                ("round_trip", C.c_int32)]
+                ("round_trip", C.c_int32), ("mis_mode", C.c_int32)]
 
 
 class tof_frame_desc(C.Structure):

@@ -254,6 +254,19 @@ def test_glossy_dynamic_crop_parity():
     _run_pair(w)
 
 
+def test_pairwise_mis_parity():
+    """Pairwise MIS in the spatial pass (only the canonical sample is shifted
+    into the neighbours): the box with temporal and spatial reuse, and the
+    64x64 crop of the 512^2 glossy scene."""
+    for w in (scenes.cornell_box(frames=4, mis_mode=scenes.MIS_PAIRWISE),
+              scenes.glossy_dynamic(width=64, height=64, full_width=512, full_height=512, crop_x0=224, crop_y0=200,
+                                    frames=3, mis_mode=scenes.MIS_PAIRWISE)):
+        gs, os_ = _run_pair(w)
+        assert gs["shifts"] > 0
+        for k in ("shifts", "newton_attempts", "newton_converged", "newton_paths_ok"):
+            assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
+
+
 def test_glossy_dynamic_full_size_sampled_parity():
     """The benchmark's launch configuration: full 512x512 frames with 256 bins
     + gate on the GPU (the same chunked passes as bench.py), compared on the

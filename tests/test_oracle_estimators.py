@@ -93,9 +93,12 @@ def test_sphere_interior_closed_form_plain_pt(oracle_lib, bounces):
     assert abs(mean.sum() - exp.sum()) < 4 * math.sqrt((se ** 2).sum())
 
 
-def test_sphere_interior_closed_form_restir(oracle_lib):
+@pytest.mark.parametrize("mis", [scenes.MIS_GBH, scenes.MIS_PAIRWISE], ids=["gbh", "pairwise"])
+def test_sphere_interior_closed_form_restir(oracle_lib, mis):
     """ReSTIR (temporal + spatial, path-length-aware shift on the curved
-    sphere chart) matches the closed form in expectation over seeds."""
+    sphere chart) matches the closed form in expectation over seeds, with
+    the generalized balance heuristic and with pairwise MIS in the spatial
+    pass."""
     R, rho, I = 1.0, 0.5, 1.0
     nb = 20
     lo = 2 * R + 0.1 * np.arange(nb)
@@ -103,7 +106,7 @@ def test_sphere_interior_closed_form_restir(oracle_lib):
     per = []
     for seed in range(16):
         w = scenes.lambert_sphere_interior(radius=R, albedo=rho, intensity=I, width=24, height=24,
-                                           n_bins=nb, frames=3, seed=seed)
+                                           n_bins=nb, frames=3, seed=seed, mis_mode=mis)
         o = oracle_lib.Oracle(w.scene, w.sensor)
         for fr in w.frames:
             out = o.render(fr)
@@ -157,13 +160,15 @@ def _assert_unbiased(R, Pt, min_entries=500):
     assert frac <= 0.005, frac
 
 
-@pytest.mark.parametrize("variant", ["pathlen", "newton_fails", "naive"])
+@pytest.mark.parametrize("variant", ["pathlen", "newton_fails", "naive", "pairwise"])
 def test_restir_unbiased_against_plain_pt(oracle_lib, variant):
     kw = {}
     if variant == "newton_fails":
         kw = dict(newton_max_iter=0)
     elif variant == "naive":
         kw = dict(shift_mode=scenes.SHIFT_NAIVE)
+    elif variant == "pairwise":
+        kw = dict(mis_mode=scenes.MIS_PAIRWISE)
     R, Pt = _unbiased_case(oracle_lib, 256, **kw)
     _assert_unbiased(R, Pt)
 

@@ -317,3 +317,29 @@ def test_wrs_selection_frequencies(oracle_lib):
     assert counts[~mask].sum() == 0
     chi2 = ((counts[mask] - exp[mask]) ** 2 / exp[mask]).sum()
     assert chi2 < 20.5      # 99.9% quantile of chi2(4)
+
+
+def test_mis_weights_partition_of_unity(oracle_lib):
+    """P7: at any path, the MIS weights of all techniques of a spatial reuse
+    sum to one (Sec. 3.2.3: the condition for GRIS to be unbiased), for the
+    generalized balance heuristic and for pairwise MIS, with unequal
+    confidences, neighbours without a pixel and failed shifts; plus weights
+    worked by hand."""
+    mw = oracle_lib.mis_weights
+    rng = np.random.default_rng(2)
+    for mode in (0, 1):
+        for _ in range(300):
+            K = int(rng.integers(1, 9))
+            M = rng.uniform(0.5, 20.0, K)
+            M[rng.random(K) < 0.2] = -1.0
+            d = rng.exponential(1.0, K) * (rng.random(K) > 0.25)
+            w = mw(mode, M, float(rng.uniform(0.5, 20.0)), d, float(rng.exponential(1.0) + 1e-3))
+            assert abs(w.sum() - 1.0) < 1e-12, (mode, w)
+            assert np.all(w >= 0.0) and np.all(w[1:][M < 0] == 0.0)
+    M, mq, d, dc = [1.0, 3.0], 2.0, [0.5, 0.25], 1.0
+    # balance heuristic: M_t d_t / (mq dc + sum M_l d_l), den = 3.25
+    assert np.allclose(mw(0, M, mq, d, dc), [2 / 3.25, 0.5 / 3.25, 0.75 / 3.25], rtol=1e-14)
+    # pairwise: mq split in two parts of 1; pair weights (M_l + 1) / 6
+    assert np.allclose(mw(1, M, mq, d, dc), [38 / 63, 1 / 9, 2 / 7], rtol=1e-14)
+    # one neighbour: pairwise is the balance heuristic
+    assert np.allclose(mw(1, [3.0, -1.0], 2.0, [0.4, 0.0], 0.7), mw(0, [3.0, -1.0], 2.0, [0.4, 0.0], 0.7))
