@@ -323,6 +323,11 @@ def main():
                                "frac": round(sp_bytes / sp_s / 1e9 / HBM_PEAK_GBS, 4),
                                "bytes_per_launch": int(sp_bytes), "occupancy": round(occ, 5),
                                "avg_launch_ms": round(sp_s * 1e3, 4), "traffic": measured_traffic("splat")}
+        if result["splat_hbm"]["traffic"]:
+            # what the counters say the kernel moves (whole cache lines, not only the algorithmic bytes)
+            tb = result["splat_hbm"]["traffic"]["bytes_per_launch"]
+            result["splat_hbm"]["measured_GBs"] = round(tb / sp_s / 1e9, 1)
+            result["splat_hbm"]["measured_frac"] = round(tb / sp_s / 1e9 / HBM_PEAK_GBS, 4)
 
     # ... and the resampling merge, from its algorithmic bytes per item and task
     merge = {}
@@ -336,6 +341,10 @@ def main():
                           "bytes_per_frame": int(mb / max(args.steps, 1)),
                           "ms_per_frame": round(kms[g] / max(args.steps, 1), 3), "launches": kl[g],
                           "traffic": measured_traffic(g)}
+            if merge[pas]["traffic"]:
+                tgbs = merge[pas]["traffic"]["bytes_per_launch"] * kl[g] / (kms[g] * 1e-3) / 1e9
+                merge[pas]["measured_GBs"] = round(tgbs, 1)
+                merge[pas]["measured_frac"] = round(tgbs / HBM_PEAK_GBS, 4)
     if merge:
         result["merge_hbm"] = merge
 
