@@ -97,8 +97,8 @@ def parse():
     ap.add_argument("--no-pairwise", action="store_true", help="skip the pairwise-MIS timing leg")
     ap.add_argument("--no-equal-rmse", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=3, help="oracle frames timed for the CPU baseline")
-    ap.add_argument("--cpu-crop", type=int, default=128, help="side of the oracle's crop for the CPU baseline")
+    ap.add_argument("--cpu-frames", type=int, default=4, help="oracle frames timed for the CPU baseline")
+    ap.add_argument("--cpu-crop", type=int, default=256, help="side of the oracle's crop for the CPU baseline")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run the serving leg alone")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -130,7 +130,7 @@ def cpu_baseline(width, first, count, crop):
     Headline: frames 0..first+count-1 of the benchmark sequence rendered on a
     crop x crop window at the image centre with every host thread, the last
     `count` timed (the frames the GPU's timed window starts with), the rate
-    divided by the pixel ratio.  Beside it: one thread on a 64x64 crop (one
+    divided by the pixel ratio.  Beside it: one thread on a 128x128 crop (one
     frame, after the same history), the tiny box configuration in full (64x64,
     4 frames) and the first 4 frames of the NLOS configuration in full (64x64
     scan, 50k-triangle torus, 1024 bins)."""
@@ -160,8 +160,8 @@ def cpu_baseline(width, first, count, crop):
                               crop_y0=x0, frames=first + count)
     times, shifts = run(w, nt, first)
     scale = (width * width) / float(crop * crop)
-    c1 = (width - 64) // 2
-    w1 = scenes.glossy_dynamic(width=64, height=64, full_width=width, full_height=width, crop_x0=c1, crop_y0=c1,
+    c1 = (width - 128) // 2
+    w1 = scenes.glossy_dynamic(width=128, height=128, full_width=width, full_height=width, crop_x0=c1, crop_y0=c1,
                                frames=first + 1)
     t1, _ = run(w1, 1, first)
     tb, _ = run(scenes.cornell_box(frames=4), nt, 0)
@@ -172,8 +172,8 @@ def cpu_baseline(width, first, count, crop):
                       f"rate divided by the pixel ratio {scale:g}; the crop clips the 30 px spatial disk at its "
                       f"border, so it does somewhat less work per pixel than the full frame",
             "shifts_per_s": round(shifts / sum(times), 1),
-            "one_thread": {"frames_per_s": round(1.0 / (t1[0] * (width * width) / 4096.0), 6),
-                           "sample": f"64x64 crop at ({c1},{c1}), frame {first} timed ({round(t1[0], 3)} s), "
+            "one_thread": {"frames_per_s": round(1.0 / (t1[0] * (width * width) / 16384.0), 6),
+                           "sample": f"128x128 crop at ({c1},{c1}), frame {first} timed ({round(t1[0], 3)} s), "
                                      f"rate divided by the pixel ratio"},
             "tiny_box_64x64_4_frames_s": round(sum(tb), 4),
             "nlos_64x64_1024_bins_s_per_frame": [round(t, 3) for t in tn]}
@@ -612,11 +612,12 @@ def equal_rmse_seq(wl, frame_at, variants, args, torch, Renderer, planes=("gate_
 
 def gate_only(wl, frame_at, args, torch, Renderer):
     """The same scene and sequence with the gate alone (no histogram bins):
-    the regime the paper targets (a narrow gate), same reuse settings, with 1
-    and 2 path trees per pixel and with either MIS of the spatial pass."""
+    the regime the paper targets (a narrow gate), same reuse settings, with 1,
+    2 and 4 path trees per pixel (initial candidates) and with either MIS of
+    the spatial pass."""
     import dataclasses
     variants = []
-    for m_init in (1, 2):
+    for m_init in (1, 2, 4):
         for mis in (0, 1):
             name = f"m_init{m_init}_" + ("pairwise" if mis else "gbh")
             variants.append((name, dataclasses.replace(wl.sensor, n_bins=0, m_init=m_init, mis_mode=mis)))

@@ -1465,7 +1465,10 @@ struct NewtonOut {
 };
 
 // Endpoints a, b carry velocities va, vb (read in the velocity domain only).
-template <typename T, bool VEL>
+// JAC = false: the caller needs only the solution (the round trip of a
+// shift); the implicit-function Jacobian's area factor is not formed (the
+// determinant of dF/dxi' is still tested, as part of convergence).
+template <typename T, bool VEL, bool JAC = true>
 __device__ inline NewtonOut newton_solve(const SceneDev& S, const SlotDev& GS, const SlotDev& GD, int obj, T xs0,
                                          T xs1, T3<T> as, T3<T> vas, T3<T> bs, T3<T> vbs, T cs, T3<T> ad, T3<T> vad,
                                          T3<T> bd, T3<T> vbd, T cd, T dl0, T tol, int maxit) {
@@ -1529,6 +1532,12 @@ __device__ inline NewtonOut newton_solve(const SceneDev& S, const SlotDev& GS, c
     const double detd = Jd00 * Jd11 - Jd01 * Jd10;
     const double dets = Js00 * Js11 - Js01 * Js10;
     if (fabs(detd) < 1e-12) return out;
+    out.conv = true;
+    out.xi0 = (float)xp0;
+    out.xi1 = (float)xp1;
+    out.iters = it;
+    out.det_area = 0.0;
+    if (!JAC) return out;
     // chart -> surface: sqrt(det J'^T J') / sqrt(det J^T J)
     const ChartT<T> cd_ = chart_eval_t<T>(S, GD, obj, xp0, xp1);
     const ChartT<T> cs_ = chart_eval_t<T>(S, GS, obj, xs0, xs1);
@@ -1712,7 +1721,7 @@ __device__ __forceinline__ ShiftOut shift_path(const Sens& s, const SceneDev& S,
                 // only if the inverse shift (source and destination swapped,
                 // Delta l negated) brings the vertex back to the source's
                 // reconnection vertex, within the reconnection distance
-                const NewtonOut bk = newton_solve<NReal, VEL>(S, GD, GS, obj, (NReal)no.xi0, (NReal)no.xi1, yk, vyk,
+                const NewtonOut bk = newton_solve<NReal, VEL, false>(S, GD, GS, obj, (NReal)no.xi0, (NReal)no.xi1, yk, vyk,
                                                               p2d, vp2dn, c_dst, xk, vxk, p2s, vp2s, c_src,
                                                               -(NReal)dl0, tol, s.max_it);
                 if (!bk.conv) return R;
