@@ -99,6 +99,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=4, help="oracle frames timed for the CPU baseline")
     ap.add_argument("--cpu-crop", type=int, default=256, help="side of the oracle's crop for the CPU baseline")
+    ap.add_argument("--no-c5", action="store_true", help="skip the near-specular stress leg")
+    ap.add_argument("--c5-only", action="store_true", help="run the near-specular stress leg alone")
+    ap.add_argument("--c5-width", type=int, default=1280)
+    ap.add_argument("--c5-height", type=int, default=720)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run the serving leg alone")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -189,6 +193,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serving_only:
         print(json.dumps({"serving": serving(args, torch)}), flush=True)
+        return
+    if args.c5_only:
+        print(json.dumps({"specular_stress": specular_stress_leg(args, torch)}), flush=True)
         return
     from paper_2605_11536_amd import scenes
     from paper_2605_11536_amd.tof import Renderer
@@ -391,6 +398,8 @@ def main():
         result["cost_vs_bins"] = bins_sweep(wl, frame_at, args, torch, Renderer)
     if not args.no_serving:
         result["serving"] = serving(args, torch)
+    if not args.no_c5:
+        result["specular_stress"] = specular_stress_leg(args, torch)
     if args.copy_probe:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
         # the scale from counter units to bytes for the traffic figure
@@ -408,48 +417,67 @@ def main():
 
 SERVE_RES = (128, 256, 512, 1024)
 SERVE_BINS = (1, 64, 256)
+SERVE_NLOS_SCAN = (32, 64)
+SERVE_NLOS_BINS = (256, 1024)
 
 
 def serving(args, torch):
-    """Batched serving: render streams arrive as a Poisson process; each is a
-    box scene of the tiny-workload generator with its own seed, a resolution
-    drawn from SERVE_RES, a gate width from U[0.01, 0.2] and a bin count from
-    SERVE_BINS (bins over path lengths [2, 8]), and asks for `serve_frames`
+    """Batched serving: streams arrive as a Poisson process.  Three in four are
+    render streams: a box scene of the tiny-workload generator with its own
+    seed, a resolution drawn from SERVE_RES, a gate width from U[0.01, 0.2]
+    and a bin count from SERVE_BINS (bins over path lengths [2, 8]).  One in
+    four is an NLOS simulation: a confocal scan of the relay wall with the
+    hidden torus (12.5k triangles), SERVE_NLOS_SCAN scan points per side and
+    SERVE_NLOS_BINS bins of 0.004 from the wall.  Each asks for `serve_frames`
     frames, one every `serve_period_ms` from its arrival (open loop).  The
     server admits streams by HBM footprint; a frame's latency runs from its
-    scheduled submission to its completion (admission wait included).  The
-    host loop submits due frames, polls tickets and closes a stream once its
-    last frame is done."""
+    scheduled submission to its completion (admission wait included); its
+    service time is the GPU time between the start and the end of its work on
+    its HIP stream (under the load of the others), its queueing delay the
+    rest.  The host loop submits due frames, polls tickets and closes a
+    stream once its last frame is done."""
     from paper_2605_11536_amd import scenes
     from paper_2605_11536_amd.tof import Renderer, Server, tof_footprint
     rng = np.random.default_rng(args.serve_seed)
     n, F, period = args.serve_streams, args.serve_frames, args.serve_period_ms * 1e-3
-    wls, fps_ = [], []
+
+    def render_stream(W, nb, gw, seed):
+        return scenes.cornell_box(width=W, height=W, frames=F, seed=seed, gate_width=gw, n_bins=nb, bin_t0=2.0,
+                                  bin_width=6.0 / nb)
+
+    def nlos_stream(scan, nb, seed):
+        return scenes.nlos_confocal(scan=scan, frames=F, seed=seed, torus_nu=125, torus_nv=50, n_bins=nb)
+
+    wls, fps_, kinds = [], [], []
     for i in range(n):
-        W = int(rng.choice(SERVE_RES))
-        nb = int(rng.choice(SERVE_BINS))
-        gw = float(rng.uniform(0.01, 0.2))
-        wl = scenes.cornell_box(width=W, height=W, frames=F, seed=1000 + i, gate_width=gw, n_bins=nb,
-                                bin_t0=2.0, bin_width=6.0 / nb)
+        if rng.random() < 0.25:
+            wl = nlos_stream(int(rng.choice(SERVE_NLOS_SCAN)), int(rng.choice(SERVE_NLOS_BINS)), 1000 + i)
+            kinds.append("nlos")
+        else:
+            W = int(rng.choice(SERVE_RES))
+            nb = int(rng.choice(SERVE_BINS))
+            wl = render_stream(W, nb, float(rng.uniform(0.01, 0.2)), 1000 + i)
+            kinds.append("render")
         wls.append(wl)
         fps_.append(tof_footprint(wl.scene, wl.sensor))
-    # solo frame time of every (resolution, bins) class: one stream alone,
-    # frames 1..F-1 timed; the mix draws the classes uniformly
+    # solo frame time of every class: one stream alone, frames 1..F-1 timed;
+    # the mix draws render classes uniformly, NLOS classes uniformly
     solo = {}
-    for W in SERVE_RES:
-        for nb in SERVE_BINS:
-            wl = scenes.cornell_box(width=W, height=W, frames=F, seed=1, gate_width=0.1, n_bins=nb, bin_t0=2.0,
-                                    bin_width=6.0 / nb)
-            r = Renderer(wl.scene, wl.sensor)
-            r.render(wl.frames[0])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for fr in wl.frames[1:]:
-                r.render(fr)
-            torch.cuda.synchronize()
-            solo[f"{W}x{nb}"] = (time.perf_counter() - t0) / max(F - 1, 1)
-            r.close()
-    mean_solo = float(np.mean(list(solo.values())))
+    classes = [(f"{W}x{nb}", render_stream(W, nb, 0.1, 1)) for W in SERVE_RES for nb in SERVE_BINS]
+    classes += [(f"nlos{sc}x{nb}", nlos_stream(sc, nb, 1)) for sc in SERVE_NLOS_SCAN for nb in SERVE_NLOS_BINS]
+    for name, wl in classes:
+        r = Renderer(wl.scene, wl.sensor)
+        r.render(wl.frames[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for fr in wl.frames[1:]:
+            r.render(fr)
+        torch.cuda.synchronize()
+        solo[name] = (time.perf_counter() - t0) / max(F - 1, 1)
+        r.close()
+    mean_render = float(np.mean([v for k, v in solo.items() if not k.startswith("nlos")]))
+    mean_nlos = float(np.mean([v for k, v in solo.items() if k.startswith("nlos")]))
+    mean_solo = 0.75 * mean_render + 0.25 * mean_nlos
     rate = args.serve_rate if args.serve_rate > 0 else args.serve_load / (F * mean_solo)
     arrive = np.cumsum(rng.exponential(1.0 / rate, n))
     arrive -= arrive[0]
@@ -458,7 +486,7 @@ def serving(args, torch):
     due = sorted((arrive[i] + j * period, i, j) for i in range(n) for j in range(F))
     sid, outs, left = {}, {}, [F] * n
     pending = {}
-    lat, adm_wait, lat_res = [], [], {}
+    lat, adm_wait, lat_res, svc, queue, lat_kind = [], [], {}, [], [], {}
     peak_used, peak_adm, used_area = 0, 0, 0.0
     k = 0
     t_open = t_close = 0.0
@@ -476,10 +504,15 @@ def serving(args, torch):
                 t_open += time.perf_counter() - ta
             pending[srv.submit(sid[i], wls[i].frames[j], outs[i])] = (i, j, ts)
         for t in list(pending):
-            if srv.query(t):
+            fin, gpu_ms = srv.query_timed(t)
+            if fin:
                 i, j, ts = pending.pop(t)
                 done = time.perf_counter() - t0
                 lat.append(done - ts)
+                if gpu_ms is not None:
+                    svc.append(gpu_ms * 1e-3)
+                    queue.append(max(done - ts - gpu_ms * 1e-3, 0.0))
+                lat_kind.setdefault(kinds[i], []).append(done - ts)
                 lat_res.setdefault(wls[i].sensor.width, []).append(done - ts)
                 if j == 0:
                     adm_wait.append(done - ts)
@@ -510,6 +543,13 @@ def serving(args, torch):
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                            "p99": round(float(np.percentile(lat, 99)), 3),
                            "max": round(float(lat.max()), 3)},
+            "service_ms": {"p50": round(float(np.percentile(svc, 50)) * 1e3, 3),
+                           "p99": round(float(np.percentile(svc, 99)) * 1e3, 3)},
+            "queueing_ms": {"p50": round(float(np.percentile(queue, 50)) * 1e3, 3),
+                            "p99": round(float(np.percentile(queue, 99)) * 1e3, 3)},
+            "latency_ms_p50_by_kind": {k: round(float(np.percentile(v, 50)) * 1e3, 3) for k, v in sorted(lat_kind.items())},
+            "latency_ms_p99_by_kind": {k: round(float(np.percentile(v, 99)) * 1e3, 3) for k, v in sorted(lat_kind.items())},
+            "nlos_streams": kinds.count("nlos"),
             "first_frame_latency_ms_p50": round(float(np.percentile(adm_wait, 50)) * 1e3, 3),
             "latency_ms_p50_by_res": {str(k): round(float(np.percentile(v, 50)) * 1e3, 3)
                                       for k, v in sorted(lat_res.items())},
@@ -519,7 +559,7 @@ def serving(args, torch):
             "mean_used_gib": round(used_area / wall / (1 << 30), 2),
             "footprint_gib": {"min": round(min(fps_) / (1 << 30), 3), "max": round(max(fps_) / (1 << 30), 3),
                               "sum": round(sum(fps_) / (1 << 30), 2)},
-            "mix": {"res": [int(w.sensor.width) for w in wls], "bins": [int(w.sensor.n_bins) for w in wls]}}
+            "mix": {"kind": kinds, "res": [int(w.sensor.width) for w in wls], "bins": [int(w.sensor.n_bins) for w in wls]}}
 
 
 def equal_rmse_seq(wl, frame_at, variants, args, torch, Renderer, planes=("gate_image", "histogram")):
@@ -622,6 +662,52 @@ def gate_only(wl, frame_at, args, torch, Renderer):
             name = f"m_init{m_init}_" + ("pairwise" if mis else "gbh")
             variants.append((name, dataclasses.replace(wl.sensor, n_bins=0, m_init=m_init, mis_mode=mis)))
     return equal_rmse_seq(wl, frame_at, variants, args, torch, Renderer, planes=("gate_image",))
+
+
+def specular_stress_leg(args, torch, warm=2, timed=3):
+    """The near-specular stress configuration (0.95M triangles, 30% GGX with
+    alpha 0.01, 4 bounces, 512 bins + gate, spline camera): frames/s, ms per
+    frame, shifts and rays per frame, timing off, frames warm..warm+timed-1.
+    Its reservoirs at 1920x1080 (about 347 GiB) do not fit one GPU's HBM, so
+    it runs at a lower resolution of the same scene and the footprint of the
+    full one is reported beside it."""
+    from paper_2605_11536_amd import scenes
+    from paper_2605_11536_amd.tof import Renderer, tof_footprint
+    W, H = args.c5_width, args.c5_height
+    t0 = time.perf_counter()
+    wl = scenes.specular_stress(width=W, height=H, frames=warm + timed)
+    full = scenes.specular_stress(frames=1)
+    t_scene = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = Renderer(wl.scene, wl.sensor)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    ms = []
+    for i in range(warm):
+        r.render(wl.frames[i])
+    torch.cuda.synchronize()
+    st0 = r.stats()
+    for i in range(warm, warm + timed):
+        t0 = time.perf_counter()
+        r.render(wl.frames[i])
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    st1 = r.stats()
+    r.close()
+    d = {k: (st1[k] - st0[k]) // timed for k in ("shifts", "shifts_ok", "newton_attempts", "newton_converged",
+                                                   "newton_paths_ok", "rays")}
+    sc = wl.scene
+    ggx = sum(2 * int(sc.obj_grid[o, 0]) * int(sc.obj_grid[o, 1]) for o in range(sc.num_objects)
+              if sc.obj_type[o] == scenes.OBJ_GRID and sc.mat_type[sc.obj_material[o]] == 1)
+    return {"workload": f"specular_stress {W}x{H}: {sc.num_triangles} triangles, "
+                        f"{round(100 * ggx / sc.num_triangles, 1)}% GGX (alpha 0.01), 4 bounces, "
+                        f"{wl.sensor.n_bins} bins + gate, temporal + 1 spatial round, Newton shift",
+            "frames": [warm, warm + timed - 1], "ms_per_frame": [round(x, 2) for x in ms],
+            "frames_per_s": round(1e3 * timed / sum(ms), 3), "per_frame": d,
+            "hbm_gib": round(tof_footprint(wl.scene, wl.sensor) / (1 << 30), 1),
+            "hbm_gib_1920x1080": round(tof_footprint(full.scene, full.sensor) / (1 << 30), 1),
+            "scene_build_s": round(t_scene, 2), "context_create_s": round(t_create, 2),
+            "bvh_overflow": st1["bvh_overflow"], "bad_records": st1["bad_records"]}
 
 
 def bins_sweep(wl, frame_at, args, torch, Renderer, bins=(4, 16, 64, 256), warm=5, timed=5):

@@ -388,6 +388,12 @@ tof_status tof_server_submit(tof_server* server, int stream_id, const tof_frame_
  * the ticket is retired), else 0. */
 tof_status tof_server_query(tof_server* server, uint64_t ticket, int* done);
 
+/* tof_server_query that also gives, once the frame is done, the time in
+ * milliseconds between the start and the end of its work on its HIP stream
+ * (*gpu_ms, -1 if unknown): the frame's service time under the load of the
+ * other streams; its queueing delay is what the caller saw beyond that. */
+tof_status tof_server_query_timed(tof_server* server, uint64_t ticket, int* done, float* gpu_ms);
+
 /* Block until the frame finished; returns its status and retires the ticket.
  * TOF_ERR_NOT_READY while its stream waits for admission.  While a wait is
  * blocked on a ticket, tof_server_query on it reports the state but leaves the

@@ -11,18 +11,24 @@ using namespace tofd;
 
 namespace {
 
+// wv = world positions (what the rays are traced against), wr = the vertices
+// turned into world orientation about their object's origin (what the charts
+// difference)
 __global__ void k_world_verts(const float4* __restrict__ lv, const int* __restrict__ vobj,
-                              const float* __restrict__ xf, float4* __restrict__ wv, int nv) {
+                              const float* __restrict__ xf, float4* __restrict__ wv, float4* __restrict__ wr, int nv) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nv) return;
     float4 q = lv[i];
     int o = vobj[i];
     if (o < 0) {   // vertex referenced by no object
         wv[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        wr[i] = make_float4(0.f, 0.f, 0.f, 0.f);
         return;
     }
     V3 p = xf_point(xf + 12 * o, mk(q.x, q.y, q.z));
+    V3 r = xf_dir(xf + 12 * o, mk(q.x, q.y, q.z));
     wv[i] = make_float4(p.x, p.y, p.z, 0.f);
+    wr[i] = make_float4(r.x, r.y, r.z, 0.f);
 }
 
 // leaves[3s..3s+2] = world vertices of triangle leaf_tri[s] (w of the first = its id)
@@ -181,9 +187,10 @@ void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, st, p, v, n);
 }
 
-void launch_world_verts(const float4* lv, const int* vobj, const float* xf, float4* wv, int nv, hipStream_t st) {
+void launch_world_verts(const float4* lv, const int* vobj, const float* xf, float4* wv, float4* wr, int nv,
+                        hipStream_t st) {
     if (nv == 0) return;
-    hipLaunchKernelGGL(k_world_verts, dim3(blocks_for(nv, 256)), dim3(256), 0, st, lv, vobj, xf, wv, nv);
+    hipLaunchKernelGGL(k_world_verts, dim3(blocks_for(nv, 256)), dim3(256), 0, st, lv, vobj, xf, wv, wr, nv);
 }
 
 void launch_leaf_gather(const int* leaf_tri, const int4* tv, const float4* wv, int T, float4* leaves,

@@ -68,6 +68,7 @@ struct Request {
     std::vector<float> xforms;
     std::vector<float> velocities;   // copy of the caller's array (empty = NULL): a held frame outlives it
     float* out[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t start = nullptr;      // recorded on the stream right before the frame's work
     hipEvent_t done = nullptr;
     bool dispatched = false;
     int waiters = 0;                 // tof_server_wait calls blocked on `done`: only they retire the ticket
@@ -125,7 +126,8 @@ tof_status hip_status(hipError_t e) { return e == hipSuccess ? TOF_OK : TOF_ERR_
 
 tof_status dispatch(tof_server* s, Stream& st, Request& r) {
     (void)s;
-    tof_status e = tof_render_frame(st.ctx, &r.frame, r.out[0], r.out[1], r.out[2], r.out[3], (void*)st.hs);
+    tof_status e = hip_status(hipEventRecord(r.start, st.hs));
+    if (e == TOF_OK) e = tof_render_frame(st.ctx, &r.frame, r.out[0], r.out[1], r.out[2], r.out[3], (void*)st.hs);
     if (e == TOF_OK) e = hip_status(hipEventRecord(r.done, st.hs));
     r.status = e;
     r.dispatched = true;
@@ -255,8 +257,10 @@ void tof_server_destroy(tof_server* s) {
     if (!s) return;
     (void)hipSetDevice(s->device);
     (void)hipDeviceSynchronize();
-    for (auto& kv : s->requests)
+    for (auto& kv : s->requests) {
         if (kv.second->done) (void)hipEventDestroy(kv.second->done);
+        if (kv.second->start) (void)hipEventDestroy(kv.second->start);
+    }
     for (auto& kv : s->streams)
         if (kv.second.admitted) release(s, kv.second.ctx, kv.second.hs, kv.second.region);
     for (Closed& z : s->closed) release(s, z.ctx, z.hs, z.region);
@@ -318,7 +322,11 @@ tof_status tof_server_submit(tof_server* s, int stream_id, const tof_frame_desc*
     r->out[1] = out_hist;
     r->out[2] = out_pt_image;
     r->out[3] = out_pt_hist;
-    if (hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) return TOF_ERR_DEVICE;
+    if (hipEventCreate(&r->done) != hipSuccess) return TOF_ERR_DEVICE;
+    if (hipEventCreate(&r->start) != hipSuccess) {
+        (void)hipEventDestroy(r->done);
+        return TOF_ERR_DEVICE;
+    }
     Request& rr = *r;
     s->requests[r->ticket] = std::move(r);
     *ticket = rr.ticket;
@@ -331,7 +339,7 @@ tof_status tof_server_submit(tof_server* s, int stream_id, const tof_frame_desc*
 // retired (event destroyed, ticket erased) unless a tof_server_wait is blocked
 // on its event, or `retire` is false: the waiter retires it.
 static tof_status poll_locked(tof_server* s, std::map<uint64_t, std::unique_ptr<Request>>::iterator it, int* done,
-                              bool retire) {
+                              bool retire, float* gpu_ms) {
     Request& r = *it->second;
     *done = 0;
     if (!r.dispatched) return TOF_OK;
@@ -342,19 +350,29 @@ static tof_status poll_locked(tof_server* s, std::map<uint64_t, std::unique_ptr<
         if (q != hipSuccess) st = TOF_ERR_DEVICE;
     }
     *done = 1;
+    if (gpu_ms) {
+        *gpu_ms = -1.f;
+        float ms = 0.f;
+        if (st == TOF_OK && hipEventElapsedTime(&ms, r.start, r.done) == hipSuccess) *gpu_ms = ms;
+    }
     if (!retire || r.waiters > 0) return st;
     (void)hipEventDestroy(r.done);
+    (void)hipEventDestroy(r.start);
     s->requests.erase(it);
     if (!s->closed.empty()) admit_waiting(s);
     return st;
 }
 
 tof_status tof_server_query(tof_server* s, uint64_t ticket, int* done) {
+    return tof_server_query_timed(s, ticket, done, nullptr);
+}
+
+tof_status tof_server_query_timed(tof_server* s, uint64_t ticket, int* done, float* gpu_ms) {
     if (!s || !done) return TOF_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(s->mu);
     auto it = s->requests.find(ticket);
     if (it == s->requests.end()) return TOF_ERR_INVALID_ARG;
-    return poll_locked(s, it, done, true);
+    return poll_locked(s, it, done, true, gpu_ms);
 }
 
 tof_status tof_server_wait(tof_server* s, uint64_t ticket) {
@@ -374,7 +392,7 @@ tof_status tof_server_wait(tof_server* s, uint64_t ticket) {
     if (it == s->requests.end()) return TOF_ERR_INVALID_ARG;   // cannot happen: only waiters retire it now
     it->second->waiters--;
     int done = 0;
-    const tof_status st = poll_locked(s, it, &done, it->second->waiters == 0);
+    const tof_status st = poll_locked(s, it, &done, it->second->waiters == 0, nullptr);
     if (e != hipSuccess) return TOF_ERR_DEVICE;
     return st;
 }

@@ -32,6 +32,7 @@ struct GeomBuf {
     float* xf = nullptr;
     float* vel = nullptr;        // [6 * objects]: linear and angular velocity (velocity domain)
     float4* wv = nullptr;
+    float4* wr = nullptr;        // vertices in world orientation about their object's origin
     Node4* nodes = nullptr;      // [n_nodes]: the tree over the objects, then the objects' trees
     NodeQ* nodesq = nullptr;     // [n_nodes]: the same nodes quantized, as traversal reads them
     uint32_t* order = nullptr;   // refit order: object-tree nodes by height, then the top tree's
@@ -256,7 +257,7 @@ size_t scene_footprint(const tof_scene_desc& d) {
         }
     const size_t V = (size_t)std::max(d.num_vertices, 1), O = (size_t)d.num_objects, N = mesh + T + 1;
     return O * (sizeof(Obj) + 4) + (size_t)d.num_materials * sizeof(Mat) + T * (sizeof(TriInfo) + 16 + 4) +
-           V * (16 + 4) + 2 * (72 * O + 16 * V + (sizeof(Node4) + sizeof(NodeQ) + 4) * N + 48 * std::max<size_t>(T, 1)) +
+           V * (16 + 4) + 2 * (72 * O + 32 * V + (sizeof(Node4) + sizeof(NodeQ) + 4) * N + 48 * std::max<size_t>(T, 1)) +
            64 * 1024;
 }
 
@@ -299,7 +300,7 @@ SlotDev slot_dev(const tof_ctx* c, int i) {
     const SlotHost& h = c->slot[i];
     const GeomBuf& g = c->geom[h.geom];
     SlotDev d;
-    d.wv = g.wv;
+    d.wr = g.wr;
     d.xf = g.xf;
     d.nodes = g.nodesq;
     d.n_nodes = c->n_nodes;
@@ -632,6 +633,7 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
         HIP_TRY(hipMemset(g.vel, 0, sizeof(float) * 6 * objs.size()));
         g.vel_host.assign(6 * objs.size(), 0.f);
         TOF_TRY(alloc_t(c, a, &g.wv, std::max(d->num_vertices, 1)));
+        TOF_TRY(alloc_t(c, a, &g.wr, std::max(d->num_vertices, 1)));
         TOF_TRY(alloc_t(c, a, &g.nodes, (size_t)c->n_nodes));
         TOF_TRY(alloc_t(c, a, &g.nodesq, (size_t)c->n_nodes));
         TOF_TRY(alloc_t(c, a, &g.order, (size_t)c->n_nodes));
@@ -1108,7 +1110,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         }
         HIP_TRY(hipEventRecord(c->xf_ev[ring], st));
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
-        tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, c->n_vert, st);
+        tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, g.wr, c->n_vert, st);
         tofh::launch_leaf_gather(c->d_leaf_tri, c->d_tv, g.wv, c->n_tri, g.leaves, st);
         tofh::launch_refit(g.nodes, g.nodesq, g.order, levels, g.leaves, c->n_tri, st);
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));

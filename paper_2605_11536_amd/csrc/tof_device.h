@@ -98,7 +98,11 @@ struct SceneDev {
 
 // One frame's geometry, camera, light and G-buffer.
 struct SlotDev {
-    const float4* wv;       // world vertices
+    // vertices turned into world orientation about their object's origin
+    // (world position = origin + wr): differences of nearby vertices stay exact
+    // to FP32 rounding of the edge, where absolute world positions would carry
+    // their rounding at the object's distance from the world origin
+    const float4* wr;
     const float* xf;        // object transforms, 12 floats each
     const NodeQ* nodes;     // 4-wide traversal nodes (quantized), root at 0
     int n_nodes;
@@ -301,16 +305,19 @@ __device__ inline Chart chart_eval(const SceneDev& S, const SlotDev& G, int obj,
         float a = uu - (float)i, b = vv - (float)j;
         int row = ob.nu + 1;
         int base = ob.voff + j * row + i;
-        V3 v00 = ld3(G.wv, base), v10 = ld3(G.wv, base + 1);
-        V3 v01 = ld3(G.wv, base + row), v11 = ld3(G.wv, base + row + 1);
+        // the cell's lower triangle (v00, v10, v01) or its upper one (v11, v01, v10)
+        const float* m = G.xf + 12 * obj;
+        const V3 org = mk(m[3], m[7], m[11]);
         if (a + b <= 1.0f) {
-            c.p = v00 + a * (v10 - v00) + b * (v01 - v00);
-            c.ju = v10 - v00;
-            c.jv = v01 - v00;
+            const V3 r0 = ld3(G.wr, base), ru = ld3(G.wr, base + 1), rv = ld3(G.wr, base + row);
+            c.ju = ru - r0;
+            c.jv = rv - r0;
+            c.p = org + (r0 + a * c.ju + b * c.jv);
         } else {
-            c.p = v11 + (1.0f - a) * (v01 - v11) + (1.0f - b) * (v10 - v11);
-            c.ju = v11 - v01;
-            c.jv = v11 - v10;
+            const V3 r0 = ld3(G.wr, base + row + 1), ru = ld3(G.wr, base + row), rv = ld3(G.wr, base + 1);
+            c.ju = r0 - ru;
+            c.jv = r0 - rv;
+            c.p = org + (r0 - (1.0f - a) * c.ju - (1.0f - b) * c.jv);
         }
         V3 cr = cross(c.ju, c.jv);
         float l = len(cr);
@@ -1118,7 +1125,7 @@ __device__ inline bool bsdf_sample(const SceneDev& S, int obj, V3 n, V3 wi, floa
     float a2 = m.alpha * m.alpha;
     float t2 = a2 * u1 / (1.0f - u1);
     float ch = 1.0f / sqrtf(1.0f + t2);
-    float sh = sqrtf(fmaxf(0.f, 1.0f - ch * ch));
+    float sh = sqrtf(t2) * ch;   // sin = tan cos, without the cancellation of 1 - cos^2
     float ph = 2.0f * kPi * u2;
     float sp, cp;
     sincosf(ph, &sp, &cp);
@@ -1321,16 +1328,18 @@ __device__ inline ChartT<T> chart_eval_t(const SceneDev& S, const SlotDev& G, in
         T a = uu - (T)i, b = vv - (T)j;
         int row = ob.nu + 1;
         int base = ob.voff + j * row + i;
-        T3<T> v00 = tld<T>(G.wv, base), v10 = tld<T>(G.wv, base + 1);
-        T3<T> v01 = tld<T>(G.wv, base + row), v11 = tld<T>(G.wv, base + row + 1);
+        const float* m = G.xf + 12 * obj;
+        const T3<T> org = T3<T>{(T)m[3], (T)m[7], (T)m[11]};
         if (a + b <= (T)1) {
-            c.p = v00 + a * (v10 - v00) + b * (v01 - v00);
-            c.ju = v10 - v00;
-            c.jv = v01 - v00;
+            const T3<T> r0 = tld<T>(G.wr, base), ru = tld<T>(G.wr, base + 1), rv = tld<T>(G.wr, base + row);
+            c.ju = ru - r0;
+            c.jv = rv - r0;
+            c.p = org + (r0 + a * c.ju + b * c.jv);
         } else {
-            c.p = v11 + ((T)1 - a) * (v01 - v11) + ((T)1 - b) * (v10 - v11);
-            c.ju = v11 - v01;
-            c.jv = v11 - v10;
+            const T3<T> r0 = tld<T>(G.wr, base + row + 1), ru = tld<T>(G.wr, base + row), rv = tld<T>(G.wr, base + 1);
+            c.ju = r0 - ru;
+            c.jv = r0 - rv;
+            c.p = org + (r0 - ((T)1 - a) * c.ju - ((T)1 - b) * c.jv);
         }
         c.ok = tlen(tcross(c.ju, c.jv)) > (T)0;
     } else {

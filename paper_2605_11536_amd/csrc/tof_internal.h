@@ -43,7 +43,9 @@ int32_t build_bvh4(const std::vector<BvhPrim>& prims, int leaf_max, int node_bas
 
 // bvh.hip
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
-void launch_world_verts(const float4* lv, const int* vobj, const float* xf, float4* wv, int nv, hipStream_t st);
+// wv = world positions, wr = vertices turned into world orientation about their object's origin
+void launch_world_verts(const float4* lv, const int* vobj, const float* xf, float4* wv, float4* wr, int nv,
+                        hipStream_t st);
 void launch_leaf_gather(const int* leaf_tri, const int4* tv, const float4* wv, int T, float4* leaves,
                         hipStream_t st);
 // boxes of the nodes order[level_off[l] .. level_off[l+1]) for l = 0, 1, ...

@@ -484,6 +484,82 @@ def glossy_dynamic(width=512, height=512, frames=60, seed=0, ground_cells=160,
     return Workload(f"glossy_dynamic_{width}", scene, sensor, fr)
 
 
+def _catmull_rom(points: np.ndarray, t: float) -> np.ndarray:
+    """Closed Catmull-Rom spline through `points` at parameter t in [0, 1)."""
+    n = len(points)
+    x = (t % 1.0) * n
+    i = int(math.floor(x))
+    u = x - i
+    p0, p1, p2, p3 = (points[(i + k) % n] for k in (-1, 0, 1, 2))
+    return 0.5 * ((2 * p1) + (-p0 + p2) * u + (2 * p0 - 5 * p1 + 4 * p2 - p3) * u * u
+                  + (-p0 + 3 * p1 - 3 * p2 + p3) * u * u * u)
+
+
+def specular_stress(width=1920, height=1080, frames=120, seed=0, ground_cells=480, n_spheres=32, sphere_nu=96,
+                    sphere_nv=80, n_specular=19, **sensor_kw) -> Workload:
+    """Near-specular stress scene, about 0.95M triangles.
+
+    Ground: 480x480-cell lattice over [-8,8]^2 displaced by 0.2*fbm, Lambertian
+    albedo 0.5 (461k triangles).  32 latitude/longitude spheres of 96x80 cells
+    (15,360 triangles each), radius U[0.3,0.7], resting on the ground: the
+    first 19 GGX with alpha 0.01 and F0 0.8 (30.7% of the triangles), the
+    others Lambertian with albedo U[0.3,0.8].  Static geometry; the camera
+    (with a co-located light) follows a closed Catmull-Rom spline through six
+    points around the scene at heights 2-4, looking at (0,0.5,0), 50 deg FOV,
+    one turn over `frames` frames.  Up to 4 bounces; 512-bin histogram
+    (t0=10, width 0.05) plus a gate at 20.0 of width 0.1; temporal reuse plus
+    one spatial round (k=5, radius 30 px).
+    """
+    rng = np.random.default_rng(5000 + seed)
+    b = _Builder()
+    ground_mat = b.material(MAT_LAMBERT, albedo=0.5)
+    n = ground_cells
+    xs = np.linspace(-8.0, 8.0, n + 1)
+    X, Z = np.meshgrid(xs, xs)
+    Y = 0.2 * _fbm(X * 0.6, Z * 0.6, seed=17 + seed)
+    lat = np.stack([X, Y, Z], -1)[::-1].copy()   # normal up
+    b.grid(lat, ground_mat)
+    centres, radii = [], []
+    tries = 0
+    while len(centres) < n_spheres and tries < 20000:
+        tries += 1
+        r = rng.uniform(0.3, 0.7)
+        c = np.array([rng.uniform(-6.0, 6.0), 0.0, rng.uniform(-6.0, 6.0)])
+        if np.hypot(c[0], c[2]) > 6.5 or any(np.linalg.norm(c[[0, 2]] - c2[[0, 2]]) < r + r2 + 0.2
+                                              for c2, r2 in zip(centres, radii)):
+            continue
+        c[1] = r + 0.25
+        centres.append(c)
+        radii.append(r)
+    sphere_lat = {}
+    for k in range(len(centres)):
+        if k < n_specular:
+            m = b.material(MAT_GGX, alpha=0.01, f0=0.8)
+        else:
+            m = b.material(MAT_LAMBERT, albedo=float(rng.uniform(0.3, 0.8)))
+        key = round(radii[k], 6)
+        if key not in sphere_lat:
+            sphere_lat[key] = _latlong_sphere(radii[k], sphere_nu, sphere_nv)
+        b.grid(sphere_lat[key], m, wrap_u=1)
+    nobj = 1 + len(centres)
+    xf = np.stack([_identity_xform()] * nobj)
+    for k in range(len(centres)):
+        xf[1 + k] = _xform(np.eye(3), centres[k])
+    scene = b.build(xf)
+    kw = dict(width=width, height=height, gate_enabled=1, gate_center=20.0, gate_width=0.1, n_bins=512,
+              bin_t0=10.0, bin_width=0.05, n_min=2, n_max=4, m_init=1, temporal=1, spatial_rounds=1,
+              spatial_k=5, spatial_radius=30, seed=seed)
+    kw.update(sensor_kw)
+    sensor = Sensor(**kw)
+    ang = np.linspace(0.0, 2 * math.pi, 6, endpoint=False)
+    ctrl = np.stack([np.array([9.0 * math.cos(a), 3.0 + math.sin(2 * a), 9.0 * math.sin(a)]) for a in ang])
+    fr = []
+    for f in range(frames):
+        cp = _catmull_rom(ctrl, f / max(frames, 1))
+        fr.append(_pinhole_frame(f, cp, (0, 0.5, 0), (0, 1, 0), 50.0, cp, xf))
+    return Workload(f"specular_stress_{width}x{height}", scene, sensor, fr)
+
+
 def nlos_confocal(scan=64, frames=32, seed=0, torus_nu=250, torus_nv=100,
                   n_bins=1024, **sensor_kw) -> Workload:
     """NLOS time-resolved simulation: relay wall + hidden displaced torus.

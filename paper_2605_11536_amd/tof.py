@@ -128,6 +128,8 @@ def lib():
         L.tof_server_submit.argtypes = [C.c_void_p, C.c_int, C.POINTER(tof_frame_desc), C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]
         L.tof_server_query.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int)]
+        L.tof_server_query_timed.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int), C.POINTER(C.c_float)]
+        L.tof_server_query_timed.restype = C.c_int
         L.tof_server_wait.argtypes = [C.c_void_p, C.c_uint64]
         L.tof_server_close.argtypes = [C.c_void_p, C.c_int]
         L.tof_server_info.argtypes = [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -451,6 +453,13 @@ class Server:
         done = C.c_int(0)
         _check("tof_server_query", lib().tof_server_query(self.h, C.c_uint64(ticket), C.byref(done)))
         return bool(done.value)
+
+    def query_timed(self, ticket):
+        """(done, GPU service time in ms of the frame once done, else None)."""
+        done, ms = C.c_int(0), C.c_float(-1.0)
+        _check("tof_server_query_timed",
+               lib().tof_server_query_timed(self.h, C.c_uint64(ticket), C.byref(done), C.byref(ms)))
+        return bool(done.value), (float(ms.value) if done.value and ms.value >= 0 else None)
 
     def wait(self, ticket) -> None:
         _check("tof_server_wait", lib().tof_server_wait(self.h, C.c_uint64(ticket)))
