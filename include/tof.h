@@ -190,8 +190,10 @@ tof_status tof_create(tof_ctx** out, int device, size_t hbm_budget_bytes, uint64
 /* Release every device allocation of the context (synchronizes the device). */
 void tof_destroy(tof_ctx* ctx);
 
-/* Copy the scene to the device and validate it (TOF_ERR_INVALID_SCENE for
- * malformed objects or 2^28 triangles or more).  Drops reservoir history. */
+/* Copy the scene to the device and validate it (TOF_ERR_INVALID_ARG for fewer
+ * than 1 or more than 4095 objects, since a reservoir record names a path's
+ * vertex objects in 12 bits; TOF_ERR_INVALID_SCENE for malformed objects or
+ * 2^28 triangles or more).  Drops reservoir history. */
 tof_status tof_scene_upload(tof_ctx* ctx, const tof_scene_desc* scene);
 
 /* Set sensor and time-domain settings and (re)allocate per-pixel state after

@@ -329,7 +329,9 @@ __global__ void k_neighbours(FrameArgs a, int round, const float* __restrict__ M
 // index of its first task (item, c), one per non-empty candidate; items and
 // tasks are numbered in the same block order, so task0 grows with the item
 // index and the tasks of an item range are contiguous.  count[0] and count[1]
-// receive the totals.  Also clears the output mask.
+// receive the totals.  Task numbers wrap modulo 2^32 on a pass with more
+// tasks than that; every later use takes the difference of two of them within
+// one chunk, which stays exact.  Also clears the output mask.
 // ---------------------------------------------------------------------------
 // the bits of mask word w that are planes (not padding)
 __device__ __forceinline__ uint32_t planes_in_word(const Sens& s, int w) {
@@ -971,7 +973,7 @@ __global__ void k_copy_plane(FrameArgs a, ResSet in, ResSet out, int pl) {
     if (pix >= P || !mask_bit(in.mask, P, pl, pix)) return;
     const size_t i = (size_t)pl * P + pix;
 #pragma unroll
-    for (int e = 0; e < 5; ++e) out.rec[5 * i + e] = in.rec[5 * i + e];
+    for (int e = 0; e < kRecF4; ++e) out.rec[kRecF4 * i + e] = in.rec[kRecF4 * i + e];
     atomicOr(out.mask + (size_t)(pl >> 5) * P + pix, 1u << (pl & 31));
 }
 
@@ -989,7 +991,7 @@ __global__ void k_splat(FrameArgs a, ResSet shown, const float* __restrict__ pt,
         const int pix = (int)(i - (size_t)pl * s.P);
         float v = 0.f;
         if (mask_bit(shown.mask, s.P, pl, pix)) {
-            float2 wp = *(const float2*)(shown.rec + i * 5);
+            float2 wp = *(const float2*)(shown.rec + i * kRecF4);
             v = wp.x * wp.y;
         }
         float vp = pt[i];

@@ -91,7 +91,11 @@ struct tof_ctx {
     tof_sensor_desc sd{};
     Sens s{};
     SlotHost slot[2];
-    ResSet sets[4];          // 0 canonical, 1 scratch/temporal, 2-3 final ping-pong
+    // 0 canonical; 1 and 2: the previous frame's final (fin_prev) and a
+    // scratch set.  Once the temporal pass has read the previous final, its
+    // set is free, so the later passes alternate between 1 and 2 and the new
+    // final ends in one of them.
+    ResSet sets[3];
     int fin_prev = 2;
     bool prev_valid = false;
     float* pt = nullptr;
@@ -234,7 +238,7 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t per_set = P * B * kRecBytes + P * 4 + P * words * 4;
     size_t gbuf = 2 * P * (4 + 4 + 4 + 16 + 16);
     const tofh::ChunkPlan pl = tofh::plan_chunks(P, B, d.spatial_k, d.bin_radius);
-    return 4 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
+    return 3 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
            P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ + P * B * 4 /*first task per item*/ +
            pl.task_cap * (8 + 16 + 32) /*tasks, forward terms, shifted fields*/ +
            pl.term_cap * (4 + 4) /*MIS terms, MIS work list*/ + 32 * pl.ray_cap +
@@ -263,7 +267,7 @@ size_t scene_footprint(const tof_scene_desc& d) {
 
 tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
     Alloc& a = c->sensor_mem;
-    TOF_TRY(alloc_t(c, a, &r.rec, P * B * 5));
+    TOF_TRY(alloc_t(c, a, &r.rec, P * B * kRecF4));
     TOF_TRY(alloc_t(c, a, &r.M, P));
     TOF_TRY(alloc_t(c, a, &r.mask, P * words));
     return TOF_OK;
@@ -474,7 +478,7 @@ void tof_destroy(tof_ctx* c) {
 
 tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
     if (!c || !d) return TOF_ERR_INVALID_ARG;
-    if (d->num_objects < 1 || d->num_objects > (1 << 20) || d->num_materials < 1 || d->num_vertices < 0 ||
+    if (d->num_objects < 1 || d->num_objects > kMaxObjects || d->num_materials < 1 || d->num_vertices < 0 ||
         !d->object_type || !d->object_material || !d->object_grid || !d->object_sphere || !d->material_type ||
         !d->material_params || (d->num_vertices > 0 && !d->vertices))
         return TOF_ERR_INVALID_ARG;
@@ -693,10 +697,10 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
               (d->round_trip == 0 || d->round_trip == 1) && (d->mis_mode == 0 || d->mis_mode == 1) &&
               (d->domain == TOF_DOMAIN_TIME || (d->bin_radius == 0 && d->shrink_k == 1.f)) &&
               std::isfinite(d->light_intensity) && std::isfinite(d->gate_center) && std::isfinite(d->bin_t0);
-    // work-list entries (tasks of a pass over fully occupied planes) are 32-bit indices
-    ok = ok && (unsigned long long)d->width * d->height * B *
-                       (unsigned long long)(std::max(std::max(d->spatial_k, 2 * d->bin_radius), 1) + 1) <
-                   (1ULL << 32);
+    // items (one per non-empty pixel-plane of a pass) are 32-bit indices;
+    // task numbers are counted modulo 2^32, as only their differences within
+    // a chunk (at most its task capacity) are ever used
+    ok = ok && (unsigned long long)d->width * d->height * B < (1ULL << 31);
     if (ok) {
         // owners of queued visibility segments (indices of the floats a blocked
         // ray zeroes: 4 per task, one per MIS term, 20 per pixel) stay below 2^31
@@ -726,7 +730,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     c->slot[0].valid = c->slot[1].valid = false;
     const size_t P = (size_t)d->width * d->height;
     const size_t words = ((size_t)B + 31) / 32;
-    for (int i = 0; i < 4; ++i) TOF_TRY(alloc_set(c, c->sets[i], P, B, words));
+    for (int i = 0; i < 3; ++i) TOF_TRY(alloc_set(c, c->sets[i], P, B, words));
     Alloc& a = c->sensor_mem;
     for (int i = 0; i < 2; ++i) {
         SlotHost& h = c->slot[i];
@@ -746,7 +750,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->tasks, pl.task_cap));
     TOF_TRY(alloc_t(c, a, &c->fwd, pl.task_cap));
     c->wide = nullptr;
-    if (shrink_mix(*d)) TOF_TRY(alloc_t(c, a, &c->wide, 5 * P));
+    if (shrink_mix(*d)) TOF_TRY(alloc_t(c, a, &c->wide, kRecF4 * P));
     TOF_TRY(alloc_t(c, a, &c->shv, 2 * pl.task_cap));
     TOF_TRY(alloc_t(c, a, &c->term, pl.term_cap));
     TOF_TRY(alloc_t(c, a, &c->rays, 2 * pl.ray_cap));
@@ -832,7 +836,9 @@ tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
         if (h->vertex_obj[i] < -1 || h->vertex_obj[i] >= c->n_obj) return TOF_ERR_INVALID_ARG;
     for (size_t i = 0; i < PB; ++i) {
         uint32_t m = h->meta[i];
-        if (((m >> 8) & 15u) > (uint32_t)kMaxVerts || ((m >> 12) & 15u) > (uint32_t)kMaxVerts) return TOF_ERR_INVALID_ARG;
+        if (((m >> 8) & 15u) > (uint32_t)kMaxVerts || ((m >> 12) & 15u) > (uint32_t)kMaxVerts ||
+            ((m >> 16) & 15u) > 1u || (m >> 17) != 0u)
+            return TOF_ERR_INVALID_ARG;
     }
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(quiesce(c));
@@ -847,11 +853,16 @@ tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
         q[3] = h->pre_pdf[i];
         q[4] = u2f(h->origin_pixel[i]);
         q[5] = u2f(h->origin_frame[i]);
-        q[6] = u2f(h->meta[i]);
+        const uint32_t m = h->meta[i];
+        uint32_t w6, w7;
+        rec_pack_meta((int)(m & 255u), (int)((m >> 8) & 15u), (int)((m >> 12) & 15u), (int)((m >> 16) & 15u),
+                      h->vertex_obj[i], h->vertex_obj[PB + i], h->vertex_obj[2 * PB + i], h->vertex_obj[3 * PB + i],
+                      w6, w7);
+        q[6] = u2f(w6);
+        q[7] = u2f(w7);
         for (int v = 0; v < 4; ++v) {
-            q[8 + 3 * v] = u2f((uint32_t)h->vertex_obj[v * PB + i]);
-            q[9 + 3 * v] = h->vertex_xi[(2 * v) * PB + i];
-            q[10 + 3 * v] = h->vertex_xi[(2 * v + 1) * PB + i];
+            q[8 + 2 * v] = h->vertex_xi[(2 * v) * PB + i];
+            q[9 + 2 * v] = h->vertex_xi[(2 * v + 1) * PB + i];
         }
     }
     HIP_TRY(hipMemcpy(r.rec, packed.data(), sizeof(float) * packed.size(), hipMemcpyHostToDevice));
@@ -1153,8 +1164,8 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     HIP_TRY(timer_mark(c, TOF_K_GBUFFER, st));
     tofh::launch_fill_u32((uint32_t*)c->pt, 0u, P * B, st);
     ResSet& can = c->sets[0];
-    ResSet& tmp = c->sets[1];
-    const int fin_new = c->fin_prev == 2 ? 3 : 2;
+    const int spare = c->fin_prev == 1 ? 2 : 1;   // the set not holding the previous frame's final
+    ResSet& tmp = c->sets[spare];
     HIP_TRY(timer_mark(c, TOF_K_INITIAL, st));
     a.counters = c->counters + (size_t)TOF_K_INITIAL * kBank;
     ResSet wide{};
@@ -1166,7 +1177,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         const tofh::ChunkPlan& pl = c->plan;
         const size_t ct = pl.ct[1], NQ = tofd::kRaySubQueues;
         const tofd::RayQueue qs{c->rays, c->ray_count, (uint32_t)(2 * ct / NQ)};
-        float* kill = (float*)(can.rec + (size_t)c->s.n_bins * P * 5);
+        float* kill = (float*)(can.rec + (size_t)c->s.n_bins * P * kRecF4);
         if (c->wide) {   // R < 1: merge of the gate and the shrunk wide-gate samples
             const tofd::RayQueue q4{c->rays, c->ray_count, (uint32_t)(4 * ct / NQ)};
             for (size_t p0 = 0; p0 < P; p0 += ct) {
@@ -1215,14 +1226,10 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     } else if (shown) {
         tofh::launch_splat(a, *shown, c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
     }
-    // the bin-axis pass and the spatial rounds alternate between the new
-    // final set and the scratch set
-    int cur_idx = temporal_done ? 1 : 0;
-    auto next_out = [&]() {
-        int out_idx = (cur_idx == fin_new) ? 1 : fin_new;
-        if (out_idx == cur_idx) out_idx = 0;
-        return out_idx;
-    };
+    // the bin-axis pass and the spatial rounds alternate between sets 1 and
+    // 2 (the previous frame's final has been read, or is not read this frame)
+    int cur_idx = temporal_done ? spare : 0;
+    auto next_out = [&]() { return cur_idx == 0 ? spare : 3 - cur_idx; };
     if (c->s.br > 0 && c->s.n_bins > 1) {
         const int out_idx = next_out();
         ResSet& in = c->sets[cur_idx];
@@ -1251,7 +1258,13 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         if (item_slot && r == 0) HIP_TRY(hipMemcpyAsync(item_slot + 2, c->count, 8, hipMemcpyDeviceToDevice, st));
         cur_idx = out_idx;
     }
-    if (cur_idx != fin_new) std::swap(c->sets[cur_idx], c->sets[fin_new]);
+    // a final still in the canonical set (no pass ran) trades places with the
+    // spare set, so that the next frame's initial samples do not overwrite it
+    if (cur_idx == 0) {
+        std::swap(c->sets[0], c->sets[spare]);
+        cur_idx = spare;
+    }
+    const int fin_new = cur_idx;
     a.counters = c->counters + (size_t)TOF_K_SPLAT * kBank;
     if (c->s.debug_stage == TOF_STAGE_FINAL) {
         HIP_TRY(timer_mark(c, TOF_K_SPLAT, st));
@@ -1340,7 +1353,7 @@ static size_t carve_work(const tof_ctx* c, const tofh::ChunkPlan& pl, char* base
     take(w.tasks, pl.task_cap);
     take(w.fwd, pl.task_cap);
     w.wide = nullptr;
-    if (shrink_mix(c->sd)) take(w.wide, 5 * P);
+    if (shrink_mix(c->sd)) take(w.wide, kRecF4 * P);
     take(w.shv, 2 * pl.task_cap);
     take(w.term, pl.term_cap);
     take(w.rays, 2 * pl.ray_cap);

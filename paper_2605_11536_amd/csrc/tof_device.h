@@ -163,17 +163,23 @@ struct Rec {
     float len, pre_pdf, phat;
 };
 
-// Reservoirs: one 80-byte record (5 x float4) per (plane, pixel), index
-// [plane * P + pixel].  Reuse work lists visit a pixel's planes together, so
-// neighbouring lanes touch different planes; a contiguous record keeps each
-// lane's access inside one or two cache lines.  Words: 0 W, 1 phat, 2 len,
-// 3 pre_pdf, 4 origin pixel, 5 origin frame, 6 meta (tree | n << 8 | k << 12
-// | nsfx << 16), 7 unused, 8..19 four vertex refs (obj, xi0, xi1).
-// M (confidence) and the non-empty bitmask are per pixel.
-constexpr int kRecWords = 20;
+// Reservoirs: one 64-byte record (4 x float4, half a 128-byte line) per
+// (plane, pixel), index [plane * P + pixel].  Reuse work lists visit a
+// pixel's planes together, so neighbouring lanes touch different planes; a
+// contiguous, line-aligned record keeps each lane's access inside one line.
+// Words: 0 W, 1 phat, 2 len, 3 pre_pdf, 4 origin pixel, 5 origin frame,
+// 6 tree (8 bits) | n << 8 (3) | k << 11 (3) | nsfx << 14 (1) | the high 4
+// bits of object 2 << 15 | object 3 << 19 (12), 7 object 0 (12) | object 1
+// << 12 (12) | the low 8 bits of object 2 << 24, 8..15 (xi0, xi1) of the four
+// vertex refs.  Objects are 12-bit, 0xFFF standing for -1 (none, or the
+// light), so a scene holds at most 4095 objects.  M (confidence) and the
+// non-empty bitmask are per pixel.
+constexpr int kRecWords = 16;
+constexpr int kRecF4 = kRecWords / 4;
+constexpr int kMaxObjects = 4095;
 
 struct ResSet {
-    float4* rec;             // [P * B * 5]
+    float4* rec;             // [P * B * kRecF4]
     float* M;                // [P]
     uint32_t* mask;          // [mask_words * P]: bit set <=> reservoir non-empty
 };
@@ -181,18 +187,29 @@ struct ResSet {
 __device__ __forceinline__ float& rec_W(const ResSet& R, size_t idx) { return ((float*)R.rec)[idx * kRecWords]; }
 __device__ __forceinline__ float rec_phat(const ResSet& R, size_t idx) { return ((const float*)R.rec)[idx * kRecWords + 1]; }
 
+// words 6 and 7 from the path's counts and its four vertex objects (-1 allowed)
+__host__ __device__ __forceinline__ void rec_pack_meta(int tree, int n, int k, int nsfx, int o0, int o1, int o2,
+                                                       int o3, uint32_t& w6, uint32_t& w7) {
+    const uint32_t b0 = (uint32_t)o0 & 0xFFFu, b1 = (uint32_t)o1 & 0xFFFu, b2 = (uint32_t)o2 & 0xFFFu,
+                   b3 = (uint32_t)o3 & 0xFFFu;
+    w6 = ((uint32_t)tree & 255u) | (((uint32_t)n & 7u) << 8) | (((uint32_t)k & 7u) << 11) |
+         (((uint32_t)nsfx & 1u) << 14) | ((b2 >> 8) << 15) | (b3 << 19);
+    w7 = b0 | (b1 << 12) | ((b2 & 255u) << 24);
+}
+__host__ __device__ __forceinline__ int rec_obj(uint32_t b) { return b == 0xFFFu ? -1 : (int)b; }
+
 __device__ __forceinline__ void store_rec(const ResSet& R, size_t idx, const Rec& r, float W) {
-    float4* q = R.rec + idx * 5;
-    uint32_t meta = (uint32_t)r.tree | ((uint32_t)r.n << 8) | ((uint32_t)r.k << 12) | ((uint32_t)r.nsfx << 16);
+    float4* q = R.rec + idx * kRecF4;
+    uint32_t w6, w7;
+    rec_pack_meta(r.tree, r.n, r.k, r.nsfx, r.v[0].obj, r.v[1].obj, r.v[2].obj, r.v[3].obj, w6, w7);
     q[0] = make_float4(W, r.phat, r.len, r.pre_pdf);
-    q[1] = make_float4(__uint_as_float(r.opix), __uint_as_float(r.ofr), __uint_as_float(meta), 0.f);
-    q[2] = make_float4(__int_as_float(r.v[0].obj), r.v[0].xi0, r.v[0].xi1, __int_as_float(r.v[1].obj));
-    q[3] = make_float4(r.v[1].xi0, r.v[1].xi1, __int_as_float(r.v[2].obj), r.v[2].xi0);
-    q[4] = make_float4(r.v[2].xi1, __int_as_float(r.v[3].obj), r.v[3].xi0, r.v[3].xi1);
+    q[1] = make_float4(__uint_as_float(r.opix), __uint_as_float(r.ofr), __uint_as_float(w6), __uint_as_float(w7));
+    q[2] = make_float4(r.v[0].xi0, r.v[0].xi1, r.v[1].xi0, r.v[1].xi1);
+    q[3] = make_float4(r.v[2].xi0, r.v[2].xi1, r.v[3].xi0, r.v[3].xi1);
 }
 __device__ __forceinline__ Rec load_rec(const ResSet& R, size_t idx, float& W) {
-    const float4* q = R.rec + idx * 5;
-    float4 a = q[0], b = q[1], c = q[2], d = q[3], e = q[4];
+    const float4* q = R.rec + idx * kRecF4;
+    float4 a = q[0], b = q[1], c = q[2], d = q[3];
     Rec r;
     W = a.x;
     r.phat = a.y;
@@ -200,15 +217,15 @@ __device__ __forceinline__ Rec load_rec(const ResSet& R, size_t idx, float& W) {
     r.pre_pdf = a.w;
     r.opix = __float_as_uint(b.x);
     r.ofr = __float_as_uint(b.y);
-    uint32_t m = __float_as_uint(b.z);
+    const uint32_t m = __float_as_uint(b.z), o = __float_as_uint(b.w);
     r.tree = (int)(m & 255u);
-    r.n = (int)((m >> 8) & 15u);
-    r.k = (int)((m >> 12) & 15u);
-    r.nsfx = (int)((m >> 16) & 15u);
-    r.v[0] = VRef{__float_as_int(c.x), c.y, c.z};
-    r.v[1] = VRef{__float_as_int(c.w), d.x, d.y};
-    r.v[2] = VRef{__float_as_int(d.z), d.w, e.x};
-    r.v[3] = VRef{__float_as_int(e.y), e.z, e.w};
+    r.n = (int)((m >> 8) & 7u);
+    r.k = (int)((m >> 11) & 7u);
+    r.nsfx = (int)((m >> 14) & 1u);
+    r.v[0] = VRef{rec_obj(o & 0xFFFu), c.x, c.y};
+    r.v[1] = VRef{rec_obj((o >> 12) & 0xFFFu), c.z, c.w};
+    r.v[2] = VRef{rec_obj(((m >> 15) & 15u) << 8 | (o >> 24)), d.x, d.y};
+    r.v[3] = VRef{rec_obj(m >> 19), d.z, d.w};
     return r;
 }
 
