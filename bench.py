@@ -654,11 +654,11 @@ def equal_rmse_seq(wl, frame_at, variants, args, torch, Renderer, planes=("gate_
 def gate_only(wl, frame_at, args, torch, Renderer):
     """The same scene and sequence with the gate alone (no histogram bins):
     the regime the paper targets (a narrow gate), same reuse settings, with 1,
-    2 and 4 path trees per pixel (initial candidates) and with either MIS of
-    the spatial pass."""
+    2, 4, 8 and 16 path trees per pixel (initial candidates) and with either
+    MIS of the spatial pass."""
     import dataclasses
     variants = []
-    for m_init in (1, 2, 4):
+    for m_init in (1, 2, 4, 8, 16):
         for mis in (0, 1):
             name = f"m_init{m_init}_" + ("pairwise" if mis else "gbh")
             variants.append((name, dataclasses.replace(wl.sensor, n_bins=0, m_init=m_init, mis_mode=mis)))

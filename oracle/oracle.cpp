@@ -209,9 +209,30 @@ struct PathRec {
 
 struct Res { PathRec y; double W = 0; };
 
+// Diagnostics of the resampling weights of one merge (a pixel-plane whose
+// weights sum to more than zero), summed per pass kind (0 temporal, 1
+// spatial): items, effective sample count (sum w)^2 / sum w^2, candidates
+// with w > 0, candidates present (non-empty, before their shift), share of
+// the canonical candidate's weight.
+struct MergeDiag {
+    double d[2][5] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+    void item(int kind, double ws, double w2, int npos, int npresent, double w0) {
+        d[kind][0] += 1.0;
+        d[kind][1] += ws * ws / w2;
+        d[kind][2] += npos;
+        d[kind][3] += npresent;
+        d[kind][4] += w0 / ws;
+    }
+};
+
 struct Stats {
     uint64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    void add(const Stats& o) { for (int i = 0; i < 8; ++i) c[i] += o.c[i]; }
+    MergeDiag md;
+    void add(const Stats& o) {
+        for (int i = 0; i < 8; ++i) c[i] += o.c[i];
+        for (int k = 0; k < 2; ++k)
+            for (int i = 0; i < 5; ++i) md.d[k][i] += o.md.d[k][i];
+    }
 };
 enum { ST_SHIFTS = 0, ST_SHIFTS_OK, ST_NEWTON_ATT, ST_NEWTON_CONV, ST_NEWTON_ITERS, ST_NEWTON_OK, ST_RAYS };
 
@@ -1478,7 +1499,8 @@ struct Oracle {
             uint64_t fp = full_pixel(pix);
             for (int pl : planes) {
                 Draw u = draw(s.seed, fp, frame, PASS_TEMPORAL, 0, (uint64_t)pl);
-                double ws = 0.0;
+                double ws = 0.0, w2 = 0.0, w0 = 0.0;
+                int npos = 0, npresent = 0;
                 bool have = false;
                 PathRec sel;
                 auto itc = can[pix].find(pl);
@@ -1492,22 +1514,30 @@ struct Oracle {
                     }
                     double w = (mc * ph / den) * ph * xr.W;
                     ws += w;
+                    w2 += w * w;
+                    w0 = w;
+                    ++npresent;
+                    npos += w > 0.0;
                     if (u.u(0) * ws < w) { sel = xr.y; have = true; }
                 }
                 if (qp >= 0) {
                     auto itp = fin_prev[qp].find(pl);
                     if (itp != fin_prev[qp].end()) {
                         const Res& xr = itp->second;
+                        ++npresent;
                         ShiftOut sh = shift(xr.y, 1, qp, 0, pix, pl, gate_shift(pl), st);
                         if (sh.ok) {
                             double a = mp * xr.y.phat / sh.J;
                             double m = a / (a + mc * sh.phat);
                             double w = m * sh.phat * xr.W * sh.J;
                             ws += w;
+                            w2 += w * w;
+                            npos += w > 0.0;
                             if (u.u(1) * ws < w) { sel = sh.y; have = true; }
                         }
                     }
                 }
+                if (ws > 0.0) st.md.item(0, ws, w2, npos, npresent, w0);
                 if (have && ws > 0.0) {
                     Res r;
                     r.y = sel;
@@ -1684,6 +1714,8 @@ struct Oracle {
                     Draw d = draw(s.seed, fp, frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + cand / 4));
                     return d.u(cand % 4);
                 };
+                double w2 = 0.0, w0 = 0.0;
+                int npos = 0, npresent = 0;
                 auto itq = in[pix].find(pl);
                 if (itq != in[pix].end()) {
                     const Res& xr = itq->second;
@@ -1696,6 +1728,10 @@ struct Oracle {
                     }
                     double w = mis_weight(s.mis_mode, -1, K, Ml.data(), mq, dl.data(), ph) * ph * xr.W;
                     ws += w;
+                    w2 += w * w;
+                    w0 = w;
+                    ++npresent;
+                    npos += w > 0.0;
                     if (uni(0) * ws < w) { sel = xr.y; have = true; }
                 }
                 for (int j = 0; j < K; ++j) {
@@ -1703,6 +1739,7 @@ struct Oracle {
                     auto itj = in[nb[j]].find(pl);
                     if (itj == in[nb[j]].end()) continue;
                     const Res& xr = itj->second;
+                    ++npresent;
                     ShiftOut sh = shift(xr.y, 0, nb[j], 0, pix, pl, 0.0, st);
                     if (!sh.ok) continue;
                     for (int l = 0; l < K; ++l) {
@@ -1714,8 +1751,11 @@ struct Oracle {
                     dl[j] = xr.y.phat / sh.J;
                     double w = mis_weight(s.mis_mode, j, K, Ml.data(), mq, dl.data(), sh.phat) * sh.phat * xr.W * sh.J;
                     ws += w;
+                    w2 += w * w;
+                    npos += w > 0.0;
                     if (uni(j + 1) * ws < w) { sel = sh.y; have = true; }
                 }
+                if (ws > 0.0) st.md.item(1, ws, w2, npos, npresent, w0);
                 if (have && ws > 0.0) {
                     Res r;
                     r.y = sel;
@@ -1859,6 +1899,12 @@ int orc_render_frame(void* ctx, const orc_frame* frame, double* out_image, doubl
 void orc_get_stats(void* ctx, uint64_t out[8]) {
     Oracle* o = (Oracle*)ctx;
     for (int i = 0; i < 8; ++i) out[i] = o->stats.c[i];
+}
+
+void orc_get_merge_diag(void* ctx, double out[10]) {
+    Oracle* o = (Oracle*)ctx;
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < 5; ++i) out[5 * k + i] = o->stats.md.d[k][i];
 }
 
 int orc_export_history(void* ctx, float* W, float* phat, float* len, float* pre_pdf, uint32_t* opix, uint32_t* ofr,

@@ -87,6 +87,14 @@ int orc_render_frame(void* ctx, const orc_frame* frame, double* out_image, doubl
  * newton_iters_sum, newton_paths_ok, rays, reserved. */
 void orc_get_stats(void* ctx, uint64_t out[8]);
 
+/* Diagnostics of the resampling weights, summed over every merge so far with
+ * a positive weight sum, for the temporal pass (out[0..4]) and the spatial
+ * rounds (out[5..9]): merges, effective sample count (sum w)^2 / sum w^2,
+ * candidates with w > 0, candidates present (non-empty reservoirs, before
+ * their shift), share of the canonical candidate in the weight sum.  A
+ * diagnostic, not part of what the hot path computes. */
+void orc_get_merge_diag(void* ctx, double out[10]);
+
 /* Export the final reservoirs of the last rendered frame (the temporal
  * history of the next frame) in a flat plane-major layout, element
  * [plane*P + pixel]: W, phat, len, pre_pdf, origin pixel, origin frame,

@@ -67,6 +67,7 @@ def lib():
         _lib.orc_set_gate_center.argtypes = [C.c_void_p, C.c_double]
         _lib.orc_render_frame.argtypes = [C.c_void_p, C.POINTER(OrcFrame), _f64p, _f64p, _f64p, _f64p]
         _lib.orc_get_stats.argtypes = [C.c_void_p, _u64p]
+        _lib.orc_get_merge_diag.argtypes = [C.c_void_p, _f64p]
         _lib.orc_philox4x64.argtypes = [_u64p, _u64p, _u64p]
         _lib.orc_load_frame.argtypes = [C.c_void_p, C.POINTER(OrcFrame)]
         _lib.orc_trace.argtypes = [C.c_void_p, _f64p, _f64p, C.c_int, _f64p]
@@ -234,6 +235,16 @@ class Oracle:
         keys = ["shifts", "shifts_ok", "newton_attempts", "newton_converged", "newton_iters",
                 "newton_paths_ok", "rays", "reserved"]
         return {k: int(v) for k, v in zip(keys, o)}
+
+    def merge_diag(self):
+        """Sums over the merges so far, per pass ("temporal", "spatial"):
+        merges, ess (effective sample count), positive (candidates with w > 0),
+        present (non-empty candidate reservoirs) and canonical_share."""
+        o = np.zeros(10, dtype=np.float64)
+        lib().orc_get_merge_diag(self.h, _p(o, _f64p))
+        keys = ["merges", "ess", "positive", "present", "canonical_share"]
+        return {name: {k: float(v) for k, v in zip(keys, o[5 * i:5 * i + 5])}
+                for i, name in enumerate(("temporal", "spatial"))}
 
     def export_history(self):
         """Final reservoirs of the last frame (float32 SoA, plane-major)."""

@@ -343,3 +343,26 @@ def test_mis_weights_partition_of_unity(oracle_lib):
     assert np.allclose(mw(1, M, mq, d, dc), [38 / 63, 1 / 9, 2 / 7], rtol=1e-14)
     # one neighbour: pairwise is the balance heuristic
     assert np.allclose(mw(1, [3.0, -1.0], 2.0, [0.4, 0.0], 0.7), mw(0, [3.0, -1.0], 2.0, [0.4, 0.0], 0.7))
+
+
+def test_merge_diagnostics_are_consistent(oracle_lib):
+    """The merge diagnostics (a report of the resampling weights, not part of
+    the estimate): per merge the effective sample count lies between 1 and
+    the number of candidates with a positive weight, which is at most the
+    number present, at most k + 1; the canonical share is a fraction.  Three
+    frames of the box with temporal and spatial reuse."""
+    from oracle.oracle import Oracle
+    w = scenes.cornell_box(frames=3)
+    o = Oracle(w.scene, w.sensor)
+    for fr in w.frames:
+        o.render(fr)
+    d = o.merge_diag()
+    o.close()
+    for name, kmax in (("temporal", 2), ("spatial", w.sensor.spatial_k + 1)):
+        r = d[name]
+        n = r["merges"]
+        assert n > 0, name
+        assert n - 1e-9 <= r["ess"] <= r["positive"] + 1e-9, (name, r)
+        assert r["positive"] <= r["present"] <= kmax * n, (name, r)
+        assert 0.0 <= r["canonical_share"] <= n + 1e-9, (name, r)
+    assert d["spatial"]["ess"] > 1.05 * d["spatial"]["merges"]   # spatial reuse does pool candidates
