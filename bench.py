@@ -104,6 +104,7 @@ def parse():
     ap.add_argument("--c5-only", action="store_true", help="run the near-specular stress leg alone")
     ap.add_argument("--c5-width", type=int, default=1920)
     ap.add_argument("--c5-height", type=int, default=1080)
+    ap.add_argument("--no-autotune", action="store_true", help="skip the tuned-launch-shape leg")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run the serving leg alone")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -387,6 +388,25 @@ def main():
                               "rays_per_frame": (st1["rays"] - st0["rays"]) // args.steps,
                               "kernel_ms_per_frame": {k: round(v["ms"] / args.steps, 3) for k, v in ktp.items()
                                                       if k != "work_items"}}
+
+    # the same window with the launch shape tof_autotune picks (tuned on
+    # frames 0..7 of the sequence, outside the timed region)
+    if not args.no_autotune:
+        r = Renderer(wl.scene, sensor)
+        t0 = time.perf_counter()
+        cfg = r.autotune([frame_at(i) for i in range(8)])
+        t_tune = time.perf_counter() - t0
+        for i in range(args.warmup):
+            r.render(frame_at(i))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            r.render(frame_at(args.warmup + k))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        r.close()
+        result["autotuned"] = {"launch_config": cfg, "autotune_s": round(t_tune, 2),
+                               "frames_per_s": round(args.steps / el, 3), "ms_per_step": round(1e3 * el / args.steps, 3)}
 
     # equal RMSE against plain ToF PT on the same GPU, over the sequence
     if not args.no_equal_rmse:
@@ -681,17 +701,27 @@ def specular_stress_leg(args, torch, warm=2, timed=3):
     r = Renderer(wl.scene, wl.sensor)
     torch.cuda.synchronize()
     t_create = time.perf_counter() - t0
-    ms = []
-    for i in range(warm):
-        r.render(wl.frames[i])
-    torch.cuda.synchronize()
-    st0 = r.stats()
-    for i in range(warm, warm + timed):
-        t0 = time.perf_counter()
-        r.render(wl.frames[i])
+
+    def window():
+        ms = []
+        for i in range(warm):
+            r.render(wl.frames[i])
         torch.cuda.synchronize()
-        ms.append(1e3 * (time.perf_counter() - t0))
-    st1 = r.stats()
+        s0 = r.stats()
+        for i in range(warm, warm + timed):
+            t0 = time.perf_counter()
+            r.render(wl.frames[i])
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+        return ms, s0, r.stats()
+
+    ms_default, _, _ = window()
+    # the launch shape tuned on the same frames (tof_autotune drops the
+    # history, so the window starts from an empty one again)
+    t0 = time.perf_counter()
+    cfg = r.autotune(wl.frames[:warm + timed - 1])
+    t_tune = time.perf_counter() - t0
+    ms, st0, st1 = window()
     r.close()
     d = {k: (st1[k] - st0[k]) // timed for k in ("shifts", "shifts_ok", "newton_attempts", "newton_converged",
                                                    "newton_paths_ok", "rays")}
@@ -702,7 +732,10 @@ def specular_stress_leg(args, torch, warm=2, timed=3):
                         f"{round(100 * ggx / sc.num_triangles, 1)}% GGX (alpha 0.01), 4 bounces, "
                         f"{wl.sensor.n_bins} bins + gate, temporal + 1 spatial round, Newton shift",
             "frames": [warm, warm + timed - 1], "ms_per_frame": [round(x, 2) for x in ms],
-            "frames_per_s": round(1e3 * timed / sum(ms), 3), "per_frame": d,
+            "frames_per_s": round(1e3 * timed / sum(ms), 3), "launch_config": cfg, "autotune_s": round(t_tune, 2),
+            "default_launch": {"ms_per_frame": [round(x, 2) for x in ms_default],
+                               "frames_per_s": round(1e3 * timed / sum(ms_default), 3)},
+            "per_frame": d,
             "hbm_gib": round(tof_footprint(wl.scene, wl.sensor) / (1 << 30), 1),
             "scene_build_s": round(t_scene, 2), "context_create_s": round(t_create, 2),
             "bvh_overflow": st1["bvh_overflow"], "bad_records": st1["bad_records"]}

@@ -202,8 +202,8 @@ tof_status tof_scene_upload(tof_ctx* ctx, const tof_scene_desc* scene);
  * keeps the history, and the next frame's temporal reuse shifts the previous
  * frame's paths by the move, Delta l = new centre - old centre (Sec. 4.1,
  * time-gate shifting).  Bins never move.  TOF_ERR_INVALID_ARG for settings
- * out of range, including width * height * planes * (spatial_k + 1) >= 2^32
- * (work lists use 32-bit indices).  Per-(pixel, plane) reservoirs are
+ * out of range, including width * height * planes >= 2^31 (work items use
+ * 32-bit indices).  Per-(pixel, plane) reservoirs are
  * allocated densely; the reuse passes run over chunks of work items whose
  * work space is sized to a ray budget, so the footprint grows with the
  * planes mainly through the reservoirs. */
@@ -222,7 +222,13 @@ tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
  * The frames of one context depend on each other (temporal reuse, scratch
  * work lists): issue them on one stream, or order the streams.  Calls that
  * read or replace the context's state (stats, timing, history, scene, sensor)
- * wait for the last frame issued, not for the whole device.  The bin-axis
+ * wait for the last frame issued, not for the whole device.  When a reuse
+ * pass may need more than one chunk of work items (large sensors: planes x
+ * pixels beyond one chunk's capacity), the call reads back the pass's item
+ * count after counting them on `stream` (a wait for the device that far) and
+ * launches only the chunks that hold items; contexts of the server and
+ * tof_render_frame_noalloc never wait, and launch every chunk the plan
+ * allows.  The bin-axis
  * pass and the shrink mapping count into the spatial and initial kernel
  * groups of tof_kernel_times.
  * Errors: TOF_ERR_NOT_READY without scene+sensor; TOF_ERR_INVALID_ARG for a
@@ -252,6 +258,36 @@ tof_status tof_render_frame(tof_ctx* ctx, const tof_frame_desc* frame, float* ou
  * is not recorded for these frames. */
 tof_status tof_render_frame_noalloc(tof_ctx* ctx, const tof_frame_desc* frame, float* out_image, float* out_hist,
                                     float* out_pt_image, float* out_pt_hist, void* stream);
+
+/* Launch shape of the reuse passes: the most blocks (of 128 lanes) that a
+ * shift kernel (forward and MIS shifts, the shrink mapping) and the
+ * visibility kernel launch per chunk.  shift_blocks: a multiple of 64 up to
+ * 8192, vis_blocks: a multiple of 64 up to 65536; 0 = the default (8192,
+ * 16384).  A smaller shift grid also makes the chunks smaller (each chunk is
+ * a whole number of grid sweeps).  Results do not depend on it, only speed:
+ * which lane shifts or traces what changes, not what is computed.  For
+ * callers that tune per workload (frame size, planes, scene); not in the
+ * paper.  Kept across sensor changes.  Waits for the context's last frame. */
+typedef struct {
+    uint32_t shift_blocks;
+    uint32_t vis_blocks;
+} tof_launch_config;
+tof_status tof_set_launch_config(tof_ctx* ctx, const tof_launch_config* config);
+tof_status tof_get_launch_config(tof_ctx* ctx, tof_launch_config* config);
+
+/* Pick the launch shape for this context's scene and sensor by timing:
+ * frames[0 .. n_frames-1] (host descriptors, 2 <= n_frames <= 64) are
+ * rendered from an empty history, once per candidate, on `stream`, and the
+ * later half of each run is timed with HIP events; the candidates are the
+ * shift grids 8192, 4096, 2048 at the default visibility grid, then the
+ * visibility grids 4096, 8192, 32768 at the best of those.  The fastest is
+ * set and returned in *chosen (may be NULL).  The tuning frames leave no other
+ * trace: the counters of tof_get_stats are restored, the temporal history is
+ * dropped (the next frame renders without temporal reuse), nothing is
+ * written to any output.  Errors as tof_render_frame; on an error the
+ * previous shape stays. */
+tof_status tof_autotune(tof_ctx* ctx, const tof_frame_desc* frames, int n_frames, void* stream,
+                        tof_launch_config* chosen);
 
 /* Drop the temporal history (the previous frame's final reservoirs that
  * temporal reuse resamples, Sec. 3.2.4 and Sec. 6): the next frame renders

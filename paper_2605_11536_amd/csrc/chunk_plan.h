@@ -18,7 +18,7 @@ constexpr unsigned kVisGrid = 16384;
 inline size_t lane_grid(size_t lanes, size_t cap) {
     return std::max<size_t>(64, std::min<size_t>(cap, ((lanes + 127) / 128 + 63) / 64 * 64));
 }
-inline size_t shift_grid(size_t tasks) { return lane_grid(tasks, kShiftGrid); }
+inline size_t shift_grid(size_t tasks, unsigned cap = kShiftGrid) { return lane_grid(tasks, cap); }
 // Scenes of at least this many triangles trace visibility with persistent
 // lanes, smaller ones one ray per lane on at most kShiftGrid blocks (the box
 // scenes of the serving mix: p50 latency 32.9 -> 27.7 ms that way).
@@ -34,9 +34,13 @@ struct ChunkPlan {
     unsigned grid[3] = {0, 0, 0}, vis_grid[3] = {0, 0, 0};
 };
 
-// ray_budget > 0 lowers the budget (test support: more, smaller chunks); a
-// chunk still holds at least one sweep of the smallest grid.
-inline ChunkPlan plan_chunks(size_t P, size_t B, int k, int br, size_t ray_budget = 0) {
+// ray_budget > 0 lowers the budget (more, smaller chunks); a chunk still
+// holds at least one sweep of the smallest grid.  shift_cap and vis_cap
+// (multiples of 64; shift_cap at most kShiftGrid when `within` is given) cap
+// the grids; `within`, the plan a work space was sized for, clamps every
+// chunk to that plan's (a multiple of this grid's sweep, which divides it).
+inline ChunkPlan plan_chunks(size_t P, size_t B, int k, int br, size_t ray_budget = 0, unsigned shift_cap = kShiftGrid,
+                             unsigned vis_cap = kVisGrid, const ChunkPlan* within = nullptr) {
     ChunkPlan p;
     const int modes = br > 0 ? 3 : 2;
     const size_t K[3] = {1, (size_t)std::max(k, 1), 2 * (size_t)std::max(br, 1)};
@@ -51,13 +55,14 @@ inline ChunkPlan plan_chunks(size_t P, size_t B, int k, int br, size_t ray_budge
     for (int m = 0; m < modes; ++m) {
         const size_t all = P * B * (K[m] + 1);
         const size_t raw = std::max<size_t>(1, std::min(p.rays / (seg[m] * K[m]), all));
-        const size_t G = tofh::shift_grid(raw), Q = G * 128;
+        const size_t G = tofh::shift_grid(raw, shift_cap), Q = G * 128;
         // a pass whose every task fits takes one chunk (rounded up to the
         // grid), else whole grid sweeps within the budget
         p.ct[m] = raw >= all ? (all + Q - 1) / Q * Q : std::max(Q, raw / Q * Q);
+        if (within) p.ct[m] = std::max(Q, std::min(p.ct[m], within->ct[m]) / Q * Q);
         p.ci[m] = std::max<size_t>(1, p.ct[m] / (K[m] + 1));
         p.grid[m] = (unsigned)G;
-        p.vis_grid[m] = (unsigned)tofh::lane_grid(seg[m] * K[m] * p.ct[m], kVisGrid);
+        p.vis_grid[m] = (unsigned)tofh::lane_grid(seg[m] * K[m] * p.ct[m], vis_cap);
         p.task_cap = std::max(p.task_cap, p.ct[m]);
         p.term_cap = std::max(p.term_cap, K[m] * p.ct[m]);
         p.ray_cap = std::max(p.ray_cap, seg[m] * K[m] * p.ct[m]);

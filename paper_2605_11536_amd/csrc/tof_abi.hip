@@ -107,7 +107,7 @@ struct tof_ctx {
     // workspace of one item chunk (sizes in plan)
     uint2* tasks = nullptr;    // [task_cap]
     float4* fwd = nullptr;     // [task_cap]: forward-shift terms per task
-    float4* wide = nullptr;    // [5 P]: wide-gate reservoirs of the shrink mapping with R < 1, else none
+    float4* wide = nullptr;    // [kRecF4 P]: wide-gate reservoirs of the shrink mapping with R < 1, else none
     float4* shv = nullptr;     // [2 * task_cap]: fields rewritten by each forward shift
     float* term = nullptr;     // [term_cap]: MIS terms per (task, neighbour)
     float4* rays = nullptr;    // [2 * ray_cap]: queued visibility segments
@@ -116,7 +116,17 @@ struct tof_ctx {
     uint32_t* mis_count = nullptr;
     uint32_t* count = nullptr;      // [0] items, [1] tasks, [2..3] window of the current chunk
     size_t max_items = 0;
-    tofh::ChunkPlan plan;
+    tofh::ChunkPlan alloc_plan;   // the plan the chunk work space was sized for
+    tofh::ChunkPlan plan;         // the plan the passes run: alloc_plan's chunks or smaller
+    // launch shape (tof_set_launch_config): most blocks of the shift kernels
+    // and of the visibility kernel
+    unsigned shift_blocks = tofh::kShiftGrid, vis_blocks = tofh::kVisGrid;
+    size_t ray_budget = 0;        // a lowered ray budget (test support), 0 = the plan's own
+    // a pass that may need more than one chunk reads its item count back and
+    // launches only the chunks that hold items (contexts of tof_create; a
+    // server context never waits in its dispatch, and launches them all)
+    bool sync_counts = false;
+    uint32_t* count_host = nullptr;   // pinned: the item count of the current pass
     // misc
     unsigned long long* counters = nullptr;
     float* xf_pinned[2] = {nullptr, nullptr};
@@ -367,6 +377,7 @@ namespace {
 // on that device, with the device current) and kept in g_scratch.
 // ---------------------------------------------------------------------------
 constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr unsigned kMaxVisBlocks = 65536;   // most blocks a launch shape may give the visibility kernel
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 constexpr int kMaxScratchDevices = 64;
 static std::mutex g_scratch_mu;
@@ -420,9 +431,15 @@ tof_status make_ctx(tof_ctx** out, int device, size_t budget, uint64_t seed, voi
     // the null-stream fill must be complete before any stream reads the counters
     ok = ok && hipMemset(c->counters, 0, kCounterBytes) == hipSuccess && hipStreamSynchronize(nullptr) == hipSuccess &&
          hipEventCreateWithFlags(&c->done, hipEventDisableTiming) == hipSuccess;
+    if (ok && !c->hbase) {
+        c->sync_counts = true;
+        ok = hipHostMalloc((void**)&c->count_host, 64) == hipSuccess;
+    }
     if (!ok) {
         (void)hipGetLastError();
         if (c->counters && !c->rbase) (void)hipFree(c->counters);
+        if (c->count_host) (void)hipHostFree(c->count_host);
+        if (c->done) (void)hipEventDestroy(c->done);
         delete c;
         return TOF_ERR_DEVICE;
     }
@@ -430,6 +447,12 @@ tof_status make_ctx(tof_ctx** out, int device, size_t budget, uint64_t seed, voi
     return TOF_OK;
 }
 
+// the passes' chunk plan for the context's launch shape and a ray budget (0:
+// the default), within the work space sized at tof_sensor_set
+tofh::ChunkPlan plan_of(const tof_ctx* c, size_t rays) {
+    return tofh::plan_chunks((size_t)c->s.P, (size_t)c->s.B, c->s.k, c->s.br, rays, c->shift_blocks, c->vis_blocks,
+                             &c->alloc_plan);
+}
 }  // namespace
 
 namespace tofh {
@@ -473,6 +496,7 @@ void tof_destroy(tof_ctx* c) {
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     if (c->done) (void)hipEventDestroy(c->done);
+    if (c->count_host) (void)hipHostFree(c->count_host);
     delete c;
 }
 
@@ -744,7 +768,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->direct, P));
     TOF_TRY(alloc_t(c, a, &c->prev_pix, P));
     TOF_TRY(alloc_t(c, a, &c->nb, P * (size_t)std::max(d->spatial_k, 1)));
-    const tofh::ChunkPlan& pl = c->plan = tofh::plan_chunks(P, (size_t)B, d->spatial_k, d->bin_radius);
+    const tofh::ChunkPlan& pl = c->alloc_plan = tofh::plan_chunks(P, (size_t)B, d->spatial_k, d->bin_radius);
     TOF_TRY(alloc_t(c, a, &c->items, P * B));
     TOF_TRY(alloc_t(c, a, &c->task0, P * B));
     TOF_TRY(alloc_t(c, a, &c->tasks, pl.task_cap));
@@ -805,6 +829,8 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     s.B = B;
     s.mask_words = (int)words;
     s.seed = c->seed;
+    c->ray_budget = 0;
+    c->plan = plan_of(c, 0);
     c->fin_prev = 2;
     c->has_sensor = true;
     return TOF_OK;
@@ -815,14 +841,108 @@ tof_status tof_debug_set_ray_budget(tof_ctx* c, size_t rays, size_t* spatial_ite
     if (!c->has_sensor) return TOF_ERR_NOT_READY;
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(quiesce(c));
-    const size_t P = (size_t)c->s.P, B = (size_t)c->s.B;
-    const tofh::ChunkPlan full = tofh::plan_chunks(P, B, c->s.k, c->s.br);   // what the work space holds
-    const tofh::ChunkPlan pl = tofh::plan_chunks(P, B, c->s.k, c->s.br, rays);
+    const tofh::ChunkPlan& full = c->alloc_plan;   // what the work space holds
+    const tofh::ChunkPlan pl = plan_of(c, rays);
     if (pl.task_cap > full.task_cap || pl.term_cap > full.term_cap || pl.ray_cap > full.ray_cap)
         return TOF_ERR_INVALID_ARG;
     c->plan = pl;
+    c->ray_budget = rays;
     if (spatial_items_per_chunk) *spatial_items_per_chunk = pl.ci[1];
     return TOF_OK;
+}
+
+tof_status tof_set_launch_config(tof_ctx* c, const tof_launch_config* cfg) {
+    if (!c || !cfg) return TOF_ERR_INVALID_ARG;
+    const unsigned sb = cfg->shift_blocks ? cfg->shift_blocks : tofh::kShiftGrid;
+    const unsigned vb = cfg->vis_blocks ? cfg->vis_blocks : tofh::kVisGrid;
+    if (sb % 64 != 0 || sb > tofh::kShiftGrid || vb % 64 != 0 || vb > kMaxVisBlocks) return TOF_ERR_INVALID_ARG;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(quiesce(c));
+    c->shift_blocks = sb;
+    c->vis_blocks = vb;
+    if (c->has_sensor) c->plan = plan_of(c, c->ray_budget);
+    return TOF_OK;
+}
+
+tof_status tof_get_launch_config(tof_ctx* c, tof_launch_config* out) {
+    if (!c || !out) return TOF_ERR_INVALID_ARG;
+    out->shift_blocks = c->shift_blocks;
+    out->vis_blocks = c->vis_blocks;
+    return TOF_OK;
+}
+
+tof_status tof_autotune(tof_ctx* c, const tof_frame_desc* frames, int n_frames, void* stream,
+                        tof_launch_config* chosen) {
+    if (!c || !frames || n_frames < 2 || n_frames > 64) return TOF_ERR_INVALID_ARG;
+    if (!c->has_scene || !c->has_sensor) return TOF_ERR_NOT_READY;
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(quiesce(c));
+    // the tuning frames leave no trace but the chosen shape: the counters and
+    // the frame count are restored and the temporal history is dropped
+    std::vector<unsigned long long> saved(kCounterBytes / sizeof(unsigned long long));
+    HIP_TRY(hipMemcpy(saved.data(), c->counters, kCounterBytes, hipMemcpyDeviceToHost));
+    const uint64_t frames0 = c->frames;
+    const bool timing = c->timing;
+    const unsigned sb0 = c->shift_blocks, vb0 = c->vis_blocks;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    tof_status res = TOF_OK;
+    unsigned best_sb = sb0, best_vb = vb0;
+    float best_ms = 3e38f;
+    // one candidate: the frames from the first, without history; the later
+    // half timed (the earlier half fills the reservoirs)
+    auto trial = [&](unsigned sb, unsigned vb) -> tof_status {
+        c->shift_blocks = sb;
+        c->vis_blocks = vb;
+        c->plan = plan_of(c, c->ray_budget);
+        c->prev_valid = false;
+        for (int i = 0; i < n_frames; ++i) {
+            if (i == n_frames / 2 && hipEventRecord(ev[0], st) != hipSuccess) return TOF_ERR_DEVICE;
+            TOF_TRY(tof_render_frame(c, frames + i, nullptr, nullptr, nullptr, nullptr, stream));
+        }
+        float ms = 0.f;
+        if (hipEventRecord(ev[1], st) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
+            return TOF_ERR_DEVICE;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_sb = sb;
+            best_vb = vb;
+        }
+        return TOF_OK;
+    };
+    c->timing = false;
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) res = TOF_ERR_DEVICE;
+    // coordinate search over powers of two: the shift kernels' blocks at the
+    // default visibility grid, then the visibility blocks at the best of those
+    for (unsigned sb : {tofh::kShiftGrid, tofh::kShiftGrid / 2, tofh::kShiftGrid / 4})
+        if (res == TOF_OK) res = trial(sb, tofh::kVisGrid);
+    const unsigned sb_best = best_sb;
+    for (unsigned vb : {tofh::kVisGrid / 4, tofh::kVisGrid / 2, tofh::kVisGrid * 2})
+        if (res == TOF_OK) res = trial(sb_best, vb);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (res == TOF_OK) {
+        c->shift_blocks = best_sb;
+        c->vis_blocks = best_vb;
+    } else {
+        c->shift_blocks = sb0;
+        c->vis_blocks = vb0;
+    }
+    c->plan = plan_of(c, c->ray_budget);
+    c->timing = timing;
+    c->prev_valid = false;
+    if (quiesce(c) == hipSuccess &&
+        hipMemcpy(c->counters, saved.data(), kCounterBytes, hipMemcpyHostToDevice) == hipSuccess) {
+        c->frames = frames0;
+    } else if (res == TOF_OK) {
+        res = TOF_ERR_DEVICE;
+    }
+    if (chosen) {
+        chosen->shift_blocks = c->shift_blocks;
+        chosen->vis_blocks = c->vis_blocks;
+    }
+    return res;
 }
 
 tof_status tof_debug_set_history(tof_ctx* c, const tof_history_desc* h) {
@@ -980,7 +1100,15 @@ tof_status run_pass(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, c
         tofh::launch_vis(a, slot, q, kill, pl.vis_grid[mode], st);
         return timer_mark(c, kv, st);
     };
-    for (size_t i0 = 0; i0 < c->max_items; i0 += ci) {
+    // the chunks that hold items: all the plan allows, or (when more than one
+    // is possible) those below the count k_items wrote, read back here
+    size_t n_items = c->max_items;
+    if (c->sync_counts && n_items > ci) {
+        HIP_TRY(hipMemcpyAsync(c->count_host, c->count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        n_items = std::min<size_t>(n_items, c->count_host[0]);
+    }
+    for (size_t i0 = 0; i0 < n_items; i0 += ci) {
         HIP_TRY(timer_mark(c, kf, st));
         tofh::launch_tasks(c->items, c->task0, c->count, i0, ci, c->tasks, win, st);
         tofh::launch_fill_u32(c->ray_count, 0u, ncounters, st);
@@ -1377,7 +1505,7 @@ tof_status tof_render_frame_noalloc(tof_ctx* c, const tof_frame_desc* fr, float*
     while (carve_work(c, pl, nullptr, w) > kScratchBytes) {
         if (rays <= 1) return TOF_ERR_OUT_OF_MEMORY;   // the per-(pixel, plane) parts alone do not fit
         rays /= 2;
-        pl = tofh::plan_chunks((size_t)c->s.P, (size_t)c->s.B, c->s.k, c->s.br, rays);
+        pl = plan_of(c, rays);
     }
     HIP_TRY(hipSetDevice(c->device));
     void* base = nullptr;
@@ -1388,14 +1516,16 @@ tof_status tof_render_frame_noalloc(tof_ctx* c, const tof_frame_desc* fr, float*
     // so the previous call's contents do not matter
     const FrameWork own = work_of(c);
     const tofh::ChunkPlan own_plan = c->plan;
-    const bool timing = c->timing;
+    const bool timing = c->timing, sync_counts = c->sync_counts;
     c->timing = false;   // event timing creates events on demand: not recorded here
+    c->sync_counts = false;   // no wait for the device inside the call: every chunk is launched
     set_work(c, w);
     c->plan = pl;
     const tof_status st = tof_render_frame(c, fr, out_image, out_hist, out_pt_image, out_pt_hist, stream);
     set_work(c, own);
     c->plan = own_plan;
     c->timing = timing;
+    c->sync_counts = sync_counts;
     return st;
 }
 

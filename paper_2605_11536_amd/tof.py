@@ -51,6 +51,10 @@ class tof_sensor_desc(C.Structure):
                 ("round_trip", C.c_int32), ("mis_mode", C.c_int32)]
 
 
+class tof_launch_config(C.Structure):
+    _fields_ = [("shift_blocks", C.c_uint32), ("vis_blocks", C.c_uint32)]
+
+
 class tof_frame_desc(C.Structure):
     _fields_ = [("frame_index", C.c_int32), ("cam_pos", C.c_float * 3), ("cam_fwd", C.c_float * 3),
                 ("cam_up", C.c_float * 3), ("fov_y_deg", C.c_float), ("ortho_half", C.c_float * 2),
@@ -113,6 +117,12 @@ def lib():
         L.tof_debug_set_ray_budget.restype = C.c_int
         L.tof_debug_set_history.argtypes = [C.c_void_p, C.POINTER(tof_history_desc)]
         L.tof_debug_set_history.restype = C.c_int
+        L.tof_set_launch_config.argtypes = [C.c_void_p, C.POINTER(tof_launch_config)]
+        L.tof_get_launch_config.argtypes = [C.c_void_p, C.POINTER(tof_launch_config)]
+        L.tof_autotune.argtypes = [C.c_void_p, C.POINTER(tof_frame_desc), C.c_int, C.c_void_p,
+                                   C.POINTER(tof_launch_config)]
+        for f in ("tof_set_launch_config", "tof_get_launch_config", "tof_autotune"):
+            getattr(L, f).restype = C.c_int
         L.tof_set_kernel_timing.argtypes = [C.c_void_p, C.c_int]
         L.tof_set_kernel_timing.restype = C.c_int
         L.tof_get_kernel_times.argtypes = [C.c_void_p, C.POINTER(tof_kernel_times)]
@@ -269,6 +279,34 @@ def tof_render_frame_noalloc(h, frame, out_image=None, out_hist=None, out_pt_ima
                                           _dptr(out_pt_hist), C.c_void_p(stream.cuda_stream)))
 
 
+def tof_set_launch_config(h, shift_blocks: int = 0, vis_blocks: int = 0) -> None:
+    cfg = tof_launch_config(int(shift_blocks), int(vis_blocks))
+    _check("tof_set_launch_config", lib().tof_set_launch_config(h, C.byref(cfg)))
+
+
+def tof_get_launch_config(h) -> dict:
+    cfg = tof_launch_config()
+    _check("tof_get_launch_config", lib().tof_get_launch_config(h, C.byref(cfg)))
+    return {"shift_blocks": int(cfg.shift_blocks), "vis_blocks": int(cfg.vis_blocks)}
+
+
+def tof_autotune(h, frames, stream=None) -> dict:
+    """Time the candidate launch shapes over `frames` (a list of Frame) and
+    keep the fastest; returns it."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    descs, keep = [], []
+    for fr in frames:
+        d, k = frame_desc(fr)
+        descs.append(d)
+        keep.append(k)
+    arr = (tof_frame_desc * len(descs))(*descs)
+    cfg = tof_launch_config()
+    _check("tof_autotune", lib().tof_autotune(h, arr, len(descs), C.c_void_p(stream.cuda_stream), C.byref(cfg)))
+    return {"shift_blocks": int(cfg.shift_blocks), "vis_blocks": int(cfg.vis_blocks)}
+
+
 def tof_reservoirs_reset(h) -> None:
     _check("tof_reservoirs_reset", lib().tof_reservoirs_reset(h))
 
@@ -385,6 +423,15 @@ class Renderer:
 
     def set_history(self, hist: dict):
         tof_debug_set_history(self.h, hist)
+
+    def set_launch_config(self, shift_blocks: int = 0, vis_blocks: int = 0):
+        tof_set_launch_config(self.h, shift_blocks, vis_blocks)
+
+    def launch_config(self) -> dict:
+        return tof_get_launch_config(self.h)
+
+    def autotune(self, frames, stream=None) -> dict:
+        return tof_autotune(self.h, frames, stream)
 
     def close(self):
         if self.h:

@@ -120,6 +120,21 @@ static void plan_check() {
                             CHECK(q.ci[m] >= 1 && q.ci[m] * (K[m] + 1) <= q.ct[m]);
                         }
                     }
+                    // any launch shape within the work space (tof_set_launch_config,
+                    // tof_autotune): whole sweeps of its own grid, no chunk larger
+                    // than the default plan's, grids within their caps
+                    for (unsigned sb : {64u, 192u, 2048u, 4096u, tofh::kShiftGrid})
+                        for (unsigned vb : {64u, 4096u, 32768u, 65536u})
+                            for (size_t rays : {(size_t)0, (size_t)81920}) {
+                                const tofh::ChunkPlan q = tofh::plan_chunks(P, B, k, br, rays, sb, vb, &p);
+                                CHECK(q.task_cap <= p.task_cap && q.term_cap <= p.term_cap && q.ray_cap <= p.ray_cap);
+                                for (int m = 0; m < (br > 0 ? 3 : 2); ++m) {
+                                    CHECK(q.grid[m] >= 64 && q.grid[m] <= sb && q.grid[m] % 64 == 0);
+                                    CHECK(q.vis_grid[m] >= 64 && q.vis_grid[m] <= vb && q.vis_grid[m] % 64 == 0);
+                                    CHECK(q.ct[m] % ((size_t)q.grid[m] * 128) == 0 && q.ct[m] <= p.ct[m]);
+                                    CHECK(q.ci[m] >= 1 && q.ci[m] * (K[m] + 1) <= q.ct[m]);
+                                }
+                            }
                 }
 }
 
