@@ -689,13 +689,38 @@ __global__ void __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(6))) k
 // Weights follow eq. GRIS_resampling_weight with the generalized balance
 // heuristic from the terms of k_fwd and k_mis.  A selected neighbour sample is
 // its source record with the fields its shift into q rewrote.
+//
+// A wave takes 64 consecutive items, whose tasks are contiguous.  Its lanes
+// first take one item each (pixel, plane, confidences, staged in LDS), then
+// one task each over the items' task range -- consecutive lanes read
+// consecutive forward terms and MIS terms -- and leave each task's weight in
+// LDS; then one item each again, drawing in candidate order from those
+// weights (the same arithmetic, in the same order, as a lane that walks its
+// item's candidates alone); then four lanes per item copy the winners'
+// records, one float4 each, with the fields the shift rewrote (the same bits
+// as decoding the record, patching it and encoding it again).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, ResSet Bp,
-                                               const int* __restrict__ links, const uint2* __restrict__ items,
-                                               const uint32_t* __restrict__ task0, const uint32_t* __restrict__ count,
-                                               uint32_t i0, uint32_t ci, const uint32_t* __restrict__ win,
-                                               const float4* __restrict__ fwd, const float* __restrict__ term,
-                                               const float4* __restrict__ shv, int round, ResSet out) {
+constexpr int kMergeWaves = 4;                   // waves per block of k_merge
+constexpr int kMergeTasks = 64 * (kMaxK + 1);    // tasks of a wave's 64 items, at most
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mode, ResSet A, ResSet Bp,
+                                                            const int* __restrict__ links,
+                                                            const uint2* __restrict__ items,
+                                                            const uint2* __restrict__ tasks,
+                                                            const uint32_t* __restrict__ task0,
+                                                            const uint32_t* __restrict__ count, uint32_t i0,
+                                                            uint32_t ci, const uint32_t* __restrict__ win,
+                                                            const float4* __restrict__ fwd,
+                                                            const float* __restrict__ term,
+                                                            const float4* __restrict__ shv, int round, ResSet out) {
+    __shared__ float2 s_w[kMergeWaves][kMergeTasks];   // per task: weight (-1: not a candidate), phat_q
+    __shared__ float4 s_it[kMergeWaves][64];           // per item: M_q, M_tot, M_q / k_v, pairwise (1) or not (0)
+    __shared__ float s_ml[kMergeWaves][64 * kMaxK];    // per item: neighbour confidences (-1: no pixel)
+    __shared__ uint4 s_sel[kMergeWaves][64];           // per item: source record, output record, task, W bits
     const Sens& s = a.s;
     const int P = s.P;
     const int K = pass_K(s, mode);
@@ -705,106 +730,172 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
     const uint32_t n = ni - i0 > ci ? i0 + ci : ni;
     const uint32_t tb = win[0];
     const int lane = (int)__lane_id();
-    // wave-uniform loop (the mask reduction below needs every lane)
-    for (uint32_t it0 = i0 + blockIdx.x * 256 + (threadIdx.x & ~63u); it0 < n; it0 += gridDim.x * 256) {
+    const int wv = (int)(threadIdx.x >> 6);
+    const bool pw = mode == 1 && s.mis_mode == 1;
+    // wave-uniform loop (the shuffles below need every lane)
+    for (uint32_t it0 = i0 + blockIdx.x * (64 * kMergeWaves) + 64 * (uint32_t)wv; it0 < n;
+         it0 += gridDim.x * (64 * kMergeWaves)) {
         const uint32_t it = it0 + (uint32_t)lane;
-        // mask word and bit this lane sets (0xFFFFFFFF: none)
-        uint32_t mkey = 0xFFFFFFFFu, mbit = 0u;
-        if (it < n) {
-        const uint2 item = items[it];
-        const int pix = (int)item.x, pl = (int)(item.y & 0xFFFFu);
-        const uint32_t cm = item.y >> 16;
-        const uint32_t t0 = task0[it] - tb;
-        const uint64_t fp = full_pixel(s, pix);
-        const float mq = A.M[pix];
-        // pairwise MIS: the neighbours' confidences and the canonical share
-        const bool pw = mode == 1 && s.mis_mode == 1;
-        float ml[kMaxK];
-        float mtot = mq, mqk = mq;
-        int kv = 0;
-        if (pw) {
-            for (int l = 0; l < K; ++l) {
-                const int dp = links[(size_t)l * P + pix];
-                ml[l] = dp >= 0 ? A.M[dp] : -1.f;   // -1: no neighbour pixel
-                if (dp >= 0) {
-                    mtot += ml[l];
-                    ++kv;
+        const bool have = it < n;
+        // 1. one lane per item
+        int pix = 0, pl = 0;
+        uint32_t cm = 0, t0 = 0;
+        if (have) {
+            const uint2 item = items[it];
+            pix = (int)item.x;
+            pl = (int)(item.y & 0xFFFFu);
+            cm = item.y >> 16;
+            t0 = task0[it] - tb;
+            const float mq = A.M[pix];
+            // pairwise MIS: the neighbours' confidences and the canonical share
+            float mtot = mq, mqk = mq;
+            int kv = 0;
+            if (pw) {
+                for (int l = 0; l < K; ++l) {
+                    const int dp = links[(size_t)l * P + pix];
+                    const float ml = dp >= 0 ? A.M[dp] : -1.f;   // -1: no neighbour pixel
+                    s_ml[wv][lane * kMaxK + l] = ml;
+                    if (dp >= 0) {
+                        mtot += ml;
+                        ++kv;
+                    }
                 }
+                if (kv > 0) mqk = mq / (float)kv;
             }
-            if (kv > 0) mqk = mq / (float)kv;
+            s_it[wv][lane] = make_float4(mq, mtot, mqk, pw && kv > 0 ? 1.f : 0.f);
         }
-        const bool pairwise = pw && kv > 0;
-        Draw ut;
-        if (mode == 0) ut = philox(s.seed, fp, a.frame, PASS_TEMPORAL, 0, (uint64_t)pl);
-        float ws = 0.f, sel_phat = 0.f;
-        int sel = -1;
-        uint32_t sel_t = 0;
-        // one Philox draw serves four candidates: drawn when its first
-        // candidate with a weight needs it
-        Draw ug;
-        int ug_id = -1;
-        for (int c = 0; c < ncand; ++c) {
-            if (!((cm >> c) & 1u)) continue;
-            const uint32_t t = t0 + (uint32_t)__popc(cm & ((1u << c) - 1u));
+        // the wave's task range: from its first item's first task to the end
+        // of its last item's tasks
+        const uint32_t tlo = __shfl(t0, 0, 64);
+        const uint64_t live = __ballot(have);
+        const int last = 63 - __clzll((long long)live);
+        const uint32_t thi = __shfl(t0 + (uint32_t)__popc(cm), last, 64);
+        const uint32_t nt = thi - tlo;
+        wave_sync();
+        // 2. one lane per task: its weight
+        for (uint32_t j = (uint32_t)lane; j < nt; j += 64) {
+            const uint32_t t = tlo + j;
+            const uint2 tk = tasks[t];
+            const int il = (int)(tk.x - it0), c = (int)tk.y;
             const float4 fw = fwd[t];
             const float phq = fw.x;
-            if (c > 0 && !(phq > 0.f)) continue;   // the shift into q failed
-            float m;
-            if (pairwise) {
-                if (c == 0) {
-                    m = 0.f;
-                    const float qk = mqk * phq;
-                    for (int l = 0; l < K; ++l)
-                        if (ml[l] >= 0.f) m += (ml[l] + mqk) / mtot * (qk / (qk + term[(size_t)t * K + l]));
+            float w = -1.f;
+            if (c == 0 || phq > 0.f) {   // else the shift into q failed
+                const float4 iv = s_it[wv][il];
+                const float mq = iv.x;
+                float m;
+                if (iv.w != 0.f) {   // pairwise
+                    const float mtot = iv.y, mqk = iv.z;
+                    const float* ml = &s_ml[wv][il * kMaxK];
+                    if (c == 0) {
+                        m = 0.f;
+                        const float qk = mqk * phq;
+                        for (int l = 0; l < K; ++l)
+                            if (ml[l] >= 0.f) m += (ml[l] + mqk) / mtot * (qk / (qk + term[(size_t)t * K + l]));
+                    } else {
+                        m = (ml[c - 1] + mqk) / mtot * (fw.z / (fw.z + mqk * phq));
+                    }
                 } else {
-                    m = (ml[c - 1] + mqk) / mtot * (fw.z / (fw.z + mqk * phq));
+                    float den = fw.z + mq * phq;
+                    for (int l = 0; l < K; ++l) den += term[(size_t)t * K + l];
+                    m = (c == 0 ? mq * phq : fw.z) / den;
                 }
-            } else {
-                float den = fw.z + mq * phq;
-                for (int l = 0; l < K; ++l) den += term[(size_t)t * K + l];
-                m = (c == 0 ? mq * phq : fw.z) / den;
+                w = m * phq * fw.w * fw.y;
+                if (c > 0 && !(w > 0.f)) w = -1.f;
             }
-            const float w = m * phq * fw.w * fw.y;
-            if (c > 0 && !(w > 0.f)) continue;
-            float u;
-            if (mode == 0) {
-                u = ut.u_sel(c);
-            } else {
-                if (c / 4 != ug_id) {
-                    ug_id = c / 4;
-                    ug = mode == 1 ? philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2,
-                                            (uint64_t)(pl * 2 + ug_id))
-                                   : philox(s.seed, fp, a.frame, PASS_BIN, 0, (uint64_t)(pl * 4 + ug_id));
+            s_w[wv][j] = make_float2(w, phq);
+        }
+        wave_sync();
+        // 3. one lane per item: the draw over its candidates in order
+        uint32_t mkey = 0xFFFFFFFFu, mbit = 0u;   // mask word and bit this lane sets (none)
+        if (have) {
+            const uint64_t fp = full_pixel(s, pix);
+            Draw ut;
+            if (mode == 0) ut = philox(s.seed, fp, a.frame, PASS_TEMPORAL, 0, (uint64_t)pl);
+            float ws = 0.f, sel_phat = 0.f;
+            int sel = -1;
+            uint32_t sel_t = 0;
+            // one Philox draw serves four candidates: drawn when its first
+            // candidate with a weight needs it
+            Draw ug;
+            int ug_id = -1;
+            for (int c = 0; c < ncand; ++c) {
+                if (!((cm >> c) & 1u)) continue;
+                const uint32_t t = t0 + (uint32_t)__popc(cm & ((1u << c) - 1u));
+                const float2 wp = s_w[wv][t - tlo];
+                const float w = wp.x;
+                if (w < 0.f) continue;
+                float u;
+                if (mode == 0) {
+                    u = ut.u_sel(c);
+                } else {
+                    if (c / 4 != ug_id) {
+                        ug_id = c / 4;
+                        ug = mode == 1 ? philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2,
+                                                (uint64_t)(pl * 2 + ug_id))
+                                       : philox(s.seed, fp, a.frame, PASS_BIN, 0, (uint64_t)(pl * 4 + ug_id));
+                    }
+                    u = ug.u_sel(c % 4);
                 }
-                u = ug.u_sel(c % 4);
+                ws += w;
+                if (u * ws < w) {
+                    sel = c;
+                    sel_phat = wp.y;
+                    sel_t = t;
+                }
             }
-            ws += w;
-            if (u * ws < w) {
-                sel = c;
-                sel_phat = phq;
-                sel_t = t;
+            // the winner: its record (plane-major index; bit 31 set for the
+            // canonical one, whose fields stay), the output record, its task
+            // and the new contribution weight; none: an empty output index
+            uint4 wsel = make_uint4(0u, 0xFFFFFFFFu, 0u, 0u);
+            if (sel >= 0 && ws > 0.f) {
+                const uint32_t oidx = (uint32_t)pl * (uint32_t)P + (uint32_t)pix;
+                const uint32_t sidx = sel == 0 ? (oidx | 0x80000000u)
+                                               : (uint32_t)cand_plane(mode, pl, sel) * (uint32_t)P +
+                                                     (uint32_t)cand_src(mode, links, P, pix, sel);
+                wsel = make_uint4(sidx, oidx, sel_t, __float_as_uint(ws / sel_phat));
+                mkey = (uint32_t)(pl >> 5) * (uint32_t)P + (uint32_t)pix;
+                mbit = 1u << (pl & 31);
             }
+            s_sel[wv][lane] = wsel;
+        } else {
+            s_sel[wv][lane] = make_uint4(0u, 0xFFFFFFFFu, 0u, 0u);
         }
-        if (sel >= 0 && ws > 0.f) {
-            const size_t oidx = (size_t)pl * P + pix;
-            float Wx;
-            if (sel == 0) {
-                const Rec x = load_rec(A, oidx, Wx);
-                store_rec(out, oidx, x, ws / sel_phat);
-            } else {
-                const int src = cand_src(mode, links, P, pix, sel);
-                Rec x = load_rec(mode == 0 ? Bp : A, (size_t)cand_plane(mode, pl, sel) * P + src, Wx);
-                const float4 s0 = shv[2 * (size_t)sel_t], s1 = shv[2 * (size_t)sel_t + 1];
-                x.v[0] = VRef{__float_as_int(s0.x), s0.y, s0.z};
-                x.v[1] = VRef{__float_as_int(s0.w), s1.x, s1.y};
-                x.len = s1.z;
-                x.pre_pdf = s1.w;
-                x.phat = sel_phat;
-                store_rec(out, oidx, x, ws / sel_phat);
+        wave_sync();
+        // 4. four lanes per item: float4 e of the winner's record
+        {
+            const int e = lane & 3;
+            const ResSet& srcset = mode == 0 ? Bp : A;
+            for (int r = 0; r < 4; ++r) {
+                const uint4 ws4 = s_sel[wv][16 * r + (lane >> 2)];
+                if (ws4.y == 0xFFFFFFFFu) continue;
+                const bool canon = (ws4.x & 0x80000000u) != 0u;
+                const size_t si = canon ? (size_t)(ws4.x & 0x7FFFFFFFu) : (size_t)ws4.x;
+                const float Wn = __uint_as_float(ws4.w);
+                const float4* q = (canon ? A : srcset).rec + si * kRecF4;
+                float4 v;
+                if (canon) {
+                    v = q[e];
+                    if (e == 0) v.x = Wn;
+                } else {
+                    const float4 s0 = shv[2 * (size_t)ws4.z], s1 = shv[2 * (size_t)ws4.z + 1];
+                    if (e == 0) {
+                        v = make_float4(Wn, fwd[ws4.z].x, s1.z, s1.w);
+                    } else if (e == 1) {
+                        v = q[1];
+                        // objects 0 and 1 of word 7 from the shift, object 2's low bits kept
+                        const uint32_t w7 = (__float_as_uint(v.w) & 0xFF000000u) |
+                                            ((uint32_t)__float_as_int(s0.x) & 0xFFFu) |
+                                            (((uint32_t)__float_as_int(s0.w) & 0xFFFu) << 12);
+                        v.w = __uint_as_float(w7);
+                    } else if (e == 2) {
+                        v = make_float4(s0.y, s0.z, s1.x, s1.y);
+                    } else {
+                        v = q[3];
+                    }
+                }
+                out.rec[(size_t)ws4.y * kRecF4 + e] = v;
             }
-            mkey = (uint32_t)(pl >> 5) * (uint32_t)P + (uint32_t)pix;
-            mbit = 1u << (pl & 31);
-        }
         }
         // Items of one pixel are consecutive, so lanes that set bits of the
         // same mask word form runs: OR the bits down each run (a segmented
@@ -817,6 +908,7 @@ __global__ void __launch_bounds__(256) k_merge(FrameArgs a, int mode, ResSet A, 
         }
         const uint32_t kprev = __shfl_up(mkey, 1, 64);
         if (mbit && (lane == 0 || kprev != mkey)) atomicOr(out.mask + mkey, mbit);
+        wave_sync();   // the next items' weights overwrite this wave's LDS
     }
 }
 
@@ -1080,11 +1172,13 @@ void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, un
         hipLaunchKernelGGL(k_vis_lanes, dim3(std::min(grid, kShiftGrid)), dim3(kTB), 0, st, a, slot, q, kill);
 }
 void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
-                  const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,
+                  const uint2* items, const uint2* tasks, const uint32_t* task0, const uint32_t* count, size_t i0,
+                  size_t ci,
                   const uint32_t* win, const float4* fwd, const float* term, const float4* shv, int round, ResSet out,
                   hipStream_t st) {
-    hipLaunchKernelGGL(k_merge, dim3(grid_for(ci, 256, 32768)), dim3(256), 0, st, a, mode, A, Bp, links, items,
-                       task0, count, (uint32_t)i0, (uint32_t)ci, win, fwd, term, shv, round, out);
+    hipLaunchKernelGGL(k_merge, dim3(grid_for(ci, 64 * kMergeWaves, 32768)), dim3(64 * kMergeWaves), 0, st, a, mode,
+                       A, Bp, links, items, tasks, task0, count, (uint32_t)i0, (uint32_t)ci, win, fwd, term, shv,
+                       round, out);
 }
 void launch_shrink(const FrameArgs& a, const ResSet& can, size_t p0, size_t np, const RayQueue& q, unsigned grid,
                    hipStream_t st) {

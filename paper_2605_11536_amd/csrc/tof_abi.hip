@@ -1126,8 +1126,8 @@ tof_status run_pass(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, c
         HIP_TRY(vis(mode == 0 ? 1 : 0, qm, c->term));
         HIP_TRY(timer_mark(c, kg, st));
         a.counters = c->counters + (size_t)kg * kBank;
-        tofh::launch_merge(a, mode, A, Bp, links, c->items, c->task0, c->count, i0, ci, win, c->fwd, c->term, c->shv,
-                           round, out, st);
+        tofh::launch_merge(a, mode, A, Bp, links, c->items, c->tasks, c->task0, c->count, i0, ci, win, c->fwd, c->term,
+                           c->shv, round, out, st);
         HIP_TRY(timer_mark(c, kg, st));
     }
     return TOF_OK;
