@@ -52,36 +52,32 @@ MIN_FRAC = 0.999
 MIN_FRAC_NEWTON = 0.998
 
 
-def has_ggx(scene):
-    return bool((scene.mat_type == 1).any())
-
-
 def bar_for(key, scene, stage):
     """Which bar an output meets.
 
     "strict": >= 99.9% of the support within 1e-4 (at least one entry may lie
-    outside on a support under 1000 entries) and all of it within 1e-3.  Plain
-    PT (and the canonical reservoirs, before any shift) of scenes without GGX
-    surfaces.  The entries outside 1e-4 here are paths that meet a sphere at a
-    grazing angle and then see the light at a grazing angle: the FP32 hit point
-    moves along the surface by a few 1e-6, and the light's cosine of a few
-    1e-2 by 1e-4 of itself.
+    outside on a support under 1000 entries) and all of it within 1e-3.
+    Plain PT, and the canonical reservoirs before any shift, of every scene,
+    GGX surfaces included.  The entries outside 1e-4 here are paths that meet
+    a surface or the light at a grazing angle: the FP32 hit point moves along
+    the surface by a few 1e-6, and a cosine of a few 1e-2 by 1e-4 of itself.
+    (GGX scenes met it once the GGX sampler took sin = tan cos instead of
+    sqrt(1 - cos^2) and the charts took their tangents from vertices relative
+    to their object's origin.)
 
     "statistical": >= 99.9% of all entries within 1e-4, >= 99.8% of the
     support within 1e-3, and no systematic sign of the entries outside 1e-4.
     ReSTIR outputs after reuse: the Newton system is ill-conditioned where the
     path length is nearly stationary on the chart, so the FP32 positions of the
     device (1e-7 relative) move the shifted vertex and its Jacobian by up to a
-    few 1e-4.  Plain PT of GGX scenes: paths that graze a surface (|cos| of a
-    few 1e-3) or a silhouette (a ray within 1e-6 of an edge) turn FP32
-    position rounding into 1e-4..1e-3 of a contribution, or decide a hit
-    differently.  A few support entries (about 0.1% of a frame after two or
+    few 1e-4.  A few support entries (about 0.1% of a frame after two or
     three frames of reuse) differ by a whole sample: a Newton convergence, a
     round trip or a weighted selection decided the other way where the FP32
     and FP64 values straddle the threshold; the shift counts of both sides
     agree to 0.2%."""
+    del scene   # the bar no longer depends on the materials
     canonical = stage == 0 and not key.startswith("pt_")
-    if (key.startswith("pt_") or canonical) and not has_ggx(scene):
+    if key.startswith("pt_") or canonical:
         return "strict"
     return "statistical"
 
