@@ -267,6 +267,47 @@ def test_specular_stress_crop_parity():
         assert abs(gs[k] - os_[k]) <= 0.002 * max(os_[k], 1) + 2, (k, gs[k], os_[k])
 
 
+def test_specular_stress_full_size_sampled_parity():
+    """The near-specular stress configuration at its full 1920x1080 x 513
+    planes (1.06 G pixel-planes, the benchmark's configuration and launch
+    shape, 219.7 GiB of device memory), compared on the central 48x32 pixels
+    with an oracle rendering a 176x160 crop around them, on the first frame
+    (no temporal history; spatial reuse reaches 30 px, inside the 64 px
+    margin), at the per-frame bar.  Later frames carry the whole frame's
+    history on the GPU and the crop's on the oracle, so they are not
+    comparable pixel by pixel here; the crop case above covers them."""
+    import torch
+    from oracle.oracle import Oracle
+    from paper_2605_11536_amd.tof import Renderer
+    full = scenes.specular_stress(frames=2)
+    crop = scenes.specular_stress(width=176, height=160, full_width=1920, full_height=1080, crop_x0=872, crop_y0=460,
+                                  frames=2)
+    nb = full.sensor.n_bins
+    ys, xs = slice(524, 556), slice(936, 984)      # the centre in the full frame
+    oys, oxs = slice(64, 96), slice(64, 112)       # the same pixels in the crop
+    gpu = Renderer(full.scene, full.sensor)
+    orc = Oracle(crop.scene, crop.sensor)
+    try:
+        print("case specular full 1920x1080 frame 0", flush=True)
+        gpu.render(full.frames[0])
+        g = {"image": gpu.out_image.view(1080, 1920)[ys, xs].cpu().numpy(),
+             "pt_image": gpu.out_pt_image.view(1080, 1920)[ys, xs].cpu().numpy(),
+             "hist": gpu.out_hist.view(nb, 1080, 1920)[:, ys, xs].cpu().numpy(),
+             "pt_hist": gpu.out_pt_hist.view(nb, 1080, 1920)[:, ys, xs].cpu().numpy()}
+        o = orc.render(crop.frames[0])
+        assert np.count_nonzero(o["hist"][..., oys, oxs]) > 500
+        for key in ("image", "pt_image", "hist", "pt_hist"):
+            assert_parity(g[key], o[key][..., oys, oxs], f"specular full f0 {key}",
+                          bar_for(key, full.scene, full.sensor.debug_stage))
+        st = gpu.stats()
+        assert st["bvh_overflow"] == 0 and st["bad_records"] == 0 and st["shifts"] > 0
+    finally:
+        gpu.close()
+        orc.close()
+        del gpu
+        torch.cuda.empty_cache()   # 220 GiB and its output tensors, before the next test
+
+
 def test_pairwise_mis_parity():
     """Pairwise MIS in the spatial pass (only the canonical sample is shifted
     into the neighbours): the box with temporal and spatial reuse, and the
