@@ -194,7 +194,10 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.serving_only:
-        print(json.dumps({"serving": serving(args, torch)}), flush=True)
+        s0 = serving(args, torch)
+        s1 = serving(args, torch, graphs=True, solo=s0.pop("_solo_s"))
+        s1.pop("_solo_s")
+        print(json.dumps({"serving": s0, "serving_graphs": s1}), flush=True)
         return
     if args.c5_only:
         print(json.dumps({"specular_stress": specular_stress_leg(args, torch)}), flush=True)
@@ -419,6 +422,11 @@ def main():
         result["cost_vs_bins"] = bins_sweep(wl, frame_at, args, torch, Renderer)
     if not args.no_serving:
         result["serving"] = serving(args, torch)
+        # the same arrivals with every frame recorded into a graph and
+        # launched as one (tof_server_set_graphs)
+        sg = serving(args, torch, graphs=True, solo=result["serving"].pop("_solo_s"))
+        result["serving_graphs"] = {k: sg[k] for k in ("latency_ms", "service_ms", "queueing_ms", "latency_ms_p50_by_kind",
+                                                       "latency_ms_p99_by_kind", "frames_per_s", "wall_s")}
     if not args.no_c5:
         result["specular_stress"] = specular_stress_leg(args, torch)
     if args.copy_probe:
@@ -442,7 +450,7 @@ SERVE_NLOS_SCAN = (32, 64)
 SERVE_NLOS_BINS = (256, 1024)
 
 
-def serving(args, torch):
+def serving(args, torch, graphs=False, solo=None):
     """Batched serving: streams arrive as a Poisson process.  Three in four are
     render streams: a box scene of the tiny-workload generator with its own
     seed, a resolution drawn from SERVE_RES, a gate width from U[0.01, 0.2]
@@ -482,10 +490,12 @@ def serving(args, torch):
         wls.append(wl)
         fps_.append(tof_footprint(wl.scene, wl.sensor))
     # solo frame time of every class: one stream alone, frames 1..F-1 timed;
-    # the mix draws render classes uniformly, NLOS classes uniformly
-    solo = {}
-    classes = [(f"{W}x{nb}", render_stream(W, nb, 0.1, 1)) for W in SERVE_RES for nb in SERVE_BINS]
-    classes += [(f"nlos{sc}x{nb}", nlos_stream(sc, nb, 1)) for sc in SERVE_NLOS_SCAN for nb in SERVE_NLOS_BINS]
+    # the mix draws render classes uniformly, NLOS classes uniformly (taken
+    # from an earlier run when given, so that both runs share the arrivals)
+    classes = [] if solo is not None else (
+        [(f"{W}x{nb}", render_stream(W, nb, 0.1, 1)) for W in SERVE_RES for nb in SERVE_BINS] +
+        [(f"nlos{sc}x{nb}", nlos_stream(sc, nb, 1)) for sc in SERVE_NLOS_SCAN for nb in SERVE_NLOS_BINS])
+    solo = dict(solo) if solo is not None else {}
     for name, wl in classes:
         r = Renderer(wl.scene, wl.sensor)
         r.render(wl.frames[0])
@@ -504,6 +514,7 @@ def serving(args, torch):
     arrive -= arrive[0]
     budget = int(args.serve_budget_gib * (1 << 30))
     srv = Server(hbm_budget_bytes=budget)
+    srv.set_graphs(graphs)
     due = sorted((arrive[i] + j * period, i, j) for i in range(n) for j in range(F))
     sid, outs, left = {}, {}, [F] * n
     pending = {}
@@ -556,7 +567,8 @@ def serving(args, torch):
     srv.close()
     lat = np.array(lat) * 1e3
     pp = sum(w.sensor.width * w.sensor.height * w.sensor.b_tot for w in wls) * F
-    return {"streams": n, "frames_per_stream": F, "arrival_rate_per_s": round(rate, 4),
+    return {"_solo_s": solo, "streams": n, "graphs": graphs, "frames_per_stream": F,
+            "arrival_rate_per_s": round(rate, 4),
             "offered_load": round(rate * F * mean_solo, 3),
             "solo_frame_ms": {k: round(v * 1e3, 3) for k, v in solo.items()},
             "host_open_s": round(t_open, 3), "host_close_s": round(t_close, 3),

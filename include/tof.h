@@ -448,6 +448,16 @@ tof_status tof_server_close(tof_server* server, int stream_id);
  * freed, the number of admitted streams, streams waiting. */
 tof_status tof_server_info(tof_server* server, size_t* used_bytes, int* admitted, int* waiting);
 
+/* Graph mode (enabled = 1; 0, the default, turns it off) for the frames
+ * dispatched after the call: each frame's work is recorded by stream capture
+ * into a HIP graph and launched as one graph on the stream's HIP stream; a
+ * stream keeps its executable graph and updates it from the next frame when
+ * the frame has the same shape (kernels, copies, their order), else builds it
+ * anew.  Results are the same as without graphs.  For callers that want
+ * fewer launches per frame (a launch-bound mix of small frames); not in the
+ * paper.  TOF_ERR_INVALID_ARG for other values. */
+tof_status tof_server_set_graphs(tof_server* server, int enabled);
+
 #ifdef __cplusplus
 }
 #endif

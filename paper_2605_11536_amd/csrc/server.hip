@@ -88,6 +88,7 @@ struct Stream {
     Region region;
     tof_ctx* ctx = nullptr;
     hipStream_t hs = nullptr;
+    hipGraphExec_t exec = nullptr;   // the last frame's graph (graph mode), updated frame to frame
     bool admitted = false, failed = false;
     std::deque<uint64_t> held;   // frames submitted before admission
 };
@@ -99,6 +100,7 @@ struct Closed {
     hipStream_t hs = nullptr;
     size_t footprint = 0;
     Region region;
+    hipGraphExec_t exec = nullptr;
 };
 
 struct tof_server {
@@ -111,6 +113,7 @@ struct tof_server {
     std::vector<hipStream_t> idle_streams;
     std::vector<Closed> closed;   // closed streams whose region is not returned yet
     std::mutex mu;
+    bool graphs = false;          // frames recorded into a graph per stream and launched as one
     int next_stream = 0;
     uint64_t next_ticket = 1;
     std::map<int, Stream> streams;
@@ -124,17 +127,53 @@ constexpr size_t kPinnedArena = (size_t)64 << 20;
 
 tof_status hip_status(hipError_t e) { return e == hipSuccess ? TOF_OK : TOF_ERR_DEVICE; }
 
+// Graph mode: the frame's work is recorded by stream capture into a graph
+// and launched as one; the stream's executable graph is updated from it when
+// the frame has the same shape as the last (kernels, copies and their order),
+// else built anew.  A recording that fails is ended before returning.
+tof_status render_graph(Stream& st, Request& r) {
+    const tof_status ep = tofh::prepare_frame_capture(st.ctx);
+    if (ep != TOF_OK) return ep;
+    if (hipStreamBeginCapture(st.hs, hipStreamCaptureModeRelaxed) != hipSuccess) return TOF_ERR_DEVICE;
+    tof_status e = tof_render_frame(st.ctx, &r.frame, r.out[0], r.out[1], r.out[2], r.out[3], (void*)st.hs);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(st.hs, &g) != hipSuccess && e == TOF_OK) e = TOF_ERR_DEVICE;
+    if (e == TOF_OK) {
+        bool updated = false;
+        if (st.exec) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+            updated = hipGraphExecUpdate(st.exec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+            if (!updated) {
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(st.exec);
+                st.exec = nullptr;
+            }
+        }
+        if (!updated && hipGraphInstantiate(&st.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            st.exec = nullptr;
+            e = TOF_ERR_DEVICE;
+        }
+        if (e == TOF_OK && hipGraphLaunch(st.exec, st.hs) != hipSuccess) e = TOF_ERR_DEVICE;
+        if (e == TOF_OK) e = tofh::record_frame_events(st.ctx, st.hs);
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+}
+
 tof_status dispatch(tof_server* s, Stream& st, Request& r) {
-    (void)s;
     tof_status e = hip_status(hipEventRecord(r.start, st.hs));
-    if (e == TOF_OK) e = tof_render_frame(st.ctx, &r.frame, r.out[0], r.out[1], r.out[2], r.out[3], (void*)st.hs);
+    if (e == TOF_OK)
+        e = s->graphs ? render_graph(st, r)
+                      : tof_render_frame(st.ctx, &r.frame, r.out[0], r.out[1], r.out[2], r.out[3], (void*)st.hs);
     if (e == TOF_OK) e = hip_status(hipEventRecord(r.done, st.hs));
     r.status = e;
     r.dispatched = true;
     return e;
 }
 
-void release(tof_server* s, tof_ctx* ctx, hipStream_t hs, const Region& r) {
+void release(tof_server* s, tof_ctx* ctx, hipStream_t hs, const Region& r, hipGraphExec_t exec) {
+    if (exec) (void)hipGraphExecDestroy(exec);
     if (ctx) tof_destroy(ctx);   // region context: waits for its own frames only
     if (hs) s->idle_streams.push_back(hs);
     s->dev_arena.free(r.dev_off, r.dev_bytes);
@@ -149,7 +188,7 @@ void reap(tof_server* s) {
             ++i;
             continue;
         }
-        release(s, z.ctx, z.hs, z.region);
+        release(s, z.ctx, z.hs, z.region, z.exec);
         s->used -= z.footprint;
         s->closed[i] = s->closed.back();
         s->closed.pop_back();
@@ -185,7 +224,7 @@ tof_status admit(tof_server* s, Stream& st, bool* no_room) {
         }
     }
     if (e != TOF_OK) {
-        release(s, st.ctx, st.hs, r);
+        release(s, st.ctx, st.hs, r, nullptr);
         st.ctx = nullptr;
         st.hs = nullptr;
         return e;
@@ -262,8 +301,8 @@ void tof_server_destroy(tof_server* s) {
         if (kv.second->start) (void)hipEventDestroy(kv.second->start);
     }
     for (auto& kv : s->streams)
-        if (kv.second.admitted) release(s, kv.second.ctx, kv.second.hs, kv.second.region);
-    for (Closed& z : s->closed) release(s, z.ctx, z.hs, z.region);
+        if (kv.second.admitted) release(s, kv.second.ctx, kv.second.hs, kv.second.region, kv.second.exec);
+    for (Closed& z : s->closed) release(s, z.ctx, z.hs, z.region, z.exec);
     for (hipStream_t h : s->idle_streams) (void)hipStreamDestroy(h);
     (void)hipFree(s->dev_base);
     (void)hipHostFree(s->host_base);
@@ -406,7 +445,7 @@ tof_status tof_server_close(tof_server* s, int stream_id) {
     if (hipSetDevice(s->device) != hipSuccess) return TOF_ERR_DEVICE;
     if (st.admitted) {
         // its region returns once its queued frames are done (see reap)
-        s->closed.push_back(Closed{st.ctx, st.hs, st.footprint, st.region});
+        s->closed.push_back(Closed{st.ctx, st.hs, st.footprint, st.region, st.exec});
     } else {
         for (auto w = s->waiting.begin(); w != s->waiting.end(); ++w)
             if (*w == stream_id) {
@@ -420,6 +459,13 @@ tof_status tof_server_close(tof_server* s, int stream_id) {
     }
     s->streams.erase(it);
     admit_waiting(s);
+    return TOF_OK;
+}
+
+tof_status tof_server_set_graphs(tof_server* s, int enabled) {
+    if (!s || (enabled != 0 && enabled != 1)) return TOF_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(s->mu);
+    s->graphs = enabled != 0;
     return TOF_OK;
 }
 

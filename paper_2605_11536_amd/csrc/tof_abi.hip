@@ -140,6 +140,8 @@ struct tof_ctx {
     char* hbase = nullptr;
     size_t hsize = 0;
     hipEvent_t done = nullptr;   // recorded after each frame on its stream
+    int xf_pending = -1;         // a captured frame's upload-ring event, for record_frame_events
+    bool done_pending = false;   // a captured frame's end event, likewise
     bool has_work = false;
     // kernel timing: event pairs recorded in order, reduced on query
     bool timing = false;
@@ -461,6 +463,24 @@ tof_status create_in_region(tof_ctx** out, int device, void* dev, size_t dev_byt
                             uint64_t seed) {
     if (!dev || !dev_bytes || !host || !host_bytes) return TOF_ERR_INVALID_ARG;
     return make_ctx(out, device, dev_bytes, seed, dev, dev_bytes, host, host_bytes);
+}
+
+tof_status prepare_frame_capture(tof_ctx* c) {
+    HIP_TRY(hipSetDevice(c->device));
+    if (c->xf_ev[c->xf_ring]) HIP_TRY(hipEventSynchronize(c->xf_ev[c->xf_ring]));
+    return TOF_OK;
+}
+
+tof_status record_frame_events(tof_ctx* c, hipStream_t st) {
+    if (c->xf_pending >= 0) {
+        HIP_TRY(hipEventRecord(c->xf_ev[c->xf_pending], st));
+        c->xf_pending = -1;
+    }
+    if (c->done_pending) {
+        HIP_TRY(hipEventRecord(c->done, st));
+        c->done_pending = false;
+    }
+    return TOF_OK;
 }
 
 size_t scene_pinned_bytes(const tof_scene_desc& d) {
@@ -1161,6 +1181,12 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         return TOF_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)stream;
+    // a caller recording the frame into a graph (stream capture): the events
+    // the host waits on (the pinned upload ring, the frame's end) are left to
+    // it, to record on the stream after it has launched the graph
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cap));
+    const bool capturing = cap == hipStreamCaptureStatusActive;
     const size_t O = (size_t)c->n_obj;
     // rotate: the previous call's frame becomes slot 1
     if (c->slot[0].valid) std::swap(c->slot[0], c->slot[1]);
@@ -1183,7 +1209,9 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         g.xf_host.assign(fr->object_xforms, fr->object_xforms + 12 * O);
         int ring = c->xf_ring;
         c->xf_ring ^= 1;
-        HIP_TRY(hipEventSynchronize(c->xf_ev[ring]));
+        // the pinned slot's last upload is done (under capture the caller has
+        // waited for it before the capture began: prepare_frame_capture)
+        if (!capturing) HIP_TRY(hipEventSynchronize(c->xf_ev[ring]));
         char* pin = (char*)c->xf_pinned[ring];
         std::memcpy(pin, fr->object_xforms, sizeof(float) * 12 * O);
         HIP_TRY(hipMemcpyAsync(g.xf, pin, sizeof(float) * 12 * O, hipMemcpyHostToDevice, st));
@@ -1247,7 +1275,10 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
             HIP_TRY(hipMemcpyAsync(g.vel, pv, sizeof(float) * 6 * O, hipMemcpyHostToDevice, st));
             g.vel_host = vel_now;
         }
-        HIP_TRY(hipEventRecord(c->xf_ev[ring], st));
+        if (capturing)
+            c->xf_pending = ring;   // recorded by the caller once the graph is launched
+        else
+            HIP_TRY(hipEventRecord(c->xf_ev[ring], st));
         HIP_TRY(timer_mark(c, TOF_K_BVH, st));
         tofh::launch_world_verts(c->d_lv, c->d_vobj, g.xf, g.wv, g.wr, c->n_vert, st);
         tofh::launch_leaf_gather(c->d_leaf_tri, c->d_tv, g.wv, c->n_tri, g.leaves, st);
@@ -1404,7 +1435,10 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         timer_reduce(c);
     }
     if (hipGetLastError() != hipSuccess) return TOF_ERR_DEVICE;
-    HIP_TRY(hipEventRecord(c->done, st));
+    if (capturing)
+        c->done_pending = true;
+    else
+        HIP_TRY(hipEventRecord(c->done, st));
     c->has_work = true;
     c->fin_prev = fin_new;
     c->prev_valid = true;

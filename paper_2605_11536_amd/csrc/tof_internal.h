@@ -21,6 +21,14 @@ namespace tofh {
 // device.  dev_bytes from tof_footprint, host_bytes from scene_pinned_bytes.
 tof_status create_in_region(tof_ctx** out, int device, void* dev, size_t dev_bytes, void* host, size_t host_bytes,
                             uint64_t seed);
+// before recording a frame of tof_render_frame under stream capture: wait for
+// the pinned upload slot the frame may reuse (an event recorded on the stream
+// being captured cannot be waited for during the capture)
+tof_status prepare_frame_capture(tof_ctx* c);
+// after launching a graph recorded from tof_render_frame under stream capture:
+// record on `st` the events the capture left out (the upload ring's and the
+// frame's end), which the context's host waits use
+tof_status record_frame_events(tof_ctx* c, hipStream_t st);
 size_t scene_pinned_bytes(const tof_scene_desc& d);
 
 struct FrameArgs {

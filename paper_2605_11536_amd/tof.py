@@ -143,6 +143,8 @@ def lib():
         L.tof_server_wait.argtypes = [C.c_void_p, C.c_uint64]
         L.tof_server_close.argtypes = [C.c_void_p, C.c_int]
         L.tof_server_info.argtypes = [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.tof_server_set_graphs.argtypes = [C.c_void_p, C.c_int]
+        L.tof_server_set_graphs.restype = C.c_int
         for f in ("tof_footprint", "tof_server_create", "tof_server_open", "tof_server_submit", "tof_server_query",
                   "tof_server_wait", "tof_server_close", "tof_server_info"):
             getattr(L, f).restype = C.c_int
@@ -514,6 +516,10 @@ class Server:
     def close_stream(self, sid) -> None:
         _check("tof_server_close", lib().tof_server_close(self.h, sid))
         self.sensors.pop(sid, None)
+
+    def set_graphs(self, enabled: bool) -> None:
+        """Record each later frame into a HIP graph and launch it as one."""
+        _check("tof_server_set_graphs", lib().tof_server_set_graphs(self.h, 1 if enabled else 0))
 
     def info(self) -> dict:
         used, adm, wait = C.c_size_t(0), C.c_int(0), C.c_int(0)

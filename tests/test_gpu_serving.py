@@ -45,11 +45,17 @@ def _alone(w):
     return out
 
 
-def test_streams_in_the_mix_match_alone():
+@pytest.mark.parametrize("graphs", [False, True], ids=["launches", "graphs"])
+def test_streams_in_the_mix_match_alone(graphs):
+    """Every frame of every stream in the mix is bit-identical to the stream
+    rendered alone, with the frames launched kernel by kernel and with each
+    frame recorded into a graph (the first frame, the first with temporal
+    reuse and a later one: a new graph, another shape, an updated one)."""
     from paper_2605_11536_amd.tof import Server
     ws = _workloads()
     alone = {k: _alone(w) for k, w in ws.items()}
     srv = Server(hbm_budget_bytes=64 * GIB)
+    srv.set_graphs(graphs)
     sids = {}
     for k, w in ws.items():
         sid, admitted = srv.open(w.scene, w.sensor)
