@@ -1187,6 +1187,10 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(st, &cap));
     const bool capturing = cap == hipStreamCaptureStatusActive;
+    if (!capturing) {   // an earlier recording that never launched leaves nothing to record
+        c->xf_pending = -1;
+        c->done_pending = false;
+    }
     const size_t O = (size_t)c->n_obj;
     // rotate: the previous call's frame becomes slot 1
     if (c->slot[0].valid) std::swap(c->slot[0], c->slot[1]);
