@@ -226,9 +226,13 @@ tof_status tof_sensor_set(tof_ctx* ctx, const tof_sensor_desc* sensor);
  * pass may need more than one chunk of work items (large sensors: planes x
  * pixels beyond one chunk's capacity), the call reads back the pass's item
  * count after counting them on `stream` (a wait for the device that far) and
- * launches only the chunks that hold items; contexts of the server and
- * tof_render_frame_noalloc never wait, and launch every chunk the plan
- * allows.  The bin-axis
+ * launches only the chunks that hold items; contexts of the server,
+ * tof_render_frame_noalloc and a frame issued under stream capture never
+ * wait, and launch every chunk the plan allows.  Under stream capture the
+ * call also leaves out the events the context's host waits use (the pinned
+ * upload ring, the frame's end): recording a frame into a graph is done by
+ * the server's graph mode, which records them after launching the graph.
+ * The bin-axis
  * pass and the shrink mapping count into the spatial and initial kernel
  * groups of tof_kernel_times.
  * Errors: TOF_ERR_NOT_READY without scene+sensor; TOF_ERR_INVALID_ARG for a

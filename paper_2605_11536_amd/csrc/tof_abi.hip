@@ -140,6 +140,7 @@ struct tof_ctx {
     char* hbase = nullptr;
     size_t hsize = 0;
     hipEvent_t done = nullptr;   // recorded after each frame on its stream
+    bool capturing = false;      // the frame being issued is recorded by stream capture
     int xf_pending = -1;         // a captured frame's upload-ring event, for record_frame_events
     bool done_pending = false;   // a captured frame's end event, likewise
     bool has_work = false;
@@ -1121,9 +1122,10 @@ tof_status run_pass(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, c
         return timer_mark(c, kv, st);
     };
     // the chunks that hold items: all the plan allows, or (when more than one
-    // is possible) those below the count k_items wrote, read back here
+    // is possible, and the frame is not being recorded into a graph) those
+    // below the count k_items wrote, read back here
     size_t n_items = c->max_items;
-    if (c->sync_counts && n_items > ci) {
+    if (c->sync_counts && !c->capturing && n_items > ci) {
         HIP_TRY(hipMemcpyAsync(c->count_host, c->count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         n_items = std::min<size_t>(n_items, c->count_host[0]);
@@ -1187,6 +1189,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(st, &cap));
     const bool capturing = cap == hipStreamCaptureStatusActive;
+    c->capturing = capturing;
     if (!capturing) {   // an earlier recording that never launched leaves nothing to record
         c->xf_pending = -1;
         c->done_pending = false;
