@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--c5-width", type=int, default=1920)
     ap.add_argument("--c5-height", type=int, default=1080)
     ap.add_argument("--no-autotune", action="store_true", help="skip the tuned-launch-shape leg")
+    ap.add_argument("--no-bvh", action="store_true", help="skip the tree-builder comparison leg")
+    ap.add_argument("--bvh-only", action="store_true", help="run the tree-builder comparison leg alone")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="run the serving leg alone")
     ap.add_argument("--serve-streams", type=int, default=64)
@@ -201,6 +203,9 @@ def main():
         return
     if args.c5_only:
         print(json.dumps({"specular_stress": specular_stress_leg(args, torch)}), flush=True)
+        return
+    if args.bvh_only:
+        print(json.dumps({"bvh_builders": bvh_builders(args, torch)}), flush=True)
         return
     from paper_2605_11536_amd import scenes
     from paper_2605_11536_amd.tof import Renderer
@@ -427,6 +432,8 @@ def main():
         sg = serving(args, torch, graphs=True, solo=result["serving"].pop("_solo_s"))
         result["serving_graphs"] = {k: sg[k] for k in ("latency_ms", "service_ms", "queueing_ms", "latency_ms_p50_by_kind",
                                                        "latency_ms_p99_by_kind", "frames_per_s", "wall_s")}
+    if not args.no_bvh:
+        result["bvh_builders"] = bvh_builders(args, torch)
     if not args.no_c5:
         result["specular_stress"] = specular_stress_leg(args, torch)
     if args.copy_probe:
@@ -751,6 +758,48 @@ def specular_stress_leg(args, torch, warm=2, timed=3):
             "hbm_gib": round(tof_footprint(wl.scene, wl.sensor) / (1 << 30), 1),
             "scene_build_s": round(t_scene, 2), "context_create_s": round(t_create, 2),
             "bvh_overflow": st1["bvh_overflow"], "bad_records": st1["bad_records"]}
+
+
+def bvh_builders(args, torch, warm=5, timed=5):
+    """The objects' trees built on the host (binned SAH) and on the device
+    (agglomerative clustering over a Morton-sorted order): build time (wall
+    clock around the build, readbacks included), 4-wide nodes, refit levels,
+    and what the trees cost the frame -- ms per frame (timing off) and node
+    visits and triangle tests per visibility ray over frames
+    warm..warm+timed-1 -- on the glossy scene at the benchmark's size and on
+    the near-specular stress scene (0.95M triangles) at 480x270."""
+    from paper_2605_11536_amd import scenes
+    from paper_2605_11536_amd.tof import BVH_DEVICE, BVH_HOST, Renderer
+    torch.cuda.empty_cache()
+    cases = (("glossy_dynamic 512x512", lambda: scenes.glossy_dynamic(width=args.width, height=args.width,
+                                                                      frames=warm + timed)),
+             ("specular_stress 480x270", lambda: scenes.specular_stress(width=480, height=270, frames=warm + timed)))
+    out = {}
+    for name, make in cases:
+        wl = make()
+        res = {"triangles": int(wl.scene.num_triangles)}
+        for b, key in ((BVH_HOST, "host"), (BVH_DEVICE, "device")):
+            r = Renderer(wl.scene, wl.sensor, bvh_builder=b)
+            info = r.bvh_info()
+            for i in range(warm):
+                r.render(wl.frames[i])
+            torch.cuda.synchronize()
+            s0 = r.stats()
+            t0 = time.perf_counter()
+            for i in range(warm, warm + timed):
+                r.render(wl.frames[i])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            s1 = r.stats()
+            r.close()
+            rays = max(s1["rays"] - s0["rays"], 1)
+            res[key] = {"build_ms": round(info["build_ms"], 2), "nodes": info["num_nodes"],
+                        "levels": info["num_levels"], "rounds": info["rounds"],
+                        "ms_per_frame": round(1e3 * el / timed, 3),
+                        "nodes_per_ray": round((s1["node_visits"] - s0["node_visits"]) / rays, 3),
+                        "tri_tests_per_ray": round((s1["tri_tests"] - s0["tri_tests"]) / rays, 3)}
+        out[name] = res
+    return out
 
 
 def bins_sweep(wl, frame_at, args, torch, Renderer, bins=(4, 16, 64, 256), warm=5, timed=5):

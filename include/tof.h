@@ -196,6 +196,36 @@ void tof_destroy(tof_ctx* ctx);
  * 2^28 triangles or more).  Drops reservoir history. */
 tof_status tof_scene_upload(tof_ctx* ctx, const tof_scene_desc* scene);
 
+/* Which builder makes the mesh objects' trees at the next tof_scene_upload
+ * (the traversal the paper's GPU ray tracing needs, Sec. 6; any tree gives
+ * the same hits: closest hit is the least (distance, triangle id) and the
+ * boxes are conservative, so images do not depend on the builder).
+ * TOF_BVH_HOST: binned SAH on the host, collapsed to 4-wide nodes (the
+ * default).  TOF_BVH_DEVICE: built on the GPU from a Morton-ordered radix
+ * sort by agglomerative clustering (PLOC), with SAH leaf sizes and the same
+ * collapse; it needs about 260 bytes of device work space per triangle
+ * during the upload (counted by tof_footprint).  Both cap leaves at 4
+ * triangles.  TOF_ERR_INVALID_ARG for another value. */
+enum { TOF_BVH_HOST = 0, TOF_BVH_DEVICE = 1 };
+tof_status tof_set_bvh_builder(tof_ctx* ctx, int32_t builder);
+
+/* The mesh objects' trees of the last tof_scene_upload: the builder, the
+ * 4-wide node count, the refit levels, the clustering rounds (device
+ * builder), the build's wall time in ms (host-side, readbacks included),
+ * and, when leaf_triangles is not NULL, the triangle of every leaf slot
+ * ([num_triangles] host array, filled after a device synchronization).
+ * TOF_ERR_NOT_READY before a scene upload. */
+typedef struct {
+    int32_t builder;
+    int32_t num_nodes;
+    int32_t num_levels;
+    int32_t rounds;
+    int32_t num_triangles;
+    int32_t pad;
+    double build_ms;
+} tof_bvh_info;
+tof_status tof_get_bvh_info(tof_ctx* ctx, tof_bvh_info* info, int32_t* leaf_triangles);
+
 /* Set sensor and time-domain settings and (re)allocate per-pixel state after
  * checking the footprint against the budget.  Any change drops the temporal
  * history (reservoirs are reset), except a move of gate_center alone: that

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtof.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["bvh.hip", "bvh_host.hip", "render.hip", "server.hip", "tof_abi.hip"]
+SOURCES = ["bvh.hip", "bvh_build.hip", "bvh_host.hip", "render.hip", "server.hip", "tof_abi.hip"]
 ARCH = os.environ.get("TOF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -2,6 +2,7 @@
 // frame driver and statistics.  See include/tof.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -64,6 +65,9 @@ struct tof_ctx {
     size_t budget = 0;
     uint64_t seed = 0;
     Alloc scene_mem, sensor_mem;
+    Alloc build_mem;                     // the device tree builder's work space during an upload
+    int bvh_builder = TOF_BVH_HOST;
+    tof_bvh_info bvh_info = {};
     // scene
     bool has_scene = false;
     int n_obj = 0, n_mat = 0, n_vert = 0, n_tri = 0, n_sph = 0;
@@ -167,7 +171,8 @@ tof_status dev_alloc(tof_ctx* c, Alloc& a, void** out, size_t bytes) {
     *out = nullptr;
     if (bytes == 0) bytes = 16;
     bytes = (bytes + 255) & ~(size_t)255;
-    if (c->budget && c->scene_mem.bytes + c->sensor_mem.bytes + bytes > c->budget) return TOF_ERR_OUT_OF_MEMORY;
+    if (c->budget && c->scene_mem.bytes + c->sensor_mem.bytes + c->build_mem.bytes + bytes > c->budget)
+        return TOF_ERR_OUT_OF_MEMORY;
     if (c->rbase) {
         if (c->rused + bytes > c->rsize) return TOF_ERR_OUT_OF_MEMORY;
         if (a.off0 == SIZE_MAX) a.off0 = c->rused;
@@ -275,7 +280,7 @@ size_t scene_footprint(const tof_scene_desc& d) {
     const size_t V = (size_t)std::max(d.num_vertices, 1), O = (size_t)d.num_objects, N = mesh + T + 1;
     return O * (sizeof(Obj) + 4) + (size_t)d.num_materials * sizeof(Mat) + T * (sizeof(TriInfo) + 16 + 4) +
            V * (16 + 4) + 2 * (72 * O + 32 * V + (sizeof(Node4) + sizeof(NodeQ) + 4) * N + 48 * std::max<size_t>(T, 1)) +
-           64 * 1024;
+           tofh::blas_build_bytes(T, mesh) + 64 * 1024;
 }
 
 tof_status alloc_set(tof_ctx* c, ResSet& r, size_t P, size_t B, size_t words) {
@@ -632,8 +637,37 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
     int n_mesh = 0;
     for (int o = 0; o < d->num_objects; ++o) n_mesh += objs[o].type == TOF_OBJ_GRID ? 1 : 0;
     c->n_tlas_cap = std::max(n_mesh, 1);
+    TOF_TRY(alloc_t(c, a, &c->d_leaf_tri, (size_t)std::max(T, 1)));
+    c->bvh_info = tof_bvh_info{};
+    c->bvh_info.builder = c->bvh_builder;
+    c->bvh_info.num_triangles = T;
+    const auto tb0 = std::chrono::steady_clock::now();
     int slot = 0;
-    for (int o = 0; o < d->num_objects; ++o) {
+    if (c->bvh_builder == TOF_BVH_DEVICE && T > 0) {
+        // mesh object m: leaf slots [m_slot[m], m_slot[m + 1]), triangles from m_tri[m]
+        std::vector<int> m_slot{0}, m_tri;
+        for (int o = 0; o < d->num_objects; ++o) {
+            const Obj& ob = objs[o];
+            if (ob.type != TOF_OBJ_GRID) continue;
+            m_tri.push_back(ob.tri_base);
+            m_slot.push_back(m_slot.back() + 2 * ob.nu * ob.nv);
+            c->mesh_objs.push_back(o);
+        }
+        const size_t wb = tofh::blas_build_bytes(T, m_tri.size());
+        void* ws = nullptr;
+        TOF_TRY(dev_alloc(c, c->build_mem, &ws, wb));
+        tofh::BlasResult br;
+        const tof_status bs =
+            tofh::build_blas_device(ws, wb, c->d_tv, c->d_lv, m_slot, m_tri, c->n_tlas_cap, c->d_leaf_tri, br);
+        free_all(c, c->build_mem);
+        TOF_TRY(bs);
+        blas = std::move(br.nodes);
+        heights = std::move(br.heights);
+        c->blas_root = br.roots;
+        c->obj_lbox = br.lbox;
+        c->bvh_info.rounds = br.rounds;
+    }
+    for (int o = 0; o < d->num_objects && !(c->bvh_builder == TOF_BVH_DEVICE && T > 0); ++o) {
         const Obj& ob = objs[o];
         if (ob.type != TOF_OBJ_GRID) continue;
         const int nt = 2 * ob.nu * ob.nv;
@@ -674,8 +708,11 @@ tof_status tof_scene_upload(tof_ctx* c, const tof_scene_desc* d) {
             if (heights[i] == h) border.push_back((uint32_t)(c->n_tlas_cap + i));
         c->level_off.push_back((int)border.size());
     }
-    TOF_TRY(alloc_t(c, a, &c->d_leaf_tri, (size_t)std::max(T, 1)));
-    if (T) HIP_TRY(hipMemcpy(c->d_leaf_tri, leaf_tri.data(), sizeof(int) * T, hipMemcpyHostToDevice));
+    if (T && c->bvh_builder != TOF_BVH_DEVICE)
+        HIP_TRY(hipMemcpy(c->d_leaf_tri, leaf_tri.data(), sizeof(int) * T, hipMemcpyHostToDevice));
+    c->bvh_info.num_nodes = c->n_blas;
+    c->bvh_info.num_levels = hmax + 1;
+    c->bvh_info.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb0).count();
     for (auto& g : c->geom) {
         TOF_TRY(alloc_t(c, a, &g.xf, 12 * (size_t)objs.size()));
         TOF_TRY(alloc_t(c, a, &g.vel, 6 * (size_t)objs.size()));
@@ -882,6 +919,24 @@ tof_status tof_set_launch_config(tof_ctx* c, const tof_launch_config* cfg) {
     c->shift_blocks = sb;
     c->vis_blocks = vb;
     if (c->has_sensor) c->plan = plan_of(c, c->ray_budget);
+    return TOF_OK;
+}
+
+tof_status tof_set_bvh_builder(tof_ctx* c, int32_t builder) {
+    if (!c || (builder != TOF_BVH_HOST && builder != TOF_BVH_DEVICE)) return TOF_ERR_INVALID_ARG;
+    c->bvh_builder = builder;
+    return TOF_OK;
+}
+
+tof_status tof_get_bvh_info(tof_ctx* c, tof_bvh_info* out, int32_t* leaf_triangles) {
+    if (!c || !out) return TOF_ERR_INVALID_ARG;
+    if (!c->has_scene) return TOF_ERR_NOT_READY;
+    *out = c->bvh_info;
+    if (leaf_triangles && c->n_tri > 0) {
+        HIP_TRY(hipSetDevice(c->device));
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(leaf_triangles, c->d_leaf_tri, sizeof(int32_t) * (size_t)c->n_tri, hipMemcpyDeviceToHost));
+    }
     return TOF_OK;
 }
 

@@ -49,6 +49,26 @@ int32_t leaf_ref(int first, int count);
 int32_t build_bvh4(const std::vector<BvhPrim>& prims, int leaf_max, int node_base, int slot_base,
                    std::vector<tofd::Node4>& nodes, std::vector<int>& heights, std::vector<int>& order);
 
+// bvh_build.hip: the objects' 4-wide trees built on the device (Morton
+// order, agglomerative clustering, SAH leaves, the host's collapse rule).
+// Mesh object m owns leaf slots [m_slot[m], m_slot[m + 1]) and triangles
+// m_tri[m] + 0 .. ; nodes are numbered from node_base; leaf_tri[slot] is
+// written on the device.  heights: a refit level per node (children in lower
+// levels than their parents).  The workspace (blas_build_bytes) is device
+// memory the caller owns; the null stream is used and left idle.
+struct BlasResult {
+    std::vector<tofd::Node4> nodes;   // child links and counts (boxes are the refit's)
+    std::vector<int> heights;
+    std::vector<int> roots;           // per mesh object: node or leaf reference, -1 without triangles
+    std::vector<float> lbox;          // per mesh object: object-space box lo xyz, hi xyz
+    int rounds = 0;                   // clustering rounds
+    double build_ms = 0.0;
+};
+size_t blas_build_bytes(size_t T, size_t M);
+tof_status build_blas_device(void* work, size_t work_bytes, const int4* tv, const float4* lv,
+                             const std::vector<int>& m_slot, const std::vector<int>& m_tri, int node_base,
+                             int* leaf_tri, BlasResult& res);
+
 // bvh.hip
 void launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t st);
 // wv = world positions, wr = vertices turned into world orientation about their object's origin

@@ -55,6 +55,14 @@ class tof_launch_config(C.Structure):
     _fields_ = [("shift_blocks", C.c_uint32), ("vis_blocks", C.c_uint32)]
 
 
+class tof_bvh_info(C.Structure):
+    _fields_ = [("builder", C.c_int32), ("num_nodes", C.c_int32), ("num_levels", C.c_int32), ("rounds", C.c_int32),
+                ("num_triangles", C.c_int32), ("pad", C.c_int32), ("build_ms", C.c_double)]
+
+
+BVH_HOST, BVH_DEVICE = 0, 1
+
+
 class tof_frame_desc(C.Structure):
     _fields_ = [("frame_index", C.c_int32), ("cam_pos", C.c_float * 3), ("cam_fwd", C.c_float * 3),
                 ("cam_up", C.c_float * 3), ("fov_y_deg", C.c_float), ("ortho_half", C.c_float * 2),
@@ -121,7 +129,10 @@ def lib():
         L.tof_get_launch_config.argtypes = [C.c_void_p, C.POINTER(tof_launch_config)]
         L.tof_autotune.argtypes = [C.c_void_p, C.POINTER(tof_frame_desc), C.c_int, C.c_void_p,
                                    C.POINTER(tof_launch_config)]
-        for f in ("tof_set_launch_config", "tof_get_launch_config", "tof_autotune"):
+        L.tof_set_bvh_builder.argtypes = [C.c_void_p, C.c_int32]
+        L.tof_get_bvh_info.argtypes = [C.c_void_p, C.POINTER(tof_bvh_info), C.c_void_p]
+        for f in ("tof_set_launch_config", "tof_get_launch_config", "tof_autotune", "tof_set_bvh_builder",
+                  "tof_get_bvh_info"):
             getattr(L, f).restype = C.c_int
         L.tof_set_kernel_timing.argtypes = [C.c_void_p, C.c_int]
         L.tof_set_kernel_timing.restype = C.c_int
@@ -292,6 +303,24 @@ def tof_get_launch_config(h) -> dict:
     return {"shift_blocks": int(cfg.shift_blocks), "vis_blocks": int(cfg.vis_blocks)}
 
 
+def tof_set_bvh_builder(h, builder: int) -> None:
+    _check("tof_set_bvh_builder", lib().tof_set_bvh_builder(h, int(builder)))
+
+
+def tof_get_bvh_info(h, leaf_triangles: bool = False):
+    """The last scene upload's tree summary as a dict, and with
+    leaf_triangles the triangle of every leaf slot (numpy int32)."""
+    info = tof_bvh_info()
+    _check("tof_get_bvh_info", lib().tof_get_bvh_info(h, C.byref(info), None))
+    out = {"builder": int(info.builder), "num_nodes": int(info.num_nodes), "num_levels": int(info.num_levels),
+           "rounds": int(info.rounds), "num_triangles": int(info.num_triangles), "build_ms": float(info.build_ms)}
+    if leaf_triangles:
+        arr = np.zeros(max(info.num_triangles, 0), np.int32)
+        _check("tof_get_bvh_info", lib().tof_get_bvh_info(h, C.byref(info), arr.ctypes.data_as(C.c_void_p)))
+        out["leaf_triangles"] = arr
+    return out
+
+
 def tof_autotune(h, frames, stream=None) -> dict:
     """Time the candidate launch shapes over `frames` (a list of Frame) and
     keep the fastest; returns it."""
@@ -359,13 +388,14 @@ def tof_status_string(status: int) -> str:
 class Renderer:
     """One render stream: a context with a scene and a sensor."""
 
-    def __init__(self, scene, sensor, device: int = 0, hbm_budget_bytes: int = 0):
+    def __init__(self, scene, sensor, device: int = 0, hbm_budget_bytes: int = 0, bvh_builder: int = BVH_HOST):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the ToF ReSTIR library runs on HIP devices only")
         self.device = torch.device("cuda", device)
         self.sensor = sensor
         self.h = tof_create(device, hbm_budget_bytes, sensor.seed)
+        tof_set_bvh_builder(self.h, bvh_builder)
         tof_scene_upload(self.h, scene)
         tof_sensor_set(self.h, sensor)
         P = sensor.width * sensor.height
@@ -434,6 +464,16 @@ class Renderer:
 
     def autotune(self, frames, stream=None) -> dict:
         return tof_autotune(self.h, frames, stream)
+
+    def upload_scene(self, scene, bvh_builder: int = None):
+        """Replace the scene (drops the temporal history); bvh_builder
+        BVH_HOST or BVH_DEVICE, else the context's current choice."""
+        if bvh_builder is not None:
+            tof_set_bvh_builder(self.h, bvh_builder)
+        tof_scene_upload(self.h, scene)
+
+    def bvh_info(self, leaf_triangles: bool = False) -> dict:
+        return tof_get_bvh_info(self.h, leaf_triangles)
 
     def close(self):
         if self.h:

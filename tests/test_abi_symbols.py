@@ -72,7 +72,8 @@ def test_binding_struct_sizes_and_offsets_match_c(tmp_path):
     structs = {"tof_scene_desc": tof.tof_scene_desc, "tof_sensor_desc": tof.tof_sensor_desc,
                "tof_frame_desc": tof.tof_frame_desc, "tof_stats": tof.tof_stats,
                "tof_history_desc": tof.tof_history_desc, "tof_kernel_work": tof.tof_kernel_work,
-               "tof_kernel_times": tof.tof_kernel_times}
+               "tof_kernel_times": tof.tof_kernel_times, "tof_bvh_info": tof.tof_bvh_info,
+               "tof_launch_config": tof.tof_launch_config}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tof.h"', "int main(void) {"]
     for cname, pycls in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
