@@ -701,7 +701,15 @@ __global__ void __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(6))) k
 // as decoding the record, patching it and encoding it again).
 // ---------------------------------------------------------------------------
 constexpr int kMergeWaves = 4;                   // waves per block of k_merge
-constexpr int kMergeTasks = 64 * (kMaxK + 1);    // tasks of a wave's 64 items, at most
+constexpr int kMergeTPL = 2;                     // tasks a lane loads at once in the weight phase
+constexpr int kMergeP4 = 2;                      // rounds of 16 records whose loads are issued together
+// LDS of one merge wave, sized for the pass's K: per item its confidences
+// (float4) and its selection (uint4), per task (64 (K + 1) at most) its
+// weight and phat_q (float2), and under pairwise MIS per item the K
+// neighbours' confidences (float)
+__host__ __device__ __forceinline__ size_t merge_wave_lds(int K, bool pairwise) {
+    return 64 * 16 + 64 * 16 + (size_t)64 * (K + 1) * 8 + (pairwise ? (size_t)64 * K * 4 : 0);
+}
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -717,10 +725,7 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
                                                             const float4* __restrict__ fwd,
                                                             const float* __restrict__ term,
                                                             const float4* __restrict__ shv, int round, ResSet out) {
-    __shared__ float2 s_w[kMergeWaves][kMergeTasks];   // per task: weight (-1: not a candidate), phat_q
-    __shared__ float4 s_it[kMergeWaves][64];           // per item: M_q, M_tot, M_q / k_v, pairwise (1) or not (0)
-    __shared__ float s_ml[kMergeWaves][64 * kMaxK];    // per item: neighbour confidences (-1: no pixel)
-    __shared__ uint4 s_sel[kMergeWaves][64];           // per item: source record, output record, task, W bits
+    extern __shared__ __align__(16) unsigned char merge_lds[];
     const Sens& s = a.s;
     const int P = s.P;
     const int K = pass_K(s, mode);
@@ -732,6 +737,11 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
     const int lane = (int)__lane_id();
     const int wv = (int)(threadIdx.x >> 6);
     const bool pw = mode == 1 && s.mis_mode == 1;
+    unsigned char* lds = merge_lds + (size_t)wv * merge_wave_lds(K, pw);
+    float4* s_it = (float4*)lds;                  // per item: M_q, M_tot, M_q / k_v, pairwise (1) or not (0)
+    uint4* s_sel = (uint4*)(lds + 64 * 16);       // per item: source record, output record, task, W bits
+    float2* s_w = (float2*)(lds + 2 * 64 * 16);   // per task: weight (-1: not a candidate), phat_q
+    float* s_ml = (float*)(lds + 2 * 64 * 16 + (size_t)64 * (K + 1) * 8);   // per item: neighbour confidences (-1: no pixel)
     // wave-uniform loop (the shuffles below need every lane)
     for (uint32_t it0 = i0 + blockIdx.x * (64 * kMergeWaves) + 64 * (uint32_t)wv; it0 < n;
          it0 += gridDim.x * (64 * kMergeWaves)) {
@@ -754,7 +764,7 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
                 for (int l = 0; l < K; ++l) {
                     const int dp = links[(size_t)l * P + pix];
                     const float ml = dp >= 0 ? A.M[dp] : -1.f;   // -1: no neighbour pixel
-                    s_ml[wv][lane * kMaxK + l] = ml;
+                    s_ml[lane * K + l] = ml;
                     if (dp >= 0) {
                         mtot += ml;
                         ++kv;
@@ -762,7 +772,7 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
                 }
                 if (kv > 0) mqk = mq / (float)kv;
             }
-            s_it[wv][lane] = make_float4(mq, mtot, mqk, pw && kv > 0 ? 1.f : 0.f);
+            s_it[lane] = make_float4(mq, mtot, mqk, pw && kv > 0 ? 1.f : 0.f);
         }
         // the wave's task range: from its first item's first task to the end
         // of its last item's tasks
@@ -772,38 +782,65 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
         const uint32_t thi = __shfl(t0 + (uint32_t)__popc(cm), last, 64);
         const uint32_t nt = thi - tlo;
         wave_sync();
-        // 2. one lane per task: its weight
-        for (uint32_t j = (uint32_t)lane; j < nt; j += 64) {
-            const uint32_t t = tlo + j;
-            const uint2 tk = tasks[t];
-            const int il = (int)(tk.x - it0), c = (int)tk.y;
-            const float4 fw = fwd[t];
-            const float phq = fw.x;
-            float w = -1.f;
-            if (c == 0 || phq > 0.f) {   // else the shift into q failed
-                const float4 iv = s_it[wv][il];
-                const float mq = iv.x;
-                float m;
-                if (iv.w != 0.f) {   // pairwise
-                    const float mtot = iv.y, mqk = iv.z;
-                    const float* ml = &s_ml[wv][il * kMaxK];
-                    if (c == 0) {
-                        m = 0.f;
-                        const float qk = mqk * phq;
-                        for (int l = 0; l < K; ++l)
-                            if (ml[l] >= 0.f) m += (ml[l] + mqk) / mtot * (qk / (qk + term[(size_t)t * K + l]));
-                    } else {
-                        m = (ml[c - 1] + mqk) / mtot * (fw.z / (fw.z + mqk * phq));
-                    }
-                } else {
-                    float den = fw.z + mq * phq;
-                    for (int l = 0; l < K; ++l) den += term[(size_t)t * K + l];
-                    m = (c == 0 ? mq * phq : fw.z) / den;
+        // 2. one lane per task: its weight.  A lane takes kMergeTPL tasks at
+        // a time and issues all their loads before it uses any of them, so
+        // their memory latencies overlap.
+        for (uint32_t j0 = 0; j0 < nt; j0 += 64 * kMergeTPL) {
+            uint2 tk[kMergeTPL];
+            float4 fw[kMergeTPL];
+            float tm[kMergeTPL][kMaxK];
+#pragma unroll
+            for (int k = 0; k < kMergeTPL; ++k) {
+                const uint32_t j = j0 + 64 * (uint32_t)k + (uint32_t)lane;
+                tk[k] = make_uint2(0u, 0u);
+                fw[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                for (int l = 0; l < kMaxK; ++l) tm[k][l] = 0.f;
+                if (j < nt) {
+                    const uint32_t t = tlo + j;
+                    tk[k] = tasks[t];
+                    fw[k] = fwd[t];
+#pragma unroll
+                    for (int l = 0; l < kMaxK; ++l)
+                        if (l < K) tm[k][l] = term[(size_t)t * K + l];
                 }
-                w = m * phq * fw.w * fw.y;
-                if (c > 0 && !(w > 0.f)) w = -1.f;
             }
-            s_w[wv][j] = make_float2(w, phq);
+#pragma unroll
+            for (int k = 0; k < kMergeTPL; ++k) {
+                const uint32_t j = j0 + 64 * (uint32_t)k + (uint32_t)lane;
+                if (j >= nt) continue;
+                const int il = (int)(tk[k].x - it0), c = (int)tk[k].y;
+                const float4 f4 = fw[k];
+                const float phq = f4.x;
+                float w = -1.f;
+                if (c == 0 || phq > 0.f) {   // else the shift into q failed
+                    const float4 iv = s_it[il];
+                    const float mq = iv.x;
+                    float m;
+                    if (iv.w != 0.f) {   // pairwise
+                        const float mtot = iv.y, mqk = iv.z;
+                        const float* ml = &s_ml[il * K];
+                        if (c == 0) {
+                            m = 0.f;
+                            const float qk = mqk * phq;
+#pragma unroll
+                            for (int l = 0; l < kMaxK; ++l)
+                                if (l < K && ml[l] >= 0.f) m += (ml[l] + mqk) / mtot * (qk / (qk + tm[k][l]));
+                        } else {
+                            m = (ml[c - 1] + mqk) / mtot * (f4.z / (f4.z + mqk * phq));
+                        }
+                    } else {
+                        float den = f4.z + mq * phq;
+#pragma unroll
+                        for (int l = 0; l < kMaxK; ++l)
+                            if (l < K) den += tm[k][l];
+                        m = (c == 0 ? mq * phq : f4.z) / den;
+                    }
+                    w = m * phq * f4.w * f4.y;
+                    if (c > 0 && !(w > 0.f)) w = -1.f;
+                }
+                s_w[j] = make_float2(w, phq);
+            }
         }
         wave_sync();
         // 3. one lane per item: the draw over its candidates in order
@@ -815,27 +852,35 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
             float ws = 0.f, sel_phat = 0.f;
             int sel = -1;
             uint32_t sel_t = 0;
-            // one Philox draw serves four candidates: drawn when its first
-            // candidate with a weight needs it
-            Draw ug;
-            int ug_id = -1;
+            // one Philox draw serves four candidates; a group's draw is made
+            // if any of its candidates has a weight.  The groups are drawn in
+            // turn, each by every lane that needs it at once, so the wave
+            // runs the generator once per group (the values do not depend
+            // on when they are drawn).
+            uint32_t need = 0;   // bit g: group g of four candidates has a weight
             for (int c = 0; c < ncand; ++c) {
                 if (!((cm >> c) & 1u)) continue;
                 const uint32_t t = t0 + (uint32_t)__popc(cm & ((1u << c) - 1u));
-                const float2 wp = s_w[wv][t - tlo];
+                if (s_w[t - tlo].x >= 0.f) need |= 1u << (c / 4);
+            }
+            auto group_draw = [&](int g) {
+                if (mode == 0 || !((need >> g) & 1u)) return Draw{{0ull, 0ull, 0ull, 0ull}};
+                return mode == 1 ? philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2, (uint64_t)(pl * 2 + g))
+                                 : philox(s.seed, fp, a.frame, PASS_BIN, 0, (uint64_t)(pl * 4 + g));
+            };
+            const Draw ug0 = group_draw(0), ug1 = group_draw(1), ug2 = group_draw(2);
+            for (int c = 0; c < ncand; ++c) {
+                if (!((cm >> c) & 1u)) continue;
+                const uint32_t t = t0 + (uint32_t)__popc(cm & ((1u << c) - 1u));
+                const float2 wp = s_w[t - tlo];
                 const float w = wp.x;
                 if (w < 0.f) continue;
                 float u;
                 if (mode == 0) {
                     u = ut.u_sel(c);
                 } else {
-                    if (c / 4 != ug_id) {
-                        ug_id = c / 4;
-                        ug = mode == 1 ? philox(s.seed, fp, a.frame, PASS_SPATIAL + (uint64_t)round, 2,
-                                                (uint64_t)(pl * 2 + ug_id))
-                                       : philox(s.seed, fp, a.frame, PASS_BIN, 0, (uint64_t)(pl * 4 + ug_id));
-                    }
-                    u = ug.u_sel(c % 4);
+                    const int g = c / 4, e4 = c % 4;
+                    u = g == 0 ? ug0.u_sel(e4) : (g == 1 ? ug1.u_sel(e4) : ug2.u_sel(e4));
                 }
                 ws += w;
                 if (u * ws < w) {
@@ -857,44 +902,66 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
                 mkey = (uint32_t)(pl >> 5) * (uint32_t)P + (uint32_t)pix;
                 mbit = 1u << (pl & 31);
             }
-            s_sel[wv][lane] = wsel;
+            s_sel[lane] = wsel;
         } else {
-            s_sel[wv][lane] = make_uint4(0u, 0xFFFFFFFFu, 0u, 0u);
+            s_sel[lane] = make_uint4(0u, 0xFFFFFFFFu, 0u, 0u);
         }
         wave_sync();
-        // 4. four lanes per item: float4 e of the winner's record
+        // 4. four lanes per item: float4 e of the winner's record, in four
+        // rounds of 16 items; the loads of kMergeP4 rounds are issued before
+        // any of their records is assembled (more would cost the registers
+        // of a wave per SIMD); a lane reads only the parts its float4 needs.
         {
             const int e = lane & 3;
             const ResSet& srcset = mode == 0 ? Bp : A;
-            for (int r = 0; r < 4; ++r) {
-                const uint4 ws4 = s_sel[wv][16 * r + (lane >> 2)];
-                if (ws4.y == 0xFFFFFFFFu) continue;
-                const bool canon = (ws4.x & 0x80000000u) != 0u;
-                const size_t si = canon ? (size_t)(ws4.x & 0x7FFFFFFFu) : (size_t)ws4.x;
-                const float Wn = __uint_as_float(ws4.w);
-                const float4* q = (canon ? A : srcset).rec + si * kRecF4;
-                float4 v;
-                if (canon) {
-                    v = q[e];
-                    if (e == 0) v.x = Wn;
-                } else {
-                    const float4 s0 = shv[2 * (size_t)ws4.z], s1 = shv[2 * (size_t)ws4.z + 1];
-                    if (e == 0) {
-                        v = make_float4(Wn, fwd[ws4.z].x, s1.z, s1.w);
-                    } else if (e == 1) {
-                        v = q[1];
-                        // objects 0 and 1 of word 7 from the shift, object 2's low bits kept
-                        const uint32_t w7 = (__float_as_uint(v.w) & 0xFF000000u) |
-                                            ((uint32_t)__float_as_int(s0.x) & 0xFFFu) |
-                                            (((uint32_t)__float_as_int(s0.w) & 0xFFFu) << 12);
-                        v.w = __uint_as_float(w7);
-                    } else if (e == 2) {
-                        v = make_float4(s0.y, s0.z, s1.x, s1.y);
-                    } else {
-                        v = q[3];
+            for (int r0 = 0; r0 < 4; r0 += kMergeP4) {
+                uint4 ws4[kMergeP4];
+                float4 qv[kMergeP4], s0[kMergeP4], s1[kMergeP4];
+                float phq[kMergeP4];
+#pragma unroll
+                for (int r = 0; r < kMergeP4; ++r) {
+                    ws4[r] = s_sel[16 * (r0 + r) + (lane >> 2)];
+                    qv[r] = s0[r] = s1[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    phq[r] = 0.f;
+                    if (ws4[r].y == 0xFFFFFFFFu) continue;
+                    const bool canon = (ws4[r].x & 0x80000000u) != 0u;
+                    const size_t si = canon ? (size_t)(ws4[r].x & 0x7FFFFFFFu) : (size_t)ws4[r].x;
+                    const float4* q = (canon ? A : srcset).rec + si * kRecF4;
+                    const size_t t = ws4[r].z;
+                    if (canon || e == 1 || e == 3) qv[r] = q[e];
+                    if (!canon) {
+                        if (e == 0) {
+                            s1[r] = shv[2 * t + 1];
+                            phq[r] = fwd[t].x;
+                        } else if (e == 1) {
+                            s0[r] = shv[2 * t];
+                        } else if (e == 2) {
+                            s0[r] = shv[2 * t];
+                            s1[r] = shv[2 * t + 1];
+                        }
                     }
                 }
-                out.rec[(size_t)ws4.y * kRecF4 + e] = v;
+#pragma unroll
+                for (int r = 0; r < kMergeP4; ++r) {
+                    if (ws4[r].y == 0xFFFFFFFFu) continue;
+                    const bool canon = (ws4[r].x & 0x80000000u) != 0u;
+                    const float Wn = __uint_as_float(ws4[r].w);
+                    float4 v = qv[r];
+                    if (canon) {
+                        if (e == 0) v.x = Wn;
+                    } else if (e == 0) {
+                        v = make_float4(Wn, phq[r], s1[r].z, s1[r].w);
+                    } else if (e == 1) {
+                        // objects 0 and 1 of word 7 from the shift, object 2's low bits kept
+                        const uint32_t w7 = (__float_as_uint(v.w) & 0xFF000000u) |
+                                            ((uint32_t)__float_as_int(s0[r].x) & 0xFFFu) |
+                                            (((uint32_t)__float_as_int(s0[r].w) & 0xFFFu) << 12);
+                        v.w = __uint_as_float(w7);
+                    } else if (e == 2) {
+                        v = make_float4(s0[r].y, s0[r].z, s1[r].x, s1[r].y);
+                    }
+                    out.rec[(size_t)ws4[r].y * kRecF4 + e] = v;
+                }
             }
         }
         // Items of one pixel are consecutive, so lanes that set bits of the
@@ -1176,7 +1243,8 @@ void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& B
                   size_t ci,
                   const uint32_t* win, const float4* fwd, const float* term, const float4* shv, int round, ResSet out,
                   hipStream_t st) {
-    hipLaunchKernelGGL(k_merge, dim3(grid_for(ci, 64 * kMergeWaves, 32768)), dim3(64 * kMergeWaves), 0, st, a, mode,
+    const size_t lds = kMergeWaves * merge_wave_lds(pass_K(a.s, mode), mode == 1 && a.s.mis_mode == 1);
+    hipLaunchKernelGGL(k_merge, dim3(grid_for(ci, 64 * kMergeWaves, 32768)), dim3(64 * kMergeWaves), lds, st, a, mode,
                        A, Bp, links, items, tasks, task0, count, (uint32_t)i0, (uint32_t)ci, win, fwd, term, shv,
                        round, out);
 }

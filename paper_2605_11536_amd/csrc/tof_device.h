@@ -149,7 +149,7 @@ struct Sens {
 // Reuse passes: 0 temporal, 1 spatial, 2 bin axis (Sec. 4.5).  K = the
 // number of other domains per item; bin-axis domain l of bin b is bin
 // b + bin_offset(l), offsets -1, +1, -2, +2, ...
-__device__ __forceinline__ int pass_K(const Sens& s, int mode) { return mode == 0 ? 1 : (mode == 1 ? s.k : 2 * s.br); }
+__host__ __device__ __forceinline__ int pass_K(const Sens& s, int mode) { return mode == 0 ? 1 : (mode == 1 ? s.k : 2 * s.br); }
 __host__ __device__ __forceinline__ int bin_offset(int l) { return (l / 2 + 1) * ((l & 1) ? 1 : -1); }
 
 struct VRef {
