@@ -1140,26 +1140,31 @@ __global__ void k_copy_plane(FrameArgs a, ResSet in, ResSet out, int pl) {
 // final shading (Sec. 3.2.4 step 4): I = phat(y) W per plane, divided by the
 // gate/bin width; optional deterministic direct term; plain PT alongside.
 // ---------------------------------------------------------------------------
-__global__ void k_splat(FrameArgs a, ResSet shown, const float* __restrict__ pt, const float2* __restrict__ direct,
-                        float* __restrict__ out_image, float* __restrict__ out_hist, float* __restrict__ out_pt_image,
-                        float* __restrict__ out_pt_hist) {
+// One thread per pixel and group of 32 planes (the planes of one mask word),
+// the planes in turn: the pixel's mask word and direct term are read once,
+// and at every plane the lanes of a wave read and write consecutive pixels.
+__global__ void __launch_bounds__(256) k_splat(FrameArgs a, ResSet shown, const float* __restrict__ pt,
+                                               const float2* __restrict__ direct, float* __restrict__ out_image,
+                                               float* __restrict__ out_hist, float* __restrict__ out_pt_image,
+                                               float* __restrict__ out_pt_hist) {
     const Sens& s = a.s;
-    const size_t total = (size_t)s.B * s.P;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-        const int pl = (int)(i / (size_t)s.P);
-        const int pix = (int)(i - (size_t)pl * s.P);
+    const int P = s.P;
+    const int pix = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (pix >= P) return;
+    const int pl0 = 32 * (int)blockIdx.y, pl1 = min(s.B, pl0 + 32);
+    const uint32_t mw = shown.mask[(size_t)blockIdx.y * P + pix];
+    const float2 d = s.include_direct ? direct[pix] : make_float2(0.f, 0.f);
+    for (int pl = pl0; pl < pl1; ++pl) {
+        const size_t i = (size_t)pl * P + pix;
         float v = 0.f;
-        if (mask_bit(shown.mask, s.P, pl, pix)) {
-            float2 wp = *(const float2*)(shown.rec + i * kRecF4);
+        if ((mw >> (pl - pl0)) & 1u) {
+            const float2 wp = *(const float2*)(shown.rec + i * kRecF4);
             v = wp.x * wp.y;
         }
         float vp = pt[i];
-        if (s.include_direct) {
-            float2 d = direct[pix];
-            if (d.x > 0.f && in_plane(s, pl, d.y)) {
-                v += d.x;
-                vp += d.x;
-            }
+        if (s.include_direct && d.x > 0.f && in_plane(s, pl, d.y)) {
+            v += d.x;
+            vp += d.x;
         }
         const float inv = 1.0f / plane_width(s, pl);
         if (pl < s.n_bins) {
@@ -1269,9 +1274,10 @@ void launch_copy_plane(const FrameArgs& a, const ResSet& in, const ResSet& out, 
 }
 void launch_splat(const FrameArgs& a, const ResSet& shown, const float* pt, const float2* direct, float* out_image,
                   float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st) {
-    size_t total = (size_t)a.s.B * a.s.P;
-    hipLaunchKernelGGL(k_splat, dim3(grid_for(total, 256, 65536)), dim3(256), 0, st, a, shown, pt, direct, out_image,
-                       out_hist, out_pt_image, out_pt_hist);
+    const unsigned gx = (unsigned)((a.s.P + 255) / 256), gy = (unsigned)((a.s.B + 31) / 32);
+    if (a.s.P > 0 && a.s.B > 0)
+        hipLaunchKernelGGL(k_splat, dim3(gx, gy), dim3(256), 0, st, a, shown, pt, direct, out_image, out_hist,
+                           out_pt_image, out_pt_hist);
 }
 
 }  // namespace tofh
