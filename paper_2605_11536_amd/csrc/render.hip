@@ -476,18 +476,42 @@ __device__ __forceinline__ void block_scan2(uint32_t a, uint32_t b, uint32_t& ea
     (void)base;
 }
 
+// per pixel, bit w set when mask word w is non-zero (at most 32 words)
+__global__ void __launch_bounds__(256) k_word_sum(const uint32_t* __restrict__ m, int P, int words,
+                                                  uint32_t* __restrict__ sum) {
+    const int pix = blockIdx.x * 256 + threadIdx.x;
+    if (pix >= P) return;
+    uint32_t v = 0;
+    for (int w = 0; w < words; ++w)
+        if (m[(size_t)w * P + pix]) v |= 1u << w;
+    sum[pix] = v;
+}
+
+// sum1, sum2: the word summaries of m1 and m2 (k_word_sum), or nullptr: a
+// pixel reads only the words some candidate holds samples in
 __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint32_t* __restrict__ m1,
                                                const uint32_t* __restrict__ m2, const int* __restrict__ links,
                                                int ncand, uint2* __restrict__ items, uint32_t* __restrict__ task0,
-                                               uint32_t* __restrict__ count, uint32_t* __restrict__ out_mask) {
+                                               uint32_t* __restrict__ count, uint32_t* __restrict__ out_mask,
+                                               const uint32_t* __restrict__ sum1, const uint32_t* __restrict__ sum2) {
     const int P = a.s.P;
     int pix = blockIdx.x * 256 + threadIdx.x;
     bool valid = pix < P && a.F.g[0].gb_obj[pix] >= 0;
     uint32_t ni = 0, nt = 0;
     if (pix < P)
         for (int w = 0; w < a.s.mask_words; ++w) out_mask[(size_t)w * P + pix] = 0u;
+    // the words any candidate of this pixel holds samples in (all without summaries)
+    uint32_t wset = 0xFFFFFFFFu;
+    if (valid && sum1) {
+        wset = sum1[pix];
+        for (int c = 1; c < ncand; ++c) {
+            const int q = mode == 0 ? links[pix] : links[(size_t)(c - 1) * P + pix];
+            if (q >= 0) wset |= (mode == 0 ? sum2 : sum1)[q];
+        }
+    }
     if (valid) {
         for (int w = 0; w < a.s.mask_words; ++w) {
+            if (!((wset >> (w & 31)) & 1u)) continue;
             uint32_t u = 0;
             const uint32_t live = planes_in_word(a.s, w);
             for (int c = 0; c < ncand; ++c) {
@@ -502,6 +526,7 @@ __global__ void __launch_bounds__(256) k_items(FrameArgs a, int mode, const uint
     block_scan2(ni, nt, pi, pt_, nullptr, count);
     if (valid && ni) {
         for (int w = 0; w < a.s.mask_words; ++w) {
+            if (!((wset >> (w & 31)) & 1u)) continue;
             uint32_t wm[kMaxK + 1];
             uint32_t u = 0;
             const uint32_t live = planes_in_word(a.s, w);
@@ -1290,9 +1315,25 @@ void launch_neighbours(const FrameArgs& a, int round, const ResSet& in, int* nb,
                        M_out);
 }
 void launch_items(const FrameArgs& a, int mode, const ResSet& first, const ResSet& second, const int* links,
-                  int ncand, uint2* items, uint32_t* task0, uint32_t* count, uint32_t* out_mask, hipStream_t st) {
-    hipLaunchKernelGGL(k_items, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, mode, first.mask,
-                       second.mask, links, ncand, items, task0, count, out_mask);
+                  int ncand, uint2* items, uint32_t* task0, uint32_t* count, uint32_t* out_mask, uint32_t* wsum,
+                  hipStream_t st) {
+    // summaries for the passes over a pixel's own planes (temporal, spatial)
+    // when the masks have at most 32 words; the bin-axis pass reads every word
+    const int P = a.s.P;
+    const uint32_t* s1 = nullptr;
+    const uint32_t* s2 = nullptr;
+    if (mode != 2 && a.s.mask_words <= 32 && wsum) {
+        hipLaunchKernelGGL(k_word_sum, dim3(grid_for(P, 256, 1u << 30)), dim3(256), 0, st, first.mask, P,
+                           a.s.mask_words, wsum);
+        s1 = wsum;
+        if (mode == 0) {
+            hipLaunchKernelGGL(k_word_sum, dim3(grid_for(P, 256, 1u << 30)), dim3(256), 0, st, second.mask, P,
+                               a.s.mask_words, wsum + P);
+            s2 = wsum + P;
+        }
+    }
+    hipLaunchKernelGGL(k_items, dim3(grid_for(P, 256, 1u << 30)), dim3(256), 0, st, a, mode, first.mask, second.mask,
+                       links, ncand, items, task0, count, out_mask, s1, s2);
 }
 void launch_tasks(const uint2* items, const uint32_t* task0, const uint32_t* count, size_t i0, size_t ci,
                   uint2* tasks, uint32_t* win, hipStream_t st) {

@@ -105,6 +105,7 @@ struct tof_ctx {
     float* pt = nullptr;
     float2* direct = nullptr;
     int* prev_pix = nullptr;
+    uint32_t* wsum = nullptr;  // [2P]: per pixel, the mask words that are non-zero (work-list pass)
     int* nb = nullptr;
     uint2* items = nullptr;    // [max_items]
     uint32_t* task0 = nullptr; // [max_items]: first task of each item
@@ -256,7 +257,7 @@ size_t sensor_footprint(const tof_sensor_desc& d) {
     size_t per_set = P * B * kRecBytes + P * 4 + P * words * 4;
     size_t gbuf = 2 * P * (4 + 4 + 4 + 16 + 16);
     const tofh::ChunkPlan pl = tofh::plan_chunks(P, B, d.spatial_k, d.bin_radius);
-    return 3 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ +
+    return 3 * per_set + gbuf + P * B * 4 /*pt*/ + P * 8 /*direct*/ + P * 4 /*prev*/ + P * 8 /*word summaries*/ +
            P * 4 * (size_t)std::max(d.spatial_k, 1) + P * B * 8 /*items*/ + P * B * 4 /*first task per item*/ +
            pl.task_cap * (8 + 16 + 32) /*tasks, forward terms, shifted fields*/ +
            pl.term_cap * (4 + 4) /*MIS terms, MIS work list*/ + 32 * pl.ray_cap +
@@ -825,6 +826,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
     TOF_TRY(alloc_t(c, a, &c->pt, P * B));
     TOF_TRY(alloc_t(c, a, &c->direct, P));
     TOF_TRY(alloc_t(c, a, &c->prev_pix, P));
+    TOF_TRY(alloc_t(c, a, &c->wsum, 2 * P));
     TOF_TRY(alloc_t(c, a, &c->nb, P * (size_t)std::max(d->spatial_k, 1)));
     const tofh::ChunkPlan& pl = c->alloc_plan = tofh::plan_chunks(P, (size_t)B, d->spatial_k, d->bin_radius);
     TOF_TRY(alloc_t(c, a, &c->items, P * B));
@@ -1434,7 +1436,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         a.counters = c->counters + (size_t)TOF_K_TEMPORAL_PREP * kBank;
         tofh::launch_reproject(a, can, pf, c->prev_pix, tmp.M, st);
         tofh::launch_fill_u32(c->count, 0u, 2, st);
-        tofh::launch_items(a, 0, can, pf, c->prev_pix, 2, c->items, c->task0, c->count, tmp.mask, st);
+        tofh::launch_items(a, 0, can, pf, c->prev_pix, 2, c->items, c->task0, c->count, tmp.mask, c->wsum, st);
         HIP_TRY(timer_mark(c, TOF_K_TEMPORAL_PREP, st));
         TOF_TRY(run_pass(c, a, 0, can, pf, c->prev_pix, 0, tmp, st));
         if (item_slot) HIP_TRY(hipMemcpyAsync(item_slot, c->count, 8, hipMemcpyDeviceToDevice, st));
@@ -1459,7 +1461,8 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         a.counters = c->counters + (size_t)TOF_K_SPATIAL_PREP * kBank;
         HIP_TRY(hipMemcpyAsync(out.M, in.M, sizeof(float) * P, hipMemcpyDeviceToDevice, st));
         tofh::launch_fill_u32(c->count, 0u, 2, st);
-        tofh::launch_items(a, 2, in, in, nullptr, 2 * c->s.br + 1, c->items, c->task0, c->count, out.mask, st);
+        tofh::launch_items(a, 2, in, in, nullptr, 2 * c->s.br + 1, c->items, c->task0, c->count, out.mask, c->wsum,
+                           st);
         if (c->s.gate_en) tofh::launch_copy_plane(a, in, out, c->s.n_bins, st);
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
         TOF_TRY(run_pass(c, a, 2, in, in, nullptr, 0, out, st));
@@ -1473,7 +1476,7 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         a.counters = c->counters + (size_t)TOF_K_SPATIAL_PREP * kBank;
         tofh::launch_neighbours(a, r, in, c->nb, out.M, st);
         tofh::launch_fill_u32(c->count, 0u, 2, st);
-        tofh::launch_items(a, 1, in, in, c->nb, c->s.k + 1, c->items, c->task0, c->count, out.mask, st);
+        tofh::launch_items(a, 1, in, in, c->nb, c->s.k + 1, c->items, c->task0, c->count, out.mask, c->wsum, st);
         HIP_TRY(timer_mark(c, TOF_K_SPATIAL_PREP, st));
         TOF_TRY(run_pass(c, a, 1, in, in, c->nb, r, out, st));
         if (item_slot && r == 0) HIP_TRY(hipMemcpyAsync(item_slot + 2, c->count, 8, hipMemcpyDeviceToDevice, st));
@@ -1516,6 +1519,7 @@ struct FrameWork {
     float* pt;
     float2* direct;
     int* prev_pix;
+    uint32_t* wsum;
     int* nb;
     uint2* items;
     uint32_t* task0;
@@ -1532,14 +1536,16 @@ struct FrameWork {
 };
 
 static FrameWork work_of(const tof_ctx* c) {
-    return FrameWork{c->pt,    c->direct, c->prev_pix, c->nb,   c->items, c->task0,     c->tasks,    c->fwd,
-                     c->wide,  c->shv,    c->term,     c->rays, c->ray_count, c->mis_list, c->mis_count, c->count};
+    return FrameWork{c->pt,   c->direct, c->prev_pix, c->wsum,      c->nb,       c->items,     c->task0,
+                     c->tasks, c->fwd,   c->wide,     c->shv,       c->term,     c->rays,      c->ray_count,
+                     c->mis_list, c->mis_count, c->count};
 }
 
 static void set_work(tof_ctx* c, const FrameWork& w) {
     c->pt = w.pt;
     c->direct = w.direct;
     c->prev_pix = w.prev_pix;
+    c->wsum = w.wsum;
     c->nb = w.nb;
     c->items = w.items;
     c->task0 = w.task0;
@@ -1571,6 +1577,7 @@ static size_t carve_work(const tof_ctx* c, const tofh::ChunkPlan& pl, char* base
     take(w.pt, P * B);
     take(w.direct, P);
     take(w.prev_pix, P);
+    take(w.wsum, 2 * P);
     take(w.nb, P * (size_t)std::max(c->s.k, 1));
     take(w.items, P * B);
     take(w.task0, P * B);

@@ -102,9 +102,12 @@ void launch_neighbours(const FrameArgs& a, int round, const tofd::ResSet& in, in
 // the ncand candidates and the index of each item's first task (one task per
 // non-empty candidate); count[0] = items, count[1] = tasks.  Task indices grow
 // with the item index.
+// wsum: [2P] work space for the per-pixel summaries of non-zero mask words
+// of `first` and `second` (the passes over pixels' own planes read only the
+// words a candidate holds samples in).
 void launch_items(const FrameArgs& a, int mode, const tofd::ResSet& first, const tofd::ResSet& second,
                   const int* links, int ncand, uint2* items, uint32_t* task0, uint32_t* count, uint32_t* out_mask,
-                  hipStream_t st);
+                  uint32_t* wsum, hipStream_t st);
 
 // A reuse pass runs over chunks of ci items; the chunk's tasks, forward and
 // MIS terms and queued rays live in a workspace sized for the chunk
