@@ -81,8 +81,6 @@ __global__ void __launch_bounds__(kTB) k_gbuffer(FrameArgs a, GBufOut out) {
 // and is splatted into the plain path-tracing buffer.  VEL: the planes
 // measure the path velocity (Sec. 4.6) instead of the path length.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kInitChunk = 64;   // pixels per chunk of the persistent initial-sample waves
-constexpr unsigned kInitBlocks = 256 * 4 * TOF_TRACE_WAVES / (kTB / 64);   // their blocks: the resident waves
 template <bool VEL>
 TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, ResSet wide, float* __restrict__ pt,
                                                  float2* __restrict__ direct) {
@@ -91,233 +89,153 @@ TOF_TRACE_KERNEL k_initial(FrameArgs a, ResSet can, ResSet wide, float* __restri
     Tracer tr{a.S, stk + threadIdx.x, kTB, kStackDepth, st};
     const Sens& s = a.s;
     const SceneDev& S = a.S;
-    const SlotDev& G = a.F.g[0];
-    const int P = s.P;
-    // the wide-gate reservoir of the shrink mapping with R < 1 (W = 0: empty)
-    const bool mix = wide.rec != nullptr;
-    // Persistent waves: wave w owns the chunks w, w + W, w + 2W, ... of
-    // kInitChunk pixels.  A lane holds one pixel and takes one bounce of its
-    // current path tree per step; after every step the lanes whose pixel is
-    // done (its last tree ended) take the next pixels of the wave's chunks,
-    // found by a ballot over the idle lanes, so that a wave does not idle
-    // behind its longest paths.  A pixel's trees and bounces run in order on
-    // one lane, so its arithmetic and its random numbers are those of a lane
-    // that walks the pixel alone.
-    constexpr uint32_t kWaves = kTB / 64;
-    const uint32_t W = gridDim.x * kWaves;
-    const int lane = (int)__lane_id();
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    uint64_t c = blockIdx.x * kWaves + threadIdx.x / 64;   // wave-uniform: current chunk
-    uint32_t cursor = (uint32_t)min((uint64_t)P, c * kInitChunk);
-    uint32_t end = (uint32_t)min((uint64_t)P, c * kInitChunk + kInitChunk);
-    bool have = false;
-    int pix = 0, tree = 0, i = 1, kfound = 0;
-    uint64_t fp = 0;
-    Vtx g, vs[kMaxVerts];
-    float pdfs[kMaxVerts];
-    float beta = 1.0f, pdf = 1.0f, plen = 0.f;
-    V3 vcur = mk(0.f, 0.f, 0.f), wi = mk(0.f, 0.f, 0.f);   // velocity of the last vertex, direction back
-    float2 dterm = make_float2(0.f, 0.f);
-    auto start_tree = [&]() {
-        vs[0] = g;
-        beta = 1.0f;
-        pdf = 1.0f;
-        plen = camera_leg<VEL>(s, G, g);
-        vcur = VEL ? vel_at(G, g.obj, g.p) : mk(0.f, 0.f, 0.f);
-        wi = toward_camera(s, G, g);
-        kfound = 0;
-        i = 1;
-    };
-    // finalize: W = (sum of weights) / phat(selected)
-    auto finish_pixel = [&]() {
-        for (int w = 0; w < s.mask_words; ++w) {
-            uint32_t m = can.mask[(size_t)w * P + pix];
-            while (m) {
-                int b = __ffs(m) - 1;
-                m &= m - 1;
-                size_t idx = (size_t)(32 * w + b) * P + pix;
-                rec_W(can, idx) = rec_W(can, idx) / rec_phat(can, idx);
-            }
-        }
-        if (mix && rec_W(wide, pix) > 0.f) rec_W(wide, pix) = rec_W(wide, pix) / rec_phat(wide, pix);
-        direct[pix] = dterm;
-        have = false;
-    };
-    while (true) {
-        // refill: idle lanes take the next pixels of the wave's chunks in lane
-        // order, across the end of a chunk into the next one
-        const uint64_t idle = __ballot(!have);
-        if (idle && cursor < end) {
-            const uint32_t rank = (uint32_t)__popcll(idle & lt), tot = (uint32_t)__popcll(idle);
-            const uint32_t rem = end - cursor;
-            const uint64_t cn = c + W;   // the next chunk
-            const uint32_t nb = (uint32_t)min((uint64_t)P, cn * kInitChunk);
-            const uint32_t ne = (uint32_t)min((uint64_t)P, cn * kInitChunk + kInitChunk);
-            const uint32_t q = rank < rem ? cursor + rank : nb + (rank - rem);
-            const bool take = rank < rem || q < ne;
-            if (tot < rem) {
-                cursor += tot;
-            } else {   // this chunk is taken: go on in the next (empty when past the frame)
-                c = cn;
-                cursor = min(ne, nb + (tot - rem));
-                end = ne;
-            }
-            if (!have && take) {
-                pix = (int)q;
-                for (int w = 0; w < s.mask_words; ++w) can.mask[(size_t)w * P + pix] = 0u;
-                if (mix) rec_W(wide, pix) = 0.f;
-                dterm = make_float2(0.f, 0.f);
-                if (G.gb_obj[pix] < 0) {
-                    can.M[pix] = 0.f;
-                    direct[pix] = dterm;
-                } else {
-                    can.M[pix] = (float)s.m_init;
-                    fp = full_pixel(s, pix);
-                    g = gbuf_vertex(G, pix);
-                    tree = 0;
-                    have = true;
-                    if (s.m_init > 0) start_tree();
-                    else finish_pixel();
-                }
-            }
-        }
-        if (cursor >= end && c * kInitChunk < (uint64_t)P) {   // an exhausted chunk: on to the next one
-            c += W;
-            cursor = (uint32_t)min((uint64_t)P, c * kInitChunk);
-            end = (uint32_t)min((uint64_t)P, c * kInitChunk + kInitChunk);
-        }
-        if (!__any(have)) {
-            if (cursor >= end) break;
-            continue;
-        }
-        if (!have) continue;
-        // one bounce: NEE at vertex i, then the next vertex (the tree ends
-        // at n_max vertices, or when sampling or tracing fails)
-        bool more = true;
-        {
-            const Vtx xi = vs[i - 1];
-            if (i >= 2 && kfound == 0 && recon_ok(S, vs[i - 2], vs[i - 1])) kfound = i;
-            bool want = (i >= 2 && i >= s.n_min) || (i == 1 && s.include_direct && s.n_min <= 1);
-            if (want) {
-                V3 L = light_pos(s, G, pix);
-                V3 dv = L - xi.p;
-                float dl = len(dv);
-                V3 wl = (1.0f / dl) * dv;
-                float fs = bsdf_eval(S, xi.obj, xi.n, wi, wl);
-                float C = beta * fs * fabsf(dot(xi.n, wl)) * light_emit(s, S, G, pix, xi.p) / (dl * dl);
-                if (C > 0.f) {
-                    Seg sg = seg_light(s, S, G, pix, xi);
-                    if (!tr.visible(G, sg)) C = 0.f;
-                }
-                const float li = plen + (VEL ? dot(vcur - light_vel(s, G, pix), wl) : dl);
-                if (C > 0.f && i == 1) {
-                    if (tree == 0) dterm = make_float2(C, li);
-                } else if (C > 0.f) {
-                    Rec rec;
-                    rec.opix = (uint32_t)fp;
-                    rec.ofr = a.frame;
-                    rec.tree = tree;
-                    rec.n = i;
-                    rec.k = kfound;
-                    rec.nsfx = 0;
-                    rec.len = li;
-                    rec.phat = C;
-                    for (int q = 0; q < 4; ++q) rec.v[q] = VRef{-1, 0.f, 0.f};
-                    if (kfound >= 2) {
-                        const int k = kfound;
-                        float pp = 1.0f;
-                        for (int j = 1; j <= k - 2; ++j) pp *= pdfs[j - 1];
-                        rec.pre_pdf = pp;
-                        rec.v[0] = VRef{vs[k - 2].obj, vs[k - 2].xi0, vs[k - 2].xi1};
-                        rec.v[1] = VRef{vs[k - 1].obj, vs[k - 1].xi0, vs[k - 1].xi1};
-                        if (k < i) rec.v[2] = VRef{vs[k].obj, vs[k].xi0, vs[k].xi1};
-                        if (k + 1 < i) {
-                            rec.v[3] = VRef{vs[k + 1].obj, vs[k + 1].xi0, vs[k + 1].xi1};
-                            rec.nsfx = 1;
+    int pix = blockIdx.x * kTB + threadIdx.x;
+    if (pix < s.P) {
+        const SlotDev& G = a.F.g[0];
+        const int P = s.P;
+        for (int w = 0; w < s.mask_words; ++w) can.mask[(size_t)w * P + pix] = 0u;
+        // the wide-gate reservoir of the shrink mapping with R < 1 (W = 0: empty)
+        const bool mix = wide.rec != nullptr;
+        if (mix) rec_W(wide, pix) = 0.f;
+        float2 dterm = make_float2(0.f, 0.f);
+        if (G.gb_obj[pix] < 0) {
+            can.M[pix] = 0.f;
+        } else {
+            can.M[pix] = (float)s.m_init;
+            const uint64_t fp = full_pixel(s, pix);
+            const Vtx g = gbuf_vertex(G, pix);
+            for (int tree = 0; tree < s.m_init; ++tree) {
+                Vtx vs[kMaxVerts];
+                float pdfs[kMaxVerts];
+                vs[0] = g;
+                float beta = 1.0f, pdf = 1.0f, plen = camera_leg<VEL>(s, G, g);
+                V3 vcur = VEL ? vel_at(G, g.obj, g.p) : mk(0.f, 0.f, 0.f);   // velocity of the last vertex
+                V3 wi = toward_camera(s, G, g);
+                int kfound = 0;
+                for (int i = 1; i <= s.n_max; ++i) {
+                    const Vtx xi = vs[i - 1];
+                    if (i >= 2 && kfound == 0 && recon_ok(S, vs[i - 2], vs[i - 1])) kfound = i;
+                    bool want = (i >= 2 && i >= s.n_min) || (i == 1 && s.include_direct && s.n_min <= 1);
+                    if (want) {
+                        V3 L = light_pos(s, G, pix);
+                        V3 dv = L - xi.p;
+                        float dl = len(dv);
+                        V3 wl = (1.0f / dl) * dv;
+                        float fs = bsdf_eval(S, xi.obj, xi.n, wi, wl);
+                        float C = beta * fs * fabsf(dot(xi.n, wl)) * light_emit(s, S, G, pix, xi.p) / (dl * dl);
+                        if (C > 0.f) {
+                            Seg sg = seg_light(s, S, G, pix, xi);
+                            if (!tr.visible(G, sg)) C = 0.f;
                         }
-                    } else {
-                        rec.pre_pdf = pdf;
-                    }
-                    Draw u = philox(s.seed, fp, a.frame, PASS_RIS, (uint64_t)tree, (uint64_t)i);
-                    // plain PT deposits into the planes; the reservoirs take
-                    // the gate's candidates from the wide gate when the
-                    // shrink mapping is on (every tree with R = 1; with
-                    // R < 1 the first R x M_init trees, into a reservoir
-                    // of their own, and the others from the gate), each
-                    // sampling technique normalized by its own tree count
-                    const bool gate_pt = s.gate_en && in_plane(s, s.n_bins, li);
-                    const bool wide_tree = s.gate_en && s.shrink_k > 1.f && tree < s.mw;
-                    const bool gate_res = wide_tree ? in_rough_gate(s, li) : gate_pt;
-                    const float m_gate = !mix ? (float)s.m_init
-                                              : (wide_tree ? (float)s.mw : (float)(s.m_init - s.mw));
-                    int planes[2] = {bin_of(s, li), gate_res ? s.n_bins : -1};
-                    if (planes[0] >= 0) pt[(size_t)planes[0] * P + pix] += C / pdf / (float)s.m_init;
-                    if (gate_pt) pt[(size_t)s.n_bins * P + pix] += C / pdf / (float)s.m_init;
-                    for (int q = 0; q < 2; ++q) {
-                        int pl = planes[q];
-                        if (pl < 0) continue;
-                        const float w = C / ((q == 0 ? (float)s.m_init : m_gate) * pdf);
-                        if (q == 1 && mix && wide_tree) {
-                            const float ws0 = rec_W(wide, pix);
-                            if (ws0 == 0.f) {
-                                store_rec(wide, pix, rec, w);
+                        const float li = plen + (VEL ? dot(vcur - light_vel(s, G, pix), wl) : dl);
+                        if (C > 0.f && i == 1) {
+                            if (tree == 0) dterm = make_float2(C, li);
+                        } else if (C > 0.f) {
+                            Rec rec;
+                            rec.opix = (uint32_t)fp;
+                            rec.ofr = a.frame;
+                            rec.tree = tree;
+                            rec.n = i;
+                            rec.k = kfound;
+                            rec.nsfx = 0;
+                            rec.len = li;
+                            rec.phat = C;
+                            for (int q = 0; q < 4; ++q) rec.v[q] = VRef{-1, 0.f, 0.f};
+                            if (kfound >= 2) {
+                                const int k = kfound;
+                                float pp = 1.0f;
+                                for (int j = 1; j <= k - 2; ++j) pp *= pdfs[j - 1];
+                                rec.pre_pdf = pp;
+                                rec.v[0] = VRef{vs[k - 2].obj, vs[k - 2].xi0, vs[k - 2].xi1};
+                                rec.v[1] = VRef{vs[k - 1].obj, vs[k - 1].xi0, vs[k - 1].xi1};
+                                if (k < i) rec.v[2] = VRef{vs[k].obj, vs[k].xi0, vs[k].xi1};
+                                if (k + 1 < i) {
+                                    rec.v[3] = VRef{vs[k + 1].obj, vs[k + 1].xi0, vs[k + 1].xi1};
+                                    rec.nsfx = 1;
+                                }
                             } else {
-                                const float ws = ws0 + w;
-                                if (u.u(q) * ws < w) store_rec(wide, pix, rec, ws);
-                                else rec_W(wide, pix) = ws;
+                                rec.pre_pdf = pdf;
                             }
-                            continue;
-                        }
-                        size_t idx = (size_t)pl * P + pix;
-                        uint32_t* mw = can.mask + (size_t)(pl >> 5) * P + pix;
-                        uint32_t bit = 1u << (pl & 31);
-                        uint32_t m = *mw;
-                        if (!(m & bit)) {   // first candidate of this plane: always selected
-                            *mw = m | bit;
-                            store_rec(can, idx, rec, w);
-                        } else {
-                            float ws = rec_W(can, idx) + w;
-                            if (u.u(q) * ws < w) store_rec(can, idx, rec, ws);
-                            else rec_W(can, idx) = ws;
+                            Draw u = philox(s.seed, fp, a.frame, PASS_RIS, (uint64_t)tree, (uint64_t)i);
+                            // plain PT deposits into the planes; the reservoirs take
+                            // the gate's candidates from the wide gate when the
+                            // shrink mapping is on (every tree with R = 1; with
+                            // R < 1 the first R x M_init trees, into a reservoir
+                            // of their own, and the others from the gate), each
+                            // sampling technique normalized by its own tree count
+                            const bool gate_pt = s.gate_en && in_plane(s, s.n_bins, li);
+                            const bool wide_tree = s.gate_en && s.shrink_k > 1.f && tree < s.mw;
+                            const bool gate_res = wide_tree ? in_rough_gate(s, li) : gate_pt;
+                            const float m_gate = !mix ? (float)s.m_init
+                                                      : (wide_tree ? (float)s.mw : (float)(s.m_init - s.mw));
+                            int planes[2] = {bin_of(s, li), gate_res ? s.n_bins : -1};
+                            if (planes[0] >= 0) pt[(size_t)planes[0] * P + pix] += C / pdf / (float)s.m_init;
+                            if (gate_pt) pt[(size_t)s.n_bins * P + pix] += C / pdf / (float)s.m_init;
+                            for (int q = 0; q < 2; ++q) {
+                                int pl = planes[q];
+                                if (pl < 0) continue;
+                                const float w = C / ((q == 0 ? (float)s.m_init : m_gate) * pdf);
+                                if (q == 1 && mix && wide_tree) {
+                                    const float ws0 = rec_W(wide, pix);
+                                    if (ws0 == 0.f) {
+                                        store_rec(wide, pix, rec, w);
+                                    } else {
+                                        const float ws = ws0 + w;
+                                        if (u.u(q) * ws < w) store_rec(wide, pix, rec, ws);
+                                        else rec_W(wide, pix) = ws;
+                                    }
+                                    continue;
+                                }
+                                size_t idx = (size_t)pl * P + pix;
+                                uint32_t* mw = can.mask + (size_t)(pl >> 5) * P + pix;
+                                uint32_t bit = 1u << (pl & 31);
+                                uint32_t m = *mw;
+                                if (!(m & bit)) {   // first candidate of this plane: always selected
+                                    *mw = m | bit;
+                                    store_rec(can, idx, rec, w);
+                                } else {
+                                    float ws = rec_W(can, idx) + w;
+                                    if (u.u(q) * ws < w) store_rec(can, idx, rec, ws);
+                                    else rec_W(can, idx) = ws;
+                                }
+                            }
                         }
                     }
-                }
-            }
-            if (i == s.n_max) {
-                more = false;
-            } else {
-                Draw u = philox(s.seed, fp, a.frame, PASS_BSDF, (uint64_t)tree, (uint64_t)i);
-                V3 wo;
-                float pw;
-                Vtx nx;
-                if (!bsdf_sample(S, xi.obj, xi.n, wi, u.u(0), u.u(1), wo, pw)) {
-                    more = false;
-                } else {
+                    if (i == s.n_max) break;
+                    Draw u = philox(s.seed, fp, a.frame, PASS_BSDF, (uint64_t)tree, (uint64_t)i);
+                    V3 wo;
+                    float pw;
+                    if (!bsdf_sample(S, xi.obj, xi.n, wi, u.u(0), u.u(1), wo, pw)) break;
                     float fcos = bsdf_eval(S, xi.obj, xi.n, wi, wo) * fabsf(dot(xi.n, wo));
-                    if (!tr.trace(G, xi, wo, nx)) {
-                        more = false;
+                    Vtx nx;
+                    if (!tr.trace(G, xi, wo, nx)) break;
+                    beta *= fcos;
+                    pdf *= pw;
+                    pdfs[i - 1] = pw;
+                    if (VEL) {
+                        const V3 vn = vel_at(G, nx.obj, nx.p);
+                        plen += seg_u(xi.p, vcur, nx.p, vn);
+                        vcur = vn;
                     } else {
-                        beta *= fcos;
-                        pdf *= pw;
-                        pdfs[i - 1] = pw;
-                        if (VEL) {
-                            const V3 vn = vel_at(G, nx.obj, nx.p);
-                            plen += seg_u(xi.p, vcur, nx.p, vn);
-                            vcur = vn;
-                        } else {
-                            plen += len(nx.p - xi.p);
-                        }
-                        vs[i] = nx;
-                        wi = -wo;
-                        ++i;
+                        plen += len(nx.p - xi.p);
                     }
+                    vs[i] = nx;
+                    wi = -wo;
                 }
             }
+            // finalize: W = (sum of weights) / phat(selected)
+            for (int w = 0; w < s.mask_words; ++w) {
+                uint32_t m = can.mask[(size_t)w * P + pix];
+                while (m) {
+                    int b = __ffs(m) - 1;
+                    m &= m - 1;
+                    size_t idx = (size_t)(32 * w + b) * P + pix;
+                    rec_W(can, idx) = rec_W(can, idx) / rec_phat(can, idx);
+                }
+            }
+            if (mix && rec_W(wide, pix) > 0.f) rec_W(wide, pix) = rec_W(wide, pix) / rec_phat(wide, pix);
         }
-        if (!more) {
-            if (++tree < s.m_init) start_tree();
-            else finish_pixel();
-        }
+        direct[pix] = dterm;
     }
     flush_counters(st, a.counters);
 }
@@ -1297,13 +1215,12 @@ void launch_gbuffer(const FrameArgs& a, GBufOut out, hipStream_t st) {
     hipLaunchKernelGGL(k_gbuffer, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, out);
 }
 void launch_initial(const FrameArgs& a, ResSet can, ResSet wide, float* pt, float2* direct, hipStream_t st) {
-    // at most the waves the device holds at once (256 CUs x 4 SIMDs x
-    // TOF_TRACE_WAVES), each starting at its own chunk of kInitChunk pixels
-    const unsigned grid = grid_for(a.s.P, kInitChunk * (kTB / 64), kInitBlocks);
     if (a.s.domain)
-        hipLaunchKernelGGL(k_initial<true>, dim3(grid), dim3(kTB), 0, st, a, can, wide, pt, direct);
+        hipLaunchKernelGGL(k_initial<true>, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, wide, pt,
+                           direct);
     else
-        hipLaunchKernelGGL(k_initial<false>, dim3(grid), dim3(kTB), 0, st, a, can, wide, pt, direct);
+        hipLaunchKernelGGL(k_initial<false>, dim3(grid_for(a.s.P, kTB, 1u << 30)), dim3(kTB), 0, st, a, can, wide,
+                           pt, direct);
 }
 void launch_reproject(const FrameArgs& a, const ResSet& can, const ResSet& prev, int* prev_pix, float* M_out,
                       hipStream_t st) {
