@@ -295,16 +295,22 @@ tof_status tof_render_frame_noalloc(tof_ctx* ctx, const tof_frame_desc* frame, f
 
 /* Launch shape of the reuse passes: the most blocks (of 128 lanes) that a
  * shift kernel (forward and MIS shifts, the shrink mapping) and the
- * visibility kernel launch per chunk.  shift_blocks: a multiple of 64 up to
- * 8192, vis_blocks: a multiple of 64 up to 65536; 0 = the default (8192,
- * 16384).  A smaller shift grid also makes the chunks smaller (each chunk is
- * a whole number of grid sweeps).  Results do not depend on it, only speed:
- * which lane shifts or traces what changes, not what is computed.  For
- * callers that tune per workload (frame size, planes, scene); not in the
- * paper.  Kept across sensor changes.  Waits for the context's last frame. */
+ * visibility kernel launch per chunk; the occupancy the visibility kernel is
+ * compiled for (waves per SIMD: its register budget); the tile of the
+ * resampling merge (tasks whose loads a lane issues at once).
+ * shift_blocks: a multiple of 64 up to 8192, vis_blocks: a multiple of 64 up
+ * to 65536, vis_waves: 5 or 6, merge_tasks: 1, 2 or 4; 0 = the default
+ * (8192, 16384, 6, 2).  A smaller shift grid also makes the chunks smaller
+ * (each chunk is a whole number of grid sweeps).  Results do not depend on
+ * any of them, only speed: which lane shifts or traces what changes, not
+ * what is computed.  For callers that tune per workload (frame size, planes,
+ * scene); not in the paper.  Kept across sensor changes.  Waits for the
+ * context's last frame.  TOF_ERR_INVALID_ARG for a value out of range. */
 typedef struct {
     uint32_t shift_blocks;
     uint32_t vis_blocks;
+    uint32_t vis_waves;
+    uint32_t merge_tasks;
 } tof_launch_config;
 tof_status tof_set_launch_config(tof_ctx* ctx, const tof_launch_config* config);
 tof_status tof_get_launch_config(tof_ctx* ctx, tof_launch_config* config);
@@ -314,7 +320,9 @@ tof_status tof_get_launch_config(tof_ctx* ctx, tof_launch_config* config);
  * rendered from an empty history, once per candidate, on `stream`, and the
  * later half of each run is timed with HIP events; the candidates are the
  * shift grids 8192, 4096, 2048 at the default visibility grid, then the
- * visibility grids 4096, 8192, 32768 at the best of those.  The fastest is
+ * visibility grids 4096, 8192, 32768 at the best of those, then the
+ * visibility kernel at 5 waves per SIMD, then merge tiles of 1 and 4
+ * tasks, each step at the best so far (a coordinate search).  The fastest is
  * set and returned in *chosen (may be NULL).  The tuning frames leave no other
  * trace: the counters of tof_get_stats are restored, the temporal history is
  * dropped (the next frame renders without temporal reuse), nothing is

@@ -689,8 +689,12 @@ __global__ void __launch_bounds__(kTB) k_vis_lanes(FrameArgs a, int slot, RayQue
     flush_counters(st, a.counters);
 }
 
-__global__ void __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(6))) k_vis(FrameArgs a, int slot, RayQueue q,
-                                                                                  float* __restrict__ kill) {
+// WPE: the waves per SIMD it is compiled for (its register budget; the LDS
+// stacks allow at most 6 waves of 128 lanes' stacks per SIMD)
+template <int WPE>
+__global__ void __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(WPE))) k_vis(FrameArgs a, int slot,
+                                                                                    RayQueue q,
+                                                                                    float* __restrict__ kill) {
     __shared__ uint32_t stk[kVisStackDepth * kTB];
     Counters st = {};
     const SlotDev& G = slot ? a.F.g[1] : a.F.g[0];
@@ -726,7 +730,6 @@ __global__ void __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(6))) k
 // as decoding the record, patching it and encoding it again).
 // ---------------------------------------------------------------------------
 constexpr int kMergeWaves = 4;                   // waves per block of k_merge
-constexpr int kMergeTPL = 2;                     // tasks a lane loads at once in the weight phase
 constexpr int kMergeP4 = 2;                      // rounds of 16 records whose loads are issued together
 // LDS of one merge wave, sized for the pass's K: per item its confidences
 // (float4) and its selection (uint4), per task (64 (K + 1) at most) its
@@ -740,6 +743,8 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+// TPL: tasks a lane loads at once in the weight phase (the tile)
+template <int TPL>
 __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mode, ResSet A, ResSet Bp,
                                                             const int* __restrict__ links,
                                                             const uint2* __restrict__ items,
@@ -807,15 +812,15 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
         const uint32_t thi = __shfl(t0 + (uint32_t)__popc(cm), last, 64);
         const uint32_t nt = thi - tlo;
         wave_sync();
-        // 2. one lane per task: its weight.  A lane takes kMergeTPL tasks at
+        // 2. one lane per task: its weight.  A lane takes TPL tasks at
         // a time and issues all their loads before it uses any of them, so
         // their memory latencies overlap.
-        for (uint32_t j0 = 0; j0 < nt; j0 += 64 * kMergeTPL) {
-            uint2 tk[kMergeTPL];
-            float4 fw[kMergeTPL];
-            float tm[kMergeTPL][kMaxK];
+        for (uint32_t j0 = 0; j0 < nt; j0 += 64 * TPL) {
+            uint2 tk[TPL];
+            float4 fw[TPL];
+            float tm[TPL][kMaxK];
 #pragma unroll
-            for (int k = 0; k < kMergeTPL; ++k) {
+            for (int k = 0; k < TPL; ++k) {
                 const uint32_t j = j0 + 64 * (uint32_t)k + (uint32_t)lane;
                 tk[k] = make_uint2(0u, 0u);
                 fw[k] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -831,7 +836,7 @@ __global__ void __launch_bounds__(64 * kMergeWaves) k_merge(FrameArgs a, int mod
                 }
             }
 #pragma unroll
-            for (int k = 0; k < kMergeTPL; ++k) {
+            for (int k = 0; k < TPL; ++k) {
                 const uint32_t j = j0 + 64 * (uint32_t)k + (uint32_t)lane;
                 if (j >= nt) continue;
                 const int il = (int)(tk[k].x - it0), c = (int)tk[k].y;
@@ -1278,21 +1283,30 @@ void launch_mis(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp,
         hipLaunchKernelGGL(k_mis<false>, dim3(grid), dim3(kTB), 0, st, a, mode, A, Bp, links, items, tasks, lq, fwd, shv,
                            term, q);
 }
-void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, unsigned grid, hipStream_t st) {
-    if (a.S.n_tri >= kVisPersistentMinTris)
-        hipLaunchKernelGGL(k_vis, dim3(grid), dim3(kTB), 0, st, a, slot, q, kill);
-    else
+void launch_vis(const FrameArgs& a, int slot, const RayQueue& q, float* kill, unsigned grid, int waves,
+                hipStream_t st) {
+    if (a.S.n_tri >= kVisPersistentMinTris) {
+        if (waves == 5)
+            hipLaunchKernelGGL(k_vis<5>, dim3(grid), dim3(kTB), 0, st, a, slot, q, kill);
+        else
+            hipLaunchKernelGGL(k_vis<6>, dim3(grid), dim3(kTB), 0, st, a, slot, q, kill);
+    } else
         hipLaunchKernelGGL(k_vis_lanes, dim3(std::min(grid, kShiftGrid)), dim3(kTB), 0, st, a, slot, q, kill);
 }
 void launch_merge(const FrameArgs& a, int mode, const ResSet& A, const ResSet& Bp, const int* links,
                   const uint2* items, const uint2* tasks, const uint32_t* task0, const uint32_t* count, size_t i0,
                   size_t ci,
                   const uint32_t* win, const float4* fwd, const float* term, const float4* shv, int round, ResSet out,
-                  hipStream_t st) {
+                  int tile, hipStream_t st) {
     const size_t lds = kMergeWaves * merge_wave_lds(pass_K(a.s, mode), mode == 1 && a.s.mis_mode == 1);
-    hipLaunchKernelGGL(k_merge, dim3(grid_for(ci, 64 * kMergeWaves, 32768)), dim3(64 * kMergeWaves), lds, st, a, mode,
-                       A, Bp, links, items, tasks, task0, count, (uint32_t)i0, (uint32_t)ci, win, fwd, term, shv,
-                       round, out);
+    const dim3 grid(grid_for(ci, 64 * kMergeWaves, 32768)), block(64 * kMergeWaves);
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, a, mode, A, Bp, links, items, tasks, task0, count,
+                           (uint32_t)i0, (uint32_t)ci, win, fwd, term, shv, round, out);
+    };
+    if (tile == 1) go(k_merge<1>);
+    else if (tile == 4) go(k_merge<4>);
+    else go(k_merge<2>);
 }
 void launch_shrink(const FrameArgs& a, const ResSet& can, size_t p0, size_t np, const RayQueue& q, unsigned grid,
                    hipStream_t st) {

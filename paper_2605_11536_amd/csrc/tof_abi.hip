@@ -126,6 +126,7 @@ struct tof_ctx {
     // launch shape (tof_set_launch_config): most blocks of the shift kernels
     // and of the visibility kernel
     unsigned shift_blocks = tofh::kShiftGrid, vis_blocks = tofh::kVisGrid;
+    int vis_waves = 6, merge_tasks = 2;   // occupancy variant of k_vis, tile of k_merge
     size_t ray_budget = 0;        // a lowered ray budget (test support), 0 = the plan's own
     // a pass that may need more than one chunk reads its item count back and
     // launches only the chunks that hold items (contexts of tof_create; a
@@ -915,11 +916,16 @@ tof_status tof_set_launch_config(tof_ctx* c, const tof_launch_config* cfg) {
     if (!c || !cfg) return TOF_ERR_INVALID_ARG;
     const unsigned sb = cfg->shift_blocks ? cfg->shift_blocks : tofh::kShiftGrid;
     const unsigned vb = cfg->vis_blocks ? cfg->vis_blocks : tofh::kVisGrid;
+    const int vw = cfg->vis_waves ? (int)cfg->vis_waves : 6;
+    const int mt = cfg->merge_tasks ? (int)cfg->merge_tasks : 2;
     if (sb % 64 != 0 || sb > tofh::kShiftGrid || vb % 64 != 0 || vb > kMaxVisBlocks) return TOF_ERR_INVALID_ARG;
+    if ((vw != 5 && vw != 6) || (mt != 1 && mt != 2 && mt != 4)) return TOF_ERR_INVALID_ARG;
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(quiesce(c));
     c->shift_blocks = sb;
     c->vis_blocks = vb;
+    c->vis_waves = vw;
+    c->merge_tasks = mt;
     if (c->has_sensor) c->plan = plan_of(c, c->ray_budget);
     return TOF_OK;
 }
@@ -946,6 +952,8 @@ tof_status tof_get_launch_config(tof_ctx* c, tof_launch_config* out) {
     if (!c || !out) return TOF_ERR_INVALID_ARG;
     out->shift_blocks = c->shift_blocks;
     out->vis_blocks = c->vis_blocks;
+    out->vis_waves = (uint32_t)c->vis_waves;
+    out->merge_tasks = (uint32_t)c->merge_tasks;
     return TOF_OK;
 }
 
@@ -962,16 +970,20 @@ tof_status tof_autotune(tof_ctx* c, const tof_frame_desc* frames, int n_frames, 
     const uint64_t frames0 = c->frames;
     const bool timing = c->timing;
     const unsigned sb0 = c->shift_blocks, vb0 = c->vis_blocks;
+    const int vw0 = c->vis_waves, mt0 = c->merge_tasks;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t ev[2] = {nullptr, nullptr};
     tof_status res = TOF_OK;
     unsigned best_sb = sb0, best_vb = vb0;
+    int best_vw = vw0, best_mt = mt0;
     float best_ms = 3e38f;
     // one candidate: the frames from the first, without history; the later
     // half timed (the earlier half fills the reservoirs)
-    auto trial = [&](unsigned sb, unsigned vb) -> tof_status {
+    auto trial = [&](unsigned sb, unsigned vb, int vw, int mt) -> tof_status {
         c->shift_blocks = sb;
         c->vis_blocks = vb;
+        c->vis_waves = vw;
+        c->merge_tasks = mt;
         c->plan = plan_of(c, c->ray_budget);
         c->prev_valid = false;
         for (int i = 0; i < n_frames; ++i) {
@@ -986,26 +998,38 @@ tof_status tof_autotune(tof_ctx* c, const tof_frame_desc* frames, int n_frames, 
             best_ms = ms;
             best_sb = sb;
             best_vb = vb;
+            best_vw = vw;
+            best_mt = mt;
         }
         return TOF_OK;
     };
     c->timing = false;
     if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) res = TOF_ERR_DEVICE;
-    // coordinate search over powers of two: the shift kernels' blocks at the
-    // default visibility grid, then the visibility blocks at the best of those
+    // coordinate search: the shift kernels' blocks at the default visibility
+    // grid, then the visibility blocks, the visibility kernel's occupancy and
+    // the merge tile, each at the best of the steps before
     for (unsigned sb : {tofh::kShiftGrid, tofh::kShiftGrid / 2, tofh::kShiftGrid / 4})
-        if (res == TOF_OK) res = trial(sb, tofh::kVisGrid);
+        if (res == TOF_OK) res = trial(sb, tofh::kVisGrid, 6, 2);
     const unsigned sb_best = best_sb;
     for (unsigned vb : {tofh::kVisGrid / 4, tofh::kVisGrid / 2, tofh::kVisGrid * 2})
-        if (res == TOF_OK) res = trial(sb_best, vb);
+        if (res == TOF_OK) res = trial(sb_best, vb, 6, 2);
+    const unsigned vb_best = best_vb;
+    if (res == TOF_OK) res = trial(sb_best, vb_best, 5, 2);
+    const int vw_best = best_vw;
+    for (int mt : {1, 4})
+        if (res == TOF_OK) res = trial(sb_best, vb_best, vw_best, mt);
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
     if (res == TOF_OK) {
         c->shift_blocks = best_sb;
         c->vis_blocks = best_vb;
+        c->vis_waves = best_vw;
+        c->merge_tasks = best_mt;
     } else {
         c->shift_blocks = sb0;
         c->vis_blocks = vb0;
+        c->vis_waves = vw0;
+        c->merge_tasks = mt0;
     }
     c->plan = plan_of(c, c->ray_budget);
     c->timing = timing;
@@ -1019,6 +1043,8 @@ tof_status tof_autotune(tof_ctx* c, const tof_frame_desc* frames, int n_frames, 
     if (chosen) {
         chosen->shift_blocks = c->shift_blocks;
         chosen->vis_blocks = c->vis_blocks;
+        chosen->vis_waves = (uint32_t)c->vis_waves;
+        chosen->merge_tasks = (uint32_t)c->merge_tasks;
     }
     return res;
 }
@@ -1175,7 +1201,7 @@ tof_status run_pass(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, c
         hipError_t e = timer_mark(c, kv, st);
         if (e != hipSuccess) return e;
         a.counters = c->counters + (size_t)kv * kBank;
-        tofh::launch_vis(a, slot, q, kill, pl.vis_grid[mode], st);
+        tofh::launch_vis(a, slot, q, kill, pl.vis_grid[mode], c->vis_waves, st);
         return timer_mark(c, kv, st);
     };
     // the chunks that hold items: all the plan allows, or (when more than one
@@ -1206,7 +1232,7 @@ tof_status run_pass(tof_ctx* c, tofh::FrameArgs& a, int mode, const ResSet& A, c
         HIP_TRY(timer_mark(c, kg, st));
         a.counters = c->counters + (size_t)kg * kBank;
         tofh::launch_merge(a, mode, A, Bp, links, c->items, c->tasks, c->task0, c->count, i0, ci, win, c->fwd, c->term,
-                           c->shv, round, out, st);
+                           c->shv, round, out, c->merge_tasks, st);
         HIP_TRY(timer_mark(c, kg, st));
     }
     return TOF_OK;
@@ -1407,14 +1433,14 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
                 const size_t np = std::min(ct, P - p0);
                 tofh::launch_fill_u32(c->ray_count, 0u, (size_t)tofd::kRaySubQueues * tofd::kCounterStride, st);
                 tofh::launch_shrink_mix(a, can, wide, p0, np, q4, c->fwd, pl.grid[1], st);
-                tofh::launch_vis(a, 0, q4, (float*)c->fwd, pl.vis_grid[1], st);
+                tofh::launch_vis(a, 0, q4, (float*)c->fwd, pl.vis_grid[1], c->vis_waves, st);
                 tofh::launch_shrink_mix_fin(a, can, wide, p0, np, c->fwd, st);
             }
         } else {
             for (size_t p0 = 0; p0 < P; p0 += ct) {
                 tofh::launch_fill_u32(c->ray_count, 0u, (size_t)tofd::kRaySubQueues * tofd::kCounterStride, st);
                 tofh::launch_shrink(a, can, p0, std::min(ct, P - p0), qs, pl.grid[1], st);
-                tofh::launch_vis(a, 0, qs, kill, pl.vis_grid[1], st);
+                tofh::launch_vis(a, 0, qs, kill, pl.vis_grid[1], c->vis_waves, st);
             }
             tofh::launch_shrink_fin(a, can, st);
         }

@@ -131,13 +131,15 @@ void launch_fwd(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd:
 void launch_mis(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
                 const uint2* items, const uint2* tasks, const uint32_t* win, const float4* fwd, const float4* shv,
                 float* term, const tofd::IdxQueue& lq, const tofd::RayQueue& q, unsigned grid, hipStream_t st);
-void launch_vis(const FrameArgs& a, int slot, const tofd::RayQueue& q, float* kill, unsigned grid, hipStream_t st);
+// waves: the occupancy variant of the persistent visibility kernel (5 or 6 waves per SIMD)
+void launch_vis(const FrameArgs& a, int slot, const tofd::RayQueue& q, float* kill, unsigned grid, int waves,
+                hipStream_t st);
 // Weighted reservoir merge of the candidates of items [i0, i0 + ci) into `out`.
 void launch_merge(const FrameArgs& a, int mode, const tofd::ResSet& A, const tofd::ResSet& Bp, const int* links,
                   const uint2* items, const uint2* tasks, const uint32_t* task0, const uint32_t* count, size_t i0,
                   size_t ci,
                   const uint32_t* win, const float4* fwd, const float* term, const float4* shv, int round,
-                  tofd::ResSet out, hipStream_t st);
+                  tofd::ResSet out, int tile, hipStream_t st);
 // Shrink mapping of the gate reservoirs of pixels [p0, p0 + np) (at most 2
 // visibility segments each, queued in q) and, after their visibility, the
 // emptying of the failed ones.

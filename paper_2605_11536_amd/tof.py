@@ -52,7 +52,13 @@ class tof_sensor_desc(C.Structure):
 
 
 class tof_launch_config(C.Structure):
-    _fields_ = [("shift_blocks", C.c_uint32), ("vis_blocks", C.c_uint32)]
+    _fields_ = [("shift_blocks", C.c_uint32), ("vis_blocks", C.c_uint32), ("vis_waves", C.c_uint32),
+                ("merge_tasks", C.c_uint32)]
+
+
+def _launch_dict(cfg) -> dict:
+    return {"shift_blocks": int(cfg.shift_blocks), "vis_blocks": int(cfg.vis_blocks),
+            "vis_waves": int(cfg.vis_waves), "merge_tasks": int(cfg.merge_tasks)}
 
 
 class tof_bvh_info(C.Structure):
@@ -292,15 +298,16 @@ def tof_render_frame_noalloc(h, frame, out_image=None, out_hist=None, out_pt_ima
                                           _dptr(out_pt_hist), C.c_void_p(stream.cuda_stream)))
 
 
-def tof_set_launch_config(h, shift_blocks: int = 0, vis_blocks: int = 0) -> None:
-    cfg = tof_launch_config(int(shift_blocks), int(vis_blocks))
+def tof_set_launch_config(h, shift_blocks: int = 0, vis_blocks: int = 0, vis_waves: int = 0,
+                          merge_tasks: int = 0) -> None:
+    cfg = tof_launch_config(int(shift_blocks), int(vis_blocks), int(vis_waves), int(merge_tasks))
     _check("tof_set_launch_config", lib().tof_set_launch_config(h, C.byref(cfg)))
 
 
 def tof_get_launch_config(h) -> dict:
     cfg = tof_launch_config()
     _check("tof_get_launch_config", lib().tof_get_launch_config(h, C.byref(cfg)))
-    return {"shift_blocks": int(cfg.shift_blocks), "vis_blocks": int(cfg.vis_blocks)}
+    return _launch_dict(cfg)
 
 
 def tof_set_bvh_builder(h, builder: int) -> None:
@@ -335,7 +342,7 @@ def tof_autotune(h, frames, stream=None) -> dict:
     arr = (tof_frame_desc * len(descs))(*descs)
     cfg = tof_launch_config()
     _check("tof_autotune", lib().tof_autotune(h, arr, len(descs), C.c_void_p(stream.cuda_stream), C.byref(cfg)))
-    return {"shift_blocks": int(cfg.shift_blocks), "vis_blocks": int(cfg.vis_blocks)}
+    return _launch_dict(cfg)
 
 
 def tof_reservoirs_reset(h) -> None:
@@ -456,8 +463,9 @@ class Renderer:
     def set_history(self, hist: dict):
         tof_debug_set_history(self.h, hist)
 
-    def set_launch_config(self, shift_blocks: int = 0, vis_blocks: int = 0):
-        tof_set_launch_config(self.h, shift_blocks, vis_blocks)
+    def set_launch_config(self, shift_blocks: int = 0, vis_blocks: int = 0, vis_waves: int = 0,
+                          merge_tasks: int = 0):
+        tof_set_launch_config(self.h, shift_blocks, vis_blocks, vis_waves, merge_tasks)
 
     def launch_config(self) -> dict:
         return tof_get_launch_config(self.h)

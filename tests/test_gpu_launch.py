@@ -18,19 +18,21 @@ def _glossy(frames):
 
 def test_launch_shape_does_not_change_results():
     """Three frames of the glossy crop with the default shape, with the
-    smallest grids (64 shift blocks, 64 visibility blocks) and with a mixed
-    one, each over many small chunks: outputs bit-identical, counters equal."""
+    smallest grids (64 shift blocks, 64 visibility blocks), with mixed ones,
+    with the visibility kernel compiled for 5 waves per SIMD and merge
+    tiles of 1 and 4 tasks, each over many small chunks: outputs
+    bit-identical, counters equal."""
     from paper_2605_11536_amd.tof import Renderer
     w = _glossy(3)
-    shapes = [(0, 0), (64, 64), (2048, 32768)]
+    shapes = [(0, 0, 0, 0), (64, 64, 5, 1), (2048, 32768, 5, 4), (4096, 8192, 6, 2)]
     rs = []
-    for sb, vb in shapes:
+    for shape in shapes:
         r = Renderer(w.scene, w.sensor)
-        r.set_launch_config(sb, vb)
+        r.set_launch_config(*shape)
         r.set_ray_budget(1)
         rs.append(r)
-    assert rs[1].launch_config() == {"shift_blocks": 64, "vis_blocks": 64}
-    assert rs[0].launch_config() == {"shift_blocks": 8192, "vis_blocks": 16384}
+    assert rs[1].launch_config() == {"shift_blocks": 64, "vis_blocks": 64, "vis_waves": 5, "merge_tasks": 1}
+    assert rs[0].launch_config() == {"shift_blocks": 8192, "vis_blocks": 16384, "vis_waves": 6, "merge_tasks": 2}
     for fr in w.frames:
         print(f"case launch shapes frame {fr.index}", flush=True)
         outs = []
@@ -62,6 +64,7 @@ def test_autotune_leaves_no_trace_but_the_shape():
     cfg = r.autotune(w.frames[:4])
     print("chosen", cfg, flush=True)
     assert cfg["shift_blocks"] in (8192, 4096, 2048) and cfg["vis_blocks"] in (4096, 8192, 16384, 32768)
+    assert cfg["vis_waves"] in (5, 6) and cfg["merge_tasks"] in (1, 2, 4)
     assert r.launch_config() == cfg
     after = r.stats()
     for k in COUNTS:
@@ -75,7 +78,7 @@ def test_autotune_leaves_no_trace_but_the_shape():
         assert np.array_equal(got[key], ref[key]), key
     with pytest.raises(TofError):
         r.autotune(w.frames[:1])
-    for bad in ((100, 0), (16384, 0), (0, 131072)):
+    for bad in ((100, 0), (16384, 0), (0, 131072), (0, 0, 4, 0), (0, 0, 0, 3)):
         with pytest.raises(TofError):
             r.set_launch_config(*bad)
     assert r.launch_config() == cfg
