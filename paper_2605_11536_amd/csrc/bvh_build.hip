@@ -19,7 +19,7 @@
 //      merges;
 //   4. at its creation each binary node decides, from its children's costs,
 //      whether its subtree is cheaper as one leaf (at most 4 triangles; cost
-//      in units of one triangle test, 0.5 per node step, surface-area
+//      in units of one triangle test, 1 per node step, surface-area
 //      weighted, the host builder's model);
 //   5. top-down, level by level, every 4-wide node takes its binary node's
 //      children and opens the internal child of largest area until it has
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(kTB) k_merge_round(Clusters in, int n, const i
         ref_info(b, ref, ci, ki);
         ref_info(b, rj, cj, kj);
         const float A = fmaxf(box_area(ulo, uhi), 1e-30f);
-        const float inner = 0.5f + (box_area(lo, hi) * ki + box_area(lj, hj) * kj) / A;
+        const float inner = 1.0f + (box_area(lo, hi) * ki + box_area(lj, hj) * kj) / A;
         const int cnt = ci + cj;
         const bool leaf = cnt <= kLeafMax && (float)cnt <= inner;
         b.child[id] = make_int2(ref, rj);
