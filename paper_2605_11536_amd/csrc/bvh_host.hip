@@ -1,5 +1,5 @@
-// Host-side construction of 4-wide BVH topologies (binned SAH, then a
-// collapse of the binary tree into 4-wide nodes).  Used once per scene for
+// Host-side construction of 4-wide BVH topologies (binned SAH, then the
+// SAH-optimal collapse of the binary tree into 4-wide nodes).  Used once per scene for
 // every object's triangles (in object space; the device refits the boxes in
 // world space each frame, which a rigid motion keeps tight) and once per frame
 // for the top-level tree over the objects' world boxes.  Only child links and
@@ -141,20 +141,98 @@ int32_t leaf_ref(int first, int count) {
     return (int32_t)(0x80000000u | ((uint32_t)(count - 1) << 28) | (uint32_t)first);
 }
 
+// Collapse of the binary tree into 4-wide nodes by dynamic programming over
+// the SAH (the optimal collapse of a binary tree into a wide one, as in
+// Ylitie, Karras and Laine 2017): C(n, j) is the least cost of n's subtree
+// when it may occupy up to j child slots of a 4-wide node -- as one slot
+// (a leaf of at most leaf_max triangles, cost A(n) * count, or a node, cost
+// A(n) * node_cost + D(n, 4)) or, for j >= 2, spread over its binary
+// children, D(n, j) = min over k of C(left, k) + C(right, j - k).  Costs are
+// surface areas times the triangle tests and node steps they weigh, the
+// units of the binned SAH above.
+struct Collapse {
+    float c[5];        // C(n, j), j = 1..4
+    float d4;          // D(n, 4): the children of n as a node
+    int8_t node;       // C(n, 1) as a node (1) or a leaf (0)
+    int8_t spread[5];  // for j >= 2: 0 = one slot, k > 0 = left child takes k slots
+    int8_t k4;         // left child's slots in D(n, 4)
+};
+
 // 4-wide tree over prims: nodes appended to `nodes` (global index = node_base
 // + position), heights (1 + the highest internal child, leaves count 0)
 // appended likewise, order = primitive indices in leaf order, leaf slots
 // numbered from slot_base.  Returns the root reference.
 int32_t build_bvh4(const std::vector<BvhPrim>& prims, int leaf_max, int node_base, int slot_base,
                    std::vector<tofd::Node4>& nodes, std::vector<int>& heights, std::vector<int>& order) {
+    constexpr float kNodeCost = 1.0f;   // a node step in triangle tests, as in the split cost
     order.resize(prims.size());
     for (size_t i = 0; i < prims.size(); ++i) order[i] = (int)i;
     if (prims.empty()) return -1;
+    const int lmax = std::min(leaf_max, 8);
     std::vector<BinNode> bin;
-    build_binary(prims, order, std::min(leaf_max, 8), bin);
-    if (bin[0].left < 0) return leaf_ref(slot_base + bin[0].first, bin[0].count);
-    // collapse: every 4-wide node takes its binary node's children and opens
-    // the internal child of largest area until it has four
+    build_binary(prims, order, lmax, bin);
+    // children have larger indices than their parents: fill bottom-up
+    std::vector<Collapse> dp(bin.size());
+    for (size_t i = bin.size(); i-- > 0;) {
+        const BinNode& b = bin[i];
+        Collapse& q = dp[i];
+        const float A = area(b.lo, b.hi);
+        const float leaf = b.count <= lmax ? A * (float)b.count : 3e38f;
+        if (b.left < 0) {   // a binary leaf is a leaf (count <= lmax by construction)
+            for (int j = 1; j <= 4; ++j) {
+                q.c[j] = leaf;
+                q.spread[j] = 0;
+            }
+            q.node = 0;
+            q.d4 = 3e38f;
+            q.k4 = 0;
+            continue;
+        }
+        const Collapse& l = dp[b.left];
+        const Collapse& r = dp[b.right];
+        auto distribute = [&](int j, int& kbest) {
+            float best = 3e38f;
+            kbest = 0;
+            for (int k = 1; k < j; ++k) {
+                const float v = l.c[k] + r.c[j - k];
+                if (v < best) {
+                    best = v;
+                    kbest = k;
+                }
+            }
+            return best;
+        };
+        int k4 = 0;
+        q.d4 = distribute(4, k4);
+        q.k4 = (int8_t)k4;
+        const float as_node = A * kNodeCost + q.d4;
+        q.node = as_node < leaf ? 1 : 0;
+        q.c[1] = std::min(as_node, leaf);
+        q.spread[1] = 0;
+        for (int j = 2; j <= 4; ++j) {
+            int k = 0;
+            const float d = distribute(j, k);
+            if (d < q.c[1]) {
+                q.c[j] = d;
+                q.spread[j] = (int8_t)k;
+            } else {
+                q.c[j] = q.c[1];
+                q.spread[j] = 0;
+            }
+        }
+    }
+    if (!dp[0].node) return leaf_ref(slot_base + bin[0].first, bin[0].count);
+    // the subtrees in the slots of n spread over j slots
+    std::vector<int> kids;
+    auto slots = [&](auto&& self, int n, int j) -> void {
+        const int k = dp[n].spread[j];
+        if (k == 0 || bin[n].left < 0) {
+            kids.push_back(n);
+        } else {
+            self(self, bin[n].left, k);
+            self(self, bin[n].right, j - k);
+        }
+    };
     const size_t base = nodes.size();
     struct Item {
         int bin;     // binary node of this 4-wide node
@@ -166,26 +244,14 @@ int32_t build_bvh4(const std::vector<BvhPrim>& prims, int leaf_max, int node_bas
     std::vector<std::pair<int, int>> parent_of;   // (4-wide child position, 4-wide parent position)
     for (size_t w = 0; w < work.size(); ++w) {
         const Item it = work[w];
-        std::vector<int> kids{bin[it.bin].left, bin[it.bin].right};
-        while (kids.size() < 4) {
-            int pick = -1;
-            float pa = -1.f;
-            for (size_t k = 0; k < kids.size(); ++k) {
-                const BinNode& b = bin[kids[k]];
-                if (b.left >= 0 && area(b.lo, b.hi) > pa) {
-                    pa = area(b.lo, b.hi);
-                    pick = (int)k;
-                }
-            }
-            if (pick < 0) break;
-            const int open = kids[pick];
-            kids[pick] = bin[open].left;
-            kids.push_back(bin[open].right);
-        }
+        kids.clear();
+        const int k4 = dp[it.bin].k4;
+        slots(slots, bin[it.bin].left, k4);
+        slots(slots, bin[it.bin].right, 4 - k4);
         int ref[4] = {-1, -1, -1, -1};
         for (size_t k = 0; k < kids.size(); ++k) {
             const BinNode& b = bin[kids[k]];
-            if (b.left < 0) {
+            if (b.left < 0 || !dp[kids[k]].node) {
                 ref[k] = leaf_ref(slot_base + b.first, b.count);
             } else {
                 const int pos = (int)nodes.size();
