@@ -17,14 +17,14 @@
 //      Distances are symmetric and ties are broken by the pair's positions,
 //      so the least pair of an object is always mutual and every round
 //      merges;
-//   4. at its creation each binary node decides, from its children's costs,
-//      whether its subtree is cheaper as one leaf (at most 4 triangles; cost
-//      in units of one triangle test, 1 per node step, surface-area
-//      weighted, the host builder's model);
-//   5. top-down, level by level, every 4-wide node takes its binary node's
-//      children and opens the internal child of largest area until it has
-//      four (the host's collapse rule); children numbered by a scan, leaf
-//      slots assigned in depth-first order so that each leaf's triangles are
+//   4. at its creation each binary node takes the SAH-optimal collapse of
+//      its subtree into 4-wide nodes from its children's (the host builder's
+//      dynamic program: the least cost in up to j = 1..4 child slots, as a
+//      leaf of at most 4 triangles, as a node, or spread over its children;
+//      surface areas times triangle tests and node steps, 1 per step);
+//   5. top-down, level by level, every 4-wide node takes the slots its
+//      binary node's plan gives; children numbered by a scan, leaf slots
+//      assigned in depth-first order so that each leaf's triangles are
 //      contiguous.
 //
 // The host reads back only the small results (cluster counts per round, the
@@ -51,6 +51,7 @@ constexpr int kIPT = 8;             // elements per thread of the scan and sort 
 constexpr int kTile = kTB * kIPT;   // 2048
 constexpr int kRadius = 16;         // clustering window (places on either side; 32 and 64 were no better)
 constexpr int kLeafMax = 4;         // triangles per leaf
+constexpr float kNodeCost = 1.0f;   // a node step in triangle tests (the host builder's model)
 
 __device__ __forceinline__ int fkey(float f) {
     const int i = __float_as_int(f);
@@ -309,8 +310,9 @@ struct BinTree {
     float4* lo;
     float4* hi;
     int* count;
-    float* cost;
-    int* leaf;   // the subtree is one leaf
+    float4* c;   // C(n, j), j = 1..4: least cost of the subtree in up to j child slots
+    int* plan;   // bit 0: a node (else one leaf); bits 1-2: left child's slots as a node;
+                 // bits 2j+1..2j+2 for j = 2..4: left child's slots when spread over j (0: one slot)
 };
 
 __global__ void __launch_bounds__(kTB) k_init_clusters(const uint64_t* __restrict__ keys,
@@ -366,14 +368,12 @@ __global__ void __launch_bounds__(kTB) k_pairs(const int* __restrict__ nn, int n
     make[i] = (mutual && i < j) ? 1u : 0u;
 }
 
-__device__ __forceinline__ void ref_info(const BinTree& b, int ref, int& count, float& cost) {
-    if (ref < 0) {
-        count = 1;
-        cost = 1.f;
-    } else {
-        count = b.count[ref];
-        cost = b.cost[ref];
-    }
+// C(ref, j) for j = 1..4 (a triangle: a leaf of one, its area)
+__device__ __forceinline__ float4 ref_cost(const BinTree& b, int ref, float area) {
+    return ref < 0 ? make_float4(area, area, area, area) : b.c[ref];
+}
+__device__ __forceinline__ float cj(const float4& c, int j) {
+    return j == 1 ? c.x : (j == 2 ? c.y : (j == 3 ? c.z : c.w));
 }
 
 __global__ void __launch_bounds__(kTB) k_merge_round(Clusters in, int n, const int* __restrict__ nn,
@@ -393,20 +393,44 @@ __global__ void __launch_bounds__(kTB) k_merge_round(Clusters in, int n, const i
         const float4 lj = in.lo[j], hj = in.hi[j];
         const int rj = in.ref[j];
         const float4 ulo = min4(lo, lj), uhi = max4(hi, hj);
-        int ci, cj;
-        float ki, kj;
-        ref_info(b, ref, ci, ki);
-        ref_info(b, rj, cj, kj);
-        const float A = fmaxf(box_area(ulo, uhi), 1e-30f);
-        const float inner = 1.0f + (box_area(lo, hi) * ki + box_area(lj, hj) * kj) / A;
-        const int cnt = ci + cj;
-        const bool leaf = cnt <= kLeafMax && (float)cnt <= inner;
+        const int cnt = (ref < 0 ? 1 : b.count[ref]) + (rj < 0 ? 1 : b.count[rj]);
+        const float4 cl = ref_cost(b, ref, box_area(lo, hi)), cr = ref_cost(b, rj, box_area(lj, hj));
+        // the SAH-optimal collapse into 4-wide nodes, one binary node at a
+        // time (its children were made in earlier rounds): as one leaf, as a
+        // node over its children spread into 4 slots, or (for a parent with
+        // j >= 2 slots to give) spread itself
+        const float A = box_area(ulo, uhi);
+        auto spread = [&](int j, int& kb) {
+            float best = 3.0e38f;
+            kb = 0;
+            for (int k = 1; k < j; ++k) {
+                const float v = cj(cl, k) + cj(cr, j - k);
+                if (v < best) {
+                    best = v;
+                    kb = k;
+                }
+            }
+            return best;
+        };
+        int k4 = 0;
+        const float as_node = A * kNodeCost + spread(4, k4);
+        const float leaf = cnt <= kLeafMax ? A * (float)cnt : 3.0e38f;
+        const bool node = as_node < leaf;
+        const float c1 = node ? as_node : leaf;
+        float cjs[3];
+        int plan = (node ? 1 : 0) | (k4 << 1);
+        for (int j = 2; j <= 4; ++j) {
+            int k = 0;
+            const float d = spread(j, k);
+            cjs[j - 2] = d < c1 ? d : c1;
+            plan |= (d < c1 ? k : 0) << (2 * j - 1 + 2);
+        }
         b.child[id] = make_int2(ref, rj);
         b.lo[id] = ulo;
         b.hi[id] = uhi;
         b.count[id] = cnt;
-        b.cost[id] = leaf ? (float)cnt : inner;
-        b.leaf[id] = leaf ? 1 : 0;
+        b.c[id] = make_float4(c1, cjs[0], cjs[1], cjs[2]);
+        b.plan[id] = plan;
         lo = ulo;
         hi = uhi;
         ref = id;
@@ -420,31 +444,36 @@ __global__ void __launch_bounds__(kTB) k_merge_round(Clusters in, int n, const i
 // ---------------------------------------------------------------------------
 // 4-wide collapse
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool openable(const BinTree& b, int ref) { return ref >= 0 && !b.leaf[ref]; }
+__device__ __forceinline__ bool openable(const BinTree& b, int ref) { return ref >= 0 && (b.plan[ref] & 1); }
+// left child's slots when ref's subtree is spread over j >= 2 slots (0: one slot)
+__device__ __forceinline__ int spread_of(const BinTree& b, int ref, int j) {
+    return ref < 0 ? 0 : (b.plan[ref] >> (2 * j + 1)) & 3;
+}
 __device__ __forceinline__ int ref_count(const BinTree& b, int ref) { return ref < 0 ? 1 : b.count[ref]; }
 
-// children of a 4-wide node made from binary node r: its two children, then
-// the openable child of largest area opened until there are four
+// children of a 4-wide node made from binary node r: its children spread
+// over 4 slots as the collapse chose (left child k4 slots, the right one
+// 4 - k4; a subtree given j >= 2 slots spreads further or takes one)
 __device__ __forceinline__ int gather_kids(const BinTree& b, int r, int kids[4]) {
     const int2 c = b.child[r];
-    kids[0] = c.x;
-    kids[1] = c.y;
-    int nk = 2;
-    while (nk < 4) {
-        int pick = -1;
-        float pa = -1.f;
-        for (int k = 0; k < nk; ++k)
-            if (openable(b, kids[k])) {
-                const float a = box_area(b.lo[kids[k]], b.hi[kids[k]]);
-                if (a > pa) {
-                    pa = a;
-                    pick = k;
-                }
-            }
-        if (pick < 0) break;
-        const int2 oc = b.child[kids[pick]];
-        kids[pick] = oc.x;
-        kids[nk++] = oc.y;
+    const int k4 = (b.plan[r] >> 1) & 3;
+    int st_ref[4], st_j[4], sp = 0, nk = 0;
+    st_ref[sp] = c.y;   // right after left: a stack
+    st_j[sp++] = 4 - k4;
+    st_ref[sp] = c.x;
+    st_j[sp++] = k4;
+    while (sp > 0 && nk < 4) {
+        const int x = st_ref[--sp], j = st_j[sp];
+        const int k = j >= 2 ? spread_of(b, x, j) : 0;
+        if (k == 0) {
+            kids[nk++] = x;
+        } else if (sp + 2 <= 4) {
+            const int2 cx = b.child[x];
+            st_ref[sp] = cx.y;
+            st_j[sp++] = j - k;
+            st_ref[sp] = cx.x;
+            st_j[sp++] = k;
+        }
     }
     return nk;
 }
@@ -576,7 +605,7 @@ size_t blas_build_bytes(size_t T, size_t M) {
     const size_t per_t = 2 * 8 + 2 * 4            // keys, values
                          + 2 * (16 + 16 + 4 + 4)  // clusters
                          + 4 + 4 * 4              // neighbours, keep, make and their scans
-                         + 8 + 16 + 16 + 4 + 4 + 4  // binary nodes
+                         + 8 + 16 + 16 + 4 + 16 + 4  // binary nodes
                          + 2 * 16 + 4              // frontiers, child counts
                          + 16 + 4 + 4;             // 4-wide nodes
     return per_t * (T + 1) + 2 * 4 * 256 * nt + 4 * ((scan_max + kTile - 1) / kTile + 1) + 64 * (M + 1) +
@@ -617,8 +646,8 @@ tof_status build_blas_device(void* work, size_t work_bytes, const int4* tv, cons
     b.lo = cv.take<float4>(T);
     b.hi = cv.take<float4>(T);
     b.count = cv.take<int>(T);
-    b.cost = cv.take<float>(T);
-    b.leaf = cv.take<int>(T);
+    b.c = cv.take<float4>(T);
+    b.plan = cv.take<int>(T);
     int4* F[2] = {cv.take<int4>(T), cv.take<int4>(T)};
     uint32_t* fcnt = cv.take<uint32_t>(T);
     int4* nd_child = cv.take<int4>(T);
