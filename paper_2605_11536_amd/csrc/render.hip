@@ -1173,7 +1173,9 @@ __global__ void k_copy_plane(FrameArgs a, ResSet in, ResSet out, int pl) {
 // One thread per pixel and group of 32 planes (the planes of one mask word),
 // the planes in turn: the pixel's mask word and direct term are read once,
 // and at every plane the lanes of a wave read and write consecutive pixels.
-__global__ void __launch_bounds__(256) k_splat(FrameArgs a, ResSet shown, const float* __restrict__ pt,
+// clear_pt: the deposits it reads are set back to zero (only the non-zero
+// ones are written), so that the next frame finds the buffer cleared.
+__global__ void __launch_bounds__(256) k_splat(FrameArgs a, ResSet shown, float* __restrict__ pt, int clear_pt,
                                                const float2* __restrict__ direct, float* __restrict__ out_image,
                                                float* __restrict__ out_hist, float* __restrict__ out_pt_image,
                                                float* __restrict__ out_pt_hist) {
@@ -1192,6 +1194,7 @@ __global__ void __launch_bounds__(256) k_splat(FrameArgs a, ResSet shown, const 
             v = wp.x * wp.y;
         }
         float vp = pt[i];
+        if (clear_pt && vp != 0.f) pt[i] = 0.f;
         if (s.include_direct && d.x > 0.f && in_plane(s, pl, d.y)) {
             v += d.x;
             vp += d.x;
@@ -1327,12 +1330,12 @@ void launch_shrink_fin(const FrameArgs& a, const ResSet& can, hipStream_t st) {
 void launch_copy_plane(const FrameArgs& a, const ResSet& in, const ResSet& out, int pl, hipStream_t st) {
     hipLaunchKernelGGL(k_copy_plane, dim3(grid_for(a.s.P, 256, 1u << 30)), dim3(256), 0, st, a, in, out, pl);
 }
-void launch_splat(const FrameArgs& a, const ResSet& shown, const float* pt, const float2* direct, float* out_image,
-                  float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st) {
+void launch_splat(const FrameArgs& a, const ResSet& shown, float* pt, bool clear_pt, const float2* direct,
+                  float* out_image, float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st) {
     const unsigned gx = (unsigned)((a.s.P + 255) / 256), gy = (unsigned)((a.s.B + 31) / 32);
     if (a.s.P > 0 && a.s.B > 0)
-        hipLaunchKernelGGL(k_splat, dim3(gx, gy), dim3(256), 0, st, a, shown, pt, direct, out_image, out_hist,
-                           out_pt_image, out_pt_hist);
+        hipLaunchKernelGGL(k_splat, dim3(gx, gy), dim3(256), 0, st, a, shown, pt, clear_pt ? 1 : 0, direct,
+                           out_image, out_hist, out_pt_image, out_pt_hist);
 }
 
 }  // namespace tofh

@@ -106,6 +106,8 @@ struct tof_ctx {
     float2* direct = nullptr;
     int* prev_pix = nullptr;
     uint32_t* wsum = nullptr;  // [2P]: per pixel, the mask words that are non-zero (work-list pass)
+    bool pt_zero = false;      // pt holds zeros (the last frame's splat cleared what it read)
+    bool pt_zero_pending = false;   // a captured frame's splat: pt_zero once its graph is launched
     int* nb = nullptr;
     uint2* items = nullptr;    // [max_items]
     uint32_t* task0 = nullptr; // [max_items]: first task of each item
@@ -488,6 +490,10 @@ tof_status record_frame_events(tof_ctx* c, hipStream_t st) {
         HIP_TRY(hipEventRecord(c->done, st));
         c->done_pending = false;
     }
+    if (c->pt_zero_pending) {
+        c->pt_zero = true;
+        c->pt_zero_pending = false;
+    }
     return TOF_OK;
 }
 
@@ -825,6 +831,7 @@ tof_status tof_sensor_set(tof_ctx* c, const tof_sensor_desc* d) {
         TOF_TRY(alloc_t(c, a, &h.gb_n, P));
     }
     TOF_TRY(alloc_t(c, a, &c->pt, P * B));
+    c->pt_zero = c->pt_zero_pending = false;
     TOF_TRY(alloc_t(c, a, &c->direct, P));
     TOF_TRY(alloc_t(c, a, &c->prev_pix, P));
     TOF_TRY(alloc_t(c, a, &c->wsum, 2 * P));
@@ -1411,7 +1418,11 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     a.counters = c->counters + (size_t)TOF_K_GBUFFER * kBank;
     tofh::launch_gbuffer(a, gout, st);
     HIP_TRY(timer_mark(c, TOF_K_GBUFFER, st));
-    tofh::launch_fill_u32((uint32_t*)c->pt, 0u, P * B, st);
+    // the plain-PT deposits start from zero: cleared by the last frame's
+    // splat, else filled here
+    if (!c->pt_zero) tofh::launch_fill_u32((uint32_t*)c->pt, 0u, P * B, st);
+    c->pt_zero = false;   // until this frame's splat has been issued
+    c->pt_zero_pending = false;
     ResSet& can = c->sets[0];
     const int spare = c->fin_prev == 1 ? 2 : 1;   // the set not holding the previous frame's final
     ResSet& tmp = c->sets[spare];
@@ -1471,9 +1482,9 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     }
     a.counters = c->counters + (size_t)TOF_K_SPLAT * kBank;
     if (c->s.debug_stage == TOF_STAGE_TEMPORAL) {
-        tofh::launch_splat(a, *cur_set, c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
+        tofh::launch_splat(a, *cur_set, c->pt, true, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
     } else if (shown) {
-        tofh::launch_splat(a, *shown, c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
+        tofh::launch_splat(a, *shown, c->pt, true, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
     }
     // the bin-axis pass and the spatial rounds alternate between sets 1 and
     // 2 (the previous frame's final has been read, or is not read this frame)
@@ -1518,7 +1529,8 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
     a.counters = c->counters + (size_t)TOF_K_SPLAT * kBank;
     if (c->s.debug_stage == TOF_STAGE_FINAL) {
         HIP_TRY(timer_mark(c, TOF_K_SPLAT, st));
-        tofh::launch_splat(a, c->sets[fin_new], c->pt, c->direct, out_image, out_hist, out_pt_image, out_pt_hist, st);
+        tofh::launch_splat(a, c->sets[fin_new], c->pt, true, c->direct, out_image, out_hist, out_pt_image,
+                           out_pt_hist, st);
         HIP_TRY(timer_mark(c, TOF_K_SPLAT, st));
     }
     if (c->timing && c->ev_used > 4096) {   // bound the pool: fold finished pairs
@@ -1526,6 +1538,10 @@ tof_status tof_render_frame(tof_ctx* c, const tof_frame_desc* fr, float* out_ima
         timer_reduce(c);
     }
     if (hipGetLastError() != hipSuccess) return TOF_ERR_DEVICE;
+    // exactly one splat per frame reads (and clears) every deposit; a
+    // recorded frame's only once its graph has been launched
+    if (capturing) c->pt_zero_pending = true;
+    else c->pt_zero = true;
     if (capturing)
         c->done_pending = true;
     else
@@ -1648,6 +1664,10 @@ tof_status tof_render_frame_noalloc(tof_ctx* c, const tof_frame_desc* fr, float*
     const bool timing = c->timing, sync_counts = c->sync_counts;
     c->timing = false;   // event timing creates events on demand: not recorded here
     c->sync_counts = false;   // no wait for the device inside the call: every chunk is launched
+    // the array's deposits are whatever its last user left: filled here;
+    // the context's own buffer keeps its state
+    const bool pt_zero = c->pt_zero;
+    c->pt_zero = false;
     set_work(c, w);
     c->plan = pl;
     const tof_status st = tof_render_frame(c, fr, out_image, out_hist, out_pt_image, out_pt_hist, stream);
@@ -1655,6 +1675,7 @@ tof_status tof_render_frame_noalloc(tof_ctx* c, const tof_frame_desc* fr, float*
     c->plan = own_plan;
     c->timing = timing;
     c->sync_counts = sync_counts;
+    c->pt_zero = pt_zero;
     return st;
 }
 

@@ -27,7 +27,8 @@ tof_status create_in_region(tof_ctx** out, int device, void* dev, size_t dev_byt
 tof_status prepare_frame_capture(tof_ctx* c);
 // after launching a graph recorded from tof_render_frame under stream capture:
 // record on `st` the events the capture left out (the upload ring's and the
-// frame's end), which the context's host waits use
+// frame's end), which the context's host waits use, and take the frame's
+// splat as having cleared the plain-PT deposits (the next frame skips its fill)
 tof_status record_frame_events(tof_ctx* c, hipStream_t st);
 size_t scene_pinned_bytes(const tof_scene_desc& d);
 
@@ -157,7 +158,8 @@ void launch_shrink_mix_fin(const FrameArgs& a, const tofd::ResSet& can, const to
 // Records and mask bits of plane pl copied from `in` to `out` (the gate plane
 // across the bin-axis pass).
 void launch_copy_plane(const FrameArgs& a, const tofd::ResSet& in, const tofd::ResSet& out, int pl, hipStream_t st);
-void launch_splat(const FrameArgs& a, const tofd::ResSet& shown, const float* pt, const float2* direct,
+// clear_pt: the plain-PT deposits are set back to zero as they are read
+void launch_splat(const FrameArgs& a, const tofd::ResSet& shown, float* pt, bool clear_pt, const float2* direct,
                   float* out_image, float* out_hist, float* out_pt_image, float* out_pt_hist, hipStream_t st);
 
 }  // namespace tofh
